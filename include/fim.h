@@ -1,0 +1,309 @@
+/*
+ * fim.h — C ABI of the MI355X frequent-itemset miner (libfim.so).
+ *
+ * Problem (thesis, chapter "Mathematical foundation": definitions of
+ * transaction, database, itemset cover and support, frequent itemset):
+ * given a database D of transactions, each a set of item ids, and an
+ * absolute minimum support m >= 1, report every non-empty itemset U with
+ * supp(U) = |{t in D : U subset of t}| >= m, together with supp(U).
+ *
+ * Method: depth-first Eclat over prefix-based equivalence classes
+ * (definition of a PBEC and of its extensions; appendix "The Eclat
+ * algorithm"), with supports computed as the popcount of the bitwise AND of
+ * vertical transaction bitmaps (bitmap form of the lemma that the support of
+ * U is the size of the intersection of its items' tid-lists).  The classes
+ * are ordered and split for the workers of a persistent GPU kernel by the
+ * thesis's sample-based estimate of class sizes (Phase 1 reservoir variant,
+ * the Partition and LPT-Schedule algorithms of Phase 2).  The result is
+ * always exact: the estimate only decides the order of work.
+ *
+ * Conventions
+ *  - Every function returns a fim_status (0 = FIM_OK, negative = error) and
+ *    never throws or aborts across the ABI.  fim_last_error() returns a
+ *    thread-local text describing the last error of the calling thread.
+ *  - "host" pointers point to CPU memory, "device" pointers to GPU memory.
+ *    Unless stated otherwise every pointer argument is a host pointer.
+ *  - Objects (fim_ctx, fim_db, fim_result, fim_server) are opaque and owned
+ *    by the library until destroyed by the matching *_destroy call.
+ *    destroy(NULL) is a no-op.
+ *  - A fim_ctx is bound to one GPU and one HIP stream and is not
+ *    thread-safe: calls with the same ctx must not overlap.  The server
+ *    functions are the exception and are documented below.
+ */
+#ifndef FIM_H
+#define FIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fim_status;
+
+#define FIM_OK 0
+#define FIM_E_INVALID_ARG (-1)  /* bad pointer, size, flag or minimum support */
+#define FIM_E_ITEM_RANGE (-2)   /* an item id >= n_item_ids */
+#define FIM_E_OOM_HOST (-3)     /* host allocation failed */
+#define FIM_E_OOM_DEVICE (-4)   /* device allocation failed (allocator returned NULL) */
+#define FIM_E_DEVICE (-5)       /* a HIP runtime call or kernel failed */
+#define FIM_E_OUTPUT_LIMIT (-6) /* more frequent itemsets than options.max_itemsets */
+#define FIM_E_BUSY (-7)         /* server queue full */
+#define FIM_E_CANCELLED (-8)    /* server request was cancelled */
+#define FIM_E_NOT_FOUND (-9)    /* unknown server ticket */
+#define FIM_E_NO_DEVICE (-10)   /* no usable gfx950 GPU */
+
+/* Text of a status code (static string). */
+const char *fim_status_str(fim_status s);
+
+/* Text of the last error on the calling thread ("" if none). */
+const char *fim_last_error(void);
+
+/* Library version string, e.g. "fim 1.0 gfx950". */
+const char *fim_version(void);
+
+/* ------------------------------------------------------------------ */
+/* Context                                                            */
+
+/*
+ * Device-memory allocator supplied by the caller (for instance a framework's
+ * caching allocator).  alloc returns a device pointer of at least `bytes`
+ * bytes usable on `stream`, or NULL on failure; free releases it.  `user` is
+ * passed back unchanged.  The library calls them only from the thread that
+ * calls the ctx functions, except for a server, which calls them from its
+ * own thread.
+ */
+typedef struct fim_allocator {
+    void *(*alloc)(size_t bytes, void *stream, void *user);
+    void (*free)(void *ptr, void *stream, void *user);
+    void *user;
+} fim_allocator;
+
+typedef struct fim_ctx fim_ctx;
+
+/*
+ * Create a context on GPU `device` (HIP ordinal).  hip_stream is a
+ * hipStream_t cast to void* (NULL = the null stream); all GPU work of the
+ * context is ordered on it.  alloc may be NULL (hipMalloc / hipFree are then
+ * used).  The allocator struct is copied.
+ * Errors: FIM_E_INVALID_ARG (out == NULL), FIM_E_NO_DEVICE (no such device or
+ * not gfx950), FIM_E_DEVICE.
+ */
+fim_status fim_ctx_create(int device, void *hip_stream, const fim_allocator *alloc,
+                          fim_ctx **out);
+void fim_ctx_destroy(fim_ctx *ctx);
+
+/* ------------------------------------------------------------------ */
+/* Database                                                           */
+
+typedef struct fim_db fim_db;
+
+/*
+ * Upload a transaction database (definition of a database: a sequence of
+ * transactions, each an itemset) given in CSR form:
+ *   tx_offsets[n_tx + 1] (host, uint64, non-decreasing, tx_offsets[0] = 0),
+ *   items[tx_offsets[n_tx]] (host, uint32, each < n_item_ids).
+ * Transaction t holds items[tx_offsets[t] .. tx_offsets[t+1]).  Transactions
+ * are sets: item order is free and repeated items count once.  Empty
+ * transactions are allowed and count towards the database size.
+ * n_tx = 0 is allowed (every result is then empty).
+ * The data are copied (the caller keeps ownership of its arrays) and stay
+ * resident in device memory until fim_db_destroy.  n_tx must be < 2^31.
+ * Errors: FIM_E_INVALID_ARG (NULL pointers, non-monotone offsets,
+ * n_item_ids == 0), FIM_E_ITEM_RANGE, FIM_E_OOM_HOST, FIM_E_OOM_DEVICE,
+ * FIM_E_DEVICE.
+ */
+fim_status fim_db_create(fim_ctx *ctx, uint64_t n_tx, const uint64_t *tx_offsets,
+                         const uint32_t *items, uint32_t n_item_ids, fim_db **out);
+void fim_db_destroy(fim_db *db);
+
+/* Number of transactions and of distinct (transaction, item) pairs. */
+fim_status fim_db_sizes(const fim_db *db, uint64_t *n_tx, uint64_t *nnz);
+
+/*
+ * Absolute minimum support from a relative one (definition of a frequent
+ * itemset with relative support): out = ceil(rel * n_tx) computed in double
+ * precision, at least 1.  Errors: FIM_E_INVALID_ARG if rel is not in (0, 1].
+ */
+fim_status fim_minsup_from_relative(uint64_t n_tx, double rel, uint32_t *out_abs);
+
+/* ------------------------------------------------------------------ */
+/* Mining                                                             */
+
+/* options.flags */
+#define FIM_FLAG_NO_ESTIMATE 0x1u  /* order classes by a cheap size proxy, skip the sample */
+#define FIM_FLAG_ORDER_BY_ID 0x2u  /* extensions ordered by item id, not ascending support */
+#define FIM_FLAG_NO_SPLIT 0x4u     /* never split first-level classes */
+
+/*
+ * Options of a mining call.  A zero field selects its default.
+ *  max_len         longest itemset to report (0 = unlimited)
+ *  max_itemsets    limit on |F| (0 = unlimited); exceeded -> FIM_E_OUTPUT_LIMIT
+ *  seed            seed of the database sample and the reservoir (default fixed)
+ *  alpha           Partition parameter alpha of Phase 2 (default 0.3)
+ *  sample_tx       database sample size |D~| (default from the Chernoff bound
+ *                  of Toivonen's theorem with eps = 0.02, delta = 0.05,
+ *                  capped at n_tx / 4)
+ *  sample_fi       reservoir size |S| (default from the hypergeometric KL
+ *                  bound with rho = 0.001, eps = 0.0005, delta = 0.05)
+ *  tile_words      bitmap words per tile of the pair kernels (0 = autotuned)
+ *  classes_per_wg  work items a worker claims at once (0 = autotuned)
+ *  workers         persistent workers (waves) to launch (0 = autotuned)
+ *  flags           FIM_FLAG_*
+ */
+typedef struct fim_options {
+    uint32_t max_len;
+    uint64_t max_itemsets;
+    uint64_t seed;
+    double alpha;
+    uint32_t sample_tx;
+    uint32_t sample_fi;
+    uint32_t tile_words;
+    uint32_t classes_per_wg;
+    uint32_t workers;
+    uint32_t flags;
+} fim_options;
+
+typedef struct fim_result fim_result;
+
+/*
+ * Mine every frequent itemset of db at absolute minimum support minsup_abs
+ * (>= 1).  opts may be NULL (all defaults).  On success *out receives a new
+ * result owned by the caller (fim_result_destroy).  The whole computation
+ * (item supports, bitmap build, estimate, support counting, result
+ * compaction) runs on the context's GPU and stream; the call returns after
+ * the result has been copied to host memory.
+ * Errors: FIM_E_INVALID_ARG (minsup_abs == 0, NULL db/out, db of another
+ * device), FIM_E_OUTPUT_LIMIT (no partial result), FIM_E_OOM_DEVICE,
+ * FIM_E_OOM_HOST, FIM_E_DEVICE.
+ */
+fim_status fim_mine(fim_ctx *ctx, const fim_db *db, uint32_t minsup_abs, const fim_options *opts,
+                    fim_result **out);
+
+/*
+ * Mine n independent instances in one persistent launch (captured in a HIP
+ * graph).  dbs[n] and minsups[n]; outs[n] receives one result per instance,
+ * identical to what fim_mine returns for that instance.  All-or-nothing: on
+ * error no result is returned.
+ */
+fim_status fim_mine_batch(fim_ctx *ctx, uint32_t n, const fim_db *const *dbs,
+                          const uint32_t *minsups, const fim_options *opts, fim_result **outs);
+
+/* ------------------------------------------------------------------ */
+/* Results                                                            */
+
+/*
+ * Statistics of one mining run.
+ *  candidates       support computations of item pairs inside classes
+ *                   (sum over classes of k(k-1)/2 for k extensions)
+ *  pair_words       32-bit bitmap words AND-popcounted for those candidates
+ *  item_supports    level-1 supports computed (= number of item ids)
+ *  n_frequent_items frequent items (1-itemsets)
+ *  bytes_algorithmic sibling bitmap bytes read once per class plus child
+ *                   bitmap bytes written once
+ *  kernel_ns        GPU time of the support-counting kernels
+ *  total_ns         wall time of the whole call
+ *  estimate_ns      wall time of the sample-based estimate
+ *  n_tasks          work items given to the persistent kernel
+ *  retries          re-runs after an arena overflow
+ */
+typedef struct fim_stats {
+    uint64_t candidates;
+    uint64_t pair_words;
+    uint64_t item_supports;
+    uint64_t n_frequent_items;
+    uint64_t bytes_algorithmic;
+    uint64_t kernel_ns;
+    uint64_t total_ns;
+    uint64_t estimate_ns;
+    uint64_t n_tasks;
+    uint64_t retries;
+} fim_stats;
+
+/* Number of itemsets and total number of items over all itemsets. */
+fim_status fim_result_sizes(const fim_result *r, uint64_t *n_itemsets, uint64_t *n_items_total);
+
+/*
+ * Copy the result in canonical order into caller arrays:
+ *   offsets[n_itemsets + 1], items[n_items_total], supports[n_itemsets].
+ * Itemset i is items[offsets[i] .. offsets[i+1]) ascending by item id; the
+ * itemsets are in lexicographic order (definition of the lexicographic order
+ * of itemsets in the chapter on executing Eclat in Phase 4: a prefix comes
+ * before its extensions).  The empty itemset is never reported.  Any of the
+ * three pointers may be NULL to skip that array.
+ */
+fim_status fim_result_copy(const fim_result *r, uint64_t *offsets, uint32_t *items,
+                           uint32_t *supports);
+
+fim_status fim_result_stats(const fim_result *r, fim_stats *out);
+void fim_result_destroy(fim_result *r);
+
+/* ------------------------------------------------------------------ */
+/* Serving (continuous batching)                                      */
+
+typedef struct fim_server fim_server;
+
+/*
+ * Server configuration.
+ *  max_active        requests resident on the GPU at once (slots)
+ *  max_queue         waiting requests before submit returns FIM_E_BUSY
+ *  hbm_budget_bytes  device memory the server may hold for resident
+ *                    requests (admission by footprint); 0 = 3/4 of free memory
+ *  step_tasks        work items per persistent step launch (0 = automatic)
+ *  opts              mining options applied to every request
+ */
+typedef struct fim_server_config {
+    uint32_t max_active;
+    uint32_t max_queue;
+    uint64_t hbm_budget_bytes;
+    uint32_t step_tasks;
+    fim_options opts;
+} fim_server_config;
+
+typedef struct fim_server_stats {
+    uint64_t submitted;
+    uint64_t completed;
+    uint64_t cancelled;
+    uint64_t steps;
+    uint64_t peak_active;
+    uint64_t peak_bytes;
+} fim_server_stats;
+
+/*
+ * Start a server on ctx (the server owns a worker thread that drives the GPU;
+ * the ctx must not be used by other calls until fim_server_destroy).
+ * cfg may be NULL for defaults.
+ */
+fim_status fim_server_create(fim_ctx *ctx, const fim_server_config *cfg, fim_server **out);
+
+/*
+ * Submit a request (db must stay alive until its result was taken or it was
+ * cancelled).  Thread-safe.  *ticket identifies the request.
+ * Errors: FIM_E_INVALID_ARG, FIM_E_BUSY (queue full).
+ */
+fim_status fim_server_submit(fim_server *s, const fim_db *db, uint32_t minsup_abs,
+                             uint64_t *ticket);
+
+/*
+ * Non-blocking: *out = the result if the request finished (ownership passes
+ * to the caller and the ticket is retired), NULL while it is pending.
+ * Errors: FIM_E_NOT_FOUND, FIM_E_CANCELLED, or the request's own error.
+ */
+fim_status fim_server_poll(fim_server *s, uint64_t ticket, fim_result **out);
+
+/* Blocking variant of fim_server_poll. */
+fim_status fim_server_wait(fim_server *s, uint64_t ticket, fim_result **out);
+
+/* Cancel a waiting or running request (its later poll gives FIM_E_CANCELLED). */
+fim_status fim_server_cancel(fim_server *s, uint64_t ticket);
+
+fim_status fim_server_stats_get(const fim_server *s, fim_server_stats *out);
+
+/* Stop the worker thread, cancel what is pending, free the server. */
+void fim_server_destroy(fim_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FIM_H */
