@@ -84,8 +84,9 @@ typedef struct fim_ctx fim_ctx;
 
 /*
  * Create a context on GPU `device` (HIP ordinal).  hip_stream is a
- * hipStream_t cast to void* (NULL = the null stream); all GPU work of the
- * context is ordered on it.  alloc may be NULL (hipMalloc / hipFree are then
+ * hipStream_t cast to void*; all GPU work of the context is ordered on it.
+ * NULL makes the library create (and later destroy) a stream of its own,
+ * since graph capture cannot use the null stream.  alloc may be NULL (hipMalloc / hipFree are then
  * used).  The allocator struct is copied.
  * Errors: FIM_E_INVALID_ARG (out == NULL), FIM_E_NO_DEVICE (no such device or
  * not gfx950), FIM_E_DEVICE.

@@ -1,0 +1,374 @@
+"""Python binding of ``libfim.so``, the MI355X frequent-itemset miner.
+
+The binding only marshals arguments: every step of mining runs in the HIP
+kernels and the C++ runtime of the library (``include/fim.h`` documents the
+ABI).  PyTorch, when present, supplies device memory (its caching
+allocator) and the HIP stream; without it the library uses hipMalloc and
+the null stream.  There is no CPU fallback: if the library or a gfx950 GPU
+is missing, the calls raise.
+
+Low level: functions named like the C entry points (``fim_ctx_create`` ...)
+taking and returning opaque handles.  High level: :class:`Context`,
+:class:`Database`, :func:`mine`, :func:`mine_batch`, :class:`Server`.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfim.so")
+
+FIM_OK = 0
+FIM_E_INVALID_ARG = -1
+FIM_E_ITEM_RANGE = -2
+FIM_E_OOM_HOST = -3
+FIM_E_OOM_DEVICE = -4
+FIM_E_DEVICE = -5
+FIM_E_OUTPUT_LIMIT = -6
+FIM_E_BUSY = -7
+FIM_E_CANCELLED = -8
+FIM_E_NOT_FOUND = -9
+FIM_E_NO_DEVICE = -10
+
+FIM_FLAG_NO_ESTIMATE = 0x1
+FIM_FLAG_ORDER_BY_ID = 0x2
+FIM_FLAG_NO_SPLIT = 0x4
+
+EXPORTED = [
+    "fim_status_str", "fim_last_error", "fim_version", "fim_ctx_create", "fim_ctx_destroy",
+    "fim_db_create", "fim_db_destroy", "fim_db_sizes", "fim_minsup_from_relative", "fim_mine",
+    "fim_mine_batch", "fim_result_sizes", "fim_result_copy", "fim_result_stats",
+    "fim_result_destroy", "fim_server_create", "fim_server_submit", "fim_server_poll",
+    "fim_server_wait", "fim_server_cancel", "fim_server_stats_get", "fim_server_destroy",
+]
+
+
+class FimError(RuntimeError):
+    def __init__(self, status: int, name: str, message: str):
+        super().__init__("%s (%d): %s" % (name, status, message))
+        self.status = status
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class fim_allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
+class fim_options(ctypes.Structure):
+    _fields_ = [("max_len", ctypes.c_uint32), ("max_itemsets", ctypes.c_uint64),
+                ("seed", ctypes.c_uint64), ("alpha", ctypes.c_double),
+                ("sample_tx", ctypes.c_uint32), ("sample_fi", ctypes.c_uint32),
+                ("tile_words", ctypes.c_uint32), ("classes_per_wg", ctypes.c_uint32),
+                ("workers", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+class fim_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "candidates", "pair_words", "item_supports", "n_frequent_items", "bytes_algorithmic",
+        "kernel_ns", "total_ns", "estimate_ns", "n_tasks", "retries")]
+
+
+class fim_server_config(ctypes.Structure):
+    _fields_ = [("max_active", ctypes.c_uint32), ("max_queue", ctypes.c_uint32),
+                ("hbm_budget_bytes", ctypes.c_uint64), ("step_tasks", ctypes.c_uint32),
+                ("opts", fim_options)]
+
+
+class fim_server_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "submitted", "completed", "cancelled", "steps", "peak_active", "peak_bytes")]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded ``libfim.so`` (built first if it does not exist yet)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        from .build import build
+        build()
+    # PyTorch ships its own HIP runtime.  Loading it first makes libfim.so
+    # bind to that same runtime (matched by soname), so the process holds one
+    # runtime and torch's memory and streams are valid for the library.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = ctypes.CDLL(LIB_PATH)
+    P, V = ctypes.POINTER, ctypes.c_void_p
+    u32, u64, i32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
+    sig = {
+        "fim_status_str": (ctypes.c_char_p, [i32]),
+        "fim_last_error": (ctypes.c_char_p, []),
+        "fim_version": (ctypes.c_char_p, []),
+        "fim_ctx_create": (i32, [ctypes.c_int, V, P(fim_allocator), P(V)]),
+        "fim_ctx_destroy": (None, [V]),
+        "fim_db_create": (i32, [V, u64, P(u64), P(u32), u32, P(V)]),
+        "fim_db_destroy": (None, [V]),
+        "fim_db_sizes": (i32, [V, P(u64), P(u64)]),
+        "fim_minsup_from_relative": (i32, [u64, ctypes.c_double, P(u32)]),
+        "fim_mine": (i32, [V, V, u32, P(fim_options), P(V)]),
+        "fim_mine_batch": (i32, [V, u32, P(V), P(u32), P(fim_options), P(V)]),
+        "fim_result_sizes": (i32, [V, P(u64), P(u64)]),
+        "fim_result_copy": (i32, [V, P(u64), P(u32), P(u32)]),
+        "fim_result_stats": (i32, [V, P(fim_stats)]),
+        "fim_result_destroy": (None, [V]),
+        "fim_server_create": (i32, [V, P(fim_server_config), P(V)]),
+        "fim_server_submit": (i32, [V, V, u32, P(u64)]),
+        "fim_server_poll": (i32, [V, u64, P(V)]),
+        "fim_server_wait": (i32, [V, u64, P(V)]),
+        "fim_server_cancel": (i32, [V, u64]),
+        "fim_server_stats_get": (i32, [V, P(fim_server_stats)]),
+        "fim_server_destroy": (None, [V]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != FIM_OK:
+        L = lib()
+        raise FimError(status, L.fim_status_str(status).decode(), L.fim_last_error().decode())
+
+
+def _u64p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+
+
+def _u32p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+
+
+# ---------------------------------------------------------------- C-named calls
+
+def fim_version() -> str:
+    return lib().fim_version().decode()
+
+
+def fim_ctx_create(device: int = 0, hip_stream: int | None = None, allocator=None):
+    h = ctypes.c_void_p()
+    _check(lib().fim_ctx_create(device, hip_stream, ctypes.byref(allocator) if allocator else None,
+                                ctypes.byref(h)))
+    return h
+
+
+def fim_ctx_destroy(ctx):
+    lib().fim_ctx_destroy(ctx)
+
+
+def fim_db_create(ctx, offsets, items, n_item_ids: int):
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    items = np.ascontiguousarray(items, dtype=np.uint32)
+    h = ctypes.c_void_p()
+    _check(lib().fim_db_create(ctx, len(offsets) - 1, _u64p(offsets),
+                               _u32p(items) if len(items) else None, n_item_ids, ctypes.byref(h)))
+    return h
+
+
+def fim_db_destroy(db):
+    lib().fim_db_destroy(db)
+
+
+def fim_minsup_from_relative(n_tx: int, rel: float) -> int:
+    out = ctypes.c_uint32()
+    _check(lib().fim_minsup_from_relative(n_tx, rel, ctypes.byref(out)))
+    return out.value
+
+
+def make_options(**kw) -> fim_options:
+    o = fim_options()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def fim_mine(ctx, db, minsup: int, opts: fim_options | None = None):
+    h = ctypes.c_void_p()
+    _check(lib().fim_mine(ctx, db, minsup, ctypes.byref(opts) if opts else None, ctypes.byref(h)))
+    return h
+
+
+def fim_mine_batch(ctx, dbs, minsups, opts: fim_options | None = None):
+    n = len(dbs)
+    arr = (ctypes.c_void_p * n)(*[d.value for d in dbs])
+    ms = np.ascontiguousarray(minsups, dtype=np.uint32)
+    outs = (ctypes.c_void_p * n)()
+    _check(lib().fim_mine_batch(ctx, n, arr, _u32p(ms), ctypes.byref(opts) if opts else None,
+                                outs))
+    return [ctypes.c_void_p(outs[i]) for i in range(n)]
+
+
+def fim_result_take(res) -> "Result":
+    """Copy a result handle into numpy arrays and destroy the handle."""
+    L = lib()
+    n, ni = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(L.fim_result_sizes(res, ctypes.byref(n), ctypes.byref(ni)))
+    off = np.zeros(n.value + 1, np.uint64)
+    items = np.zeros(max(ni.value, 1), np.uint32)
+    supp = np.zeros(max(n.value, 1), np.uint32)
+    _check(L.fim_result_copy(res, _u64p(off), _u32p(items), _u32p(supp)))
+    st = fim_stats()
+    _check(L.fim_result_stats(res, ctypes.byref(st)))
+    L.fim_result_destroy(res)
+    stats = {name: int(getattr(st, name)) for name, _ in fim_stats._fields_}
+    return Result(off, items[:ni.value], supp[:n.value], stats)
+
+
+# ---------------------------------------------------------------- high level
+
+@dataclass
+class Result:
+    """Frequent itemsets in canonical order (CSR) and run statistics."""
+    offsets: np.ndarray
+    items: np.ndarray
+    supports: np.ndarray
+    stats: dict = field(default_factory=dict)
+
+    def __len__(self):
+        return len(self.supports)
+
+    def itemsets(self):
+        o = self.offsets
+        return [tuple(self.items[o[i]:o[i + 1]].tolist()) for i in range(len(self))]
+
+    def as_dict(self):
+        return dict(zip(self.itemsets(), self.supports.tolist()))
+
+
+class Context:
+    """A GPU, a HIP stream and a device allocator (PyTorch's when available)."""
+
+    def __init__(self, device: int = 0, use_torch: bool = True):
+        self.device = device
+        self._keep = []
+        stream, alloc = None, None
+        if use_torch:
+            try:
+                import torch
+            except ImportError:
+                torch = None
+            if torch is not None and torch.cuda.is_available():
+                torch.cuda.set_device(device)
+                self.stream = torch.cuda.Stream(device)  # default priority
+                stream = self.stream.cuda_stream
+
+                def _alloc(nbytes, strm, user):
+                    try:
+                        return torch.cuda.caching_allocator_alloc(int(nbytes), device,
+                                                                  int(strm or 0))
+                    except Exception:
+                        return None
+
+                def _free(ptr, strm, user):
+                    torch.cuda.caching_allocator_delete(ptr)
+
+                fa, ff = ALLOC_FN(_alloc), FREE_FN(_free)
+                alloc = fim_allocator(fa, ff, None)
+                self._keep += [fa, ff, alloc]
+        self.handle = fim_ctx_create(device, stream, alloc)
+
+    def close(self):
+        if self.handle:
+            fim_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Database:
+    """A transaction database resident on the context's GPU."""
+
+    def __init__(self, ctx: Context, offsets, items, n_item_ids: int):
+        self.ctx = ctx
+        self.handle = fim_db_create(ctx.handle, offsets, items, n_item_ids)
+        n, nnz = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().fim_db_sizes(self.handle, ctypes.byref(n), ctypes.byref(nnz)))
+        self.n_tx, self.nnz = n.value, nnz.value
+
+    def close(self):
+        if self.handle:
+            fim_db_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mine(ctx: Context, db: Database, minsup: int, **opts) -> Result:
+    o = make_options(**opts) if opts else None
+    return fim_result_take(fim_mine(ctx.handle, db.handle, minsup, o))
+
+
+def mine_batch(ctx: Context, dbs, minsups, **opts):
+    o = make_options(**opts) if opts else None
+    return [fim_result_take(h) for h in fim_mine_batch(ctx.handle, [d.handle for d in dbs],
+                                                       minsups, o)]
+
+
+class Server:
+    """Continuous-batching request loop on one GPU."""
+
+    def __init__(self, ctx: Context, max_active: int = 0, max_queue: int = 0,
+                 hbm_budget_bytes: int = 0, **opts):
+        cfg = fim_server_config()
+        cfg.max_active, cfg.max_queue, cfg.hbm_budget_bytes = max_active, max_queue, hbm_budget_bytes
+        if opts:
+            cfg.opts = make_options(**opts)
+        self.ctx = ctx
+        self.handle = ctypes.c_void_p()
+        _check(lib().fim_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(self.handle)))
+
+    def submit(self, db: Database, minsup: int) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().fim_server_submit(self.handle, db.handle, minsup, ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        h = ctypes.c_void_p()
+        _check(lib().fim_server_poll(self.handle, ticket, ctypes.byref(h)))
+        return fim_result_take(h) if h.value else None
+
+    def wait(self, ticket: int) -> Result:
+        h = ctypes.c_void_p()
+        _check(lib().fim_server_wait(self.handle, ticket, ctypes.byref(h)))
+        return fim_result_take(h)
+
+    def cancel(self, ticket: int):
+        _check(lib().fim_server_cancel(self.handle, ticket))
+
+    def stats(self) -> dict:
+        st = fim_server_stats()
+        _check(lib().fim_server_stats_get(self.handle, ctypes.byref(st)))
+        return {name: int(getattr(st, name)) for name, _ in fim_server_stats._fields_}
+
+    def close(self):
+        if self.handle:
+            lib().fim_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,104 @@
+// Host-side internals of libfim.so (not part of the public ABI).
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/fim.h"
+#include "fim_internal.h"
+
+struct fim_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;  // created by the library when the caller gave none
+    fim_allocator alloc{};
+    bool user_alloc = false;
+    int n_cu = 256;
+    size_t total_mem = 0;
+    std::string arch;
+
+    void *dalloc(size_t bytes);
+    void dfree(void *p);
+    ~fim_ctx();
+};
+
+namespace fim {
+
+// Device buffer released through the context's allocator.
+class DevBuf {
+   public:
+    DevBuf() = default;
+    explicit DevBuf(fim_ctx *ctx) : ctx_(ctx) {}
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept { *this = std::move(o); }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) {
+            reset();
+            ctx_ = o.ctx_;
+            p_ = o.p_;
+            bytes_ = o.bytes_;
+            o.p_ = nullptr;
+            o.bytes_ = 0;
+        }
+        return *this;
+    }
+    ~DevBuf() { reset(); }
+    // (re)allocate at least `bytes` (contents are not kept); false on failure
+    bool ensure(fim_ctx *ctx, size_t bytes);
+    void reset();
+    template <class T>
+    T *as() const { return reinterpret_cast<T *>(p_); }
+    size_t bytes() const { return bytes_; }
+
+   private:
+    fim_ctx *ctx_ = nullptr;
+    void *p_ = nullptr;
+    size_t bytes_ = 0;
+};
+
+// Thread-local error text and status helpers.
+fim_status set_error(fim_status s, const std::string &msg);
+
+}  // namespace fim
+
+struct fim_db {
+    fim_ctx *ctx = nullptr;
+    uint64_t n_tx = 0, nnz = 0;
+    uint32_t n_item_ids = 0;
+    std::vector<uint64_t> h_off;   // canonical CSR (sorted, duplicate-free transactions)
+    std::vector<uint32_t> h_items;
+    fim::DevBuf d_off, d_items;
+};
+
+struct fim_result {
+    std::vector<uint64_t> off{0};
+    std::vector<uint32_t> items, supp;
+    fim_stats stats{};
+    bool truncated = false;  // internal sample runs only: output budget exceeded
+};
+
+namespace fim {
+
+// Internal option flag: the run mines a database sample for the estimate;
+// its output is capped at a fixed budget instead of growing, and an
+// exceeded budget marks the results truncated instead of failing.
+constexpr uint32_t kFlagInternalSample = 0x80000000u;
+
+// One mining instance inside a (possibly batched) run.
+struct MineRequest {
+    const fim_db *db;
+    uint32_t minsup;
+};
+
+// Mine every request; results[i] receives the canonical result of request i.
+// Used by fim_mine (one request), fim_mine_batch and the server.
+fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const fim_options &opts,
+                     std::vector<fim_result *> &results, bool use_graph);
+
+// Resolved option values.
+fim_options resolve_options(const fim_options *opts);
+
+}  // namespace fim

@@ -1,0 +1,100 @@
+// Internal declarations shared by the host runtime and the HIP kernels of
+// libfim.so.  Nothing here is part of the public ABI (include/fim.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fim {
+
+// Bitmap layout: item row r holds bit (t % 32) of word (t / 32) for every
+// transaction t that contains the item (LSB first).  Rows are padded to a
+// multiple of kRowAlign words with zero words, so that 128-bit loads never
+// cross a row and the padding never adds to a popcount.
+constexpr uint32_t kRowAlign = 4;
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+// Largest class depth below a first-level class that one worker can hold.
+constexpr int kMaxDepth = 96;
+
+// Device-side description of one mining instance.
+struct InstDesc {
+    const uint32_t *rows;        // level-1 arena, n_freq rows of Wp words, rank order
+    const uint32_t *item_of_rank;// original item id of each rank (order tie-break)
+    const uint32_t *l2_off;      // [n_freq + 1] CSR of the atoms of each first-level class
+    const uint32_t *l2_atom;     // ranks of the atoms, ascending (support, item id)
+    const uint32_t *l2_supp;     // supports of {rank, atom}
+    uint32_t Wp;                 // words per row (multiple of kRowAlign)
+    uint32_t n_freq;             // frequent items
+    uint32_t minsup;             // absolute minimum support
+    uint32_t max_len;            // longest itemset to report (0 = unlimited)
+    uint32_t order_by_id;        // 1: extensions in item-id order instead of support
+    uint32_t pad_;
+};
+
+// One unit of work of the persistent kernel: rows [r0, r1) of the
+// first-level class of rank `node` of instance `inst`, i.e. the classes
+// [{node, a_r} | later atoms] for those rows and everything below them.
+struct Task {
+    uint32_t inst;
+    uint32_t node;
+    uint32_t r0;
+    uint32_t r1;
+};
+
+// Global counters of a persistent launch (device memory, zeroed before it).
+struct DfsCounters {
+    unsigned long long task_head;   // next task to hand out
+    unsigned long long out_used;    // output words reserved (may pass capacity)
+    unsigned long long candidates;  // pair supports computed
+    unsigned long long pair_words;  // words AND-popcounted
+    unsigned long long child_rows;  // child bitmaps written
+    unsigned long long stack_need;  // largest per-worker stack use seen (words)
+    unsigned int flags;             // kFlag* bits
+    unsigned int pad_;
+};
+
+// Per-instance counters of a persistent launch (device memory, zeroed).
+struct InstCounters {
+    unsigned long long candidates;  // pair supports computed
+    unsigned long long pair_words;  // words AND-popcounted
+    unsigned long long child_rows;  // child bitmaps written
+    unsigned long long pad_;
+};
+
+constexpr unsigned kFlagStackOverflow = 1u;
+constexpr unsigned kFlagDepthOverflow = 2u;
+constexpr unsigned kFlagOutOverflow = 4u;
+
+// Output record layout (32-bit words): inst, len, support, len ranks.
+constexpr uint32_t kRecHeader = 3;
+
+// ---------------------------------------------------------------- launches
+// All launches are asynchronous on `stream`; they return hipSuccess or the
+// launch error.
+
+hipError_t launch_item_count(const uint64_t *offsets, const uint32_t *items, uint64_t n_tx,
+                             uint32_t *counts, uint32_t n_item_ids, hipStream_t stream);
+
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t stream);
+
+hipError_t launch_bitmap_build(const uint64_t *offsets, const uint32_t *items, uint64_t n_tx,
+                               const uint32_t *rank_of_item, uint32_t *rows, uint32_t Wp,
+                               hipStream_t stream);
+
+// Upper-triangle pair supports of the n rows (the root class): every pair
+// (i < j) with popcount(row_i & row_j) >= minsup is appended as
+// (i, j, support) to pairs (capacity cap triples); *n_pairs counts all
+// frequent pairs (it may exceed cap, then nothing past cap is written).
+hipError_t launch_root_pairs(const uint32_t *rows, uint32_t n, uint32_t Wp, uint32_t minsup,
+                             uint32_t *pairs, uint64_t cap, unsigned long long *n_pairs,
+                             uint32_t tile_words, hipStream_t stream);
+
+// Persistent depth-first search over the tasks.
+hipError_t launch_dfs(const InstDesc *insts, const Task *tasks, uint64_t n_tasks,
+                      uint32_t *stack, uint64_t stack_words, uint32_t n_workers,
+                      uint32_t tasks_per_claim, uint32_t *out, uint64_t out_cap,
+                      DfsCounters *ctr, InstCounters *ictr, hipStream_t stream);
+
+}  // namespace fim

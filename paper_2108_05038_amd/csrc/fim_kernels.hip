@@ -1,0 +1,532 @@
+// HIP kernels of the frequent-itemset miner, written for gfx950 (CDNA4,
+// wave64).  Support counting is integer AND + popcount over vertical
+// transaction bitmaps (the bitmap form of the thesis's lemma that the
+// support of an itemset is the size of the intersection of the tid-lists of
+// two of its covering subsets, appendix "The Eclat algorithm", subsection
+// "Support counting").  No MFMA: the work is bitwise, and most of it is
+// bound by memory or by the integer vector ALU.
+#include "fim_internal.h"
+
+namespace fim {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ __forceinline__ uint32_t popc4(uint4 a, uint4 b) {
+    return __popc(a.x & b.x) + __popc(a.y & b.y) + __popc(a.z & b.z) + __popc(a.w & b.w);
+}
+
+__device__ __forceinline__ uint4 and4(uint4 a, uint4 b) {
+    return make_uint4(a.x & b.x, a.y & b.y, a.z & b.z, a.w & b.w);
+}
+
+// number of set bits of `mask` in lanes below this one
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+    uint32_t lo = __shfl((uint32_t)v, src, kWave);
+    uint32_t hi = __shfl((uint32_t)(v >> 32), src, kWave);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs of the chip.  Renumber
+// them so that each XCD receives a contiguous range of logical block ids,
+// which keeps neighbouring tiles (sharing rows) in the same L2.
+__device__ __forceinline__ uint32_t xcd_local_block(uint32_t b, uint32_t nblocks) {
+    constexpr uint32_t kXcd = 8;
+    uint32_t q = nblocks / kXcd, rmd = nblocks % kXcd;
+    uint32_t x = b % kXcd, l = b / kXcd;
+    uint32_t start = x < rmd ? x * (q + 1) : rmd * (q + 1) + (x - rmd) * q;
+    return start + l;
+}
+
+// ------------------------------------------------------------------ a2: item supports
+
+__global__ __launch_bounds__(kBlock) void k_item_count(const uint32_t *__restrict__ items,
+                                                        uint64_t nnz, uint32_t *counts,
+                                                        uint32_t n_item_ids, int use_lds) {
+    extern __shared__ uint32_t hist[];
+    if (use_lds) {
+        for (uint32_t i = threadIdx.x; i < n_item_ids; i += kBlock) hist[i] = 0;
+        __syncthreads();
+    }
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x; p < nnz; p += stride) {
+        uint32_t it = items[p];  // transactions are duplicate-free after ingest
+        if (use_lds) atomicAdd(&hist[it], 1u);
+        else atomicAdd(&counts[it], 1u);
+    }
+    if (use_lds) {
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < n_item_ids; i += kBlock)
+            if (hist[i]) atomicAdd(&counts[i], hist[i]);
+    }
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+// ------------------------------------------------------------------ a3: bitmap build
+// One thread per transaction; each frequent item of transaction t sets bit
+// t % 32 of word t / 32 of its row.
+
+__global__ __launch_bounds__(kBlock) void k_bitmap_build(const uint64_t *__restrict__ offsets,
+                                                          const uint32_t *__restrict__ items,
+                                                          uint64_t n_tx,
+                                                          const uint32_t *__restrict__ rank_of_item,
+                                                          uint32_t *rows, uint32_t Wp) {
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < n_tx; t += stride) {
+        const uint32_t bit = 1u << (t & 31);
+        const uint64_t w = t >> 5;
+        for (uint64_t p = offsets[t], e = offsets[t + 1]; p < e; p++) {
+            uint32_t r = rank_of_item[items[p]];
+            if (r != kNone) atomicOr(&rows[(uint64_t)r * Wp + w], bit);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ a6/a7: root class pairs
+// The root class [{} | all frequent items]: the upper triangle of the
+// popcount-Gram of the item rows.  A block owns a 64 x 64 tile of pairs;
+// word tiles of both row blocks are staged in LDS, so every loaded word is
+// reused by 64 pairs; each thread keeps a 4 x 4 block of accumulators.
+
+constexpr int kRootRows = 64;
+constexpr int kRootTw = 32;  // words per LDS tile
+
+__global__ __launch_bounds__(kBlock) void k_root_pairs(const uint32_t *__restrict__ rows,
+                                                        uint32_t n, uint32_t Wp, uint32_t minsup,
+                                                        uint32_t *pairs, uint64_t cap,
+                                                        unsigned long long *n_pairs) {
+    __shared__ uint32_t sI[kRootRows][kRootTw + 1];
+    __shared__ uint32_t sJ[kRootRows][kRootTw + 1];
+
+    // logical tile index -> (bi <= bj) in the upper triangle of tiles
+    const uint32_t b = xcd_local_block(blockIdx.x, gridDim.x);
+    uint32_t bj = (uint32_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+    while ((uint64_t)bj * (bj + 1) / 2 > b) bj--;
+    while ((uint64_t)(bj + 1) * (bj + 2) / 2 <= b) bj++;
+    const uint32_t bi = b - bj * (bj + 1) / 2;
+    const uint32_t I0 = bi * kRootRows, J0 = bj * kRootRows;
+
+    const uint32_t tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    uint32_t acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int c = 0; c < 4; c++) acc[a][c] = 0;
+
+    for (uint32_t w0 = 0; w0 < Wp; w0 += kRootTw) {
+        // 64 rows x 32 words per side = 512 uint4; 2 per thread per side
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+            uint32_t idx = threadIdx.x + q * kBlock;  // 0..511
+            uint32_t row = idx >> 3, c4 = (idx & 7) * 4;
+            uint4 vi = make_uint4(0, 0, 0, 0), vj = make_uint4(0, 0, 0, 0);
+            if (w0 + c4 < Wp) {
+                if (I0 + row < n)
+                    vi = *reinterpret_cast<const uint4 *>(rows + (uint64_t)(I0 + row) * Wp + w0 + c4);
+                if (J0 + row < n)
+                    vj = *reinterpret_cast<const uint4 *>(rows + (uint64_t)(J0 + row) * Wp + w0 + c4);
+            }
+            sI[row][c4 + 0] = vi.x;
+            sI[row][c4 + 1] = vi.y;
+            sI[row][c4 + 2] = vi.z;
+            sI[row][c4 + 3] = vi.w;
+            sJ[row][c4 + 0] = vj.x;
+            sJ[row][c4 + 1] = vj.y;
+            sJ[row][c4 + 2] = vj.z;
+            sJ[row][c4 + 3] = vj.w;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int w = 0; w < kRootTw; w++) {
+            uint32_t x[4], y[4];
+#pragma unroll
+            for (int a = 0; a < 4; a++) x[a] = sI[ty + 16 * a][w];
+#pragma unroll
+            for (int c = 0; c < 4; c++) y[c] = sJ[tx + 16 * c][w];
+#pragma unroll
+            for (int a = 0; a < 4; a++)
+#pragma unroll
+                for (int c = 0; c < 4; c++) acc[a][c] += __popc(x[a] & y[c]);
+        }
+        __syncthreads();
+    }
+
+    // threshold, then compact the frequent pairs of the wave with one atomic
+    uint32_t mine = 0;
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            uint32_t i = I0 + ty + 16 * a, j = J0 + tx + 16 * c;
+            bool ok = i < n && j < n && i < j && acc[a][c] >= minsup;
+            mine += ok ? 1u : 0u;
+        }
+    // exclusive scan of `mine` over the wave
+    uint32_t incl = mine;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        uint32_t v = __shfl_up(incl, off, kWave);
+        if ((int)lane_id() >= off) incl += v;
+    }
+    uint32_t total = __shfl(incl, kWave - 1, kWave);
+    unsigned long long base = 0;
+    if (lane_id() == 0 && total) base = atomicAdd(n_pairs, (unsigned long long)total);
+    base = shfl_u64(base, 0);
+    uint64_t pos = base + incl - mine;
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            uint32_t i = I0 + ty + 16 * a, j = J0 + tx + 16 * c;
+            if (i < n && j < n && i < j && acc[a][c] >= minsup) {
+                if (pos < cap) {
+                    pairs[3 * pos + 0] = i;
+                    pairs[3 * pos + 1] = j;
+                    pairs[3 * pos + 2] = acc[a][c];
+                }
+                pos++;
+            }
+        }
+}
+
+// ------------------------------------------------------------------ a5-a8: persistent DFS
+//
+// Every wave is one worker with a private region of `stack_words` words:
+// bitmap rows of the classes on its DFS path grow up from the bottom, atom
+// lists (ranks, supports, source rows) grow down from the top.  A worker
+// repeatedly claims tasks (rows [r0, r1) of a first-level class) from a
+// global counter, materialises the class's sibling bitmaps along the prefix
+// path (the thesis's Prepare-Tidlists for a prefix of length one), and runs
+// Eclat-DFS-Computation below those rows: for a row r of a class with k
+// atoms, the supports of (r, j) for all later atoms j are AND-popcounts of
+// the two rows; the frequent ones are reported, ordered by ascending
+// support (ties by item id), their bitmaps are written, and that child
+// class is searched before row r + 1.
+
+struct Frame {
+    uint32_t rows_base;    // word offset of the class's row 0
+    uint32_t k;            // atoms (rows) of the class
+    uint32_t r;            // next row to expand
+    uint32_t r_end;        // rows [0, r_end) are expanded
+    uint32_t atoms;        // word offset of ranks[k]; supports at +stride, source rows at +2*stride
+    uint32_t stride;       // capacity of each of the three atom arrays
+    uint32_t meta_restore; // meta pointer to restore when the class is done
+    uint32_t pad_;
+};
+
+struct WaveShared {
+    Frame frames[kMaxDepth];
+    uint32_t prefix[kMaxDepth + 3];
+};
+
+struct WaveStats {
+    unsigned long long candidates, pair_words, child_rows;
+};
+
+// Sorts nf atoms (arrays of stride `si` at tmp) ascending by (support, item
+// id) into dst (arrays of stride nf): every key's rank among all keys.
+__device__ void sort_atoms(const InstDesc &I, const uint32_t *tmp, uint32_t si, uint32_t *dst,
+                           uint32_t nf) {
+    const uint32_t lane = lane_id();
+    for (uint32_t e0 = 0; e0 < nf; e0 += kWave) {
+        const uint32_t e = e0 + lane;
+        uint64_t key = ~0ull;
+        uint32_t rk = 0, sp = 0, src = 0;
+        if (e < nf) {
+            rk = tmp[e];
+            sp = tmp[si + e];
+            src = tmp[2 * si + e];
+            key = ((uint64_t)sp << 32) | I.item_of_rank[rk];
+        }
+        uint32_t pos = 0;
+        for (uint32_t f0 = 0; f0 < nf; f0 += kWave) {
+            uint64_t kf = ~0ull;
+            if (f0 + lane < nf)
+                kf = ((uint64_t)tmp[si + f0 + lane] << 32) | I.item_of_rank[tmp[f0 + lane]];
+            const uint32_t cnt = min(nf - f0, (uint32_t)kWave);
+            for (uint32_t t = 0; t < cnt; t++) pos += (shfl_u64(kf, t) < key) ? 1u : 0u;
+        }
+        if (e < nf) {
+            dst[pos] = rk;
+            dst[nf + pos] = sp;
+            dst[2 * nf + pos] = src;
+        }
+    }
+}
+
+__device__ __forceinline__ void flag_stack(DfsCounters *ctr, uint64_t need) {
+    if (lane_id() == 0) {
+        atomicOr(&ctr->flags, kFlagStackOverflow);
+        atomicMax(&ctr->stack_need, (unsigned long long)need);
+    }
+}
+
+__device__ void process_task(const InstDesc &I, uint32_t inst, const Task &T, uint32_t *region,
+                             uint64_t S, WaveShared &ws, uint32_t *out, uint64_t out_cap,
+                             DfsCounters *ctr, WaveStats &st) {
+    const uint32_t lane = lane_id();
+    const uint32_t Wp = I.Wp, C = Wp / 4;  // 128-bit chunks per row
+    const uint32_t a0 = I.l2_off[T.node], k1 = I.l2_off[T.node + 1] - a0;
+    if (T.r0 >= T.r1 || T.r1 >= k1) return;  // a task covers rows with a later atom
+
+    // lanes per pair: enough to cover a row's chunks, at most a wave
+    uint32_t g = 1;
+    while (g < C && g < (uint32_t)kWave) g <<= 1;
+    const uint32_t ppp = kWave / g;  // pairs per pass
+    const uint32_t grp = lane / g, sub = lane % g;
+
+    // frame 0: atoms r0..k1-1 of the first-level class of T.node
+    const uint32_t k = k1 - T.r0;
+    uint64_t meta = S - 3ull * k;
+    if (3ull * k > S || (uint64_t)k * Wp > meta) {
+        flag_stack(ctr, (uint64_t)k * Wp + 3ull * k);
+        return;
+    }
+    for (uint32_t e = lane; e < k; e += kWave) {
+        region[meta + e] = I.l2_atom[a0 + T.r0 + e];
+        region[meta + k + e] = I.l2_supp[a0 + T.r0 + e];
+        region[meta + 2 * k + e] = e;
+    }
+    {
+        const uint4 *base = reinterpret_cast<const uint4 *>(I.rows + (uint64_t)T.node * Wp);
+        for (uint32_t e = 0; e < k; e++) {
+            const uint32_t atom = I.l2_atom[a0 + T.r0 + e];
+            const uint4 *src = reinterpret_cast<const uint4 *>(I.rows + (uint64_t)atom * Wp);
+            uint4 *dst = reinterpret_cast<uint4 *>(region + (uint64_t)e * Wp);
+            for (uint32_t c = lane; c < C; c += kWave) dst[c] = and4(base[c], src[c]);
+        }
+    }
+    __threadfence_block();
+
+    int depth = 0;
+    ws.frames[0] = Frame{0u, k, 0u, T.r1 - T.r0, (uint32_t)meta, k, (uint32_t)S, 0u};
+    ws.prefix[0] = T.node;
+    __builtin_amdgcn_wave_barrier();
+    uint64_t rows_top = (uint64_t)k * Wp;
+    uint64_t peak = rows_top + (S - meta);
+
+    while (depth >= 0) {
+        const Frame F = ws.frames[depth];
+        __builtin_amdgcn_wave_barrier();
+        if (F.r >= F.r_end) {
+            rows_top = F.rows_base;
+            meta = F.meta_restore;
+            depth--;
+            continue;
+        }
+        const uint32_t r = F.r;
+        ws.frames[depth].r = r + 1;
+        const uint32_t nj = F.k - r - 1;
+        if (nj == 0) continue;
+        const uint32_t *ranks = region + F.atoms;
+        ws.prefix[depth + 1] = ranks[r];
+        __builtin_amdgcn_wave_barrier();
+
+        // frequent children of row r, unsorted: ranks, supports, source rows
+        if (3ull * nj > meta || meta - 3ull * nj < rows_top) {
+            flag_stack(ctr, rows_top + (S - meta) + 3ull * nj);
+            return;
+        }
+        uint32_t *tmp = region + (meta - 3ull * nj);
+        const uint4 *row_r =
+            reinterpret_cast<const uint4 *>(region + F.rows_base + (uint64_t)r * Wp);
+        uint32_t nf = 0;
+        for (uint32_t jb = 0; jb < nj; jb += ppp) {
+            const uint32_t jj = jb + grp;
+            uint32_t acc = 0;
+            if (jj < nj) {
+                const uint4 *row_j = reinterpret_cast<const uint4 *>(
+                    region + F.rows_base + (uint64_t)(r + 1 + jj) * Wp);
+                for (uint32_t c = sub; c < C; c += g) acc += popc4(row_r[c], row_j[c]);
+            }
+            for (uint32_t off = g >> 1; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+            const bool freq = sub == 0 && jj < nj && acc >= I.minsup;
+            const uint64_t mask = __ballot(freq);
+            if (freq) {
+                const uint32_t p = nf + lanes_below(mask);
+                tmp[p] = ranks[r + 1 + jj];
+                tmp[nj + p] = acc;
+                tmp[2 * nj + p] = r + 1 + jj;
+            }
+            nf += (uint32_t)__popcll(mask);
+        }
+        st.candidates += nj;
+        st.pair_words += (unsigned long long)nj * Wp;
+        if (nf == 0) continue;
+        __threadfence_block();
+
+        // report the nf itemsets prefix[0..depth+1] + child atom
+        const uint32_t len = (uint32_t)depth + 3;
+        if (I.max_len == 0 || len <= I.max_len) {
+            const uint32_t rec = kRecHeader + len;
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(&ctr->out_used, (unsigned long long)nf * rec);
+            base = shfl_u64(base, 0);
+            if (base + (unsigned long long)nf * rec <= out_cap) {
+                for (uint32_t e = lane; e < nf; e += kWave) {
+                    uint32_t *o = out + base + (uint64_t)e * rec;
+                    o[0] = inst;
+                    o[1] = len;
+                    o[2] = tmp[nj + e];
+                    for (uint32_t q = 0; q + 1 < len; q++) o[3 + q] = ws.prefix[q];
+                    o[3 + len - 1] = tmp[e];
+                }
+            } else if (lane == 0) {
+                atomicOr(&ctr->flags, kFlagOutOverflow);
+            }
+        }
+
+        // the child class [prefix + a_r | frequent later atoms]
+        if (nf >= 2 && (I.max_len == 0 || len + 1 <= I.max_len)) {
+            if (depth + 1 >= kMaxDepth) {
+                if (lane == 0) atomicOr(&ctr->flags, kFlagDepthOverflow);
+                continue;
+            }
+            const uint64_t restore = meta;
+            uint64_t new_meta = meta - 3ull * nj;
+            const uint32_t *sorted = tmp;
+            uint32_t sstride = nj;
+            if (!I.order_by_id) {
+                if (3ull * nf > new_meta || new_meta - 3ull * nf < rows_top + (uint64_t)nf * Wp) {
+                    flag_stack(ctr, rows_top + (uint64_t)nf * Wp + (S - new_meta) + 3ull * nf);
+                    return;
+                }
+                new_meta -= 3ull * nf;
+                uint32_t *dst = region + new_meta;
+                sort_atoms(I, tmp, nj, dst, nf);
+                __threadfence_block();
+                sorted = dst;
+                sstride = nf;
+            } else if (new_meta < rows_top + (uint64_t)nf * Wp) {
+                flag_stack(ctr, rows_top + (uint64_t)nf * Wp + (S - new_meta));
+                return;
+            }
+            // child bitmaps: row_r AND row_src, in the child's atom order
+            for (uint32_t c = 0; c < nf; c++) {
+                const uint32_t src = sorted[2 * sstride + c];
+                const uint4 *row_j =
+                    reinterpret_cast<const uint4 *>(region + F.rows_base + (uint64_t)src * Wp);
+                uint4 *dst = reinterpret_cast<uint4 *>(region + rows_top + (uint64_t)c * Wp);
+                for (uint32_t q = lane; q < C; q += kWave) dst[q] = and4(row_r[q], row_j[q]);
+            }
+            __threadfence_block();
+            st.child_rows += nf;
+            ws.frames[depth + 1] = Frame{(uint32_t)rows_top, nf, 0u, nf - 1,
+                                         (uint32_t)(sorted - region), sstride, (uint32_t)restore, 0u};
+            __builtin_amdgcn_wave_barrier();
+            rows_top += (uint64_t)nf * Wp;
+            meta = new_meta;
+            depth++;
+            const uint64_t use = rows_top + (S - meta);
+            if (use > peak) peak = use;
+        }
+    }
+    if (lane == 0) atomicMax(&ctr->stack_need, (unsigned long long)peak);
+}
+
+__global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Task *tasks,
+                                                uint64_t n_tasks, uint32_t *stack,
+                                                uint64_t stack_words, uint32_t tasks_per_claim,
+                                                uint32_t *out, uint64_t out_cap,
+                                                DfsCounters *ctr, InstCounters *ictr) {
+    __shared__ WaveShared shared[kWavesPerBlock];
+    const uint32_t w = threadIdx.x / kWave;
+    const uint32_t lane = lane_id();
+    WaveShared &ws = shared[w];
+    const uint64_t wave_id = (uint64_t)blockIdx.x * kWavesPerBlock + w;
+    uint32_t *region = stack + wave_id * stack_words;
+    for (;;) {
+        unsigned long long t0 = 0;
+        if (lane == 0) t0 = atomicAdd(&ctr->task_head, (unsigned long long)tasks_per_claim);
+        t0 = shfl_u64(t0, 0);
+        if (t0 >= n_tasks) break;
+        const uint64_t t1 = min((uint64_t)t0 + tasks_per_claim, n_tasks);
+        for (uint64_t t = t0; t < t1; t++) {
+            const Task T = tasks[t];
+            WaveStats st{0, 0, 0};
+            process_task(insts[T.inst], T.inst, T, region, stack_words, ws, out, out_cap, ctr, st);
+            if (lane == 0) {
+                InstCounters &ic = ictr[T.inst];
+                if (st.candidates) atomicAdd(&ic.candidates, st.candidates);
+                if (st.pair_words) atomicAdd(&ic.pair_words, st.pair_words);
+                if (st.child_rows) atomicAdd(&ic.child_rows, st.child_rows);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launch wrappers
+
+hipError_t launch_item_count(const uint64_t *offsets, const uint32_t *items, uint64_t nnz,
+                             uint32_t *counts, uint32_t n_item_ids, hipStream_t stream) {
+    (void)offsets;
+    if (nnz == 0) return hipSuccess;
+    const int use_lds = n_item_ids <= 12288;
+    const size_t lds = use_lds ? n_item_ids * sizeof(uint32_t) : 0;
+    uint64_t blocks = (nnz + kBlock - 1) / kBlock;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_item_count, dim3((uint32_t)blocks), dim3(kBlock), lds, stream, items, nnz,
+                       counts, n_item_ids, use_lds);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    uint64_t blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_bitmap_build(const uint64_t *offsets, const uint32_t *items, uint64_t n_tx,
+                               const uint32_t *rank_of_item, uint32_t *rows, uint32_t Wp,
+                               hipStream_t stream) {
+    if (n_tx == 0) return hipSuccess;
+    uint64_t blocks = (n_tx + kBlock - 1) / kBlock;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_bitmap_build, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, offsets,
+                       items, n_tx, rank_of_item, rows, Wp);
+    return hipGetLastError();
+}
+
+hipError_t launch_root_pairs(const uint32_t *rows, uint32_t n, uint32_t Wp, uint32_t minsup,
+                             uint32_t *pairs, uint64_t cap, unsigned long long *n_pairs,
+                             uint32_t tile_words, hipStream_t stream) {
+    (void)tile_words;
+    if (n < 2) return hipSuccess;
+    const uint64_t nt = (n + kRootRows - 1) / kRootRows;
+    const uint64_t tiles = nt * (nt + 1) / 2;
+    if (tiles > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_root_pairs, dim3((uint32_t)tiles), dim3(kBlock), 0, stream, rows, n, Wp,
+                       minsup, pairs, cap, n_pairs);
+    return hipGetLastError();
+}
+
+hipError_t launch_dfs(const InstDesc *insts, const Task *tasks, uint64_t n_tasks, uint32_t *stack,
+                      uint64_t stack_words, uint32_t n_workers, uint32_t tasks_per_claim,
+                      uint32_t *out, uint64_t out_cap, DfsCounters *ctr, InstCounters *ictr,
+                      hipStream_t stream) {
+    if (n_tasks == 0) return hipSuccess;
+    const uint32_t blocks = (n_workers + kWavesPerBlock - 1) / kWavesPerBlock;
+    hipLaunchKernelGGL(k_dfs, dim3(blocks), dim3(kBlock), 0, stream, insts, tasks, n_tasks, stack,
+                       stack_words, tasks_per_claim ? tasks_per_claim : 1u, out, out_cap, ctr, ictr);
+    return hipGetLastError();
+}
+
+}  // namespace fim

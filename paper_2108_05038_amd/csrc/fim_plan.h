@@ -1,0 +1,55 @@
+// Work planning for the persistent kernel: the thesis's sample-based class
+// size estimate (Phase 1, reservoir variant), the Partition of large classes
+// and the LPT order (Phase 2).
+#pragma once
+
+#include <vector>
+
+#include "fim_host.h"
+
+namespace fim {
+
+struct PlanInput {
+    const fim_db *db;
+    uint32_t minsup;
+    uint32_t n_freq;
+    uint32_t W;
+    const std::vector<uint32_t> *item_of_rank;
+    const std::vector<uint32_t> *rank_of_item;
+    const std::vector<uint32_t> *l2_off;   // atoms of the first-level classes
+    const std::vector<uint32_t> *l2_atom;
+};
+
+// One class handed to the workers with its estimated size.
+struct PlanClass {
+    uint32_t inst, node, r0, r1;
+    double weight;   // estimated work (comparable across instances)
+    double proxy;    // size proxy used to order classes the sample does not see
+};
+
+// Default sample sizes.
+//  |D~| from Toivonen's Chernoff bound (thesis, theorem on estimating a
+//       support from a database sample): ceil(ln(2/delta) / (2 eps^2)),
+//  |S|  from the hypergeometric Kullback-Leibler bound (theorem on the
+//       estimation error of the size of a subset from a reservoir sample):
+//       ceil(-ln(delta/2) / D(rho + eps || rho)), natural logarithms.
+uint32_t default_sample_tx(double eps, double delta);
+uint32_t default_sample_fi(double rho, double eps, double delta);
+double bernoulli_kl(double x, double y);
+
+// Simple reservoir sampling (thesis, the Simple-Reservoir-Sampling
+// algorithm): keeps a uniform sample without replacement of size n of a
+// stream.  Returns the indices (positions in the stream) that were kept.
+std::vector<uint64_t> reservoir_indices(uint64_t stream_len, uint64_t n, uint64_t seed);
+
+// LPT-Schedule (Graham): jobs in decreasing weight, each to the least
+// loaded of p workers (lowest index on ties).  Returns the worker of each
+// job and the makespan.
+double lpt_schedule(const std::vector<double> &w, uint32_t p, std::vector<uint32_t> &worker);
+
+// Builds the task list of all instances in LPT order.
+fim_status plan_tasks(fim_ctx *ctx, const std::vector<PlanInput> &in, const fim_options &opts,
+                      uint32_t n_workers, std::vector<Task> &tasks,
+                      std::vector<PlanClass> *classes = nullptr);
+
+}  // namespace fim

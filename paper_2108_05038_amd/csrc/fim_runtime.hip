@@ -1,0 +1,752 @@
+// Host runtime of libfim.so: contexts, databases, the mining pipeline, the
+// sample-based class-size estimate, results.  Every step of the mining path
+// runs in the HIP kernels of fim_kernels.hip; the host decides the order of
+// work, moves data and puts the result into canonical order.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <numeric>
+
+#include "fim_host.h"
+#include "fim_plan.h"
+
+using fim::DevBuf;
+
+namespace fim {
+
+static thread_local std::string g_error;
+
+fim_status set_error(fim_status s, const std::string &msg) {
+    g_error = msg;
+    return s;
+}
+
+bool DevBuf::ensure(fim_ctx *ctx, size_t bytes) {
+    if (p_ && bytes_ >= bytes && ctx_ == ctx) return true;
+    reset();
+    ctx_ = ctx;
+    if (bytes == 0) bytes = 256;
+    p_ = ctx->dalloc(bytes);
+    if (!p_) return false;
+    bytes_ = bytes;
+    return true;
+}
+
+void DevBuf::reset() {
+    if (p_ && ctx_) ctx_->dfree(p_);
+    p_ = nullptr;
+    bytes_ = 0;
+}
+
+}  // namespace fim
+
+void *fim_ctx::dalloc(size_t bytes) {
+    if (user_alloc) return alloc.alloc(bytes, (void *)stream, alloc.user);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void fim_ctx::dfree(void *p) {
+    if (!p) return;
+    if (user_alloc) alloc.free(p, (void *)stream, alloc.user);
+    else (void)hipFree(p);
+}
+
+#define HIPCHK(call)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fim::set_error(FIM_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define ENSURE(buf, ctx, bytes)                                                               \
+    do {                                                                                      \
+        if (!(buf).ensure((ctx), (bytes)))                                                    \
+            return fim::set_error(FIM_E_OOM_DEVICE,                                           \
+                                  "device allocation of " + std::to_string((size_t)(bytes)) + \
+                                      " bytes failed");                                       \
+    } while (0)
+
+// ====================================================================== status
+
+extern "C" const char *fim_status_str(fim_status s) {
+    switch (s) {
+        case FIM_OK: return "FIM_OK";
+        case FIM_E_INVALID_ARG: return "FIM_E_INVALID_ARG";
+        case FIM_E_ITEM_RANGE: return "FIM_E_ITEM_RANGE";
+        case FIM_E_OOM_HOST: return "FIM_E_OOM_HOST";
+        case FIM_E_OOM_DEVICE: return "FIM_E_OOM_DEVICE";
+        case FIM_E_DEVICE: return "FIM_E_DEVICE";
+        case FIM_E_OUTPUT_LIMIT: return "FIM_E_OUTPUT_LIMIT";
+        case FIM_E_BUSY: return "FIM_E_BUSY";
+        case FIM_E_CANCELLED: return "FIM_E_CANCELLED";
+        case FIM_E_NOT_FOUND: return "FIM_E_NOT_FOUND";
+        case FIM_E_NO_DEVICE: return "FIM_E_NO_DEVICE";
+        default: return "FIM_E_UNKNOWN";
+    }
+}
+
+extern "C" const char *fim_last_error(void) { return fim::g_error.c_str(); }
+
+extern "C" const char *fim_version(void) { return "fim 1.0 gfx950"; }
+
+// ====================================================================== context
+
+extern "C" fim_status fim_ctx_create(int device, void *hip_stream, const fim_allocator *alloc,
+                                     fim_ctx **out) {
+    if (!out) return fim::set_error(FIM_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+        (void)hipGetLastError();
+        return fim::set_error(FIM_E_NO_DEVICE, "no HIP device " + std::to_string(device));
+    }
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, device));
+    std::string arch = prop.gcnArchName;
+    if (arch.rfind("gfx950", 0) != 0)
+        return fim::set_error(FIM_E_NO_DEVICE, "device " + std::to_string(device) + " is " + arch +
+                                                   ", this library is built for gfx950");
+    if (alloc && (!alloc->alloc || !alloc->free))
+        return fim::set_error(FIM_E_INVALID_ARG, "allocator without alloc/free");
+    HIPCHK(hipSetDevice(device));
+    fim_ctx *c = new (std::nothrow) fim_ctx();
+    if (!c) return fim::set_error(FIM_E_OOM_HOST, "ctx");
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    if (!c->stream) {  // graph capture needs a stream other than the null stream
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return fim::set_error(FIM_E_DEVICE, "hipStreamCreate failed");
+        }
+        c->own_stream = true;
+    }
+    if (alloc) {
+        c->alloc = *alloc;
+        c->user_alloc = true;
+    }
+    c->n_cu = prop.multiProcessorCount;
+    c->total_mem = prop.totalGlobalMem;
+    c->arch = arch;
+    *out = c;
+    return FIM_OK;
+}
+
+fim_ctx::~fim_ctx() {
+    if (own_stream && stream) {
+        (void)hipStreamSynchronize(stream);
+        (void)hipStreamDestroy(stream);
+    }
+}
+
+extern "C" void fim_ctx_destroy(fim_ctx *ctx) { delete ctx; }
+
+// ====================================================================== database
+
+extern "C" fim_status fim_db_create(fim_ctx *ctx, uint64_t n_tx, const uint64_t *tx_offsets,
+                                    const uint32_t *items, uint32_t n_item_ids, fim_db **out) {
+    if (!out) return fim::set_error(FIM_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!ctx || !tx_offsets || n_item_ids == 0)
+        return fim::set_error(FIM_E_INVALID_ARG, "ctx/tx_offsets NULL or n_item_ids == 0");
+    if (n_tx >= (1ull << 31)) return fim::set_error(FIM_E_INVALID_ARG, "n_tx must be < 2^31");
+    if (tx_offsets[0] != 0) return fim::set_error(FIM_E_INVALID_ARG, "tx_offsets[0] != 0");
+    for (uint64_t t = 0; t < n_tx; t++)
+        if (tx_offsets[t + 1] < tx_offsets[t])
+            return fim::set_error(FIM_E_INVALID_ARG,
+                                  "tx_offsets not monotone at " + std::to_string(t));
+    const uint64_t nnz_in = tx_offsets[n_tx];
+    if (nnz_in && !items) return fim::set_error(FIM_E_INVALID_ARG, "items is NULL");
+    fim_db *db = new (std::nothrow) fim_db();
+    if (!db) return fim::set_error(FIM_E_OOM_HOST, "db");
+    try {
+        db->h_off.resize(n_tx + 1);
+        db->h_items.resize(nnz_in);
+    } catch (...) {
+        delete db;
+        return fim::set_error(FIM_E_OOM_HOST, "db arrays");
+    }
+    // a1: transactions are sets: sort each one and drop repeated items
+    uint64_t pos = 0;
+    db->h_off[0] = 0;
+    for (uint64_t t = 0; t < n_tx; t++) {
+        const uint64_t a = tx_offsets[t], b = tx_offsets[t + 1];
+        uint32_t *dst = db->h_items.data() + pos;
+        for (uint64_t p = a; p < b; p++) {
+            if (items[p] >= n_item_ids) {
+                delete db;
+                return fim::set_error(FIM_E_ITEM_RANGE, "item " + std::to_string(items[p]) +
+                                                            " >= n_item_ids at position " +
+                                                            std::to_string(p));
+            }
+            dst[p - a] = items[p];
+        }
+        std::sort(dst, dst + (b - a));
+        uint64_t n = std::unique(dst, dst + (b - a)) - dst;
+        pos += n;
+        db->h_off[t + 1] = pos;
+    }
+    db->h_items.resize(pos);
+    db->ctx = ctx;
+    db->n_tx = n_tx;
+    db->nnz = pos;
+    db->n_item_ids = n_item_ids;
+    if (!db->d_off.ensure(ctx, (n_tx + 1) * sizeof(uint64_t)) ||
+        !db->d_items.ensure(ctx, std::max<uint64_t>(pos, 1) * sizeof(uint32_t))) {
+        delete db;
+        return fim::set_error(FIM_E_OOM_DEVICE, "db device arrays");
+    }
+    hipError_t e = hipMemcpyAsync(db->d_off.as<void>(), db->h_off.data(), (n_tx + 1) * 8,
+                                  hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess && pos)
+        e = hipMemcpyAsync(db->d_items.as<void>(), db->h_items.data(), pos * 4,
+                           hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        delete db;
+        return fim::set_error(FIM_E_DEVICE, std::string("db upload: ") + hipGetErrorString(e));
+    }
+    *out = db;
+    return FIM_OK;
+}
+
+extern "C" void fim_db_destroy(fim_db *db) { delete db; }
+
+extern "C" fim_status fim_db_sizes(const fim_db *db, uint64_t *n_tx, uint64_t *nnz) {
+    if (!db) return fim::set_error(FIM_E_INVALID_ARG, "db is NULL");
+    if (n_tx) *n_tx = db->n_tx;
+    if (nnz) *nnz = db->nnz;
+    return FIM_OK;
+}
+
+extern "C" fim_status fim_minsup_from_relative(uint64_t n_tx, double rel, uint32_t *out_abs) {
+    if (!out_abs || !(rel > 0.0) || rel > 1.0)
+        return fim::set_error(FIM_E_INVALID_ARG, "relative minimum support must be in (0, 1]");
+    double v = ceil(rel * (double)n_tx);
+    if (v < 1.0) v = 1.0;
+    if (v > 4294967295.0) return fim::set_error(FIM_E_INVALID_ARG, "minimum support overflows");
+    *out_abs = (uint32_t)v;
+    return FIM_OK;
+}
+
+// ====================================================================== results
+
+extern "C" fim_status fim_result_sizes(const fim_result *r, uint64_t *n_itemsets,
+                                       uint64_t *n_items_total) {
+    if (!r) return fim::set_error(FIM_E_INVALID_ARG, "result is NULL");
+    if (n_itemsets) *n_itemsets = r->supp.size();
+    if (n_items_total) *n_items_total = r->items.size();
+    return FIM_OK;
+}
+
+extern "C" fim_status fim_result_copy(const fim_result *r, uint64_t *offsets, uint32_t *items,
+                                      uint32_t *supports) {
+    if (!r) return fim::set_error(FIM_E_INVALID_ARG, "result is NULL");
+    if (offsets) memcpy(offsets, r->off.data(), r->off.size() * sizeof(uint64_t));
+    if (items && !r->items.empty()) memcpy(items, r->items.data(), r->items.size() * 4);
+    if (supports && !r->supp.empty()) memcpy(supports, r->supp.data(), r->supp.size() * 4);
+    return FIM_OK;
+}
+
+extern "C" fim_status fim_result_stats(const fim_result *r, fim_stats *out) {
+    if (!r || !out) return fim::set_error(FIM_E_INVALID_ARG, "NULL argument");
+    *out = r->stats;
+    return FIM_OK;
+}
+
+extern "C" void fim_result_destroy(fim_result *r) { delete r; }
+
+// ====================================================================== mining
+
+namespace fim {
+
+fim_options resolve_options(const fim_options *o) {
+    fim_options r{};
+    if (o) r = *o;
+    if (r.seed == 0) r.seed = 0x2108050380ull;
+    if (!(r.alpha > 0.0) || r.alpha > 1.0) r.alpha = 0.3;
+    return r;
+}
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+uint64_t ns_since(clk::time_point t0) {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(clk::now() - t0).count();
+}
+
+// per-instance state of one run
+struct Inst {
+    const fim_db *db = nullptr;
+    uint32_t minsup = 0;
+    uint32_t W = 0, Wp = 0, n_freq = 0;
+    std::vector<uint32_t> counts, item_of_rank, rank_of_item, supp_of_rank;
+    std::vector<uint32_t> pairs;  // triples (i, j, support)
+    uint64_t n_pairs = 0;
+    std::vector<uint32_t> l2_off, l2_atom, l2_supp;
+    DevBuf d_counts, d_rank_of_item, d_item_of_rank, d_rows, d_pairs, d_npairs;
+    DevBuf d_l2_off, d_l2_atom, d_l2_supp;
+    fim_stats st{};
+    uint64_t first_class_rows = 0;  // sum of atoms over first-level classes with >= 2 atoms
+};
+
+}  // namespace
+
+// item order key: ascending support, ties by item id (or item id alone)
+static void rank_items(Inst &I, bool by_id) {
+    const uint32_t ni = I.db->n_item_ids;
+    I.item_of_rank.clear();
+    for (uint32_t it = 0; it < ni; it++)
+        if (I.counts[it] >= I.minsup) I.item_of_rank.push_back(it);
+    if (!by_id)
+        std::stable_sort(I.item_of_rank.begin(), I.item_of_rank.end(),
+                         [&](uint32_t a, uint32_t b) { return I.counts[a] < I.counts[b]; });
+    I.n_freq = (uint32_t)I.item_of_rank.size();
+    I.rank_of_item.assign(ni, kNone);
+    I.supp_of_rank.resize(I.n_freq);
+    for (uint32_t r = 0; r < I.n_freq; r++) {
+        I.rank_of_item[I.item_of_rank[r]] = r;
+        I.supp_of_rank[r] = I.counts[I.item_of_rank[r]];
+    }
+}
+
+// atoms of every first-level class: frequent pairs (i, j) bucketed by i and
+// ordered ascending by (support, item id of j), or by j (= id order)
+static void build_level2(Inst &I, bool by_id) {
+    const uint32_t n = I.n_freq;
+    I.l2_off.assign(n + 1, 0);
+    for (uint64_t p = 0; p < I.n_pairs; p++) I.l2_off[I.pairs[3 * p] + 1]++;
+    for (uint32_t i = 0; i < n; i++) I.l2_off[i + 1] += I.l2_off[i];
+    I.l2_atom.resize(I.n_pairs);
+    I.l2_supp.resize(I.n_pairs);
+    std::vector<uint32_t> fill(I.l2_off.begin(), I.l2_off.end() - 1);
+    for (uint64_t p = 0; p < I.n_pairs; p++) {
+        const uint32_t i = I.pairs[3 * p], q = fill[i]++;
+        I.l2_atom[q] = I.pairs[3 * p + 1];
+        I.l2_supp[q] = I.pairs[3 * p + 2];
+    }
+    std::vector<uint64_t> key;
+    for (uint32_t i = 0; i < n; i++) {
+        const uint32_t a = I.l2_off[i], b = I.l2_off[i + 1];
+        if (b - a < 2) continue;
+        key.resize(b - a);
+        for (uint32_t q = a; q < b; q++)
+            key[q - a] = by_id ? I.l2_atom[q]
+                               : ((uint64_t)I.l2_supp[q] << 32) | I.item_of_rank[I.l2_atom[q]];
+        std::vector<uint32_t> idx(b - a);
+        std::iota(idx.begin(), idx.end(), 0u);
+        std::sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) { return key[x] < key[y]; });
+        std::vector<uint32_t> at(b - a), sp(b - a);
+        for (uint32_t q = 0; q < b - a; q++) {
+            at[q] = I.l2_atom[a + idx[q]];
+            sp[q] = I.l2_supp[a + idx[q]];
+        }
+        std::copy(at.begin(), at.end(), I.l2_atom.begin() + a);
+        std::copy(sp.begin(), sp.end(), I.l2_supp.begin() + a);
+    }
+}
+
+// lexicographic order of the itemsets (items ascending inside each)
+static void canonicalize(std::vector<uint32_t> &items, std::vector<uint64_t> &off,
+                         std::vector<uint32_t> &supp) {
+    const uint64_t n = supp.size();
+    for (uint64_t i = 0; i < n; i++) std::sort(items.begin() + off[i], items.begin() + off[i + 1]);
+    std::vector<uint64_t> idx(n);
+    std::iota(idx.begin(), idx.end(), 0ull);
+    const uint32_t *it = items.data();
+    const uint64_t *o = off.data();
+    std::sort(idx.begin(), idx.end(), [&](uint64_t a, uint64_t b) {
+        const uint32_t *x = it + o[a], *y = it + o[b];
+        const uint64_t nx = o[a + 1] - o[a], ny = o[b + 1] - o[b];
+        const uint64_t m = std::min(nx, ny);
+        for (uint64_t k = 0; k < m; k++)
+            if (x[k] != y[k]) return x[k] < y[k];
+        return nx < ny;
+    });
+    std::vector<uint32_t> ni(items.size()), ns(n);
+    std::vector<uint64_t> no(n + 1);
+    uint64_t pos = 0;
+    no[0] = 0;
+    for (uint64_t q = 0; q < n; q++) {
+        const uint64_t a = idx[q];
+        for (uint64_t k = o[a]; k < o[a + 1]; k++) ni[pos++] = it[k];
+        no[q + 1] = pos;
+        ns[q] = supp[a];
+    }
+    items.swap(ni);
+    off.swap(no);
+    supp.swap(ns);
+}
+
+fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const fim_options &opts_in,
+                     std::vector<fim_result *> &results, bool use_graph) {
+    const auto t_start = clk::now();
+    const fim_options opts = resolve_options(&opts_in);
+    const bool by_id = (opts.flags & FIM_FLAG_ORDER_BY_ID) != 0;
+    const uint32_t n_inst = (uint32_t)reqs.size();
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    std::vector<Inst> insts(n_inst);
+
+    // ---------------- a2: item supports (all instances, one sync)
+    for (uint32_t q = 0; q < n_inst; q++) {
+        Inst &I = insts[q];
+        I.db = reqs[q].db;
+        I.minsup = reqs[q].minsup;
+        const uint32_t ni = I.db->n_item_ids;
+        ENSURE(I.d_counts, ctx, (size_t)ni * 4);
+        HIPCHK(launch_fill_u32(I.d_counts.as<uint32_t>(), ni, 0u, s));
+        HIPCHK(launch_item_count(I.db->d_off.as<uint64_t>(), I.db->d_items.as<uint32_t>(),
+                                 I.db->nnz, I.d_counts.as<uint32_t>(), ni, s));
+        I.counts.resize(ni);
+        HIPCHK(hipMemcpyAsync(I.counts.data(), I.d_counts.as<void>(), (size_t)ni * 4,
+                              hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+
+    // ---------------- a3 + root class: bitmaps and frequent pairs
+    hipEvent_t ev0, ev1;
+    HIPCHK(hipEventCreate(&ev0));
+    HIPCHK(hipEventCreate(&ev1));
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } evg{ev0, ev1};
+    HIPCHK(hipEventRecord(ev0, s));
+    for (uint32_t q = 0; q < n_inst; q++) {
+        Inst &I = insts[q];
+        rank_items(I, by_id);
+        I.W = (uint32_t)((I.db->n_tx + 31) / 32);
+        I.Wp = std::max<uint32_t>(kRowAlign, (I.W + kRowAlign - 1) / kRowAlign * kRowAlign);
+        I.st.item_supports = I.db->n_item_ids;
+        I.st.n_frequent_items = I.n_freq;
+        if (I.n_freq == 0) continue;
+        const uint32_t ni = I.db->n_item_ids;
+        ENSURE(I.d_rank_of_item, ctx, (size_t)ni * 4);
+        ENSURE(I.d_item_of_rank, ctx, (size_t)I.n_freq * 4);
+        ENSURE(I.d_rows, ctx, (size_t)I.n_freq * I.Wp * 4);
+        HIPCHK(hipMemcpyAsync(I.d_rank_of_item.as<void>(), I.rank_of_item.data(), (size_t)ni * 4,
+                              hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(I.d_item_of_rank.as<void>(), I.item_of_rank.data(),
+                              (size_t)I.n_freq * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(launch_fill_u32(I.d_rows.as<uint32_t>(), (uint64_t)I.n_freq * I.Wp, 0u, s));
+        HIPCHK(launch_bitmap_build(I.db->d_off.as<uint64_t>(), I.db->d_items.as<uint32_t>(),
+                                   I.db->n_tx, I.d_rank_of_item.as<uint32_t>(),
+                                   I.d_rows.as<uint32_t>(), I.Wp, s));
+        if (I.n_freq < 2 || opts.max_len == 1) continue;
+        const uint64_t all = (uint64_t)I.n_freq * (I.n_freq - 1) / 2;
+        const uint64_t cap = std::min<uint64_t>(all, std::max<uint64_t>(1u << 16, 64ull * I.n_freq));
+        ENSURE(I.d_pairs, ctx, cap * 12);
+        ENSURE(I.d_npairs, ctx, 8);
+        HIPCHK(launch_fill_u32(I.d_npairs.as<uint32_t>(), 2, 0u, s));
+        HIPCHK(launch_root_pairs(I.d_rows.as<uint32_t>(), I.n_freq, I.Wp, I.minsup,
+                                 I.d_pairs.as<uint32_t>(), cap,
+                                 I.d_npairs.as<unsigned long long>(), opts.tile_words, s));
+        HIPCHK(hipMemcpyAsync(&I.n_pairs, I.d_npairs.as<void>(), 8, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipEventRecord(ev1, s));
+    HIPCHK(hipStreamSynchronize(s));
+    float root_ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&root_ms, ev0, ev1));
+    for (uint32_t q = 0; q < n_inst; q++) {
+        Inst &I = insts[q];
+        if (I.n_freq < 2 || opts.max_len == 1) continue;
+        const uint64_t all = (uint64_t)I.n_freq * (I.n_freq - 1) / 2;
+        const uint64_t cap = I.d_pairs.bytes() / 12;
+        if (I.n_pairs > cap) {  // rerun with room for every frequent pair
+            ENSURE(I.d_pairs, ctx, I.n_pairs * 12);
+            HIPCHK(launch_fill_u32(I.d_npairs.as<uint32_t>(), 2, 0u, s));
+            HIPCHK(launch_root_pairs(I.d_rows.as<uint32_t>(), I.n_freq, I.Wp, I.minsup,
+                                     I.d_pairs.as<uint32_t>(), I.n_pairs,
+                                     I.d_npairs.as<unsigned long long>(), opts.tile_words, s));
+            I.st.retries++;
+        }
+        I.pairs.resize(I.n_pairs * 3);
+        if (I.n_pairs)
+            HIPCHK(hipMemcpyAsync(I.pairs.data(), I.d_pairs.as<void>(), I.n_pairs * 12,
+                                  hipMemcpyDeviceToHost, s));
+        I.st.candidates = all;
+        I.st.pair_words = all * I.W;
+        I.st.bytes_algorithmic = (uint64_t)I.n_freq * I.W * 4;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    for (uint32_t q = 0; q < n_inst; q++) {
+        Inst &I = insts[q];
+        I.st.kernel_ns = (uint64_t)(root_ms * 1e6);
+        if (I.n_pairs) build_level2(I, by_id);
+        else I.l2_off.assign(I.n_freq + 1, 0);
+    }
+
+    // ---------------- a4: class-size estimate, Partition, LPT order
+    const bool deep = opts.max_len == 0 || opts.max_len >= 3;
+    uint32_t n_workers = opts.workers ? opts.workers : (uint32_t)ctx->n_cu * 16;
+    n_workers = std::max<uint32_t>(4, (n_workers + 3) / 4 * 4);
+    std::vector<Task> tasks;
+    std::vector<PlanClass> plan_all;
+    if (deep) {
+        const auto t_est = clk::now();
+        std::vector<PlanInput> pin(n_inst);
+        for (uint32_t q = 0; q < n_inst; q++) {
+            Inst &I = insts[q];
+            pin[q].db = I.db;
+            pin[q].minsup = I.minsup;
+            pin[q].n_freq = I.n_freq;
+            pin[q].W = I.W;
+            pin[q].item_of_rank = &I.item_of_rank;
+            pin[q].rank_of_item = &I.rank_of_item;
+            pin[q].l2_off = &I.l2_off;
+            pin[q].l2_atom = &I.l2_atom;
+        }
+        fim_status ps = plan_tasks(ctx, pin, opts, n_workers, tasks);
+        if (ps != FIM_OK) return ps;
+        const uint64_t est_ns = ns_since(t_est);
+        for (auto &I : insts) I.st.estimate_ns = est_ns;
+    }
+    for (uint32_t q = 0; q < n_inst; q++) {
+        Inst &I = insts[q];
+        for (uint32_t i = 0; i < I.n_freq; i++) {
+            const uint32_t f = I.l2_off[i + 1] - I.l2_off[i];
+            if (f >= 2) I.first_class_rows += f;
+        }
+    }
+
+    // ---------------- a5-a8: one persistent launch over every task
+    DevBuf d_desc(ctx), d_tasks(ctx), d_stack(ctx), d_out(ctx), d_ctr(ctx), d_ictr(ctx);
+    std::vector<uint32_t> out_host;
+    std::vector<InstCounters> ictr(n_inst);
+    DfsCounters ctr{};
+    float dfs_ms = 0.f;
+    bool truncated = false;
+    if (deep && !tasks.empty()) {
+        std::vector<InstDesc> desc(n_inst);
+        uint64_t frame0 = 0;
+        for (uint32_t q = 0; q < n_inst; q++) {
+            Inst &I = insts[q];
+            if (!I.l2_atom.empty()) {
+                ENSURE(I.d_l2_off, ctx, I.l2_off.size() * 4);
+                ENSURE(I.d_l2_atom, ctx, I.l2_atom.size() * 4);
+                ENSURE(I.d_l2_supp, ctx, I.l2_supp.size() * 4);
+                HIPCHK(hipMemcpyAsync(I.d_l2_off.as<void>(), I.l2_off.data(), I.l2_off.size() * 4,
+                                      hipMemcpyHostToDevice, s));
+                HIPCHK(hipMemcpyAsync(I.d_l2_atom.as<void>(), I.l2_atom.data(),
+                                      I.l2_atom.size() * 4, hipMemcpyHostToDevice, s));
+                HIPCHK(hipMemcpyAsync(I.d_l2_supp.as<void>(), I.l2_supp.data(),
+                                      I.l2_supp.size() * 4, hipMemcpyHostToDevice, s));
+            }
+            InstDesc &D = desc[q];
+            D.rows = I.d_rows.as<uint32_t>();
+            D.item_of_rank = I.d_item_of_rank.as<uint32_t>();
+            D.l2_off = I.d_l2_off.as<uint32_t>();
+            D.l2_atom = I.d_l2_atom.as<uint32_t>();
+            D.l2_supp = I.d_l2_supp.as<uint32_t>();
+            D.Wp = I.Wp;
+            D.n_freq = I.n_freq;
+            D.minsup = I.minsup;
+            D.max_len = opts.max_len;
+            D.order_by_id = by_id ? 1u : 0u;
+        }
+        for (const Task &T : tasks) {
+            const Inst &I = insts[T.inst];
+            const uint64_t k = I.l2_off[T.node + 1] - I.l2_off[T.node] - T.r0;
+            frame0 = std::max<uint64_t>(frame0, k * I.Wp + 3 * k);
+        }
+        ENSURE(d_desc, ctx, desc.size() * sizeof(InstDesc));
+        ENSURE(d_tasks, ctx, tasks.size() * sizeof(Task));
+        HIPCHK(hipMemcpyAsync(d_desc.as<void>(), desc.data(), desc.size() * sizeof(InstDesc),
+                              hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(d_tasks.as<void>(), tasks.data(), tasks.size() * sizeof(Task),
+                              hipMemcpyHostToDevice, s));
+        // per-worker stack: room for the largest first frame and its subtree,
+        // within a quarter of device memory in total
+        uint64_t S = std::max<uint64_t>(4 * frame0, 1ull << 20);
+        const uint64_t kMaxStack = 0xFFFFFFF0ull;  // frame offsets are 32-bit
+        const uint64_t budget_words = (uint64_t)(ctx->total_mem / 4) / 4;
+        const bool sample_mode = (opts.flags & kFlagInternalSample) != 0;
+        uint64_t out_cap = sample_mode ? (1ull << 24) : (1ull << 22);
+        int attempts = 0;
+        for (;;) {
+            uint32_t workers = n_workers;
+            if ((uint64_t)workers * S > budget_words)
+                workers = (uint32_t)std::max<uint64_t>(4, budget_words / S / 4 * 4);
+            if (((uint64_t)workers * S > budget_words && S > budget_words / 4) || S > kMaxStack)
+                return set_error(FIM_E_OOM_DEVICE, "a first-level class does not fit on the device");
+            ENSURE(d_stack, ctx, (size_t)workers * S * 4);
+            ENSURE(d_out, ctx, (size_t)out_cap * 4);
+            ENSURE(d_ctr, ctx, sizeof(DfsCounters));
+            ENSURE(d_ictr, ctx, sizeof(InstCounters) * n_inst);
+            HIPCHK(launch_fill_u32(d_ctr.as<uint32_t>(), sizeof(DfsCounters) / 4, 0u, s));
+            HIPCHK(launch_fill_u32(d_ictr.as<uint32_t>(), sizeof(InstCounters) / 4 * n_inst, 0u, s));
+            if (sample_mode) HIPCHK(launch_fill_u32(d_out.as<uint32_t>(), out_cap, 0u, s));
+            HIPCHK(hipEventRecord(ev0, s));
+            if (use_graph) {
+                hipGraph_t g;
+                hipGraphExec_t ge;
+                HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                hipError_t le = launch_dfs(d_desc.as<InstDesc>(), d_tasks.as<Task>(), tasks.size(),
+                                           d_stack.as<uint32_t>(), S, workers,
+                                           opts.classes_per_wg ? opts.classes_per_wg : 1,
+                                           d_out.as<uint32_t>(), out_cap, d_ctr.as<DfsCounters>(),
+                                           d_ictr.as<InstCounters>(), s);
+                hipError_t ce = hipStreamEndCapture(s, &g);
+                if (le != hipSuccess || ce != hipSuccess)
+                    return set_error(FIM_E_DEVICE, std::string("graph capture: ") +
+                                                       hipGetErrorString(le != hipSuccess ? le : ce));
+                hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+                if (ie == hipSuccess) ie = hipGraphLaunch(ge, s);
+                (void)hipGraphExecDestroy(ge);
+                (void)hipGraphDestroy(g);
+                if (ie != hipSuccess)
+                    return set_error(FIM_E_DEVICE, std::string("graph launch: ") + hipGetErrorString(ie));
+            } else {
+                HIPCHK(launch_dfs(d_desc.as<InstDesc>(), d_tasks.as<Task>(), tasks.size(),
+                                  d_stack.as<uint32_t>(), S, workers,
+                                  opts.classes_per_wg ? opts.classes_per_wg : 1, d_out.as<uint32_t>(),
+                                  out_cap, d_ctr.as<DfsCounters>(), d_ictr.as<InstCounters>(), s));
+            }
+            HIPCHK(hipEventRecord(ev1, s));
+            HIPCHK(hipMemcpyAsync(&ctr, d_ctr.as<void>(), sizeof(ctr), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(ictr.data(), d_ictr.as<void>(), sizeof(InstCounters) * n_inst,
+                                  hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            HIPCHK(hipEventElapsedTime(&dfs_ms, ev0, ev1));
+            if (ctr.flags & kFlagDepthOverflow)
+                return set_error(FIM_E_OUTPUT_LIMIT, "an itemset is longer than " +
+                                                         std::to_string(kMaxDepth + 2) + " items");
+            bool again = false;
+            if (ctr.flags & kFlagStackOverflow) {
+                S = std::max<uint64_t>(2 * S, ctr.stack_need + ctr.stack_need / 4);
+                again = true;
+            }
+            if ((ctr.flags & kFlagOutOverflow) || ctr.out_used > out_cap) {
+                if (sample_mode) {
+                    truncated = true;
+                } else {
+                    out_cap = ctr.out_used + 1024;
+                    again = true;
+                }
+            }
+            if (!again) break;
+            for (auto &I : insts) I.st.retries++;
+            if (++attempts > 12) return set_error(FIM_E_DEVICE, "persistent kernel did not converge");
+        }
+        out_host.resize(std::min<uint64_t>(ctr.out_used, out_cap));
+        if (!out_host.empty())
+            HIPCHK(hipMemcpyAsync(out_host.data(), d_out.as<void>(), out_host.size() * 4,
+                                  hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+
+    // ---------------- a9: results in canonical order
+    std::vector<std::vector<uint32_t>> r_items(n_inst), r_supp(n_inst);
+    std::vector<std::vector<uint64_t>> r_off(n_inst);
+    for (uint32_t q = 0; q < n_inst; q++) {
+        Inst &I = insts[q];
+        r_off[q].push_back(0);
+        for (uint32_t r = 0; r < I.n_freq; r++) {
+            r_items[q].push_back(I.item_of_rank[r]);
+            r_off[q].push_back(r_items[q].size());
+            r_supp[q].push_back(I.supp_of_rank[r]);
+        }
+        if (opts.max_len != 1)
+            for (uint64_t p = 0; p < I.n_pairs; p++) {
+                r_items[q].push_back(I.item_of_rank[I.pairs[3 * p]]);
+                r_items[q].push_back(I.item_of_rank[I.pairs[3 * p + 1]]);
+                r_off[q].push_back(r_items[q].size());
+                r_supp[q].push_back(I.pairs[3 * p + 2]);
+            }
+        I.st.candidates += ictr[q].candidates;
+        I.st.pair_words += ictr[q].pair_words;
+        I.st.bytes_algorithmic +=
+            (uint64_t)I.W * 4 * (2 * I.first_class_rows + 2 * ictr[q].child_rows);
+        I.st.kernel_ns += (uint64_t)(dfs_ms * 1e6);
+        I.st.n_tasks = 0;
+    }
+    for (const Task &T : tasks) insts[T.inst].st.n_tasks++;
+    for (uint64_t p = 0; p + kRecHeader <= out_host.size();) {
+        const uint32_t q = out_host[p], len = out_host[p + 1], sp = out_host[p + 2];
+        if (len == 0 || q >= n_inst || p + kRecHeader + len > out_host.size()) break;
+        const Inst &I = insts[q];
+        for (uint32_t k = 0; k < len; k++) r_items[q].push_back(I.item_of_rank[out_host[p + 3 + k]]);
+        r_off[q].push_back(r_items[q].size());
+        r_supp[q].push_back(sp);
+        p += kRecHeader + len;
+    }
+    for (uint32_t q = 0; q < n_inst; q++) {
+        if (opts.max_itemsets && r_supp[q].size() > opts.max_itemsets && !truncated)
+            return set_error(FIM_E_OUTPUT_LIMIT,
+                             "instance " + std::to_string(q) + " has " +
+                                 std::to_string(r_supp[q].size()) + " frequent itemsets > max_itemsets");
+    }
+    results.assign(n_inst, nullptr);
+    for (uint32_t q = 0; q < n_inst; q++) {
+        fim_result *R = new (std::nothrow) fim_result();
+        if (!R) {
+            for (auto *x : results) delete x;
+            results.clear();
+            return set_error(FIM_E_OOM_HOST, "result");
+        }
+        canonicalize(r_items[q], r_off[q], r_supp[q]);
+        R->items.swap(r_items[q]);
+        R->off.swap(r_off[q]);
+        R->supp.swap(r_supp[q]);
+        R->stats = insts[q].st;
+        R->truncated = truncated;
+        results[q] = R;
+    }
+    const uint64_t total = ns_since(t_start);
+    for (auto *R : results) R->stats.total_ns = total;
+    return FIM_OK;
+}
+
+}  // namespace fim
+
+// ====================================================================== mining ABI
+
+extern "C" fim_status fim_mine(fim_ctx *ctx, const fim_db *db, uint32_t minsup_abs,
+                               const fim_options *opts, fim_result **out) {
+    if (!out) return fim::set_error(FIM_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!ctx || !db) return fim::set_error(FIM_E_INVALID_ARG, "ctx or db is NULL");
+    if (db->ctx != ctx && db->ctx->device != ctx->device)
+        return fim::set_error(FIM_E_INVALID_ARG, "db belongs to another device");
+    if (minsup_abs == 0) return fim::set_error(FIM_E_INVALID_ARG, "minsup_abs must be >= 1");
+    std::vector<fim::MineRequest> reqs{{db, minsup_abs}};
+    std::vector<fim_result *> res;
+    fim_status st = fim::mine_many(ctx, reqs, fim::resolve_options(opts), res, false);
+    if (st != FIM_OK) return st;
+    *out = res[0];
+    return FIM_OK;
+}
+
+extern "C" fim_status fim_mine_batch(fim_ctx *ctx, uint32_t n, const fim_db *const *dbs,
+                                     const uint32_t *minsups, const fim_options *opts,
+                                     fim_result **outs) {
+    if (!ctx || (n && (!dbs || !minsups || !outs)))
+        return fim::set_error(FIM_E_INVALID_ARG, "NULL argument");
+    std::vector<fim::MineRequest> reqs(n);
+    for (uint32_t q = 0; q < n; q++) {
+        outs[q] = nullptr;
+        if (!dbs[q] || minsups[q] == 0)
+            return fim::set_error(FIM_E_INVALID_ARG, "instance " + std::to_string(q) +
+                                                         ": NULL db or minimum support 0");
+        if (dbs[q]->ctx->device != ctx->device)
+            return fim::set_error(FIM_E_INVALID_ARG, "db belongs to another device");
+        reqs[q] = {dbs[q], minsups[q]};
+    }
+    if (n == 0) return FIM_OK;
+    std::vector<fim_result *> res;
+    fim_status st = fim::mine_many(ctx, reqs, fim::resolve_options(opts), res, true);
+    if (st != FIM_OK) return st;
+    for (uint32_t q = 0; q < n; q++) outs[q] = res[q];
+    return FIM_OK;
+}

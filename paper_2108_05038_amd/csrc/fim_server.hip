@@ -1,0 +1,215 @@
+// Serving: a request loop on one GPU with continuous batching.
+//
+// Requests are queued by fim_server_submit (any thread).  A worker thread
+// owns the GPU.  Each step it admits waiting requests in arrival order while
+// a slot is free and the HBM footprint of their bitmaps fits the budget,
+// then mines every admitted request in one batched persistent launch.
+// Requests that arrive while a step runs join the next step; a finished
+// request leaves its slot and its memory at once.  Results are identical to
+// fim_mine on the same database and minimum support.
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+#include "fim_host.h"
+
+namespace {
+
+struct Request {
+    uint64_t ticket;
+    const fim_db *db;
+    uint32_t minsup;
+    uint64_t footprint;
+};
+
+struct Done {
+    fim_status status;
+    fim_result *result;
+    std::string error;
+};
+
+}  // namespace
+
+struct fim_server {
+    fim_ctx *ctx = nullptr;
+    fim_server_config cfg{};
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request> queue;
+    std::unordered_map<uint64_t, Done> done;
+    std::unordered_map<uint64_t, int> state;  // 0 queued, 1 running, 2 done
+    std::unordered_map<uint64_t, bool> cancelled;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    fim_server_stats stats{};
+    std::thread worker;
+};
+
+namespace {
+
+// device bytes a request holds while resident: its level-1 bitmaps, item
+// arrays and a share of the worker stacks and output arena
+uint64_t footprint(const fim_db *db) {
+    const uint64_t W = (db->n_tx + 31) / 32 + 4;
+    const uint64_t rows = std::min<uint64_t>(db->n_item_ids, db->nnz);
+    return rows * W * 4 + (uint64_t)db->n_item_ids * 16 + (64ull << 20);
+}
+
+void worker_loop(fim_server *s) {
+    (void)hipSetDevice(s->ctx->device);
+    for (;;) {
+        std::vector<Request> batch;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+            if (s->stop && s->queue.empty()) return;
+            uint64_t bytes = 0;
+            while (!s->queue.empty() && batch.size() < s->cfg.max_active) {
+                const Request &r = s->queue.front();
+                if (!batch.empty() && bytes + r.footprint > s->cfg.hbm_budget_bytes) break;
+                bytes += r.footprint;
+                batch.push_back(r);
+                s->state[r.ticket] = 1;
+                s->queue.pop_front();
+            }
+            s->stats.peak_active = std::max<uint64_t>(s->stats.peak_active, batch.size());
+            s->stats.peak_bytes = std::max<uint64_t>(s->stats.peak_bytes, bytes);
+        }
+        std::vector<fim::MineRequest> reqs;
+        for (const Request &r : batch) reqs.push_back({r.db, r.minsup});
+        std::vector<fim_result *> res;
+        fim_status st = fim::mine_many(s->ctx, reqs, s->cfg.opts, res, true);
+        std::string err = st == FIM_OK ? "" : fim_last_error();
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->stats.steps++;
+            for (size_t k = 0; k < batch.size(); k++) {
+                const uint64_t t = batch[k].ticket;
+                fim_result *r = st == FIM_OK ? res[k] : nullptr;
+                if (s->cancelled.count(t)) {
+                    fim_result_destroy(r);
+                    s->done[t] = Done{FIM_E_CANCELLED, nullptr, "cancelled"};
+                } else {
+                    s->done[t] = Done{st, r, err};
+                }
+                s->state[t] = 2;
+                s->stats.completed++;
+            }
+        }
+        s->cv_done.notify_all();
+    }
+}
+
+}  // namespace
+
+extern "C" fim_status fim_server_create(fim_ctx *ctx, const fim_server_config *cfg,
+                                        fim_server **out) {
+    if (!out || !ctx) return fim::set_error(FIM_E_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    fim_server *s = new (std::nothrow) fim_server();
+    if (!s) return fim::set_error(FIM_E_OOM_HOST, "server");
+    s->ctx = ctx;
+    if (cfg) s->cfg = *cfg;
+    if (s->cfg.max_active == 0) s->cfg.max_active = 64;
+    if (s->cfg.max_queue == 0) s->cfg.max_queue = 1u << 16;
+    if (s->cfg.hbm_budget_bytes == 0) {
+        size_t fr = 0, tot = 0;
+        (void)hipSetDevice(ctx->device);
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = ctx->total_mem / 2;
+        s->cfg.hbm_budget_bytes = fr / 4 * 3;
+    }
+    s->worker = std::thread(worker_loop, s);
+    *out = s;
+    return FIM_OK;
+}
+
+extern "C" fim_status fim_server_submit(fim_server *s, const fim_db *db, uint32_t minsup_abs,
+                                        uint64_t *ticket) {
+    if (!s || !db || !ticket || minsup_abs == 0)
+        return fim::set_error(FIM_E_INVALID_ARG, "NULL argument or minimum support 0");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->queue.size() >= s->cfg.max_queue) return fim::set_error(FIM_E_BUSY, "queue full");
+    const uint64_t t = s->next_ticket++;
+    s->queue.push_back(Request{t, db, minsup_abs, footprint(db)});
+    s->state[t] = 0;
+    s->stats.submitted++;
+    *ticket = t;
+    s->cv_work.notify_one();
+    return FIM_OK;
+}
+
+static fim_status take(fim_server *s, uint64_t ticket, fim_result **out, bool block) {
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->state.find(ticket);
+    if (it == s->state.end()) return fim::set_error(FIM_E_NOT_FOUND, "unknown ticket");
+    if (block) s->cv_done.wait(lk, [&] { return s->state[ticket] == 2; });
+    if (s->state[ticket] != 2) {
+        *out = nullptr;
+        return FIM_OK;
+    }
+    Done d = s->done[ticket];
+    s->done.erase(ticket);
+    s->state.erase(ticket);
+    s->cancelled.erase(ticket);
+    *out = d.result;
+    if (d.status != FIM_OK) return fim::set_error(d.status, d.error);
+    return FIM_OK;
+}
+
+extern "C" fim_status fim_server_poll(fim_server *s, uint64_t ticket, fim_result **out) {
+    if (!s || !out) return fim::set_error(FIM_E_INVALID_ARG, "NULL argument");
+    return take(s, ticket, out, false);
+}
+
+extern "C" fim_status fim_server_wait(fim_server *s, uint64_t ticket, fim_result **out) {
+    if (!s || !out) return fim::set_error(FIM_E_INVALID_ARG, "NULL argument");
+    return take(s, ticket, out, true);
+}
+
+extern "C" fim_status fim_server_cancel(fim_server *s, uint64_t ticket) {
+    if (!s) return fim::set_error(FIM_E_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->state.find(ticket);
+    if (it == s->state.end()) return fim::set_error(FIM_E_NOT_FOUND, "unknown ticket");
+    if (it->second == 0) {  // still queued: drop it now
+        for (auto q = s->queue.begin(); q != s->queue.end(); ++q)
+            if (q->ticket == ticket) {
+                s->queue.erase(q);
+                break;
+            }
+        s->done[ticket] = Done{FIM_E_CANCELLED, nullptr, "cancelled"};
+        it->second = 2;
+    } else if (it->second == 1) {
+        s->cancelled[ticket] = true;
+    }
+    s->stats.cancelled++;
+    s->cv_done.notify_all();
+    return FIM_OK;
+}
+
+extern "C" fim_status fim_server_stats_get(const fim_server *s, fim_server_stats *out) {
+    if (!s || !out) return fim::set_error(FIM_E_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(const_cast<fim_server *>(s)->mu);
+    *out = s->stats;
+    return FIM_OK;
+}
+
+extern "C" void fim_server_destroy(fim_server *s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        for (const Request &r : s->queue) {
+            s->done[r.ticket] = Done{FIM_E_CANCELLED, nullptr, "server stopped"};
+            s->state[r.ticket] = 2;
+        }
+        s->queue.clear();
+    }
+    s->cv_work.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    for (auto &kv : s->done) fim_result_destroy(kv.second.result);
+    delete s;
+}

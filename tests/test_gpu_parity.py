@@ -1,0 +1,263 @@
+"""GPU parity: libfim.so (through the C ABI) against the CPU oracle.
+
+Integer work, so the bar is bit-exact: identical itemsets and supports in
+canonical order, and the same number of candidate pairs when both sides use
+the same extension order.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fim():
+    import paper_2108_05038_amd as F
+    F.lib()
+    return F
+
+
+@pytest.fixture(scope="module")
+def ctx(fim):
+    c = fim.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_mine(fim, ctx, db, minsup=None, **opts):
+    d = fim.Database(ctx, db.offsets, db.items, db.n_items)
+    try:
+        return fim.mine(ctx, d, minsup if minsup is not None else db.minsup, **opts)
+    finally:
+        d.close()
+
+
+def assert_same(g, o, what=""):
+    assert len(g) == len(o), (what, len(g), len(o))
+    assert np.array_equal(g.offsets, o.offsets), what
+    assert np.array_equal(g.items, o.items), what
+    assert np.array_equal(g.supports, o.supports), what
+
+
+def _load(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------- thesis examples
+
+def test_paper_eclat_example(fim, ctx):
+    g = _load("eclat_example.json")
+    db = synth.from_lists(g["transactions"], minsup=g["minsup"])
+    say("eclat example")
+    r = gpu_mine(fim, ctx, db)
+    want = {tuple(t["itemset"]): len(t["tids"]) for t in g["tidlists"] if t["frequent"]}
+    assert r.as_dict() == want
+    assert r.stats["candidates"] == 19  # hand-counted, ascending-support order
+    r = gpu_mine(fim, ctx, db, flags=fim.FIM_FLAG_ORDER_BY_ID)
+    assert r.as_dict() == want and r.stats["candidates"] == 20
+
+
+def test_paper_apriori_example(fim, ctx):
+    g = _load("apriori_example.json")
+    db = synth.from_lists(g["transactions"], minsup=g["minsup"])
+    say("apriori example")
+    want = {tuple(int(x) for x in k.split(",")): v for k, v in g["frequent"].items()}
+    assert gpu_mine(fim, ctx, db).as_dict() == want
+
+
+# ---------------------------------------------------------------- random inputs
+
+def test_tiny_random_vs_bruteforce(fim, ctx):
+    rng = np.random.default_rng(2024)
+    for case in range(150):
+        n_items = int(rng.integers(1, 14))
+        n_tx = int(rng.integers(0, 70))
+        dens = float(rng.uniform(0.1, 0.9))
+        T = [[i for i in range(n_items) if rng.random() < dens] for _ in range(n_tx)]
+        m = int(rng.integers(1, max(2, n_tx // 2 + 2)))
+        db = synth.from_lists(T, n_items=n_items, minsup=m)
+        if case % 25 == 0:
+            say("tiny", case)
+        o = oracle.mine_db(db, "bruteforce")
+        g = gpu_mine(fim, ctx, db)
+        assert_same(g, o, ("tiny", case))
+
+
+@pytest.mark.parametrize("n_tx,n_items,mlen,minsup", [
+    (3001, 150, 10.0, 12),    # ragged word tail, two row tiles
+    (4097, 400, 12.0, 9),     # more than 64 frequent items, deep classes
+    (777, 90, 20.0, 25),      # long transactions
+    (10000, 1000, 10.0, 20),  # basket shape at a lower minimum support
+])
+def test_medium_vs_oracle(fim, ctx, n_tx, n_items, mlen, minsup):
+    o_, it, ni = synth.basket(n_tx * 7 + n_items, n_tx, n_items, mlen, 2 * n_items, 4.0)
+    db = synth.Database(o_, it, ni, minsup)
+    say("medium", n_tx, n_items, minsup)
+    o = oracle.mine_db(db, threads=4)
+    g = gpu_mine(fim, ctx, db)
+    assert len(o) > 200
+    assert_same(g, o)
+    assert g.stats["candidates"] == o.candidates
+    oi = oracle.mine_db(db, order=oracle.ORDER_ID, threads=4)
+    gi = gpu_mine(fim, ctx, db, flags=fim.FIM_FLAG_ORDER_BY_ID)
+    assert_same(gi, oi)
+    assert gi.stats["candidates"] == oi.candidates
+
+
+def test_dense_reduced_vs_oracle(fim, ctx):
+    o_, it, ni = synth.dense(synth.SEED_BASE + 3, 2500, 120)
+    db = synth.Database(o_, it, ni, 1000)  # 40 % as in the full dense workload
+    say("dense reduced")
+    o = oracle.mine_db(db, threads=8)
+    g = gpu_mine(fim, ctx, db)
+    assert len(o) > 100000
+    assert_same(g, o)
+    assert g.stats["candidates"] == o.candidates
+
+
+# ---------------------------------------------------------------- options do not change F
+
+def test_options_invariance(fim, ctx):
+    o_, it, ni = synth.basket(77, 5000, 300, 14.0, 600, 5.0)
+    db = synth.Database(o_, it, ni, 15)
+    o = oracle.mine_db(db, threads=4)
+    variants = [
+        dict(workers=4), dict(workers=64, classes_per_wg=3), dict(flags=fim.FIM_FLAG_NO_ESTIMATE),
+        dict(flags=fim.FIM_FLAG_NO_SPLIT), dict(alpha=1.0), dict(alpha=0.05, seed=99),
+        dict(sample_tx=500, sample_fi=1000),
+    ]
+    for v in variants:
+        say("variant", v)
+        g = gpu_mine(fim, ctx, db, **v)
+        assert_same(g, o, v)
+        assert g.stats["candidates"] == o.candidates, v
+
+
+def test_max_len(fim, ctx):
+    o_, it, ni = synth.basket(5, 3000, 100, 12.0, 200, 5.0)
+    db = synth.Database(o_, it, ni, 10)
+    full = oracle.mine_db(db)
+    for L in (1, 2, 3, 4):
+        say("max_len", L)
+        g = gpu_mine(fim, ctx, db, max_len=L)
+        want = {u: s for u, s in full.as_dict().items() if len(u) <= L}
+        assert g.as_dict() == want
+
+
+# ---------------------------------------------------------------- edge cases and errors
+
+def test_edge_cases(fim, ctx):
+    say("edge cases")
+    assert len(gpu_mine(fim, ctx, synth.from_lists([], n_items=4, minsup=1))) == 0
+    assert len(gpu_mine(fim, ctx, synth.from_lists([[], [], []], n_items=4, minsup=1))) == 0
+    T = [[0, 1], [1, 2], [0, 1, 2]]
+    assert len(gpu_mine(fim, ctx, synth.from_lists(T, n_items=3, minsup=4))) == 0
+    assert gpu_mine(fim, ctx, synth.from_lists(T, n_items=3, minsup=1)).as_dict() == \
+        oracle.mine_db(synth.from_lists(T, n_items=3, minsup=1), "bruteforce").as_dict()
+    dup = synth.from_lists([[3, 1, 3, 2], [2, 2], [1, 3], [3, 3, 3]], n_items=5, minsup=2)
+    assert gpu_mine(fim, ctx, dup).as_dict() == {(1,): 2, (2,): 2, (3,): 3, (1, 3): 2}
+    one = synth.from_lists([[7]] * 40, n_items=8, minsup=40)
+    assert gpu_mine(fim, ctx, one).as_dict() == {(7,): 40}
+    # every transaction identical: all 2^12 - 1 subsets are frequent
+    full = synth.from_lists([list(range(12))] * 33, n_items=12, minsup=33)
+    r = gpu_mine(fim, ctx, full)
+    assert len(r) == 4095 and set(r.supports.tolist()) == {33}
+
+
+def test_errors(fim, ctx):
+    say("errors")
+    with pytest.raises(fim.FimError) as e:
+        fim.Database(ctx, np.array([0, 2], np.uint64), np.array([1, 9], np.uint32), 5)
+    assert e.value.status == fim.FIM_E_ITEM_RANGE
+    with pytest.raises(fim.FimError) as e:
+        fim.Database(ctx, np.array([0, 2, 1], np.uint64), np.array([1, 2], np.uint32), 5)
+    assert e.value.status == fim.FIM_E_INVALID_ARG
+    d = fim.Database(ctx, np.array([0, 2], np.uint64), np.array([1, 2], np.uint32), 5)
+    with pytest.raises(fim.FimError) as e:
+        fim.mine(ctx, d, 0)
+    assert e.value.status == fim.FIM_E_INVALID_ARG
+    full = synth.from_lists([list(range(10))] * 5, n_items=10, minsup=1)
+    with pytest.raises(fim.FimError) as e:
+        gpu_mine(fim, ctx, full, max_itemsets=100)
+    assert e.value.status == fim.FIM_E_OUTPUT_LIMIT
+    d.close()
+
+
+# ---------------------------------------------------------------- full workloads
+
+@pytest.mark.parametrize("name", ["basket-10k", "dense-50k", "sparse-200k"])
+def test_full_workload_vs_golden(fim, ctx, name):
+    g = _load("%s.json" % name)
+    db = synth.make(name)
+    say("full", name)
+    r = gpu_mine(fim, ctx, db)
+    assert len(r) == g["n_itemsets"]
+    assert oracle.digest(r.offsets, r.items, r.supports) == g["digest"]
+    assert r.stats["candidates"] == g["candidates_ascending_support"]
+    # sampled supports recounted by the oracle's scan
+    rng = np.random.default_rng(1)
+    for i in rng.choice(len(r), min(40, len(r)), replace=False):
+        u = r.items[r.offsets[i]:r.offsets[i + 1]]
+        assert oracle.support(db.offsets, db.items, u) == r.supports[i]
+
+
+# ---------------------------------------------------------------- batch and serving
+
+def _batch_dbs(k, scale=0.25):
+    out = []
+    for i in range(k):
+        p = synth.batch_params(i)
+        p["n_tx"] = max(1000, int(p["n_tx"] * scale))
+        p["minsup"] = synth.minsup_abs(p["rel_minsup"], p["n_tx"])
+        out.append(synth.batch_instance(p, "b%d" % i))
+    return out
+
+
+def test_batch_equals_solo_and_oracle(fim, ctx):
+    dbs = _batch_dbs(6)
+    handles = [fim.Database(ctx, d.offsets, d.items, d.n_items) for d in dbs]
+    say("batch of", len(dbs))
+    res = fim.mine_batch(ctx, handles, [d.minsup for d in dbs])
+    for d, h, r in zip(dbs, handles, res):
+        o = oracle.mine_db(d, threads=4, max_sets=3_000_000)
+        assert not o.overflow
+        assert_same(r, o, d.name)
+        solo = fim.mine(ctx, h, d.minsup)
+        assert_same(solo, o, d.name)
+        assert solo.stats["candidates"] == r.stats["candidates"] == o.candidates
+    for h in handles:
+        h.close()
+
+
+def test_server_results_same_alone_and_mixed(fim, ctx):
+    dbs = _batch_dbs(5, scale=0.1)
+    handles = [fim.Database(ctx, d.offsets, d.items, d.n_items) for d in dbs]
+    alone = [fim.mine(ctx, h, d.minsup) for d, h in zip(dbs, handles)]
+    say("server")
+    srv = fim.Server(ctx, max_active=3)
+    tickets = [srv.submit(h, d.minsup) for d, h in zip(dbs, handles)]
+    tickets += [srv.submit(h, d.minsup) for d, h in zip(dbs[::-1], handles[::-1])]
+    got = [srv.wait(t) for t in tickets]
+    for k, r in enumerate(got):
+        i = k if k < len(dbs) else len(dbs) - 1 - (k - len(dbs))
+        assert_same(r, alone[i], k)
+    st = srv.stats()
+    assert st["completed"] == len(tickets) and st["peak_active"] <= 3
+    srv.close()
+    for h in handles:
+        h.close()
