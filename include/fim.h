@@ -208,6 +208,14 @@ fim_status fim_mine_batch(fim_ctx *ctx, uint32_t n, const fim_db *const *dbs,
  *  estimate_ns      wall time of the sample-based estimate
  *  n_tasks          work items given to the persistent kernel
  *  retries          re-runs after an arena overflow
+ *  root_candidates  candidates of the root class (all pairs of frequent items)
+ *  root_pair_words  words AND-popcounted by the root-class kernel
+ *  root_kernel_ns   GPU time of the root-class pair kernel (HIP events)
+ *  dfs_kernel_ns    GPU time of the persistent depth-first kernel (HIP events)
+ *  dfs_bytes_algorithmic  bitmap bytes the depth-first kernel must move:
+ *                   every class's sibling rows written once and read once
+ *  n_itemsets       frequent itemsets reported
+ *  In a batch, the kernel times are those of the whole batched launch.
  */
 typedef struct fim_stats {
     uint64_t candidates;
@@ -220,6 +228,12 @@ typedef struct fim_stats {
     uint64_t estimate_ns;
     uint64_t n_tasks;
     uint64_t retries;
+    uint64_t root_candidates;
+    uint64_t root_pair_words;
+    uint64_t root_kernel_ns;
+    uint64_t dfs_kernel_ns;
+    uint64_t dfs_bytes_algorithmic;
+    uint64_t n_itemsets;
 } fim_stats;
 
 /* Number of itemsets and total number of items over all itemsets. */
@@ -239,6 +253,61 @@ fim_status fim_result_copy(const fim_result *r, uint64_t *offsets, uint32_t *ite
 
 fim_status fim_result_stats(const fim_result *r, fim_stats *out);
 void fim_result_destroy(fim_result *r);
+
+/* ------------------------------------------------------------------ */
+/* Estimator building blocks (host only, no GPU needed)               */
+
+/*
+ * Default sample sizes of the class-size estimate.
+ *  *sample_tx = ceil(ln(2/delta_db) / (2 eps_db^2)): database sample size of
+ *    Toivonen's theorem (chapter on approximate counting, estimating the
+ *    support of an itemset from a database sample): the support error exceeds
+ *    eps_db with probability at most delta_db.
+ *  *sample_fi = ceil(-ln(delta_fi/2) / D(rho + eps_fi || rho)): reservoir size
+ *    of the theorem on the estimation error of the size of a subset from a
+ *    hypergeometrically distributed (reservoir) sample, with D the
+ *    Kullback-Leibler divergence of two Bernoulli distributions, natural logs.
+ * Errors: FIM_E_INVALID_ARG unless 0 < eps, delta < 1, 0 < rho, rho + eps_fi < 1.
+ */
+fim_status fim_estimate_sample_sizes(double eps_db, double delta_db, double rho, double eps_fi,
+                                     double delta_fi, uint32_t *sample_tx, uint32_t *sample_fi);
+
+/*
+ * Simple reservoir sampling (the Simple-Reservoir-Sampling algorithm of the
+ * chapter on approximate counting): a uniform sample without replacement of
+ * n positions of a stream of stream_len records.  out[min(n, stream_len)]
+ * receives the kept positions (slot order of the reservoir).  The uniform
+ * draws come from SplitMix64 seeded with `seed`.
+ */
+fim_status fim_reservoir_sample(uint64_t stream_len, uint64_t n, uint64_t seed, uint64_t *out);
+
+/*
+ * Partition and LPT-Schedule (Phase 2 of the thesis's method).  Class c is a
+ * first-level class with n_atoms[c] atoms; row_weights holds, class after
+ * class, n_atoms[c] estimated sizes of its second-level classes (the last one
+ * of each class is ignored: it has no extensions).  A class whose total
+ * exceeds alpha * (sum of all weights) / n_workers is split into contiguous
+ * ranges of rows, each within that threshold unless a single row exceeds it
+ * (FIM_FLAG_NO_SPLIT disables splitting).  The resulting tasks
+ * (class, r0, r1) — rows [r0, r1) — are written to tasks[3 * capacity] in
+ * LPT order (decreasing estimate); *n_tasks receives their number and
+ * *makespan the largest worker load of the LPT assignment to n_workers
+ * workers.  Classes with fewer than 2 atoms give no task.
+ * Errors: FIM_E_INVALID_ARG, FIM_E_OUTPUT_LIMIT (capacity too small;
+ * *n_tasks still receives the number needed).
+ */
+fim_status fim_partition_lpt(uint32_t n_classes, const uint32_t *n_atoms,
+                             const double *row_weights, double alpha, uint32_t n_workers,
+                             uint32_t flags, uint32_t *tasks, uint32_t capacity,
+                             uint32_t *n_tasks, double *makespan);
+
+/*
+ * LPT-Schedule alone: jobs in decreasing weight, each to the currently least
+ * loaded of n_workers workers (lowest index on ties).  worker_of_job[n_jobs];
+ * *makespan = largest load.  Graham's bound: makespan <= 4/3 of optimal.
+ */
+fim_status fim_lpt_schedule(const double *weights, uint64_t n_jobs, uint32_t n_workers,
+                            uint32_t *worker_of_job, double *makespan);
 
 /* ------------------------------------------------------------------ */
 /* Serving (continuous batching)                                      */

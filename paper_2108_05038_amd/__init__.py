@@ -44,6 +44,7 @@ EXPORTED = [
     "fim_mine_batch", "fim_result_sizes", "fim_result_copy", "fim_result_stats",
     "fim_result_destroy", "fim_server_create", "fim_server_submit", "fim_server_poll",
     "fim_server_wait", "fim_server_cancel", "fim_server_stats_get", "fim_server_destroy",
+    "fim_estimate_sample_sizes", "fim_reservoir_sample", "fim_partition_lpt", "fim_lpt_schedule",
 ]
 
 
@@ -72,7 +73,9 @@ class fim_options(ctypes.Structure):
 class fim_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
         "candidates", "pair_words", "item_supports", "n_frequent_items", "bytes_algorithmic",
-        "kernel_ns", "total_ns", "estimate_ns", "n_tasks", "retries")]
+        "kernel_ns", "total_ns", "estimate_ns", "n_tasks", "retries", "root_candidates",
+        "root_pair_words", "root_kernel_ns", "dfs_kernel_ns", "dfs_bytes_algorithmic",
+        "n_itemsets")]
 
 
 class fim_server_config(ctypes.Structure):
@@ -130,6 +133,11 @@ def lib():
         "fim_server_cancel": (i32, [V, u64]),
         "fim_server_stats_get": (i32, [V, P(fim_server_stats)]),
         "fim_server_destroy": (None, [V]),
+        "fim_estimate_sample_sizes": (i32, [ctypes.c_double] * 5 + [P(u32), P(u32)]),
+        "fim_reservoir_sample": (i32, [u64, u64, u64, P(u64)]),
+        "fim_partition_lpt": (i32, [u32, P(u32), P(ctypes.c_double), ctypes.c_double, u32, u32,
+                                    P(u32), u32, P(u32), P(ctypes.c_double)]),
+        "fim_lpt_schedule": (i32, [P(ctypes.c_double), u64, u32, P(u32), P(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -226,6 +234,42 @@ def fim_result_take(res) -> "Result":
     L.fim_result_destroy(res)
     stats = {name: int(getattr(st, name)) for name, _ in fim_stats._fields_}
     return Result(off, items[:ni.value], supp[:n.value], stats)
+
+
+def fim_estimate_sample_sizes(eps_db=0.02, delta_db=0.05, rho=0.001, eps_fi=0.0005,
+                              delta_fi=0.05):
+    a, b = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(lib().fim_estimate_sample_sizes(eps_db, delta_db, rho, eps_fi, delta_fi,
+                                           ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def fim_reservoir_sample(stream_len: int, n: int, seed: int) -> np.ndarray:
+    out = np.zeros(max(1, min(n, stream_len)), np.uint64)
+    _check(lib().fim_reservoir_sample(stream_len, n, seed, _u64p(out)))
+    return out[:min(n, stream_len)]
+
+
+def fim_lpt_schedule(weights, n_workers: int):
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    wk = np.zeros(max(1, len(w)), np.uint32)
+    ms = ctypes.c_double()
+    _check(lib().fim_lpt_schedule(w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(w),
+                                  n_workers, _u32p(wk), ctypes.byref(ms)))
+    return wk[:len(w)], ms.value
+
+
+def fim_partition_lpt(n_atoms, row_weights, alpha: float, n_workers: int, flags: int = 0):
+    na = np.ascontiguousarray(n_atoms, dtype=np.uint32)
+    rw = np.ascontiguousarray(row_weights, dtype=np.float64)
+    cap = int(na.sum()) + 1
+    tasks = np.zeros(3 * cap, np.uint32)
+    nt, ms = ctypes.c_uint32(), ctypes.c_double()
+    _check(lib().fim_partition_lpt(len(na), _u32p(na),
+                                   rw.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), alpha,
+                                   n_workers, flags, _u32p(tasks), cap, ctypes.byref(nt),
+                                   ctypes.byref(ms)))
+    return tasks[:3 * nt.value].reshape(-1, 3), ms.value
 
 
 # ---------------------------------------------------------------- high level

@@ -51,6 +51,8 @@ struct DfsCounters {
     unsigned long long pair_words;  // words AND-popcounted
     unsigned long long child_rows;  // child bitmaps written
     unsigned long long stack_need;  // largest per-worker stack use seen (words)
+    unsigned long long busy_sum;    // wall-clock ticks workers spent on tasks, summed
+    unsigned long long busy_max;    // ... and of the busiest worker
     unsigned int flags;             // kFlag* bits
     unsigned int pad_;
 };
@@ -67,8 +69,11 @@ constexpr unsigned kFlagStackOverflow = 1u;
 constexpr unsigned kFlagDepthOverflow = 2u;
 constexpr unsigned kFlagOutOverflow = 4u;
 
-// Output record layout (32-bit words): inst, len, support, len ranks.
-constexpr uint32_t kRecHeader = 3;
+// Output arena: chunks with a header of kChunkHeader words (size, task,
+// seq, used) followed by records of kRecHeader + len words (len, support,
+// len ranks in the instance's item order).
+constexpr uint32_t kChunkHeader = 4;
+constexpr uint32_t kRecHeader = 2;
 
 // ---------------------------------------------------------------- launches
 // All launches are asynchronous on `stream`; they return hipSuccess or the

@@ -25,6 +25,38 @@ __device__ __forceinline__ uint4 and4(uint4 a, uint4 b) {
     return make_uint4(a.x & b.x, a.y & b.y, a.z & b.z, a.w & b.w);
 }
 
+// popcount(a AND b) over the 128-bit chunks c = sub, sub + g, ... < C; four
+// chunk pairs are loaded before any is used, so a lane keeps eight loads
+// in flight
+__device__ __forceinline__ uint32_t popc_rows(const uint4 *a, const uint4 *b, uint32_t C,
+                                              uint32_t sub, uint32_t g) {
+    uint32_t acc = 0, c = sub;
+    for (; c + 3 * g < C; c += 4 * g) {
+        const uint4 a0 = a[c], b0 = b[c], a1 = a[c + g], b1 = b[c + g];
+        const uint4 a2 = a[c + 2 * g], b2 = b[c + 2 * g], a3 = a[c + 3 * g], b3 = b[c + 3 * g];
+        acc += popc4(a0, b0) + popc4(a1, b1) + popc4(a2, b2) + popc4(a3, b3);
+    }
+    for (; c < C; c += g) acc += popc4(a[c], b[c]);
+    return acc;
+}
+
+// dst = a AND b over C chunks, the wave's lanes striding by 64, four
+// chunks in flight per lane
+__device__ __forceinline__ void and_rows(uint4 *dst, const uint4 *a, const uint4 *b, uint32_t C,
+                                         uint32_t lane) {
+    uint32_t c = lane;
+    for (; c + 3 * kWave < C; c += 4 * kWave) {
+        const uint4 a0 = a[c], b0 = b[c], a1 = a[c + kWave], b1 = b[c + kWave];
+        const uint4 a2 = a[c + 2 * kWave], b2 = b[c + 2 * kWave];
+        const uint4 a3 = a[c + 3 * kWave], b3 = b[c + 3 * kWave];
+        dst[c] = and4(a0, b0);
+        dst[c + kWave] = and4(a1, b1);
+        dst[c + 2 * kWave] = and4(a2, b2);
+        dst[c + 3 * kWave] = and4(a3, b3);
+    }
+    for (; c < C; c += kWave) dst[c] = and4(a[c], b[c]);
+}
+
 // number of set bits of `mask` in lanes below this one
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
@@ -268,6 +300,52 @@ __device__ void sort_atoms(const InstDesc &I, const uint32_t *tmp, uint32_t si, 
     }
 }
 
+// Output of one task goes to chunks of the output arena claimed with one
+// atomic each: header [size, task, seq, used] then records [len, support,
+// len ranks].  Chunks of a task are numbered, so the host can put the
+// records back in the task's own depth-first order.
+struct OutChunk {
+    uint64_t base;   // word offset of the chunk, kNoChunk if none
+    uint32_t size;   // words allocated
+    uint32_t pos;    // words used, header included
+    uint32_t seq;    // chunk number within the task
+    uint32_t valid;  // 0 once the arena is full (records are then dropped)
+};
+
+constexpr uint64_t kNoChunk = ~0ull;
+
+__device__ __forceinline__ void close_chunk(OutChunk &c, uint32_t *out) {
+    if (c.base != kNoChunk && c.valid && lane_id() == 0) out[c.base + 3] = c.pos;
+}
+
+// make room for `need` words; returns false when the arena is full
+__device__ bool chunk_reserve(OutChunk &c, uint32_t need, uint32_t task, uint32_t *out,
+                              uint64_t out_cap, DfsCounters *ctr) {
+    if (c.base != kNoChunk && c.pos + need <= c.size) return c.valid != 0;
+    close_chunk(c, out);
+    const uint32_t grow = c.seq < 6 ? (256u << c.seq) : 16384u;
+    const uint32_t size = max(grow, need + kChunkHeader);
+    unsigned long long base = 0;
+    if (lane_id() == 0) base = atomicAdd(&ctr->out_used, (unsigned long long)size);
+    base = shfl_u64(base, 0);
+    c.seq += c.base == kNoChunk ? 0u : 1u;
+    c.base = base;
+    c.size = size;
+    c.pos = kChunkHeader;
+    c.valid = base + size <= out_cap ? 1u : 0u;
+    if (c.valid) {
+        if (lane_id() == 0) {
+            out[base] = size;
+            out[base + 1] = task;
+            out[base + 2] = c.seq;
+            out[base + 3] = 0;
+        }
+    } else if (lane_id() == 0) {
+        atomicOr(&ctr->flags, kFlagOutOverflow);
+    }
+    return c.valid != 0;
+}
+
 __device__ __forceinline__ void flag_stack(DfsCounters *ctr, uint64_t need) {
     if (lane_id() == 0) {
         atomicOr(&ctr->flags, kFlagStackOverflow);
@@ -275,9 +353,9 @@ __device__ __forceinline__ void flag_stack(DfsCounters *ctr, uint64_t need) {
     }
 }
 
-__device__ void process_task(const InstDesc &I, uint32_t inst, const Task &T, uint32_t *region,
+__device__ void process_task(const InstDesc &I, uint32_t task, const Task &T, uint32_t *region,
                              uint64_t S, WaveShared &ws, uint32_t *out, uint64_t out_cap,
-                             DfsCounters *ctr, WaveStats &st) {
+                             DfsCounters *ctr, WaveStats &st, OutChunk &oc) {
     const uint32_t lane = lane_id();
     const uint32_t Wp = I.Wp, C = Wp / 4;  // 128-bit chunks per row
     const uint32_t a0 = I.l2_off[T.node], k1 = I.l2_off[T.node + 1] - a0;
@@ -307,7 +385,7 @@ __device__ void process_task(const InstDesc &I, uint32_t inst, const Task &T, ui
             const uint32_t atom = I.l2_atom[a0 + T.r0 + e];
             const uint4 *src = reinterpret_cast<const uint4 *>(I.rows + (uint64_t)atom * Wp);
             uint4 *dst = reinterpret_cast<uint4 *>(region + (uint64_t)e * Wp);
-            for (uint32_t c = lane; c < C; c += kWave) dst[c] = and4(base[c], src[c]);
+            and_rows(dst, base, src, C, lane);
         }
     }
     __threadfence_block();
@@ -351,7 +429,7 @@ __device__ void process_task(const InstDesc &I, uint32_t inst, const Task &T, ui
             if (jj < nj) {
                 const uint4 *row_j = reinterpret_cast<const uint4 *>(
                     region + F.rows_base + (uint64_t)(r + 1 + jj) * Wp);
-                for (uint32_t c = sub; c < C; c += g) acc += popc4(row_r[c], row_j[c]);
+                acc = popc_rows(row_r, row_j, C, sub, g);
             }
             for (uint32_t off = g >> 1; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, kWave);
             const bool freq = sub == 0 && jj < nj && acc >= I.minsup;
@@ -373,21 +451,17 @@ __device__ void process_task(const InstDesc &I, uint32_t inst, const Task &T, ui
         const uint32_t len = (uint32_t)depth + 3;
         if (I.max_len == 0 || len <= I.max_len) {
             const uint32_t rec = kRecHeader + len;
-            unsigned long long base = 0;
-            if (lane == 0) base = atomicAdd(&ctr->out_used, (unsigned long long)nf * rec);
-            base = shfl_u64(base, 0);
-            if (base + (unsigned long long)nf * rec <= out_cap) {
+            if (chunk_reserve(oc, nf * rec, task, out, out_cap, ctr)) {
+                uint32_t *base = out + oc.base + oc.pos;
                 for (uint32_t e = lane; e < nf; e += kWave) {
-                    uint32_t *o = out + base + (uint64_t)e * rec;
-                    o[0] = inst;
-                    o[1] = len;
-                    o[2] = tmp[nj + e];
-                    for (uint32_t q = 0; q + 1 < len; q++) o[3 + q] = ws.prefix[q];
-                    o[3 + len - 1] = tmp[e];
+                    uint32_t *o = base + (uint64_t)e * rec;
+                    o[0] = len;
+                    o[1] = tmp[nj + e];
+                    for (uint32_t q = 0; q + 1 < len; q++) o[2 + q] = ws.prefix[q];
+                    o[2 + len - 1] = tmp[e];
                 }
-            } else if (lane == 0) {
-                atomicOr(&ctr->flags, kFlagOutOverflow);
             }
+            oc.pos += nf * rec;
         }
 
         // the child class [prefix + a_r | frequent later atoms]
@@ -421,7 +495,7 @@ __device__ void process_task(const InstDesc &I, uint32_t inst, const Task &T, ui
                 const uint4 *row_j =
                     reinterpret_cast<const uint4 *>(region + F.rows_base + (uint64_t)src * Wp);
                 uint4 *dst = reinterpret_cast<uint4 *>(region + rows_top + (uint64_t)c * Wp);
-                for (uint32_t q = lane; q < C; q += kWave) dst[q] = and4(row_r[q], row_j[q]);
+                and_rows(dst, row_r, row_j, C, lane);
             }
             __threadfence_block();
             st.child_rows += nf;
@@ -449,6 +523,7 @@ __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Tas
     WaveShared &ws = shared[w];
     const uint64_t wave_id = (uint64_t)blockIdx.x * kWavesPerBlock + w;
     uint32_t *region = stack + wave_id * stack_words;
+    unsigned long long busy = 0;
     for (;;) {
         unsigned long long t0 = 0;
         if (lane == 0) t0 = atomicAdd(&ctr->task_head, (unsigned long long)tasks_per_claim);
@@ -458,7 +533,12 @@ __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Tas
         for (uint64_t t = t0; t < t1; t++) {
             const Task T = tasks[t];
             WaveStats st{0, 0, 0};
-            process_task(insts[T.inst], T.inst, T, region, stack_words, ws, out, out_cap, ctr, st);
+            OutChunk oc{kNoChunk, 0u, 0u, 0u, 0u};
+            const unsigned long long c0 = wall_clock64();
+            process_task(insts[T.inst], (uint32_t)t, T, region, stack_words, ws, out, out_cap, ctr,
+                         st, oc);
+            close_chunk(oc, out);
+            busy += wall_clock64() - c0;
             if (lane == 0) {
                 InstCounters &ic = ictr[T.inst];
                 if (st.candidates) atomicAdd(&ic.candidates, st.candidates);
@@ -466,6 +546,10 @@ __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Tas
                 if (st.child_rows) atomicAdd(&ic.child_rows, st.child_rows);
             }
         }
+    }
+    if (lane == 0 && busy) {
+        atomicAdd(&ctr->busy_sum, busy);
+        atomicMax(&ctr->busy_max, busy);
     }
 }
 

@@ -47,9 +47,17 @@ std::vector<uint64_t> reservoir_indices(uint64_t stream_len, uint64_t n, uint64_
 // job and the makespan.
 double lpt_schedule(const std::vector<double> &w, uint32_t p, std::vector<uint32_t> &worker);
 
+// Partition + LPT order of first-level classes given per-row weights.
+void partition_lpt_order(const std::vector<PlanClass> &cls_in,
+                         const std::vector<const double *> &rw,
+                         const std::vector<const double *> &rp, double alpha, uint32_t n_workers,
+                         bool no_split, std::vector<PlanClass> &out);
+
 // Builds the task list of all instances in LPT order.
+// *est_out_words receives an estimate of the output words of the whole
+// run (0 without a sample estimate).
 fim_status plan_tasks(fim_ctx *ctx, const std::vector<PlanInput> &in, const fim_options &opts,
                       uint32_t n_workers, std::vector<Task> &tasks,
-                      std::vector<PlanClass> *classes = nullptr);
+                      std::vector<PlanClass> *classes = nullptr, uint64_t *est_out_words = nullptr);
 
 }  // namespace fim

@@ -88,7 +88,8 @@ double lpt_schedule(const std::vector<double> &w, uint32_t p, std::vector<uint32
 // usable estimate exists for that instance.
 static fim_status estimate_rows(fim_ctx *ctx, const std::vector<PlanInput> &in,
                                 const fim_options &opts,
-                                std::vector<std::vector<double>> &row_w) {
+                                std::vector<std::vector<double>> &row_w, uint64_t &out_words) {
+    out_words = 0;
     const uint32_t n_inst = (uint32_t)in.size();
     row_w.assign(n_inst, {});
     const uint32_t want_tx = opts.sample_tx ? opts.sample_tx : default_sample_tx(0.02, 0.05);
@@ -153,6 +154,8 @@ static fim_status estimate_rows(fim_ctx *ctx, const std::vector<PlanInput> &in,
         if (R->truncated) continue;  // exploded sample: no estimate
         const uint64_t L = R->supp.size();
         if (L == 0) continue;
+        // the sample's output, with room to spare, sizes the real output
+        out_words += (R->items.size() + (kRecHeader + 1) * L) * 2;
         std::vector<uint64_t> keep = reservoir_indices(L, n_fi, opts.seed + 7 * q + 1);
         // Phase 2 sizes: every sampled itemset of length >= 3 lies in one
         // second-level class [a, b | ...]: a = its first item in the miner's
@@ -209,79 +212,101 @@ static fim_status estimate_rows(fim_ctx *ctx, const std::vector<PlanInput> &in,
     return FIM_OK;
 }
 
+// Partition + LPT order over classes given by their row weights.
+// cls_in: one entry per first-level class with >= 2 atoms (inst, node,
+// r0 = 0, r1 = n_atoms - 1); rw[k] the row weights of class k; rp[k] the
+// row proxies.  Output classes in LPT order.
+void partition_lpt_order(const std::vector<PlanClass> &cls_in,
+                         const std::vector<const double *> &rw,
+                         const std::vector<const double *> &rp, double alpha, uint32_t n_workers,
+                         bool no_split, std::vector<PlanClass> &out) {
+    out.clear();
+    double total = 0.0;
+    for (size_t k = 0; k < cls_in.size(); k++)
+        for (uint32_t r = 0; r < cls_in[k].r1; r++) total += rw[k][r];
+    const double theta = std::max(alpha * total / (double)std::max<uint32_t>(n_workers, 1), 1e-300);
+    for (size_t k = 0; k < cls_in.size(); k++) {
+        const PlanClass &c = cls_in[k];
+        const uint32_t rows = c.r1;  // rows with a later atom
+        double cw = 0.0, cp = 0.0;
+        for (uint32_t r = 0; r < rows; r++) {
+            cw += rw[k][r];
+            cp += rp[k][r];
+        }
+        if (cw <= theta || no_split || rows == 1) {
+            out.push_back({c.inst, c.node, 0, rows, cw, cp});
+            continue;
+        }
+        uint32_t r0 = 0;
+        double acc = 0.0, accp = 0.0;
+        for (uint32_t r = 0; r < rows; r++) {
+            const double v = rw[k][r];
+            if (r > r0 && acc + v > theta) {
+                out.push_back({c.inst, c.node, r0, r, acc, accp});
+                r0 = r;
+                acc = 0.0;
+                accp = 0.0;
+            }
+            acc += v;
+            accp += rp[k][r];
+        }
+        out.push_back({c.inst, c.node, r0, rows, acc, accp});
+    }
+    // LPT order: decreasing estimate, then decreasing proxy, then position
+    std::stable_sort(out.begin(), out.end(), [](const PlanClass &a, const PlanClass &b) {
+        if (a.weight != b.weight) return a.weight > b.weight;
+        return a.proxy > b.proxy;
+    });
+}
+
 fim_status plan_tasks(fim_ctx *ctx, const std::vector<PlanInput> &in, const fim_options &opts,
                       uint32_t n_workers, std::vector<Task> &tasks,
-                      std::vector<PlanClass> *classes_out) {
+                      std::vector<PlanClass> *classes_out, uint64_t *est_out_words) {
     tasks.clear();
     const uint32_t n_inst = (uint32_t)in.size();
     std::vector<std::vector<double>> row_w;
+    uint64_t ow = 0;
     if (!(opts.flags & FIM_FLAG_NO_ESTIMATE)) {
-        fim_status s = estimate_rows(ctx, in, opts, row_w);
+        fim_status s = estimate_rows(ctx, in, opts, row_w, ow);
+        if (est_out_words) *est_out_words = ow;
         if (s != FIM_OK) return s;
     } else {
         row_w.assign(n_inst, {});
     }
     // proxy weight of a second-level class: pairs of its child class times
     // words per row (the weight of a class with k atoms in Zaki's bitonic
-    // scheduling is C(k, 2))
-    auto proxy = [&](uint32_t q, uint32_t i, uint32_t r) {
-        const uint32_t f = (*in[q].l2_off)[i + 1] - (*in[q].l2_off)[i];
-        const double k = (double)(f - r - 1);
-        return (k * (k + 1.0) / 2.0 + 1.0) * (double)in[q].W;
-    };
-    // when an instance has no sample estimate, its rows get proxy weights
-    double total = 0.0;
-    std::vector<std::vector<double>> w(n_inst);
+    // scheduling is C(k, 2)); instances without a sample estimate use it
+    std::vector<std::vector<double>> w(n_inst), px(n_inst);
+    std::vector<PlanClass> cls_in;
+    std::vector<const double *> rw, rp;
     for (uint32_t q = 0; q < n_inst; q++) {
         const auto &l2o = *in[q].l2_off;
-        w[q].assign(in[q].l2_atom->size(), 0.0);
+        const size_t na = in[q].l2_atom->size();
+        w[q].assign(na, 0.0);
+        px[q].assign(na, 0.0);
         const bool est = !row_w[q].empty();
-        for (uint32_t i = 0; i < in[q].n_freq; i++)
-            for (uint32_t r = 0; r + 1 < l2o[i + 1] - l2o[i]; r++) {
-                const double v = est ? row_w[q][l2o[i] + r] : proxy(q, i, r);
-                w[q][l2o[i] + r] = v;
-                total += v;
+        for (uint32_t i = 0; i < in[q].n_freq; i++) {
+            const uint32_t f = l2o[i + 1] - l2o[i];
+            for (uint32_t r = 0; r + 1 < f; r++) {
+                const double k = (double)(f - r - 1);
+                px[q][l2o[i] + r] = (k * (k + 1.0) / 2.0 + 1.0) * (double)in[q].W;
+                w[q][l2o[i] + r] = est ? row_w[q][l2o[i] + r] : px[q][l2o[i] + r];
             }
+        }
     }
-    // Partition: split a class whose estimate exceeds alpha * total / P into
-    // contiguous ranges of its second-level classes
-    const double theta = std::max(opts.alpha * total / (double)std::max<uint32_t>(n_workers, 1), 1e-300);
-    std::vector<PlanClass> cls;
     for (uint32_t q = 0; q < n_inst; q++) {
         const auto &l2o = *in[q].l2_off;
         for (uint32_t i = 0; i < in[q].n_freq; i++) {
             const uint32_t f = l2o[i + 1] - l2o[i];
             if (f < 2) continue;
-            double cw = 0.0, cp = 0.0;
-            for (uint32_t r = 0; r + 1 < f; r++) {
-                cw += w[q][l2o[i] + r];
-                cp += proxy(q, i, r);
-            }
-            if (cw <= theta || (opts.flags & FIM_FLAG_NO_SPLIT) || f == 2) {
-                cls.push_back({q, i, 0, f - 1, cw, cp});
-                continue;
-            }
-            uint32_t r0 = 0;
-            double acc = 0.0, accp = 0.0;
-            for (uint32_t r = 0; r + 1 < f; r++) {
-                const double v = w[q][l2o[i] + r];
-                if (r > r0 && acc + v > theta) {
-                    cls.push_back({q, i, r0, r, acc, accp});
-                    r0 = r;
-                    acc = 0.0;
-                    accp = 0.0;
-                }
-                acc += v;
-                accp += proxy(q, i, r);
-            }
-            cls.push_back({q, i, r0, f - 1, acc, accp});
+            cls_in.push_back({q, i, 0, f - 1, 0.0, 0.0});
+            rw.push_back(w[q].data() + l2o[i]);
+            rp.push_back(px[q].data() + l2o[i]);
         }
     }
-    // LPT order: decreasing estimate, then decreasing proxy, then position
-    std::stable_sort(cls.begin(), cls.end(), [](const PlanClass &a, const PlanClass &b) {
-        if (a.weight != b.weight) return a.weight > b.weight;
-        return a.proxy > b.proxy;
-    });
+    std::vector<PlanClass> cls;
+    partition_lpt_order(cls_in, rw, rp, opts.alpha, n_workers,
+                        (opts.flags & FIM_FLAG_NO_SPLIT) != 0, cls);
     tasks.reserve(cls.size());
     for (const PlanClass &c : cls) tasks.push_back(Task{c.inst, c.node, c.r0, c.r1});
     if (classes_out) *classes_out = std::move(cls);
@@ -289,3 +314,79 @@ fim_status plan_tasks(fim_ctx *ctx, const std::vector<PlanInput> &in, const fim_
 }
 
 }  // namespace fim
+
+// ====================================================================== ABI
+
+extern "C" fim_status fim_estimate_sample_sizes(double eps_db, double delta_db, double rho,
+                                                double eps_fi, double delta_fi,
+                                                uint32_t *sample_tx, uint32_t *sample_fi) {
+    auto in01 = [](double x) { return x > 0.0 && x < 1.0; };
+    if (!in01(eps_db) || !in01(delta_db) || !in01(rho) || !in01(eps_fi) || !in01(delta_fi) ||
+        rho + eps_fi >= 1.0)
+        return fim::set_error(FIM_E_INVALID_ARG, "sample-size parameters out of range");
+    if (sample_tx) *sample_tx = fim::default_sample_tx(eps_db, delta_db);
+    if (sample_fi) *sample_fi = fim::default_sample_fi(rho, eps_fi, delta_fi);
+    return FIM_OK;
+}
+
+extern "C" fim_status fim_reservoir_sample(uint64_t stream_len, uint64_t n, uint64_t seed,
+                                           uint64_t *out) {
+    if (!out && n && stream_len) return fim::set_error(FIM_E_INVALID_ARG, "out is NULL");
+    std::vector<uint64_t> r = fim::reservoir_indices(stream_len, n, seed);
+    std::copy(r.begin(), r.end(), out);
+    return FIM_OK;
+}
+
+extern "C" fim_status fim_lpt_schedule(const double *weights, uint64_t n_jobs, uint32_t n_workers,
+                                       uint32_t *worker_of_job, double *makespan) {
+    if ((n_jobs && (!weights || !worker_of_job)) || n_workers == 0)
+        return fim::set_error(FIM_E_INVALID_ARG, "NULL argument or no workers");
+    std::vector<double> w(weights, weights + n_jobs);
+    std::vector<uint32_t> wk;
+    const double ms = fim::lpt_schedule(w, n_workers, wk);
+    std::copy(wk.begin(), wk.end(), worker_of_job);
+    if (makespan) *makespan = ms;
+    return FIM_OK;
+}
+
+extern "C" fim_status fim_partition_lpt(uint32_t n_classes, const uint32_t *n_atoms,
+                                        const double *row_weights, double alpha,
+                                        uint32_t n_workers, uint32_t flags, uint32_t *tasks,
+                                        uint32_t capacity, uint32_t *n_tasks, double *makespan) {
+    if ((n_classes && (!n_atoms || !row_weights)) || !n_tasks || n_workers == 0 ||
+        !(alpha > 0.0) || alpha > 1.0)
+        return fim::set_error(FIM_E_INVALID_ARG, "invalid argument");
+    std::vector<fim::PlanClass> cls_in;
+    std::vector<const double *> rw, rp;
+    std::vector<double> zeros;
+    uint64_t off = 0, maxa = 0;
+    for (uint32_t c = 0; c < n_classes; c++) maxa = std::max<uint64_t>(maxa, n_atoms[c]);
+    zeros.assign(maxa + 1, 0.0);
+    for (uint32_t c = 0; c < n_classes; c++) {
+        if (n_atoms[c] >= 2) {
+            cls_in.push_back({0, c, 0, n_atoms[c] - 1, 0.0, 0.0});
+            rw.push_back(row_weights + off);
+            rp.push_back(zeros.data());
+        }
+        off += n_atoms[c];
+    }
+    std::vector<fim::PlanClass> out;
+    fim::partition_lpt_order(cls_in, rw, rp, alpha, n_workers, (flags & FIM_FLAG_NO_SPLIT) != 0,
+                             out);
+    *n_tasks = (uint32_t)out.size();
+    if (makespan) {
+        std::vector<double> w;
+        for (auto &c : out) w.push_back(c.weight);
+        std::vector<uint32_t> wk;
+        *makespan = fim::lpt_schedule(w, n_workers, wk);
+    }
+    if (out.size() > capacity)
+        return fim::set_error(FIM_E_OUTPUT_LIMIT, "task capacity too small");
+    if (!tasks && !out.empty()) return fim::set_error(FIM_E_INVALID_ARG, "tasks is NULL");
+    for (size_t k = 0; k < out.size(); k++) {
+        tasks[3 * k] = out[k].node;
+        tasks[3 * k + 1] = out[k].r0;
+        tasks[3 * k + 2] = out[k].r1;
+    }
+    return FIM_OK;
+}

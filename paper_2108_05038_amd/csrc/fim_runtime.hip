@@ -3,11 +3,15 @@
 // runs in the HIP kernels of fim_kernels.hip; the host decides the order of
 // work, moves data and puts the result into canonical order.
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <numeric>
+#include <thread>
 
 #include "fim_host.h"
 #include "fim_plan.h"
@@ -282,6 +286,22 @@ uint64_t ns_since(clk::time_point t0) {
     return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(clk::now() - t0).count();
 }
 
+// FIM_TRACE=1 prints the wall time of every phase of a run to stderr
+struct Tracer {
+    bool on;
+    clk::time_point t0, last;
+    const char *tag;
+    explicit Tracer(const char *t) : on(getenv("FIM_TRACE") != nullptr), t0(clk::now()), last(t0), tag(t) {}
+    void mark(const char *what) {
+        if (!on) return;
+        const auto now = clk::now();
+        fprintf(stderr, "[fim %s] %-24s %8.3f ms (total %8.3f ms)\n", tag, what,
+                std::chrono::duration<double, std::milli>(now - last).count(),
+                std::chrono::duration<double, std::milli>(now - t0).count());
+        last = now;
+    }
+};
+
 // per-instance state of one run
 struct Inst {
     const fim_db *db = nullptr;
@@ -353,33 +373,117 @@ static void build_level2(Inst &I, bool by_id) {
     }
 }
 
-// lexicographic order of the itemsets (items ascending inside each)
+// run fn(i) for i in [0, count) on up to n_thr threads
+template <class Fn>
+static void parallel_for(uint64_t count, uint32_t n_thr, Fn fn) {
+    if (n_thr <= 1 || count < 2) {
+        for (uint64_t i = 0; i < count; i++) fn(i);
+        return;
+    }
+    std::atomic<uint64_t> next{0};
+    std::vector<std::thread> th;
+    for (uint32_t t = 0; t < std::min<uint64_t>(n_thr, count); t++)
+        th.emplace_back([&] {
+            for (uint64_t i; (i = next.fetch_add(1)) < count;) fn(i);
+        });
+    for (auto &x : th) x.join();
+}
+
+static uint32_t host_threads(uint64_t work) {
+    if (work < 20000) return 1;
+    return std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+}
+
+// lexicographic order of the itemsets (items ascending inside each).  When
+// every itemset fits in 128 bits as a sequence of (item + 1) codes, most
+// significant first (a prefix then sorts before its extensions because the
+// missing codes are 0), the itemsets are sorted as integer keys; otherwise
+// by comparing item sequences.  Itemsets are bucketed by their first item
+// and the buckets sorted in parallel.
 static void canonicalize(std::vector<uint32_t> &items, std::vector<uint64_t> &off,
                          std::vector<uint32_t> &supp) {
     const uint64_t n = supp.size();
-    for (uint64_t i = 0; i < n; i++) std::sort(items.begin() + off[i], items.begin() + off[i + 1]);
-    std::vector<uint64_t> idx(n);
-    std::iota(idx.begin(), idx.end(), 0ull);
-    const uint32_t *it = items.data();
+    if (n == 0) return;
+    const uint32_t n_thr = host_threads(n);
+    uint32_t *it = items.data();
     const uint64_t *o = off.data();
-    std::sort(idx.begin(), idx.end(), [&](uint64_t a, uint64_t b) {
-        const uint32_t *x = it + o[a], *y = it + o[b];
-        const uint64_t nx = o[a + 1] - o[a], ny = o[b + 1] - o[b];
-        const uint64_t m = std::min(nx, ny);
-        for (uint64_t k = 0; k < m; k++)
-            if (x[k] != y[k]) return x[k] < y[k];
-        return nx < ny;
+    const uint64_t blk = 8192, nblk = (n + blk - 1) / blk;
+    parallel_for(nblk, n_thr, [&](uint64_t b) {
+        for (uint64_t i = b * blk; i < std::min(n, (b + 1) * blk); i++)
+            if (o[i + 1] - o[i] > 1) std::sort(it + o[i], it + o[i + 1]);
     });
-    std::vector<uint32_t> ni(items.size()), ns(n);
-    std::vector<uint64_t> no(n + 1);
-    uint64_t pos = 0;
-    no[0] = 0;
-    for (uint64_t q = 0; q < n; q++) {
-        const uint64_t a = idx[q];
-        for (uint64_t k = o[a]; k < o[a + 1]; k++) ni[pos++] = it[k];
-        no[q + 1] = pos;
-        ns[q] = supp[a];
+    uint32_t max_item = 0;
+    uint64_t max_len = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        max_len = std::max<uint64_t>(max_len, o[i + 1] - o[i]);
+        max_item = std::max(max_item, it[o[i + 1] - 1]);
     }
+    uint32_t bits = 1;
+    while (bits < 32 && ((uint64_t)max_item + 1) >> bits) bits++;
+    std::vector<uint64_t> start(max_item + 2, 0);
+    for (uint64_t i = 0; i < n; i++) start[it[o[i]] + 1]++;
+    for (uint32_t b = 0; b <= max_item; b++) start[b + 1] += start[b];
+    std::vector<uint64_t> idx(n);
+    {
+        std::vector<uint64_t> fill(start.begin(), start.end() - 1);
+        for (uint64_t i = 0; i < n; i++) idx[fill[it[o[i]]]++] = i;
+    }
+    std::vector<uint32_t> order;
+    for (uint32_t b = 0; b <= max_item; b++)
+        if (start[b + 1] - start[b] > 1) order.push_back(b);
+    std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        return start[a + 1] - start[a] > start[b + 1] - start[b];
+    });
+    if ((uint64_t)bits * max_len <= 128) {
+        typedef unsigned __int128 u128;
+        struct KI {
+            u128 key;
+            uint64_t i;
+        };
+        std::vector<KI> kv(n);
+        parallel_for(nblk, n_thr, [&](uint64_t b) {
+            for (uint64_t q = b * blk; q < std::min(n, (b + 1) * blk); q++) {
+                const uint64_t a = idx[q];
+                u128 key = 0;
+                uint32_t sh = 128;
+                for (uint64_t k = o[a]; k < o[a + 1]; k++) {
+                    sh -= bits;
+                    key |= (u128)(it[k] + 1) << sh;
+                }
+                kv[q] = KI{key, a};
+            }
+        });
+        parallel_for(order.size(), n_thr, [&](uint64_t k) {
+            const uint32_t b = order[k];
+            std::sort(kv.begin() + start[b], kv.begin() + start[b + 1],
+                      [](const KI &x, const KI &y) { return x.key < y.key; });
+        });
+        for (uint64_t q = 0; q < n; q++) idx[q] = kv[q].i;
+    } else {
+        auto less = [&](uint64_t a, uint64_t b) {
+            const uint32_t *x = it + o[a], *y = it + o[b];
+            const uint64_t nx = o[a + 1] - o[a], ny = o[b + 1] - o[b];
+            const uint64_t m = std::min(nx, ny);
+            for (uint64_t k = 1; k < m; k++)  // item 0 is the bucket
+                if (x[k] != y[k]) return x[k] < y[k];
+            return nx < ny;
+        };
+        parallel_for(order.size(), n_thr, [&](uint64_t k) {
+            const uint32_t b = order[k];
+            std::sort(idx.begin() + start[b], idx.begin() + start[b + 1], less);
+        });
+    }
+    std::vector<uint64_t> no(n + 1);
+    no[0] = 0;
+    for (uint64_t q = 0; q < n; q++) no[q + 1] = no[q] + (o[idx[q] + 1] - o[idx[q]]);
+    std::vector<uint32_t> ni(items.size()), ns(n);
+    parallel_for(nblk, n_thr, [&](uint64_t b) {
+        for (uint64_t q = b * blk; q < std::min(n, (b + 1) * blk); q++) {
+            const uint64_t a = idx[q];
+            std::copy(it + o[a], it + o[a + 1], ni.begin() + no[q]);
+            ns[q] = supp[a];
+        }
+    });
     items.swap(ni);
     off.swap(no);
     supp.swap(ns);
@@ -389,6 +493,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                      std::vector<fim_result *> &results, bool use_graph) {
     const auto t_start = clk::now();
     const fim_options opts = resolve_options(&opts_in);
+    Tracer tr((opts.flags & kFlagInternalSample) ? "sample" : "mine");
     const bool by_id = (opts.flags & FIM_FLAG_ORDER_BY_ID) != 0;
     const uint32_t n_inst = (uint32_t)reqs.size();
     HIPCHK(hipSetDevice(ctx->device));
@@ -410,6 +515,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                               hipMemcpyDeviceToHost, s));
     }
     HIPCHK(hipStreamSynchronize(s));
+    tr.mark("item supports");
 
     // ---------------- a3 + root class: bitmaps and frequent pairs
     hipEvent_t ev0, ev1;
@@ -422,7 +528,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             (void)hipEventDestroy(b);
         }
     } evg{ev0, ev1};
-    HIPCHK(hipEventRecord(ev0, s));
+    float root_ms = 0.f;
     for (uint32_t q = 0; q < n_inst; q++) {
         Inst &I = insts[q];
         rank_items(I, by_id);
@@ -449,15 +555,20 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         ENSURE(I.d_pairs, ctx, cap * 12);
         ENSURE(I.d_npairs, ctx, 8);
         HIPCHK(launch_fill_u32(I.d_npairs.as<uint32_t>(), 2, 0u, s));
+        HIPCHK(hipEventRecord(ev0, s));
         HIPCHK(launch_root_pairs(I.d_rows.as<uint32_t>(), I.n_freq, I.Wp, I.minsup,
                                  I.d_pairs.as<uint32_t>(), cap,
                                  I.d_npairs.as<unsigned long long>(), opts.tile_words, s));
+        HIPCHK(hipEventRecord(ev1, s));
         HIPCHK(hipMemcpyAsync(&I.n_pairs, I.d_npairs.as<void>(), 8, hipMemcpyDeviceToHost, s));
+        // one instance's kernel time (the copy above synchronises the host
+        // only at the end, so read the events after the stream sync below)
+        HIPCHK(hipStreamSynchronize(s));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
+        root_ms += ms;
     }
-    HIPCHK(hipEventRecord(ev1, s));
     HIPCHK(hipStreamSynchronize(s));
-    float root_ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&root_ms, ev0, ev1));
     for (uint32_t q = 0; q < n_inst; q++) {
         Inst &I = insts[q];
         if (I.n_freq < 2 || opts.max_len == 1) continue;
@@ -477,22 +588,26 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                                   hipMemcpyDeviceToHost, s));
         I.st.candidates = all;
         I.st.pair_words = all * I.W;
+        I.st.root_candidates = all;
+        I.st.root_pair_words = all * I.W;
         I.st.bytes_algorithmic = (uint64_t)I.n_freq * I.W * 4;
     }
     HIPCHK(hipStreamSynchronize(s));
     for (uint32_t q = 0; q < n_inst; q++) {
         Inst &I = insts[q];
-        I.st.kernel_ns = (uint64_t)(root_ms * 1e6);
+        I.st.root_kernel_ns = (uint64_t)(root_ms * 1e6);
+        I.st.kernel_ns = I.st.root_kernel_ns;
         if (I.n_pairs) build_level2(I, by_id);
         else I.l2_off.assign(I.n_freq + 1, 0);
     }
 
+    tr.mark("bitmaps + root pairs");
     // ---------------- a4: class-size estimate, Partition, LPT order
     const bool deep = opts.max_len == 0 || opts.max_len >= 3;
     uint32_t n_workers = opts.workers ? opts.workers : (uint32_t)ctx->n_cu * 16;
     n_workers = std::max<uint32_t>(4, (n_workers + 3) / 4 * 4);
     std::vector<Task> tasks;
-    std::vector<PlanClass> plan_all;
+    uint64_t est_out_words = 0;
     if (deep) {
         const auto t_est = clk::now();
         std::vector<PlanInput> pin(n_inst);
@@ -507,7 +622,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             pin[q].l2_off = &I.l2_off;
             pin[q].l2_atom = &I.l2_atom;
         }
-        fim_status ps = plan_tasks(ctx, pin, opts, n_workers, tasks);
+        fim_status ps = plan_tasks(ctx, pin, opts, n_workers, tasks, nullptr, &est_out_words);
         if (ps != FIM_OK) return ps;
         const uint64_t est_ns = ns_since(t_est);
         for (auto &I : insts) I.st.estimate_ns = est_ns;
@@ -520,6 +635,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         }
     }
 
+    tr.mark("estimate + plan");
     // ---------------- a5-a8: one persistent launch over every task
     DevBuf d_desc(ctx), d_tasks(ctx), d_stack(ctx), d_out(ctx), d_ctr(ctx), d_ictr(ctx);
     std::vector<uint32_t> out_host;
@@ -572,7 +688,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         const uint64_t kMaxStack = 0xFFFFFFF0ull;  // frame offsets are 32-bit
         const uint64_t budget_words = (uint64_t)(ctx->total_mem / 4) / 4;
         const bool sample_mode = (opts.flags & kFlagInternalSample) != 0;
-        uint64_t out_cap = sample_mode ? (1ull << 24) : (1ull << 22);
+        uint64_t out_cap = sample_mode ? (1ull << 24) : std::max<uint64_t>(1ull << 24, est_out_words);
         int attempts = 0;
         for (;;) {
             uint32_t workers = n_workers;
@@ -619,6 +735,14 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                                   hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             HIPCHK(hipEventElapsedTime(&dfs_ms, ev0, ev1));
+            if (tr.on) {
+                int clk_khz = 0;
+                (void)hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, ctx->device);
+                const double mean = (double)ctr.busy_sum / workers;
+                fprintf(stderr, "[fim %s] dfs kernel %.3f ms, %zu tasks, %u workers, busiest %.3f ms, mean %.3f ms, imbalance %.1f, flags %u\n",
+                        tr.tag, dfs_ms, tasks.size(), workers, clk_khz ? ctr.busy_max / (double)clk_khz : 0.0,
+                        clk_khz ? mean / clk_khz : 0.0, mean > 0 ? ctr.busy_max / mean : 0.0, ctr.flags);
+            }
             if (ctr.flags & kFlagDepthOverflow)
                 return set_error(FIM_E_OUTPUT_LIMIT, "an itemset is longer than " +
                                                          std::to_string(kMaxDepth + 2) + " items");
@@ -646,6 +770,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         HIPCHK(hipStreamSynchronize(s));
     }
 
+    tr.mark("persistent dfs + copy");
     // ---------------- a9: results in canonical order
     std::vector<std::vector<uint32_t>> r_items(n_inst), r_supp(n_inst);
     std::vector<std::vector<uint64_t>> r_off(n_inst);
@@ -657,29 +782,95 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             r_off[q].push_back(r_items[q].size());
             r_supp[q].push_back(I.supp_of_rank[r]);
         }
-        if (opts.max_len != 1)
-            for (uint64_t p = 0; p < I.n_pairs; p++) {
-                r_items[q].push_back(I.item_of_rank[I.pairs[3 * p]]);
-                r_items[q].push_back(I.item_of_rank[I.pairs[3 * p + 1]]);
-                r_off[q].push_back(r_items[q].size());
-                r_supp[q].push_back(I.pairs[3 * p + 2]);
-            }
+        if (opts.max_len != 1 && I.n_pairs)  // in class order: deterministic
+            for (uint32_t i = 0; i < I.n_freq; i++)
+                for (uint32_t k = I.l2_off[i]; k < I.l2_off[i + 1]; k++) {
+                    r_items[q].push_back(I.item_of_rank[i]);
+                    r_items[q].push_back(I.item_of_rank[I.l2_atom[k]]);
+                    r_off[q].push_back(r_items[q].size());
+                    r_supp[q].push_back(I.l2_supp[k]);
+                }
         I.st.candidates += ictr[q].candidates;
         I.st.pair_words += ictr[q].pair_words;
-        I.st.bytes_algorithmic +=
+        I.st.dfs_bytes_algorithmic =
             (uint64_t)I.W * 4 * (2 * I.first_class_rows + 2 * ictr[q].child_rows);
-        I.st.kernel_ns += (uint64_t)(dfs_ms * 1e6);
+        I.st.bytes_algorithmic += I.st.dfs_bytes_algorithmic;
+        I.st.dfs_kernel_ns = (uint64_t)(dfs_ms * 1e6);
+        I.st.kernel_ns += I.st.dfs_kernel_ns;
         I.st.n_tasks = 0;
     }
     for (const Task &T : tasks) insts[T.inst].st.n_tasks++;
-    for (uint64_t p = 0; p + kRecHeader <= out_host.size();) {
-        const uint32_t q = out_host[p], len = out_host[p + 1], sp = out_host[p + 2];
-        if (len == 0 || q >= n_inst || p + kRecHeader + len > out_host.size()) break;
-        const Inst &I = insts[q];
-        for (uint32_t k = 0; k < len; k++) r_items[q].push_back(I.item_of_rank[out_host[p + 3 + k]]);
-        r_off[q].push_back(r_items[q].size());
-        r_supp[q].push_back(sp);
-        p += kRecHeader + len;
+    {
+        // chunks of the output arena, put back in (task, chunk number) order
+        struct Chunk {
+            uint32_t task, seq;
+            uint64_t off, used;
+        };
+        std::vector<Chunk> chunks;
+        const uint64_t limit = out_host.size();
+        for (uint64_t p = 0; p + kChunkHeader <= limit;) {
+            const uint32_t size = out_host[p];
+            if (size < kChunkHeader || p + size > limit) break;
+            const uint32_t used = out_host[p + 3];
+            if (used >= kChunkHeader && used <= size && out_host[p + 1] < tasks.size())
+                chunks.push_back({out_host[p + 1], out_host[p + 2], p, used});
+            p += size;
+        }
+        std::sort(chunks.begin(), chunks.end(), [](const Chunk &a, const Chunk &b) {
+            return a.task != b.task ? a.task < b.task : a.seq < b.seq;
+        });
+        // records and items of every chunk, then each chunk fills its own
+        // slice of the preallocated result arrays
+        const uint64_t nch = chunks.size();
+        std::vector<uint64_t> c_sets(nch, 0), c_items(nch, 0);
+        const uint32_t n_thr = host_threads(out_host.size() / 8);
+        parallel_for(nch, n_thr, [&](uint64_t k) {
+            const Chunk &c = chunks[k];
+            for (uint64_t p = c.off + kChunkHeader; p + kRecHeader <= c.off + c.used;) {
+                const uint32_t len = out_host[p];
+                if (len == 0 || p + kRecHeader + len > c.off + c.used) break;
+                c_sets[k]++;
+                c_items[k] += len;
+                p += kRecHeader + len;
+            }
+        });
+        std::vector<uint64_t> set_at(nch), item_at(nch);
+        {
+            std::vector<uint64_t> ns(n_inst), ni(n_inst);
+            for (uint32_t q = 0; q < n_inst; q++) {
+                ns[q] = r_supp[q].size();
+                ni[q] = r_items[q].size();
+            }
+            for (uint64_t k = 0; k < nch; k++) {
+                const uint32_t q = tasks[chunks[k].task].inst;
+                set_at[k] = ns[q];
+                item_at[k] = ni[q];
+                ns[q] += c_sets[k];
+                ni[q] += c_items[k];
+            }
+            for (uint32_t q = 0; q < n_inst; q++) {
+                r_items[q].resize(ni[q]);
+                r_supp[q].resize(ns[q]);
+                r_off[q].resize(ns[q] + 1);
+            }
+        }
+        parallel_for(nch, n_thr, [&](uint64_t k) {
+            const Chunk &c = chunks[k];
+            const uint32_t q = tasks[c.task].inst;
+            const Inst &I = insts[q];
+            uint32_t *ri = r_items[q].data();
+            uint64_t *ro = r_off[q].data();
+            uint32_t *rs = r_supp[q].data();
+            uint64_t si = set_at[k], ii = item_at[k];
+            for (uint64_t p = c.off + kChunkHeader; p + kRecHeader <= c.off + c.used;) {
+                const uint32_t len = out_host[p];
+                if (len == 0 || p + kRecHeader + len > c.off + c.used) break;
+                for (uint32_t x = 0; x < len; x++) ri[ii++] = I.item_of_rank[out_host[p + 2 + x]];
+                rs[si] = out_host[p + 1];
+                ro[++si] = ii;
+                p += kRecHeader + len;
+            }
+        });
     }
     for (uint32_t q = 0; q < n_inst; q++) {
         if (opts.max_itemsets && r_supp[q].size() > opts.max_itemsets && !truncated)
@@ -695,14 +886,18 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             results.clear();
             return set_error(FIM_E_OOM_HOST, "result");
         }
-        canonicalize(r_items[q], r_off[q], r_supp[q]);
+        // internal sample runs keep the deterministic task order (the
+        // reservoir does not need the canonical one)
+        if (!(opts.flags & kFlagInternalSample)) canonicalize(r_items[q], r_off[q], r_supp[q]);
         R->items.swap(r_items[q]);
         R->off.swap(r_off[q]);
         R->supp.swap(r_supp[q]);
         R->stats = insts[q].st;
+        R->stats.n_itemsets = R->supp.size();
         R->truncated = truncated;
         results[q] = R;
     }
+    tr.mark("decode + canonical order");
     const uint64_t total = ns_since(t_start);
     for (auto *R : results) R->stats.total_ns = total;
     return FIM_OK;
