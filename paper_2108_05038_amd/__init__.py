@@ -318,7 +318,10 @@ class Context:
                         return None
 
                 def _free(ptr, strm, user):
-                    torch.cuda.caching_allocator_delete(ptr)
+                    try:
+                        torch.cuda.caching_allocator_delete(ptr)
+                    except Exception:  # interpreter shutdown
+                        pass
 
                 fa, ff = ALLOC_FN(_alloc), FREE_FN(_free)
                 alloc = fim_allocator(fa, ff, None)

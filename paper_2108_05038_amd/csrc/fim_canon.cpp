@@ -1,0 +1,195 @@
+// Canonical order of a frequent-itemset result (host).
+#include "fim_canon.h"
+
+#include <memory>
+
+namespace fim {
+
+namespace {
+
+typedef unsigned __int128 u128;
+
+struct KeyRec {
+    u128 key;
+    uint64_t i;  // index of the itemset in the input
+};
+
+// exclusive prefix sums of blocks of v computed in parallel
+void block_scan(const std::vector<uint64_t> &block_sum, std::vector<uint64_t> &block_start) {
+    block_start.resize(block_sum.size() + 1);
+    block_start[0] = 0;
+    for (size_t b = 0; b < block_sum.size(); b++) block_start[b + 1] = block_start[b] + block_sum[b];
+}
+
+// itemsets as keys of (item + 1) codes of `bits` bits, most significant
+// first: a prefix has zero codes where its extensions continue, so it sorts
+// first, and two itemsets compare like their item sequences
+void canonical_by_keys(U32Vec &items, U64Vec &off, U32Vec &supp, uint32_t bits, uint32_t n_thr) {
+    const uint64_t n = supp.size();
+    const uint32_t *it = items.data();
+    const uint64_t *o = off.data();
+    std::unique_ptr<KeyRec[]> kv(new KeyRec[n]), kb(new KeyRec[n]);
+    const uint32_t T = std::max(1u, n_thr);
+    const uint64_t per = (n + T - 1) / T;
+    // radix partition on the top B bits (about the first two items)
+    const uint32_t B = std::min<uint32_t>(16, 2 * bits);
+    const uint32_t NB = 1u << B;
+    std::vector<std::vector<uint64_t>> hist(T, std::vector<uint64_t>(NB, 0));
+    parallel_for(T, T, [&](uint64_t t) {
+        const uint64_t a = t * per, e = std::min(n, a + per);
+        auto &h = hist[t];
+        for (uint64_t q = a; q < e; q++) {
+            u128 key = 0;
+            uint32_t sh = 128;
+            for (uint64_t k = o[q]; k < o[q + 1]; k++) {
+                sh -= bits;
+                key |= (u128)(it[k] + 1) << sh;
+            }
+            kv[q].key = key;
+            kv[q].i = q;
+            h[(uint32_t)(key >> (128 - B))]++;
+        }
+    });
+    std::vector<uint64_t> bstart(NB + 1, 0);
+    for (uint32_t b = 0; b < NB; b++) {
+        uint64_t sum = 0;
+        for (uint32_t t = 0; t < T; t++) sum += hist[t][b];
+        bstart[b + 1] = bstart[b] + sum;
+    }
+    parallel_for(T, T, [&](uint64_t t) {
+        // this thread's first slot in every bucket
+        std::vector<uint64_t> pos(NB);
+        for (uint32_t b = 0; b < NB; b++) {
+            uint64_t p = bstart[b];
+            for (uint32_t u = 0; u < t; u++) p += hist[u][b];
+            pos[b] = p;
+        }
+        const uint64_t a = t * per, e = std::min(n, a + per);
+        for (uint64_t q = a; q < e; q++) kb[pos[(uint32_t)(kv[q].key >> (128 - B))]++] = kv[q];
+    });
+    std::vector<uint32_t> big;
+    for (uint32_t b = 0; b < NB; b++)
+        if (bstart[b + 1] - bstart[b] > 1) big.push_back(b);
+    std::sort(big.begin(), big.end(), [&](uint32_t x, uint32_t y) {
+        return bstart[x + 1] - bstart[x] > bstart[y + 1] - bstart[y];
+    });
+    parallel_for(big.size(), T, [&](uint64_t k) {
+        const uint32_t b = big[k];
+        std::sort(kb.get() + bstart[b], kb.get() + bstart[b + 1],
+                  [](const KeyRec &x, const KeyRec &y) { return x.key < y.key; });
+    });
+    // gather: lengths per block, block starts, then every block in parallel
+    const uint64_t blk = 1u << 14, nblk = (n + blk - 1) / blk;
+    std::vector<uint64_t> bsum(nblk, 0), bst;
+    parallel_for(nblk, T, [&](uint64_t b) {
+        uint64_t s = 0;
+        for (uint64_t q = b * blk; q < std::min(n, (b + 1) * blk); q++) {
+            const uint64_t a = kb[q].i;
+            s += o[a + 1] - o[a];
+        }
+        bsum[b] = s;
+    });
+    block_scan(bsum, bst);
+    U32Vec ni(items.size()), ns(n);
+    U64Vec no(n + 1);
+    parallel_for(nblk, T, [&](uint64_t b) {
+        uint64_t w = bst[b];
+        for (uint64_t q = b * blk; q < std::min(n, (b + 1) * blk); q++) {
+            const uint64_t a = kb[q].i;
+            for (uint64_t k = o[a]; k < o[a + 1]; k++) ni[w++] = it[k];
+            no[q + 1] = w;
+            ns[q] = supp[a];
+        }
+    });
+    no[0] = 0;
+    items.swap(ni);
+    off.swap(no);
+    supp.swap(ns);
+}
+
+// general case: itemsets bucketed by their first item, buckets sorted by
+// comparing item sequences
+void canonical_by_compare(U32Vec &items, U64Vec &off, U32Vec &supp, uint32_t max_item,
+                          uint32_t n_thr) {
+    const uint64_t n = supp.size();
+    const uint32_t *it = items.data();
+    const uint64_t *o = off.data();
+    std::vector<uint64_t> start(max_item + 2, 0);
+    for (uint64_t i = 0; i < n; i++) start[it[o[i]] + 1]++;
+    for (uint32_t b = 0; b <= max_item; b++) start[b + 1] += start[b];
+    std::vector<uint64_t> idx(n);
+    {
+        std::vector<uint64_t> fill(start.begin(), start.end() - 1);
+        for (uint64_t i = 0; i < n; i++) idx[fill[it[o[i]]]++] = i;
+    }
+    std::vector<uint32_t> order;
+    for (uint32_t b = 0; b <= max_item; b++)
+        if (start[b + 1] - start[b] > 1) order.push_back(b);
+    std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        return start[a + 1] - start[a] > start[b + 1] - start[b];
+    });
+    auto less = [&](uint64_t a, uint64_t b) {
+        const uint32_t *x = it + o[a], *y = it + o[b];
+        const uint64_t nx = o[a + 1] - o[a], ny = o[b + 1] - o[b];
+        const uint64_t m = std::min(nx, ny);
+        for (uint64_t k = 1; k < m; k++)  // item 0 is the bucket
+            if (x[k] != y[k]) return x[k] < y[k];
+        return nx < ny;
+    };
+    parallel_for(order.size(), n_thr, [&](uint64_t k) {
+        const uint32_t b = order[k];
+        std::sort(idx.begin() + start[b], idx.begin() + start[b + 1], less);
+    });
+    U64Vec no(n + 1);
+    no[0] = 0;
+    for (uint64_t q = 0; q < n; q++) no[q + 1] = no[q] + (o[idx[q] + 1] - o[idx[q]]);
+    U32Vec ni(items.size()), ns(n);
+    const uint64_t blk = 8192, nblk = (n + blk - 1) / blk;
+    parallel_for(nblk, n_thr, [&](uint64_t b) {
+        for (uint64_t q = b * blk; q < std::min(n, (b + 1) * blk); q++) {
+            const uint64_t a = idx[q];
+            std::copy(it + o[a], it + o[a + 1], ni.begin() + no[q]);
+            ns[q] = supp[a];
+        }
+    });
+    items.swap(ni);
+    off.swap(no);
+    supp.swap(ns);
+}
+
+}  // namespace
+
+// Items ascending inside every itemset, then the itemsets in lexicographic
+// order: as 128-bit integer keys when every itemset fits (radix partition on
+// the top bits, buckets sorted in parallel), otherwise by comparison.
+void canonicalize(U32Vec &items, U64Vec &off, U32Vec &supp) {
+    const uint64_t n = supp.size();
+    if (n == 0) return;
+    const uint32_t n_thr = host_threads(n);
+    uint32_t *it = items.data();
+    const uint64_t *o = off.data();
+    const uint64_t blk = 8192, nblk = (n + blk - 1) / blk;
+    std::vector<uint32_t> bmax(nblk, 0);
+    std::vector<uint64_t> blen(nblk, 0);
+    parallel_for(nblk, n_thr, [&](uint64_t b) {
+        uint32_t mi = 0;
+        uint64_t ml = 0;
+        for (uint64_t i = b * blk; i < std::min(n, (b + 1) * blk); i++) {
+            if (o[i + 1] - o[i] > 1) std::sort(it + o[i], it + o[i + 1]);
+            mi = std::max(mi, it[o[i + 1] - 1]);
+            ml = std::max<uint64_t>(ml, o[i + 1] - o[i]);
+        }
+        bmax[b] = mi;
+        blen[b] = ml;
+    });
+    const uint32_t max_item = *std::max_element(bmax.begin(), bmax.end());
+    const uint64_t max_len = *std::max_element(blen.begin(), blen.end());
+    uint32_t bits = 1;
+    while (bits < 32 && ((uint64_t)max_item + 1) >> bits) bits++;
+    if ((uint64_t)bits * max_len <= 128)
+        canonical_by_keys(items, off, supp, bits, n_thr);
+    else
+        canonical_by_compare(items, off, supp, max_item, n_thr);
+}
+
+}  // namespace fim

@@ -1,0 +1,66 @@
+// Host-side helpers for results: a small thread pool loop and the
+// canonical (lexicographic) order of itemsets.
+#pragma once
+
+#include <stdint.h>
+
+#include <algorithm>
+#include <atomic>
+#include <memory>
+#include <utility>
+#include <thread>
+#include <vector>
+
+namespace fim {
+
+// std::allocator whose value-less construct leaves the element
+// uninitialised, so that resizing large result arrays does not first zero
+// them on one thread
+template <class T>
+struct UninitAlloc : std::allocator<T> {
+    template <class U>
+    struct rebind {
+        using other = UninitAlloc<U>;
+    };
+    UninitAlloc() = default;
+    template <class U>
+    UninitAlloc(const UninitAlloc<U> &) {}
+    template <class U>
+    void construct(U *p) noexcept {
+        ::new ((void *)p) U;
+    }
+    template <class U, class... A>
+    void construct(U *p, A &&...a) {
+        ::new ((void *)p) U(std::forward<A>(a)...);
+    }
+};
+
+using U32Vec = std::vector<uint32_t, UninitAlloc<uint32_t>>;
+using U64Vec = std::vector<uint64_t, UninitAlloc<uint64_t>>;
+
+// run fn(i) for i in [0, count) on up to n_thr threads
+template <class Fn>
+inline void parallel_for(uint64_t count, uint32_t n_thr, Fn fn) {
+    if (n_thr <= 1 || count < 2) {
+        for (uint64_t i = 0; i < count; i++) fn(i);
+        return;
+    }
+    std::atomic<uint64_t> next{0};
+    std::vector<std::thread> th;
+    for (uint32_t t = 0; t < std::min<uint64_t>(n_thr, count); t++)
+        th.emplace_back([&] {
+            for (uint64_t i; (i = next.fetch_add(1)) < count;) fn(i);
+        });
+    for (auto &x : th) x.join();
+}
+
+inline uint32_t host_threads(uint64_t work) {
+    if (work < 20000) return 1;
+    return std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+}
+
+// Puts a result into canonical order: items ascending inside every itemset,
+// itemsets in lexicographic order (a prefix before its extensions).
+void canonicalize(U32Vec &items, U64Vec &off, U32Vec &supp);
+
+}  // namespace fim

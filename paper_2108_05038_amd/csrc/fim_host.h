@@ -8,6 +8,7 @@
 
 #include "../../include/fim.h"
 #include "fim_internal.h"
+#include "fim_canon.h"
 
 struct fim_ctx {
     int device = 0;
@@ -18,6 +19,11 @@ struct fim_ctx {
     int n_cu = 256;
     size_t total_mem = 0;
     std::string arch;
+
+    // pinned host staging buffer for device-to-host copies of results
+    uint32_t *pinned = nullptr;
+    size_t pinned_words = 0;
+    uint32_t *stage(size_t words);
 
     void *dalloc(size_t bytes);
     void dfree(void *p);
@@ -74,8 +80,8 @@ struct fim_db {
 };
 
 struct fim_result {
-    std::vector<uint64_t> off{0};
-    std::vector<uint32_t> items, supp;
+    fim::U64Vec off{0};
+    fim::U32Vec items, supp;
     fim_stats stats{};
     bool truncated = false;  // internal sample runs only: output budget exceeded
 };

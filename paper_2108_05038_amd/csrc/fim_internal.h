@@ -44,15 +44,28 @@ struct Task {
 };
 
 // Global counters of a persistent launch (device memory, zeroed before it).
+// Counters that many waves touch concurrently sit on cache lines of their
+// own, so that polling one does not slow the others.
+struct alignas(128) CtrLine {
+    unsigned long long v;
+    unsigned long long pad_[15];
+};
+
 struct DfsCounters {
-    unsigned long long task_head;   // next task to hand out
-    unsigned long long out_used;    // output words reserved (may pass capacity)
+    CtrLine task_head;      // next task to hand out
+    CtrLine out_used;       // output words reserved (may pass capacity)
+    CtrLine don_head;       // next donation slot to take
+    CtrLine don_tail;       // donation slots reserved
+    CtrLine idle;           // waves waiting for donated work
+    CtrLine active;         // waves working on a task or donation
+    CtrLine don_heap_used;  // words of the donation heap used
     unsigned long long candidates;  // pair supports computed
     unsigned long long pair_words;  // words AND-popcounted
     unsigned long long child_rows;  // child bitmaps written
     unsigned long long stack_need;  // largest per-worker stack use seen (words)
     unsigned long long busy_sum;    // wall-clock ticks workers spent on tasks, summed
     unsigned long long busy_max;    // ... and of the busiest worker
+    unsigned long long donations;   // donations published
     unsigned int flags;             // kFlag* bits
     unsigned int pad_;
 };
@@ -68,11 +81,12 @@ struct InstCounters {
 constexpr unsigned kFlagStackOverflow = 1u;
 constexpr unsigned kFlagDepthOverflow = 2u;
 constexpr unsigned kFlagOutOverflow = 4u;
+constexpr unsigned kFlagSpin = 8u;  // a bounded wait of the work sharing ran out
 
 // Output arena: chunks with a header of kChunkHeader words (size, task,
-// seq, used) followed by records of kRecHeader + len words (len, support,
+// seq, used, inst) followed by records of kRecHeader + len words (len, support,
 // len ranks in the instance's item order).
-constexpr uint32_t kChunkHeader = 4;
+constexpr uint32_t kChunkHeader = 5;
 constexpr uint32_t kRecHeader = 2;
 
 // ---------------------------------------------------------------- launches
@@ -96,10 +110,20 @@ hipError_t launch_root_pairs(const uint32_t *rows, uint32_t n, uint32_t Wp, uint
                              uint32_t *pairs, uint64_t cap, unsigned long long *n_pairs,
                              uint32_t tile_words, hipStream_t stream);
 
+// Variant of the persistent kernel for rows of at most max_chunks 128-bit
+// chunks (0 = rows are streamed, 2/4/8 = chunks per lane held in registers).
+uint32_t dfs_variant(uint32_t max_chunks);
+
+// Waves of that persistent kernel variant that fit on the device at once.
+uint32_t dfs_resident_workers(int n_cu, uint32_t variant);
+
 // Persistent depth-first search over the tasks.
 hipError_t launch_dfs(const InstDesc *insts, const Task *tasks, uint64_t n_tasks,
                       uint32_t *stack, uint64_t stack_words, uint32_t n_workers,
                       uint32_t tasks_per_claim, uint32_t *out, uint64_t out_cap,
-                      DfsCounters *ctr, InstCounters *ictr, hipStream_t stream);
+                      DfsCounters *ctr, InstCounters *ictr, unsigned long long *don_slots,
+                      uint64_t n_slots, uint32_t *don_heap, uint64_t heap_words,
+                      uint64_t wait_ticks, unsigned long long *trace, uint32_t variant,
+                      hipStream_t stream);
 
 }  // namespace fim

@@ -63,6 +63,9 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// a value every lane holds alike, moved to a scalar register
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
 __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
     uint32_t lo = __shfl((uint32_t)v, src, kWave);
     uint32_t hi = __shfl((uint32_t)(v >> 32), src, kWave);
@@ -266,11 +269,115 @@ struct WaveShared {
 };
 
 struct WaveStats {
-    unsigned long long candidates, pair_words, child_rows;
+    unsigned long long candidates, pair_words, child_rows, given, max_k, max_depth;
 };
 
+// per-wave trace record (written when a trace buffer is given)
+struct WaveTrace {
+    unsigned long long busy, pieces, given, candidates, max_k, max_depth, pad0, pad1;
+};
+
+// Where the first class of a piece of work comes from: its prefix itemset,
+// its atoms (ranks and supports of prefix + atom) and how many of its rows
+// to expand.  A task of the planner is the first-level class of one item;
+// donated work is any class a busy worker handed over.
+struct FrameSrc {
+    const uint32_t *prefix;  // plen ranks
+    const uint32_t *ranks;   // k atom ranks
+    const uint32_t *supps;   // k supports
+    uint32_t plen, k, r_end;
+};
+
+// Work sharing between waves.  An idle wave counts itself in `idle`; a
+// busy wave that sees idle > 0 hands over the upper part of the unexpanded
+// rows of its shallowest class: it writes a record (instance, prefix,
+// remaining atoms) to the donation heap, then publishes the heap offset in
+// the next queue slot.  Waves finish when no wave is active and the queue
+// is drained; every wait is bounded.
+struct Donation {
+    unsigned long long *slots;  // per slot: heap offset + 1 once published, 0 before
+    uint32_t *heap;
+    uint64_t n_slots, heap_words;
+    uint64_t wait_ticks;        // longest wait (wall-clock ticks) before giving up
+    uint32_t enabled;
+    unsigned long long *trace;  // WaveTrace per wave, or null
+};
+
+// Output of one piece of work goes to chunks of the output arena claimed
+// with one atomic each: header [size, task, seq, used, inst] then records
+// [len, support, len ranks].  Chunks are numbered, so the host can put the
+// records of a piece back in its own depth-first order.
+struct OutChunk {
+    uint64_t base;   // word offset of the chunk, kNoChunk if none
+    uint32_t size;   // words allocated
+    uint32_t pos;    // words used, header included
+    uint32_t seq;    // chunk number within the piece of work
+    uint32_t valid;  // 0 once the arena is full (records are then dropped)
+};
+
+constexpr uint64_t kNoChunk = ~0ull;
+
+__device__ __forceinline__ void close_chunk(OutChunk &c, uint32_t *out) {
+    if (c.base != kNoChunk && c.valid && lane_id() == 0) out[c.base + 3] = c.pos;
+}
+
+// make room for `need` words; returns false when the arena is full
+__device__ bool chunk_reserve(OutChunk &c, uint32_t need, uint32_t task, uint32_t inst,
+                              uint32_t *out, uint64_t out_cap, DfsCounters *ctr) {
+    if (c.base != kNoChunk && c.pos + need <= c.size) return c.valid != 0;
+    close_chunk(c, out);
+    const uint32_t grow = c.seq < 6 ? (256u << c.seq) : 16384u;
+    const uint32_t size = max(grow, need + kChunkHeader);
+    unsigned long long base = 0;
+    if (lane_id() == 0) base = atomicAdd(&ctr->out_used.v, (unsigned long long)size);
+    base = shfl_u64(base, 0);
+    c.seq += c.base == kNoChunk ? 0u : 1u;
+    c.base = base;
+    c.size = size;
+    c.pos = kChunkHeader;
+    c.valid = base + size <= out_cap ? 1u : 0u;
+    if (c.valid) {
+        if (lane_id() == 0) {
+            out[base] = size;
+            out[base + 1] = task;
+            out[base + 2] = c.seq;
+            out[base + 3] = 0;
+            out[base + 4] = inst;
+        }
+    } else if (lane_id() == 0) {
+        atomicOr(&ctr->flags, kFlagOutOverflow);
+    }
+    return c.valid != 0;
+}
+
+__device__ __forceinline__ void flag_stack(DfsCounters *ctr, uint64_t need) {
+    if (lane_id() == 0) {
+        atomicOr(&ctr->flags, kFlagStackOverflow);
+        atomicMax(&ctr->stack_need, (unsigned long long)need);
+    }
+}
+
+// Loads and stores that are coherent across the chip's XCDs (each XCD has
+// an L2 of its own).  They avoid agent-scope fences, which would write back
+// or invalidate a whole L2 and evict the bitmaps other waves are using.
+__device__ __forceinline__ uint64_t load_coherent(unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t load_coherent32(const uint32_t *p) {
+    return __hip_atomic_load(const_cast<uint32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_coherent32(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// wait for this wave's own memory operations to complete (no cache maintenance)
+__device__ __forceinline__ void wave_mem_wait() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
+
+// Rank of every key of `tmp` among all nf keys; writes the sorted atoms.
 // Sorts nf atoms (arrays of stride `si` at tmp) ascending by (support, item
-// id) into dst (arrays of stride nf): every key's rank among all keys.
+// id) into dst (arrays of stride nf).
 __device__ void sort_atoms(const InstDesc &I, const uint32_t *tmp, uint32_t si, uint32_t *dst,
                            uint32_t nf) {
     const uint32_t lane = lane_id();
@@ -300,66 +407,104 @@ __device__ void sort_atoms(const InstDesc &I, const uint32_t *tmp, uint32_t si, 
     }
 }
 
-// Output of one task goes to chunks of the output arena claimed with one
-// atomic each: header [size, task, seq, used] then records [len, support,
-// len ranks].  Chunks of a task are numbered, so the host can put the
-// records back in the task's own depth-first order.
-struct OutChunk {
-    uint64_t base;   // word offset of the chunk, kNoChunk if none
-    uint32_t size;   // words allocated
-    uint32_t pos;    // words used, header included
-    uint32_t seq;    // chunk number within the task
-    uint32_t valid;  // 0 once the arena is full (records are then dropped)
-};
-
-constexpr uint64_t kNoChunk = ~0ull;
-
-__device__ __forceinline__ void close_chunk(OutChunk &c, uint32_t *out) {
-    if (c.base != kNoChunk && c.valid && lane_id() == 0) out[c.base + 3] = c.pos;
-}
-
-// make room for `need` words; returns false when the arena is full
-__device__ bool chunk_reserve(OutChunk &c, uint32_t need, uint32_t task, uint32_t *out,
-                              uint64_t out_cap, DfsCounters *ctr) {
-    if (c.base != kNoChunk && c.pos + need <= c.size) return c.valid != 0;
-    close_chunk(c, out);
-    const uint32_t grow = c.seq < 6 ? (256u << c.seq) : 16384u;
-    const uint32_t size = max(grow, need + kChunkHeader);
-    unsigned long long base = 0;
-    if (lane_id() == 0) base = atomicAdd(&ctr->out_used, (unsigned long long)size);
-    base = shfl_u64(base, 0);
-    c.seq += c.base == kNoChunk ? 0u : 1u;
-    c.base = base;
-    c.size = size;
-    c.pos = kChunkHeader;
-    c.valid = base + size <= out_cap ? 1u : 0u;
-    if (c.valid) {
-        if (lane_id() == 0) {
-            out[base] = size;
-            out[base + 1] = task;
-            out[base + 2] = c.seq;
-            out[base + 3] = 0;
+// Hand the upper part of the unexpanded rows of the shallowest class that
+// is worth it to the donation queue.  Rows are split so that both parts
+// have about the same number of candidate pairs; a part is worth handing
+// over if it holds several candidate pairs per row the receiver has to
+// rebuild from the level-1 bitmaps.
+__device__ bool try_donate(const InstDesc &I, uint32_t inst, uint32_t plen, int depth,
+                           uint32_t *region, WaveShared &ws, Donation &dn, DfsCounters *ctr) {
+    const uint32_t lane = lane_id();
+    int d0 = -1;
+    uint32_t mid = 0;
+    for (int d = 0; d <= depth && d0 < 0; d++) {
+        const Frame F = ws.frames[d];
+        if (F.r_end < F.r + 2) continue;
+        // pairs of rows [F.r, F.r_end): row r has F.k - 1 - r partners
+        uint64_t total = 0;
+        for (uint32_t r = F.r; r < F.r_end; r++) total += F.k - 1 - r;
+        uint64_t acc = 0;
+        uint32_t m = F.r + 1;
+        for (uint32_t r = F.r; r < F.r_end; r++) {
+            acc += F.k - 1 - r;
+            if (2 * acc >= total) {
+                m = max(r + 1, F.r + 1);
+                break;
+            }
         }
-    } else if (lane_id() == 0) {
-        atomicOr(&ctr->flags, kFlagOutOverflow);
+        if (m >= F.r_end) m = F.r_end - 1;
+        uint64_t given = 0;
+        for (uint32_t r = m; r < F.r_end; r++) given += F.k - 1 - r;
+        const uint32_t pl = plen + (uint32_t)d;
+        // the rows' subtrees usually hold far more pairs than the rows
+        // themselves, so a modest first level already pays for the rebuild
+        if (given < 4 || 2 * given < (uint64_t)(F.k - m + pl) || pl + 2 > kMaxDepth) continue;
+        d0 = d;
+        mid = m;
     }
-    return c.valid != 0;
+    if (d0 < 0) return false;
+    const Frame F = ws.frames[d0];
+    const uint32_t pl = plen + (uint32_t)d0;  // prefix of class d0
+    const uint32_t kk = F.k - mid;
+    const uint32_t words = 4 + pl + 2 * kk;
+    unsigned long long hb = 0, sl = 0;
+    if (lane == 0) {
+        hb = atomicAdd(&ctr->don_heap_used.v, (unsigned long long)words);
+        sl = hb + words <= dn.heap_words ? atomicAdd(&ctr->don_tail.v, 1ull) : ~0ull;
+    }
+    hb = shfl_u64(hb, 0);
+    sl = shfl_u64(sl, 0);
+    if (sl >= dn.n_slots) return false;  // heap or queue full: keep the work
+    uint32_t *rec = dn.heap + hb;
+    const uint32_t *ranks = region + F.atoms;
+    const uint32_t *supps = ranks + F.stride;
+    if (lane == 0) {
+        store_coherent32(rec + 0, inst);
+        store_coherent32(rec + 1, pl);
+        store_coherent32(rec + 2, kk);
+        store_coherent32(rec + 3, F.r_end - mid);
+    }
+    for (uint32_t q = lane; q < pl; q += kWave) store_coherent32(rec + 4 + q, ws.prefix[q]);
+    for (uint32_t e = lane; e < kk; e += kWave) {
+        store_coherent32(rec + 4 + pl + e, ranks[mid + e]);
+        store_coherent32(rec + 4 + pl + kk + e, supps[mid + e]);
+    }
+    wave_mem_wait();  // the record is complete before it is published
+    if (lane == 0) {
+        __hip_atomic_store(&dn.slots[sl], (unsigned long long)hb + 1ull, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        atomicAdd(&ctr->donations, 1ull);
+    }
+    ws.frames[d0].r_end = mid;
+    __builtin_amdgcn_wave_barrier();
+    return true;
 }
 
-__device__ __forceinline__ void flag_stack(DfsCounters *ctr, uint64_t need) {
+// more waves wait than donations are queued for them
+__device__ __forceinline__ bool donation_wanted(DfsCounters *ctr) {
+    uint32_t want = 0;
     if (lane_id() == 0) {
-        atomicOr(&ctr->flags, kFlagStackOverflow);
-        atomicMax(&ctr->stack_need, (unsigned long long)need);
+        const uint64_t idle = load_coherent(&ctr->idle.v);
+        if (idle) {
+            const uint64_t queued = load_coherent(&ctr->don_tail.v) - load_coherent(&ctr->don_head.v);
+            want = idle > queued ? 1u : 0u;
+        }
     }
+    return __shfl(want, 0, kWave) != 0;
 }
 
-__device__ void process_task(const InstDesc &I, uint32_t task, const Task &T, uint32_t *region,
-                             uint64_t S, WaveShared &ws, uint32_t *out, uint64_t out_cap,
-                             DfsCounters *ctr, WaveStats &st, OutChunk &oc) {
+// CPL > 0: a row spans at most 64 * CPL chunks and the expanded row is held
+// in registers (CPL chunks per lane) for all its pairs and child rows, with
+// two partner rows loaded per round.  CPL = 0: rows of any width, streamed.
+template <int CPL>
+__device__ void process_frame(const InstDesc &I, uint32_t inst, uint32_t task, const FrameSrc &src,
+                              uint32_t *region, uint64_t S, WaveShared &ws, uint32_t *out,
+                              uint64_t out_cap, DfsCounters *ctr, WaveStats &st, OutChunk &oc,
+                              Donation &dn) {
     const uint32_t lane = lane_id();
     const uint32_t Wp = I.Wp, C = Wp / 4;  // 128-bit chunks per row
-    const uint32_t a0 = I.l2_off[T.node], k1 = I.l2_off[T.node + 1] - a0;
-    if (T.r0 >= T.r1 || T.r1 >= k1) return;  // a task covers rows with a later atom
+    const uint32_t k = src.k, plen = src.plen;
+    if (src.r_end == 0 || src.r_end >= k || plen == 0 || plen + 2 > kMaxDepth) return;
 
     // lanes per pair: enough to cover a row's chunks, at most a wave
     uint32_t g = 1;
@@ -367,39 +512,63 @@ __device__ void process_task(const InstDesc &I, uint32_t task, const Task &T, ui
     const uint32_t ppp = kWave / g;  // pairs per pass
     const uint32_t grp = lane / g, sub = lane % g;
 
-    // frame 0: atoms r0..k1-1 of the first-level class of T.node
-    const uint32_t k = k1 - T.r0;
+    // first class: rows T(prefix + atom) = T(prefix) AND T(atom), with
+    // T(prefix) the AND of the prefix items' rows (Prepare-Tidlists)
+    const uint64_t prow = plen > 1 ? 1 : 0;  // scratch row for T(prefix)
     uint64_t meta = S - 3ull * k;
-    if (3ull * k > S || (uint64_t)k * Wp > meta) {
-        flag_stack(ctr, (uint64_t)k * Wp + 3ull * k);
+    if (3ull * k > S || ((uint64_t)k + prow) * Wp > meta) {
+        flag_stack(ctr, ((uint64_t)k + prow) * Wp + 3ull * k);
         return;
     }
     for (uint32_t e = lane; e < k; e += kWave) {
-        region[meta + e] = I.l2_atom[a0 + T.r0 + e];
-        region[meta + k + e] = I.l2_supp[a0 + T.r0 + e];
+        region[meta + e] = src.ranks[e];
+        region[meta + k + e] = src.supps[e];
         region[meta + 2 * k + e] = e;
     }
-    {
-        const uint4 *base = reinterpret_cast<const uint4 *>(I.rows + (uint64_t)T.node * Wp);
-        for (uint32_t e = 0; e < k; e++) {
-            const uint32_t atom = I.l2_atom[a0 + T.r0 + e];
-            const uint4 *src = reinterpret_cast<const uint4 *>(I.rows + (uint64_t)atom * Wp);
-            uint4 *dst = reinterpret_cast<uint4 *>(region + (uint64_t)e * Wp);
-            and_rows(dst, base, src, C, lane);
+    for (uint32_t q = lane; q < plen; q += kWave) ws.prefix[q] = src.prefix[q];
+    const uint4 *base = reinterpret_cast<const uint4 *>(I.rows + (uint64_t)src.prefix[0] * Wp);
+    if (plen > 1) {
+        uint4 *pr = reinterpret_cast<uint4 *>(region + (uint64_t)k * Wp);
+        and_rows(pr, base,
+                 reinterpret_cast<const uint4 *>(I.rows + (uint64_t)src.prefix[1] * Wp), C, lane);
+        __threadfence_block();
+        for (uint32_t q = 2; q < plen; q++) {
+            and_rows(pr, pr, reinterpret_cast<const uint4 *>(I.rows + (uint64_t)src.prefix[q] * Wp),
+                     C, lane);
+            __threadfence_block();
         }
+        base = pr;
+    }
+    for (uint32_t e = 0; e < k; e++) {
+        const uint4 *arow = reinterpret_cast<const uint4 *>(I.rows + (uint64_t)src.ranks[e] * Wp);
+        and_rows(reinterpret_cast<uint4 *>(region + (uint64_t)e * Wp), base, arow, C, lane);
     }
     __threadfence_block();
 
     int depth = 0;
-    ws.frames[0] = Frame{0u, k, 0u, T.r1 - T.r0, (uint32_t)meta, k, (uint32_t)S, 0u};
-    ws.prefix[0] = T.node;
+    ws.frames[0] = Frame{0u, k, 0u, src.r_end, (uint32_t)meta, k, (uint32_t)S, 0u};
     __builtin_amdgcn_wave_barrier();
-    uint64_t rows_top = (uint64_t)k * Wp;
-    uint64_t peak = rows_top + (S - meta);
+    uint64_t rows_top = (uint64_t)k * Wp;  // the T(prefix) row is no longer needed
+    uint64_t peak = rows_top + prow * Wp + (S - meta);
+    uint32_t polls = 0, cool = 0;
 
     while (depth >= 0) {
-        const Frame F = ws.frames[depth];
+        if (dn.enabled && cool == 0 && ((++polls & 3u) == 0) && donation_wanted(ctr)) {
+            const bool gave = try_donate(I, inst, plen, depth, region, ws, dn, ctr);
+            cool = gave ? 8u : 4u;
+            st.given += gave ? 1u : 0u;
+        }
+        else if (cool)
+            cool--;
+        Frame F = ws.frames[depth];
         __builtin_amdgcn_wave_barrier();
+        F.rows_base = uni(F.rows_base);
+        F.k = uni(F.k);
+        F.r = uni(F.r);
+        F.r_end = uni(F.r_end);
+        F.atoms = uni(F.atoms);
+        F.stride = uni(F.stride);
+        F.meta_restore = uni(F.meta_restore);
         if (F.r >= F.r_end) {
             rows_top = F.rows_base;
             meta = F.meta_restore;
@@ -411,7 +580,7 @@ __device__ void process_task(const InstDesc &I, uint32_t task, const Task &T, ui
         const uint32_t nj = F.k - r - 1;
         if (nj == 0) continue;
         const uint32_t *ranks = region + F.atoms;
-        ws.prefix[depth + 1] = ranks[r];
+        ws.prefix[plen + depth] = ranks[r];
         __builtin_amdgcn_wave_barrier();
 
         // frequent children of row r, unsorted: ranks, supports, source rows
@@ -423,38 +592,89 @@ __device__ void process_task(const InstDesc &I, uint32_t task, const Task &T, ui
         const uint4 *row_r =
             reinterpret_cast<const uint4 *>(region + F.rows_base + (uint64_t)r * Wp);
         uint32_t nf = 0;
-        for (uint32_t jb = 0; jb < nj; jb += ppp) {
-            const uint32_t jj = jb + grp;
-            uint32_t acc = 0;
-            if (jj < nj) {
-                const uint4 *row_j = reinterpret_cast<const uint4 *>(
+        uint4 rr[CPL > 0 ? CPL : 1];
+        if constexpr (CPL > 0) {
+            // row r in registers; partners two at a time, all their loads in flight
+#pragma unroll
+            for (int m = 0; m < CPL; m++) {
+                const uint32_t c = lane + m * kWave;
+                rr[m] = c < C ? row_r[c] : make_uint4(0, 0, 0, 0);
+            }
+            for (uint32_t jj = 0; jj < nj; jj += 2) {
+                const bool two = jj + 1 < nj;
+                const uint4 *r0 = reinterpret_cast<const uint4 *>(
                     region + F.rows_base + (uint64_t)(r + 1 + jj) * Wp);
-                acc = popc_rows(row_r, row_j, C, sub, g);
+                const uint4 *r1 = two ? r0 + Wp / 4 : r0;
+                uint4 x0[CPL], x1[CPL];
+#pragma unroll
+                for (int m = 0; m < CPL; m++) {
+                    const uint32_t c = lane + m * kWave;
+                    x0[m] = c < C ? r0[c] : make_uint4(0, 0, 0, 0);
+                    x1[m] = c < C ? r1[c] : make_uint4(0, 0, 0, 0);
+                }
+                uint32_t a0 = 0, a1 = 0;
+#pragma unroll
+                for (int m = 0; m < CPL; m++) {
+                    a0 += popc4(rr[m], x0[m]);
+                    a1 += popc4(rr[m], x1[m]);
+                }
+#pragma unroll
+                for (int off = kWave / 2; off >= 1; off >>= 1) {
+                    a0 += __shfl_xor(a0, off, kWave);
+                    a1 += __shfl_xor(a1, off, kWave);
+                }
+                const bool f0 = a0 >= I.minsup, f1 = two && a1 >= I.minsup;
+                if (lane == 0) {
+                    if (f0) {
+                        tmp[nf] = ranks[r + 1 + jj];
+                        tmp[nj + nf] = a0;
+                        tmp[2 * nj + nf] = r + 1 + jj;
+                    }
+                    if (f1) {
+                        const uint32_t p = nf + (f0 ? 1u : 0u);
+                        tmp[p] = ranks[r + 2 + jj];
+                        tmp[nj + p] = a1;
+                        tmp[2 * nj + p] = r + 2 + jj;
+                    }
+                }
+                nf += (f0 ? 1u : 0u) + (f1 ? 1u : 0u);
             }
-            for (uint32_t off = g >> 1; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, kWave);
-            const bool freq = sub == 0 && jj < nj && acc >= I.minsup;
-            const uint64_t mask = __ballot(freq);
-            if (freq) {
-                const uint32_t p = nf + lanes_below(mask);
-                tmp[p] = ranks[r + 1 + jj];
-                tmp[nj + p] = acc;
-                tmp[2 * nj + p] = r + 1 + jj;
+        } else {
+            for (uint32_t jb = 0; jb < nj; jb += ppp) {
+                const uint32_t jj = jb + grp;
+                uint32_t acc = 0;
+                if (jj < nj) {
+                    const uint4 *row_j = reinterpret_cast<const uint4 *>(
+                        region + F.rows_base + (uint64_t)(r + 1 + jj) * Wp);
+                    acc = popc_rows(row_r, row_j, C, sub, g);
+                }
+                for (uint32_t off = g >> 1; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+                const bool freq = sub == 0 && jj < nj && acc >= I.minsup;
+                const uint64_t mask = __ballot(freq);
+                if (freq) {
+                    const uint32_t p = nf + lanes_below(mask);
+                    tmp[p] = ranks[r + 1 + jj];
+                    tmp[nj + p] = acc;
+                    tmp[2 * nj + p] = r + 1 + jj;
+                }
+                nf += (uint32_t)__popcll(mask);
             }
-            nf += (uint32_t)__popcll(mask);
         }
         st.candidates += nj;
         st.pair_words += (unsigned long long)nj * Wp;
+        if (F.k > st.max_k) st.max_k = F.k;
+        if ((unsigned long long)depth > st.max_depth) st.max_depth = depth;
         if (nf == 0) continue;
         __threadfence_block();
 
-        // report the nf itemsets prefix[0..depth+1] + child atom
-        const uint32_t len = (uint32_t)depth + 3;
+        // report the nf itemsets prefix + a_r + child atom
+        const uint32_t len = plen + (uint32_t)depth + 2;
         if (I.max_len == 0 || len <= I.max_len) {
             const uint32_t rec = kRecHeader + len;
-            if (chunk_reserve(oc, nf * rec, task, out, out_cap, ctr)) {
-                uint32_t *base = out + oc.base + oc.pos;
+            if (chunk_reserve(oc, nf * rec, task, inst, out, out_cap, ctr)) {
+                uint32_t *obase = out + oc.base + oc.pos;
                 for (uint32_t e = lane; e < nf; e += kWave) {
-                    uint32_t *o = base + (uint64_t)e * rec;
+                    uint32_t *o = obase + (uint64_t)e * rec;
                     o[0] = len;
                     o[1] = tmp[nj + e];
                     for (uint32_t q = 0; q + 1 < len; q++) o[2 + q] = ws.prefix[q];
@@ -466,7 +686,7 @@ __device__ void process_task(const InstDesc &I, uint32_t task, const Task &T, ui
 
         // the child class [prefix + a_r | frequent later atoms]
         if (nf >= 2 && (I.max_len == 0 || len + 1 <= I.max_len)) {
-            if (depth + 1 >= kMaxDepth) {
+            if (depth + 1 >= kMaxDepth || plen + depth + 3 > kMaxDepth + 2) {
                 if (lane == 0) atomicOr(&ctr->flags, kFlagDepthOverflow);
                 continue;
             }
@@ -490,12 +710,41 @@ __device__ void process_task(const InstDesc &I, uint32_t task, const Task &T, ui
                 return;
             }
             // child bitmaps: row_r AND row_src, in the child's atom order
-            for (uint32_t c = 0; c < nf; c++) {
-                const uint32_t src = sorted[2 * sstride + c];
-                const uint4 *row_j =
-                    reinterpret_cast<const uint4 *>(region + F.rows_base + (uint64_t)src * Wp);
-                uint4 *dst = reinterpret_cast<uint4 *>(region + rows_top + (uint64_t)c * Wp);
-                and_rows(dst, row_r, row_j, C, lane);
+            if constexpr (CPL > 0) {
+                for (uint32_t c = 0; c < nf; c += 2) {
+                    const bool two = c + 1 < nf;
+                    const uint4 *s0 = reinterpret_cast<const uint4 *>(
+                        region + F.rows_base + (uint64_t)sorted[2 * sstride + c] * Wp);
+                    const uint4 *s1 = two ? reinterpret_cast<const uint4 *>(
+                                                region + F.rows_base +
+                                                (uint64_t)sorted[2 * sstride + c + 1] * Wp)
+                                          : s0;
+                    uint4 *d0 = reinterpret_cast<uint4 *>(region + rows_top + (uint64_t)c * Wp);
+                    uint4 *d1 = d0 + Wp / 4;
+                    uint4 x0[CPL], x1[CPL];
+#pragma unroll
+                    for (int m = 0; m < CPL; m++) {
+                        const uint32_t q = lane + m * kWave;
+                        x0[m] = q < C ? s0[q] : make_uint4(0, 0, 0, 0);
+                        x1[m] = q < C ? s1[q] : make_uint4(0, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int m = 0; m < CPL; m++) {
+                        const uint32_t q = lane + m * kWave;
+                        if (q < C) {
+                            d0[q] = and4(rr[m], x0[m]);
+                            if (two) d1[q] = and4(rr[m], x1[m]);
+                        }
+                    }
+                }
+            } else {
+                for (uint32_t c = 0; c < nf; c++) {
+                    const uint32_t sr = sorted[2 * sstride + c];
+                    const uint4 *row_j =
+                        reinterpret_cast<const uint4 *>(region + F.rows_base + (uint64_t)sr * Wp);
+                    uint4 *dst = reinterpret_cast<uint4 *>(region + rows_top + (uint64_t)c * Wp);
+                    and_rows(dst, row_r, row_j, C, lane);
+                }
             }
             __threadfence_block();
             st.child_rows += nf;
@@ -512,11 +761,37 @@ __device__ void process_task(const InstDesc &I, uint32_t task, const Task &T, ui
     if (lane == 0) atomicMax(&ctr->stack_need, (unsigned long long)peak);
 }
 
+// the process_frame variant for the row width of the instance: rows of
+// more than 64 chunks and at most 64 * CPL chunks keep the expanded row in
+// registers, all others stream
+template <int CPL>
+__device__ void run_frame(const InstDesc &I, uint32_t inst, uint32_t task, const FrameSrc &src,
+                          uint32_t *region, uint64_t S, WaveShared &ws, uint32_t *out,
+                          uint64_t out_cap, DfsCounters *ctr, WaveStats &st, OutChunk &oc,
+                          Donation &dn) {
+    const uint32_t C = I.Wp / 4;
+    if (CPL > 0 && C > (uint32_t)kWave && C <= (uint32_t)(CPL * kWave))
+        process_frame<CPL>(I, inst, task, src, region, S, ws, out, out_cap, ctr, st, oc, dn);
+    else
+        process_frame<0>(I, inst, task, src, region, S, ws, out, out_cap, ctr, st, oc, dn);
+}
+
+__device__ __forceinline__ void flush_stats(InstCounters *ictr, uint32_t inst, const WaveStats &st) {
+    if (lane_id() == 0) {
+        InstCounters &ic = ictr[inst];
+        if (st.candidates) atomicAdd(&ic.candidates, st.candidates);
+        if (st.pair_words) atomicAdd(&ic.pair_words, st.pair_words);
+        if (st.child_rows) atomicAdd(&ic.child_rows, st.child_rows);
+    }
+}
+
+template <int CPL>
 __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Task *tasks,
                                                 uint64_t n_tasks, uint32_t *stack,
                                                 uint64_t stack_words, uint32_t tasks_per_claim,
                                                 uint32_t *out, uint64_t out_cap,
-                                                DfsCounters *ctr, InstCounters *ictr) {
+                                                DfsCounters *ctr, InstCounters *ictr,
+                                                Donation dn) {
     __shared__ WaveShared shared[kWavesPerBlock];
     const uint32_t w = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
@@ -524,32 +799,143 @@ __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Tas
     const uint64_t wave_id = (uint64_t)blockIdx.x * kWavesPerBlock + w;
     uint32_t *region = stack + wave_id * stack_words;
     unsigned long long busy = 0;
+    WaveTrace wt{0, 0, 0, 0, 0, 0, 0, 0};
+    auto note = [&](const WaveStats &st) {
+        wt.pieces++;
+        wt.given += st.given;
+        wt.candidates += st.candidates;
+        wt.max_k = max(wt.max_k, st.max_k);
+        wt.max_depth = max(wt.max_depth, st.max_depth);
+    };
+    // planned tasks, in LPT order
     for (;;) {
         unsigned long long t0 = 0;
-        if (lane == 0) t0 = atomicAdd(&ctr->task_head, (unsigned long long)tasks_per_claim);
+        if (lane == 0) {
+            atomicAdd(&ctr->active.v, 1ull);
+            t0 = atomicAdd(&ctr->task_head.v, (unsigned long long)tasks_per_claim);
+        }
         t0 = shfl_u64(t0, 0);
-        if (t0 >= n_tasks) break;
+        if (t0 >= n_tasks) {
+            wave_mem_wait();
+            if (lane == 0) atomicSub(&ctr->active.v, 1ull);
+            break;
+        }
         const uint64_t t1 = min((uint64_t)t0 + tasks_per_claim, n_tasks);
         for (uint64_t t = t0; t < t1; t++) {
             const Task T = tasks[t];
-            WaveStats st{0, 0, 0};
+            const InstDesc &I = insts[T.inst];
+            const uint32_t a0 = I.l2_off[T.node], k1 = I.l2_off[T.node + 1] - a0;
+            if (T.r0 >= T.r1 || T.r1 >= k1) continue;  // rows with a later atom only
+            WaveStats st{0, 0, 0, 0, 0, 0};
             OutChunk oc{kNoChunk, 0u, 0u, 0u, 0u};
+            const FrameSrc fs{&tasks[t].node, I.l2_atom + a0 + T.r0, I.l2_supp + a0 + T.r0, 1u,
+                              k1 - T.r0, T.r1 - T.r0};
             const unsigned long long c0 = wall_clock64();
-            process_task(insts[T.inst], (uint32_t)t, T, region, stack_words, ws, out, out_cap, ctr,
-                         st, oc);
+            run_frame<CPL>(I, T.inst, (uint32_t)t, fs, region, stack_words, ws, out, out_cap, ctr,
+                           st, oc, dn);
             close_chunk(oc, out);
             busy += wall_clock64() - c0;
-            if (lane == 0) {
-                InstCounters &ic = ictr[T.inst];
-                if (st.candidates) atomicAdd(&ic.candidates, st.candidates);
-                if (st.pair_words) atomicAdd(&ic.pair_words, st.pair_words);
-                if (st.child_rows) atomicAdd(&ic.child_rows, st.child_rows);
-            }
+            flush_stats(ictr, T.inst, st);
+            note(st);
         }
+        wave_mem_wait();  // donations of this task are published before it counts as done
+        if (lane == 0) atomicSub(&ctr->active.v, 1ull);
+    }
+    // donated work until no wave is active and the queue is drained
+    if (dn.enabled) {
+        if (lane == 0) atomicAdd(&ctr->idle.v, 1ull);
+        unsigned long long since = wall_clock64();
+        uint32_t nap = 1;
+        for (;;) {
+            unsigned long long got = ~0ull;
+            uint32_t done = 0;
+            if (lane == 0) {
+                const unsigned long long h = load_coherent(&ctr->don_head.v);
+                const unsigned long long t = min(load_coherent(&ctr->don_tail.v), dn.n_slots);
+                if (h < t) {
+                    if (atomicCAS(&ctr->don_head.v, h, h + 1) == h) got = h;
+                } else if (load_coherent(&ctr->active.v) == 0) {
+                    // nobody can donate any more; re-read the queue after
+                    // seeing that
+                    const unsigned long long h2 = load_coherent(&ctr->don_head.v);
+                    const unsigned long long t2 = min(load_coherent(&ctr->don_tail.v), dn.n_slots);
+                    done = h2 >= t2 ? 1u : 0u;
+                }
+            }
+            got = shfl_u64(got, 0);
+            done = __shfl(done, 0, kWave);
+            if (done) break;
+            if (got == ~0ull) {
+                if (wall_clock64() - since > dn.wait_ticks) {
+                    if (lane == 0) atomicOr(&ctr->flags, kFlagSpin);
+                    break;
+                }
+                // back off: 1, 2, 4 ... 64 naps of about 8000 cycles
+                for (uint32_t q = 0; q < nap; q++) __builtin_amdgcn_s_sleep(127);
+                if (nap < 64) nap <<= 1;
+                continue;
+            }
+            nap = 1;
+            if (lane == 0) {
+                atomicAdd(&ctr->active.v, 1ull);
+                atomicSub(&ctr->idle.v, 1ull);
+            }
+            // wait until the donor has published the slot it reserved
+            unsigned long long off = 0;
+            const unsigned long long w0 = wall_clock64();
+            for (;;) {
+                if (lane == 0) off = load_coherent(&dn.slots[got]);
+                off = shfl_u64(off, 0);
+                if (off != 0 || wall_clock64() - w0 > dn.wait_ticks) break;
+                __builtin_amdgcn_s_sleep(4);
+            }
+            if (off != 0) {
+                // copy the record into this wave's own memory with coherent loads
+                const uint32_t *rec = dn.heap + (off - 1);
+                const uint32_t inst = load_coherent32(rec), pl = load_coherent32(rec + 1);
+                const uint32_t kk = load_coherent32(rec + 2), re = load_coherent32(rec + 3);
+                const uint32_t words = pl + 2 * kk;
+                if ((uint64_t)words <= stack_words / 2) {
+                    uint32_t *copy = region + (stack_words - words);
+                    for (uint32_t q = lane; q < words; q += kWave)
+                        copy[q] = load_coherent32(rec + 4 + q);
+                    wave_mem_wait();
+                    const InstDesc &I = insts[inst];
+                    const FrameSrc fs{copy, copy + pl, copy + pl + kk, pl, kk, re};
+                    WaveStats st{0, 0, 0, 0, 0, 0};
+                    OutChunk oc{kNoChunk, 0u, 0u, 0u, 0u};
+                    const unsigned long long c0 = wall_clock64();
+                    // the frame's own atom arrays go below the copy
+                    run_frame<CPL>(I, inst, (uint32_t)(n_tasks + got), fs, region,
+                                   stack_words - words, ws, out, out_cap, ctr, st, oc, dn);
+                    close_chunk(oc, out);
+                    busy += wall_clock64() - c0;
+                    flush_stats(ictr, inst, st);
+                    note(st);
+                } else if (lane == 0) {
+                    atomicOr(&ctr->flags, kFlagStackOverflow);
+                    atomicMax(&ctr->stack_need, 2ull * words);
+                }
+            } else if (lane == 0) {
+                atomicOr(&ctr->flags, kFlagSpin);
+            }
+            wave_mem_wait();
+            if (lane == 0) {
+                atomicAdd(&ctr->idle.v, 1ull);
+                atomicSub(&ctr->active.v, 1ull);
+            }
+            since = wall_clock64();
+        }
+        if (lane == 0) atomicSub(&ctr->idle.v, 1ull);
     }
     if (lane == 0 && busy) {
         atomicAdd(&ctr->busy_sum, busy);
         atomicMax(&ctr->busy_max, busy);
+    }
+    if (lane == 0 && dn.trace) {
+        wt.busy = busy;
+        WaveTrace *tr = reinterpret_cast<WaveTrace *>(dn.trace) + wave_id;
+        *tr = wt;
     }
 }
 
@@ -602,14 +988,62 @@ hipError_t launch_root_pairs(const uint32_t *rows, uint32_t n, uint32_t Wp, uint
     return hipGetLastError();
 }
 
+uint32_t dfs_variant(uint32_t max_chunks) {
+    if (max_chunks <= (uint32_t)kWave) return 0;
+    if (max_chunks <= 2u * kWave) return 2;
+    if (max_chunks <= 4u * kWave) return 4;
+    if (max_chunks <= 8u * kWave) return 8;
+    return 0;
+}
+
+template <int CPL>
+static uint32_t resident(int n_cu) {
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_dfs<CPL>, kBlock, 0) != hipSuccess ||
+        blocks <= 0) {
+        (void)hipGetLastError();
+        blocks = 1;
+    }
+    return (uint32_t)blocks * kWavesPerBlock * (uint32_t)n_cu;
+}
+
+uint32_t dfs_resident_workers(int n_cu, uint32_t variant) {
+    switch (variant) {
+        case 2: return resident<2>(n_cu);
+        case 4: return resident<4>(n_cu);
+        case 8: return resident<8>(n_cu);
+        default: return resident<0>(n_cu);
+    }
+}
+
 hipError_t launch_dfs(const InstDesc *insts, const Task *tasks, uint64_t n_tasks, uint32_t *stack,
                       uint64_t stack_words, uint32_t n_workers, uint32_t tasks_per_claim,
                       uint32_t *out, uint64_t out_cap, DfsCounters *ctr, InstCounters *ictr,
-                      hipStream_t stream) {
+                      unsigned long long *don_slots, uint64_t n_slots, uint32_t *don_heap,
+                      uint64_t heap_words, uint64_t wait_ticks, unsigned long long *trace,
+                      uint32_t variant, hipStream_t stream) {
     if (n_tasks == 0) return hipSuccess;
     const uint32_t blocks = (n_workers + kWavesPerBlock - 1) / kWavesPerBlock;
-    hipLaunchKernelGGL(k_dfs, dim3(blocks), dim3(kBlock), 0, stream, insts, tasks, n_tasks, stack,
-                       stack_words, tasks_per_claim ? tasks_per_claim : 1u, out, out_cap, ctr, ictr);
+    Donation dn{don_slots, don_heap, n_slots, heap_words, wait_ticks,
+                (don_slots && don_heap && n_slots && heap_words) ? 1u : 0u, trace};
+    const uint32_t tpc = tasks_per_claim ? tasks_per_claim : 1u;
+    switch (variant) {
+        case 2:
+            hipLaunchKernelGGL(k_dfs<2>, dim3(blocks), dim3(kBlock), 0, stream, insts, tasks,
+                               n_tasks, stack, stack_words, tpc, out, out_cap, ctr, ictr, dn);
+            break;
+        case 4:
+            hipLaunchKernelGGL(k_dfs<4>, dim3(blocks), dim3(kBlock), 0, stream, insts, tasks,
+                               n_tasks, stack, stack_words, tpc, out, out_cap, ctr, ictr, dn);
+            break;
+        case 8:
+            hipLaunchKernelGGL(k_dfs<8>, dim3(blocks), dim3(kBlock), 0, stream, insts, tasks,
+                               n_tasks, stack, stack_words, tpc, out, out_cap, ctr, ictr, dn);
+            break;
+        default:
+            hipLaunchKernelGGL(k_dfs<0>, dim3(blocks), dim3(kBlock), 0, stream, insts, tasks,
+                               n_tasks, stack, stack_words, tpc, out, out_cap, ctr, ictr, dn);
+    }
     return hipGetLastError();
 }
 

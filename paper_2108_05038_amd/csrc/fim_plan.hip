@@ -93,7 +93,6 @@ static fim_status estimate_rows(fim_ctx *ctx, const std::vector<PlanInput> &in,
     const uint32_t n_inst = (uint32_t)in.size();
     row_w.assign(n_inst, {});
     const uint32_t want_tx = opts.sample_tx ? opts.sample_tx : default_sample_tx(0.02, 0.05);
-    const uint32_t n_fi = opts.sample_fi ? opts.sample_fi : default_sample_fi(0.001, 0.0005, 0.05);
 
     // Phase 1: draw |D~| transactions uniformly with replacement
     std::vector<fim_db *> sdb(n_inst, nullptr);
@@ -152,11 +151,15 @@ static fim_status estimate_rows(fim_ctx *ctx, const std::vector<PlanInput> &in,
         const PlanInput &P = in[q];
         const fim_result *R = res[k];
         if (R->truncated) continue;  // exploded sample: no estimate
-        const uint64_t L = R->supp.size();
-        if (L == 0) continue;
+        // the sample run returns the reservoir's itemsets and the length of
+        // its whole stream of frequent itemsets
+        const uint64_t L = R->stats.n_itemsets;
+        if (L == 0 || R->supp.empty()) continue;
+        const double avg_len = (double)R->items.size() / (double)R->supp.size();
         // the sample's output, with room to spare, sizes the real output
-        out_words += (R->items.size() + (kRecHeader + 1) * L) * 2;
-        std::vector<uint64_t> keep = reservoir_indices(L, n_fi, opts.seed + 7 * q + 1);
+        out_words += (uint64_t)((avg_len + kRecHeader + 1.0) * (double)L * 2.0);
+        std::vector<uint64_t> keep(R->supp.size());
+        for (uint64_t j = 0; j < keep.size(); j++) keep[j] = j;
         // Phase 2 sizes: every sampled itemset of length >= 3 lies in one
         // second-level class [a, b | ...]: a = its first item in the miner's
         // order, b = the next one in the order of a's atoms

@@ -15,6 +15,7 @@
 
 #include "fim_host.h"
 #include "fim_plan.h"
+#include "fim_canon.h"
 
 using fim::DevBuf;
 
@@ -142,7 +143,23 @@ extern "C" fim_status fim_ctx_create(int device, void *hip_stream, const fim_all
     return FIM_OK;
 }
 
+uint32_t *fim_ctx::stage(size_t words) {
+    if (words <= pinned_words && pinned) return pinned;
+    if (pinned) (void)hipHostFree(pinned);
+    pinned = nullptr;
+    pinned_words = 0;
+    const size_t want = std::max<size_t>(words + words / 4, 1u << 20);
+    if (hipHostMalloc((void **)&pinned, want * 4, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        pinned = nullptr;
+        return nullptr;
+    }
+    pinned_words = want;
+    return pinned;
+}
+
 fim_ctx::~fim_ctx() {
+    if (pinned) (void)hipHostFree(pinned);
     if (own_stream && stream) {
         (void)hipStreamSynchronize(stream);
         (void)hipStreamDestroy(stream);
@@ -373,127 +390,12 @@ static void build_level2(Inst &I, bool by_id) {
     }
 }
 
-// run fn(i) for i in [0, count) on up to n_thr threads
-template <class Fn>
-static void parallel_for(uint64_t count, uint32_t n_thr, Fn fn) {
-    if (n_thr <= 1 || count < 2) {
-        for (uint64_t i = 0; i < count; i++) fn(i);
-        return;
-    }
-    std::atomic<uint64_t> next{0};
-    std::vector<std::thread> th;
-    for (uint32_t t = 0; t < std::min<uint64_t>(n_thr, count); t++)
-        th.emplace_back([&] {
-            for (uint64_t i; (i = next.fetch_add(1)) < count;) fn(i);
-        });
-    for (auto &x : th) x.join();
-}
-
-static uint32_t host_threads(uint64_t work) {
-    if (work < 20000) return 1;
-    return std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-}
-
-// lexicographic order of the itemsets (items ascending inside each).  When
-// every itemset fits in 128 bits as a sequence of (item + 1) codes, most
-// significant first (a prefix then sorts before its extensions because the
-// missing codes are 0), the itemsets are sorted as integer keys; otherwise
-// by comparing item sequences.  Itemsets are bucketed by their first item
-// and the buckets sorted in parallel.
-static void canonicalize(std::vector<uint32_t> &items, std::vector<uint64_t> &off,
-                         std::vector<uint32_t> &supp) {
-    const uint64_t n = supp.size();
-    if (n == 0) return;
-    const uint32_t n_thr = host_threads(n);
-    uint32_t *it = items.data();
-    const uint64_t *o = off.data();
-    const uint64_t blk = 8192, nblk = (n + blk - 1) / blk;
-    parallel_for(nblk, n_thr, [&](uint64_t b) {
-        for (uint64_t i = b * blk; i < std::min(n, (b + 1) * blk); i++)
-            if (o[i + 1] - o[i] > 1) std::sort(it + o[i], it + o[i + 1]);
-    });
-    uint32_t max_item = 0;
-    uint64_t max_len = 0;
-    for (uint64_t i = 0; i < n; i++) {
-        max_len = std::max<uint64_t>(max_len, o[i + 1] - o[i]);
-        max_item = std::max(max_item, it[o[i + 1] - 1]);
-    }
-    uint32_t bits = 1;
-    while (bits < 32 && ((uint64_t)max_item + 1) >> bits) bits++;
-    std::vector<uint64_t> start(max_item + 2, 0);
-    for (uint64_t i = 0; i < n; i++) start[it[o[i]] + 1]++;
-    for (uint32_t b = 0; b <= max_item; b++) start[b + 1] += start[b];
-    std::vector<uint64_t> idx(n);
-    {
-        std::vector<uint64_t> fill(start.begin(), start.end() - 1);
-        for (uint64_t i = 0; i < n; i++) idx[fill[it[o[i]]]++] = i;
-    }
-    std::vector<uint32_t> order;
-    for (uint32_t b = 0; b <= max_item; b++)
-        if (start[b + 1] - start[b] > 1) order.push_back(b);
-    std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
-        return start[a + 1] - start[a] > start[b + 1] - start[b];
-    });
-    if ((uint64_t)bits * max_len <= 128) {
-        typedef unsigned __int128 u128;
-        struct KI {
-            u128 key;
-            uint64_t i;
-        };
-        std::vector<KI> kv(n);
-        parallel_for(nblk, n_thr, [&](uint64_t b) {
-            for (uint64_t q = b * blk; q < std::min(n, (b + 1) * blk); q++) {
-                const uint64_t a = idx[q];
-                u128 key = 0;
-                uint32_t sh = 128;
-                for (uint64_t k = o[a]; k < o[a + 1]; k++) {
-                    sh -= bits;
-                    key |= (u128)(it[k] + 1) << sh;
-                }
-                kv[q] = KI{key, a};
-            }
-        });
-        parallel_for(order.size(), n_thr, [&](uint64_t k) {
-            const uint32_t b = order[k];
-            std::sort(kv.begin() + start[b], kv.begin() + start[b + 1],
-                      [](const KI &x, const KI &y) { return x.key < y.key; });
-        });
-        for (uint64_t q = 0; q < n; q++) idx[q] = kv[q].i;
-    } else {
-        auto less = [&](uint64_t a, uint64_t b) {
-            const uint32_t *x = it + o[a], *y = it + o[b];
-            const uint64_t nx = o[a + 1] - o[a], ny = o[b + 1] - o[b];
-            const uint64_t m = std::min(nx, ny);
-            for (uint64_t k = 1; k < m; k++)  // item 0 is the bucket
-                if (x[k] != y[k]) return x[k] < y[k];
-            return nx < ny;
-        };
-        parallel_for(order.size(), n_thr, [&](uint64_t k) {
-            const uint32_t b = order[k];
-            std::sort(idx.begin() + start[b], idx.begin() + start[b + 1], less);
-        });
-    }
-    std::vector<uint64_t> no(n + 1);
-    no[0] = 0;
-    for (uint64_t q = 0; q < n; q++) no[q + 1] = no[q] + (o[idx[q] + 1] - o[idx[q]]);
-    std::vector<uint32_t> ni(items.size()), ns(n);
-    parallel_for(nblk, n_thr, [&](uint64_t b) {
-        for (uint64_t q = b * blk; q < std::min(n, (b + 1) * blk); q++) {
-            const uint64_t a = idx[q];
-            std::copy(it + o[a], it + o[a + 1], ni.begin() + no[q]);
-            ns[q] = supp[a];
-        }
-    });
-    items.swap(ni);
-    off.swap(no);
-    supp.swap(ns);
-}
-
 fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const fim_options &opts_in,
                      std::vector<fim_result *> &results, bool use_graph) {
     const auto t_start = clk::now();
     const fim_options opts = resolve_options(&opts_in);
-    Tracer tr((opts.flags & kFlagInternalSample) ? "sample" : "mine");
+    const bool sample_run = (opts.flags & kFlagInternalSample) != 0;
+    Tracer tr(sample_run ? "sample" : "mine");
     const bool by_id = (opts.flags & FIM_FLAG_ORDER_BY_ID) != 0;
     const uint32_t n_inst = (uint32_t)reqs.size();
     HIPCHK(hipSetDevice(ctx->device));
@@ -604,7 +506,10 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
     tr.mark("bitmaps + root pairs");
     // ---------------- a4: class-size estimate, Partition, LPT order
     const bool deep = opts.max_len == 0 || opts.max_len >= 3;
-    uint32_t n_workers = opts.workers ? opts.workers : (uint32_t)ctx->n_cu * 16;
+    uint32_t max_chunks = 0;
+    for (const Inst &I : insts) max_chunks = std::max(max_chunks, I.Wp / 4);
+    const uint32_t variant = dfs_variant(max_chunks);
+    uint32_t n_workers = opts.workers ? opts.workers : dfs_resident_workers(ctx->n_cu, variant);
     n_workers = std::max<uint32_t>(4, (n_workers + 3) / 4 * 4);
     std::vector<Task> tasks;
     uint64_t est_out_words = 0;
@@ -638,7 +543,14 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
     tr.mark("estimate + plan");
     // ---------------- a5-a8: one persistent launch over every task
     DevBuf d_desc(ctx), d_tasks(ctx), d_stack(ctx), d_out(ctx), d_ctr(ctx), d_ictr(ctx);
-    std::vector<uint32_t> out_host;
+    DevBuf d_slots(ctx), d_heap(ctx), d_trace(ctx);
+    struct Span {
+        const uint32_t *p = nullptr;
+        size_t n = 0;
+        uint32_t operator[](size_t i) const { return p[i]; }
+        size_t size() const { return n; }
+        bool empty() const { return n == 0; }
+    } out_host;
     std::vector<InstCounters> ictr(n_inst);
     DfsCounters ctr{};
     float dfs_ms = 0.f;
@@ -700,6 +612,22 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             ENSURE(d_out, ctx, (size_t)out_cap * 4);
             ENSURE(d_ctr, ctx, sizeof(DfsCounters));
             ENSURE(d_ictr, ctx, sizeof(InstCounters) * n_inst);
+            // work sharing between waves
+            const uint64_t n_slots = 1ull << 16;
+            const uint64_t heap_words = 1ull << 24;
+            // a wave gives up waiting for donated work after 60 s of wall clock
+            int clk_khz = 0;
+            (void)hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, ctx->device);
+            const uint64_t wait_ticks = (uint64_t)(clk_khz > 0 ? clk_khz : 100000) * 60000ull;
+            if (tr.on) {
+                ENSURE(d_trace, ctx, (size_t)workers * 64);
+                HIPCHK(launch_fill_u32(d_trace.as<uint32_t>(), (uint64_t)workers * 16, 0u, s));
+            }
+            if (n_slots) {
+                ENSURE(d_slots, ctx, n_slots * 8);
+                ENSURE(d_heap, ctx, heap_words * 4);
+                HIPCHK(launch_fill_u32(d_slots.as<uint32_t>(), n_slots * 2, 0u, s));
+            }
             HIPCHK(launch_fill_u32(d_ctr.as<uint32_t>(), sizeof(DfsCounters) / 4, 0u, s));
             HIPCHK(launch_fill_u32(d_ictr.as<uint32_t>(), sizeof(InstCounters) / 4 * n_inst, 0u, s));
             if (sample_mode) HIPCHK(launch_fill_u32(d_out.as<uint32_t>(), out_cap, 0u, s));
@@ -712,7 +640,12 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                                            d_stack.as<uint32_t>(), S, workers,
                                            opts.classes_per_wg ? opts.classes_per_wg : 1,
                                            d_out.as<uint32_t>(), out_cap, d_ctr.as<DfsCounters>(),
-                                           d_ictr.as<InstCounters>(), s);
+                                           d_ictr.as<InstCounters>(),
+                                           n_slots ? d_slots.as<unsigned long long>() : nullptr,
+                                           n_slots, n_slots ? d_heap.as<uint32_t>() : nullptr,
+                                           heap_words, wait_ticks,
+                                           tr.on ? d_trace.as<unsigned long long>() : nullptr,
+                                           variant, s);
                 hipError_t ce = hipStreamEndCapture(s, &g);
                 if (le != hipSuccess || ce != hipSuccess)
                     return set_error(FIM_E_DEVICE, std::string("graph capture: ") +
@@ -727,7 +660,10 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                 HIPCHK(launch_dfs(d_desc.as<InstDesc>(), d_tasks.as<Task>(), tasks.size(),
                                   d_stack.as<uint32_t>(), S, workers,
                                   opts.classes_per_wg ? opts.classes_per_wg : 1, d_out.as<uint32_t>(),
-                                  out_cap, d_ctr.as<DfsCounters>(), d_ictr.as<InstCounters>(), s));
+                                  out_cap, d_ctr.as<DfsCounters>(), d_ictr.as<InstCounters>(),
+                                  n_slots ? d_slots.as<unsigned long long>() : nullptr, n_slots,
+                                  n_slots ? d_heap.as<uint32_t>() : nullptr, heap_words, wait_ticks,
+                                  tr.on ? d_trace.as<unsigned long long>() : nullptr, variant, s));
             }
             HIPCHK(hipEventRecord(ev1, s));
             HIPCHK(hipMemcpyAsync(&ctr, d_ctr.as<void>(), sizeof(ctr), hipMemcpyDeviceToHost, s));
@@ -739,10 +675,24 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                 int clk_khz = 0;
                 (void)hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, ctx->device);
                 const double mean = (double)ctr.busy_sum / workers;
-                fprintf(stderr, "[fim %s] dfs kernel %.3f ms, %zu tasks, %u workers, busiest %.3f ms, mean %.3f ms, imbalance %.1f, flags %u\n",
-                        tr.tag, dfs_ms, tasks.size(), workers, clk_khz ? ctr.busy_max / (double)clk_khz : 0.0,
+                std::vector<unsigned long long> wt((size_t)workers * 8);
+                if (hipMemcpy(wt.data(), d_trace.as<void>(), wt.size() * 8, hipMemcpyDeviceToHost) == hipSuccess) {
+                    std::vector<uint32_t> ord(workers);
+                    std::iota(ord.begin(), ord.end(), 0u);
+                    std::sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) { return wt[8 * a] > wt[8 * b]; });
+                    for (uint32_t x = 0; x < std::min<uint32_t>(5, workers); x++) {
+                        const unsigned long long *v = &wt[8 * ord[x]];
+                        fprintf(stderr, "[fim %s]   wave %u busy %.3f ms pieces %llu given %llu cands %llu max_k %llu max_depth %llu\n",
+                                tr.tag, ord[x], clk_khz ? v[0] / (double)clk_khz : 0.0, v[1], v[2], v[3], v[4], v[5]);
+                    }
+                }
+                fprintf(stderr, "[fim %s] dfs kernel %.3f ms, %zu tasks, %llu donations, %u workers, busiest %.3f ms, mean %.3f ms, imbalance %.1f, flags %u\n",
+                        tr.tag, dfs_ms, tasks.size(), (unsigned long long)ctr.donations, workers,
+                        clk_khz ? ctr.busy_max / (double)clk_khz : 0.0,
                         clk_khz ? mean / clk_khz : 0.0, mean > 0 ? ctr.busy_max / mean : 0.0, ctr.flags);
             }
+            if (ctr.flags & kFlagSpin)
+                return set_error(FIM_E_DEVICE, "work sharing between waves timed out");
             if (ctr.flags & kFlagDepthOverflow)
                 return set_error(FIM_E_OUTPUT_LIMIT, "an itemset is longer than " +
                                                          std::to_string(kMaxDepth + 2) + " items");
@@ -751,11 +701,11 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                 S = std::max<uint64_t>(2 * S, ctr.stack_need + ctr.stack_need / 4);
                 again = true;
             }
-            if ((ctr.flags & kFlagOutOverflow) || ctr.out_used > out_cap) {
+            if ((ctr.flags & kFlagOutOverflow) || ctr.out_used.v > out_cap) {
                 if (sample_mode) {
                     truncated = true;
                 } else {
-                    out_cap = ctr.out_used + 1024;
+                    out_cap = ctr.out_used.v + ctr.out_used.v / 2 + 4096;  // work sharing varies it
                     again = true;
                 }
             }
@@ -763,17 +713,20 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             for (auto &I : insts) I.st.retries++;
             if (++attempts > 12) return set_error(FIM_E_DEVICE, "persistent kernel did not converge");
         }
-        out_host.resize(std::min<uint64_t>(ctr.out_used, out_cap));
-        if (!out_host.empty())
-            HIPCHK(hipMemcpyAsync(out_host.data(), d_out.as<void>(), out_host.size() * 4,
-                                  hipMemcpyDeviceToHost, s));
+        out_host.n = std::min<uint64_t>(ctr.out_used.v, out_cap);
+        if (out_host.n) {
+            uint32_t *st = ctx->stage(out_host.n);
+            if (!st) return set_error(FIM_E_OOM_HOST, "pinned staging buffer");
+            out_host.p = st;
+            HIPCHK(hipMemcpyAsync(st, d_out.as<void>(), out_host.n * 4, hipMemcpyDeviceToHost, s));
+        }
         HIPCHK(hipStreamSynchronize(s));
     }
 
     tr.mark("persistent dfs + copy");
     // ---------------- a9: results in canonical order
-    std::vector<std::vector<uint32_t>> r_items(n_inst), r_supp(n_inst);
-    std::vector<std::vector<uint64_t>> r_off(n_inst);
+    std::vector<U32Vec> r_items(n_inst), r_supp(n_inst);
+    std::vector<U64Vec> r_off(n_inst);
     for (uint32_t q = 0; q < n_inst; q++) {
         Inst &I = insts[q];
         r_off[q].push_back(0);
@@ -803,7 +756,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
     {
         // chunks of the output arena, put back in (task, chunk number) order
         struct Chunk {
-            uint32_t task, seq;
+            uint32_t task, seq, inst;
             uint64_t off, used;
         };
         std::vector<Chunk> chunks;
@@ -812,8 +765,8 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             const uint32_t size = out_host[p];
             if (size < kChunkHeader || p + size > limit) break;
             const uint32_t used = out_host[p + 3];
-            if (used >= kChunkHeader && used <= size && out_host[p + 1] < tasks.size())
-                chunks.push_back({out_host[p + 1], out_host[p + 2], p, used});
+            if (used >= kChunkHeader && used <= size && out_host[p + 4] < n_inst)
+                chunks.push_back({out_host[p + 1], out_host[p + 2], out_host[p + 4], p, used});
             p += size;
         }
         std::sort(chunks.begin(), chunks.end(), [](const Chunk &a, const Chunk &b) {
@@ -842,21 +795,87 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                 ni[q] = r_items[q].size();
             }
             for (uint64_t k = 0; k < nch; k++) {
-                const uint32_t q = tasks[chunks[k].task].inst;
+                const uint32_t q = chunks[k].inst;
                 set_at[k] = ns[q];
                 item_at[k] = ni[q];
                 ns[q] += c_sets[k];
                 ni[q] += c_items[k];
             }
-            for (uint32_t q = 0; q < n_inst; q++) {
+            for (uint32_t q = 0; q < n_inst && !sample_run; q++) {
                 r_items[q].resize(ni[q]);
                 r_supp[q].resize(ns[q]);
                 r_off[q].resize(ns[q] + 1);
             }
         }
+        if (sample_run) {
+            // a sample run returns only the itemsets the reservoir keeps
+            // (Simple-Reservoir-Sampling over the instance's stream: its
+            // 1-itemsets, its 2-itemsets, then the records in chunk order)
+            const uint32_t n_fi = opts.sample_fi ? opts.sample_fi
+                                                 : default_sample_fi(0.001, 0.0005, 0.05);
+            std::vector<std::vector<uint64_t>> chunks_of(n_inst);
+            for (uint64_t k = 0; k < nch; k++) chunks_of[chunks[k].inst].push_back(k);
+            for (uint32_t q = 0; q < n_inst; q++) {
+                const Inst &I = insts[q];
+                const uint64_t head = r_supp[q].size();
+                uint64_t L = head;
+                for (uint64_t k : chunks_of[q]) L += c_sets[k];
+                std::vector<uint64_t> keep = reservoir_indices(L, n_fi, opts.seed + 7 * q + 1);
+                std::sort(keep.begin(), keep.end());
+                U32Vec ki, ks;
+                U64Vec ko{0};
+                size_t j = 0;
+                for (; j < keep.size() && keep[j] < head; j++) {
+                    const uint64_t i = keep[j];
+                    ki.insert(ki.end(), r_items[q].begin() + r_off[q][i],
+                              r_items[q].begin() + r_off[q][i + 1]);
+                    ko.push_back(ki.size());
+                    ks.push_back(r_supp[q][i]);
+                }
+                // kept records of every chunk, found in parallel, joined in order
+                const std::vector<uint64_t> &cq = chunks_of[q];
+                std::vector<uint64_t> cpos(cq.size() + 1, head);
+                for (size_t x = 0; x < cq.size(); x++) cpos[x + 1] = cpos[x] + c_sets[cq[x]];
+                std::vector<U32Vec> pi(cq.size()), ps(cq.size());
+                std::vector<std::vector<uint32_t>> pl(cq.size());
+                parallel_for(cq.size(), n_thr, [&](uint64_t x) {
+                    auto lo = std::lower_bound(keep.begin() + j, keep.end(), cpos[x]);
+                    auto hi = std::lower_bound(lo, keep.end(), cpos[x + 1]);
+                    if (lo == hi) return;
+                    const Chunk &c = chunks[cq[x]];
+                    uint64_t pos = cpos[x];
+                    for (uint64_t p = c.off + kChunkHeader; p + kRecHeader <= c.off + c.used && lo != hi;) {
+                        const uint32_t len = out_host[p];
+                        if (len == 0 || p + kRecHeader + len > c.off + c.used) break;
+                        if (*lo == pos) {
+                            for (uint32_t y = 0; y < len; y++)
+                                pi[x].push_back(I.item_of_rank[out_host[p + 2 + y]]);
+                            pl[x].push_back(len);
+                            ps[x].push_back(out_host[p + 1]);
+                            ++lo;
+                        }
+                        pos++;
+                        p += kRecHeader + len;
+                    }
+                });
+                for (size_t x = 0; x < cq.size(); x++) {
+                    uint64_t a = 0;
+                    for (size_t y = 0; y < pl[x].size(); y++) {
+                        ki.insert(ki.end(), pi[x].begin() + a, pi[x].begin() + a + pl[x][y]);
+                        a += pl[x][y];
+                        ko.push_back(ki.size());
+                        ks.push_back(ps[x][y]);
+                    }
+                }
+                r_items[q].swap(ki);
+                r_off[q].swap(ko);
+                r_supp[q].swap(ks);
+                insts[q].st.n_itemsets = L;
+            }
+        } else {
         parallel_for(nch, n_thr, [&](uint64_t k) {
             const Chunk &c = chunks[k];
-            const uint32_t q = tasks[c.task].inst;
+            const uint32_t q = c.inst;
             const Inst &I = insts[q];
             uint32_t *ri = r_items[q].data();
             uint64_t *ro = r_off[q].data();
@@ -871,6 +890,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                 p += kRecHeader + len;
             }
         });
+        }
     }
     for (uint32_t q = 0; q < n_inst; q++) {
         if (opts.max_itemsets && r_supp[q].size() > opts.max_itemsets && !truncated)
@@ -893,7 +913,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         R->off.swap(r_off[q]);
         R->supp.swap(r_supp[q]);
         R->stats = insts[q].st;
-        R->stats.n_itemsets = R->supp.size();
+        if (!sample_run) R->stats.n_itemsets = R->supp.size();
         R->truncated = truncated;
         results[q] = R;
     }
