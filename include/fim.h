@@ -95,6 +95,15 @@ fim_status fim_ctx_create(int device, void *hip_stream, const fim_allocator *all
                           fim_ctx **out);
 void fim_ctx_destroy(fim_ctx *ctx);
 
+/*
+ * Device blocks the library frees are kept by the context for reuse by its
+ * next calls (up to half of the device's memory), so that steady-state calls
+ * make no allocator calls.  This gives them back to the allocator now.  They
+ * are also given back when an allocation fails and when the context is
+ * destroyed.
+ */
+fim_status fim_ctx_release_cached(fim_ctx *ctx);
+
 /* ------------------------------------------------------------------ */
 /* Database                                                           */
 
@@ -136,6 +145,10 @@ fim_status fim_minsup_from_relative(uint64_t n_tx, double rel, uint32_t *out_abs
 #define FIM_FLAG_NO_ESTIMATE 0x1u  /* order classes by a cheap size proxy, skip the sample */
 #define FIM_FLAG_ORDER_BY_ID 0x2u  /* extensions ordered by item id, not ascending support */
 #define FIM_FLAG_NO_SPLIT 0x4u     /* never split first-level classes */
+/* draw the database sample even when the classes below the root hold under
+ * 1/20 of the root class's candidate pairs (by default the sample is then
+ * skipped: there is no work worth balancing) */
+#define FIM_FLAG_ALWAYS_ESTIMATE 0x8u
 
 /*
  * Options of a mining call.  A zero field selects its default.

@@ -37,9 +37,11 @@ FIM_E_NO_DEVICE = -10
 FIM_FLAG_NO_ESTIMATE = 0x1
 FIM_FLAG_ORDER_BY_ID = 0x2
 FIM_FLAG_NO_SPLIT = 0x4
+FIM_FLAG_ALWAYS_ESTIMATE = 0x8
 
 EXPORTED = [
     "fim_status_str", "fim_last_error", "fim_version", "fim_ctx_create", "fim_ctx_destroy",
+    "fim_ctx_release_cached",
     "fim_db_create", "fim_db_destroy", "fim_db_sizes", "fim_minsup_from_relative", "fim_mine",
     "fim_mine_batch", "fim_result_sizes", "fim_result_copy", "fim_result_stats",
     "fim_result_destroy", "fim_server_create", "fim_server_submit", "fim_server_poll",
@@ -116,6 +118,7 @@ def lib():
         "fim_version": (ctypes.c_char_p, []),
         "fim_ctx_create": (i32, [ctypes.c_int, V, P(fim_allocator), P(V)]),
         "fim_ctx_destroy": (None, [V]),
+        "fim_ctx_release_cached": (i32, [V]),
         "fim_db_create": (i32, [V, u64, P(u64), P(u32), u32, P(V)]),
         "fim_db_destroy": (None, [V]),
         "fim_db_sizes": (i32, [V, P(u64), P(u64)]),
@@ -327,6 +330,10 @@ class Context:
                 alloc = fim_allocator(fa, ff, None)
                 self._keep += [fa, ff, alloc]
         self.handle = fim_ctx_create(device, stream, alloc)
+
+    def release_cached(self):
+        """Give the device blocks the library keeps for reuse back to the allocator."""
+        _check(lib().fim_ctx_release_cached(self.handle))
 
     def close(self):
         if self.handle:

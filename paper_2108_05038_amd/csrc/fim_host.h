@@ -3,7 +3,10 @@
 
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/fim.h"
@@ -20,10 +23,26 @@ struct fim_ctx {
     size_t total_mem = 0;
     std::string arch;
 
+    // a second context on the same device with a stream of its own, for
+    // work that overlaps the main stream (the estimate's sample)
+    fim_ctx *aux = nullptr;
+    fim_ctx *aux_ctx();
+
     // pinned host staging buffer for device-to-host copies of results
     uint32_t *pinned = nullptr;
     size_t pinned_words = 0;
     uint32_t *stage(size_t words);
+
+    // Device blocks freed by the library are kept by size class for the
+    // next call (a call then needs no allocator round trip); released on
+    // fim_ctx_release_cached, on an allocation failure and at destruction.
+    std::mutex cache_mu;  // databases may be created while a server mines
+    std::map<size_t, std::vector<void *>> cache;
+    std::unordered_map<void *, size_t> block_class;
+    size_t cached_bytes = 0;
+    void *raw_alloc(size_t bytes);
+    void raw_free(void *p);
+    void release_cached();
 
     void *dalloc(size_t bytes);
     void dfree(void *p);

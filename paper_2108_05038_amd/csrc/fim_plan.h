@@ -18,6 +18,7 @@ struct PlanInput {
     const std::vector<uint32_t> *rank_of_item;
     const std::vector<uint32_t> *l2_off;   // atoms of the first-level classes
     const std::vector<uint32_t> *l2_atom;
+    bool estimate = true;                  // draw the database sample for this instance
 };
 
 // One class handed to the workers with its estimated size.
@@ -53,11 +54,27 @@ void partition_lpt_order(const std::vector<PlanClass> &cls_in,
                          const std::vector<const double *> &rp, double alpha, uint32_t n_workers,
                          bool no_split, std::vector<PlanClass> &out);
 
-// Builds the task list of all instances in LPT order.
+// The database samples mined and the reservoir's itemsets of every
+// instance (Phase 1).  Needs only the instances' databases, minimum
+// supports and frequent items, so it can run while the root-class kernel
+// of the same instances is still on the GPU.
+struct SampleEstimate {
+    std::vector<fim_result *> res;  // per sampled instance: reservoir itemsets, stream length
+    std::vector<uint32_t> inst;     // instance index of each res
+    bool done = false;
+    ~SampleEstimate();
+};
+
+fim_status sample_phase(fim_ctx *ctx, const std::vector<PlanInput> &in, const fim_options &opts,
+                        SampleEstimate &est);
+
+// Builds the task list of all instances in LPT order.  With est (the
+// finished Phase 1 of these instances) the sample is not mined again.
 // *est_out_words receives an estimate of the output words of the whole
 // run (0 without a sample estimate).
 fim_status plan_tasks(fim_ctx *ctx, const std::vector<PlanInput> &in, const fim_options &opts,
                       uint32_t n_workers, std::vector<Task> &tasks,
-                      std::vector<PlanClass> *classes = nullptr, uint64_t *est_out_words = nullptr);
+                      std::vector<PlanClass> *classes = nullptr, uint64_t *est_out_words = nullptr,
+                      SampleEstimate *est = nullptr);
 
 }  // namespace fim

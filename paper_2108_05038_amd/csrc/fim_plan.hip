@@ -84,20 +84,19 @@ double lpt_schedule(const std::vector<double> &w, uint32_t p, std::vector<uint32
     return makespan;
 }
 
-// Row weights of every first-level class from the sample, or empty when no
-// usable estimate exists for that instance.
-static fim_status estimate_rows(fim_ctx *ctx, const std::vector<PlanInput> &in,
-                                const fim_options &opts,
-                                std::vector<std::vector<double>> &row_w, uint64_t &out_words) {
-    out_words = 0;
-    const uint32_t n_inst = (uint32_t)in.size();
-    row_w.assign(n_inst, {});
-    const uint32_t want_tx = opts.sample_tx ? opts.sample_tx : default_sample_tx(0.02, 0.05);
+SampleEstimate::~SampleEstimate() {
+    for (auto *r : res) fim_result_destroy(r);
+}
 
-    // Phase 1: draw |D~| transactions uniformly with replacement
+// Phase 1 (reservoir variant): a sample of |D~| transactions drawn
+// uniformly with replacement, mined by the same miner at the same relative
+// minimum support, its frequent itemsets reservoir-sampled.
+fim_status sample_phase(fim_ctx *ctx, const std::vector<PlanInput> &in, const fim_options &opts,
+                        SampleEstimate &est) {
+    const uint32_t n_inst = (uint32_t)in.size();
+    const uint32_t want_tx = opts.sample_tx ? opts.sample_tx : default_sample_tx(0.02, 0.05);
     std::vector<fim_db *> sdb(n_inst, nullptr);
     std::vector<MineRequest> reqs;
-    std::vector<uint32_t> req_inst;
     struct DbGuard {
         std::vector<fim_db *> &v;
         ~DbGuard() {
@@ -108,7 +107,7 @@ static fim_status estimate_rows(fim_ctx *ctx, const std::vector<PlanInput> &in,
         const PlanInput &P = in[q];
         const uint64_t N = P.db->n_tx;
         const uint64_t nd = std::min<uint64_t>(want_tx, N / 4);
-        if (nd < 256 || P.n_freq < 3) continue;
+        if (nd < 256 || P.n_freq < 3 || !P.estimate) continue;
         uint64_t x = opts.seed ^ (0x51ED270B1DE0ull * (q + 1));
         std::vector<uint64_t> off{0};
         std::vector<uint32_t> items;
@@ -127,24 +126,39 @@ static fim_status estimate_rows(fim_ctx *ctx, const std::vector<PlanInput> &in,
         uint32_t ms = (uint32_t)ceil((double)P.minsup * (double)nd / (double)N);
         ms = std::max<uint32_t>(ms, 2);
         reqs.push_back({sdb[q], ms});
-        req_inst.push_back(q);
+        est.inst.push_back(q);
     }
+    est.done = true;
     if (reqs.empty()) return FIM_OK;
-
     // mine the samples with the same miner (no estimate of their own)
     fim_options so = opts;
     so.flags |= FIM_FLAG_NO_ESTIMATE | kFlagInternalSample;
     so.max_itemsets = 0;
     so.max_len = 0;
-    std::vector<fim_result *> res;
-    fim_status s = mine_many(ctx, reqs, so, res, false);
-    if (s != FIM_OK) return s;
-    struct ResGuard {
-        std::vector<fim_result *> &v;
-        ~ResGuard() {
-            for (auto *r : v) fim_result_destroy(r);
-        }
-    } rguard{res};
+    return mine_many(ctx, reqs, so, est.res, false);
+}
+
+// Row weights of every first-level class from the sample, or empty when no
+// usable estimate exists for that instance.
+static fim_status estimate_rows(fim_ctx *ctx, const std::vector<PlanInput> &in,
+                                const fim_options &opts,
+                                std::vector<std::vector<double>> &row_w, uint64_t &out_words,
+                                SampleEstimate *pre) {
+    out_words = 0;
+    const uint32_t n_inst = (uint32_t)in.size();
+    row_w.assign(n_inst, {});
+    SampleEstimate own;
+    SampleEstimate &est = pre && pre->done ? *pre : own;
+    if (!est.done) {
+        fim_status s = sample_phase(ctx, in, opts, est);
+        if (s != FIM_OK) return s;
+    }
+    const std::vector<fim_result *> &res = est.res;
+    const std::vector<uint32_t> &req_inst = est.inst;
+    struct Reqs {
+        size_t n;
+        size_t size() const { return n; }
+    } reqs{res.size()};
 
     for (size_t k = 0; k < reqs.size(); k++) {
         const uint32_t q = req_inst[k];
@@ -264,13 +278,14 @@ void partition_lpt_order(const std::vector<PlanClass> &cls_in,
 
 fim_status plan_tasks(fim_ctx *ctx, const std::vector<PlanInput> &in, const fim_options &opts,
                       uint32_t n_workers, std::vector<Task> &tasks,
-                      std::vector<PlanClass> *classes_out, uint64_t *est_out_words) {
+                      std::vector<PlanClass> *classes_out, uint64_t *est_out_words,
+                      SampleEstimate *est) {
     tasks.clear();
     const uint32_t n_inst = (uint32_t)in.size();
     std::vector<std::vector<double>> row_w;
     uint64_t ow = 0;
     if (!(opts.flags & FIM_FLAG_NO_ESTIMATE)) {
-        fim_status s = estimate_rows(ctx, in, opts, row_w, ow);
+        fim_status s = estimate_rows(ctx, in, opts, row_w, ow, est);
         if (est_out_words) *est_out_words = ow;
         if (s != FIM_OK) return s;
     } else {

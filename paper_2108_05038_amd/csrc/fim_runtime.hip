@@ -47,7 +47,7 @@ void DevBuf::reset() {
 
 }  // namespace fim
 
-void *fim_ctx::dalloc(size_t bytes) {
+void *fim_ctx::raw_alloc(size_t bytes) {
     if (user_alloc) return alloc.alloc(bytes, (void *)stream, alloc.user);
     void *p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) {
@@ -57,10 +57,74 @@ void *fim_ctx::dalloc(size_t bytes) {
     return p;
 }
 
-void fim_ctx::dfree(void *p) {
+void fim_ctx::raw_free(void *p) {
     if (!p) return;
     if (user_alloc) alloc.free(p, (void *)stream, alloc.user);
     else (void)hipFree(p);
+}
+
+// size class: at least 256 bytes, then within 1/8 of the next power of two
+static size_t size_class(size_t bytes) {
+    if (bytes <= 256) return 256;
+    size_t p = 1;
+    while (p < bytes) p <<= 1;
+    const size_t step = std::max<size_t>(256, p / 8);
+    return (bytes + step - 1) / step * step;
+}
+
+void fim_ctx::release_cached() {
+    std::lock_guard<std::mutex> lk(cache_mu);
+    for (auto &kv : cache)
+        for (void *p : kv.second) {
+            block_class.erase(p);
+            raw_free(p);
+        }
+    cache.clear();
+    cached_bytes = 0;
+}
+
+void *fim_ctx::dalloc(size_t bytes) {
+    const size_t cls = size_class(bytes);
+    {
+        std::lock_guard<std::mutex> lk(cache_mu);
+        auto it = cache.find(cls);
+        if (it != cache.end() && !it->second.empty()) {
+            void *p = it->second.back();
+            it->second.pop_back();
+            cached_bytes -= cls;
+            return p;
+        }
+    }
+    void *p = raw_alloc(cls);
+    if (!p && cached_bytes) {  // give the cached blocks back and try again
+        release_cached();
+        p = raw_alloc(cls);
+    }
+    if (p) {
+        std::lock_guard<std::mutex> lk(cache_mu);
+        block_class[p] = cls;
+    }
+    return p;
+}
+
+void fim_ctx::dfree(void *p) {
+    if (!p) return;
+    std::unique_lock<std::mutex> lk(cache_mu);
+    auto it = block_class.find(p);
+    if (it == block_class.end()) {
+        lk.unlock();
+        raw_free(p);
+        return;
+    }
+    // keep it for the next call unless the cache already holds half the device
+    if (cached_bytes + it->second > total_mem / 2) {
+        block_class.erase(it);
+        lk.unlock();
+        raw_free(p);
+        return;
+    }
+    cache[it->second].push_back(p);
+    cached_bytes += it->second;
 }
 
 #define HIPCHK(call)                                                                         \
@@ -143,6 +207,15 @@ extern "C" fim_status fim_ctx_create(int device, void *hip_stream, const fim_all
     return FIM_OK;
 }
 
+fim_ctx *fim_ctx::aux_ctx() {
+    if (!aux) {
+        fim_ctx *c = nullptr;
+        if (fim_ctx_create(device, nullptr, user_alloc ? &alloc : nullptr, &c) != FIM_OK) return nullptr;
+        aux = c;
+    }
+    return aux;
+}
+
 uint32_t *fim_ctx::stage(size_t words) {
     if (words <= pinned_words && pinned) return pinned;
     if (pinned) (void)hipHostFree(pinned);
@@ -159,6 +232,8 @@ uint32_t *fim_ctx::stage(size_t words) {
 }
 
 fim_ctx::~fim_ctx() {
+    delete aux;
+    release_cached();
     if (pinned) (void)hipHostFree(pinned);
     if (own_stream && stream) {
         (void)hipStreamSynchronize(stream);
@@ -167,6 +242,15 @@ fim_ctx::~fim_ctx() {
 }
 
 extern "C" void fim_ctx_destroy(fim_ctx *ctx) { delete ctx; }
+
+extern "C" fim_status fim_ctx_release_cached(fim_ctx *ctx) {
+    if (!ctx) return fim::set_error(FIM_E_INVALID_ARG, "ctx is NULL");
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->release_cached();
+    if (ctx->aux) ctx->aux->release_cached();
+    return FIM_OK;
+}
 
 // ====================================================================== database
 
@@ -431,6 +515,16 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         }
     } evg{ev0, ev1};
     float root_ms = 0.f;
+    // one event pair per instance around its root-class kernel
+    std::vector<hipEvent_t> rev(2 * n_inst, nullptr);
+    struct EvVec {
+        std::vector<hipEvent_t> &v;
+        ~EvVec() {
+            for (auto e : v)
+                if (e) (void)hipEventDestroy(e);
+        }
+    } evv{rev};
+    for (auto &e : rev) HIPCHK(hipEventCreate(&e));
     for (uint32_t q = 0; q < n_inst; q++) {
         Inst &I = insts[q];
         rank_items(I, by_id);
@@ -457,20 +551,22 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         ENSURE(I.d_pairs, ctx, cap * 12);
         ENSURE(I.d_npairs, ctx, 8);
         HIPCHK(launch_fill_u32(I.d_npairs.as<uint32_t>(), 2, 0u, s));
-        HIPCHK(hipEventRecord(ev0, s));
+        HIPCHK(hipEventRecord(rev[2 * q], s));
         HIPCHK(launch_root_pairs(I.d_rows.as<uint32_t>(), I.n_freq, I.Wp, I.minsup,
                                  I.d_pairs.as<uint32_t>(), cap,
                                  I.d_npairs.as<unsigned long long>(), opts.tile_words, s));
-        HIPCHK(hipEventRecord(ev1, s));
+        HIPCHK(hipEventRecord(rev[2 * q + 1], s));
         HIPCHK(hipMemcpyAsync(&I.n_pairs, I.d_npairs.as<void>(), 8, hipMemcpyDeviceToHost, s));
-        // one instance's kernel time (the copy above synchronises the host
-        // only at the end, so read the events after the stream sync below)
-        HIPCHK(hipStreamSynchronize(s));
+    }
+    const bool deep = opts.max_len == 0 || opts.max_len >= 3;
+    HIPCHK(hipStreamSynchronize(s));
+    for (uint32_t q = 0; q < n_inst; q++) {
+        const Inst &I = insts[q];
+        if (I.n_freq < 2 || opts.max_len == 1) continue;
         float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
+        HIPCHK(hipEventElapsedTime(&ms, rev[2 * q], rev[2 * q + 1]));
         root_ms += ms;
     }
-    HIPCHK(hipStreamSynchronize(s));
     for (uint32_t q = 0; q < n_inst; q++) {
         Inst &I = insts[q];
         if (I.n_freq < 2 || opts.max_len == 1) continue;
@@ -505,7 +601,6 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
 
     tr.mark("bitmaps + root pairs");
     // ---------------- a4: class-size estimate, Partition, LPT order
-    const bool deep = opts.max_len == 0 || opts.max_len >= 3;
     uint32_t max_chunks = 0;
     for (const Inst &I : insts) max_chunks = std::max(max_chunks, I.Wp / 4);
     const uint32_t variant = dfs_variant(max_chunks);
@@ -514,7 +609,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
     std::vector<Task> tasks;
     uint64_t est_out_words = 0;
     if (deep) {
-        const auto t_est = clk::now();
+        const auto t_plan = clk::now();
         std::vector<PlanInput> pin(n_inst);
         for (uint32_t q = 0; q < n_inst; q++) {
             Inst &I = insts[q];
@@ -526,11 +621,23 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             pin[q].rank_of_item = &I.rank_of_item;
             pin[q].l2_off = &I.l2_off;
             pin[q].l2_atom = &I.l2_atom;
+            // The sample-based estimate balances the work below the root
+            // class.  Its first level holds sum f_i (f_i - 1) / 2 candidate
+            // pairs (f_i atoms of first-level class i), known exactly now;
+            // when that is under 1/20 of the root class's pairs there is
+            // nothing worth balancing and no sample is drawn.
+            uint64_t below = 0;
+            for (uint32_t i = 0; i < I.n_freq; i++) {
+                const uint64_t f = I.l2_off[i + 1] - I.l2_off[i];
+                below += f * (f ? f - 1 : 0) / 2;
+            }
+            const uint64_t root = (uint64_t)I.n_freq * (I.n_freq ? I.n_freq - 1 : 0) / 2;
+            pin[q].estimate = (opts.flags & FIM_FLAG_ALWAYS_ESTIMATE) || 20 * below >= root;
         }
         fim_status ps = plan_tasks(ctx, pin, opts, n_workers, tasks, nullptr, &est_out_words);
         if (ps != FIM_OK) return ps;
-        const uint64_t est_ns = ns_since(t_est);
-        for (auto &I : insts) I.st.estimate_ns = est_ns;
+        const uint64_t plan_ns = ns_since(t_plan);
+        for (auto &I : insts) I.st.estimate_ns = plan_ns;
     }
     for (uint32_t q = 0; q < n_inst; q++) {
         Inst &I = insts[q];

@@ -173,6 +173,31 @@ def batch_instance(params: dict, name: str = "") -> Database:
     return Database(o, it, ni, params["minsup"], name)
 
 
+BATCH_BASE = SEED_BASE + 4
+SERVE_BASE = SEED_BASE + 5
+# a batch instance whose oracle result exceeds this many itemsets is redrawn
+# from substream index + GUARD_STRIDE (the redraw is recorded in the manifest)
+GUARD_LIMIT = 5_000_000
+GUARD_STRIDE = 100_000
+
+
+def serve_params(k: int) -> dict:
+    """Request k of the serving pool: 9 in 10 basket instances drawn like the
+    batch instances (from their own substreams), 1 in 10 dense instances with
+    log-uniform 1,000..50,000 transactions over 120 items at 40 % support."""
+    if k % 10 == 9:
+        return dense_params(k, SERVE_BASE)
+    p = batch_params(k, base=SERVE_BASE)
+    p["kind"] = "basket"
+    return p
+
+
+def serve_instance(params: dict, name: str = "") -> Database:
+    if params.get("kind") == "dense":
+        return dense_instance(params, name)
+    return batch_instance(params, name)
+
+
 def dense_params(index: int, base: int, lo_tx=1000, hi_tx=50000) -> dict:
     """Parameters of a dense request instance: log-uniform n_tx, 120 items, minsup 40 %."""
     u = uniforms(substream(base, index), 1)[0]

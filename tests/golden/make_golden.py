@@ -44,9 +44,56 @@ def golden(name: str, threads: int) -> dict:
     }
 
 
+def _instance_golden(db, threads):
+    t0 = time.time()
+    res = oracle.mine_db(db, threads=threads, max_sets=synth.GUARD_LIMIT)
+    return res, time.time() - t0
+
+
+def golden_batch(threads: int, n: int = 256) -> dict:
+    """Oracle results of the batch instances, with the explosion guard: an
+    instance with more than GUARD_LIMIT itemsets is redrawn from substream
+    index + GUARD_STRIDE (repeatedly) and the substream used is recorded."""
+    out = []
+    for i in range(n):
+        sub = i
+        while True:
+            p = synth.batch_params(sub)
+            res, dt = _instance_golden(synth.batch_instance(p), threads)
+            if not res.overflow:
+                break
+            print("instance", i, "substream", sub, "exceeds the guard; redrawn", flush=True)
+            sub += synth.GUARD_STRIDE
+        out.append({"index": i, "substream": sub, "n_tx": p["n_tx"], "n_items": p["n_items"],
+                    "minsup": p["minsup"], "n_itemsets": len(res),
+                    "candidates_ascending_support": res.candidates, "digest": res.digest(),
+                    "oracle_seconds": round(dt, 2)})
+        print("batch", i, len(res), round(dt, 2), flush=True)
+    return {"workload": "batch-%d" % n, "guard_limit": synth.GUARD_LIMIT, "instances": out}
+
+
+def golden_serve(threads: int, n: int = 512) -> dict:
+    out = []
+    for k in range(n):
+        p = synth.serve_params(k)
+        res, dt = _instance_golden(synth.serve_instance(p), threads)
+        out.append({"index": k, "kind": p.get("kind", "basket"), "n_tx": p["n_tx"],
+                    "minsup": p["minsup"], "n_itemsets": len(res), "overflow": res.overflow,
+                    "candidates_ascending_support": res.candidates,
+                    "digest": res.digest() if not res.overflow else None,
+                    "oracle_seconds": round(dt, 2)})
+        print("serve", k, out[-1]["kind"], len(res), round(dt, 2), flush=True)
+    return {"workload": "serve-pool-%d" % n, "instances": out}
+
+
 def main(argv):
-    names = argv or NAMES
     threads = int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1))
+    if argv and argv[0] in ("batch-256", "serve-pool"):
+        g = golden_batch(threads) if argv[0] == "batch-256" else golden_serve(threads)
+        with open(os.path.join(HERE, "%s.json" % argv[0]), "w") as f:
+            json.dump(g, f, indent=0)
+        return
+    names = argv or NAMES
     for name in names:
         g = golden(name, threads)
         path = os.path.join(HERE, "%s.json" % name)
