@@ -8,19 +8,33 @@ uploaded once before the timed region.  Default workload: ``sparse-200k``
 (200,000 basket transactions over 5,000 items, minimum support 0.1 %).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                    [--no-batch] [--no-serve] [--no-cpu]
 
 Prints one JSON line.  ``value`` is candidate supports per second (pairs of
 extensions whose support was computed, summed over all classes) of the whole
 call.  ``roofline`` describes the dominant kernel, timed with HIP events on
-the library's stream inside the timed region: the root-class pair kernel is
-bound by the integer vector ALU (two 32-bit operations per AND-popcounted
-word pair), the depth-first kernel by HBM bandwidth (algorithmic bytes:
-every class's sibling bitmaps written once and read once).  ``cpu_baseline``
-is the CPU oracle (plain Eclat over sorted tid-lists) timed on this host.
+the library's stream inside the timed region: the root-class pair kernels
+are bound by the integer vector ALU (two 32-bit operations per
+AND-popcounted word pair), the depth-first kernel by HBM bandwidth
+(algorithmic bytes: every class's sibling bitmaps written once and read
+once).  ``cpu_baseline`` is the CPU oracle (plain Eclat over sorted
+tid-lists) timed on this host.
+
+Two more legs go into the same line:
+  ``batched``  256 independent basket instances (log-uniform sizes) mined by
+               one ``fim_mine_batch`` call with autotuned tile width and
+               classes per workgroup, against the plain miner called once per
+               instance; every instance's result is checked against its
+               stored digest.
+  ``served``   a seeded Poisson stream of requests (basket instances like the
+               batch, one in ten dense) offered to the continuous-batching
+               server, against the plain miner serving the same stream one
+               request at a time; p50/p99 latency and throughput per rate.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -33,11 +47,222 @@ METRIC = "candidate supports/s + HBM GB/s; served p50/p99 latency, batched vs pl
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: 32-bit integer VALU operations per second
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
+
+def digest(r) -> str:
+    """SHA-256 of a result's canonical binary CSR (little-endian u64 offsets,
+    u32 items, u32 supports), the format the stored expected values use."""
+    import numpy as np
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(r.offsets, dtype="<u8").tobytes())
+    h.update(np.ascontiguousarray(r.items, dtype="<u4").tobytes())
+    h.update(np.ascontiguousarray(r.supports, dtype="<u4").tobytes())
+    return h.hexdigest()
+
+
+def load_golden(name):
+    p = os.path.join(GOLDEN, name)
+    return json.load(open(p)) if os.path.exists(p) else None
+
+
+# ---------------------------------------------------------------- batched leg
+
+def batch_leg(F, ctx, args):
+    import numpy as np
+    import torch
+
+    import synth
+    g = load_golden("batch-256.json")
+    n = args.batch
+    subs = [g["instances"][i]["substream"] for i in range(n)] if g else list(range(n))
+    log("batched: generating %d instances ..." % n)
+    t0 = time.perf_counter()
+    params = [synth.batch_params(s) for s in subs]
+    handles, minsups = [], []
+    for p in params:
+        d = synth.batch_instance(p)
+        handles.append(F.Database(ctx, d.offsets, d.items, d.n_items))
+        minsups.append(d.minsup)
+        del d
+    log("batched: generated and uploaded in %.1f s" % (time.perf_counter() - t0))
+
+    t0 = time.perf_counter()
+    tuned = F.autotune(ctx, handles, minsups, reps=1)
+    tune_s = time.perf_counter() - t0
+    log("batched: autotuned in %.1f s:" % tune_s, tuned)
+    opts = dict(tile_words=tuned["tile_words"], classes_per_wg=tuned["classes_per_wg"])
+
+    res = F.mine_batch(ctx, handles, minsups, **opts)
+    verified = None
+    if g:
+        bad = [i for i, r in enumerate(res)
+               if digest(r) != g["instances"][i]["digest"]
+               or r.stats["candidates"] != g["instances"][i]["candidates_ascending_support"]]
+        verified = not bad
+        log("batched: %d of %d instances match their digests" % (n - len(bad), n))
+    cands = sum(r.stats["candidates"] for r in res)
+    n_sets = sum(len(r) for r in res)
+    dfs_ns = res[0].stats["dfs_kernel_ns"]
+    del res
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_steps):
+        res = F.mine_batch(ctx, handles, minsups, **opts)
+        del res
+    torch.cuda.synchronize()
+    batch_s = (time.perf_counter() - t0) / args.batch_steps
+
+    # plain: the one-instance-per-launch miner over the same instances
+    for i in range(min(4, n)):
+        F.mine(ctx, handles[i], minsups[i])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for h, m in zip(handles, minsups):
+        F.mine(ctx, h, m)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    for h in handles:
+        h.close()
+    ctx.release_cached()
+    return {
+        "instances": n, "n_itemsets": n_sets, "candidates": cands,
+        "ms_per_batch": batch_s * 1e3, "value": cands / batch_s,
+        "plain_ms": plain_s * 1e3, "plain_value": cands / plain_s,
+        "speedup_vs_plain": plain_s / batch_s,
+        "dfs_kernel_ms": dfs_ns / 1e6,
+        "tile_words": tuned["tile_words"], "classes_per_wg": tuned["classes_per_wg"],
+        "autotune_s": tune_s, "verified_vs_oracle": verified,
+        "unit": "candidate supports/s",
+    }
+
+
+# ---------------------------------------------------------------- served leg
+
+def _trace(rate, seconds, pool_n):
+    """Seeded Poisson arrival times and the pool request each one is."""
+    import numpy as np
+
+    import synth
+    base = synth.substream(synth.SERVE_BASE, 1_000_000 + int(rate))
+    n = int(rate * seconds * 1.5) + 16
+    gaps = synth.exponentials(base, n, 1.0 / rate)
+    t = np.cumsum(gaps)
+    t = t[t < seconds]
+    u = synth.uniforms(synth.substream(base, 1), len(t))
+    return t, np.minimum((u * pool_n).astype(np.int64), pool_n - 1)
+
+
+def _stats(lat, censored, seconds, done):
+    import numpy as np
+    a = np.maximum(np.array(lat), 0.0) if lat else np.zeros(1)
+    return {"p50_ms": float(np.percentile(a, 50) * 1e3), "p99_ms": float(np.percentile(a, 99) * 1e3),
+            "mean_ms": float(a.mean() * 1e3), "completed": done, "censored": censored,
+            "throughput_rps": done / seconds}
+
+
+def serve_served(F, ctx, handles, minsups, arr, idx, seconds, lanes, first):
+    srv = F.Server(ctx, lanes=lanes)
+    deadline = 2 * seconds + 10
+    pending, lat = {}, []
+    k, n = 0, len(arr)
+    t0 = time.perf_counter()
+    while k < n or pending:
+        now = time.perf_counter() - t0
+        if now > deadline:
+            break
+        busy = False
+        while k < n and arr[k] <= now:
+            pending[srv.submit(handles[idx[k]], minsups[idx[k]])] = k
+            k += 1
+            busy = True
+        for t in list(pending):
+            r = srv.poll(t)
+            if r is not None:
+                q = pending.pop(t)
+                lat.append(time.perf_counter() - t0 - arr[q])
+                first.setdefault(int(idx[q]), r)
+                busy = True
+        if not busy:
+            time.sleep(0.0002)
+    end = time.perf_counter() - t0
+    # requests still open at the deadline count with their waiting time so
+    # far (a lower bound), so that overload shows in the percentiles
+    censored = len(pending) + (n - k)
+    lat += [end - arr[q] for q in pending.values()] + [end - a for a in arr[k:]]
+    for t in pending:
+        srv.cancel(t)
+    srv.close()
+    out = _stats(lat, censored, max(seconds, end), n - censored)
+    out["server"] = {"lanes": lanes}
+    return out
+
+
+def serve_plain(F, ctx, handles, minsups, arr, idx, seconds):
+    deadline = 2 * seconds + 10
+    lat = []
+    t0 = time.perf_counter()
+    k = 0
+    for k in range(len(arr)):
+        now = time.perf_counter() - t0
+        if now > deadline:
+            break
+        if arr[k] > now:
+            time.sleep(arr[k] - now)
+        F.mine(ctx, handles[idx[k]], minsups[idx[k]])
+        lat.append(time.perf_counter() - t0 - arr[k])
+    end = time.perf_counter() - t0
+    done = len(lat)
+    lat += [end - a for a in arr[done:]]  # open at the deadline: lower bounds
+    return _stats(lat, len(arr) - done, max(seconds, end), done)
+
+
+def serve_leg(F, ctx, args):
+    import synth
+    g = load_golden("serve-pool.json")
+    pool_n = args.serve_pool
+    log("served: generating a pool of %d requests ..." % pool_n)
+    t0 = time.perf_counter()
+    handles, minsups, kinds = [], [], []
+    for k in range(pool_n):
+        p = synth.serve_params(k, g["instances"][k].get("substream", k) if g else None)
+        d = synth.serve_instance(p)
+        handles.append(F.Database(ctx, d.offsets, d.items, d.n_items))
+        minsups.append(d.minsup)
+        kinds.append(p.get("kind", "basket"))
+        del d
+    log("served: pool ready in %.1f s (%d dense)" % (time.perf_counter() - t0, kinds.count("dense")))
+    # warm both paths on a few requests
+    for k in range(min(8, pool_n)):
+        F.mine(ctx, handles[k], minsups[k])
+    rates = [float(x) for x in args.serve_rates.split(",") if x]
+    out = {"seconds": args.serve_seconds, "pool": pool_n, "rates": {}}
+    first = {}
+    for rate in rates:
+        arr, idx = _trace(rate, args.serve_seconds, pool_n)
+        log("served: %g req/s, %d requests ..." % (rate, len(arr)))
+        s = serve_served(F, ctx, handles, minsups, arr, idx, args.serve_seconds, args.lanes, first)
+        log("served: continuous batching", s)
+        p = serve_plain(F, ctx, handles, minsups, arr, idx, args.serve_seconds)
+        log("served: plain per request", p)
+        out["rates"]["%g" % rate] = {"requests": len(arr), "batched": s, "plain": p}
+    if g:
+        bad = [k for k, r in first.items()
+               if g["instances"][k]["digest"] is not None and g["instances"][k]["digest"] != digest(r)]
+        out["verified_vs_oracle"] = not bad
+        out["verified_requests"] = len(first)
+    for h in handles:
+        h.close()
+    ctx.release_cached()
+    return out
+
+
+# ---------------------------------------------------------------- main
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
@@ -49,7 +274,29 @@ def main(argv=None):
     ap.add_argument("--cpu-threads", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--flags", type=int, default=0, help="fim_options.flags")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch", type=int, default=256, help="instances of the batched leg")
+    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-rates", default="50,200", help="request rates (req/s)")
+    ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--serve-pool", type=int, default=128, help="distinct requests (<= 512)")
+    ap.add_argument("--lanes", type=int, default=0, help="server lanes (0 = default)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes three times (the "
+                         "reference for scaling the HBM byte counters) and exit")
     args = ap.parse_args(argv)
+
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(args.calibrate_copy, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.calibrate_copy, "copies": 3}), flush=True)
+        return 0
 
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -59,21 +306,19 @@ def main(argv=None):
     import numpy as np
     import torch
 
-    import oracle
     import paper_2108_05038_amd as F
     import synth
 
     db = synth.make(args.workload)
     ctx = F.Context(0)
     d = F.Database(ctx, db.offsets, db.items, db.n_items)
-    gold_path = os.path.join(ROOT, "tests", "golden", "%s.json" % args.workload)
-    gold = json.load(open(gold_path)) if os.path.exists(gold_path) else None
+    gold = load_golden("%s.json" % args.workload)
 
     verified = None
     for i in range(args.warmup):
         r = F.mine(ctx, d, db.minsup, flags=args.flags)
         if i == 0 and gold is not None:
-            verified = (oracle.digest(r.offsets, r.items, r.supports) == gold["digest"]
+            verified = (digest(r) == gold["digest"]
                         and r.stats["candidates"] == gold["candidates_ascending_support"])
             log("warmup result matches the oracle's golden digest:", verified)
     torch.cuda.synchronize()
@@ -88,28 +333,34 @@ def main(argv=None):
     st = stats[-1]
     cands = st["candidates"]
     value = cands / dt
+    log("main leg: %.3f ms/step" % (dt * 1e3))
 
     root_ns = float(np.mean([s["root_kernel_ns"] for s in stats]))
     dfs_ns = float(np.mean([s["dfs_kernel_ns"] for s in stats]))
+    root_name = "k_root_sparse" if st["root_sparse"] else "k_root_pairs"
     root_tops = 2.0 * st["root_pair_words"] / root_ns / 1e3 if root_ns else 0.0
     dfs_gbs = st["dfs_bytes_algorithmic"] / dfs_ns if dfs_ns else 0.0
     kernels = {
-        "k_root_pairs": {"ms": root_ns / 1e6, "bound": "alu", "achieved_TOPs": root_tops,
-                         "frac": root_tops / VALU_PEAK_TOPS,
-                         "ops_per_launch": 2 * st["root_pair_words"]},
+        root_name: {"ms": root_ns / 1e6, "bound": "alu", "achieved_TOPs": root_tops,
+                    "frac": root_tops / VALU_PEAK_TOPS, "ops_per_launch": 2 * st["root_pair_words"]},
         "k_dfs": {"ms": dfs_ns / 1e6, "bound": "hbm", "achieved_GBs": dfs_gbs,
                   "frac": dfs_gbs / HBM_PEAK_GBS, "bytes_per_launch": st["dfs_bytes_algorithmic"]},
     }
     if root_ns >= dfs_ns:
-        roofline = {"kernel": "k_root_pairs", "bound": "alu", "achieved": root_tops,
+        roofline = {"kernel": root_name, "bound": "alu", "achieved": root_tops,
                     "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": root_tops / VALU_PEAK_TOPS,
                     "traffic": None}
     else:
         roofline = {"kernel": "k_dfs", "bound": "hbm", "achieved": dfs_gbs, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": dfs_gbs / HBM_PEAK_GBS, "traffic": None}
+    d.close()
+
+    batched = None if args.no_batch else batch_leg(F, ctx, args)
+    served = None if args.no_serve else serve_leg(F, ctx, args)
 
     cpu = None
     if not args.no_cpu:
+        import oracle
         threads = max(1, min(args.cpu_threads, os.cpu_count() or 1))
         log("timing the CPU oracle with %d threads ..." % threads)
         c0 = time.perf_counter()
@@ -119,7 +370,7 @@ def main(argv=None):
                "cores": threads, "kind": "oracle",
                "sample": "the full %s workload, one run (%d candidate pairs, %.1f s)"
                          % (args.workload, o.candidates, c1 - c0),
-               "matches_gpu": bool(o.digest() == oracle.digest(r.offsets, r.items, r.supports))}
+               "matches_gpu": bool(o.digest() == digest(r))}
 
     out = {
         "metric": METRIC,
@@ -142,9 +393,10 @@ def main(argv=None):
         "kernels": kernels,
         "hbm_GBs_dfs": dfs_gbs,
         "verified_vs_oracle": verified,
+        "batched": batched,
+        "served": served,
     }
     print(json.dumps(out), flush=True)
-    d.close()
     ctx.close()
     return 0
 

@@ -149,6 +149,10 @@ fim_status fim_minsup_from_relative(uint64_t n_tx, double rel, uint32_t *out_abs
  * 1/20 of the root class's candidate pairs (by default the sample is then
  * skipped: there is no work worth balancing) */
 #define FIM_FLAG_ALWAYS_ESTIMATE 0x8u
+/* count the root class over whole rows even when most of their words are
+ * zero (by default the pairs (i, j) are counted over the non-zero words of
+ * row i only when that skips at least two thirds of the words) */
+#define FIM_FLAG_DENSE_ROOT 0x10u
 
 /*
  * Options of a mining call.  A zero field selects its default.
@@ -161,9 +165,17 @@ fim_status fim_minsup_from_relative(uint64_t n_tx, double rel, uint32_t *out_abs
  *                  capped at n_tx / 4)
  *  sample_fi       reservoir size |S| (default from the hypergeometric KL
  *                  bound with rho = 0.001, eps = 0.0005, delta = 0.05)
- *  tile_words      bitmap words per tile of the pair kernels (0 = autotuned)
- *  classes_per_wg  work items a worker claims at once (0 = autotuned)
- *  workers         persistent workers (waves) to launch (0 = autotuned)
+ *  tile_words      bitmap row tile of the depth-first kernel: a wave keeps
+ *                  rows of up to this many words in registers while it pairs
+ *                  them with later rows (512, 1024 or 2048; other values are
+ *                  rounded up to the next of these), wider rows and 256 are
+ *                  streamed from memory in 256-word tiles
+ *                  (0 = from the widest row of the call; fim_autotune picks
+ *                  it by measurement)
+ *  classes_per_wg  first-level classes a worker claims at once
+ *                  (0 = 1; fim_autotune picks it by measurement)
+ *  workers         persistent workers (waves) to launch (0 = as many as the
+ *                  GPU keeps resident)
  *  flags           FIM_FLAG_*
  */
 typedef struct fim_options {
@@ -228,6 +240,8 @@ fim_status fim_mine_batch(fim_ctx *ctx, uint32_t n, const fim_db *const *dbs,
  *  dfs_bytes_algorithmic  bitmap bytes the depth-first kernel must move:
  *                   every class's sibling rows written once and read once
  *  n_itemsets       frequent itemsets reported
+ *  root_sparse      1 if the root class was counted over each row's non-zero
+ *                   words (cover-projected kernel), 0 over whole rows
  *  In a batch, the kernel times are those of the whole batched launch.
  */
 typedef struct fim_stats {
@@ -247,6 +261,7 @@ typedef struct fim_stats {
     uint64_t dfs_kernel_ns;
     uint64_t dfs_bytes_algorithmic;
     uint64_t n_itemsets;
+    uint64_t root_sparse;
 } fim_stats;
 
 /* Number of itemsets and total number of items over all itemsets. */
@@ -322,6 +337,21 @@ fim_status fim_partition_lpt(uint32_t n_classes, const uint32_t *n_atoms,
 fim_status fim_lpt_schedule(const double *weights, uint64_t n_jobs, uint32_t n_workers,
                             uint32_t *worker_of_job, double *makespan);
 
+/*
+ * Autotuner of the batched launch: mines the batch once per candidate
+ * setting of tile_words (256, 512, 1024, 2048) with classes_per_wg = 1, then
+ * classes_per_wg (2, 4) at the best tile width, each setting `reps` times
+ * (0 = 2), and writes into *out the options `base` (NULL = defaults) with
+ * the two fields of the fastest depth-first launch (least GPU time, HIP
+ * events).  The settings do not change results, only speed; the results of
+ * the trial runs are discarded.  *best_ns (may be NULL) receives the
+ * winner's kernel time.
+ * Errors: as fim_mine_batch.
+ */
+fim_status fim_autotune(fim_ctx *ctx, uint32_t n, const fim_db *const *dbs,
+                        const uint32_t *minsups, const fim_options *base, uint32_t reps,
+                        fim_options *out, uint64_t *best_ns);
+
 /* ------------------------------------------------------------------ */
 /* Serving (continuous batching)                                      */
 
@@ -333,14 +363,16 @@ typedef struct fim_server fim_server;
  *  max_queue         waiting requests before submit returns FIM_E_BUSY
  *  hbm_budget_bytes  device memory the server may hold for resident
  *                    requests (admission by footprint); 0 = 3/4 of free memory
- *  step_tasks        work items per persistent step launch (0 = automatic)
+ *  lanes             batches mined at once, each by a worker thread on a
+ *                    HIP stream of its own (0 = 2, at most 8); a lane that is
+ *                    idle admits waiting requests while others still run
  *  opts              mining options applied to every request
  */
 typedef struct fim_server_config {
     uint32_t max_active;
     uint32_t max_queue;
     uint64_t hbm_budget_bytes;
-    uint32_t step_tasks;
+    uint32_t lanes;
     fim_options opts;
 } fim_server_config;
 

@@ -38,12 +38,13 @@ FIM_FLAG_NO_ESTIMATE = 0x1
 FIM_FLAG_ORDER_BY_ID = 0x2
 FIM_FLAG_NO_SPLIT = 0x4
 FIM_FLAG_ALWAYS_ESTIMATE = 0x8
+FIM_FLAG_DENSE_ROOT = 0x10
 
 EXPORTED = [
     "fim_status_str", "fim_last_error", "fim_version", "fim_ctx_create", "fim_ctx_destroy",
     "fim_ctx_release_cached",
     "fim_db_create", "fim_db_destroy", "fim_db_sizes", "fim_minsup_from_relative", "fim_mine",
-    "fim_mine_batch", "fim_result_sizes", "fim_result_copy", "fim_result_stats",
+    "fim_mine_batch", "fim_autotune", "fim_result_sizes", "fim_result_copy", "fim_result_stats",
     "fim_result_destroy", "fim_server_create", "fim_server_submit", "fim_server_poll",
     "fim_server_wait", "fim_server_cancel", "fim_server_stats_get", "fim_server_destroy",
     "fim_estimate_sample_sizes", "fim_reservoir_sample", "fim_partition_lpt", "fim_lpt_schedule",
@@ -77,12 +78,12 @@ class fim_stats(ctypes.Structure):
         "candidates", "pair_words", "item_supports", "n_frequent_items", "bytes_algorithmic",
         "kernel_ns", "total_ns", "estimate_ns", "n_tasks", "retries", "root_candidates",
         "root_pair_words", "root_kernel_ns", "dfs_kernel_ns", "dfs_bytes_algorithmic",
-        "n_itemsets")]
+        "n_itemsets", "root_sparse")]
 
 
 class fim_server_config(ctypes.Structure):
     _fields_ = [("max_active", ctypes.c_uint32), ("max_queue", ctypes.c_uint32),
-                ("hbm_budget_bytes", ctypes.c_uint64), ("step_tasks", ctypes.c_uint32),
+                ("hbm_budget_bytes", ctypes.c_uint64), ("lanes", ctypes.c_uint32),
                 ("opts", fim_options)]
 
 
@@ -125,6 +126,7 @@ def lib():
         "fim_minsup_from_relative": (i32, [u64, ctypes.c_double, P(u32)]),
         "fim_mine": (i32, [V, V, u32, P(fim_options), P(V)]),
         "fim_mine_batch": (i32, [V, u32, P(V), P(u32), P(fim_options), P(V)]),
+        "fim_autotune": (i32, [V, u32, P(V), P(u32), P(fim_options), u32, P(fim_options), P(u64)]),
         "fim_result_sizes": (i32, [V, P(u64), P(u64)]),
         "fim_result_copy": (i32, [V, P(u64), P(u32), P(u32)]),
         "fim_result_stats": (i32, [V, P(fim_stats)]),
@@ -221,6 +223,17 @@ def fim_mine_batch(ctx, dbs, minsups, opts: fim_options | None = None):
     _check(lib().fim_mine_batch(ctx, n, arr, _u32p(ms), ctypes.byref(opts) if opts else None,
                                 outs))
     return [ctypes.c_void_p(outs[i]) for i in range(n)]
+
+
+def fim_autotune(ctx, dbs, minsups, base: fim_options | None = None, reps: int = 0):
+    """Returns (tuned options, best depth-first kernel ns)."""
+    n = len(dbs)
+    arr = (ctypes.c_void_p * n)(*[d.value for d in dbs])
+    ms = np.ascontiguousarray(minsups, dtype=np.uint32)
+    out, ns = fim_options(), ctypes.c_uint64()
+    _check(lib().fim_autotune(ctx, n, arr, _u32p(ms), ctypes.byref(base) if base else None, reps,
+                              ctypes.byref(out), ctypes.byref(ns)))
+    return out, ns.value
 
 
 def fim_result_take(res) -> "Result":
@@ -380,13 +393,23 @@ def mine_batch(ctx: Context, dbs, minsups, **opts):
                                                        minsups, o)]
 
 
+def autotune(ctx: Context, dbs, minsups, reps: int = 0, **opts) -> dict:
+    """Tile width and classes per workgroup for this batch, by measurement;
+    returns the options to pass to ``mine_batch`` (``tile_words``,
+    ``classes_per_wg``) and the winner's kernel time."""
+    o, ns = fim_autotune(ctx.handle, [d.handle for d in dbs], minsups,
+                         make_options(**opts) if opts else None, reps)
+    return {"tile_words": o.tile_words, "classes_per_wg": o.classes_per_wg, "dfs_kernel_ns": ns}
+
+
 class Server:
     """Continuous-batching request loop on one GPU."""
 
     def __init__(self, ctx: Context, max_active: int = 0, max_queue: int = 0,
-                 hbm_budget_bytes: int = 0, **opts):
+                 hbm_budget_bytes: int = 0, lanes: int = 0, **opts):
         cfg = fim_server_config()
         cfg.max_active, cfg.max_queue, cfg.hbm_budget_bytes = max_active, max_queue, hbm_budget_bytes
+        cfg.lanes = lanes
         if opts:
             cfg.opts = make_options(**opts)
         self.ctx = ctx

@@ -112,6 +112,11 @@ namespace fim {
 // exceeded budget marks the results truncated instead of failing.
 constexpr uint32_t kFlagInternalSample = 0x80000000u;
 
+// Limits of an internal sample run: itemsets below the first level per
+// instance, and words of the output arena of the whole run.
+constexpr unsigned long long kSampleRecordBudget = 1ull << 21;
+constexpr uint64_t kSampleOutCap = 1ull << 27;
+
 // One mining instance inside a (possibly batched) run.
 struct MineRequest {
     const fim_db *db;

@@ -31,6 +31,9 @@ struct InstDesc {
     uint32_t max_len;            // longest itemset to report (0 = unlimited)
     uint32_t order_by_id;        // 1: extensions in item-id order instead of support
     uint32_t pad_;
+    // itemsets below the first level the instance may report before its
+    // remaining work is abandoned (0 = unlimited)
+    unsigned long long rec_budget;
 };
 
 // One unit of work of the persistent kernel: rows [r0, r1) of the
@@ -75,7 +78,9 @@ struct InstCounters {
     unsigned long long candidates;  // pair supports computed
     unsigned long long pair_words;  // words AND-popcounted
     unsigned long long child_rows;  // child bitmaps written
-    unsigned long long pad_;
+    unsigned long long records;     // itemsets reported (counted when rec_budget > 0)
+    uint32_t stop;                  // 1 once records exceeded rec_budget
+    uint32_t pad_;
 };
 
 constexpr unsigned kFlagStackOverflow = 1u;
@@ -108,11 +113,26 @@ hipError_t launch_bitmap_build(const uint64_t *offsets, const uint32_t *items, u
 // frequent pairs (it may exceed cap, then nothing past cap is written).
 hipError_t launch_root_pairs(const uint32_t *rows, uint32_t n, uint32_t Wp, uint32_t minsup,
                              uint32_t *pairs, uint64_t cap, unsigned long long *n_pairs,
-                             uint32_t tile_words, hipStream_t stream);
+                             hipStream_t stream);
 
 // Variant of the persistent kernel for rows of at most max_chunks 128-bit
 // chunks (0 = rows are streamed, 2/4/8 = chunks per lane held in registers).
+uint32_t tile_variant(uint32_t tile_words);
 uint32_t dfs_variant(uint32_t max_chunks);
+
+// Root class over the covers of its first-level prefixes (sparse rows):
+// non-zero words of every row (capacity offsets nz_off[n+1], counts
+// nz_cnt[n]), the word-major transpose bt[W][np] (np = n rounded up to 4),
+// and the pair supports counted over row i's non-zero words only.
+hipError_t launch_row_nonzero(const uint32_t *rows, uint32_t n, uint32_t Wp, const uint64_t *nz_off,
+                              uint32_t *nz_w, uint32_t *nz_m, uint32_t *nz_cnt,
+                              hipStream_t stream);
+hipError_t launch_transpose(const uint32_t *rows, uint32_t n, uint32_t Wp, uint32_t W, uint32_t *bt,
+                            uint32_t np, hipStream_t stream);
+hipError_t launch_root_sparse(const uint32_t *bt, uint32_t np, const uint64_t *nz_off,
+                              const uint32_t *nz_cnt, const uint32_t *nz_w, const uint32_t *nz_m,
+                              uint32_t n, uint32_t minsup, uint32_t *pairs, uint64_t cap,
+                              unsigned long long *n_pairs, hipStream_t stream);
 
 // Waves of that persistent kernel variant that fit on the device at once.
 uint32_t dfs_resident_workers(int n_cu, uint32_t variant);

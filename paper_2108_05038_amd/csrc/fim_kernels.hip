@@ -238,6 +238,135 @@ __global__ __launch_bounds__(kBlock) void k_root_pairs(const uint32_t *__restric
         }
 }
 
+// ------------------------------------------------------------------ a6/a7: root class over covers
+// The pairs (i, j > i) of the root class counted only over the words where
+// row i (the sparser one: rows ascend by support) is non-zero, i.e. over
+// the cover of the first-level prefix {a_i}.  The other words add nothing
+// to popcount(row_i AND row_j), so the supports are the same.  Row i's
+// non-zero words and their masks are listed once (k_row_nonzero); the rows
+// are transposed word-major (k_transpose), so that for one word of row i the
+// lanes of a block read consecutive partner rows j with 128-bit loads.
+
+// one wave per row: the row's non-zero words, compacted with ballot/mbcnt
+__global__ __launch_bounds__(kBlock) void k_row_nonzero(const uint32_t *__restrict__ rows,
+                                                         uint32_t n, uint32_t Wp,
+                                                         const uint64_t *__restrict__ nz_off,
+                                                         uint32_t *nz_w, uint32_t *nz_m,
+                                                         uint32_t *nz_cnt) {
+    const uint32_t r = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    if (r >= n) return;
+    const uint32_t lane = lane_id();
+    const uint32_t *row = rows + (uint64_t)r * Wp;
+    const uint64_t base = nz_off[r], cap = nz_off[r + 1] - base;
+    uint32_t cnt = 0;
+    for (uint32_t w0 = 0; w0 < Wp; w0 += kWave) {
+        const uint32_t w = w0 + lane;
+        const uint32_t x = w < Wp ? row[w] : 0u;
+        const uint64_t mask = __ballot(x != 0u);
+        if (x) {
+            const uint32_t p = cnt + lanes_below(mask);
+            if (p < cap) {
+                nz_w[base + p] = w;
+                nz_m[base + p] = x;
+            }
+        }
+        cnt += (uint32_t)__popcll(mask);
+    }
+    if (lane == 0) nz_cnt[r] = cnt < cap ? cnt : (uint32_t)cap;
+}
+
+// bt[w * np + j] = rows[j * Wp + w] for w < W, j < np (zero for j >= n)
+__global__ __launch_bounds__(kBlock) void k_transpose(const uint32_t *__restrict__ rows, uint32_t n,
+                                                       uint32_t Wp, uint32_t W, uint32_t *bt,
+                                                       uint32_t np) {
+    __shared__ uint32_t tile[64][65];
+    const uint32_t w0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+    const uint32_t tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (uint32_t r = ty; r < 64; r += 4) {
+        const uint32_t j = j0 + r, w = w0 + tx;
+        tile[r][tx] = (j < n && w < W) ? rows[(uint64_t)j * Wp + w] : 0u;
+    }
+    __syncthreads();
+    for (uint32_t r = ty; r < 64; r += 4) {
+        const uint32_t w = w0 + r, j = j0 + tx;
+        if (w < W && j < np) bt[(uint64_t)w * np + j] = tile[tx][r];
+    }
+}
+
+constexpr uint32_t kSparseCols = 4 * kBlock;  // partner rows per block
+
+// block (jb, i): row i against partners j in [jb * 1024, jb * 1024 + 1024),
+// four per thread
+__global__ __launch_bounds__(kBlock) void k_root_sparse(
+    const uint32_t *__restrict__ bt, uint32_t np, const uint64_t *__restrict__ nz_off,
+    const uint32_t *__restrict__ nz_cnt, const uint32_t *__restrict__ nz_w,
+    const uint32_t *__restrict__ nz_m, uint32_t n, uint32_t minsup, uint32_t *pairs, uint64_t cap,
+    unsigned long long *n_pairs) {
+    const uint32_t i = blockIdx.y;
+    const uint32_t jb0 = blockIdx.x * kSparseCols;
+    if (jb0 + kSparseCols <= i + 1) return;  // no partner j > i in this block
+    const uint32_t j0 = jb0 + threadIdx.x * 4;
+    const uint64_t base = nz_off[i];
+    const uint32_t cnt = nz_cnt[i];
+    uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    if (j0 < np) {
+        const uint32_t *col = bt + j0;
+        uint32_t k = 0;
+        for (; k + 4 <= cnt; k += 4) {
+            const uint32_t w0 = nz_w[base + k], w1 = nz_w[base + k + 1];
+            const uint32_t w2 = nz_w[base + k + 2], w3 = nz_w[base + k + 3];
+            const uint32_t m0 = nz_m[base + k], m1 = nz_m[base + k + 1];
+            const uint32_t m2 = nz_m[base + k + 2], m3 = nz_m[base + k + 3];
+            const uint4 x0 = *reinterpret_cast<const uint4 *>(col + (uint64_t)w0 * np);
+            const uint4 x1 = *reinterpret_cast<const uint4 *>(col + (uint64_t)w1 * np);
+            const uint4 x2 = *reinterpret_cast<const uint4 *>(col + (uint64_t)w2 * np);
+            const uint4 x3 = *reinterpret_cast<const uint4 *>(col + (uint64_t)w3 * np);
+            a0 += __popc(m0 & x0.x) + __popc(m1 & x1.x) + __popc(m2 & x2.x) + __popc(m3 & x3.x);
+            a1 += __popc(m0 & x0.y) + __popc(m1 & x1.y) + __popc(m2 & x2.y) + __popc(m3 & x3.y);
+            a2 += __popc(m0 & x0.z) + __popc(m1 & x1.z) + __popc(m2 & x2.z) + __popc(m3 & x3.z);
+            a3 += __popc(m0 & x0.w) + __popc(m1 & x1.w) + __popc(m2 & x2.w) + __popc(m3 & x3.w);
+        }
+        for (; k < cnt; k++) {
+            const uint32_t m = nz_m[base + k];
+            const uint4 x = *reinterpret_cast<const uint4 *>(col + (uint64_t)nz_w[base + k] * np);
+            a0 += __popc(m & x.x);
+            a1 += __popc(m & x.y);
+            a2 += __popc(m & x.z);
+            a3 += __popc(m & x.w);
+        }
+    }
+    const uint32_t acc[4] = {a0, a1, a2, a3};
+    uint32_t mine = 0;
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        const uint32_t j = j0 + c;
+        mine += (j > i && j < n && acc[c] >= minsup) ? 1u : 0u;
+    }
+    uint32_t incl = mine;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t v = __shfl_up(incl, off, kWave);
+        if ((int)lane_id() >= off) incl += v;
+    }
+    const uint32_t total = __shfl(incl, kWave - 1, kWave);
+    unsigned long long b = 0;
+    if (lane_id() == 0 && total) b = atomicAdd(n_pairs, (unsigned long long)total);
+    b = shfl_u64(b, 0);
+    uint64_t pos = b + incl - mine;
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        const uint32_t j = j0 + c;
+        if (j > i && j < n && acc[c] >= minsup) {
+            if (pos < cap) {
+                pairs[3 * pos + 0] = i;
+                pairs[3 * pos + 1] = j;
+                pairs[3 * pos + 2] = acc[c];
+            }
+            pos++;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ a5-a8: persistent DFS
 //
 // Every wave is one worker with a private region of `stack_words` words:
@@ -496,11 +625,19 @@ __device__ __forceinline__ bool donation_wanted(DfsCounters *ctr) {
 // CPL > 0: a row spans at most 64 * CPL chunks and the expanded row is held
 // in registers (CPL chunks per lane) for all its pairs and child rows, with
 // two partner rows loaded per round.  CPL = 0: rows of any width, streamed.
+// the instance went over its record budget (wave-uniform)
+__device__ __forceinline__ bool inst_stopped(const InstDesc &I, InstCounters *ictr, uint32_t inst) {
+    if (I.rec_budget == 0) return false;
+    uint32_t v = 0;
+    if (lane_id() == 0) v = load_coherent32(&ictr[inst].stop);
+    return __shfl(v, 0, kWave) != 0;
+}
+
 template <int CPL>
 __device__ void process_frame(const InstDesc &I, uint32_t inst, uint32_t task, const FrameSrc &src,
                               uint32_t *region, uint64_t S, WaveShared &ws, uint32_t *out,
-                              uint64_t out_cap, DfsCounters *ctr, WaveStats &st, OutChunk &oc,
-                              Donation &dn) {
+                              uint64_t out_cap, DfsCounters *ctr, InstCounters *ictr, WaveStats &st,
+                              OutChunk &oc, Donation &dn) {
     const uint32_t lane = lane_id();
     const uint32_t Wp = I.Wp, C = Wp / 4;  // 128-bit chunks per row
     const uint32_t k = src.k, plen = src.plen;
@@ -550,9 +687,10 @@ __device__ void process_frame(const InstDesc &I, uint32_t inst, uint32_t task, c
     __builtin_amdgcn_wave_barrier();
     uint64_t rows_top = (uint64_t)k * Wp;  // the T(prefix) row is no longer needed
     uint64_t peak = rows_top + prow * Wp + (S - meta);
-    uint32_t polls = 0, cool = 0;
+    uint32_t polls = 0, cool = 0, iters = 0;
 
     while (depth >= 0) {
+        if ((++iters & 15u) == 0 && inst_stopped(I, ictr, inst)) return;
         if (dn.enabled && cool == 0 && ((++polls & 3u) == 0) && donation_wanted(ctr)) {
             const bool gave = try_donate(I, inst, plen, depth, region, ws, dn, ctr);
             cool = gave ? 8u : 4u;
@@ -670,6 +808,16 @@ __device__ void process_frame(const InstDesc &I, uint32_t inst, uint32_t task, c
         // report the nf itemsets prefix + a_r + child atom
         const uint32_t len = plen + (uint32_t)depth + 2;
         if (I.max_len == 0 || len <= I.max_len) {
+            if (I.rec_budget) {
+                unsigned long long before = 0;
+                if (lane == 0) before = atomicAdd(&ictr[inst].records, (unsigned long long)nf);
+                before = shfl_u64(before, 0);
+                if (before + nf > I.rec_budget) {
+                    // over budget: the instance's remaining work is abandoned
+                    if (lane == 0) atomicOr(&ictr[inst].stop, 1u);
+                    return;
+                }
+            }
             const uint32_t rec = kRecHeader + len;
             if (chunk_reserve(oc, nf * rec, task, inst, out, out_cap, ctr)) {
                 uint32_t *obase = out + oc.base + oc.pos;
@@ -767,13 +915,14 @@ __device__ void process_frame(const InstDesc &I, uint32_t inst, uint32_t task, c
 template <int CPL>
 __device__ void run_frame(const InstDesc &I, uint32_t inst, uint32_t task, const FrameSrc &src,
                           uint32_t *region, uint64_t S, WaveShared &ws, uint32_t *out,
-                          uint64_t out_cap, DfsCounters *ctr, WaveStats &st, OutChunk &oc,
-                          Donation &dn) {
+                          uint64_t out_cap, DfsCounters *ctr, InstCounters *ictr, WaveStats &st,
+                          OutChunk &oc, Donation &dn) {
+    if (inst_stopped(I, ictr, inst)) return;
     const uint32_t C = I.Wp / 4;
     if (CPL > 0 && C > (uint32_t)kWave && C <= (uint32_t)(CPL * kWave))
-        process_frame<CPL>(I, inst, task, src, region, S, ws, out, out_cap, ctr, st, oc, dn);
+        process_frame<CPL>(I, inst, task, src, region, S, ws, out, out_cap, ctr, ictr, st, oc, dn);
     else
-        process_frame<0>(I, inst, task, src, region, S, ws, out, out_cap, ctr, st, oc, dn);
+        process_frame<0>(I, inst, task, src, region, S, ws, out, out_cap, ctr, ictr, st, oc, dn);
 }
 
 __device__ __forceinline__ void flush_stats(InstCounters *ictr, uint32_t inst, const WaveStats &st) {
@@ -832,7 +981,7 @@ __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Tas
                               k1 - T.r0, T.r1 - T.r0};
             const unsigned long long c0 = wall_clock64();
             run_frame<CPL>(I, T.inst, (uint32_t)t, fs, region, stack_words, ws, out, out_cap, ctr,
-                           st, oc, dn);
+                           ictr, st, oc, dn);
             close_chunk(oc, out);
             busy += wall_clock64() - c0;
             flush_stats(ictr, T.inst, st);
@@ -907,7 +1056,7 @@ __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Tas
                     const unsigned long long c0 = wall_clock64();
                     // the frame's own atom arrays go below the copy
                     run_frame<CPL>(I, inst, (uint32_t)(n_tasks + got), fs, region,
-                                   stack_words - words, ws, out, out_cap, ctr, st, oc, dn);
+                                   stack_words - words, ws, out, out_cap, ctr, ictr, st, oc, dn);
                     close_chunk(oc, out);
                     busy += wall_clock64() - c0;
                     flush_stats(ictr, inst, st);
@@ -977,8 +1126,7 @@ hipError_t launch_bitmap_build(const uint64_t *offsets, const uint32_t *items, u
 
 hipError_t launch_root_pairs(const uint32_t *rows, uint32_t n, uint32_t Wp, uint32_t minsup,
                              uint32_t *pairs, uint64_t cap, unsigned long long *n_pairs,
-                             uint32_t tile_words, hipStream_t stream) {
-    (void)tile_words;
+                             hipStream_t stream) {
     if (n < 2) return hipSuccess;
     const uint64_t nt = (n + kRootRows - 1) / kRootRows;
     const uint64_t tiles = nt * (nt + 1) / 2;
@@ -986,6 +1134,44 @@ hipError_t launch_root_pairs(const uint32_t *rows, uint32_t n, uint32_t Wp, uint
     hipLaunchKernelGGL(k_root_pairs, dim3((uint32_t)tiles), dim3(kBlock), 0, stream, rows, n, Wp,
                        minsup, pairs, cap, n_pairs);
     return hipGetLastError();
+}
+
+hipError_t launch_row_nonzero(const uint32_t *rows, uint32_t n, uint32_t Wp, const uint64_t *nz_off,
+                              uint32_t *nz_w, uint32_t *nz_m, uint32_t *nz_cnt,
+                              hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_row_nonzero, dim3((n + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock),
+                       0, stream, rows, n, Wp, nz_off, nz_w, nz_m, nz_cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose(const uint32_t *rows, uint32_t n, uint32_t Wp, uint32_t W, uint32_t *bt,
+                            uint32_t np, hipStream_t stream) {
+    if (n == 0 || W == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_transpose, dim3((W + 63) / 64, (np + 63) / 64), dim3(kBlock), 0, stream,
+                       rows, n, Wp, W, bt, np);
+    return hipGetLastError();
+}
+
+hipError_t launch_root_sparse(const uint32_t *bt, uint32_t np, const uint64_t *nz_off,
+                              const uint32_t *nz_cnt, const uint32_t *nz_w, const uint32_t *nz_m,
+                              uint32_t n, uint32_t minsup, uint32_t *pairs, uint64_t cap,
+                              unsigned long long *n_pairs, hipStream_t stream) {
+    if (n < 2) return hipSuccess;
+    const uint32_t jblocks = (np + kSparseCols - 1) / kSparseCols;
+    hipLaunchKernelGGL(k_root_sparse, dim3(jblocks, n), dim3(kBlock), 0, stream, bt, np, nz_off,
+                       nz_cnt, nz_w, nz_m, n, minsup, pairs, cap, n_pairs);
+    return hipGetLastError();
+}
+
+// row tile in words -> register-resident variant (256 words and wider than
+// 2048 words: streamed)
+uint32_t tile_variant(uint32_t tile_words) {
+    if (tile_words <= 256) return 0;
+    if (tile_words <= 512) return 2;
+    if (tile_words <= 1024) return 4;
+    if (tile_words <= 2048) return 8;
+    return 0;
 }
 
 uint32_t dfs_variant(uint32_t max_chunks) {

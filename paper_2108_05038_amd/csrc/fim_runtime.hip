@@ -414,6 +414,11 @@ struct Inst {
     std::vector<uint32_t> l2_off, l2_atom, l2_supp;
     DevBuf d_counts, d_rank_of_item, d_item_of_rank, d_rows, d_pairs, d_npairs;
     DevBuf d_l2_off, d_l2_atom, d_l2_supp;
+    // root class over covers: non-zero words per row and the transposed arena
+    bool sparse_root = false;
+    std::vector<uint64_t> nz_off;
+    std::vector<uint32_t> nz_cnt;
+    DevBuf d_nz_off, d_nz_w, d_nz_m, d_nz_cnt, d_bt;
     fim_stats st{};
     uint64_t first_class_rows = 0;  // sum of atoms over first-level classes with >= 2 atoms
 };
@@ -551,11 +556,49 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         ENSURE(I.d_pairs, ctx, cap * 12);
         ENSURE(I.d_npairs, ctx, 8);
         HIPCHK(launch_fill_u32(I.d_npairs.as<uint32_t>(), 2, 0u, s));
-        HIPCHK(hipEventRecord(rev[2 * q], s));
-        HIPCHK(launch_root_pairs(I.d_rows.as<uint32_t>(), I.n_freq, I.Wp, I.minsup,
-                                 I.d_pairs.as<uint32_t>(), cap,
-                                 I.d_npairs.as<unsigned long long>(), opts.tile_words, s));
-        HIPCHK(hipEventRecord(rev[2 * q + 1], s));
+        // Root class over the covers of its prefixes when that skips most
+        // words: row i has at most min(supp_i, W) non-zero words, so the
+        // pair-words to count are bounded by sum_i min(supp_i, W)(n - 1 - i)
+        const uint32_t n = I.n_freq;
+        double bound = 0.0;
+        for (uint32_t r = 0; r < n; r++)
+            bound += (double)std::min<uint32_t>(I.supp_of_rank[r], I.W) * (double)(n - 1 - r);
+        I.sparse_root = !(opts.flags & FIM_FLAG_DENSE_ROOT) && n >= 64 && n <= 65535 &&
+                        3.0 * bound < (double)all * (double)I.W;
+        if (I.sparse_root) {
+            I.nz_off.assign(n + 1, 0);
+            for (uint32_t r = 0; r < n; r++)
+                I.nz_off[r + 1] = I.nz_off[r] + std::min<uint32_t>(I.supp_of_rank[r], I.W);
+            const uint64_t np = (n + 3) / 4 * 4;
+            ENSURE(I.d_nz_off, ctx, (n + 1) * 8);
+            ENSURE(I.d_nz_w, ctx, std::max<uint64_t>(I.nz_off[n], 1) * 4);
+            ENSURE(I.d_nz_m, ctx, std::max<uint64_t>(I.nz_off[n], 1) * 4);
+            ENSURE(I.d_nz_cnt, ctx, (size_t)n * 4);
+            ENSURE(I.d_bt, ctx, (size_t)I.W * np * 4);
+            HIPCHK(hipMemcpyAsync(I.d_nz_off.as<void>(), I.nz_off.data(), (n + 1) * 8,
+                                  hipMemcpyHostToDevice, s));
+            HIPCHK(launch_row_nonzero(I.d_rows.as<uint32_t>(), n, I.Wp, I.d_nz_off.as<uint64_t>(),
+                                      I.d_nz_w.as<uint32_t>(), I.d_nz_m.as<uint32_t>(),
+                                      I.d_nz_cnt.as<uint32_t>(), s));
+            HIPCHK(launch_transpose(I.d_rows.as<uint32_t>(), n, I.Wp, I.W, I.d_bt.as<uint32_t>(),
+                                    (uint32_t)np, s));
+            HIPCHK(hipEventRecord(rev[2 * q], s));
+            HIPCHK(launch_root_sparse(I.d_bt.as<uint32_t>(), (uint32_t)np, I.d_nz_off.as<uint64_t>(),
+                                      I.d_nz_cnt.as<uint32_t>(), I.d_nz_w.as<uint32_t>(),
+                                      I.d_nz_m.as<uint32_t>(), n, I.minsup,
+                                      I.d_pairs.as<uint32_t>(), cap,
+                                      I.d_npairs.as<unsigned long long>(), s));
+            HIPCHK(hipEventRecord(rev[2 * q + 1], s));
+            I.nz_cnt.resize(n);
+            HIPCHK(hipMemcpyAsync(I.nz_cnt.data(), I.d_nz_cnt.as<void>(), (size_t)n * 4,
+                                  hipMemcpyDeviceToHost, s));
+        } else {
+            HIPCHK(hipEventRecord(rev[2 * q], s));
+            HIPCHK(launch_root_pairs(I.d_rows.as<uint32_t>(), I.n_freq, I.Wp, I.minsup,
+                                     I.d_pairs.as<uint32_t>(), cap,
+                                     I.d_npairs.as<unsigned long long>(), s));
+            HIPCHK(hipEventRecord(rev[2 * q + 1], s));
+        }
         HIPCHK(hipMemcpyAsync(&I.n_pairs, I.d_npairs.as<void>(), 8, hipMemcpyDeviceToHost, s));
     }
     const bool deep = opts.max_len == 0 || opts.max_len >= 3;
@@ -575,9 +618,16 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         if (I.n_pairs > cap) {  // rerun with room for every frequent pair
             ENSURE(I.d_pairs, ctx, I.n_pairs * 12);
             HIPCHK(launch_fill_u32(I.d_npairs.as<uint32_t>(), 2, 0u, s));
-            HIPCHK(launch_root_pairs(I.d_rows.as<uint32_t>(), I.n_freq, I.Wp, I.minsup,
-                                     I.d_pairs.as<uint32_t>(), I.n_pairs,
-                                     I.d_npairs.as<unsigned long long>(), opts.tile_words, s));
+            if (I.sparse_root)
+                HIPCHK(launch_root_sparse(I.d_bt.as<uint32_t>(), (uint32_t)((I.n_freq + 3) / 4 * 4),
+                                          I.d_nz_off.as<uint64_t>(), I.d_nz_cnt.as<uint32_t>(),
+                                          I.d_nz_w.as<uint32_t>(), I.d_nz_m.as<uint32_t>(),
+                                          I.n_freq, I.minsup, I.d_pairs.as<uint32_t>(), I.n_pairs,
+                                          I.d_npairs.as<unsigned long long>(), s));
+            else
+                HIPCHK(launch_root_pairs(I.d_rows.as<uint32_t>(), I.n_freq, I.Wp, I.minsup,
+                                         I.d_pairs.as<uint32_t>(), I.n_pairs,
+                                         I.d_npairs.as<unsigned long long>(), s));
             I.st.retries++;
         }
         I.pairs.resize(I.n_pairs * 3);
@@ -585,10 +635,24 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             HIPCHK(hipMemcpyAsync(I.pairs.data(), I.d_pairs.as<void>(), I.n_pairs * 12,
                                   hipMemcpyDeviceToHost, s));
         I.st.candidates = all;
-        I.st.pair_words = all * I.W;
         I.st.root_candidates = all;
-        I.st.root_pair_words = all * I.W;
-        I.st.bytes_algorithmic = (uint64_t)I.n_freq * I.W * 4;
+        if (I.sparse_root) {
+            // words counted: row i's cover words against every later row;
+            // bytes: each row's non-zero words (word + mask) and the
+            // transposed arena read once
+            uint64_t pw = 0, nzt = 0;
+            for (uint32_t r = 0; r < I.n_freq; r++) {
+                pw += (uint64_t)I.nz_cnt[r] * (I.n_freq - 1 - r);
+                nzt += I.nz_cnt[r];
+            }
+            I.st.root_pair_words = pw;
+            I.st.bytes_algorithmic = 8 * nzt + (uint64_t)I.n_freq * I.W * 4;
+            I.st.root_sparse = 1;
+        } else {
+            I.st.root_pair_words = all * I.W;
+            I.st.bytes_algorithmic = (uint64_t)I.n_freq * I.W * 4;
+        }
+        I.st.pair_words = I.st.root_pair_words;
     }
     HIPCHK(hipStreamSynchronize(s));
     for (uint32_t q = 0; q < n_inst; q++) {
@@ -603,7 +667,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
     // ---------------- a4: class-size estimate, Partition, LPT order
     uint32_t max_chunks = 0;
     for (const Inst &I : insts) max_chunks = std::max(max_chunks, I.Wp / 4);
-    const uint32_t variant = dfs_variant(max_chunks);
+    const uint32_t variant = opts.tile_words ? tile_variant(opts.tile_words) : dfs_variant(max_chunks);
     uint32_t n_workers = opts.workers ? opts.workers : dfs_resident_workers(ctx->n_cu, variant);
     n_workers = std::max<uint32_t>(4, (n_workers + 3) / 4 * 4);
     std::vector<Task> tasks;
@@ -689,6 +753,12 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             D.minsup = I.minsup;
             D.max_len = opts.max_len;
             D.order_by_id = by_id ? 1u : 0u;
+            // A sample drawn with replacement at a small scaled support can
+            // make every subset of a repeatedly drawn long transaction
+            // frequent; its search is abandoned past a fixed budget (the
+            // instance then has no estimate).  A real run stops early once
+            // it is certain to exceed max_itemsets.
+            D.rec_budget = sample_run ? kSampleRecordBudget : opts.max_itemsets;
         }
         for (const Task &T : tasks) {
             const Inst &I = insts[T.inst];
@@ -808,11 +878,20 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                 S = std::max<uint64_t>(2 * S, ctr.stack_need + ctr.stack_need / 4);
                 again = true;
             }
+            if (!sample_mode)
+                for (uint32_t q = 0; q < n_inst; q++)
+                    if (ictr[q].stop)
+                        return set_error(FIM_E_OUTPUT_LIMIT,
+                                         "instance " + std::to_string(q) +
+                                             ": more frequent itemsets than max_itemsets");
             if ((ctr.flags & kFlagOutOverflow) || ctr.out_used.v > out_cap) {
-                if (sample_mode) {
+                // grow the arena (work sharing varies the need between runs);
+                // a sample run past a hard cap is cut short instead
+                const uint64_t want = ctr.out_used.v + ctr.out_used.v / 2 + 4096;
+                if (sample_mode && want > kSampleOutCap) {
                     truncated = true;
                 } else {
-                    out_cap = ctr.out_used.v + ctr.out_used.v / 2 + 4096;  // work sharing varies it
+                    out_cap = want;
                     again = true;
                 }
             }
@@ -1021,7 +1100,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         R->supp.swap(r_supp[q]);
         R->stats = insts[q].st;
         if (!sample_run) R->stats.n_itemsets = R->supp.size();
-        R->truncated = truncated;
+        R->truncated = truncated || (sample_run && ictr[q].stop);
         results[q] = R;
     }
     tr.mark("decode + canonical order");
@@ -1070,5 +1149,47 @@ extern "C" fim_status fim_mine_batch(fim_ctx *ctx, uint32_t n, const fim_db *con
     fim_status st = fim::mine_many(ctx, reqs, fim::resolve_options(opts), res, true);
     if (st != FIM_OK) return st;
     for (uint32_t q = 0; q < n; q++) outs[q] = res[q];
+    return FIM_OK;
+}
+
+extern "C" fim_status fim_autotune(fim_ctx *ctx, uint32_t n, const fim_db *const *dbs,
+                                   const uint32_t *minsups, const fim_options *base, uint32_t reps,
+                                   fim_options *out, uint64_t *best_ns) {
+    if (!out) return fim::set_error(FIM_E_INVALID_ARG, "out is NULL");
+    const fim_options b = fim::resolve_options(base);
+    *out = b;
+    if (reps == 0) reps = 2;
+    std::vector<fim_result *> res(n);
+    // least depth-first kernel time of `reps` runs with tile t and claim c
+    auto trial = [&](uint32_t t, uint32_t c, uint64_t &ns) -> fim_status {
+        fim_options o = b;
+        o.tile_words = t;
+        o.classes_per_wg = c;
+        ns = ~0ull;
+        for (uint32_t k = 0; k < reps; k++) {
+            fim_status st = fim_mine_batch(ctx, n, dbs, minsups, &o, res.data());
+            if (st != FIM_OK) return st;
+            fim_stats s0{};
+            if (n) (void)fim_result_stats(res[0], &s0);
+            ns = std::min<uint64_t>(ns, s0.dfs_kernel_ns);
+            for (fim_result *r : res) fim_result_destroy(r);
+        }
+        return FIM_OK;
+    };
+    uint32_t best_t = 0, best_c = 1;
+    uint64_t best = ~0ull, ns = 0;
+    for (uint32_t t : {256u, 512u, 1024u, 2048u}) {
+        fim_status st = trial(t, 1, ns);
+        if (st != FIM_OK) return st;
+        if (ns < best) best = ns, best_t = t;
+    }
+    for (uint32_t c : {2u, 4u}) {
+        fim_status st = trial(best_t, c, ns);
+        if (st != FIM_OK) return st;
+        if (ns < best) best = ns, best_c = c;
+    }
+    out->tile_words = best_t;
+    out->classes_per_wg = best_c;
+    if (best_ns) *best_ns = best;
     return FIM_OK;
 }

@@ -1,12 +1,14 @@
 // Serving: a request loop on one GPU with continuous batching.
 //
-// Requests are queued by fim_server_submit (any thread).  A worker thread
-// owns the GPU.  Each step it admits waiting requests in arrival order while
-// a slot is free and the HBM footprint of their bitmaps fits the budget,
-// then mines every admitted request in one batched persistent launch.
-// Requests that arrive while a step runs join the next step; a finished
-// request leaves its slot and its memory at once.  Results are identical to
-// fim_mine on the same database and minimum support.
+// Requests are queued by fim_server_submit (any thread).  The server runs
+// several lanes, each a worker thread with a HIP stream of its own.  An idle
+// lane admits the waiting requests in arrival order while a slot is free and
+// the HBM footprint of their bitmaps fits what the other lanes leave of the
+// budget, and mines them in one batched persistent launch.  Requests that
+// arrive while a batch runs are taken by the next idle lane, so their work
+// overlaps the running batch on the device (and its host-side stages); a
+// finished batch gives its slots and memory back at once.  Results are
+// identical to fim_mine on the same database and minimum support.
 #include <atomic>
 #include <condition_variable>
 #include <deque>
@@ -31,6 +33,12 @@ struct Done {
     std::string error;
 };
 
+struct Lane {
+    fim_ctx *ctx = nullptr;
+    bool own = false;
+    std::thread th;
+};
+
 }  // namespace
 
 struct fim_server {
@@ -43,9 +51,10 @@ struct fim_server {
     std::unordered_map<uint64_t, int> state;  // 0 queued, 1 running, 2 done
     std::unordered_map<uint64_t, bool> cancelled;
     uint64_t next_ticket = 1;
+    uint64_t active = 0, active_bytes = 0;  // over all lanes
     bool stop = false;
     fim_server_stats stats{};
-    std::thread worker;
+    std::vector<Lane> lanes;
 };
 
 namespace {
@@ -58,34 +67,49 @@ uint64_t footprint(const fim_db *db) {
     return rows * W * 4 + (uint64_t)db->n_item_ids * 16 + (64ull << 20);
 }
 
-void worker_loop(fim_server *s) {
-    (void)hipSetDevice(s->ctx->device);
+// the front request fits the free slots and memory (a request alone on an
+// idle device is always admitted, whatever its size)
+bool admissible(const fim_server *s, uint64_t taken, uint64_t taken_bytes) {
+    if (s->queue.empty()) return false;
+    if (s->active + taken >= s->cfg.max_active) return false;
+    const uint64_t busy = s->active + taken;
+    return busy == 0 || s->active_bytes + taken_bytes + s->queue.front().footprint <=
+                            s->cfg.hbm_budget_bytes;
+}
+
+void worker_loop(fim_server *s, fim_ctx *ctx) {
+    (void)hipSetDevice(ctx->device);
     for (;;) {
         std::vector<Request> batch;
+        uint64_t bytes = 0;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
-            if (s->stop && s->queue.empty()) return;
-            uint64_t bytes = 0;
-            while (!s->queue.empty() && batch.size() < s->cfg.max_active) {
+            s->cv_work.wait(lk, [&] {
+                return (s->stop && s->queue.empty()) || admissible(s, 0, 0);
+            });
+            if (s->queue.empty()) return;  // stopping
+            while (admissible(s, batch.size(), bytes)) {
                 const Request &r = s->queue.front();
-                if (!batch.empty() && bytes + r.footprint > s->cfg.hbm_budget_bytes) break;
                 bytes += r.footprint;
                 batch.push_back(r);
                 s->state[r.ticket] = 1;
                 s->queue.pop_front();
             }
-            s->stats.peak_active = std::max<uint64_t>(s->stats.peak_active, batch.size());
-            s->stats.peak_bytes = std::max<uint64_t>(s->stats.peak_bytes, bytes);
+            s->active += batch.size();
+            s->active_bytes += bytes;
+            s->stats.peak_active = std::max<uint64_t>(s->stats.peak_active, s->active);
+            s->stats.peak_bytes = std::max<uint64_t>(s->stats.peak_bytes, s->active_bytes);
         }
         std::vector<fim::MineRequest> reqs;
         for (const Request &r : batch) reqs.push_back({r.db, r.minsup});
         std::vector<fim_result *> res;
-        fim_status st = fim::mine_many(s->ctx, reqs, s->cfg.opts, res, true);
+        fim_status st = fim::mine_many(ctx, reqs, s->cfg.opts, res, true);
         std::string err = st == FIM_OK ? "" : fim_last_error();
         {
             std::lock_guard<std::mutex> lk(s->mu);
             s->stats.steps++;
+            s->active -= batch.size();
+            s->active_bytes -= bytes;
             for (size_t k = 0; k < batch.size(); k++) {
                 const uint64_t t = batch[k].ticket;
                 fim_result *r = st == FIM_OK ? res[k] : nullptr;
@@ -100,6 +124,7 @@ void worker_loop(fim_server *s) {
             }
         }
         s->cv_done.notify_all();
+        s->cv_work.notify_all();  // freed slots and memory may admit more
     }
 }
 
@@ -115,13 +140,34 @@ extern "C" fim_status fim_server_create(fim_ctx *ctx, const fim_server_config *c
     if (cfg) s->cfg = *cfg;
     if (s->cfg.max_active == 0) s->cfg.max_active = 64;
     if (s->cfg.max_queue == 0) s->cfg.max_queue = 1u << 16;
+    if (s->cfg.lanes == 0) s->cfg.lanes = 2;
+    if (s->cfg.lanes > 8) {
+        delete s;
+        return fim::set_error(FIM_E_INVALID_ARG, "at most 8 lanes");
+    }
     if (s->cfg.hbm_budget_bytes == 0) {
         size_t fr = 0, tot = 0;
         (void)hipSetDevice(ctx->device);
         if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = ctx->total_mem / 2;
         s->cfg.hbm_budget_bytes = fr / 4 * 3;
     }
-    s->worker = std::thread(worker_loop, s);
+    // lane 0 mines on the caller's context; the others on contexts of their
+    // own (same device and allocator, a stream each)
+    s->lanes.resize(s->cfg.lanes);
+    s->lanes[0].ctx = ctx;
+    for (uint32_t l = 1; l < s->cfg.lanes; l++) {
+        fim_ctx *c = nullptr;
+        const fim_status st = fim_ctx_create(ctx->device, nullptr,
+                                             ctx->user_alloc ? &ctx->alloc : nullptr, &c);
+        if (st != FIM_OK) {
+            for (uint32_t q = 1; q < l; q++) fim_ctx_destroy(s->lanes[q].ctx);
+            delete s;
+            return st;
+        }
+        s->lanes[l].ctx = c;
+        s->lanes[l].own = true;
+    }
+    for (Lane &L : s->lanes) L.th = std::thread(worker_loop, s, L.ctx);
     *out = s;
     return FIM_OK;
 }
@@ -209,7 +255,10 @@ extern "C" void fim_server_destroy(fim_server *s) {
         s->queue.clear();
     }
     s->cv_work.notify_all();
-    if (s->worker.joinable()) s->worker.join();
+    for (Lane &L : s->lanes)
+        if (L.th.joinable()) L.th.join();
+    for (Lane &L : s->lanes)
+        if (L.own) fim_ctx_destroy(L.ctx);
     for (auto &kv : s->done) fim_result_destroy(kv.second.result);
     delete s;
 }

@@ -181,13 +181,16 @@ GUARD_LIMIT = 5_000_000
 GUARD_STRIDE = 100_000
 
 
-def serve_params(k: int) -> dict:
+def serve_params(k: int, sub: int | None = None) -> dict:
     """Request k of the serving pool: 9 in 10 basket instances drawn like the
     batch instances (from their own substreams), 1 in 10 dense instances with
-    log-uniform 1,000..50,000 transactions over 120 items at 40 % support."""
+    log-uniform 1,000..50,000 transactions over 120 items at 40 % support.
+    ``sub`` is the substream drawn from (default k; a request whose result
+    exceeds GUARD_LIMIT itemsets is redrawn from k + GUARD_STRIDE, ...)."""
+    sub = k if sub is None else sub
     if k % 10 == 9:
-        return dense_params(k, SERVE_BASE)
-    p = batch_params(k, base=SERVE_BASE)
+        return dense_params(sub, SERVE_BASE)
+    p = batch_params(sub, base=SERVE_BASE)
     p["kind"] = "basket"
     return p
 

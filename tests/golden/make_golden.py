@@ -73,17 +73,24 @@ def golden_batch(threads: int, n: int = 256) -> dict:
 
 
 def golden_serve(threads: int, n: int = 512) -> dict:
+    """Oracle results of the serving pool, with the same explosion guard as
+    the batch (redraws recorded as the substream used)."""
     out = []
     for k in range(n):
-        p = synth.serve_params(k)
-        res, dt = _instance_golden(synth.serve_instance(p), threads)
-        out.append({"index": k, "kind": p.get("kind", "basket"), "n_tx": p["n_tx"],
-                    "minsup": p["minsup"], "n_itemsets": len(res), "overflow": res.overflow,
-                    "candidates_ascending_support": res.candidates,
-                    "digest": res.digest() if not res.overflow else None,
+        sub = k
+        while True:
+            p = synth.serve_params(k, sub)
+            res, dt = _instance_golden(synth.serve_instance(p), threads)
+            if not res.overflow:
+                break
+            print("request", k, "substream", sub, "exceeds the guard; redrawn", flush=True)
+            sub += synth.GUARD_STRIDE
+        out.append({"index": k, "substream": sub, "kind": p.get("kind", "basket"),
+                    "n_tx": p["n_tx"], "minsup": p["minsup"], "n_itemsets": len(res),
+                    "candidates_ascending_support": res.candidates, "digest": res.digest(),
                     "oracle_seconds": round(dt, 2)})
         print("serve", k, out[-1]["kind"], len(res), round(dt, 2), flush=True)
-    return {"workload": "serve-pool-%d" % n, "instances": out}
+    return {"workload": "serve-pool-%d" % n, "guard_limit": synth.GUARD_LIMIT, "instances": out}
 
 
 def main(argv):

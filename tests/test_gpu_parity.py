@@ -139,6 +139,7 @@ def test_options_invariance(fim, ctx):
     variants = [
         dict(workers=4), dict(workers=64, classes_per_wg=3), dict(flags=fim.FIM_FLAG_NO_ESTIMATE),
         dict(flags=fim.FIM_FLAG_NO_SPLIT), dict(alpha=1.0), dict(alpha=0.05, seed=99),
+        dict(flags=fim.FIM_FLAG_DENSE_ROOT), dict(flags=fim.FIM_FLAG_ALWAYS_ESTIMATE),
         dict(sample_tx=500, sample_fi=1000),
     ]
     for v in variants:
@@ -146,6 +147,26 @@ def test_options_invariance(fim, ctx):
         g = gpu_mine(fim, ctx, db, **v)
         assert_same(g, o, v)
         assert g.stats["candidates"] == o.candidates, v
+
+
+@pytest.mark.parametrize("n_tx,n_items,mlen,minsup", [(20000, 800, 10.0, 40), (9000, 300, 25.0, 60)])
+def test_root_over_covers_equals_whole_rows(fim, ctx, n_tx, n_items, mlen, minsup):
+    # the root class counted over the non-zero words of row i only, and over
+    # whole rows, both against the oracle
+    o_, it, ni = synth.basket(n_tx + n_items, n_tx, n_items, mlen, 2 * n_items, 4.0)
+    db = synth.Database(o_, it, ni, minsup)
+    say("root paths", n_tx, n_items)
+    o = oracle.mine_db(db, threads=4)
+    a = gpu_mine(fim, ctx, db)
+    b = gpu_mine(fim, ctx, db, flags=fim.FIM_FLAG_DENSE_ROOT)
+    assert_same(a, o)
+    assert_same(b, o)
+    assert a.stats["candidates"] == b.stats["candidates"] == o.candidates
+    assert b.stats["root_sparse"] == 0
+    if n_items == 800:  # sparse enough for the cover-projected kernel
+        assert a.stats["root_sparse"] == 1
+    if a.stats["root_sparse"]:
+        assert a.stats["root_pair_words"] < b.stats["root_pair_words"]  # covers skip words
 
 
 def test_max_len(fim, ctx):
@@ -244,12 +265,64 @@ def test_batch_equals_solo_and_oracle(fim, ctx):
         h.close()
 
 
-def test_server_results_same_alone_and_mixed(fim, ctx):
+def test_exploding_estimate_sample_is_abandoned(fim, ctx):
+    # Small instances at a low minimum support: the estimate's sample, drawn
+    # with replacement at the scaled support (at least 2), makes every subset
+    # of a long transaction drawn twice frequent.  Its search must be cut off
+    # (no estimate for that instance) and the real result stay exact.
+    g = _load("batch-256.json")
+    picks = [227, 56, 90, 131]
+    dbs = [synth.batch_instance(synth.batch_params(g["instances"][i]["substream"])) for i in picks]
+    handles = [fim.Database(ctx, d.offsets, d.items, d.n_items) for d in dbs]
+    for i, d, h in zip(picks, dbs, handles):
+        say("exploding sample", i)
+        r = fim.mine(ctx, h, d.minsup, flags=fim.FIM_FLAG_ALWAYS_ESTIMATE)
+        assert oracle.digest(r.offsets, r.items, r.supports) == g["instances"][i]["digest"], i
+    say("exploding samples, batched")
+    res = fim.mine_batch(ctx, handles, [d.minsup for d in dbs], flags=fim.FIM_FLAG_ALWAYS_ESTIMATE)
+    for i, r in zip(picks, res):
+        assert oracle.digest(r.offsets, r.items, r.supports) == g["instances"][i]["digest"], i
+    for h in handles:
+        h.close()
+
+
+def test_max_itemsets_stops_early(fim, ctx):
+    # the whole powerset of 26 items (67 M itemsets) is never enumerated:
+    # the kernel stops once the limit is certain to be exceeded
+    db = synth.from_lists([list(range(26))] * 3, n_items=26, minsup=2)
+    say("max_itemsets early stop")
+    with pytest.raises(fim.FimError) as e:
+        gpu_mine(fim, ctx, db, max_itemsets=100000)
+    assert e.value.status == fim.FIM_E_OUTPUT_LIMIT
+
+
+def test_autotune_settings_do_not_change_results(fim, ctx):
+    dbs = _batch_dbs(4, scale=0.1)
+    handles = [fim.Database(ctx, d.offsets, d.items, d.n_items) for d in dbs]
+    ms = [d.minsup for d in dbs]
+    say("autotune")
+    t = fim.autotune(ctx, handles, ms, reps=1)
+    assert t["tile_words"] in (256, 512, 1024, 2048) and t["classes_per_wg"] in (1, 2, 4)
+    ref = fim.mine_batch(ctx, handles, ms)
+    for tw in (256, 512, 1024, 2048, 3000):
+        for c in (1, 4):
+            got = fim.mine_batch(ctx, handles, ms, tile_words=tw, classes_per_wg=c)
+            for a, b in zip(got, ref):
+                assert_same(a, b, (tw, c))
+                assert a.stats["candidates"] == b.stats["candidates"]
+    for h in handles:
+        h.close()
+
+
+@pytest.mark.parametrize("lanes,max_active,budget", [(1, 3, 0), (3, 4, 0), (2, 64, 1)])
+def test_server_results_same_alone_and_mixed(fim, ctx, lanes, max_active, budget):
     dbs = _batch_dbs(5, scale=0.1)
+    dbs.append(synth.dense_instance(synth.dense_params(9, synth.SERVE_BASE, 1000, 4000)))
     handles = [fim.Database(ctx, d.offsets, d.items, d.n_items) for d in dbs]
     alone = [fim.mine(ctx, h, d.minsup) for d, h in zip(dbs, handles)]
-    say("server")
-    srv = fim.Server(ctx, max_active=3)
+    assert_same(alone[-1], oracle.mine_db(dbs[-1], threads=4), "dense")
+    say("server", lanes, max_active, budget)
+    srv = fim.Server(ctx, max_active=max_active, lanes=lanes, hbm_budget_bytes=budget)
     tickets = [srv.submit(h, d.minsup) for d, h in zip(dbs, handles)]
     tickets += [srv.submit(h, d.minsup) for d, h in zip(dbs[::-1], handles[::-1])]
     got = [srv.wait(t) for t in tickets]
@@ -257,7 +330,9 @@ def test_server_results_same_alone_and_mixed(fim, ctx):
         i = k if k < len(dbs) else len(dbs) - 1 - (k - len(dbs))
         assert_same(r, alone[i], k)
     st = srv.stats()
-    assert st["completed"] == len(tickets) and st["peak_active"] <= 3
+    assert st["completed"] == len(tickets) and st["peak_active"] <= max_active
+    if budget == 1:  # every request is admitted alone
+        assert st["peak_active"] == 1 and st["steps"] == len(tickets)
     srv.close()
     for h in handles:
         h.close()
