@@ -337,7 +337,7 @@ def main(argv=None):
 
     root_ns = float(np.mean([s["root_kernel_ns"] for s in stats]))
     dfs_ns = float(np.mean([s["dfs_kernel_ns"] for s in stats]))
-    root_name = "k_root_sparse" if st["root_sparse"] else "k_root_pairs"
+    root_name = ("k_root_pairs", "k_root_sparse", "k_root_project")[st["root_kernel"]]
     root_tops = 2.0 * st["root_pair_words"] / root_ns / 1e3 if root_ns else 0.0
     dfs_gbs = st["dfs_bytes_algorithmic"] / dfs_ns if dfs_ns else 0.0
     kernels = {

@@ -149,10 +149,23 @@ fim_status fim_minsup_from_relative(uint64_t n_tx, double rel, uint32_t *out_abs
  * 1/20 of the root class's candidate pairs (by default the sample is then
  * skipped: there is no work worth balancing) */
 #define FIM_FLAG_ALWAYS_ESTIMATE 0x8u
-/* count the root class over whole rows even when most of their words are
- * zero (by default the pairs (i, j) are counted over the non-zero words of
- * row i only when that skips at least two thirds of the words) */
+/*
+ * The root class (all pairs of frequent items) has three exact kernels; by
+ * default the one with the least estimated time is used:
+ *  - whole rows: popcount-Gram of the item bitmaps, LDS-tiled (dense data);
+ *  - covers: pair (i, j) counted over the non-zero words of row i only;
+ *  - projected: supp({a, b}) as the number of transactions of the cover of
+ *    a that hold b, walking the frequent items of those transactions (long
+ *    sparse rows: the work is the pairs inside transactions, not the words).
+ * These flags force one of them (the lowest set flag wins).
+ */
 #define FIM_FLAG_DENSE_ROOT 0x10u
+#define FIM_FLAG_ROOT_COVERS 0x20u
+#define FIM_FLAG_ROOT_PROJECT 0x40u
+/* below the root, keep every class's rows at the full database width (by
+ * default a piece of work whose prefix covers at most a quarter of the
+ * transactions builds its rows projected on that cover) */
+#define FIM_FLAG_NO_PROJECT 0x80u
 
 /*
  * Options of a mining call.  A zero field selects its default.
@@ -238,10 +251,12 @@ fim_status fim_mine_batch(fim_ctx *ctx, uint32_t n, const fim_db *const *dbs,
  *  root_kernel_ns   GPU time of the root-class pair kernel (HIP events)
  *  dfs_kernel_ns    GPU time of the persistent depth-first kernel (HIP events)
  *  dfs_bytes_algorithmic  bitmap bytes the depth-first kernel must move:
- *                   every class's sibling rows written once and read once
+ *                   every class's sibling rows (at the width used, full or
+ *                   projected) written once and read once
  *  n_itemsets       frequent itemsets reported
- *  root_sparse      1 if the root class was counted over each row's non-zero
- *                   words (cover-projected kernel), 0 over whole rows
+ *  root_kernel      root-class kernel used: 0 whole rows, 1 covers,
+ *                   2 projected transactions (root_pair_words then counts
+ *                   the pair increments)
  *  In a batch, the kernel times are those of the whole batched launch.
  */
 typedef struct fim_stats {
@@ -261,7 +276,7 @@ typedef struct fim_stats {
     uint64_t dfs_kernel_ns;
     uint64_t dfs_bytes_algorithmic;
     uint64_t n_itemsets;
-    uint64_t root_sparse;
+    uint64_t root_kernel;
 } fim_stats;
 
 /* Number of itemsets and total number of items over all itemsets. */

@@ -39,6 +39,9 @@ FIM_FLAG_ORDER_BY_ID = 0x2
 FIM_FLAG_NO_SPLIT = 0x4
 FIM_FLAG_ALWAYS_ESTIMATE = 0x8
 FIM_FLAG_DENSE_ROOT = 0x10
+FIM_FLAG_ROOT_COVERS = 0x20
+FIM_FLAG_ROOT_PROJECT = 0x40
+FIM_FLAG_NO_PROJECT = 0x80
 
 EXPORTED = [
     "fim_status_str", "fim_last_error", "fim_version", "fim_ctx_create", "fim_ctx_destroy",
@@ -78,7 +81,7 @@ class fim_stats(ctypes.Structure):
         "candidates", "pair_words", "item_supports", "n_frequent_items", "bytes_algorithmic",
         "kernel_ns", "total_ns", "estimate_ns", "n_tasks", "retries", "root_candidates",
         "root_pair_words", "root_kernel_ns", "dfs_kernel_ns", "dfs_bytes_algorithmic",
-        "n_itemsets", "root_sparse")]
+        "n_itemsets", "root_kernel")]
 
 
 class fim_server_config(ctypes.Structure):

@@ -93,6 +93,7 @@ struct fim_db {
     fim_ctx *ctx = nullptr;
     uint64_t n_tx = 0, nnz = 0;
     uint32_t n_item_ids = 0;
+    uint64_t pairs_in_tx = 0;      // sum over transactions of L (L - 1) / 2
     std::vector<uint64_t> h_off;   // canonical CSR (sorted, duplicate-free transactions)
     std::vector<uint32_t> h_items;
     fim::DevBuf d_off, d_items;

@@ -30,7 +30,7 @@ struct InstDesc {
     uint32_t minsup;             // absolute minimum support
     uint32_t max_len;            // longest itemset to report (0 = unlimited)
     uint32_t order_by_id;        // 1: extensions in item-id order instead of support
-    uint32_t pad_;
+    uint32_t project;            // 1: rows of a piece of work may be projected on its prefix's cover
     // itemsets below the first level the instance may report before its
     // remaining work is abandoned (0 = unlimited)
     unsigned long long rec_budget;
@@ -79,6 +79,7 @@ struct InstCounters {
     unsigned long long pair_words;  // words AND-popcounted
     unsigned long long child_rows;  // child bitmaps written
     unsigned long long records;     // itemsets reported (counted when rec_budget > 0)
+    unsigned long long row_words;   // words of sibling rows written (first frames and children)
     uint32_t stop;                  // 1 once records exceeded rec_budget
     uint32_t pad_;
 };
@@ -117,6 +118,18 @@ hipError_t launch_root_pairs(const uint32_t *rows, uint32_t n, uint32_t Wp, uint
 
 // Variant of the persistent kernel for rows of at most max_chunks 128-bit
 // chunks (0 = rows are streamed, 2/4/8 = chunks per lane held in registers).
+hipError_t launch_rank_tx(const uint64_t *off, const uint32_t *items, uint64_t n_tx,
+                          const uint32_t *rank_of_item, uint32_t *rk, uint32_t *len,
+                          hipStream_t stream);
+hipError_t launch_tidlist(const uint64_t *off, const uint32_t *rk, const uint32_t *len,
+                          uint64_t n_tx, const uint64_t *tl_off, uint32_t *fill, uint32_t *tl,
+                          hipStream_t stream);
+void project_tile(uint32_t n, uint32_t *R, uint32_t *J);
+hipError_t launch_root_project(const uint64_t *off, const uint32_t *rk, const uint32_t *len,
+                               const uint32_t *tl, const uint64_t *tl_off, uint32_t n,
+                               uint32_t minsup, uint32_t *pairs, uint64_t cap,
+                               unsigned long long *n_pairs, unsigned long long *work,
+                               hipStream_t stream);
 uint32_t tile_variant(uint32_t tile_words);
 uint32_t dfs_variant(uint32_t max_chunks);
 
@@ -144,6 +157,6 @@ hipError_t launch_dfs(const InstDesc *insts, const Task *tasks, uint64_t n_tasks
                       DfsCounters *ctr, InstCounters *ictr, unsigned long long *don_slots,
                       uint64_t n_slots, uint32_t *don_heap, uint64_t heap_words,
                       uint64_t wait_ticks, unsigned long long *trace, uint32_t variant,
-                      hipStream_t stream);
+                      uint32_t nap_max, hipStream_t stream);
 
 }  // namespace fim

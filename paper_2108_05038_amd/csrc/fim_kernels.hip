@@ -5,6 +5,8 @@
 // two of its covering subsets, appendix "The Eclat algorithm", subsection
 // "Support counting").  No MFMA: the work is bitwise, and most of it is
 // bound by memory or by the integer vector ALU.
+#include <algorithm>
+
 #include "fim_internal.h"
 
 namespace fim {
@@ -367,6 +369,128 @@ __global__ __launch_bounds__(kBlock) void k_root_sparse(
     }
 }
 
+// ------------------------------------------------------------------ a6/a7: root class over projected transactions
+// supp({a, b}) is the number of transactions of the cover T(a) that also
+// hold b, i.e. the support of b in the database projected on T(a).  The
+// transactions are rewritten as ascending lists of frequent ranks
+// (k_rank_tx), every rank lists the transactions that hold it (k_tidlist),
+// and a block counts the pairs (a, b > a) of a few consecutive rows a in
+// LDS: for every transaction of T(a) it walks the ranks after a.  The work
+// is the number of pairs inside the transactions, independent of the
+// bitmap width, which is what makes it the choice for long sparse rows.
+
+// transaction t -> its frequent ranks, ascending, at rk[off[t] ..) and
+// their count in len[t] (insertion sort per thread: transactions are short)
+__global__ __launch_bounds__(kBlock) void k_rank_tx(const uint64_t *__restrict__ off,
+                                                     const uint32_t *__restrict__ items,
+                                                     uint64_t n_tx,
+                                                     const uint32_t *__restrict__ rank_of_item,
+                                                     uint32_t *rk, uint32_t *len) {
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < n_tx; t += stride) {
+        const uint64_t a = off[t], e = off[t + 1];
+        uint32_t L = 0;
+        for (uint64_t p = a; p < e; p++) {
+            const uint32_t r = rank_of_item[items[p]];
+            if (r == kNone) continue;
+            uint64_t q = a + L;
+            while (q > a && rk[q - 1] > r) {
+                rk[q] = rk[q - 1];
+                q--;
+            }
+            rk[q] = r;
+            L++;
+        }
+        len[t] = L;
+    }
+}
+
+// tl[tl_off[r] ..) = the transactions holding rank r (any order)
+__global__ __launch_bounds__(kBlock) void k_tidlist(const uint64_t *__restrict__ off,
+                                                     const uint32_t *__restrict__ rk,
+                                                     const uint32_t *__restrict__ len, uint64_t n_tx,
+                                                     const uint64_t *__restrict__ tl_off,
+                                                     uint32_t *fill, uint32_t *tl) {
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < n_tx; t += stride) {
+        const uint64_t a = off[t];
+        const uint32_t L = len[t];
+        for (uint32_t q = 0; q < L; q++) {
+            const uint32_t r = rk[a + q];
+            const uint32_t pos = atomicAdd(&fill[r], 1u);
+            tl[tl_off[r] + pos] = (uint32_t)t;
+        }
+    }
+}
+
+constexpr uint32_t kProjectMaxRows = 64;
+
+// block (x, y): rows [i0, i0 + R) (x counted from the last, heaviest rows)
+// against partner columns [j0, j0 + J); counters cnt[R][J] in LDS
+__global__ __launch_bounds__(kBlock) void k_root_project(
+    const uint64_t *__restrict__ off, const uint32_t *__restrict__ rk,
+    const uint32_t *__restrict__ len, const uint32_t *__restrict__ tl,
+    const uint64_t *__restrict__ tl_off, uint32_t n, uint32_t R, uint32_t J, uint32_t minsup,
+    uint32_t *pairs, uint64_t cap, unsigned long long *n_pairs, unsigned long long *work) {
+    extern __shared__ uint32_t cnt[];
+    __shared__ uint64_t s_off[kProjectMaxRows + 1];
+    const uint32_t nrb = (n + R - 1) / R;
+    const uint32_t i0 = (nrb - 1 - blockIdx.x) * R, i1 = min(i0 + R, n);
+    const uint32_t j0 = blockIdx.y * J, j1 = min(j0 + J, n);
+    if (j1 <= i0 + 1) return;  // no pair (a, b > a) in this tile (uniform over the block)
+    for (uint32_t e = threadIdx.x; e < R * J; e += kBlock) cnt[e] = 0;
+    for (uint32_t e = threadIdx.x; e <= i1 - i0; e += kBlock) s_off[e] = tl_off[i0 + e];
+    __syncthreads();
+    unsigned long long wk = 0;
+    const uint64_t p1 = s_off[i1 - i0];
+    uint32_t a_rel = 0;
+    for (uint64_t p = s_off[0] + threadIdx.x; p < p1; p += kBlock) {
+        while (s_off[a_rel + 1] <= p) a_rel++;  // p only grows: the row index only grows
+        const uint32_t a = i0 + a_rel;
+        const uint32_t t = tl[p];
+        const uint64_t b0 = off[t];
+        const uint32_t L = len[t];
+        // first position after a, then the first rank >= j0
+        const uint32_t lim = max(a + 1, j0);
+        uint32_t lo = 0, hi = L;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (rk[b0 + mid] < lim) lo = mid + 1;
+            else hi = mid;
+        }
+        uint32_t *row = cnt + a_rel * J;
+        for (uint32_t q = lo; q < L; q++) {
+            const uint32_t b = rk[b0 + q];
+            if (b >= j1) break;
+            atomicAdd(&row[b - j0], 1u);
+            wk++;
+        }
+    }
+    __syncthreads();
+    // frequent pairs of the tile, compacted per wave with one atomic
+    for (uint32_t e0 = 0; e0 < R * J; e0 += kBlock) {
+        const uint32_t e = e0 + threadIdx.x;
+        const uint32_t a = i0 + e / J, b = j0 + e % J;
+        const uint32_t c = e < R * J ? cnt[e] : 0u;
+        const bool ok = e < R * J && a < i1 && b < j1 && b > a && c >= minsup;
+        const uint64_t mask = __ballot(ok);
+        unsigned long long base = 0;
+        if (lane_id() == 0 && mask) base = atomicAdd(n_pairs, (unsigned long long)__popcll(mask));
+        base = shfl_u64(base, 0);
+        if (ok) {
+            const uint64_t pos = base + lanes_below(mask);
+            if (pos < cap) {
+                pairs[3 * pos + 0] = a;
+                pairs[3 * pos + 1] = b;
+                pairs[3 * pos + 2] = c;
+            }
+        }
+    }
+#pragma unroll
+    for (int o = kWave / 2; o >= 1; o >>= 1) wk += __shfl_xor(wk, o, kWave);
+    if (lane_id() == 0 && wk) atomicAdd(work, wk);
+}
+
 // ------------------------------------------------------------------ a5-a8: persistent DFS
 //
 // Every wave is one worker with a private region of `stack_words` words:
@@ -392,13 +516,17 @@ struct Frame {
     uint32_t pad_;
 };
 
+constexpr uint32_t kStageWords = 68;  // words a chunk of 64 projected entries can touch, + slack
+
 struct WaveShared {
     Frame frames[kMaxDepth];
     uint32_t prefix[kMaxDepth + 3];
+    uint32_t stage[4 * kStageWords];  // assembly of projected rows, four at a time
 };
 
 struct WaveStats {
-    unsigned long long candidates, pair_words, child_rows, given, max_k, max_depth;
+    unsigned long long candidates, pair_words, child_rows, given, max_k, max_depth, row_words;
+    unsigned long long rec_pending;  // records not yet added to the instance's count
 };
 
 // per-wave trace record (written when a trace buffer is given)
@@ -430,6 +558,7 @@ struct Donation {
     uint64_t wait_ticks;        // longest wait (wall-clock ticks) before giving up
     uint32_t enabled;
     unsigned long long *trace;  // WaveTrace per wave, or null
+    uint32_t nap_max;           // longest back-off of an idle wave, in naps of ~8000 cycles
 };
 
 // Output of one piece of work goes to chunks of the output arena claimed
@@ -634,59 +763,28 @@ __device__ __forceinline__ bool inst_stopped(const InstDesc &I, InstCounters *ic
 }
 
 template <int CPL>
-__device__ void process_frame(const InstDesc &I, uint32_t inst, uint32_t task, const FrameSrc &src,
+__device__ void process_frame(const InstDesc &I, uint32_t inst, uint32_t task, uint32_t plen,
+                              uint32_t k, uint32_t r_end, uint32_t Wp, uint64_t meta, uint64_t peak0,
                               uint32_t *region, uint64_t S, WaveShared &ws, uint32_t *out,
                               uint64_t out_cap, DfsCounters *ctr, InstCounters *ictr, WaveStats &st,
                               OutChunk &oc, Donation &dn) {
     const uint32_t lane = lane_id();
-    const uint32_t Wp = I.Wp, C = Wp / 4;  // 128-bit chunks per row
-    const uint32_t k = src.k, plen = src.plen;
-    if (src.r_end == 0 || src.r_end >= k || plen == 0 || plen + 2 > kMaxDepth) return;
+    const uint32_t C = Wp / 4;  // 128-bit chunks per row
 
-    // lanes per pair: enough to cover a row's chunks, at most a wave
+    // lanes per pair: about four chunks per lane (their loads in flight at
+    // once), at most a wave; narrow rows put several pairs in one pass
     uint32_t g = 1;
-    while (g < C && g < (uint32_t)kWave) g <<= 1;
+    const uint32_t want = (C + 3) / 4;
+    while (g < want && g < (uint32_t)kWave) g <<= 1;
     const uint32_t ppp = kWave / g;  // pairs per pass
     const uint32_t grp = lane / g, sub = lane % g;
 
-    // first class: rows T(prefix + atom) = T(prefix) AND T(atom), with
-    // T(prefix) the AND of the prefix items' rows (Prepare-Tidlists)
-    const uint64_t prow = plen > 1 ? 1 : 0;  // scratch row for T(prefix)
-    uint64_t meta = S - 3ull * k;
-    if (3ull * k > S || ((uint64_t)k + prow) * Wp > meta) {
-        flag_stack(ctr, ((uint64_t)k + prow) * Wp + 3ull * k);
-        return;
-    }
-    for (uint32_t e = lane; e < k; e += kWave) {
-        region[meta + e] = src.ranks[e];
-        region[meta + k + e] = src.supps[e];
-        region[meta + 2 * k + e] = e;
-    }
-    for (uint32_t q = lane; q < plen; q += kWave) ws.prefix[q] = src.prefix[q];
-    const uint4 *base = reinterpret_cast<const uint4 *>(I.rows + (uint64_t)src.prefix[0] * Wp);
-    if (plen > 1) {
-        uint4 *pr = reinterpret_cast<uint4 *>(region + (uint64_t)k * Wp);
-        and_rows(pr, base,
-                 reinterpret_cast<const uint4 *>(I.rows + (uint64_t)src.prefix[1] * Wp), C, lane);
-        __threadfence_block();
-        for (uint32_t q = 2; q < plen; q++) {
-            and_rows(pr, pr, reinterpret_cast<const uint4 *>(I.rows + (uint64_t)src.prefix[q] * Wp),
-                     C, lane);
-            __threadfence_block();
-        }
-        base = pr;
-    }
-    for (uint32_t e = 0; e < k; e++) {
-        const uint4 *arow = reinterpret_cast<const uint4 *>(I.rows + (uint64_t)src.ranks[e] * Wp);
-        and_rows(reinterpret_cast<uint4 *>(region + (uint64_t)e * Wp), base, arow, C, lane);
-    }
-    __threadfence_block();
-
+    // the first class's rows are region[0, k * Wp), its atom arrays at meta
     int depth = 0;
-    ws.frames[0] = Frame{0u, k, 0u, src.r_end, (uint32_t)meta, k, (uint32_t)S, 0u};
+    ws.frames[0] = Frame{0u, k, 0u, r_end, (uint32_t)meta, k, (uint32_t)S, 0u};
     __builtin_amdgcn_wave_barrier();
-    uint64_t rows_top = (uint64_t)k * Wp;  // the T(prefix) row is no longer needed
-    uint64_t peak = rows_top + prow * Wp + (S - meta);
+    uint64_t rows_top = (uint64_t)k * Wp;
+    uint64_t peak = peak0;
     uint32_t polls = 0, cool = 0, iters = 0;
 
     while (depth >= 0) {
@@ -809,13 +907,20 @@ __device__ void process_frame(const InstDesc &I, uint32_t inst, uint32_t task, c
         const uint32_t len = plen + (uint32_t)depth + 2;
         if (I.max_len == 0 || len <= I.max_len) {
             if (I.rec_budget) {
-                unsigned long long before = 0;
-                if (lane == 0) before = atomicAdd(&ictr[inst].records, (unsigned long long)nf);
-                before = shfl_u64(before, 0);
-                if (before + nf > I.rec_budget) {
-                    // over budget: the instance's remaining work is abandoned
-                    if (lane == 0) atomicOr(&ictr[inst].stop, 1u);
-                    return;
+                // records are added to the instance's count in batches; the
+                // count never exceeds the records really found, so the work
+                // is abandoned only once the budget is certainly exceeded
+                st.rec_pending += nf;
+                if (st.rec_pending >= 4096) {
+                    unsigned long long before = 0;
+                    if (lane == 0) before = atomicAdd(&ictr[inst].records, st.rec_pending);
+                    before = shfl_u64(before, 0);
+                    const unsigned long long now = before + st.rec_pending;
+                    st.rec_pending = 0;
+                    if (now > I.rec_budget) {
+                        if (lane == 0) atomicOr(&ictr[inst].stop, 1u);
+                        return;
+                    }
                 }
             }
             const uint32_t rec = kRecHeader + len;
@@ -885,7 +990,7 @@ __device__ void process_frame(const InstDesc &I, uint32_t inst, uint32_t task, c
                         }
                     }
                 }
-            } else {
+            } else if (g == (uint32_t)kWave) {
                 for (uint32_t c = 0; c < nf; c++) {
                     const uint32_t sr = sorted[2 * sstride + c];
                     const uint4 *row_j =
@@ -893,9 +998,22 @@ __device__ void process_frame(const InstDesc &I, uint32_t inst, uint32_t task, c
                     uint4 *dst = reinterpret_cast<uint4 *>(region + rows_top + (uint64_t)c * Wp);
                     and_rows(dst, row_r, row_j, C, lane);
                 }
+            } else {
+                // narrow rows: ppp children at a time, g lanes each
+                for (uint32_t c0 = 0; c0 < nf; c0 += ppp) {
+                    const uint32_t c = c0 + grp;
+                    if (c < nf) {
+                        const uint32_t sr = sorted[2 * sstride + c];
+                        const uint4 *row_j = reinterpret_cast<const uint4 *>(
+                            region + F.rows_base + (uint64_t)sr * Wp);
+                        uint4 *dst = reinterpret_cast<uint4 *>(region + rows_top + (uint64_t)c * Wp);
+                        for (uint32_t q = sub; q < C; q += g) dst[q] = and4(row_r[q], row_j[q]);
+                    }
+                }
             }
             __threadfence_block();
             st.child_rows += nf;
+            st.row_words += (unsigned long long)nf * Wp;
             ws.frames[depth + 1] = Frame{(uint32_t)rows_top, nf, 0u, nf - 1,
                                          (uint32_t)(sorted - region), sstride, (uint32_t)restore, 0u};
             __builtin_amdgcn_wave_barrier();
@@ -909,28 +1027,223 @@ __device__ void process_frame(const InstDesc &I, uint32_t inst, uint32_t task, c
     if (lane == 0) atomicMax(&ctr->stack_need, (unsigned long long)peak);
 }
 
-// the process_frame variant for the row width of the instance: rows of
-// more than 64 chunks and at most 64 * CPL chunks keep the expanded row in
-// registers, all others stream
+// the bits of v at the set bits of m, packed from bit 0 up
+__device__ __forceinline__ uint32_t pext32(uint32_t v, uint32_t m) {
+    uint32_t r = 0, i = 0;
+    while (m) {
+        const uint32_t b = m & (0u - m);
+        if (v & b) r |= 1u << i;
+        i++;
+        m ^= b;
+    }
+    return r;
+}
+
+// Rows of the first class projected on the cover T(prefix) (see run_frame);
+// false when the wave's region is too small.
+__device__ bool build_projected(const InstDesc &I, const uint32_t *P, uint32_t s,
+                                const uint32_t *ranks, uint32_t k, uint32_t Wq, uint32_t *region,
+                                uint64_t S, uint64_t &low, DfsCounters *ctr, uint32_t *stage) {
+    const uint32_t lane = lane_id();
+    const uint32_t Wf = I.Wp;
+    const uint32_t nzc = min(s, Wf);
+    if (low < 3ull * nzc + (uint64_t)k * Wq) {
+        flag_stack(ctr, (S - low) + 3ull * nzc + (uint64_t)k * Wq);
+        return false;
+    }
+    low -= 3ull * nzc;
+    uint32_t *nzw = region + low, *nzm = nzw + nzc, *nzo = nzm + nzc;
+    // the non-zero words of T(prefix) and where their bits start in the
+    // projected row
+    uint32_t cnt = 0, obase = 0;
+    for (uint32_t b0 = 0; b0 < Wf; b0 += 8 * kWave) {
+        uint32_t xs[8];  // eight words per lane loaded before any is used
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const uint32_t w = b0 + j * kWave + lane;
+            xs[j] = w < Wf ? P[w] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            const uint32_t w = b0 + j * kWave + lane;
+            const uint32_t x = xs[j];
+            const uint64_t mask = __ballot(x != 0u);
+            const uint32_t pc = __popc(x);
+            uint32_t incl = pc;
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const uint32_t v = __shfl_up(incl, off, kWave);
+                if ((int)lane >= off) incl += v;
+            }
+            if (x) {
+                const uint32_t p = cnt + lanes_below(mask);
+                nzw[p] = w;
+                nzm[p] = x;
+                nzo[p] = obase + incl - pc;
+            }
+            cnt += (uint32_t)__popcll(mask);
+            obase += __shfl(incl, kWave - 1, kWave);
+        }
+    }
+    __threadfence_block();
+    // words past the projected bits are zero
+    const uint32_t used = (s + 31) / 32;
+    for (uint32_t e = 0; e < k; e++)
+        for (uint32_t q = used + lane; q < Wq; q += kWave) region[(uint64_t)e * Wq + q] = 0u;
+    // Lanes take 64 consecutive non-zero words of T(prefix) at a time; the
+    // bits of four atoms' rows at those words are packed (pext), ORed into
+    // LDS at their offsets in the projected rows (a chunk spans at most 65
+    // words), and the touched words are written out.  The first word of a
+    // chunk may already hold bits of the previous chunk.
+    uint32_t prev_last = ~0u;
+    for (uint32_t c0 = 0; c0 < cnt; c0 += kWave) {
+        const uint32_t idx = c0 + lane;
+        const bool valid = idx < cnt;
+        const uint32_t w = valid ? nzw[idx] : 0u, m = valid ? nzm[idx] : 0u;
+        const uint32_t o = valid ? nzo[idx] : 0u, nb = __popc(m);
+        const uint32_t q0 = uni(o) >> 5;  // lane 0 always holds an entry
+        const uint32_t lastl = min(cnt - 1 - c0, (uint32_t)kWave - 1);
+        const uint32_t oend = __shfl(o + nb, (int)lastl, kWave);
+        const uint32_t nw = ((oend - 1) >> 5) - q0 + 1;
+        const uint32_t rel = o - q0 * 32, qq = rel >> 5, sh = rel & 31;
+        for (uint32_t e0 = 0; e0 < k; e0 += 4) {
+            const uint32_t ne = min(4u, k - e0);
+            for (uint32_t i = lane; i < 4 * kStageWords; i += kWave) stage[i] = 0u;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            uint32_t x[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                x[j] = (valid && (uint32_t)j < ne) ? I.rows[(uint64_t)ranks[e0 + j] * Wf + w] : 0u;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const uint32_t bits = pext32(x[j] & m, m);
+                if (bits) {
+                    atomicOr(&stage[j * kStageWords + qq], bits << sh);
+                    if (sh && sh + nb > 32) atomicOr(&stage[j * kStageWords + qq + 1], bits >> (32 - sh));
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            for (uint32_t i = lane; i < nw; i += kWave)
+                for (uint32_t j = 0; j < ne; j++) {
+                    uint32_t *dst = region + (uint64_t)(e0 + j) * Wq + q0 + i;
+                    uint32_t v = stage[j * kStageWords + i];
+                    if (i == 0 && q0 == prev_last) v |= *dst;
+                    *dst = v;
+                }
+            wave_mem_wait();  // the next chunk may read its first word back
+            __builtin_amdgcn_wave_barrier();
+        }
+        prev_last = q0 + nw - 1;
+    }
+    return true;
+}
+
+// The first class of a piece of work: its sibling rows T(prefix + atom) for
+// every atom (Prepare-Tidlists), then its depth-first search.  When the
+// cover T(prefix) holds at most a quarter of the row's bits, the rows are
+// built projected on that cover: bit i of a projected row is the row's bit
+// at the i-th transaction of T(prefix).  Every support below the prefix is
+// a popcount of ANDs of such rows, so the results are the same, and the
+// whole subtree works on rows of ceil(supp(prefix) / 32) words.  The
+// process_frame variant is then picked for the width actually used: rows
+// of more than 64 and at most 64 * CPL chunks are held in registers.
 template <int CPL>
 __device__ void run_frame(const InstDesc &I, uint32_t inst, uint32_t task, const FrameSrc &src,
                           uint32_t *region, uint64_t S, WaveShared &ws, uint32_t *out,
                           uint64_t out_cap, DfsCounters *ctr, InstCounters *ictr, WaveStats &st,
                           OutChunk &oc, Donation &dn) {
     if (inst_stopped(I, ictr, inst)) return;
-    const uint32_t C = I.Wp / 4;
+    const uint32_t lane = lane_id();
+    const uint32_t k = src.k, plen = src.plen;
+    if (src.r_end == 0 || src.r_end >= k || plen == 0 || plen + 2 > kMaxDepth) return;
+    const uint32_t Wf = I.Wp, Cf = Wf / 4;
+    if (3ull * k + (uint64_t)k * kRowAlign > S) {
+        flag_stack(ctr, 3ull * k + (uint64_t)k * Wf);
+        return;
+    }
+    const uint64_t meta = S - 3ull * k;
+    for (uint32_t e = lane; e < k; e += kWave) {
+        region[meta + e] = src.ranks[e];
+        region[meta + k + e] = src.supps[e];
+        region[meta + 2 * k + e] = e;
+    }
+    for (uint32_t q = lane; q < plen; q += kWave) ws.prefix[q] = src.prefix[q];
+    // T(prefix): the item's own row, or the AND of the prefix items' rows
+    uint64_t low = meta;  // region[0, low) is free
+    const uint32_t *P = I.rows + (uint64_t)src.prefix[0] * Wf;
+    if (plen > 1) {
+        if (low < Wf) {
+            flag_stack(ctr, (uint64_t)(k + 1) * Wf + 3ull * k);
+            return;
+        }
+        low -= Wf;
+        uint4 *pr = reinterpret_cast<uint4 *>(region + low);
+        and_rows(pr, reinterpret_cast<const uint4 *>(P),
+                 reinterpret_cast<const uint4 *>(I.rows + (uint64_t)src.prefix[1] * Wf), Cf, lane);
+        __threadfence_block();
+        for (uint32_t q = 2; q < plen; q++) {
+            and_rows(pr, pr, reinterpret_cast<const uint4 *>(I.rows + (uint64_t)src.prefix[q] * Wf),
+                     Cf, lane);
+            __threadfence_block();
+        }
+        P = region + low;
+    }
+    // the prefix's support, and the width of rows projected on its cover
+    uint32_t s = 0;
+    {
+        uint32_t w = lane;
+        for (; w + 7 * kWave < Wf; w += 8 * kWave) {  // eight loads in flight
+            uint32_t x[8];
+#pragma unroll
+            for (int j = 0; j < 8; j++) x[j] = P[w + j * kWave];
+#pragma unroll
+            for (int j = 0; j < 8; j++) s += __popc(x[j]);
+        }
+        for (; w < Wf; w += kWave) s += __popc(P[w]);
+    }
+#pragma unroll
+    for (int o = kWave / 2; o >= 1; o >>= 1) s += __shfl_xor(s, o, kWave);
+    s = uni(s);
+    const uint32_t Wq = max(kRowAlign, ((s + 31) / 32 + kRowAlign - 1) / kRowAlign * kRowAlign);
+    uint32_t Wp = Wf;
+    if (I.project && 4ull * Wq <= Wf) {
+        if (!build_projected(I, P, s, src.ranks, k, Wq, region, S, low, ctr, ws.stage)) return;
+        Wp = Wq;
+    } else {
+        if (low < (uint64_t)k * Wf) {
+            flag_stack(ctr, (uint64_t)k * Wf + (S - low));
+            return;
+        }
+        for (uint32_t e = 0; e < k; e++)
+            and_rows(reinterpret_cast<uint4 *>(region + (uint64_t)e * Wf),
+                     reinterpret_cast<const uint4 *>(P),
+                     reinterpret_cast<const uint4 *>(I.rows + (uint64_t)src.ranks[e] * Wf), Cf, lane);
+    }
+    __threadfence_block();
+    st.row_words += (unsigned long long)k * Wp;
+    const uint64_t peak0 = (S - low) + (uint64_t)k * Wp;
+    const uint32_t C = Wp / 4;
     if (CPL > 0 && C > (uint32_t)kWave && C <= (uint32_t)(CPL * kWave))
-        process_frame<CPL>(I, inst, task, src, region, S, ws, out, out_cap, ctr, ictr, st, oc, dn);
+        process_frame<CPL>(I, inst, task, plen, k, src.r_end, Wp, meta, peak0, region, S, ws, out,
+                           out_cap, ctr, ictr, st, oc, dn);
     else
-        process_frame<0>(I, inst, task, src, region, S, ws, out, out_cap, ctr, ictr, st, oc, dn);
+        process_frame<0>(I, inst, task, plen, k, src.r_end, Wp, meta, peak0, region, S, ws, out,
+                         out_cap, ctr, ictr, st, oc, dn);
 }
 
-__device__ __forceinline__ void flush_stats(InstCounters *ictr, uint32_t inst, const WaveStats &st) {
+__device__ __forceinline__ void flush_stats(const InstDesc &I, InstCounters *ictr, uint32_t inst,
+                                            const WaveStats &st) {
     if (lane_id() == 0) {
         InstCounters &ic = ictr[inst];
         if (st.candidates) atomicAdd(&ic.candidates, st.candidates);
         if (st.pair_words) atomicAdd(&ic.pair_words, st.pair_words);
         if (st.child_rows) atomicAdd(&ic.child_rows, st.child_rows);
+        if (st.row_words) atomicAdd(&ic.row_words, st.row_words);
+        if (st.rec_pending &&
+            atomicAdd(&ic.records, st.rec_pending) + st.rec_pending > I.rec_budget)
+            atomicOr(&ic.stop, 1u);
     }
 }
 
@@ -975,7 +1288,7 @@ __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Tas
             const InstDesc &I = insts[T.inst];
             const uint32_t a0 = I.l2_off[T.node], k1 = I.l2_off[T.node + 1] - a0;
             if (T.r0 >= T.r1 || T.r1 >= k1) continue;  // rows with a later atom only
-            WaveStats st{0, 0, 0, 0, 0, 0};
+            WaveStats st{};
             OutChunk oc{kNoChunk, 0u, 0u, 0u, 0u};
             const FrameSrc fs{&tasks[t].node, I.l2_atom + a0 + T.r0, I.l2_supp + a0 + T.r0, 1u,
                               k1 - T.r0, T.r1 - T.r0};
@@ -984,7 +1297,7 @@ __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Tas
                            ictr, st, oc, dn);
             close_chunk(oc, out);
             busy += wall_clock64() - c0;
-            flush_stats(ictr, T.inst, st);
+            flush_stats(I, ictr, T.inst, st);
             note(st);
         }
         wave_mem_wait();  // donations of this task are published before it counts as done
@@ -1019,9 +1332,9 @@ __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Tas
                     if (lane == 0) atomicOr(&ctr->flags, kFlagSpin);
                     break;
                 }
-                // back off: 1, 2, 4 ... 64 naps of about 8000 cycles
+                // back off: 1, 2, 4 ... nap_max naps of about 8000 cycles
                 for (uint32_t q = 0; q < nap; q++) __builtin_amdgcn_s_sleep(127);
-                if (nap < 64) nap <<= 1;
+                if (nap < dn.nap_max) nap <<= 1;
                 continue;
             }
             nap = 1;
@@ -1051,7 +1364,7 @@ __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Tas
                     wave_mem_wait();
                     const InstDesc &I = insts[inst];
                     const FrameSrc fs{copy, copy + pl, copy + pl + kk, pl, kk, re};
-                    WaveStats st{0, 0, 0, 0, 0, 0};
+                    WaveStats st{};
                     OutChunk oc{kNoChunk, 0u, 0u, 0u, 0u};
                     const unsigned long long c0 = wall_clock64();
                     // the frame's own atom arrays go below the copy
@@ -1059,7 +1372,7 @@ __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Tas
                                    stack_words - words, ws, out, out_cap, ctr, ictr, st, oc, dn);
                     close_chunk(oc, out);
                     busy += wall_clock64() - c0;
-                    flush_stats(ictr, inst, st);
+                    flush_stats(I, ictr, inst, st);
                     note(st);
                 } else if (lane == 0) {
                     atomicOr(&ctr->flags, kFlagStackOverflow);
@@ -1164,6 +1477,47 @@ hipError_t launch_root_sparse(const uint32_t *bt, uint32_t np, const uint64_t *n
     return hipGetLastError();
 }
 
+hipError_t launch_rank_tx(const uint64_t *off, const uint32_t *items, uint64_t n_tx,
+                          const uint32_t *rank_of_item, uint32_t *rk, uint32_t *len,
+                          hipStream_t stream) {
+    if (n_tx == 0) return hipSuccess;
+    const uint64_t blocks = std::min<uint64_t>((n_tx + kBlock - 1) / kBlock, 16384);
+    hipLaunchKernelGGL(k_rank_tx, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, off, items, n_tx,
+                       rank_of_item, rk, len);
+    return hipGetLastError();
+}
+
+hipError_t launch_tidlist(const uint64_t *off, const uint32_t *rk, const uint32_t *len,
+                          uint64_t n_tx, const uint64_t *tl_off, uint32_t *fill, uint32_t *tl,
+                          hipStream_t stream) {
+    if (n_tx == 0) return hipSuccess;
+    const uint64_t blocks = std::min<uint64_t>((n_tx + kBlock - 1) / kBlock, 16384);
+    hipLaunchKernelGGL(k_tidlist, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, off, rk, len,
+                       n_tx, tl_off, fill, tl);
+    return hipGetLastError();
+}
+
+// counters of a block: R rows x J columns in 60 KB of LDS
+void project_tile(uint32_t n, uint32_t *R, uint32_t *J) {
+    const uint32_t words = 15360;
+    *J = std::max<uint32_t>(1, std::min<uint32_t>(n, words));
+    *R = std::max<uint32_t>(1, std::min<uint32_t>(kProjectMaxRows, words / *J));
+}
+
+hipError_t launch_root_project(const uint64_t *off, const uint32_t *rk, const uint32_t *len,
+                               const uint32_t *tl, const uint64_t *tl_off, uint32_t n,
+                               uint32_t minsup, uint32_t *pairs, uint64_t cap,
+                               unsigned long long *n_pairs, unsigned long long *work,
+                               hipStream_t stream) {
+    if (n < 2) return hipSuccess;
+    uint32_t R = 0, J = 0;
+    project_tile(n, &R, &J);
+    const dim3 grid((n + R - 1) / R, (n + J - 1) / J);
+    hipLaunchKernelGGL(k_root_project, grid, dim3(kBlock), (size_t)R * J * 4, stream, off, rk, len,
+                       tl, tl_off, n, R, J, minsup, pairs, cap, n_pairs, work);
+    return hipGetLastError();
+}
+
 // row tile in words -> register-resident variant (256 words and wider than
 // 2048 words: streamed)
 uint32_t tile_variant(uint32_t tile_words) {
@@ -1207,11 +1561,12 @@ hipError_t launch_dfs(const InstDesc *insts, const Task *tasks, uint64_t n_tasks
                       uint32_t *out, uint64_t out_cap, DfsCounters *ctr, InstCounters *ictr,
                       unsigned long long *don_slots, uint64_t n_slots, uint32_t *don_heap,
                       uint64_t heap_words, uint64_t wait_ticks, unsigned long long *trace,
-                      uint32_t variant, hipStream_t stream) {
+                      uint32_t variant, uint32_t nap_max, hipStream_t stream) {
     if (n_tasks == 0) return hipSuccess;
     const uint32_t blocks = (n_workers + kWavesPerBlock - 1) / kWavesPerBlock;
     Donation dn{don_slots, don_heap, n_slots, heap_words, wait_ticks,
-                (don_slots && don_heap && n_slots && heap_words) ? 1u : 0u, trace};
+                (don_slots && don_heap && n_slots && heap_words) ? 1u : 0u, trace,
+                nap_max ? nap_max : 64u};
     const uint32_t tpc = tasks_per_claim ? tasks_per_claim : 1u;
     switch (variant) {
         case 2:

@@ -296,6 +296,7 @@ extern "C" fim_status fim_db_create(fim_ctx *ctx, uint64_t n_tx, const uint64_t 
         uint64_t n = std::unique(dst, dst + (b - a)) - dst;
         pos += n;
         db->h_off[t + 1] = pos;
+        db->pairs_in_tx += n * (n ? n - 1 : 0) / 2;
     }
     db->h_items.resize(pos);
     db->ctx = ctx;
@@ -414,11 +415,16 @@ struct Inst {
     std::vector<uint32_t> l2_off, l2_atom, l2_supp;
     DevBuf d_counts, d_rank_of_item, d_item_of_rank, d_rows, d_pairs, d_npairs;
     DevBuf d_l2_off, d_l2_atom, d_l2_supp;
-    // root class over covers: non-zero words per row and the transposed arena
-    bool sparse_root = false;
+    // root-class kernel: 0 whole rows, 1 covers, 2 projected transactions
+    uint32_t root_kind = 0;
+    // covers: non-zero words per row and the transposed arena
     std::vector<uint64_t> nz_off;
     std::vector<uint32_t> nz_cnt;
     DevBuf d_nz_off, d_nz_w, d_nz_m, d_nz_cnt, d_bt;
+    // projected: ranked transactions, tid lists, pair increments
+    std::vector<uint64_t> tl_off;
+    DevBuf d_rk, d_len, d_tl, d_tl_off, d_fill, d_work;
+    unsigned long long project_work = 0;
     fim_stats st{};
     uint64_t first_class_rows = 0;  // sum of atoms over first-level classes with >= 2 atoms
 };
@@ -556,16 +562,57 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         ENSURE(I.d_pairs, ctx, cap * 12);
         ENSURE(I.d_npairs, ctx, 8);
         HIPCHK(launch_fill_u32(I.d_npairs.as<uint32_t>(), 2, 0u, s));
-        // Root class over the covers of its prefixes when that skips most
-        // words: row i has at most min(supp_i, W) non-zero words, so the
-        // pair-words to count are bounded by sum_i min(supp_i, W)(n - 1 - i)
+        // Root-class kernel by estimated time (picoseconds per unit measured
+        // on MI355X): whole rows cost all * W pair-words; covers at most
+        // sum_i min(supp_i, W)(n - 1 - i) pair-words (row i has at most
+        // min(supp_i, W) non-zero words), each a cached 4-byte load; the
+        // projected count one LDS increment per pair inside a transaction
+        // (bounded by the pairs over all items) plus its set-up.
         const uint32_t n = I.n_freq;
         double bound = 0.0;
         for (uint32_t r = 0; r < n; r++)
             bound += (double)std::min<uint32_t>(I.supp_of_rank[r], I.W) * (double)(n - 1 - r);
-        I.sparse_root = !(opts.flags & FIM_FLAG_DENSE_ROOT) && n >= 64 && n <= 65535 &&
-                        3.0 * bound < (double)all * (double)I.W;
-        if (I.sparse_root) {
+        const double t_rows = 0.075 * (double)all * (double)I.W;
+        const double t_covers = n >= 64 && n <= 65535 ? 0.75 * bound + 1.5e5 : 1e300;
+        const double t_project = I.db->n_tx < (1ull << 32)
+                                     ? 20.0 * (double)I.db->pairs_in_tx + 6.0 * (double)I.db->nnz + 1.5e5
+                                     : 1e300;
+        if (opts.flags & FIM_FLAG_DENSE_ROOT) I.root_kind = 0;
+        else if (opts.flags & FIM_FLAG_ROOT_COVERS) I.root_kind = n <= 65535 ? 1 : 0;
+        else if (opts.flags & FIM_FLAG_ROOT_PROJECT) I.root_kind = I.db->n_tx < (1ull << 32) ? 2 : 0;
+        else if (t_project <= t_covers && t_project < t_rows) I.root_kind = 2;
+        else if (t_covers < t_rows) I.root_kind = 1;
+        else I.root_kind = 0;
+        if (I.root_kind == 2) {
+            // tid lists of the ranks: CSR offsets from the item supports
+            I.tl_off.assign(n + 1, 0);
+            for (uint32_t r = 0; r < n; r++) I.tl_off[r + 1] = I.tl_off[r] + I.supp_of_rank[r];
+            ENSURE(I.d_rk, ctx, std::max<uint64_t>(I.db->nnz, 1) * 4);
+            ENSURE(I.d_len, ctx, std::max<uint64_t>(I.db->n_tx, 1) * 4);
+            ENSURE(I.d_tl, ctx, std::max<uint64_t>(I.tl_off[n], 1) * 4);
+            ENSURE(I.d_tl_off, ctx, (n + 1) * 8);
+            ENSURE(I.d_fill, ctx, (size_t)n * 4 + 8);
+            ENSURE(I.d_work, ctx, 8);
+            HIPCHK(hipMemcpyAsync(I.d_tl_off.as<void>(), I.tl_off.data(), (n + 1) * 8,
+                                  hipMemcpyHostToDevice, s));
+            HIPCHK(launch_fill_u32(I.d_fill.as<uint32_t>(), n + 2, 0u, s));
+            HIPCHK(launch_fill_u32(I.d_work.as<uint32_t>(), 2, 0u, s));
+            HIPCHK(launch_rank_tx(I.db->d_off.as<uint64_t>(), I.db->d_items.as<uint32_t>(),
+                                  I.db->n_tx, I.d_rank_of_item.as<uint32_t>(), I.d_rk.as<uint32_t>(),
+                                  I.d_len.as<uint32_t>(), s));
+            HIPCHK(launch_tidlist(I.db->d_off.as<uint64_t>(), I.d_rk.as<uint32_t>(),
+                                  I.d_len.as<uint32_t>(), I.db->n_tx, I.d_tl_off.as<uint64_t>(),
+                                  I.d_fill.as<uint32_t>(), I.d_tl.as<uint32_t>(), s));
+            HIPCHK(hipEventRecord(rev[2 * q], s));
+            HIPCHK(launch_root_project(I.db->d_off.as<uint64_t>(), I.d_rk.as<uint32_t>(),
+                                       I.d_len.as<uint32_t>(), I.d_tl.as<uint32_t>(),
+                                       I.d_tl_off.as<uint64_t>(), n, I.minsup,
+                                       I.d_pairs.as<uint32_t>(), cap,
+                                       I.d_npairs.as<unsigned long long>(),
+                                       I.d_work.as<unsigned long long>(), s));
+            HIPCHK(hipEventRecord(rev[2 * q + 1], s));
+            HIPCHK(hipMemcpyAsync(&I.project_work, I.d_work.as<void>(), 8, hipMemcpyDeviceToHost, s));
+        } else if (I.root_kind == 1) {
             I.nz_off.assign(n + 1, 0);
             for (uint32_t r = 0; r < n; r++)
                 I.nz_off[r + 1] = I.nz_off[r] + std::min<uint32_t>(I.supp_of_rank[r], I.W);
@@ -618,7 +665,14 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         if (I.n_pairs > cap) {  // rerun with room for every frequent pair
             ENSURE(I.d_pairs, ctx, I.n_pairs * 12);
             HIPCHK(launch_fill_u32(I.d_npairs.as<uint32_t>(), 2, 0u, s));
-            if (I.sparse_root)
+            if (I.root_kind == 2)
+                HIPCHK(launch_root_project(I.db->d_off.as<uint64_t>(), I.d_rk.as<uint32_t>(),
+                                           I.d_len.as<uint32_t>(), I.d_tl.as<uint32_t>(),
+                                           I.d_tl_off.as<uint64_t>(), I.n_freq, I.minsup,
+                                           I.d_pairs.as<uint32_t>(), I.n_pairs,
+                                           I.d_npairs.as<unsigned long long>(),
+                                           I.d_work.as<unsigned long long>(), s));
+            else if (I.root_kind == 1)
                 HIPCHK(launch_root_sparse(I.d_bt.as<uint32_t>(), (uint32_t)((I.n_freq + 3) / 4 * 4),
                                           I.d_nz_off.as<uint64_t>(), I.d_nz_cnt.as<uint32_t>(),
                                           I.d_nz_w.as<uint32_t>(), I.d_nz_m.as<uint32_t>(),
@@ -636,7 +690,13 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                                   hipMemcpyDeviceToHost, s));
         I.st.candidates = all;
         I.st.root_candidates = all;
-        if (I.sparse_root) {
+        I.st.root_kernel = I.root_kind;
+        if (I.root_kind == 2) {
+            // increments: the pairs inside the transactions; bytes: every
+            // transaction of T(a) read for each frequent a, the tid lists once
+            I.st.root_pair_words = I.project_work;
+            I.st.bytes_algorithmic = 4 * (I.project_work + 2 * I.tl_off[I.n_freq]);
+        } else if (I.root_kind == 1) {
             // words counted: row i's cover words against every later row;
             // bytes: each row's non-zero words (word + mask) and the
             // transposed arena read once
@@ -647,7 +707,6 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             }
             I.st.root_pair_words = pw;
             I.st.bytes_algorithmic = 8 * nzt + (uint64_t)I.n_freq * I.W * 4;
-            I.st.root_sparse = 1;
         } else {
             I.st.root_pair_words = all * I.W;
             I.st.bytes_algorithmic = (uint64_t)I.n_freq * I.W * 4;
@@ -672,6 +731,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
     n_workers = std::max<uint32_t>(4, (n_workers + 3) / 4 * 4);
     std::vector<Task> tasks;
     uint64_t est_out_words = 0;
+    bool deep_work = false;  // some instance has much work below its root class
     if (deep) {
         const auto t_plan = clk::now();
         std::vector<PlanInput> pin(n_inst);
@@ -697,6 +757,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             }
             const uint64_t root = (uint64_t)I.n_freq * (I.n_freq ? I.n_freq - 1 : 0) / 2;
             pin[q].estimate = (opts.flags & FIM_FLAG_ALWAYS_ESTIMATE) || 20 * below >= root;
+            deep_work = deep_work || 20 * below >= root;
         }
         fim_status ps = plan_tasks(ctx, pin, opts, n_workers, tasks, nullptr, &est_out_words);
         if (ps != FIM_OK) return ps;
@@ -753,6 +814,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             D.minsup = I.minsup;
             D.max_len = opts.max_len;
             D.order_by_id = by_id ? 1u : 0u;
+            D.project = (opts.flags & FIM_FLAG_NO_PROJECT) ? 0u : 1u;
             // A sample drawn with replacement at a small scaled support can
             // make every subset of a repeatedly drawn long transaction
             // frequent; its search is abandoned past a fixed budget (the
@@ -796,6 +858,13 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             int clk_khz = 0;
             (void)hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, ctx->device);
             const uint64_t wait_ticks = (uint64_t)(clk_khz > 0 ? clk_khz : 100000) * 60000ull;
+            // Longest back-off of an idle wave.  Idle waves poll counters the
+            // busy waves update; with much work below the root, polling
+            // often slows those updates more than it speeds up hand-overs,
+            // while a short run mostly waits for its last sleepers to wake.
+            // (FIM_NAP_MAX overrides, for tuning.)
+            uint32_t nap_max = deep_work ? 64 : 16;
+            if (const char *e = getenv("FIM_NAP_MAX")) nap_max = (uint32_t)std::max(1, atoi(e));
             if (tr.on) {
                 ENSURE(d_trace, ctx, (size_t)workers * 64);
                 HIPCHK(launch_fill_u32(d_trace.as<uint32_t>(), (uint64_t)workers * 16, 0u, s));
@@ -822,7 +891,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                                            n_slots, n_slots ? d_heap.as<uint32_t>() : nullptr,
                                            heap_words, wait_ticks,
                                            tr.on ? d_trace.as<unsigned long long>() : nullptr,
-                                           variant, s);
+                                           variant, nap_max, s);
                 hipError_t ce = hipStreamEndCapture(s, &g);
                 if (le != hipSuccess || ce != hipSuccess)
                     return set_error(FIM_E_DEVICE, std::string("graph capture: ") +
@@ -840,7 +909,8 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                                   out_cap, d_ctr.as<DfsCounters>(), d_ictr.as<InstCounters>(),
                                   n_slots ? d_slots.as<unsigned long long>() : nullptr, n_slots,
                                   n_slots ? d_heap.as<uint32_t>() : nullptr, heap_words, wait_ticks,
-                                  tr.on ? d_trace.as<unsigned long long>() : nullptr, variant, s));
+                                  tr.on ? d_trace.as<unsigned long long>() : nullptr, variant, nap_max,
+                                  s));
             }
             HIPCHK(hipEventRecord(ev1, s));
             HIPCHK(hipMemcpyAsync(&ctr, d_ctr.as<void>(), sizeof(ctr), hipMemcpyDeviceToHost, s));
@@ -931,8 +1001,9 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                 }
         I.st.candidates += ictr[q].candidates;
         I.st.pair_words += ictr[q].pair_words;
-        I.st.dfs_bytes_algorithmic =
-            (uint64_t)I.W * 4 * (2 * I.first_class_rows + 2 * ictr[q].child_rows);
+        // every sibling row (of a first class or a child class, full width
+        // or projected) written once and read once
+        I.st.dfs_bytes_algorithmic = 8 * ictr[q].row_words;
         I.st.bytes_algorithmic += I.st.dfs_bytes_algorithmic;
         I.st.dfs_kernel_ns = (uint64_t)(dfs_ms * 1e6);
         I.st.kernel_ns += I.st.dfs_kernel_ns;

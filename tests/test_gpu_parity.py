@@ -140,6 +140,7 @@ def test_options_invariance(fim, ctx):
         dict(workers=4), dict(workers=64, classes_per_wg=3), dict(flags=fim.FIM_FLAG_NO_ESTIMATE),
         dict(flags=fim.FIM_FLAG_NO_SPLIT), dict(alpha=1.0), dict(alpha=0.05, seed=99),
         dict(flags=fim.FIM_FLAG_DENSE_ROOT), dict(flags=fim.FIM_FLAG_ALWAYS_ESTIMATE),
+        dict(flags=fim.FIM_FLAG_NO_PROJECT), dict(flags=fim.FIM_FLAG_NO_PROJECT, workers=8),
         dict(sample_tx=500, sample_fi=1000),
     ]
     for v in variants:
@@ -149,24 +150,52 @@ def test_options_invariance(fim, ctx):
         assert g.stats["candidates"] == o.candidates, v
 
 
-@pytest.mark.parametrize("n_tx,n_items,mlen,minsup", [(20000, 800, 10.0, 40), (9000, 300, 25.0, 60)])
-def test_root_over_covers_equals_whole_rows(fim, ctx, n_tx, n_items, mlen, minsup):
-    # the root class counted over the non-zero words of row i only, and over
-    # whole rows, both against the oracle
+@pytest.mark.parametrize("n_tx,n_items,mlen,minsup", [
+    (20000, 800, 10.0, 40),   # sparse rows: covers or projected transactions by default
+    (9000, 300, 25.0, 60),    # denser rows
+    (40000, 20000, 6.0, 4),   # more frequent items than one LDS tile of counters
+])
+def test_root_kernels_agree(fim, ctx, n_tx, n_items, mlen, minsup):
+    # the three exact root-class kernels, forced in turn and by default,
+    # against the oracle
     o_, it, ni = synth.basket(n_tx + n_items, n_tx, n_items, mlen, 2 * n_items, 4.0)
     db = synth.Database(o_, it, ni, minsup)
-    say("root paths", n_tx, n_items)
+    say("root kernels", n_tx, n_items)
     o = oracle.mine_db(db, threads=4)
-    a = gpu_mine(fim, ctx, db)
-    b = gpu_mine(fim, ctx, db, flags=fim.FIM_FLAG_DENSE_ROOT)
-    assert_same(a, o)
-    assert_same(b, o)
-    assert a.stats["candidates"] == b.stats["candidates"] == o.candidates
-    assert b.stats["root_sparse"] == 0
-    if n_items == 800:  # sparse enough for the cover-projected kernel
-        assert a.stats["root_sparse"] == 1
-    if a.stats["root_sparse"]:
-        assert a.stats["root_pair_words"] < b.stats["root_pair_words"]  # covers skip words
+    runs = {"default": gpu_mine(fim, ctx, db)}
+    for name, flag, kind in (("rows", fim.FIM_FLAG_DENSE_ROOT, 0),
+                             ("covers", fim.FIM_FLAG_ROOT_COVERS, 1),
+                             ("project", fim.FIM_FLAG_ROOT_PROJECT, 2)):
+        r = gpu_mine(fim, ctx, db, flags=flag)
+        if n_items <= 65535 or kind != 1:
+            assert r.stats["root_kernel"] == kind, name
+        runs[name] = r
+    for name, r in runs.items():
+        assert_same(r, o, name)
+        assert r.stats["candidates"] == o.candidates, name
+    # covers skip words of whole rows
+    assert runs["covers"].stats["root_pair_words"] < runs["rows"].stats["root_pair_words"]
+    # classes below the root on rows projected on their prefix's cover, or not
+    full = gpu_mine(fim, ctx, db, flags=fim.FIM_FLAG_NO_PROJECT)
+    assert_same(full, o, "no projection")
+    assert full.stats["candidates"] == o.candidates
+    d, f = runs["default"].stats, full.stats
+    if f["pair_words"] > f["root_pair_words"]:  # there is work below the root
+        assert d["pair_words"] - d["root_pair_words"] < f["pair_words"] - f["root_pair_words"]
+
+
+def test_projection_with_work_sharing(fim, ctx):
+    # few workers and a skewed database: donated classes (prefixes of two or
+    # more items) are rebuilt projected on their own covers
+    o_, it, ni = synth.basket(99, 30000, 400, 18.0, 300, 7.0)
+    db = synth.Database(o_, it, ni, 60)
+    say("projection + donations")
+    o = oracle.mine_db(db, threads=8)
+    assert len(o) > 20000
+    for v in (dict(workers=4), dict(workers=16, flags=fim.FIM_FLAG_NO_SPLIT), dict()):
+        g = gpu_mine(fim, ctx, db, **v)
+        assert_same(g, o, v)
+        assert g.stats["candidates"] == o.candidates, v
 
 
 def test_max_len(fim, ctx):
