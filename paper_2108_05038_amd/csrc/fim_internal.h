@@ -34,6 +34,9 @@ struct InstDesc {
     // itemsets below the first level the instance may report before its
     // remaining work is abandoned (0 = unlimited)
     unsigned long long rec_budget;
+    // ascending transaction ids of every rank (tl[tl_off[r] ..)), or null
+    const uint32_t *tl;
+    const uint64_t *tl_off;
 };
 
 // One unit of work of the persistent kernel: rows [r0, r1) of the
@@ -121,9 +124,8 @@ hipError_t launch_root_pairs(const uint32_t *rows, uint32_t n, uint32_t Wp, uint
 hipError_t launch_rank_tx(const uint64_t *off, const uint32_t *items, uint64_t n_tx,
                           const uint32_t *rank_of_item, uint32_t *rk, uint32_t *len,
                           hipStream_t stream);
-hipError_t launch_tidlist(const uint64_t *off, const uint32_t *rk, const uint32_t *len,
-                          uint64_t n_tx, const uint64_t *tl_off, uint32_t *fill, uint32_t *tl,
-                          hipStream_t stream);
+hipError_t launch_tidlist(const uint32_t *rows, uint32_t n, uint32_t Wp, const uint64_t *tl_off,
+                          uint32_t *tl, hipStream_t stream);
 void project_tile(uint32_t n, uint32_t *R, uint32_t *J);
 hipError_t launch_root_project(const uint64_t *off, const uint32_t *rk, const uint32_t *len,
                                const uint32_t *tl, const uint64_t *tl_off, uint32_t n,

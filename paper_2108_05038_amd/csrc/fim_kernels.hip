@@ -373,53 +373,75 @@ __global__ __launch_bounds__(kBlock) void k_root_sparse(
 // supp({a, b}) is the number of transactions of the cover T(a) that also
 // hold b, i.e. the support of b in the database projected on T(a).  The
 // transactions are rewritten as ascending lists of frequent ranks
-// (k_rank_tx), every rank lists the transactions that hold it (k_tidlist),
+// (k_rank_tx), every rank lists the transactions that hold it (k_tidlist,
+// from the bitmap rows),
 // and a block counts the pairs (a, b > a) of a few consecutive rows a in
 // LDS: for every transaction of T(a) it walks the ranks after a.  The work
 // is the number of pairs inside the transactions, independent of the
 // bitmap width, which is what makes it the choice for long sparse rows.
 
 // transaction t -> its frequent ranks, ascending, at rk[off[t] ..) and
-// their count in len[t] (insertion sort per thread: transactions are short)
+// their count in len[t].  One wave per transaction: every lane holds one
+// item's rank and finds its place by counting the smaller ranks (the ranks
+// of one transaction are distinct); longer transactions go 64 at a time.
 __global__ __launch_bounds__(kBlock) void k_rank_tx(const uint64_t *__restrict__ off,
                                                      const uint32_t *__restrict__ items,
                                                      uint64_t n_tx,
                                                      const uint32_t *__restrict__ rank_of_item,
                                                      uint32_t *rk, uint32_t *len) {
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < n_tx; t += stride) {
-        const uint64_t a = off[t], e = off[t + 1];
-        uint32_t L = 0;
-        for (uint64_t p = a; p < e; p++) {
-            const uint32_t r = rank_of_item[items[p]];
-            if (r == kNone) continue;
-            uint64_t q = a + L;
-            while (q > a && rk[q - 1] > r) {
-                rk[q] = rk[q - 1];
-                q--;
+    const uint32_t lane = lane_id();
+    const uint64_t waves = (uint64_t)gridDim.x * kWavesPerBlock;
+    for (uint64_t t = (uint64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; t < n_tx;
+         t += waves) {
+        const uint64_t a = off[t];
+        const uint32_t L = (uint32_t)(off[t + 1] - a);
+        uint32_t kept = 0;
+        for (uint32_t c0 = 0; c0 < L; c0 += kWave) {
+            const uint32_t r = c0 + lane < L ? rank_of_item[items[a + c0 + lane]] : kNone;
+            // place among all frequent ranks of the transaction
+            uint32_t pos = 0;
+            for (uint32_t d0 = 0; d0 < L; d0 += kWave) {
+                const uint32_t rd = d0 == c0 ? r
+                                             : (d0 + lane < L ? rank_of_item[items[a + d0 + lane]] : kNone);
+                const uint32_t cnt = min(L - d0, (uint32_t)kWave);
+                for (uint32_t j = 0; j < cnt; j++) pos += __shfl(rd, (int)j, kWave) < r ? 1u : 0u;
             }
-            rk[q] = r;
-            L++;
+            if (r != kNone) rk[a + pos] = r;
+            kept += (uint32_t)__popcll(__ballot(r != kNone));
         }
-        len[t] = L;
+        if (lane == 0) len[t] = kept;
     }
 }
 
-// tl[tl_off[r] ..) = the transactions holding rank r (any order)
-__global__ __launch_bounds__(kBlock) void k_tidlist(const uint64_t *__restrict__ off,
-                                                     const uint32_t *__restrict__ rk,
-                                                     const uint32_t *__restrict__ len, uint64_t n_tx,
-                                                     const uint64_t *__restrict__ tl_off,
-                                                     uint32_t *fill, uint32_t *tl) {
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < n_tx; t += stride) {
-        const uint64_t a = off[t];
-        const uint32_t L = len[t];
-        for (uint32_t q = 0; q < L; q++) {
-            const uint32_t r = rk[a + q];
-            const uint32_t pos = atomicAdd(&fill[r], 1u);
-            tl[tl_off[r] + pos] = (uint32_t)t;
+// tl[tl_off[r] ..) = the transactions holding rank r, ascending: the set
+// bits of row r, one wave per row, compacted with ballot/mbcnt
+__global__ __launch_bounds__(kBlock) void k_tidlist(const uint32_t *__restrict__ rows, uint32_t n,
+                                                     uint32_t Wp, const uint64_t *__restrict__ tl_off,
+                                                     uint32_t *tl) {
+    const uint32_t r = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    if (r >= n) return;
+    const uint32_t lane = lane_id();
+    const uint32_t *row = rows + (uint64_t)r * Wp;
+    uint64_t pos = tl_off[r];
+    const uint64_t end = tl_off[r + 1];
+    for (uint32_t w0 = 0; w0 < Wp; w0 += kWave) {
+        uint32_t x = w0 + lane < Wp ? row[w0 + lane] : 0u;
+        // lanes emit their word's bits in order; the wave's total moves pos
+        const uint32_t pc = __popc(x);
+        uint32_t incl = pc;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t v = __shfl_up(incl, off, kWave);
+            if ((int)lane >= off) incl += v;
         }
+        uint64_t p = pos + incl - pc;
+        while (x) {
+            const uint32_t b = __ffs(x) - 1;
+            if (p < end) tl[p] = (w0 + lane) * 32 + b;
+            p++;
+            x &= x - 1;
+        }
+        pos += __shfl(incl, kWave - 1, kWave);
     }
 }
 
@@ -1170,8 +1192,55 @@ __device__ void run_frame(const InstDesc &I, uint32_t inst, uint32_t task, const
         region[meta + 2 * k + e] = e;
     }
     for (uint32_t q = lane; q < plen; q += kWave) ws.prefix[q] = src.prefix[q];
-    // T(prefix): the item's own row, or the AND of the prefix items' rows
     uint64_t low = meta;  // region[0, low) is free
+    // One-item prefix with its transaction list at hand: projected row e
+    // holds bit i = [the i-th transaction of T(prefix) holds atom e], 64 bits
+    // per ballot
+    if (plen == 1 && I.tl != nullptr) {
+        const uint64_t t0 = I.tl_off[src.prefix[0]];
+        const uint32_t s = uni((uint32_t)(I.tl_off[src.prefix[0] + 1] - t0));
+        const uint32_t Wq = max(kRowAlign, ((s + 31) / 32 + kRowAlign - 1) / kRowAlign * kRowAlign);
+        if (I.project && 4ull * Wq <= Wf) {
+            if (low < (uint64_t)k * Wq) {
+                flag_stack(ctr, (S - low) + (uint64_t)k * Wq);
+                return;
+            }
+            const uint32_t *tids = I.tl + t0;
+            const uint32_t filled = (s + 63) / 64 * 2;  // words the ballots write
+            for (uint32_t e = 0; e < k; e++)
+                for (uint32_t q = filled + lane; q < Wq; q += kWave) region[(uint64_t)e * Wq + q] = 0u;
+            for (uint32_t i0 = 0; i0 < s; i0 += kWave) {
+                const bool in = i0 + lane < s;
+                const uint32_t t = in ? tids[i0 + lane] : 0u;
+                const uint32_t tw = t >> 5, tb = t & 31;
+                for (uint32_t e0 = 0; e0 < k; e0 += 4) {
+                    uint32_t x[4];
+#pragma unroll
+                    for (int j = 0; j < 4; j++)
+                        x[j] = (in && e0 + j < k) ? I.rows[(uint64_t)src.ranks[e0 + j] * Wf + tw] : 0u;
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        const uint64_t bits = __ballot((x[j] >> tb) & 1u);
+                        if (e0 + j < k && lane < 2)
+                            region[(uint64_t)(e0 + j) * Wq + i0 / 32 + lane] =
+                                lane == 0 ? (uint32_t)bits : (uint32_t)(bits >> 32);
+                    }
+                }
+            }
+            __threadfence_block();
+            st.row_words += (unsigned long long)k * Wq;
+            const uint64_t peak0 = (S - low) + (uint64_t)k * Wq;
+            const uint32_t C = Wq / 4;
+            if (CPL > 0 && C > (uint32_t)kWave && C <= (uint32_t)(CPL * kWave))
+                process_frame<CPL>(I, inst, task, plen, k, src.r_end, Wq, meta, peak0, region, S, ws,
+                                   out, out_cap, ctr, ictr, st, oc, dn);
+            else
+                process_frame<0>(I, inst, task, plen, k, src.r_end, Wq, meta, peak0, region, S, ws,
+                                 out, out_cap, ctr, ictr, st, oc, dn);
+            return;
+        }
+    }
+    // T(prefix): the item's own row, or the AND of the prefix items' rows
     const uint32_t *P = I.rows + (uint64_t)src.prefix[0] * Wf;
     if (plen > 1) {
         if (low < Wf) {
@@ -1481,19 +1550,17 @@ hipError_t launch_rank_tx(const uint64_t *off, const uint32_t *items, uint64_t n
                           const uint32_t *rank_of_item, uint32_t *rk, uint32_t *len,
                           hipStream_t stream) {
     if (n_tx == 0) return hipSuccess;
-    const uint64_t blocks = std::min<uint64_t>((n_tx + kBlock - 1) / kBlock, 16384);
+    const uint64_t blocks = std::min<uint64_t>((n_tx + kWavesPerBlock - 1) / kWavesPerBlock, 65536);
     hipLaunchKernelGGL(k_rank_tx, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, off, items, n_tx,
                        rank_of_item, rk, len);
     return hipGetLastError();
 }
 
-hipError_t launch_tidlist(const uint64_t *off, const uint32_t *rk, const uint32_t *len,
-                          uint64_t n_tx, const uint64_t *tl_off, uint32_t *fill, uint32_t *tl,
-                          hipStream_t stream) {
-    if (n_tx == 0) return hipSuccess;
-    const uint64_t blocks = std::min<uint64_t>((n_tx + kBlock - 1) / kBlock, 16384);
-    hipLaunchKernelGGL(k_tidlist, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, off, rk, len,
-                       n_tx, tl_off, fill, tl);
+hipError_t launch_tidlist(const uint32_t *rows, uint32_t n, uint32_t Wp, const uint64_t *tl_off,
+                          uint32_t *tl, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tidlist, dim3((n + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock), 0,
+                       stream, rows, n, Wp, tl_off, tl);
     return hipGetLastError();
 }
 

@@ -423,7 +423,7 @@ struct Inst {
     DevBuf d_nz_off, d_nz_w, d_nz_m, d_nz_cnt, d_bt;
     // projected: ranked transactions, tid lists, pair increments
     std::vector<uint64_t> tl_off;
-    DevBuf d_rk, d_len, d_tl, d_tl_off, d_fill, d_work;
+    DevBuf d_rk, d_len, d_tl, d_tl_off, d_work;
     unsigned long long project_work = 0;
     fim_stats st{};
     uint64_t first_class_rows = 0;  // sum of atoms over first-level classes with >= 2 atoms
@@ -583,26 +583,33 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         else if (t_project <= t_covers && t_project < t_rows) I.root_kind = 2;
         else if (t_covers < t_rows) I.root_kind = 1;
         else I.root_kind = 0;
-        if (I.root_kind == 2) {
-            // tid lists of the ranks: CSR offsets from the item supports
+        // Ascending transaction lists of the ranks (the set bits of their
+        // rows), used by the projected root kernel and by pieces of work
+        // whose rows are projected on a one-item prefix's cover
+        uint32_t min_supp = ~0u;
+        for (uint32_t r = 0; r < n; r++) min_supp = std::min(min_supp, I.supp_of_rank[r]);
+        const bool lists = I.root_kind == 2 ||
+                           (!(opts.flags & FIM_FLAG_NO_PROJECT) && n >= 3 &&
+                            (opts.max_len == 0 || opts.max_len >= 3) &&
+                            4ull * min_supp <= I.db->n_tx && I.db->n_tx < (1ull << 32));
+        if (lists) {
             I.tl_off.assign(n + 1, 0);
             for (uint32_t r = 0; r < n; r++) I.tl_off[r + 1] = I.tl_off[r] + I.supp_of_rank[r];
-            ENSURE(I.d_rk, ctx, std::max<uint64_t>(I.db->nnz, 1) * 4);
-            ENSURE(I.d_len, ctx, std::max<uint64_t>(I.db->n_tx, 1) * 4);
             ENSURE(I.d_tl, ctx, std::max<uint64_t>(I.tl_off[n], 1) * 4);
             ENSURE(I.d_tl_off, ctx, (n + 1) * 8);
-            ENSURE(I.d_fill, ctx, (size_t)n * 4 + 8);
-            ENSURE(I.d_work, ctx, 8);
             HIPCHK(hipMemcpyAsync(I.d_tl_off.as<void>(), I.tl_off.data(), (n + 1) * 8,
                                   hipMemcpyHostToDevice, s));
-            HIPCHK(launch_fill_u32(I.d_fill.as<uint32_t>(), n + 2, 0u, s));
+            HIPCHK(launch_tidlist(I.d_rows.as<uint32_t>(), n, I.Wp, I.d_tl_off.as<uint64_t>(),
+                                  I.d_tl.as<uint32_t>(), s));
+        }
+        if (I.root_kind == 2) {
+            ENSURE(I.d_rk, ctx, std::max<uint64_t>(I.db->nnz, 1) * 4);
+            ENSURE(I.d_len, ctx, std::max<uint64_t>(I.db->n_tx, 1) * 4);
+            ENSURE(I.d_work, ctx, 8);
             HIPCHK(launch_fill_u32(I.d_work.as<uint32_t>(), 2, 0u, s));
             HIPCHK(launch_rank_tx(I.db->d_off.as<uint64_t>(), I.db->d_items.as<uint32_t>(),
                                   I.db->n_tx, I.d_rank_of_item.as<uint32_t>(), I.d_rk.as<uint32_t>(),
                                   I.d_len.as<uint32_t>(), s));
-            HIPCHK(launch_tidlist(I.db->d_off.as<uint64_t>(), I.d_rk.as<uint32_t>(),
-                                  I.d_len.as<uint32_t>(), I.db->n_tx, I.d_tl_off.as<uint64_t>(),
-                                  I.d_fill.as<uint32_t>(), I.d_tl.as<uint32_t>(), s));
             HIPCHK(hipEventRecord(rev[2 * q], s));
             HIPCHK(launch_root_project(I.db->d_off.as<uint64_t>(), I.d_rk.as<uint32_t>(),
                                        I.d_len.as<uint32_t>(), I.d_tl.as<uint32_t>(),
@@ -815,6 +822,9 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             D.max_len = opts.max_len;
             D.order_by_id = by_id ? 1u : 0u;
             D.project = (opts.flags & FIM_FLAG_NO_PROJECT) ? 0u : 1u;
+            const bool lists = D.project && !I.tl_off.empty();
+            D.tl = lists ? I.d_tl.as<uint32_t>() : nullptr;
+            D.tl_off = lists ? I.d_tl_off.as<uint64_t>() : nullptr;
             // A sample drawn with replacement at a small scaled support can
             // make every subset of a repeatedly drawn long transaction
             // frequent; its search is abandoned past a fixed budget (the
