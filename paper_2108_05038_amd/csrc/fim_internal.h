@@ -37,6 +37,9 @@ struct InstDesc {
     // ascending transaction ids of every rank (tl[tl_off[r] ..)), or null
     const uint32_t *tl;
     const uint64_t *tl_off;
+    // estimate run: itemsets counted per second-level class (l2 atom index)
+    // instead of reported; null in a mining run
+    unsigned long long *class_count;
 };
 
 // One unit of work of the persistent kernel: rows [r0, r1) of the
@@ -83,6 +86,7 @@ struct InstCounters {
     unsigned long long child_rows;  // child bitmaps written
     unsigned long long records;     // itemsets reported (counted when rec_budget > 0)
     unsigned long long row_words;   // words of sibling rows written (first frames and children)
+    unsigned long long out_words;   // words of the records reported (or counted)
     uint32_t stop;                  // 1 once records exceeded rec_budget
     uint32_t pad_;
 };

@@ -549,6 +549,7 @@ struct WaveShared {
 struct WaveStats {
     unsigned long long candidates, pair_words, child_rows, given, max_k, max_depth, row_words;
     unsigned long long rec_pending;  // records not yet added to the instance's count
+    unsigned long long out_words;    // words of the records reported (or counted)
 };
 
 // per-wave trace record (written when a trace buffer is given)
@@ -565,7 +566,19 @@ struct FrameSrc {
     const uint32_t *ranks;   // k atom ranks
     const uint32_t *supps;   // k supports
     uint32_t plen, k, r_end;
+    // second-level class of the piece (index into the instance's l2 atoms):
+    // for a one-item prefix the class of row 0 (row r: l2_ref + r), else the
+    // class every itemset of the piece belongs to
+    uint32_t l2_ref;
 };
+
+// the second-level class of the itemsets reported while row r of the
+// class at `depth` is expanded
+__device__ __forceinline__ uint32_t l2_class(uint32_t plen, uint32_t l2_ref, int depth, uint32_t r,
+                                            const WaveShared &ws) {
+    if (plen >= 2) return l2_ref;
+    return l2_ref + (depth == 0 ? r : ws.frames[0].r - 1);
+}
 
 // Work sharing between waves.  An idle wave counts itself in `idle`; a
 // busy wave that sees idle > 0 hands over the upper part of the unexpanded
@@ -692,8 +705,9 @@ __device__ void sort_atoms(const InstDesc &I, const uint32_t *tmp, uint32_t si, 
 // have about the same number of candidate pairs; a part is worth handing
 // over if it holds several candidate pairs per row the receiver has to
 // rebuild from the level-1 bitmaps.
-__device__ bool try_donate(const InstDesc &I, uint32_t inst, uint32_t plen, int depth,
-                           uint32_t *region, WaveShared &ws, Donation &dn, DfsCounters *ctr) {
+__device__ bool try_donate(const InstDesc &I, uint32_t inst, uint32_t plen, uint32_t l2_ref,
+                           int depth, uint32_t *region, WaveShared &ws, Donation &dn,
+                           DfsCounters *ctr) {
     const uint32_t lane = lane_id();
     int d0 = -1;
     uint32_t mid = 0;
@@ -726,7 +740,9 @@ __device__ bool try_donate(const InstDesc &I, uint32_t inst, uint32_t plen, int 
     const Frame F = ws.frames[d0];
     const uint32_t pl = plen + (uint32_t)d0;  // prefix of class d0
     const uint32_t kk = F.k - mid;
-    const uint32_t words = 4 + pl + 2 * kk;
+    const uint32_t words = 5 + pl + 2 * kk;
+    // the donated piece's second-level class reference
+    const uint32_t ref = pl == 1 ? l2_ref + mid : (plen >= 2 ? l2_ref : l2_ref + ws.frames[0].r - 1);
     unsigned long long hb = 0, sl = 0;
     if (lane == 0) {
         hb = atomicAdd(&ctr->don_heap_used.v, (unsigned long long)words);
@@ -743,11 +759,12 @@ __device__ bool try_donate(const InstDesc &I, uint32_t inst, uint32_t plen, int 
         store_coherent32(rec + 1, pl);
         store_coherent32(rec + 2, kk);
         store_coherent32(rec + 3, F.r_end - mid);
+        store_coherent32(rec + 4, ref);
     }
-    for (uint32_t q = lane; q < pl; q += kWave) store_coherent32(rec + 4 + q, ws.prefix[q]);
+    for (uint32_t q = lane; q < pl; q += kWave) store_coherent32(rec + 5 + q, ws.prefix[q]);
     for (uint32_t e = lane; e < kk; e += kWave) {
-        store_coherent32(rec + 4 + pl + e, ranks[mid + e]);
-        store_coherent32(rec + 4 + pl + kk + e, supps[mid + e]);
+        store_coherent32(rec + 5 + pl + e, ranks[mid + e]);
+        store_coherent32(rec + 5 + pl + kk + e, supps[mid + e]);
     }
     wave_mem_wait();  // the record is complete before it is published
     if (lane == 0) {
@@ -786,7 +803,8 @@ __device__ __forceinline__ bool inst_stopped(const InstDesc &I, InstCounters *ic
 
 template <int CPL>
 __device__ void process_frame(const InstDesc &I, uint32_t inst, uint32_t task, uint32_t plen,
-                              uint32_t k, uint32_t r_end, uint32_t Wp, uint64_t meta, uint64_t peak0,
+                              uint32_t l2_ref, uint32_t k, uint32_t r_end, uint32_t Wp, uint64_t meta,
+                              uint64_t peak0,
                               uint32_t *region, uint64_t S, WaveShared &ws, uint32_t *out,
                               uint64_t out_cap, DfsCounters *ctr, InstCounters *ictr, WaveStats &st,
                               OutChunk &oc, Donation &dn) {
@@ -812,7 +830,7 @@ __device__ void process_frame(const InstDesc &I, uint32_t inst, uint32_t task, u
     while (depth >= 0) {
         if ((++iters & 15u) == 0 && inst_stopped(I, ictr, inst)) return;
         if (dn.enabled && cool == 0 && ((++polls & 3u) == 0) && donation_wanted(ctr)) {
-            const bool gave = try_donate(I, inst, plen, depth, region, ws, dn, ctr);
+            const bool gave = try_donate(I, inst, plen, l2_ref, depth, region, ws, dn, ctr);
             cool = gave ? 8u : 4u;
             st.given += gave ? 1u : 0u;
         }
@@ -946,7 +964,12 @@ __device__ void process_frame(const InstDesc &I, uint32_t inst, uint32_t task, u
                 }
             }
             const uint32_t rec = kRecHeader + len;
-            if (chunk_reserve(oc, nf * rec, task, inst, out, out_cap, ctr)) {
+            st.out_words += (unsigned long long)nf * rec;
+            if (I.class_count) {
+                // estimate run: only the number of itemsets per second-level class
+                if (lane == 0) atomicAdd(&I.class_count[l2_class(plen, l2_ref, depth, r, ws)],
+                                         (unsigned long long)nf);
+            } else if (chunk_reserve(oc, nf * rec, task, inst, out, out_cap, ctr)) {
                 uint32_t *obase = out + oc.base + oc.pos;
                 for (uint32_t e = lane; e < nf; e += kWave) {
                     uint32_t *o = obase + (uint64_t)e * rec;
@@ -1232,10 +1255,10 @@ __device__ void run_frame(const InstDesc &I, uint32_t inst, uint32_t task, const
             const uint64_t peak0 = (S - low) + (uint64_t)k * Wq;
             const uint32_t C = Wq / 4;
             if (CPL > 0 && C > (uint32_t)kWave && C <= (uint32_t)(CPL * kWave))
-                process_frame<CPL>(I, inst, task, plen, k, src.r_end, Wq, meta, peak0, region, S, ws,
+                process_frame<CPL>(I, inst, task, plen, src.l2_ref, k, src.r_end, Wq, meta, peak0, region, S, ws,
                                    out, out_cap, ctr, ictr, st, oc, dn);
             else
-                process_frame<0>(I, inst, task, plen, k, src.r_end, Wq, meta, peak0, region, S, ws,
+                process_frame<0>(I, inst, task, plen, src.l2_ref, k, src.r_end, Wq, meta, peak0, region, S, ws,
                                  out, out_cap, ctr, ictr, st, oc, dn);
             return;
         }
@@ -1295,10 +1318,10 @@ __device__ void run_frame(const InstDesc &I, uint32_t inst, uint32_t task, const
     const uint64_t peak0 = (S - low) + (uint64_t)k * Wp;
     const uint32_t C = Wp / 4;
     if (CPL > 0 && C > (uint32_t)kWave && C <= (uint32_t)(CPL * kWave))
-        process_frame<CPL>(I, inst, task, plen, k, src.r_end, Wp, meta, peak0, region, S, ws, out,
+        process_frame<CPL>(I, inst, task, plen, src.l2_ref, k, src.r_end, Wp, meta, peak0, region, S, ws, out,
                            out_cap, ctr, ictr, st, oc, dn);
     else
-        process_frame<0>(I, inst, task, plen, k, src.r_end, Wp, meta, peak0, region, S, ws, out,
+        process_frame<0>(I, inst, task, plen, src.l2_ref, k, src.r_end, Wp, meta, peak0, region, S, ws, out,
                          out_cap, ctr, ictr, st, oc, dn);
 }
 
@@ -1310,6 +1333,7 @@ __device__ __forceinline__ void flush_stats(const InstDesc &I, InstCounters *ict
         if (st.pair_words) atomicAdd(&ic.pair_words, st.pair_words);
         if (st.child_rows) atomicAdd(&ic.child_rows, st.child_rows);
         if (st.row_words) atomicAdd(&ic.row_words, st.row_words);
+        if (st.out_words) atomicAdd(&ic.out_words, st.out_words);
         if (st.rec_pending &&
             atomicAdd(&ic.records, st.rec_pending) + st.rec_pending > I.rec_budget)
             atomicOr(&ic.stop, 1u);
@@ -1360,7 +1384,7 @@ __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Tas
             WaveStats st{};
             OutChunk oc{kNoChunk, 0u, 0u, 0u, 0u};
             const FrameSrc fs{&tasks[t].node, I.l2_atom + a0 + T.r0, I.l2_supp + a0 + T.r0, 1u,
-                              k1 - T.r0, T.r1 - T.r0};
+                              k1 - T.r0, T.r1 - T.r0, a0 + T.r0};
             const unsigned long long c0 = wall_clock64();
             run_frame<CPL>(I, T.inst, (uint32_t)t, fs, region, stack_words, ws, out, out_cap, ctr,
                            ictr, st, oc, dn);
@@ -1425,14 +1449,15 @@ __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Tas
                 const uint32_t *rec = dn.heap + (off - 1);
                 const uint32_t inst = load_coherent32(rec), pl = load_coherent32(rec + 1);
                 const uint32_t kk = load_coherent32(rec + 2), re = load_coherent32(rec + 3);
+                const uint32_t ref = load_coherent32(rec + 4);
                 const uint32_t words = pl + 2 * kk;
                 if ((uint64_t)words <= stack_words / 2) {
                     uint32_t *copy = region + (stack_words - words);
                     for (uint32_t q = lane; q < words; q += kWave)
-                        copy[q] = load_coherent32(rec + 4 + q);
+                        copy[q] = load_coherent32(rec + 5 + q);
                     wave_mem_wait();
                     const InstDesc &I = insts[inst];
-                    const FrameSrc fs{copy, copy + pl, copy + pl + kk, pl, kk, re};
+                    const FrameSrc fs{copy, copy + pl, copy + pl + kk, pl, kk, re, ref};
                     WaveStats st{};
                     OutChunk oc{kNoChunk, 0u, 0u, 0u, 0u};
                     const unsigned long long c0 = wall_clock64();
