@@ -166,6 +166,16 @@ fim_status fim_minsup_from_relative(uint64_t n_tx, double rel, uint32_t *out_abs
  * default a piece of work whose prefix covers at most a quarter of the
  * transactions builds its rows projected on that cover) */
 #define FIM_FLAG_NO_PROJECT 0x80u
+/*
+ * Phase 1 as the thesis runs it: the sample mined as a database of its own
+ * (own item order), its frequent itemsets reservoir-sampled (|S| =
+ * sample_fi) and assigned to second-level classes on the host.  By default
+ * the sample is mined inside the same call on the database's own classes
+ * (its bitmaps built from the sampled transactions) and the persistent
+ * kernel counts every sampled frequent itemset into its second-level class
+ * (the reservoir's estimate with the whole stream kept).
+ */
+#define FIM_FLAG_RESERVOIR 0x100u
 
 /*
  * Options of a mining call.  A zero field selects its default.

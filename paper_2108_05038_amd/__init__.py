@@ -42,6 +42,7 @@ FIM_FLAG_DENSE_ROOT = 0x10
 FIM_FLAG_ROOT_COVERS = 0x20
 FIM_FLAG_ROOT_PROJECT = 0x40
 FIM_FLAG_NO_PROJECT = 0x80
+FIM_FLAG_RESERVOIR = 0x100
 
 EXPORTED = [
     "fim_status_str", "fim_last_error", "fim_version", "fim_ctx_create", "fim_ctx_destroy",

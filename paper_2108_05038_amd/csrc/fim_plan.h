@@ -38,6 +38,12 @@ uint32_t default_sample_tx(double eps, double delta);
 uint32_t default_sample_fi(double rho, double eps, double delta);
 double bernoulli_kl(double x, double y);
 
+// Phase 1's database sample: nd transactions drawn uniformly with
+// replacement (SplitMix64 from `seed`), each reduced to the items frequent in
+// the database; CSR into off / items.
+void draw_sample(const fim_db *db, const std::vector<uint32_t> &rank_of_item, uint64_t nd,
+                 uint64_t seed, std::vector<uint64_t> &off, std::vector<uint32_t> &items);
+
 // Simple reservoir sampling (thesis, the Simple-Reservoir-Sampling
 // algorithm): keeps a uniform sample without replacement of size n of a
 // stream.  Returns the indices (positions in the stream) that were kept.
@@ -69,12 +75,15 @@ fim_status sample_phase(fim_ctx *ctx, const std::vector<PlanInput> &in, const fi
                         SampleEstimate &est);
 
 // Builds the task list of all instances in LPT order.  With est (the
-// finished Phase 1 of these instances) the sample is not mined again.
-// *est_out_words receives an estimate of the output words of the whole
-// run (0 without a sample estimate).
+// finished Phase 1 of these instances) the sample is not mined again; with
+// `given` (per instance, a weight per second-level class, or empty for no
+// estimate) no sample is drawn here at all.  *est_out_words receives an
+// estimate of the output words of the whole run (0 without a sample
+// estimate).
 fim_status plan_tasks(fim_ctx *ctx, const std::vector<PlanInput> &in, const fim_options &opts,
                       uint32_t n_workers, std::vector<Task> &tasks,
                       std::vector<PlanClass> *classes = nullptr, uint64_t *est_out_words = nullptr,
-                      SampleEstimate *est = nullptr);
+                      SampleEstimate *est = nullptr,
+                      const std::vector<std::vector<double>> *given = nullptr);
 
 }  // namespace fim

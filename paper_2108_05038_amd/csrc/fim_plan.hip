@@ -88,6 +88,22 @@ SampleEstimate::~SampleEstimate() {
     for (auto *r : res) fim_result_destroy(r);
 }
 
+void draw_sample(const fim_db *db, const std::vector<uint32_t> &rank_of_item, uint64_t nd,
+                 uint64_t seed, std::vector<uint64_t> &off, std::vector<uint32_t> &items) {
+    const uint64_t N = db->n_tx;
+    uint64_t x = seed;
+    off.assign(1, 0);
+    items.clear();
+    for (uint64_t d = 0; d < nd; d++) {
+        const uint64_t t = std::min<uint64_t>(N - 1, (uint64_t)(u01(x) * (double)N));
+        for (uint64_t p = db->h_off[t]; p < db->h_off[t + 1]; p++) {
+            const uint32_t it = db->h_items[p];
+            if (rank_of_item[it] != kNone) items.push_back(it);
+        }
+        off.push_back(items.size());
+    }
+}
+
 // Phase 1 (reservoir variant): a sample of |D~| transactions drawn
 // uniformly with replacement, mined by the same miner at the same relative
 // minimum support, its frequent itemsets reservoir-sampled.
@@ -108,17 +124,9 @@ fim_status sample_phase(fim_ctx *ctx, const std::vector<PlanInput> &in, const fi
         const uint64_t N = P.db->n_tx;
         const uint64_t nd = std::min<uint64_t>(want_tx, N / 4);
         if (nd < 256 || P.n_freq < 3 || !P.estimate) continue;
-        uint64_t x = opts.seed ^ (0x51ED270B1DE0ull * (q + 1));
-        std::vector<uint64_t> off{0};
+        std::vector<uint64_t> off;
         std::vector<uint32_t> items;
-        for (uint64_t d = 0; d < nd; d++) {
-            const uint64_t t = std::min<uint64_t>(N - 1, (uint64_t)(u01(x) * (double)N));
-            for (uint64_t p = P.db->h_off[t]; p < P.db->h_off[t + 1]; p++) {
-                const uint32_t it = P.db->h_items[p];
-                if ((*P.rank_of_item)[it] != kNone) items.push_back(it);
-            }
-            off.push_back(items.size());
-        }
+        draw_sample(P.db, *P.rank_of_item, nd, opts.seed ^ (0x51ED270B1DE0ull * (q + 1)), off, items);
         fim_status s = fim_db_create(ctx, nd, off.data(), items.empty() ? nullptr : items.data(),
                                      P.db->n_item_ids, &sdb[q]);
         if (s != FIM_OK) return s;
@@ -279,12 +287,14 @@ void partition_lpt_order(const std::vector<PlanClass> &cls_in,
 fim_status plan_tasks(fim_ctx *ctx, const std::vector<PlanInput> &in, const fim_options &opts,
                       uint32_t n_workers, std::vector<Task> &tasks,
                       std::vector<PlanClass> *classes_out, uint64_t *est_out_words,
-                      SampleEstimate *est) {
+                      SampleEstimate *est, const std::vector<std::vector<double>> *given) {
     tasks.clear();
     const uint32_t n_inst = (uint32_t)in.size();
     std::vector<std::vector<double>> row_w;
     uint64_t ow = 0;
-    if (!(opts.flags & FIM_FLAG_NO_ESTIMATE)) {
+    if (given) {
+        row_w = *given;
+    } else if (!(opts.flags & FIM_FLAG_NO_ESTIMATE)) {
         fim_status s = estimate_rows(ctx, in, opts, row_w, ow, est);
         if (est_out_words) *est_out_words = ow;
         if (s != FIM_OK) return s;

@@ -485,6 +485,279 @@ static void build_level2(Inst &I, bool by_id) {
     }
 }
 
+// One persistent depth-first launch over `tasks`, rerun with a larger
+// per-wave stack or output arena when the kernel's flags ask for it.
+struct DfsLaunch {
+    uint64_t frame0 = 0;  // words of the largest first frame
+    uint32_t variant = 0, n_workers = 0, claim = 1, nap_max = 64;
+    bool use_graph = false;
+    bool cap_output = false;     // a full output arena ends the run (internal sample runs)
+    bool stop_is_error = true;   // an instance over its record budget is an error
+    uint64_t out_cap = 1ull << 24;
+    DfsCounters ctr{};
+    std::vector<InstCounters> ictr;
+    float ms = 0.f;
+    uint32_t retries = 0;
+    bool truncated = false;
+};
+
+static fim_status run_persistent(fim_ctx *ctx, hipStream_t s, Tracer &tr,
+                                 const std::vector<InstDesc> &desc, const std::vector<Task> &tasks,
+                                 DevBuf &d_out, DfsLaunch &L) {
+    const uint32_t n_inst = (uint32_t)desc.size();
+    DevBuf d_desc(ctx), d_tasks(ctx), d_stack(ctx), d_ctr(ctx), d_ictr(ctx);
+    DevBuf d_slots(ctx), d_heap(ctx), d_trace(ctx);
+    hipEvent_t ev0, ev1;
+    HIPCHK(hipEventCreate(&ev0));
+    HIPCHK(hipEventCreate(&ev1));
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } evg{ev0, ev1};
+    ENSURE(d_desc, ctx, desc.size() * sizeof(InstDesc));
+    ENSURE(d_tasks, ctx, tasks.size() * sizeof(Task));
+    HIPCHK(hipMemcpyAsync(d_desc.as<void>(), desc.data(), desc.size() * sizeof(InstDesc),
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_tasks.as<void>(), tasks.data(), tasks.size() * sizeof(Task),
+                          hipMemcpyHostToDevice, s));
+    L.ictr.assign(n_inst, InstCounters{});
+    // per-worker stack: room for the largest first frame and its subtree,
+    // within a quarter of device memory in total
+    uint64_t S = std::max<uint64_t>(4 * L.frame0, 1ull << 20);
+    const uint64_t kMaxStack = 0xFFFFFFF0ull;  // frame offsets are 32-bit
+    const uint64_t budget_words = (uint64_t)(ctx->total_mem / 4) / 4;
+    // work sharing between waves
+    const uint64_t n_slots = 1ull << 16;
+    const uint64_t heap_words = 1ull << 24;
+    // a wave gives up waiting for donated work after 60 s of wall clock
+    int clk_khz = 0;
+    (void)hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, ctx->device);
+    const uint64_t wait_ticks = (uint64_t)(clk_khz > 0 ? clk_khz : 100000) * 60000ull;
+    uint32_t nap_max = L.nap_max;
+    if (const char *e = getenv("FIM_NAP_MAX")) nap_max = (uint32_t)std::max(1, atoi(e));  // tuning
+    for (;;) {
+        uint32_t workers = L.n_workers;
+        if ((uint64_t)workers * S > budget_words)
+            workers = (uint32_t)std::max<uint64_t>(4, budget_words / S / 4 * 4);
+        if (((uint64_t)workers * S > budget_words && S > budget_words / 4) || S > kMaxStack)
+            return set_error(FIM_E_OOM_DEVICE, "a first-level class does not fit on the device");
+        ENSURE(d_stack, ctx, (size_t)workers * S * 4);
+        ENSURE(d_out, ctx, (size_t)L.out_cap * 4);
+        ENSURE(d_ctr, ctx, sizeof(DfsCounters));
+        ENSURE(d_ictr, ctx, sizeof(InstCounters) * n_inst);
+        if (tr.on) {
+            ENSURE(d_trace, ctx, (size_t)workers * 64);
+            HIPCHK(launch_fill_u32(d_trace.as<uint32_t>(), (uint64_t)workers * 16, 0u, s));
+        }
+        ENSURE(d_slots, ctx, n_slots * 8);
+        ENSURE(d_heap, ctx, heap_words * 4);
+        HIPCHK(launch_fill_u32(d_slots.as<uint32_t>(), n_slots * 2, 0u, s));
+        HIPCHK(launch_fill_u32(d_ctr.as<uint32_t>(), sizeof(DfsCounters) / 4, 0u, s));
+        HIPCHK(launch_fill_u32(d_ictr.as<uint32_t>(), sizeof(InstCounters) / 4 * n_inst, 0u, s));
+        if (L.cap_output) HIPCHK(launch_fill_u32(d_out.as<uint32_t>(), L.out_cap, 0u, s));
+        HIPCHK(hipEventRecord(ev0, s));
+        auto launch = [&]() {
+            return launch_dfs(d_desc.as<InstDesc>(), d_tasks.as<Task>(), tasks.size(),
+                              d_stack.as<uint32_t>(), S, workers, L.claim, d_out.as<uint32_t>(),
+                              L.out_cap, d_ctr.as<DfsCounters>(), d_ictr.as<InstCounters>(),
+                              d_slots.as<unsigned long long>(), n_slots, d_heap.as<uint32_t>(),
+                              heap_words, wait_ticks,
+                              tr.on ? d_trace.as<unsigned long long>() : nullptr, L.variant, nap_max,
+                              s);
+        };
+        if (L.use_graph) {
+            hipGraph_t g;
+            hipGraphExec_t ge;
+            HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            hipError_t le = launch();
+            hipError_t ce = hipStreamEndCapture(s, &g);
+            if (le != hipSuccess || ce != hipSuccess)
+                return set_error(FIM_E_DEVICE, std::string("graph capture: ") +
+                                                   hipGetErrorString(le != hipSuccess ? le : ce));
+            hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            if (ie == hipSuccess) ie = hipGraphLaunch(ge, s);
+            (void)hipGraphExecDestroy(ge);
+            (void)hipGraphDestroy(g);
+            if (ie != hipSuccess)
+                return set_error(FIM_E_DEVICE, std::string("graph launch: ") + hipGetErrorString(ie));
+        } else {
+            HIPCHK(launch());
+        }
+        HIPCHK(hipEventRecord(ev1, s));
+        HIPCHK(hipMemcpyAsync(&L.ctr, d_ctr.as<void>(), sizeof(L.ctr), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(L.ictr.data(), d_ictr.as<void>(), sizeof(InstCounters) * n_inst,
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(hipEventElapsedTime(&L.ms, ev0, ev1));
+        const DfsCounters &ctr = L.ctr;
+        if (tr.on) {
+            const double mean = (double)ctr.busy_sum / workers;
+            std::vector<unsigned long long> wt((size_t)workers * 8);
+            if (hipMemcpy(wt.data(), d_trace.as<void>(), wt.size() * 8, hipMemcpyDeviceToHost) == hipSuccess) {
+                std::vector<uint32_t> ord(workers);
+                std::iota(ord.begin(), ord.end(), 0u);
+                std::sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) { return wt[8 * a] > wt[8 * b]; });
+                for (uint32_t x = 0; x < std::min<uint32_t>(5, workers); x++) {
+                    const unsigned long long *v = &wt[8 * ord[x]];
+                    fprintf(stderr, "[fim %s]   wave %u busy %.3f ms pieces %llu given %llu cands %llu max_k %llu max_depth %llu\n",
+                            tr.tag, ord[x], clk_khz ? v[0] / (double)clk_khz : 0.0, v[1], v[2], v[3], v[4], v[5]);
+                }
+            }
+            fprintf(stderr, "[fim %s] dfs kernel %.3f ms, %zu tasks, %llu donations, %u workers, busiest %.3f ms, mean %.3f ms, imbalance %.1f, flags %u\n",
+                    tr.tag, L.ms, tasks.size(), (unsigned long long)ctr.donations, workers,
+                    clk_khz ? ctr.busy_max / (double)clk_khz : 0.0,
+                    clk_khz ? mean / clk_khz : 0.0, mean > 0 ? ctr.busy_max / mean : 0.0, ctr.flags);
+        }
+        if (ctr.flags & kFlagSpin)
+            return set_error(FIM_E_DEVICE, "work sharing between waves timed out");
+        if (ctr.flags & kFlagDepthOverflow)
+            return set_error(FIM_E_OUTPUT_LIMIT, "an itemset is longer than " +
+                                                     std::to_string(kMaxDepth + 2) + " items");
+        bool again = false;
+        if (ctr.flags & kFlagStackOverflow) {
+            S = std::max<uint64_t>(2 * S, ctr.stack_need + ctr.stack_need / 4);
+            again = true;
+        }
+        if (L.stop_is_error)
+            for (uint32_t q = 0; q < n_inst; q++)
+                if (L.ictr[q].stop)
+                    return set_error(FIM_E_OUTPUT_LIMIT, "instance " + std::to_string(q) +
+                                                             ": more frequent itemsets than max_itemsets");
+        if ((ctr.flags & kFlagOutOverflow) || ctr.out_used.v > L.out_cap) {
+            // grow the arena (work sharing varies the need between runs);
+            // a sample run past a hard cap is cut short instead
+            const uint64_t want = ctr.out_used.v + ctr.out_used.v / 2 + 4096;
+            if (L.cap_output && want > kSampleOutCap) {
+                L.truncated = true;
+            } else {
+                L.out_cap = want;
+                again = true;
+            }
+        }
+        if (!again) break;
+        L.retries++;
+        if (L.retries > 12) return set_error(FIM_E_DEVICE, "persistent kernel did not converge");
+    }
+    return FIM_OK;
+}
+
+// Phase 1 inside the run: for every instance to estimate, a sample of
+// |D~| transactions drawn with replacement is turned into bitmaps over the
+// instance's own frequent items, and the persistent kernel mines it on the
+// instance's own first-level classes (the same atoms, in the same order) at
+// the relative minimum support, counting every frequent itemset of length
+// >= 3 into its second-level class instead of reporting it.  row_w[q] gets
+// count x words per row for every second-level class of instance q (empty
+// when the instance has no estimate); out_words the sample's record words.
+static fim_status count_estimate(fim_ctx *ctx, hipStream_t s, Tracer &tr, std::vector<Inst> &insts,
+                                 const std::vector<PlanInput> &pin, const fim_options &opts,
+                                 std::vector<std::vector<double>> &row_w, uint64_t &out_words) {
+    const uint32_t n_inst = (uint32_t)insts.size();
+    row_w.assign(n_inst, {});
+    out_words = 0;
+    const uint32_t want_tx = opts.sample_tx ? opts.sample_tx : default_sample_tx(0.02, 0.05);
+    std::vector<InstDesc> desc(n_inst);
+    std::vector<Task> tasks;
+    std::vector<DevBuf> s_off, s_items, s_rows;
+    for (uint32_t q = 0; q < n_inst; q++) {
+        s_off.emplace_back(ctx);
+        s_items.emplace_back(ctx);
+        s_rows.emplace_back(ctx);
+    }
+    std::vector<std::vector<uint64_t>> h_off(n_inst);  // kept until the copies are done
+    std::vector<std::vector<uint32_t>> h_items(n_inst);
+    std::vector<uint64_t> count_at(n_inst + 1, 0);
+    std::vector<bool> used(n_inst, false);
+    uint64_t frame0 = 0;
+    uint32_t max_chunks = 0;
+    for (uint32_t q = 0; q < n_inst; q++) {
+        Inst &I = insts[q];
+        count_at[q + 1] = count_at[q] + I.l2_atom.size();
+        const uint64_t N = I.db->n_tx;
+        const uint64_t nd = std::min<uint64_t>(want_tx, N / 4);
+        if (!pin[q].estimate || nd < 256 || I.n_freq < 3 || I.l2_atom.empty()) continue;
+        std::vector<uint64_t> &off = h_off[q];
+        std::vector<uint32_t> &items = h_items[q];
+        draw_sample(I.db, I.rank_of_item, nd, opts.seed ^ (0x51ED270B1DE0ull * (q + 1)), off, items);
+        const uint32_t Ws = (uint32_t)((nd + 31) / 32);
+        const uint32_t Wps = std::max<uint32_t>(kRowAlign, (Ws + kRowAlign - 1) / kRowAlign * kRowAlign);
+        ENSURE(s_off[q], ctx, off.size() * 8);
+        ENSURE(s_items[q], ctx, std::max<size_t>(items.size(), 1) * 4);
+        ENSURE(s_rows[q], ctx, (size_t)I.n_freq * Wps * 4);
+        HIPCHK(hipMemcpyAsync(s_off[q].as<void>(), off.data(), off.size() * 8, hipMemcpyHostToDevice, s));
+        if (!items.empty())
+            HIPCHK(hipMemcpyAsync(s_items[q].as<void>(), items.data(), items.size() * 4,
+                                  hipMemcpyHostToDevice, s));
+        HIPCHK(launch_fill_u32(s_rows[q].as<uint32_t>(), (uint64_t)I.n_freq * Wps, 0u, s));
+        HIPCHK(launch_bitmap_build(s_off[q].as<uint64_t>(), s_items[q].as<uint32_t>(), nd,
+                                   I.d_rank_of_item.as<uint32_t>(), s_rows[q].as<uint32_t>(), Wps, s));
+        InstDesc &D = desc[q];
+        D.rows = s_rows[q].as<uint32_t>();
+        D.item_of_rank = I.d_item_of_rank.as<uint32_t>();
+        D.l2_off = I.d_l2_off.as<uint32_t>();
+        D.l2_atom = I.d_l2_atom.as<uint32_t>();
+        D.l2_supp = I.d_l2_supp.as<uint32_t>();
+        D.Wp = Wps;
+        D.n_freq = I.n_freq;
+        // relative minimum support carried over to the sample, at least 2
+        D.minsup = std::max<uint32_t>(2, (uint32_t)ceil((double)I.minsup * (double)nd / (double)N));
+        D.max_len = 0;
+        D.order_by_id = (opts.flags & FIM_FLAG_ORDER_BY_ID) ? 1u : 0u;
+        D.project = (opts.flags & FIM_FLAG_NO_PROJECT) ? 0u : 1u;
+        D.rec_budget = kSampleRecordBudget;
+        used[q] = true;
+        max_chunks = std::max(max_chunks, Wps / 4);
+        for (uint32_t i = 0; i < I.n_freq; i++) {
+            const uint32_t f = I.l2_off[i + 1] - I.l2_off[i];
+            if (f < 2) continue;
+            tasks.push_back(Task{q, i, 0, f - 1});
+            frame0 = std::max<uint64_t>(frame0, (uint64_t)f * Wps + 3ull * f);
+        }
+    }
+    if (tasks.empty()) return FIM_OK;
+    // largest classes first
+    std::stable_sort(tasks.begin(), tasks.end(), [&](const Task &a, const Task &b) {
+        return a.r1 > b.r1;
+    });
+    DevBuf d_count(ctx), d_out(ctx);
+    ENSURE(d_count, ctx, std::max<uint64_t>(count_at[n_inst], 1) * 8);
+    HIPCHK(launch_fill_u32(d_count.as<uint32_t>(), std::max<uint64_t>(count_at[n_inst], 1) * 2, 0u, s));
+    for (uint32_t q = 0; q < n_inst; q++)
+        if (used[q]) desc[q].class_count = d_count.as<unsigned long long>() + count_at[q];
+    DfsLaunch L;
+    L.frame0 = frame0;
+    L.variant = dfs_variant(max_chunks);
+    L.n_workers = std::max<uint32_t>(4, dfs_resident_workers(ctx->n_cu, L.variant) / 4 * 4);
+    L.nap_max = 64;
+    L.cap_output = true;
+    L.stop_is_error = false;
+    L.out_cap = 1024;  // nothing is reported
+    Tracer sub("sample");
+    sub.on = tr.on;
+    fim_status st = run_persistent(ctx, s, sub, desc, tasks, d_out, L);
+    if (st != FIM_OK) return st;
+    std::vector<unsigned long long> cnt(count_at[n_inst]);
+    if (!cnt.empty())
+        HIPCHK(hipMemcpyAsync(cnt.data(), d_count.as<void>(), cnt.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (uint32_t q = 0; q < n_inst; q++) {
+        if (!used[q] || L.ictr[q].stop) continue;  // exploded sample: no estimate
+        const Inst &I = insts[q];
+        row_w[q].assign(I.l2_atom.size(), 0.0);
+        uint64_t any = 0;
+        for (size_t k = 0; k < I.l2_atom.size(); k++) {
+            row_w[q][k] = (double)cnt[count_at[q] + k] * (double)I.W;
+            any += cnt[count_at[q] + k];
+        }
+        if (!any) row_w[q].clear();
+        out_words += L.ictr[q].out_words;
+    }
+    return FIM_OK;
+}
+
 fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const fim_options &opts_in,
                      std::vector<fim_result *> &results, bool use_graph) {
     const auto t_start = clk::now();
@@ -766,7 +1039,32 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             pin[q].estimate = (opts.flags & FIM_FLAG_ALWAYS_ESTIMATE) || 20 * below >= root;
             deep_work = deep_work || 20 * below >= root;
         }
-        fim_status ps = plan_tasks(ctx, pin, opts, n_workers, tasks, nullptr, &est_out_words);
+        fim_status ps = FIM_OK;
+        if (opts.flags & (FIM_FLAG_RESERVOIR | FIM_FLAG_NO_ESTIMATE)) {
+            ps = plan_tasks(ctx, pin, opts, n_workers, tasks, nullptr, &est_out_words);
+        } else {
+            // l2 arrays on the device for the sample's persistent run
+            for (Inst &I : insts) {
+                if (I.l2_atom.empty()) continue;
+                ENSURE(I.d_l2_off, ctx, I.l2_off.size() * 4);
+                ENSURE(I.d_l2_atom, ctx, I.l2_atom.size() * 4);
+                ENSURE(I.d_l2_supp, ctx, I.l2_supp.size() * 4);
+                HIPCHK(hipMemcpyAsync(I.d_l2_off.as<void>(), I.l2_off.data(), I.l2_off.size() * 4,
+                                      hipMemcpyHostToDevice, s));
+                HIPCHK(hipMemcpyAsync(I.d_l2_atom.as<void>(), I.l2_atom.data(),
+                                      I.l2_atom.size() * 4, hipMemcpyHostToDevice, s));
+                HIPCHK(hipMemcpyAsync(I.d_l2_supp.as<void>(), I.l2_supp.data(),
+                                      I.l2_supp.size() * 4, hipMemcpyHostToDevice, s));
+            }
+            std::vector<std::vector<double>> row_w;
+            uint64_t sample_words = 0;
+            ps = count_estimate(ctx, s, tr, insts, pin, opts, row_w, sample_words);
+            if (ps != FIM_OK) return ps;
+            // the sample has about as many frequent itemsets as the database
+            // at the same relative support: room for twice its records
+            est_out_words = 2 * sample_words;
+            ps = plan_tasks(ctx, pin, opts, n_workers, tasks, nullptr, nullptr, nullptr, &row_w);
+        }
         if (ps != FIM_OK) return ps;
         const uint64_t plan_ns = ns_since(t_plan);
         for (auto &I : insts) I.st.estimate_ns = plan_ns;
@@ -781,8 +1079,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
 
     tr.mark("estimate + plan");
     // ---------------- a5-a8: one persistent launch over every task
-    DevBuf d_desc(ctx), d_tasks(ctx), d_stack(ctx), d_out(ctx), d_ctr(ctx), d_ictr(ctx);
-    DevBuf d_slots(ctx), d_heap(ctx), d_trace(ctx);
+    DevBuf d_out(ctx);
     struct Span {
         const uint32_t *p = nullptr;
         size_t n = 0;
@@ -837,148 +1134,28 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             const uint64_t k = I.l2_off[T.node + 1] - I.l2_off[T.node] - T.r0;
             frame0 = std::max<uint64_t>(frame0, k * I.Wp + 3 * k);
         }
-        ENSURE(d_desc, ctx, desc.size() * sizeof(InstDesc));
-        ENSURE(d_tasks, ctx, tasks.size() * sizeof(Task));
-        HIPCHK(hipMemcpyAsync(d_desc.as<void>(), desc.data(), desc.size() * sizeof(InstDesc),
-                              hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(d_tasks.as<void>(), tasks.data(), tasks.size() * sizeof(Task),
-                              hipMemcpyHostToDevice, s));
-        // per-worker stack: room for the largest first frame and its subtree,
-        // within a quarter of device memory in total
-        uint64_t S = std::max<uint64_t>(4 * frame0, 1ull << 20);
-        const uint64_t kMaxStack = 0xFFFFFFF0ull;  // frame offsets are 32-bit
-        const uint64_t budget_words = (uint64_t)(ctx->total_mem / 4) / 4;
-        const bool sample_mode = (opts.flags & kFlagInternalSample) != 0;
-        uint64_t out_cap = sample_mode ? (1ull << 24) : std::max<uint64_t>(1ull << 24, est_out_words);
-        int attempts = 0;
-        for (;;) {
-            uint32_t workers = n_workers;
-            if ((uint64_t)workers * S > budget_words)
-                workers = (uint32_t)std::max<uint64_t>(4, budget_words / S / 4 * 4);
-            if (((uint64_t)workers * S > budget_words && S > budget_words / 4) || S > kMaxStack)
-                return set_error(FIM_E_OOM_DEVICE, "a first-level class does not fit on the device");
-            ENSURE(d_stack, ctx, (size_t)workers * S * 4);
-            ENSURE(d_out, ctx, (size_t)out_cap * 4);
-            ENSURE(d_ctr, ctx, sizeof(DfsCounters));
-            ENSURE(d_ictr, ctx, sizeof(InstCounters) * n_inst);
-            // work sharing between waves
-            const uint64_t n_slots = 1ull << 16;
-            const uint64_t heap_words = 1ull << 24;
-            // a wave gives up waiting for donated work after 60 s of wall clock
-            int clk_khz = 0;
-            (void)hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, ctx->device);
-            const uint64_t wait_ticks = (uint64_t)(clk_khz > 0 ? clk_khz : 100000) * 60000ull;
-            // Longest back-off of an idle wave.  Idle waves poll counters the
-            // busy waves update; with much work below the root, polling
-            // often slows those updates more than it speeds up hand-overs,
-            // while a short run mostly waits for its last sleepers to wake.
-            // (FIM_NAP_MAX overrides, for tuning.)
-            uint32_t nap_max = deep_work ? 64 : 16;
-            if (const char *e = getenv("FIM_NAP_MAX")) nap_max = (uint32_t)std::max(1, atoi(e));
-            if (tr.on) {
-                ENSURE(d_trace, ctx, (size_t)workers * 64);
-                HIPCHK(launch_fill_u32(d_trace.as<uint32_t>(), (uint64_t)workers * 16, 0u, s));
-            }
-            if (n_slots) {
-                ENSURE(d_slots, ctx, n_slots * 8);
-                ENSURE(d_heap, ctx, heap_words * 4);
-                HIPCHK(launch_fill_u32(d_slots.as<uint32_t>(), n_slots * 2, 0u, s));
-            }
-            HIPCHK(launch_fill_u32(d_ctr.as<uint32_t>(), sizeof(DfsCounters) / 4, 0u, s));
-            HIPCHK(launch_fill_u32(d_ictr.as<uint32_t>(), sizeof(InstCounters) / 4 * n_inst, 0u, s));
-            if (sample_mode) HIPCHK(launch_fill_u32(d_out.as<uint32_t>(), out_cap, 0u, s));
-            HIPCHK(hipEventRecord(ev0, s));
-            if (use_graph) {
-                hipGraph_t g;
-                hipGraphExec_t ge;
-                HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-                hipError_t le = launch_dfs(d_desc.as<InstDesc>(), d_tasks.as<Task>(), tasks.size(),
-                                           d_stack.as<uint32_t>(), S, workers,
-                                           opts.classes_per_wg ? opts.classes_per_wg : 1,
-                                           d_out.as<uint32_t>(), out_cap, d_ctr.as<DfsCounters>(),
-                                           d_ictr.as<InstCounters>(),
-                                           n_slots ? d_slots.as<unsigned long long>() : nullptr,
-                                           n_slots, n_slots ? d_heap.as<uint32_t>() : nullptr,
-                                           heap_words, wait_ticks,
-                                           tr.on ? d_trace.as<unsigned long long>() : nullptr,
-                                           variant, nap_max, s);
-                hipError_t ce = hipStreamEndCapture(s, &g);
-                if (le != hipSuccess || ce != hipSuccess)
-                    return set_error(FIM_E_DEVICE, std::string("graph capture: ") +
-                                                       hipGetErrorString(le != hipSuccess ? le : ce));
-                hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-                if (ie == hipSuccess) ie = hipGraphLaunch(ge, s);
-                (void)hipGraphExecDestroy(ge);
-                (void)hipGraphDestroy(g);
-                if (ie != hipSuccess)
-                    return set_error(FIM_E_DEVICE, std::string("graph launch: ") + hipGetErrorString(ie));
-            } else {
-                HIPCHK(launch_dfs(d_desc.as<InstDesc>(), d_tasks.as<Task>(), tasks.size(),
-                                  d_stack.as<uint32_t>(), S, workers,
-                                  opts.classes_per_wg ? opts.classes_per_wg : 1, d_out.as<uint32_t>(),
-                                  out_cap, d_ctr.as<DfsCounters>(), d_ictr.as<InstCounters>(),
-                                  n_slots ? d_slots.as<unsigned long long>() : nullptr, n_slots,
-                                  n_slots ? d_heap.as<uint32_t>() : nullptr, heap_words, wait_ticks,
-                                  tr.on ? d_trace.as<unsigned long long>() : nullptr, variant, nap_max,
-                                  s));
-            }
-            HIPCHK(hipEventRecord(ev1, s));
-            HIPCHK(hipMemcpyAsync(&ctr, d_ctr.as<void>(), sizeof(ctr), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipMemcpyAsync(ictr.data(), d_ictr.as<void>(), sizeof(InstCounters) * n_inst,
-                                  hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            HIPCHK(hipEventElapsedTime(&dfs_ms, ev0, ev1));
-            if (tr.on) {
-                int clk_khz = 0;
-                (void)hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, ctx->device);
-                const double mean = (double)ctr.busy_sum / workers;
-                std::vector<unsigned long long> wt((size_t)workers * 8);
-                if (hipMemcpy(wt.data(), d_trace.as<void>(), wt.size() * 8, hipMemcpyDeviceToHost) == hipSuccess) {
-                    std::vector<uint32_t> ord(workers);
-                    std::iota(ord.begin(), ord.end(), 0u);
-                    std::sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) { return wt[8 * a] > wt[8 * b]; });
-                    for (uint32_t x = 0; x < std::min<uint32_t>(5, workers); x++) {
-                        const unsigned long long *v = &wt[8 * ord[x]];
-                        fprintf(stderr, "[fim %s]   wave %u busy %.3f ms pieces %llu given %llu cands %llu max_k %llu max_depth %llu\n",
-                                tr.tag, ord[x], clk_khz ? v[0] / (double)clk_khz : 0.0, v[1], v[2], v[3], v[4], v[5]);
-                    }
-                }
-                fprintf(stderr, "[fim %s] dfs kernel %.3f ms, %zu tasks, %llu donations, %u workers, busiest %.3f ms, mean %.3f ms, imbalance %.1f, flags %u\n",
-                        tr.tag, dfs_ms, tasks.size(), (unsigned long long)ctr.donations, workers,
-                        clk_khz ? ctr.busy_max / (double)clk_khz : 0.0,
-                        clk_khz ? mean / clk_khz : 0.0, mean > 0 ? ctr.busy_max / mean : 0.0, ctr.flags);
-            }
-            if (ctr.flags & kFlagSpin)
-                return set_error(FIM_E_DEVICE, "work sharing between waves timed out");
-            if (ctr.flags & kFlagDepthOverflow)
-                return set_error(FIM_E_OUTPUT_LIMIT, "an itemset is longer than " +
-                                                         std::to_string(kMaxDepth + 2) + " items");
-            bool again = false;
-            if (ctr.flags & kFlagStackOverflow) {
-                S = std::max<uint64_t>(2 * S, ctr.stack_need + ctr.stack_need / 4);
-                again = true;
-            }
-            if (!sample_mode)
-                for (uint32_t q = 0; q < n_inst; q++)
-                    if (ictr[q].stop)
-                        return set_error(FIM_E_OUTPUT_LIMIT,
-                                         "instance " + std::to_string(q) +
-                                             ": more frequent itemsets than max_itemsets");
-            if ((ctr.flags & kFlagOutOverflow) || ctr.out_used.v > out_cap) {
-                // grow the arena (work sharing varies the need between runs);
-                // a sample run past a hard cap is cut short instead
-                const uint64_t want = ctr.out_used.v + ctr.out_used.v / 2 + 4096;
-                if (sample_mode && want > kSampleOutCap) {
-                    truncated = true;
-                } else {
-                    out_cap = want;
-                    again = true;
-                }
-            }
-            if (!again) break;
-            for (auto &I : insts) I.st.retries++;
-            if (++attempts > 12) return set_error(FIM_E_DEVICE, "persistent kernel did not converge");
-        }
+        DfsLaunch L;
+        L.frame0 = frame0;
+        L.variant = variant;
+        L.n_workers = n_workers;
+        L.claim = opts.classes_per_wg ? opts.classes_per_wg : 1;
+        // Longest back-off of an idle wave.  Idle waves poll counters the
+        // busy waves update; with much work below the root, polling often
+        // slows those updates more than it speeds up hand-overs, while a
+        // short run mostly waits for its last sleepers to wake.
+        L.nap_max = deep_work ? 64 : 16;
+        L.use_graph = use_graph;
+        L.cap_output = (opts.flags & kFlagInternalSample) != 0;
+        L.stop_is_error = !L.cap_output;
+        L.out_cap = L.cap_output ? (1ull << 24) : std::max<uint64_t>(1ull << 24, est_out_words);
+        fim_status ls = run_persistent(ctx, s, tr, desc, tasks, d_out, L);
+        if (ls != FIM_OK) return ls;
+        ctr = L.ctr;
+        ictr = L.ictr;
+        dfs_ms = L.ms;
+        truncated = L.truncated;
+        const uint64_t out_cap = L.out_cap;
+        for (auto &I : insts) I.st.retries += L.retries;
         out_host.n = std::min<uint64_t>(ctr.out_used.v, out_cap);
         if (out_host.n) {
             uint32_t *st = ctx->stage(out_host.n);

@@ -124,10 +124,12 @@ def test_dense_reduced_vs_oracle(fim, ctx):
     db = synth.Database(o_, it, ni, 1000)  # 40 % as in the full dense workload
     say("dense reduced")
     o = oracle.mine_db(db, threads=8)
-    g = gpu_mine(fim, ctx, db)
     assert len(o) > 100000
-    assert_same(g, o)
-    assert g.stats["candidates"] == o.candidates
+    # estimate counted in the run, the thesis's reservoir, and none
+    for flags in (0, fim.FIM_FLAG_RESERVOIR, fim.FIM_FLAG_NO_ESTIMATE):
+        g = gpu_mine(fim, ctx, db, flags=flags)
+        assert_same(g, o, flags)
+        assert g.stats["candidates"] == o.candidates
 
 
 # ---------------------------------------------------------------- options do not change F
@@ -141,6 +143,8 @@ def test_options_invariance(fim, ctx):
         dict(flags=fim.FIM_FLAG_NO_SPLIT), dict(alpha=1.0), dict(alpha=0.05, seed=99),
         dict(flags=fim.FIM_FLAG_DENSE_ROOT), dict(flags=fim.FIM_FLAG_ALWAYS_ESTIMATE),
         dict(flags=fim.FIM_FLAG_NO_PROJECT), dict(flags=fim.FIM_FLAG_NO_PROJECT, workers=8),
+        dict(flags=fim.FIM_FLAG_RESERVOIR | fim.FIM_FLAG_ALWAYS_ESTIMATE),
+        dict(flags=fim.FIM_FLAG_ALWAYS_ESTIMATE, workers=8, alpha=0.1),
         dict(sample_tx=500, sample_fi=1000),
     ]
     for v in variants:
