@@ -162,10 +162,10 @@ void canonical_by_compare(U32Vec &items, U64Vec &off, U32Vec &supp, uint32_t max
 // Items ascending inside every itemset, then the itemsets in lexicographic
 // order: as 128-bit integer keys when every itemset fits (radix partition on
 // the top bits, buckets sorted in parallel), otherwise by comparison.
-void canonicalize(U32Vec &items, U64Vec &off, U32Vec &supp) {
+void canonicalize(U32Vec &items, U64Vec &off, U32Vec &supp, uint32_t threads) {
     const uint64_t n = supp.size();
     if (n == 0) return;
-    const uint32_t n_thr = host_threads(n);
+    const uint32_t n_thr = threads ? threads : host_threads(n);
     uint32_t *it = items.data();
     const uint64_t *o = off.data();
     const uint64_t blk = 8192, nblk = (n + blk - 1) / blk;

@@ -61,6 +61,6 @@ inline uint32_t host_threads(uint64_t work) {
 
 // Puts a result into canonical order: items ascending inside every itemset,
 // itemsets in lexicographic order (a prefix before its extensions).
-void canonicalize(U32Vec &items, U64Vec &off, U32Vec &supp);
+void canonicalize(U32Vec &items, U64Vec &off, U32Vec &supp, uint32_t threads = 0);
 
 }  // namespace fim

@@ -673,15 +673,26 @@ static fim_status count_estimate(fim_ctx *ctx, hipStream_t s, Tracer &tr, std::v
     std::vector<bool> used(n_inst, false);
     uint64_t frame0 = 0;
     uint32_t max_chunks = 0;
+    auto sample_size = [&](uint32_t q) -> uint64_t {
+        const Inst &I = insts[q];
+        const uint64_t nd = std::min<uint64_t>(want_tx, I.db->n_tx / 4);
+        return (!pin[q].estimate || nd < 256 || I.n_freq < 3 || I.l2_atom.empty()) ? 0 : nd;
+    };
+    // the instances' samples are independent: drawn side by side
+    parallel_for(n_inst, host_threads((uint64_t)n_inst * want_tx * 8), [&](uint64_t q) {
+        const uint64_t nd = sample_size((uint32_t)q);
+        if (nd)
+            draw_sample(insts[q].db, insts[q].rank_of_item, nd,
+                        opts.seed ^ (0x51ED270B1DE0ull * (q + 1)), h_off[q], h_items[q]);
+    });
     for (uint32_t q = 0; q < n_inst; q++) {
         Inst &I = insts[q];
         count_at[q + 1] = count_at[q] + I.l2_atom.size();
         const uint64_t N = I.db->n_tx;
-        const uint64_t nd = std::min<uint64_t>(want_tx, N / 4);
-        if (!pin[q].estimate || nd < 256 || I.n_freq < 3 || I.l2_atom.empty()) continue;
+        const uint64_t nd = sample_size(q);
+        if (nd == 0) continue;
         std::vector<uint64_t> &off = h_off[q];
         std::vector<uint32_t> &items = h_items[q];
-        draw_sample(I.db, I.rank_of_item, nd, opts.seed ^ (0x51ED270B1DE0ull * (q + 1)), off, items);
         const uint32_t Ws = (uint32_t)((nd + 31) / 32);
         const uint32_t Wps = std::max<uint32_t>(kRowAlign, (Ws + kRowAlign - 1) / kRowAlign * kRowAlign);
         ENSURE(s_off[q], ctx, off.size() * 8);
@@ -994,13 +1005,13 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         I.st.pair_words = I.st.root_pair_words;
     }
     HIPCHK(hipStreamSynchronize(s));
-    for (uint32_t q = 0; q < n_inst; q++) {
+    parallel_for(n_inst, host_threads((uint64_t)n_inst << 14), [&](uint64_t q) {
         Inst &I = insts[q];
         I.st.root_kernel_ns = (uint64_t)(root_ms * 1e6);
         I.st.kernel_ns = I.st.root_kernel_ns;
         if (I.n_pairs) build_level2(I, by_id);
         else I.l2_off.assign(I.n_freq + 1, 0);
-    }
+    });
 
     tr.mark("bitmaps + root pairs");
     // ---------------- a4: class-size estimate, Partition, LPT order
@@ -1147,7 +1158,9 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         L.use_graph = use_graph;
         L.cap_output = (opts.flags & kFlagInternalSample) != 0;
         L.stop_is_error = !L.cap_output;
-        L.out_cap = L.cap_output ? (1ull << 24) : std::max<uint64_t>(1ull << 24, est_out_words);
+        // a generous arena (kept by the context's block cache between calls):
+        // an overflow costs a second run of the whole launch
+        L.out_cap = L.cap_output ? (1ull << 24) : std::max<uint64_t>(1ull << 26, est_out_words);
         fim_status ls = run_persistent(ctx, s, tr, desc, tasks, d_out, L);
         if (ls != FIM_OK) return ls;
         ctr = L.ctr;
@@ -1342,6 +1355,25 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                              "instance " + std::to_string(q) + " has " +
                                  std::to_string(r_supp[q].size()) + " frequent itemsets > max_itemsets");
     }
+    // canonical order: large instances one after another with all host
+    // threads, the others side by side with one thread each (internal
+    // sample runs keep the deterministic task order: the reservoir does not
+    // need the canonical one)
+    if (!(opts.flags & kFlagInternalSample)) {
+        uint64_t total_sets = 0;
+        for (uint32_t q = 0; q < n_inst; q++) total_sets += r_supp[q].size();
+        std::vector<uint32_t> small;
+        for (uint32_t q = 0; q < n_inst; q++) {
+            if (n_inst == 1 || r_supp[q].size() * 16 > total_sets)
+                canonicalize(r_items[q], r_off[q], r_supp[q]);
+            else
+                small.push_back(q);
+        }
+        parallel_for(small.size(), host_threads(total_sets), [&](uint64_t k) {
+            const uint32_t q = small[k];
+            canonicalize(r_items[q], r_off[q], r_supp[q], 1);
+        });
+    }
     results.assign(n_inst, nullptr);
     for (uint32_t q = 0; q < n_inst; q++) {
         fim_result *R = new (std::nothrow) fim_result();
@@ -1350,9 +1382,6 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             results.clear();
             return set_error(FIM_E_OOM_HOST, "result");
         }
-        // internal sample runs keep the deterministic task order (the
-        // reservoir does not need the canonical one)
-        if (!(opts.flags & kFlagInternalSample)) canonicalize(r_items[q], r_off[q], r_supp[q]);
         R->items.swap(r_items[q]);
         R->off.swap(r_off[q]);
         R->supp.swap(r_supp[q]);
