@@ -176,20 +176,16 @@ def serve_served(F, ctx, handles, minsups, arr, idx, seconds, lanes, first):
         now = time.perf_counter() - t0
         if now > deadline:
             break
-        busy = False
         while k < n and arr[k] <= now:
             pending[srv.submit(handles[idx[k]], minsups[idx[k]])] = k
             k += 1
-            busy = True
-        for t in list(pending):
-            r = srv.poll(t)
-            if r is not None:
-                q = pending.pop(t)
-                lat.append(time.perf_counter() - t0 - arr[q])
-                first.setdefault(int(idx[q]), r)
-                busy = True
-        if not busy:
-            time.sleep(0.0002)
+        # block until a request finishes or the next one arrives
+        wait = min(arr[k] - now, 0.05) if k < n else 0.05
+        t, r = srv.next(max(wait, 0.0))
+        if t:
+            q = pending.pop(t)
+            lat.append(time.perf_counter() - t0 - arr[q])
+            first.setdefault(int(idx[q]), r)
     end = time.perf_counter() - t0
     # requests still open at the deadline count with their waiting time so
     # far (a lower bound), so that overload shows in the percentiles

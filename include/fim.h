@@ -390,7 +390,10 @@ typedef struct fim_server fim_server;
  *                    requests (admission by footprint); 0 = 3/4 of free memory
  *  lanes             batches mined at once, each by a worker thread on a
  *                    HIP stream of its own (0 = 2, at most 8); a lane that is
- *                    idle admits waiting requests while others still run
+ *                    idle admits waiting requests while others still run.
+ *                    Dense databases (an average transaction holds more than
+ *                    a quarter of the item ids) are mined in batches of their
+ *                    own; light requests may pass them in the queue
  *  opts              mining options applied to every request
  */
 typedef struct fim_server_config {
@@ -434,6 +437,17 @@ fim_status fim_server_poll(fim_server *s, uint64_t ticket, fim_result **out);
 
 /* Blocking variant of fim_server_poll. */
 fim_status fim_server_wait(fim_server *s, uint64_t ticket, fim_result **out);
+
+/*
+ * The next finished request, in completion order, whatever its ticket:
+ * waits up to timeout_us microseconds.  On return *ticket is the request's
+ * ticket (0 if none finished in time) and *out its result (ownership passes
+ * to the caller and the ticket is retired), as fim_server_poll would give
+ * it.  Requests already taken with poll / wait are skipped.
+ * Errors: FIM_E_INVALID_ARG, FIM_E_CANCELLED (for that ticket), or the
+ * request's own error.
+ */
+fim_status fim_server_next(fim_server *s, uint64_t timeout_us, uint64_t *ticket, fim_result **out);
 
 /* Cancel a waiting or running request (its later poll gives FIM_E_CANCELLED). */
 fim_status fim_server_cancel(fim_server *s, uint64_t ticket);

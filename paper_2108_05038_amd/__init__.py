@@ -50,7 +50,7 @@ EXPORTED = [
     "fim_db_create", "fim_db_destroy", "fim_db_sizes", "fim_minsup_from_relative", "fim_mine",
     "fim_mine_batch", "fim_autotune", "fim_result_sizes", "fim_result_copy", "fim_result_stats",
     "fim_result_destroy", "fim_server_create", "fim_server_submit", "fim_server_poll",
-    "fim_server_wait", "fim_server_cancel", "fim_server_stats_get", "fim_server_destroy",
+    "fim_server_wait", "fim_server_next", "fim_server_cancel", "fim_server_stats_get", "fim_server_destroy",
     "fim_estimate_sample_sizes", "fim_reservoir_sample", "fim_partition_lpt", "fim_lpt_schedule",
 ]
 
@@ -139,6 +139,7 @@ def lib():
         "fim_server_submit": (i32, [V, V, u32, P(u64)]),
         "fim_server_poll": (i32, [V, u64, P(V)]),
         "fim_server_wait": (i32, [V, u64, P(V)]),
+        "fim_server_next": (i32, [V, u64, P(u64), P(V)]),
         "fim_server_cancel": (i32, [V, u64]),
         "fim_server_stats_get": (i32, [V, P(fim_server_stats)]),
         "fim_server_destroy": (None, [V]),
@@ -434,6 +435,14 @@ class Server:
         h = ctypes.c_void_p()
         _check(lib().fim_server_wait(self.handle, ticket, ctypes.byref(h)))
         return fim_result_take(h)
+
+    def next(self, timeout_s: float):
+        """(ticket, Result) of the next finished request in completion order,
+        or (0, None) if none finishes within timeout_s seconds."""
+        t, h = ctypes.c_uint64(), ctypes.c_void_p()
+        _check(lib().fim_server_next(self.handle, max(0, int(timeout_s * 1e6)), ctypes.byref(t),
+                                     ctypes.byref(h)))
+        return (t.value, fim_result_take(h)) if t.value else (0, None)
 
     def cancel(self, ticket: int):
         _check(lib().fim_server_cancel(self.handle, ticket))

@@ -5,6 +5,9 @@
 
 namespace fim {
 
+thread_local uint32_t g_host_thread_cap = 16;
+
+
 namespace {
 
 typedef unsigned __int128 u128;

@@ -54,9 +54,13 @@ inline void parallel_for(uint64_t count, uint32_t n_thr, Fn fn) {
     for (auto &x : th) x.join();
 }
 
+// Threads the calling thread may use for host stages (a server lane sets a
+// share of the host so that lanes do not oversubscribe it).
+extern thread_local uint32_t g_host_thread_cap;
+
 inline uint32_t host_threads(uint64_t work) {
     if (work < 20000) return 1;
-    return std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    return std::max(1u, std::min({16u, g_host_thread_cap, std::thread::hardware_concurrency()}));
 }
 
 // Puts a result into canonical order: items ascending inside every itemset,

@@ -2,14 +2,20 @@
 //
 // Requests are queued by fim_server_submit (any thread).  The server runs
 // several lanes, each a worker thread with a HIP stream of its own.  An idle
-// lane admits the waiting requests in arrival order while a slot is free and
-// the HBM footprint of their bitmaps fits what the other lanes leave of the
-// budget, and mines them in one batched persistent launch.  Requests that
-// arrive while a batch runs are taken by the next idle lane, so their work
-// overlaps the running batch on the device (and its host-side stages); a
-// finished batch gives its slots and memory back at once.  Results are
-// identical to fim_mine on the same database and minimum support.
+// lane admits waiting requests while a slot is free and the HBM footprint of
+// their bitmaps fits what the other lanes leave of the budget, and mines
+// them in one batched persistent launch.  Dense databases (more than a
+// quarter of the item ids in an average transaction: deep searches with
+// many frequent itemsets) are mined in batches of their own, so that the
+// light requests behind them are not held up: an idle lane takes the oldest
+// request if it is dense, alone, and otherwise the light requests in arrival
+// order.  Requests that arrive while a batch runs are taken by the next idle
+// lane, so their work overlaps the running batch on the device (and its
+// host-side stages); a finished batch gives its slots and memory back at
+// once.  Results are identical to fim_mine on the same database and minimum
+// support.
 #include <atomic>
+#include <chrono>
 #include <condition_variable>
 #include <deque>
 #include <mutex>
@@ -25,6 +31,7 @@ struct Request {
     const fim_db *db;
     uint32_t minsup;
     uint64_t footprint;
+    bool dense;
 };
 
 struct Done {
@@ -50,6 +57,7 @@ struct fim_server {
     std::unordered_map<uint64_t, Done> done;
     std::unordered_map<uint64_t, int> state;  // 0 queued, 1 running, 2 done
     std::unordered_map<uint64_t, bool> cancelled;
+    std::deque<uint64_t> finished;  // tickets in completion order (fim_server_next)
     uint64_t next_ticket = 1;
     uint64_t active = 0, active_bytes = 0;  // over all lanes
     bool stop = false;
@@ -67,34 +75,56 @@ uint64_t footprint(const fim_db *db) {
     return rows * W * 4 + (uint64_t)db->n_item_ids * 16 + (64ull << 20);
 }
 
-// the front request fits the free slots and memory (a request alone on an
-// idle device is always admitted, whatever its size)
-bool admissible(const fim_server *s, uint64_t taken, uint64_t taken_bytes) {
-    if (s->queue.empty()) return false;
+// more than a quarter of the item ids in an average transaction
+bool is_dense(const fim_db *db) {
+    return db->n_tx && db->n_item_ids && 4 * db->nnz > (uint64_t)db->n_tx * db->n_item_ids;
+}
+
+// request r fits the free slots and memory (a request alone on an idle
+// device is always admitted, whatever its size)
+bool fits(const fim_server *s, const Request &r, uint64_t taken, uint64_t taken_bytes) {
     if (s->active + taken >= s->cfg.max_active) return false;
     const uint64_t busy = s->active + taken;
-    return busy == 0 || s->active_bytes + taken_bytes + s->queue.front().footprint <=
-                            s->cfg.hbm_budget_bytes;
+    return busy == 0 || s->active_bytes + taken_bytes + r.footprint <= s->cfg.hbm_budget_bytes;
+}
+
+// an idle lane has something to take
+bool admissible(const fim_server *s) {
+    if (s->queue.empty()) return false;
+    if (s->queue.front().dense) return fits(s, s->queue.front(), 0, 0);
+    for (const Request &r : s->queue)
+        if (!r.dense) return fits(s, r, 0, 0);
+    return false;
 }
 
 void worker_loop(fim_server *s, fim_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
+    // a share of the host for this lane's host-side stages
+    fim::g_host_thread_cap = std::max<uint32_t>(2, 16 / std::max<uint32_t>(1, s->cfg.lanes));
     for (;;) {
         std::vector<Request> batch;
         uint64_t bytes = 0;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            s->cv_work.wait(lk, [&] {
-                return (s->stop && s->queue.empty()) || admissible(s, 0, 0);
-            });
+            s->cv_work.wait(lk, [&] { return (s->stop && s->queue.empty()) || admissible(s); });
             if (s->queue.empty()) return;  // stopping
-            while (admissible(s, batch.size(), bytes)) {
-                const Request &r = s->queue.front();
-                bytes += r.footprint;
-                batch.push_back(r);
-                s->state[r.ticket] = 1;
+            if (s->queue.front().dense) {
+                batch.push_back(s->queue.front());
+                bytes = s->queue.front().footprint;
                 s->queue.pop_front();
+            } else {
+                for (auto it = s->queue.begin(); it != s->queue.end();) {
+                    if (it->dense) {
+                        ++it;
+                        continue;
+                    }
+                    if (!fits(s, *it, batch.size(), bytes)) break;
+                    bytes += it->footprint;
+                    batch.push_back(*it);
+                    it = s->queue.erase(it);
+                }
             }
+            for (const Request &r : batch) s->state[r.ticket] = 1;
             s->active += batch.size();
             s->active_bytes += bytes;
             s->stats.peak_active = std::max<uint64_t>(s->stats.peak_active, s->active);
@@ -120,6 +150,7 @@ void worker_loop(fim_server *s, fim_ctx *ctx) {
                     s->done[t] = Done{st, r, err};
                 }
                 s->state[t] = 2;
+                s->finished.push_back(t);
                 s->stats.completed++;
             }
         }
@@ -179,7 +210,7 @@ extern "C" fim_status fim_server_submit(fim_server *s, const fim_db *db, uint32_
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->queue.size() >= s->cfg.max_queue) return fim::set_error(FIM_E_BUSY, "queue full");
     const uint64_t t = s->next_ticket++;
-    s->queue.push_back(Request{t, db, minsup_abs, footprint(db)});
+    s->queue.push_back(Request{t, db, minsup_abs, footprint(db), is_dense(db)});
     s->state[t] = 0;
     s->stats.submitted++;
     *ticket = t;
@@ -215,6 +246,28 @@ extern "C" fim_status fim_server_wait(fim_server *s, uint64_t ticket, fim_result
     return take(s, ticket, out, true);
 }
 
+extern "C" fim_status fim_server_next(fim_server *s, uint64_t timeout_us, uint64_t *ticket,
+                                      fim_result **out) {
+    if (!s || !ticket || !out) return fim::set_error(FIM_E_INVALID_ARG, "NULL argument");
+    *ticket = 0;
+    *out = nullptr;
+    uint64_t t = 0;
+    {
+        std::unique_lock<std::mutex> lk(s->mu);
+        auto ready = [&] {
+            // skip tickets already taken by poll / wait
+            while (!s->finished.empty() && !s->state.count(s->finished.front()))
+                s->finished.pop_front();
+            return !s->finished.empty();
+        };
+        if (!s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) return FIM_OK;
+        t = s->finished.front();
+        s->finished.pop_front();
+    }
+    *ticket = t;
+    return take(s, t, out, false);
+}
+
 extern "C" fim_status fim_server_cancel(fim_server *s, uint64_t ticket) {
     if (!s) return fim::set_error(FIM_E_INVALID_ARG, "NULL argument");
     std::lock_guard<std::mutex> lk(s->mu);
@@ -228,6 +281,7 @@ extern "C" fim_status fim_server_cancel(fim_server *s, uint64_t ticket) {
             }
         s->done[ticket] = Done{FIM_E_CANCELLED, nullptr, "cancelled"};
         it->second = 2;
+        s->finished.push_back(ticket);
     } else if (it->second == 1) {
         s->cancelled[ticket] = true;
     }

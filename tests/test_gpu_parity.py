@@ -366,6 +366,15 @@ def test_server_results_same_alone_and_mixed(fim, ctx, lanes, max_active, budget
     assert st["completed"] == len(tickets) and st["peak_active"] <= max_active
     if budget == 1:  # every request is admitted alone
         assert st["peak_active"] == 1 and st["steps"] == len(tickets)
+    # the same requests again, taken in completion order
+    tickets = {srv.submit(h, d.minsup): i for i, (d, h) in enumerate(zip(dbs, handles))}
+    seen = 0
+    while seen < len(tickets):
+        t, r = srv.next(30.0)
+        assert t in tickets
+        assert_same(r, alone[tickets[t]], ("next", t))
+        seen += 1
+    assert srv.next(0.01) == (0, None)
     srv.close()
     for h in handles:
         h.close()
