@@ -1,6 +1,7 @@
 // Canonical order of a frequent-itemset result (host).
 #include "fim_canon.h"
 
+#include <algorithm>
 #include <memory>
 
 namespace fim {
@@ -12,11 +13,6 @@ namespace {
 
 typedef unsigned __int128 u128;
 
-struct KeyRec {
-    u128 key;
-    uint64_t i;  // index of the itemset in the input
-};
-
 // exclusive prefix sums of blocks of v computed in parallel
 void block_scan(const std::vector<uint64_t> &block_sum, std::vector<uint64_t> &block_start) {
     block_start.resize(block_sum.size() + 1);
@@ -24,14 +20,51 @@ void block_scan(const std::vector<uint64_t> &block_sum, std::vector<uint64_t> &b
     for (size_t b = 0; b < block_sum.size(); b++) block_start[b + 1] = block_start[b] + block_sum[b];
 }
 
-// itemsets as keys of (item + 1) codes of `bits` bits, most significant
+// items of one itemset ascending (insertion sort: itemsets are short)
+inline void sort_small(uint32_t *a, uint64_t n) {
+    if (n > 24) {
+        std::sort(a, a + n);
+        return;
+    }
+    for (uint64_t i = 1; i < n; i++) {
+        const uint32_t v = a[i];
+        uint64_t j = i;
+        while (j > 0 && a[j - 1] > v) {
+            a[j] = a[j - 1];
+            j--;
+        }
+        a[j] = v;
+    }
+}
+
+// Sort record: the key alone when the support fits in its unused low bits
+// (Packed), else the key and the support.
+template <bool Packed>
+struct KeyRec;
+template <>
+struct KeyRec<true> {
+    u128 key;
+    uint32_t supp() const { return (uint32_t)key; }
+};
+template <>
+struct KeyRec<false> {
+    u128 key;
+    uint32_t s;
+    uint32_t supp() const { return s; }
+};
+
+// Itemsets as keys of (item + 1) codes of `bits` bits, most significant
 // first: a prefix has zero codes where its extensions continue, so it sorts
-// first, and two itemsets compare like their item sequences
+// first, and two itemsets compare like their item sequences.  Each
+// itemset's items are sorted while its key is built, and the sorted result
+// is read back from the keys.
+template <bool Packed>
 void canonical_by_keys(U32Vec &items, U64Vec &off, U32Vec &supp, uint32_t bits, uint32_t n_thr) {
+    typedef KeyRec<Packed> Rec;
     const uint64_t n = supp.size();
     const uint32_t *it = items.data();
     const uint64_t *o = off.data();
-    std::unique_ptr<KeyRec[]> kv(new KeyRec[n]), kb(new KeyRec[n]);
+    std::unique_ptr<Rec[]> kv(new Rec[n]), kb(new Rec[n]);
     const uint32_t T = std::max(1u, n_thr);
     const uint64_t per = (n + T - 1) / T;
     // radix partition on the top B bits (about the first two items)
@@ -41,15 +74,23 @@ void canonical_by_keys(U32Vec &items, U64Vec &off, U32Vec &supp, uint32_t bits, 
     parallel_for(T, T, [&](uint64_t t) {
         const uint64_t a = t * per, e = std::min(n, a + per);
         auto &h = hist[t];
+        uint32_t buf[128];
         for (uint64_t q = a; q < e; q++) {
+            const uint64_t len = o[q + 1] - o[q];
+            for (uint64_t k = 0; k < len; k++) buf[k] = it[o[q] + k];
+            sort_small(buf, len);
             u128 key = 0;
             uint32_t sh = 128;
-            for (uint64_t k = o[q]; k < o[q + 1]; k++) {
+            for (uint64_t k = 0; k < len; k++) {
                 sh -= bits;
-                key |= (u128)(it[k] + 1) << sh;
+                key |= (u128)(buf[k] + 1) << sh;
             }
-            kv[q].key = key;
-            kv[q].i = q;
+            if constexpr (Packed) {
+                kv[q].key = key | supp[q];
+            } else {
+                kv[q].key = key;
+                kv[q].s = supp[q];
+            }
             h[(uint32_t)(key >> (128 - B))]++;
         }
     });
@@ -79,16 +120,23 @@ void canonical_by_keys(U32Vec &items, U64Vec &off, U32Vec &supp, uint32_t bits, 
     parallel_for(big.size(), T, [&](uint64_t k) {
         const uint32_t b = big[k];
         std::sort(kb.get() + bstart[b], kb.get() + bstart[b + 1],
-                  [](const KeyRec &x, const KeyRec &y) { return x.key < y.key; });
+                  [](const Rec &x, const Rec &y) { return x.key < y.key; });
     });
-    // gather: lengths per block, block starts, then every block in parallel
+    // lengths (non-zero codes) per block, block starts, then every block
+    // decodes its keys in parallel
     const uint64_t blk = 1u << 14, nblk = (n + blk - 1) / blk;
+    const uint64_t mask = (1ull << bits) - 1;
+    const uint32_t per_key = 128 / bits;
     std::vector<uint64_t> bsum(nblk, 0), bst;
+    auto code = [&](const u128 &key, uint32_t k) {
+        return (uint64_t)(key >> (128 - bits * (k + 1))) & mask;
+    };
     parallel_for(nblk, T, [&](uint64_t b) {
         uint64_t s = 0;
         for (uint64_t q = b * blk; q < std::min(n, (b + 1) * blk); q++) {
-            const uint64_t a = kb[q].i;
-            s += o[a + 1] - o[a];
+            uint32_t k = 0;
+            while (k < per_key && code(kb[q].key, k)) k++;
+            s += k;
         }
         bsum[b] = s;
     });
@@ -98,10 +146,14 @@ void canonical_by_keys(U32Vec &items, U64Vec &off, U32Vec &supp, uint32_t bits, 
     parallel_for(nblk, T, [&](uint64_t b) {
         uint64_t w = bst[b];
         for (uint64_t q = b * blk; q < std::min(n, (b + 1) * blk); q++) {
-            const uint64_t a = kb[q].i;
-            for (uint64_t k = o[a]; k < o[a + 1]; k++) ni[w++] = it[k];
+            const u128 key = kb[q].key;
+            for (uint32_t k = 0; k < per_key; k++) {
+                const uint64_t c = code(key, k);
+                if (!c) break;
+                ni[w++] = (uint32_t)c - 1;
+            }
             no[q + 1] = w;
-            ns[q] = supp[a];
+            ns[q] = kb[q].supp();
         }
     });
     no[0] = 0;
@@ -171,6 +223,7 @@ void canonicalize(U32Vec &items, U64Vec &off, U32Vec &supp, uint32_t threads) {
     const uint32_t n_thr = threads ? threads : host_threads(n);
     uint32_t *it = items.data();
     const uint64_t *o = off.data();
+    // largest item and longest itemset
     const uint64_t blk = 8192, nblk = (n + blk - 1) / blk;
     std::vector<uint32_t> bmax(nblk, 0);
     std::vector<uint64_t> blen(nblk, 0);
@@ -178,8 +231,7 @@ void canonicalize(U32Vec &items, U64Vec &off, U32Vec &supp, uint32_t threads) {
         uint32_t mi = 0;
         uint64_t ml = 0;
         for (uint64_t i = b * blk; i < std::min(n, (b + 1) * blk); i++) {
-            if (o[i + 1] - o[i] > 1) std::sort(it + o[i], it + o[i + 1]);
-            mi = std::max(mi, it[o[i + 1] - 1]);
+            for (uint64_t k = o[i]; k < o[i + 1]; k++) mi = std::max(mi, it[k]);
             ml = std::max<uint64_t>(ml, o[i + 1] - o[i]);
         }
         bmax[b] = mi;
@@ -189,10 +241,17 @@ void canonicalize(U32Vec &items, U64Vec &off, U32Vec &supp, uint32_t threads) {
     const uint64_t max_len = *std::max_element(blen.begin(), blen.end());
     uint32_t bits = 1;
     while (bits < 32 && ((uint64_t)max_item + 1) >> bits) bits++;
-    if ((uint64_t)bits * max_len <= 128)
-        canonical_by_keys(items, off, supp, bits, n_thr);
-    else
+    if ((uint64_t)bits * max_len + 32 <= 128) {
+        canonical_by_keys<true>(items, off, supp, bits, n_thr);
+    } else if ((uint64_t)bits * max_len <= 128) {
+        canonical_by_keys<false>(items, off, supp, bits, n_thr);
+    } else {
+        parallel_for(nblk, n_thr, [&](uint64_t b) {
+            for (uint64_t i = b * blk; i < std::min(n, (b + 1) * blk); i++)
+                if (o[i + 1] - o[i] > 1) sort_small(it + o[i], o[i + 1] - o[i]);
+        });
         canonical_by_compare(items, off, supp, max_item, n_thr);
+    }
 }
 
 }  // namespace fim

@@ -730,9 +730,8 @@ static fim_status count_estimate(fim_ctx *ctx, hipStream_t s, Tracer &tr, std::v
     }
     if (tasks.empty()) return FIM_OK;
     // largest classes first
-    std::stable_sort(tasks.begin(), tasks.end(), [&](const Task &a, const Task &b) {
-        return a.r1 > b.r1;
-    });
+    std::stable_sort(tasks.begin(), tasks.end(),
+                     [&](const Task &a, const Task &b) { return a.r1 > b.r1; });
     DevBuf d_count(ctx), d_out(ctx);
     ENSURE(d_count, ctx, std::max<uint64_t>(count_at[n_inst], 1) * 8);
     HIPCHK(launch_fill_u32(d_count.as<uint32_t>(), std::max<uint64_t>(count_at[n_inst], 1) * 2, 0u, s));
