@@ -17,7 +17,8 @@ OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfim.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["fim_kernels.hip", "fim_runtime.hip", "fim_plan.hip", "fim_server.hip", "fim_canon.cpp"]
+SOURCES = ["fim_kernels.hip", "fim_runtime.hip", "fim_plan.hip", "fim_server.hip", "fim_order.hip",
+           "fim_canon.cpp"]
 
 # Packed FP32 instructions are switched off for every HIP file (the code has
 # no floating-point vector math; the flag keeps the compiler from forming
@@ -48,7 +49,7 @@ def _compile(src: str) -> str:
 def build(verbose: bool = False) -> str:
     """Compile every source and link ``libfim.so``; returns its path."""
     os.makedirs(OBJDIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [_hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,-z,defs", "-o", tmp] + objs + ["-lpthread"]

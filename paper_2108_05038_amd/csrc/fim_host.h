@@ -113,6 +113,18 @@ namespace fim {
 // exceeded budget marks the results truncated instead of failing.
 constexpr uint32_t kFlagInternalSample = 0x80000000u;
 
+// Internal option flag: the persistent kernel reports variable-length
+// records that the host puts in canonical order (used when an itemset does
+// not fit a 128-bit key of its instance's item codes).
+constexpr uint32_t kFlagInternalRecords = 0x40000000u;
+
+// The canonical order of key records (see fim_order.hip): n 8-word records
+// at d_rec; bits_of[q] the code width of instance q; first[q] receives the
+// position of instance q's first itemset in the sorted result (~0 if none).
+fim_status gpu_order(fim_ctx *ctx, hipStream_t s, const uint32_t *d_rec, uint64_t n,
+                     const std::vector<uint32_t> &bits_of, std::vector<uint64_t> &first,
+                     U64Vec &off, U32Vec &items, U32Vec &supp);
+
 // Limits of an internal sample run: itemsets below the first level per
 // instance, and words of the output arena of the whole run.
 constexpr unsigned long long kSampleRecordBudget = 1ull << 21;

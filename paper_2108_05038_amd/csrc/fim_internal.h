@@ -40,6 +40,12 @@ struct InstDesc {
     // estimate run: itemsets counted per second-level class (l2 atom index)
     // instead of reported; null in a mining run
     unsigned long long *class_count;
+    // key mode (> 0): every itemset is written as an 8-word record holding
+    // its item ids ascending as (id + 1) codes of key_bits bits in a 128-bit
+    // key, its support and the instance (the arena is then a flat array of
+    // records); 0: variable-length records in per-piece chunks
+    uint32_t key_bits;
+    uint32_t pad2_;
 };
 
 // One unit of work of the persistent kernel: rows [r0, r1) of the
@@ -95,6 +101,7 @@ constexpr unsigned kFlagStackOverflow = 1u;
 constexpr unsigned kFlagDepthOverflow = 2u;
 constexpr unsigned kFlagOutOverflow = 4u;
 constexpr unsigned kFlagSpin = 8u;  // a bounded wait of the work sharing ran out
+constexpr unsigned kFlagKeyOverflow = 16u;  // an itemset too long for a 128-bit key
 
 // Output arena: chunks with a header of kChunkHeader words (size, task,
 // seq, used, inst) followed by records of kRecHeader + len words (len, support,

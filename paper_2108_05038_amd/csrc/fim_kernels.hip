@@ -446,6 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_tidlist(const uint32_t *__restrict__
 }
 
 constexpr uint32_t kProjectMaxRows = 64;
+constexpr uint32_t kProjGroup = 1;  // lanes per (item, transaction) pair (more were slower: suffixes are short)
 
 // block (x, y): rows [i0, i0 + R) (x counted from the last, heaviest rows)
 // against partner columns [j0, j0 + J); counters cnt[R][J] in LDS
@@ -463,10 +464,14 @@ __global__ __launch_bounds__(kBlock) void k_root_project(
     for (uint32_t e = threadIdx.x; e < R * J; e += kBlock) cnt[e] = 0;
     for (uint32_t e = threadIdx.x; e <= i1 - i0; e += kBlock) s_off[e] = tl_off[i0 + e];
     __syncthreads();
+    // kProjGroup lanes take one (a, t) pair together: the same search, then
+    // the ranks after a read kProjGroup at a time (independent loads)
     unsigned long long wk = 0;
     const uint64_t p1 = s_off[i1 - i0];
+    const uint32_t gl = threadIdx.x % kProjGroup, gid = threadIdx.x / kProjGroup;
+    constexpr uint32_t kGroups = kBlock / kProjGroup;
     uint32_t a_rel = 0;
-    for (uint64_t p = s_off[0] + threadIdx.x; p < p1; p += kBlock) {
+    for (uint64_t p = s_off[0] + gid; p < p1; p += kGroups) {
         while (s_off[a_rel + 1] <= p) a_rel++;  // p only grows: the row index only grows
         const uint32_t a = i0 + a_rel;
         const uint32_t t = tl[p];
@@ -481,9 +486,9 @@ __global__ __launch_bounds__(kBlock) void k_root_project(
             else hi = mid;
         }
         uint32_t *row = cnt + a_rel * J;
-        for (uint32_t q = lo; q < L; q++) {
+        for (uint32_t q = lo + gl; q < L; q += kProjGroup) {
             const uint32_t b = rk[b0 + q];
-            if (b >= j1) break;
+            if (b >= j1) break;  // ranks ascend: later lanes' ranks are larger too
             atomicAdd(&row[b - j0], 1u);
             wk++;
         }
@@ -793,6 +798,79 @@ __device__ __forceinline__ bool donation_wanted(DfsCounters *ctr) {
 // CPL > 0: a row spans at most 64 * CPL chunks and the expanded row is held
 // in registers (CPL chunks per lane) for all its pairs and child rows, with
 // two partner rows loaded per round.  CPL = 0: rows of any width, streamed.
+// Key mode: the nf itemsets prefix + child as 8-word records (128-bit key
+// of ascending (id + 1) codes, support, instance) at the end of the flat
+// arena.  The prefix's item ids are sorted once in LDS; each lane inserts
+// its child's id while packing the key.
+__device__ void emit_keys(const InstDesc &I, uint32_t inst, uint32_t len, const uint32_t *tmp,
+                          uint32_t nj, uint32_t nf, WaveShared &ws, uint32_t *out, uint64_t out_cap,
+                          DfsCounters *ctr) {
+    const uint32_t lane = lane_id();
+    const uint32_t bits = I.key_bits;
+    if (len * bits > 128) {
+        if (lane == 0) atomicOr(&ctr->flags, kFlagKeyOverflow);
+        return;
+    }
+    // the prefix's item ids ascending in LDS: lane q ranks id q among the
+    // distinct ids (len - 1 <= kMaxDepth + 1 < 2 * kWave)
+    uint32_t *sp = ws.stage;  // 4 * kStageWords >= kMaxDepth + 2 words
+    const uint32_t np = len - 1;
+    uint32_t v0 = lane < np ? I.item_of_rank[ws.prefix[lane]] : ~0u;
+    uint32_t v1 = lane + kWave < np ? I.item_of_rank[ws.prefix[lane + kWave]] : ~0u;
+    uint32_t p0 = 0, p1 = 0;
+    for (uint32_t q = 0; q < np && q < (uint32_t)kWave; q++) {
+        const uint32_t u = __shfl(v0, (int)q, kWave);
+        p0 += u < v0 ? 1u : 0u;
+        p1 += u < v1 ? 1u : 0u;
+    }
+    for (uint32_t q = kWave; q < np; q++) {
+        const uint32_t u = __shfl(v1, (int)(q - kWave), kWave);
+        p0 += u < v0 ? 1u : 0u;
+        p1 += u < v1 ? 1u : 0u;
+    }
+    if (lane < np) sp[p0] = v0;
+    if (lane + kWave < np) sp[p1] = v1;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(&ctr->out_used.v, 8ull * nf);
+    base = shfl_u64(base, 0);
+    if (base + 8ull * nf > out_cap) {
+        if (lane == 0) atomicOr(&ctr->flags, kFlagOutOverflow);
+    } else {
+        for (uint32_t e = lane; e < nf; e += kWave) {
+            const uint32_t c = I.item_of_rank[tmp[e]];
+            unsigned long long hi = 0, lo = 0;
+            uint32_t sh = 128;
+            auto put = [&](uint32_t x) {
+                const unsigned long long code = (unsigned long long)x + 1;
+                sh -= bits;
+                if (sh >= 64) hi |= code << (sh - 64);
+                else if (sh + bits <= 64) lo |= code << sh;
+                else {
+                    hi |= code >> (64 - sh);
+                    lo |= code << sh;
+                }
+            };
+            bool ins = false;
+            for (uint32_t q = 0; q + 1 < len; q++) {
+                const uint32_t v = sp[q];
+                if (!ins && c < v) {
+                    put(c);
+                    ins = true;
+                }
+                put(v);
+            }
+            if (!ins) put(c);
+            uint4 *o = reinterpret_cast<uint4 *>(out + base + 8ull * e);
+            o[0] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+            o[1] = make_uint4(tmp[nj + e], inst, 0u, 0u);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // the instance went over its record budget (wave-uniform)
 __device__ __forceinline__ bool inst_stopped(const InstDesc &I, InstCounters *ictr, uint32_t inst) {
     if (I.rec_budget == 0) return false;
@@ -964,11 +1042,13 @@ __device__ void process_frame(const InstDesc &I, uint32_t inst, uint32_t task, u
                 }
             }
             const uint32_t rec = kRecHeader + len;
-            st.out_words += (unsigned long long)nf * rec;
+            st.out_words += (unsigned long long)nf * (I.key_bits ? 8u : rec);
             if (I.class_count) {
                 // estimate run: only the number of itemsets per second-level class
                 if (lane == 0) atomicAdd(&I.class_count[l2_class(plen, l2_ref, depth, r, ws)],
                                          (unsigned long long)nf);
+            } else if (I.key_bits) {
+                emit_keys(I, inst, len, tmp, nj, nf, ws, out, out_cap, ctr);
             } else if (chunk_reserve(oc, nf * rec, task, inst, out, out_cap, ctr)) {
                 uint32_t *obase = out + oc.base + oc.pos;
                 for (uint32_t e = lane; e < nf; e += kWave) {
@@ -979,7 +1059,7 @@ __device__ void process_frame(const InstDesc &I, uint32_t inst, uint32_t task, u
                     o[2 + len - 1] = tmp[e];
                 }
             }
-            oc.pos += nf * rec;
+            if (!I.key_bits) oc.pos += nf * rec;
         }
 
         // the child class [prefix + a_r | frequent later atoms]

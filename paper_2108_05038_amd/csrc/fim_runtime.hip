@@ -494,6 +494,9 @@ struct DfsLaunch {
     bool cap_output = false;     // a full output arena ends the run (internal sample runs)
     bool stop_is_error = true;   // an instance over its record budget is an error
     uint64_t out_cap = 1ull << 24;
+    // words placed at the start of the arena before the launch (key mode:
+    // the records of the itemsets found before the persistent kernel)
+    const std::vector<uint32_t> *prefix = nullptr;
     DfsCounters ctr{};
     std::vector<InstCounters> ictr;
     float ms = 0.f;
@@ -545,6 +548,7 @@ static fim_status run_persistent(fim_ctx *ctx, hipStream_t s, Tracer &tr,
         if (((uint64_t)workers * S > budget_words && S > budget_words / 4) || S > kMaxStack)
             return set_error(FIM_E_OOM_DEVICE, "a first-level class does not fit on the device");
         ENSURE(d_stack, ctx, (size_t)workers * S * 4);
+        if (L.prefix && L.prefix->size() + 8 > L.out_cap) L.out_cap = L.prefix->size() * 2 + 4096;
         ENSURE(d_out, ctx, (size_t)L.out_cap * 4);
         ENSURE(d_ctr, ctx, sizeof(DfsCounters));
         ENSURE(d_ictr, ctx, sizeof(InstCounters) * n_inst);
@@ -556,6 +560,13 @@ static fim_status run_persistent(fim_ctx *ctx, hipStream_t s, Tracer &tr,
         ENSURE(d_heap, ctx, heap_words * 4);
         HIPCHK(launch_fill_u32(d_slots.as<uint32_t>(), n_slots * 2, 0u, s));
         HIPCHK(launch_fill_u32(d_ctr.as<uint32_t>(), sizeof(DfsCounters) / 4, 0u, s));
+        unsigned long long start = 0;
+        if (L.prefix && !L.prefix->empty()) {
+            start = L.prefix->size();
+            HIPCHK(hipMemcpyAsync(d_out.as<void>(), L.prefix->data(), start * 4, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(reinterpret_cast<char *>(d_ctr.as<void>()) + offsetof(DfsCounters, out_used),
+                                  &start, 8, hipMemcpyHostToDevice, s));
+        }
         HIPCHK(launch_fill_u32(d_ictr.as<uint32_t>(), sizeof(InstCounters) / 4 * n_inst, 0u, s));
         if (L.cap_output) HIPCHK(launch_fill_u32(d_out.as<uint32_t>(), L.out_cap, 0u, s));
         HIPCHK(hipEventRecord(ev0, s));
@@ -1087,6 +1098,13 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         }
     }
 
+    // With little work below the root class (small classes, no estimate
+    // wanted) a launch with every resident wave mostly makes the waves
+    // contend for the shared counters and caches: about one wave per eight
+    // tasks is faster (measured on sparse-200k: 0.26 ms with 256 waves,
+    // 0.48 ms with 2048).
+    if (!opts.workers && !deep_work && !tasks.empty())
+        n_workers = std::min<uint32_t>(n_workers, std::max<uint32_t>(256, (uint32_t)(tasks.size() / 8 + 3) / 4 * 4));
     tr.mark("estimate + plan");
     // ---------------- a5-a8: one persistent launch over every task
     DevBuf d_out(ctx);
@@ -1101,6 +1119,16 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
     DfsCounters ctr{};
     float dfs_ms = 0.f;
     bool truncated = false;
+    // Key mode: the persistent kernel writes fixed key records that the GPU
+    // sorts into canonical order (fim_order.hip).  Item codes of instance q
+    // take bits_of[q] bits (ids 0 .. n_item_ids - 1 as 1 .. n_item_ids).
+    const bool key_mode = !(opts.flags & (kFlagInternalSample | kFlagInternalRecords)) &&
+                          deep && !tasks.empty();
+    std::vector<uint32_t> bits_of(n_inst, 1);
+    for (uint32_t q = 0; q < n_inst; q++)
+        while ((uint64_t)insts[q].db->n_item_ids >> bits_of[q]) bits_of[q]++;
+    bool keys_done = false;
+    std::vector<uint32_t> key_prefix;  // records of the 1- and 2-itemsets
     if (deep && !tasks.empty()) {
         std::vector<InstDesc> desc(n_inst);
         uint64_t frame0 = 0;
@@ -1138,6 +1166,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             // instance then has no estimate).  A real run stops early once
             // it is certain to exceed max_itemsets.
             D.rec_budget = sample_run ? kSampleRecordBudget : opts.max_itemsets;
+            D.key_bits = key_mode ? bits_of[q] : 0u;
         }
         for (const Task &T : tasks) {
             const Inst &I = insts[T.inst];
@@ -1160,15 +1189,48 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         // a generous arena (kept by the context's block cache between calls):
         // an overflow costs a second run of the whole launch
         L.out_cap = L.cap_output ? (1ull << 24) : std::max<uint64_t>(1ull << 26, est_out_words);
+        if (key_mode) {
+            auto put = [&](uint32_t q, const uint32_t *ids, uint32_t n, uint32_t supp) {
+                unsigned __int128 k = 0;
+                uint32_t sh = 128;
+                for (uint32_t x = 0; x < n; x++) {
+                    sh -= bits_of[q];
+                    k |= (unsigned __int128)(ids[x] + 1) << sh;
+                }
+                const uint64_t lo = (uint64_t)k, hi = (uint64_t)(k >> 64);
+                const uint32_t w[8] = {(uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi,
+                                       (uint32_t)(hi >> 32), supp, q, 0u, 0u};
+                key_prefix.insert(key_prefix.end(), w, w + 8);
+            };
+            for (uint32_t q = 0; q < n_inst; q++) {
+                const Inst &I = insts[q];
+                for (uint32_t r = 0; r < I.n_freq; r++) put(q, &I.item_of_rank[r], 1, I.supp_of_rank[r]);
+                if (opts.max_len != 1)
+                    for (uint32_t i = 0; i < I.n_freq; i++)
+                        for (uint32_t k = I.l2_off[i]; k < I.l2_off[i + 1]; k++) {
+                            uint32_t ids[2] = {I.item_of_rank[i], I.item_of_rank[I.l2_atom[k]]};
+                            if (ids[0] > ids[1]) std::swap(ids[0], ids[1]);
+                            put(q, ids, 2, I.l2_supp[k]);
+                        }
+            }
+            L.prefix = &key_prefix;
+            L.out_cap = std::max<uint64_t>(L.out_cap, 2 * key_prefix.size());
+        }
         fim_status ls = run_persistent(ctx, s, tr, desc, tasks, d_out, L);
         if (ls != FIM_OK) return ls;
+        if (key_mode && (L.ctr.flags & kFlagKeyOverflow)) {
+            // an itemset longer than a key holds: the same call with records
+            fim_options ro = opts_in;
+            ro.flags |= kFlagInternalRecords;
+            return mine_many(ctx, reqs, ro, results, use_graph);
+        }
         ctr = L.ctr;
         ictr = L.ictr;
         dfs_ms = L.ms;
         truncated = L.truncated;
         const uint64_t out_cap = L.out_cap;
         for (auto &I : insts) I.st.retries += L.retries;
-        out_host.n = std::min<uint64_t>(ctr.out_used.v, out_cap);
+        out_host.n = key_mode ? 0 : std::min<uint64_t>(ctr.out_used.v, out_cap);
         if (out_host.n) {
             uint32_t *st = ctx->stage(out_host.n);
             if (!st) return set_error(FIM_E_OOM_HOST, "pinned staging buffer");
@@ -1182,8 +1244,46 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
     // ---------------- a9: results in canonical order
     std::vector<U32Vec> r_items(n_inst), r_supp(n_inst);
     std::vector<U64Vec> r_off(n_inst);
+    if (key_mode) {
+        std::vector<uint64_t> first;
+        U64Vec all_off;
+        U32Vec all_items, all_supp;
+        fim_status os = gpu_order(ctx, s, d_out.as<uint32_t>(), ctr.out_used.v / 8, bits_of, first,
+                                  all_off, all_items, all_supp);
+        if (os != FIM_OK) return os;
+        const uint64_t n_all = all_supp.size();
+        // instance q's itemsets are the sorted positions [first[q], next first)
+        std::vector<uint64_t> lo(n_inst, n_all), hi(n_inst, n_all);
+        uint64_t nxt = n_all;
+        for (uint32_t q = n_inst; q-- > 0;) {
+            if (first[q] != ~0ull) {
+                lo[q] = first[q];
+                hi[q] = nxt;
+                nxt = first[q];
+            }
+        }
+        parallel_for(n_inst, host_threads(n_all), [&](uint64_t q) {
+            const uint64_t a = lo[q], b = hi[q];
+            r_off[q].resize(b - a + 1);
+            const uint64_t base = all_off[a];
+            for (uint64_t x = a; x <= b; x++) r_off[q][x - a] = all_off[x] - base;
+            r_items[q].assign(all_items.begin() + base, all_items.begin() + all_off[b]);
+            r_supp[q].assign(all_supp.begin() + a, all_supp.begin() + b);
+        });
+        keys_done = true;
+    }
     for (uint32_t q = 0; q < n_inst; q++) {
         Inst &I = insts[q];
+        if (keys_done) {
+            I.st.candidates += ictr[q].candidates;
+            I.st.pair_words += ictr[q].pair_words;
+            I.st.dfs_bytes_algorithmic = 8 * ictr[q].row_words;
+            I.st.bytes_algorithmic += I.st.dfs_bytes_algorithmic;
+            I.st.dfs_kernel_ns = (uint64_t)(dfs_ms * 1e6);
+            I.st.kernel_ns += I.st.dfs_kernel_ns;
+            I.st.n_tasks = 0;
+            continue;
+        }
         r_off[q].push_back(0);
         for (uint32_t r = 0; r < I.n_freq; r++) {
             r_items[q].push_back(I.item_of_rank[r]);
@@ -1209,7 +1309,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         I.st.n_tasks = 0;
     }
     for (const Task &T : tasks) insts[T.inst].st.n_tasks++;
-    {
+    if (!keys_done) {
         // chunks of the output arena, put back in (task, chunk number) order
         struct Chunk {
             uint32_t task, seq, inst;
@@ -1358,7 +1458,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
     // threads, the others side by side with one thread each (internal
     // sample runs keep the deterministic task order: the reservoir does not
     // need the canonical one)
-    if (!(opts.flags & kFlagInternalSample)) {
+    if (!(opts.flags & kFlagInternalSample) && !keys_done) {
         uint64_t total_sets = 0;
         for (uint32_t q = 0; q < n_inst; q++) total_sets += r_supp[q].size();
         std::vector<uint32_t> small;

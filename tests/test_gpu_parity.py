@@ -202,6 +202,21 @@ def test_projection_with_work_sharing(fim, ctx):
         assert g.stats["candidates"] == o.candidates, v
 
 
+def test_long_itemsets_over_wide_ids(fim, ctx):
+    # 2^20 item ids need 21-bit codes: itemsets of more than 6 items do not fit
+    # a 128-bit key, so the call falls back to variable-length records
+    big = [5, 77, 1000, 65535, 99999, 400000, 777777, 1048575]
+    T = [big] * 3 + [big[:3]] * 2 + [[1, 2]] * 4 + [[2, 3, 4]] * 2
+    db = synth.from_lists(T, n_items=1 << 20, minsup=2)
+    say("long itemsets, wide ids")
+    o = oracle.mine_db(db, "bruteforce")
+    assert max(len(u) for u in o.itemsets()) == 8
+    assert_same(gpu_mine(fim, ctx, db), o)
+    # short enough for keys with wide ids
+    db6 = synth.from_lists([big[:6]] * 3 + [[1, 2]] * 4, n_items=1 << 20, minsup=2)
+    assert_same(gpu_mine(fim, ctx, db6), oracle.mine_db(db6, "bruteforce"))
+
+
 def test_max_len(fim, ctx):
     o_, it, ni = synth.basket(5, 3000, 100, 12.0, 200, 5.0)
     db = synth.Database(o_, it, ni, 10)
