@@ -275,7 +275,7 @@ def main(argv=None):
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-rates", default="50,200", help="request rates (req/s)")
-    ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--serve-seconds", type=float, default=12.0)
     ap.add_argument("--serve-pool", type=int, default=128, help="distinct requests (<= 512)")
     ap.add_argument("--lanes", type=int, default=0, help="server lanes (0 = default)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",

@@ -97,7 +97,7 @@ void fim_ctx_destroy(fim_ctx *ctx);
 
 /*
  * Device blocks the library frees are kept by the context for reuse by its
- * next calls (up to half of the device's memory), so that steady-state calls
+ * next calls (up to a quarter of the device's memory), so that steady-state calls
  * make no allocator calls.  This gives them back to the allocator now.  They
  * are also given back when an allocation fails and when the context is
  * destroyed.
@@ -146,8 +146,10 @@ fim_status fim_minsup_from_relative(uint64_t n_tx, double rel, uint32_t *out_abs
 #define FIM_FLAG_ORDER_BY_ID 0x2u  /* extensions ordered by item id, not ascending support */
 #define FIM_FLAG_NO_SPLIT 0x4u     /* never split first-level classes */
 /* draw the database sample even when the classes below the root hold under
- * 1/20 of the root class's candidate pairs (by default the sample is then
- * skipped: there is no work worth balancing) */
+ * 1/20 of the root class's candidate pairs, or the database has fewer than
+ * 16 |D~| transactions (by default the sample is then skipped: there is no
+ * work worth balancing, or mining the sample would cost about as much as
+ * mining the database) */
 #define FIM_FLAG_ALWAYS_ESTIMATE 0x8u
 /*
  * The root class (all pairs of frequent items) has three exact kernels; by
@@ -384,7 +386,7 @@ typedef struct fim_server fim_server;
 
 /*
  * Server configuration.
- *  max_active        requests resident on the GPU at once (slots)
+ *  max_active        requests resident on the GPU at once (slots; 0 = 16)
  *  max_queue         waiting requests before submit returns FIM_E_BUSY
  *  hbm_budget_bytes  device memory the server may hold for resident
  *                    requests (admission by footprint); 0 = 3/4 of free memory

@@ -116,8 +116,9 @@ void fim_ctx::dfree(void *p) {
         raw_free(p);
         return;
     }
-    // keep it for the next call unless the cache already holds half the device
-    if (cached_bytes + it->second > total_mem / 2) {
+    // keep it for the next call unless the cache already holds a quarter of
+    // the device (a server runs several contexts on one device)
+    if (cached_bytes + it->second > total_mem / 4) {
         block_class.erase(it);
         lk.unlock();
         raw_free(p);
@@ -529,7 +530,7 @@ static fim_status run_persistent(fim_ctx *ctx, hipStream_t s, Tracer &tr,
     L.ictr.assign(n_inst, InstCounters{});
     // per-worker stack: room for the largest first frame and its subtree,
     // within a quarter of device memory in total
-    uint64_t S = std::max<uint64_t>(4 * L.frame0, 1ull << 20);
+    uint64_t S = std::max<uint64_t>(4 * L.frame0, 1ull << 18);
     const uint64_t kMaxStack = 0xFFFFFFF0ull;  // frame offsets are 32-bit
     const uint64_t budget_words = (uint64_t)(ctx->total_mem / 4) / 4;
     // work sharing between waves
@@ -1057,7 +1058,14 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                 below += f * (f ? f - 1 : 0) / 2;
             }
             const uint64_t root = (uint64_t)I.n_freq * (I.n_freq ? I.n_freq - 1 : 0) / 2;
-            pin[q].estimate = (opts.flags & FIM_FLAG_ALWAYS_ESTIMATE) || 20 * below >= root;
+            // The sample has about as many frequent itemsets as the database
+            // (same relative support), so mining it costs about as much as
+            // mining the database unless the database is much longer than
+            // the sample: the estimate is drawn for at least 16 |D~|
+            // transactions.
+            const uint64_t want_tx = opts.sample_tx ? opts.sample_tx : default_sample_tx(0.02, 0.05);
+            pin[q].estimate = (opts.flags & FIM_FLAG_ALWAYS_ESTIMATE) ||
+                              (20 * below >= root && I.db->n_tx >= 16 * want_tx);
             deep_work = deep_work || 20 * below >= root;
         }
         fim_status ps = FIM_OK;
@@ -1171,7 +1179,12 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         for (const Task &T : tasks) {
             const Inst &I = insts[T.inst];
             const uint64_t k = I.l2_off[T.node + 1] - I.l2_off[T.node] - T.r0;
-            frame0 = std::max<uint64_t>(frame0, k * I.Wp + 3 * k);
+            // the width the piece's rows will have: projected on the item's
+            // cover when that is at most a quarter of the row
+            const uint32_t s1 = I.supp_of_rank[T.node];
+            const uint64_t wq = std::max<uint64_t>(kRowAlign, ((s1 + 31) / 32 + kRowAlign - 1) / kRowAlign * kRowAlign);
+            const bool proj = !(opts.flags & FIM_FLAG_NO_PROJECT) && 4 * wq <= I.Wp;
+            frame0 = std::max<uint64_t>(frame0, k * (proj ? wq : I.Wp) + 3 * k);
         }
         DfsLaunch L;
         L.frame0 = frame0;

@@ -169,7 +169,11 @@ extern "C" fim_status fim_server_create(fim_ctx *ctx, const fim_server_config *c
     if (!s) return fim::set_error(FIM_E_OOM_HOST, "server");
     s->ctx = ctx;
     if (cfg) s->cfg = *cfg;
-    if (s->cfg.max_active == 0) s->cfg.max_active = 64;
+    // defaults measured on MI355X with the serving pool, closed loop: two
+    // lanes of at most 16 requests 216 req/s, 64 requests 181 req/s, one
+    // lane 192 req/s, three lanes far fewer (the one-request-per-call
+    // miner: 133 req/s)
+    if (s->cfg.max_active == 0) s->cfg.max_active = 16;
     if (s->cfg.max_queue == 0) s->cfg.max_queue = 1u << 16;
     if (s->cfg.lanes == 0) s->cfg.lanes = 2;
     if (s->cfg.lanes > 8) {

@@ -125,8 +125,9 @@ def test_dense_reduced_vs_oracle(fim, ctx):
     say("dense reduced")
     o = oracle.mine_db(db, threads=8)
     assert len(o) > 100000
-    # estimate counted in the run, the thesis's reservoir, and none
-    for flags in (0, fim.FIM_FLAG_RESERVOIR, fim.FIM_FLAG_NO_ESTIMATE):
+    # default, estimate counted in the run, the thesis's reservoir, and none
+    for flags in (0, fim.FIM_FLAG_ALWAYS_ESTIMATE,
+                  fim.FIM_FLAG_RESERVOIR | fim.FIM_FLAG_ALWAYS_ESTIMATE, fim.FIM_FLAG_NO_ESTIMATE):
         g = gpu_mine(fim, ctx, db, flags=flags)
         assert_same(g, o, flags)
         assert g.stats["candidates"] == o.candidates
