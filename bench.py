@@ -47,6 +47,11 @@ METRIC = "candidate supports/s + HBM GB/s; served p50/p99 latency, batched vs pl
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: 32-bit integer VALU operations per second
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
+# bytes per launch measured with rocprofv3 (profiles/<kernel>.<workload>.txt)
+MEASURED_TRAFFIC = {
+    ("k_root_project", "sparse-200k"): (890.6 + 0.4) * 1e6,
+    ("k_dfs", "dense-50k"): (22387.1 + 8940.1) * 1e6,
+}
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
@@ -334,21 +339,29 @@ def main(argv=None):
     root_ns = float(np.mean([s["root_kernel_ns"] for s in stats]))
     dfs_ns = float(np.mean([s["dfs_kernel_ns"] for s in stats]))
     root_name = ("k_root_pairs", "k_root_sparse", "k_root_project")[st["root_kernel"]]
-    root_tops = 2.0 * st["root_pair_words"] / root_ns / 1e3 if root_ns else 0.0
-    dfs_gbs = st["dfs_bytes_algorithmic"] / dfs_ns if dfs_ns else 0.0
-    kernels = {
-        root_name: {"ms": root_ns / 1e6, "bound": "alu", "achieved_TOPs": root_tops,
-                    "frac": root_tops / VALU_PEAK_TOPS, "ops_per_launch": 2 * st["root_pair_words"]},
-        "k_dfs": {"ms": dfs_ns / 1e6, "bound": "hbm", "achieved_GBs": dfs_gbs,
-                  "frac": dfs_gbs / HBM_PEAK_GBS, "bytes_per_launch": st["dfs_bytes_algorithmic"]},
-    }
-    if root_ns >= dfs_ns:
-        roofline = {"kernel": root_name, "bound": "alu", "achieved": root_tops,
-                    "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": root_tops / VALU_PEAK_TOPS,
-                    "traffic": None}
+    dfs_bytes = st["dfs_bytes_algorithmic"]
+    root_bytes = st["bytes_algorithmic"] - dfs_bytes
+    dfs_gbs = dfs_bytes / dfs_ns if dfs_ns else 0.0
+    if st["root_kernel"] == 0:
+        # whole rows: two integer operations (AND, popcount-add) per pair-word
+        root_ops = 2.0 * st["root_pair_words"]
+        root_k = {"ms": root_ns / 1e6, "bound": "alu", "achieved": root_ops / root_ns / 1e3 if root_ns else 0.0,
+                  "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "algorithmic": root_ops}
     else:
-        roofline = {"kernel": "k_dfs", "bound": "hbm", "achieved": dfs_gbs, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": dfs_gbs / HBM_PEAK_GBS, "traffic": None}
+        # covers / projected transactions: the bytes the kernel must read
+        root_k = {"ms": root_ns / 1e6, "bound": "hbm", "achieved": root_bytes / root_ns if root_ns else 0.0,
+                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "algorithmic": root_bytes}
+    root_k["frac"] = root_k["achieved"] / root_k["peak"]
+    dfs_k = {"ms": dfs_ns / 1e6, "bound": "hbm", "achieved": dfs_gbs, "peak": HBM_PEAK_GBS,
+             "unit": "GB/s", "frac": dfs_gbs / HBM_PEAK_GBS, "algorithmic": dfs_bytes}
+    kernels = {root_name: root_k, "k_dfs": dfs_k}
+    name, k = (root_name, root_k) if root_ns >= dfs_ns else ("k_dfs", dfs_k)
+    # measured HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE,
+    # the copy calibration), from the summaries in profiles/ of this code
+    traffic = MEASURED_TRAFFIC.get((name, args.workload))
+    roofline = {"kernel": name, "bound": k["bound"], "achieved": k["achieved"], "peak": k["peak"],
+                "unit": k["unit"], "frac": k["frac"],
+                "traffic": traffic, "traffic_GBs": traffic / (k["ms"] * 1e6) if traffic else None}
     d.close()
 
     batched = None if args.no_batch else batch_leg(F, ctx, args)
