@@ -263,6 +263,48 @@ def serve_leg(F, ctx, args):
     return out
 
 
+# ---------------------------------------------------------------- estimator study
+
+def study(F, ctx, args):
+    """The estimate's effect on the persistent kernel (an analogue of the
+    thesis's experiment on estimated against actual per-processor work):
+    each workload mined with the sample estimate (in-run counts, and the
+    reservoir variant), with the C(k, 2) proxy instead, and with whole
+    first-level classes; per policy the call and kernel times and the
+    busiest wave's busy time over the mean one."""
+    import numpy as np
+
+    import synth
+    policies = {
+        "estimate": F.FIM_FLAG_ALWAYS_ESTIMATE,
+        "estimate_reservoir": F.FIM_FLAG_ALWAYS_ESTIMATE | F.FIM_FLAG_RESERVOIR,
+        "proxy": F.FIM_FLAG_NO_ESTIMATE,
+        "proxy_no_split": F.FIM_FLAG_NO_ESTIMATE | F.FIM_FLAG_NO_SPLIT,
+    }
+    loads = [("dense-50k", synth.make("dense-50k")), ("sparse-200k", synth.make("sparse-200k"))]
+    o, it, ni = synth.dense(synth.SEED_BASE + 6, 200000, 120)
+    loads.append(("dense-200k", synth.Database(o, it, ni, 80000, "dense-200k")))
+    out = {}
+    for name, db in loads:
+        d = F.Database(ctx, db.offsets, db.items, db.n_items)
+        row = {}
+        for pol, flags in policies.items():
+            walls, st = [], None
+            for rep in range(4):
+                t0 = time.perf_counter()
+                r = F.mine(ctx, d, db.minsup, flags=flags)
+                walls.append(time.perf_counter() - t0)
+                st = r.stats
+            row[pol] = {"wall_ms": float(np.median(walls[1:]) * 1e3),
+                        "dfs_ms": st["dfs_kernel_ns"] / 1e6, "estimate_ms": st["estimate_ns"] / 1e6,
+                        "imbalance": st["dfs_busy_max_ns"] / max(st["dfs_busy_mean_ns"], 1),
+                        "tasks": st["n_tasks"]}
+            log("study", name, pol, row[pol])
+        out[name] = row
+        d.close()
+    return out
+
+
 # ---------------------------------------------------------------- main
 
 def main(argv=None):
@@ -283,6 +325,8 @@ def main(argv=None):
     ap.add_argument("--serve-seconds", type=float, default=12.0)
     ap.add_argument("--serve-pool", type=int, default=128, help="distinct requests (<= 512)")
     ap.add_argument("--lanes", type=int, default=0, help="server lanes (0 = default)")
+    ap.add_argument("--study", action="store_true",
+                    help="only run the estimator study and print its JSON line")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes three times (the "
                          "reference for scaling the HBM byte counters) and exit")
@@ -309,6 +353,12 @@ def main(argv=None):
 
     import paper_2108_05038_amd as F
     import synth
+
+    if args.study:
+        ctx = F.Context(0)
+        print(json.dumps({"study": "estimator", "results": study(F, ctx, args)}), flush=True)
+        ctx.close()
+        return 0
 
     db = synth.make(args.workload)
     ctx = F.Context(0)

@@ -269,6 +269,9 @@ fim_status fim_mine_batch(fim_ctx *ctx, uint32_t n, const fim_db *const *dbs,
  *  root_kernel      root-class kernel used: 0 whole rows, 1 covers,
  *                   2 projected transactions (root_pair_words then counts
  *                   the pair increments)
+ *  dfs_busy_max_ns  busy time of the busiest wave of the persistent kernel
+ *  dfs_busy_mean_ns mean busy time over its waves (their ratio is the
+ *                   load imbalance the work plan and the work sharing left)
  *  In a batch, the kernel times are those of the whole batched launch.
  */
 typedef struct fim_stats {
@@ -289,6 +292,8 @@ typedef struct fim_stats {
     uint64_t dfs_bytes_algorithmic;
     uint64_t n_itemsets;
     uint64_t root_kernel;
+    uint64_t dfs_busy_max_ns;
+    uint64_t dfs_busy_mean_ns;
 } fim_stats;
 
 /* Number of itemsets and total number of items over all itemsets. */

@@ -82,7 +82,7 @@ class fim_stats(ctypes.Structure):
         "candidates", "pair_words", "item_supports", "n_frequent_items", "bytes_algorithmic",
         "kernel_ns", "total_ns", "estimate_ns", "n_tasks", "retries", "root_candidates",
         "root_pair_words", "root_kernel_ns", "dfs_kernel_ns", "dfs_bytes_algorithmic",
-        "n_itemsets", "root_kernel")]
+        "n_itemsets", "root_kernel", "dfs_busy_max_ns", "dfs_busy_mean_ns")]
 
 
 class fim_server_config(ctypes.Structure):

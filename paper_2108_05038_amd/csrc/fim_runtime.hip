@@ -503,6 +503,7 @@ struct DfsLaunch {
     float ms = 0.f;
     uint32_t retries = 0;
     bool truncated = false;
+    uint64_t busy_max_ns = 0, busy_mean_ns = 0;  // per wave
 };
 
 static fim_status run_persistent(fim_ctx *ctx, hipStream_t s, Tracer &tr,
@@ -605,6 +606,10 @@ static fim_status run_persistent(fim_ctx *ctx, hipStream_t s, Tracer &tr,
         HIPCHK(hipStreamSynchronize(s));
         HIPCHK(hipEventElapsedTime(&L.ms, ev0, ev1));
         const DfsCounters &ctr = L.ctr;
+        if (clk_khz > 0) {
+            L.busy_max_ns = (uint64_t)((double)ctr.busy_max * 1e6 / clk_khz);
+            L.busy_mean_ns = (uint64_t)((double)ctr.busy_sum / workers * 1e6 / clk_khz);
+        }
         if (tr.on) {
             const double mean = (double)ctr.busy_sum / workers;
             std::vector<unsigned long long> wt((size_t)workers * 8);
@@ -1240,6 +1245,10 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         ctr = L.ctr;
         ictr = L.ictr;
         dfs_ms = L.ms;
+        for (auto &I : insts) {
+            I.st.dfs_busy_max_ns = L.busy_max_ns;
+            I.st.dfs_busy_mean_ns = L.busy_mean_ns;
+        }
         truncated = L.truncated;
         const uint64_t out_cap = L.out_cap;
         for (auto &I : insts) I.st.retries += L.retries;

@@ -131,6 +131,10 @@ def test_dense_reduced_vs_oracle(fim, ctx):
         g = gpu_mine(fim, ctx, db, flags=flags)
         assert_same(g, o, flags)
         assert g.stats["candidates"] == o.candidates
+        # the waves' busy times are reported (busiest >= mean > 0)
+        assert g.stats["dfs_busy_max_ns"] >= g.stats["dfs_busy_mean_ns"] > 0
+        if flags & fim.FIM_FLAG_ALWAYS_ESTIMATE:
+            assert g.stats["estimate_ns"] > 0
 
 
 # ---------------------------------------------------------------- options do not change F
