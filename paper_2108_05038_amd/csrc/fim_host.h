@@ -21,6 +21,7 @@ struct fim_ctx {
     bool user_alloc = false;
     int n_cu = 256;
     size_t total_mem = 0;
+    size_t lds_per_block = 65536;  // largest LDS allocation of one workgroup
     std::string arch;
 
     // a second context on the same device with a stream of its own, for
@@ -94,6 +95,7 @@ struct fim_db {
     uint64_t n_tx = 0, nnz = 0;
     uint32_t n_item_ids = 0;
     uint64_t pairs_in_tx = 0;      // sum over transactions of L (L - 1) / 2
+    uint64_t max_tx_len = 0;       // longest transaction
     std::vector<uint64_t> h_off;   // canonical CSR (sorted, duplicate-free transactions)
     std::vector<uint32_t> h_items;
     fim::DevBuf d_off, d_items;

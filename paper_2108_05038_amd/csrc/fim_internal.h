@@ -113,14 +113,26 @@ constexpr uint32_t kRecHeader = 2;
 // All launches are asynchronous on `stream`; they return hipSuccess or the
 // launch error.
 
-hipError_t launch_item_count(const uint64_t *offsets, const uint32_t *items, uint64_t n_tx,
-                             uint32_t *counts, uint32_t n_item_ids, hipStream_t stream);
+// Item supports: counts[i] = occurrences of item i.  part is scratch of
+// item_count_scratch_words(nnz, n_item_ids) words (may be 0, then part is
+// unused).
+uint64_t item_count_scratch_words(uint64_t nnz, uint32_t n_item_ids);
+hipError_t launch_item_count(const uint32_t *items, uint64_t nnz, uint32_t *counts,
+                             uint32_t n_item_ids, uint32_t *part, hipStream_t stream);
 
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t stream);
 
+// Bitmap rows (n x Wp words) of the frequent ranks.  launch_bitmap_build
+// sets bits with global atomics into zero-filled rows; launch_bitmap_tiles
+// writes every word of the rows from LDS column tiles of K words
+// (bitmap_tile_words(n, lds_max), 0 when n rows do not fit).
 hipError_t launch_bitmap_build(const uint64_t *offsets, const uint32_t *items, uint64_t n_tx,
                                const uint32_t *rank_of_item, uint32_t *rows, uint32_t Wp,
                                hipStream_t stream);
+uint32_t bitmap_tile_words(uint32_t n, size_t lds_max);
+hipError_t launch_bitmap_tiles(const uint64_t *offsets, const uint32_t *items, uint64_t n_tx,
+                               const uint32_t *rank_of_item, uint32_t n, uint32_t *rows,
+                               uint32_t Wp, uint32_t K, hipStream_t stream);
 
 // Upper-triangle pair supports of the n rows (the root class): every pair
 // (i < j) with popcount(row_i & row_j) >= minsup is appended as
@@ -130,19 +142,34 @@ hipError_t launch_root_pairs(const uint32_t *rows, uint32_t n, uint32_t Wp, uint
                              uint32_t *pairs, uint64_t cap, unsigned long long *n_pairs,
                              hipStream_t stream);
 
-// Variant of the persistent kernel for rows of at most max_chunks 128-bit
-// chunks (0 = rows are streamed, 2/4/8 = chunks per lane held in registers).
-hipError_t launch_rank_tx(const uint64_t *off, const uint32_t *items, uint64_t n_tx,
-                          const uint32_t *rank_of_item, uint32_t *rk, uint32_t *len,
-                          hipStream_t stream);
+// Preparation of the projected root kernel.  launch_tidlist: the tid lists
+// tl (at offsets tl_off[n + 1]) from the rows, and rowpre (n x
+// rowpre_words(Wp) words: set bits of each row before every 8th word).
+// launch_rank_tx: rk (nnz + n_tx + 8 words) = every transaction's frequent
+// ranks ascending at off[t] + t, closed by 0xFFFFFFFF (also in the slots of
+// infrequent items), tlp (tl_off[n] words) = for tid-list entry p the
+// position in rk of its own rank, and suf (tl_off[n] halfwords) = the number
+// of frequent ranks after it in its transaction (transactions shorter than
+// 65536 items).
+inline uint32_t rowpre_words(uint32_t Wp) { return (Wp + 7) / 8; }
 hipError_t launch_tidlist(const uint32_t *rows, uint32_t n, uint32_t Wp, const uint64_t *tl_off,
-                          uint32_t *tl, hipStream_t stream);
+                          uint32_t *tl, uint32_t *rowpre, hipStream_t stream);
+hipError_t launch_rank_tx(const uint64_t *off, const uint32_t *items, uint64_t n_tx,
+                          const uint32_t *rank_of_item, const uint32_t *rows, uint32_t Wp,
+                          const uint32_t *rowpre, const uint64_t *tl_off, uint32_t *rk,
+                          uint32_t *tlp, uint16_t *suf, hipStream_t stream);
+// Root class over projected transactions: rk, tlp and suf as above (tid
+// lists at offsets tl_off[n + 1]); 16-bit counters when max_supp (the
+// largest row support) is at most 65535.  Pairs as for launch_root_pairs;
+// *work receives the pair increments.
 void project_tile(uint32_t n, uint32_t *R, uint32_t *J);
-hipError_t launch_root_project(const uint64_t *off, const uint32_t *rk, const uint32_t *len,
-                               const uint32_t *tl, const uint64_t *tl_off, uint32_t n,
+hipError_t launch_root_project(const uint32_t *rk, const uint32_t *tlp, const uint16_t *suf,
+                               const uint64_t *tl_off, uint32_t n, uint32_t max_supp,
                                uint32_t minsup, uint32_t *pairs, uint64_t cap,
                                unsigned long long *n_pairs, unsigned long long *work,
                                hipStream_t stream);
+// Variant of the persistent kernel for rows of at most max_chunks 128-bit
+// chunks (0 = rows are streamed, 2/4/8 = chunks per lane held in registers).
 uint32_t tile_variant(uint32_t tile_words);
 uint32_t dfs_variant(uint32_t max_chunks);
 

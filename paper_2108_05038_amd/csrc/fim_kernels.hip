@@ -87,25 +87,51 @@ __device__ __forceinline__ uint32_t xcd_local_block(uint32_t b, uint32_t nblocks
 
 // ------------------------------------------------------------------ a2: item supports
 
-__global__ __launch_bounds__(kBlock) void k_item_count(const uint32_t *__restrict__ items,
-                                                        uint64_t nnz, uint32_t *counts,
-                                                        uint32_t n_item_ids, int use_lds) {
+// Up to kHistItems item ids: block b histograms its chunk of the item array
+// in LDS and stores the histogram at part[b * n_item_ids ..]; k_item_sum adds
+// the block histograms up per item (no contended global atomics).  More item
+// ids: global atomics straight into counts.
+constexpr uint32_t kHistItems = 12288;
+
+__global__ __launch_bounds__(kBlock) void k_item_hist(const uint32_t *__restrict__ items,
+                                                       uint64_t nnz, uint64_t chunk,
+                                                       uint32_t n_item_ids, uint32_t *part) {
     extern __shared__ uint32_t hist[];
-    if (use_lds) {
-        for (uint32_t i = threadIdx.x; i < n_item_ids; i += kBlock) hist[i] = 0;
-        __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n_item_ids; i += kBlock) hist[i] = 0;
+    __syncthreads();
+    const uint64_t a = (uint64_t)blockIdx.x * chunk, e = min(nnz, a + chunk);
+    for (uint64_t p = a + threadIdx.x; p < e; p += kBlock)
+        atomicAdd(&hist[items[p]], 1u);  // transactions are duplicate-free after ingest
+    __syncthreads();
+    uint32_t *dst = part + (uint64_t)blockIdx.x * n_item_ids;
+    for (uint32_t i = threadIdx.x; i < n_item_ids; i += kBlock) dst[i] = hist[i];
+}
+
+// 64 items per block; the block's four waves add a quarter of the block
+// histograms each (independent loads), then combine in LDS
+__global__ __launch_bounds__(kBlock) void k_item_sum(const uint32_t *__restrict__ part, uint32_t nb,
+                                                      uint32_t n_item_ids, uint32_t *counts) {
+    __shared__ uint32_t acc[kWavesPerBlock][kWave];
+    const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
+    const uint32_t i = blockIdx.x * kWave + lane;
+    uint32_t c = 0;
+    if (i < n_item_ids)
+        for (uint32_t b = wv; b < nb; b += kWavesPerBlock) c += part[(uint64_t)b * n_item_ids + i];
+    acc[wv][lane] = c;
+    __syncthreads();
+    if (wv == 0 && i < n_item_ids) {
+        uint32_t sum = 0;
+#pragma unroll
+        for (int q = 0; q < kWavesPerBlock; q++) sum += acc[q][lane];
+        counts[i] = sum;
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_item_count(const uint32_t *__restrict__ items,
+                                                        uint64_t nnz, uint32_t *counts) {
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x; p < nnz; p += stride) {
-        uint32_t it = items[p];  // transactions are duplicate-free after ingest
-        if (use_lds) atomicAdd(&hist[it], 1u);
-        else atomicAdd(&counts[it], 1u);
-    }
-    if (use_lds) {
-        __syncthreads();
-        for (uint32_t i = threadIdx.x; i < n_item_ids; i += kBlock)
-            if (hist[i]) atomicAdd(&counts[i], hist[i]);
-    }
+    for (uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x; p < nnz; p += stride)
+        atomicAdd(&counts[items[p]], 1u);
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
@@ -114,22 +140,114 @@ __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
 }
 
 // ------------------------------------------------------------------ a3: bitmap build
-// One thread per transaction; each frequent item of transaction t sets bit
-// t % 32 of word t / 32 of its row.
+// A block owns kBuildTx consecutive transactions and walks their item
+// positions with consecutive threads (coalesced loads); a thread finds the
+// transaction of its position by binary search over the block's offsets in
+// LDS and sets bit t % 32 of word t / 32 of the item's row.  kBuildTx is a
+// multiple of 32 and blocks start at multiples of it, so every row word is
+// written by one block only: its atomic OR needs workgroup scope (done in the
+// L2 of the block's XCD) rather than device scope; the rows reach memory at
+// the end of the kernel.
+
+constexpr uint32_t kBuildTx = 256;
+static_assert(kBuildTx % 32 == 0, "a row word must belong to one block");
 
 __global__ __launch_bounds__(kBlock) void k_bitmap_build(const uint64_t *__restrict__ offsets,
                                                           const uint32_t *__restrict__ items,
                                                           uint64_t n_tx,
                                                           const uint32_t *__restrict__ rank_of_item,
                                                           uint32_t *rows, uint32_t Wp) {
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < n_tx; t += stride) {
-        const uint32_t bit = 1u << (t & 31);
-        const uint64_t w = t >> 5;
-        for (uint64_t p = offsets[t], e = offsets[t + 1]; p < e; p++) {
-            uint32_t r = rank_of_item[items[p]];
-            if (r != kNone) atomicOr(&rows[(uint64_t)r * Wp + w], bit);
+    __shared__ uint64_t s_off[kBuildTx + 1];
+    const uint64_t t0 = (uint64_t)blockIdx.x * kBuildTx;
+    const uint32_t nt = (uint32_t)min<uint64_t>(kBuildTx, n_tx - t0);
+    for (uint32_t e = threadIdx.x; e <= nt; e += kBlock) s_off[e] = offsets[t0 + e];
+    __syncthreads();
+    const uint64_t p0 = s_off[0], p1 = s_off[nt];
+    for (uint64_t pb = p0; pb < p1; pb += 2 * kBlock) {
+        // two positions per thread, their loads issued together
+        uint32_t r[2];
+        uint64_t p[2];
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            p[j] = pb + j * kBlock + threadIdx.x;
+            r[j] = p[j] < p1 ? items[p[j]] : kNone;
         }
+#pragma unroll
+        for (int j = 0; j < 2; j++) r[j] = r[j] != kNone ? rank_of_item[r[j]] : kNone;
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            if (r[j] == kNone) continue;
+            uint32_t lo = 0, hi = nt;  // s_off[lo] <= p < s_off[hi]
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (s_off[mid] <= p[j]) lo = mid;
+                else hi = mid;
+            }
+            const uint64_t t = t0 + lo;
+            __hip_atomic_fetch_or(&rows[(uint64_t)r[j] * Wp + (t >> 5)], 1u << (t & 31),
+                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+}
+
+// Column tiles: a block owns words [b K, b K + K) of every row, i.e. the
+// transactions [32 b K, 32 (b + 1) K).  It sets their bits in an LDS copy of
+// the tile (n x K words, LDS atomics) and writes the tile out once, K words
+// per row, zeros included: no global atomics, no separate zero fill, and
+// the padding words past the last transaction come out zero as well.
+constexpr uint32_t kTileMaxWords = 8;
+
+__global__ __launch_bounds__(kBlock) void k_bitmap_tile(const uint64_t *__restrict__ offsets,
+                                                         const uint32_t *__restrict__ items,
+                                                         uint64_t n_tx,
+                                                         const uint32_t *__restrict__ rank_of_item,
+                                                         uint32_t n, uint32_t *rows, uint32_t Wp,
+                                                         uint32_t K) {
+    extern __shared__ uint4 tile4[];  // n * K words, 16-byte aligned
+    uint32_t *tile = reinterpret_cast<uint32_t *>(tile4);
+    __shared__ uint64_t s_off[32 * kTileMaxWords + 1];
+    const uint32_t wb = blockIdx.x * K;
+    const uint32_t kw = min(K, Wp - wb);  // a multiple of 4 (K and Wp are)
+    for (uint32_t e = threadIdx.x; e < n * K; e += kBlock) tile[e] = 0;
+    const uint64_t t0 = (uint64_t)wb * 32;
+    const uint32_t nt = t0 < n_tx ? (uint32_t)min<uint64_t>((uint64_t)kw * 32, n_tx - t0) : 0u;
+    for (uint32_t e = threadIdx.x; nt > 0 && e <= nt; e += kBlock) s_off[e] = offsets[t0 + e];
+    __syncthreads();
+    if (nt > 0) {
+        // kTileUnroll positions per thread at a time: their item and rank
+        // loads are unconditional (indices clamped into the block's range)
+        // so that they are all in flight together
+        constexpr uint32_t kTileUnroll = 8;
+        const uint64_t p0 = s_off[0], p1 = s_off[nt];
+        for (uint64_t pb = p0; pb < p1; pb += kTileUnroll * kBlock) {
+            uint32_t r[kTileUnroll];
+#pragma unroll
+            for (uint32_t j = 0; j < kTileUnroll; j++) {
+                const uint64_t p = pb + j * kBlock + threadIdx.x;
+                r[j] = items[p < p1 ? p : p1 - 1];
+            }
+#pragma unroll
+            for (uint32_t j = 0; j < kTileUnroll; j++) r[j] = rank_of_item[r[j]];
+#pragma unroll
+            for (uint32_t j = 0; j < kTileUnroll; j++) {
+                const uint64_t p = pb + j * kBlock + threadIdx.x;
+                if (p >= p1 || r[j] == kNone) continue;
+                uint32_t lo = 0, hi = nt;  // s_off[lo] <= p < s_off[hi]
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (s_off[mid] <= p) lo = mid;
+                    else hi = mid;
+                }
+                atomicOr(&tile[r[j] * K + (lo >> 5)], 1u << (lo & 31));
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t q4 = kw / 4;  // 16-byte pieces per row
+    for (uint32_t e = threadIdx.x; e < n * q4; e += kBlock) {
+        const uint32_t r = e / q4, q = e % q4;
+        const uint4 v = *reinterpret_cast<const uint4 *>(tile + r * K + 4 * q);
+        *reinterpret_cast<uint4 *>(rows + (uint64_t)r * Wp + wb + 4 * q) = v;
     }
 }
 
@@ -372,133 +490,290 @@ __global__ __launch_bounds__(kBlock) void k_root_sparse(
 // ------------------------------------------------------------------ a6/a7: root class over projected transactions
 // supp({a, b}) is the number of transactions of the cover T(a) that also
 // hold b, i.e. the support of b in the database projected on T(a).  The
-// transactions are rewritten as ascending lists of frequent ranks
-// (k_rank_tx), every rank lists the transactions that hold it (k_tidlist,
-// from the bitmap rows),
-// and a block counts the pairs (a, b > a) of a few consecutive rows a in
-// LDS: for every transaction of T(a) it walks the ranks after a.  The work
-// is the number of pairs inside the transactions, independent of the
-// bitmap width, which is what makes it the choice for long sparse rows.
+// transactions are kept as ascending lists of frequent ranks, each closed by
+// kRankEnd (larger than any rank), and every entry of the tid list of a
+// points at a's own position in its transaction (both built by sorting the
+// occurrences).  A block counts the pairs (a, b > a) of a few consecutive
+// rows a in LDS: for every transaction of T(a) it reads the ranks after a's
+// position up to the end mark.  The work is the number of pairs inside the
+// transactions, independent of the bitmap width, which is what makes it the
+// choice for long sparse rows.
 
-// transaction t -> its frequent ranks, ascending, at rk[off[t] ..) and
-// their count in len[t].  One wave per transaction: every lane holds one
-// item's rank and finds its place by counting the smaller ranks (the ranks
-// of one transaction are distinct); longer transactions go 64 at a time.
-__global__ __launch_bounds__(kBlock) void k_rank_tx(const uint64_t *__restrict__ off,
-                                                     const uint32_t *__restrict__ items,
-                                                     uint64_t n_tx,
-                                                     const uint32_t *__restrict__ rank_of_item,
-                                                     uint32_t *rk, uint32_t *len) {
-    const uint32_t lane = lane_id();
-    const uint64_t waves = (uint64_t)gridDim.x * kWavesPerBlock;
-    for (uint64_t t = (uint64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; t < n_tx;
-         t += waves) {
-        const uint64_t a = off[t];
-        const uint32_t L = (uint32_t)(off[t + 1] - a);
-        uint32_t kept = 0;
-        for (uint32_t c0 = 0; c0 < L; c0 += kWave) {
-            const uint32_t r = c0 + lane < L ? rank_of_item[items[a + c0 + lane]] : kNone;
-            // place among all frequent ranks of the transaction
-            uint32_t pos = 0;
-            for (uint32_t d0 = 0; d0 < L; d0 += kWave) {
-                const uint32_t rd = d0 == c0 ? r
-                                             : (d0 + lane < L ? rank_of_item[items[a + d0 + lane]] : kNone);
-                const uint32_t cnt = min(L - d0, (uint32_t)kWave);
-                for (uint32_t j = 0; j < cnt; j++) pos += __shfl(rd, (int)j, kWave) < r ? 1u : 0u;
-            }
-            if (r != kNone) rk[a + pos] = r;
-            kept += (uint32_t)__popcll(__ballot(r != kNone));
-        }
-        if (lane == 0) len[t] = kept;
-    }
-}
+constexpr uint32_t kRankEnd = 0xFFFFFFFFu;  // equal to kNone: infrequent items sort last
 
 // tl[tl_off[r] ..) = the transactions holding rank r, ascending: the set
-// bits of row r, one wave per row, compacted with ballot/mbcnt
+// bits of row r, one wave per row, compacted with a wave prefix sum of the
+// words' popcounts.  rowpre[r * Wb + j] = set bits of row r before word 8 j,
+// the coarse rank index k_rank_tx uses to place a transaction in the list.
 __global__ __launch_bounds__(kBlock) void k_tidlist(const uint32_t *__restrict__ rows, uint32_t n,
                                                      uint32_t Wp, const uint64_t *__restrict__ tl_off,
-                                                     uint32_t *tl) {
+                                                     uint32_t *tl, uint32_t *rowpre, uint32_t Wb) {
     const uint32_t r = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     if (r >= n) return;
     const uint32_t lane = lane_id();
     const uint32_t *row = rows + (uint64_t)r * Wp;
-    uint64_t pos = tl_off[r];
-    const uint64_t end = tl_off[r + 1];
-    for (uint32_t w0 = 0; w0 < Wp; w0 += kWave) {
-        uint32_t x = w0 + lane < Wp ? row[w0 + lane] : 0u;
-        // lanes emit their word's bits in order; the wave's total moves pos
-        const uint32_t pc = __popc(x);
-        uint32_t incl = pc;
+    uint32_t *pre = rowpre + (uint64_t)r * Wb;
+    const uint64_t base = tl_off[r], end = tl_off[r + 1];
+    uint32_t pos = 0;  // set bits before the current window
+    for (uint32_t w0 = 0; w0 < Wp; w0 += 4 * kWave) {
+        uint32_t x[4];
 #pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            const uint32_t v = __shfl_up(incl, off, kWave);
-            if ((int)lane >= off) incl += v;
+        for (int j = 0; j < 4; j++) {
+            const uint32_t w = w0 + j * kWave + lane;
+            x[j] = w < Wp ? row[w] : 0u;
         }
-        uint64_t p = pos + incl - pc;
-        while (x) {
-            const uint32_t b = __ffs(x) - 1;
-            if (p < end) tl[p] = (w0 + lane) * 32 + b;
-            p++;
-            x &= x - 1;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint32_t w = w0 + j * kWave + lane;
+            const uint32_t pc = __popc(x[j]);
+            uint32_t incl = pc;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const uint32_t v = __shfl_up(incl, o, kWave);
+                if ((int)lane >= o) incl += v;
+            }
+            const uint32_t before = pos + incl - pc;
+            if (rowpre != nullptr && w < Wp && (w & 7) == 0) pre[w >> 3] = before;
+            uint64_t q = base + before;
+            uint32_t y = x[j];
+            while (y) {
+                const uint32_t b = __ffs(y) - 1;
+                if (q < end) tl[q] = w * 32 + b;
+                q++;
+                y &= y - 1;
+            }
+            pos += __shfl(incl, kWave - 1, kWave);
         }
-        pos += __shfl(incl, kWave - 1, kWave);
+    }
+}
+
+// Ranked transactions: transaction t's ranks ascending at rk[off[t] + t ..),
+// its infrequent items' slots and one slot more holding kRankEnd.  A wave
+// takes kRankGroup transactions at a time (their loads overlap): every lane
+// holds one item's rank of each and finds its slot by counting the smaller
+// ranks (ties, only between infrequent items, by position).  A transaction of
+// more than 64 items is done alone, 64 items at a time.  For a frequent rank
+// r the lane also finds t's index in the tid list of r, the set bits of row r
+// before t (rowpre plus at most eight words), and stores the slot's address
+// there: tlp[tl_off[r] + index] = off[t] + t + slot.
+
+constexpr uint32_t kRankGroup = 4;
+
+__device__ __forceinline__ uint32_t tid_index(const uint32_t *__restrict__ rows, uint32_t Wp,
+                                              const uint32_t *__restrict__ rowpre, uint32_t Wb,
+                                              uint32_t r, uint64_t t) {
+    // words w8 .. w of row r: w8 + 3 < Wp always (Wp is a multiple of 4), the
+    // second half only when w reaches into it
+    const uint32_t w = (uint32_t)(t >> 5), tb = (uint32_t)(t & 31), w8 = w & ~7u;
+    const uint32_t *row = rows + (uint64_t)r * Wp;
+    const uint4 x0 = *reinterpret_cast<const uint4 *>(row + w8);
+    const uint4 x1 = w >= w8 + 4 ? *reinterpret_cast<const uint4 *>(row + w8 + 4)
+                                 : make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t xs[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+    uint32_t idx = rowpre[(uint64_t)r * Wb + (w >> 3)];
+#pragma unroll
+    for (uint32_t q = 0; q < 8; q++) {
+        if (w8 + q < w) idx += __popc(xs[q]);
+        else if (w8 + q == w) idx += __popc(xs[q] & ((1u << tb) - 1u));
+    }
+    return idx;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rank_tx(
+    const uint64_t *__restrict__ off, const uint32_t *__restrict__ items, uint64_t n_tx,
+    const uint32_t *__restrict__ rank_of_item, const uint32_t *__restrict__ rows, uint32_t Wp,
+    const uint32_t *__restrict__ rowpre, uint32_t Wb, const uint64_t *__restrict__ tl_off,
+    uint32_t *rk, uint32_t *tlp, uint16_t *suf) {
+    const uint32_t lane = lane_id();
+    const uint64_t waves = (uint64_t)gridDim.x * kWavesPerBlock;
+    const uint64_t n_groups = (n_tx + kRankGroup - 1) / kRankGroup;
+    for (uint64_t g = (uint64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; g < n_groups;
+         g += waves) {
+        const uint64_t tg0 = g * kRankGroup;
+        const uint32_t ng = (uint32_t)min<uint64_t>(kRankGroup, n_tx - tg0);
+        uint64_t a[kRankGroup];
+        uint32_t L[kRankGroup], r[kRankGroup];
+        bool small = true;
+#pragma unroll
+        for (uint32_t j = 0; j < kRankGroup; j++) {
+            a[j] = j < ng ? off[tg0 + j] : 0;
+            L[j] = j < ng ? (uint32_t)(off[tg0 + j + 1] - a[j]) : 0u;
+            small = small && L[j] <= (uint32_t)kWave;
+        }
+        if (small) {
+            // loads unconditional (indices clamped in bounds), so that the
+            // group's loads are in flight together
+#pragma unroll
+            for (uint32_t j = 0; j < kRankGroup; j++)
+                r[j] = items[L[j] ? a[j] + min(lane, L[j] - 1) : 0];
+#pragma unroll
+            for (uint32_t j = 0; j < kRankGroup; j++) {
+                const uint32_t rr = rank_of_item[r[j]];
+                r[j] = lane < L[j] ? rr : kNone;
+            }
+            uint32_t pos[kRankGroup];
+#pragma unroll
+            for (uint32_t j = 0; j < kRankGroup; j++) {
+                pos[j] = 0;
+                for (uint32_t i = 0; i < L[j]; i++) {
+                    const uint32_t v = __shfl(r[j], (int)i, kWave);
+                    pos[j] += (v < r[j] || (v == r[j] && i < lane)) ? 1u : 0u;
+                }
+            }
+            uint32_t idx[kRankGroup];
+            uint64_t lo[kRankGroup];
+#pragma unroll
+            for (uint32_t j = 0; j < kRankGroup; j++) {
+                // lanes without a frequent rank look up row 0 (in bounds) and
+                // drop the result
+                const uint32_t rq = r[j] != kNone ? r[j] : 0u;
+                idx[j] = tid_index(rows, Wp, rowpre, Wb, rq, j < ng ? tg0 + j : tg0);
+                lo[j] = tl_off[rq];
+            }
+#pragma unroll
+            for (uint32_t j = 0; j < kRankGroup; j++) {
+                if (j >= ng) continue;
+                const uint64_t base = a[j] + tg0 + j;
+                const uint32_t lf = (uint32_t)__popcll(__ballot(r[j] != kNone));  // frequent items
+                if (lane < L[j]) {
+                    rk[base + pos[j]] = r[j];
+                    if (r[j] != kNone) {
+                        tlp[lo[j] + idx[j]] = (uint32_t)(base + pos[j]);
+                        suf[lo[j] + idx[j]] = (uint16_t)(lf - 1 - pos[j]);
+                    }
+                }
+                if (lane == 0) rk[base + L[j]] = kRankEnd;
+            }
+            continue;
+        }
+        // one transaction at a time, 64 items at a time
+        for (uint32_t j = 0; j < ng; j++) {
+            const uint64_t t = tg0 + j, base = a[j] + t;
+            const uint32_t Lt = L[j];
+            uint32_t lf = 0;  // frequent items of t
+            for (uint32_t c0 = 0; c0 < Lt; c0 += kWave) {
+                const uint32_t c = c0 + lane;
+                const bool f = c < Lt && rank_of_item[items[a[j] + c]] != kNone;
+                lf += (uint32_t)__popcll(__ballot(f));
+            }
+            for (uint32_t c0 = 0; c0 < Lt; c0 += kWave) {
+                const uint32_t c = c0 + lane;
+                const uint32_t rc = c < Lt ? rank_of_item[items[a[j] + c]] : kNone;
+                uint32_t p = 0;
+                for (uint32_t d0 = 0; d0 < Lt; d0 += kWave) {
+                    const uint32_t rd = d0 == c0 ? rc
+                                                 : (d0 + lane < Lt ? rank_of_item[items[a[j] + d0 + lane]] : kNone);
+                    const uint32_t cnt = min(Lt - d0, (uint32_t)kWave);
+                    for (uint32_t i = 0; i < cnt; i++) {
+                        const uint32_t v = __shfl(rd, (int)i, kWave);
+                        p += (v < rc || (v == rc && d0 + i < c)) ? 1u : 0u;
+                    }
+                }
+                if (c >= Lt) continue;
+                rk[base + p] = rc;
+                if (rc != kNone) {
+                    const uint64_t i = tl_off[rc] + tid_index(rows, Wp, rowpre, Wb, rc, t);
+                    tlp[i] = (uint32_t)(base + p);
+                    suf[i] = (uint16_t)(lf - 1 - p);
+                }
+            }
+            if (lane == 0) rk[base + Lt] = kRankEnd;
+        }
     }
 }
 
 constexpr uint32_t kProjectMaxRows = 64;
-constexpr uint32_t kProjGroup = 1;  // lanes per (item, transaction) pair (more were slower: suffixes are short)
 
 // block (x, y): rows [i0, i0 + R) (x counted from the last, heaviest rows)
 // against partner columns [j0, j0 + J); counters cnt[R][J] in LDS
+// One block per R consecutive rows a (and J columns from j0): LDS counters
+// of the pairs (a, b), 32-bit, or 16-bit halves of 32-bit words (Packed)
+// when no row's support exceeds 65535.  A wave takes 64 tid-list entries at
+// a time; each entry (a, t) brings the position of a in t and the number of
+// t's ranks after it (suf), and the wave lays those rank reads out flat
+// (prefix sum of suf): lane x reads the x-th rank of the lot, found by a
+// binary search over the prefix sums in LDS, so that every lane has a read
+// in flight however the suffix lengths differ.
+template <bool Packed>
 __global__ __launch_bounds__(kBlock) void k_root_project(
-    const uint64_t *__restrict__ off, const uint32_t *__restrict__ rk,
-    const uint32_t *__restrict__ len, const uint32_t *__restrict__ tl,
-    const uint64_t *__restrict__ tl_off, uint32_t n, uint32_t R, uint32_t J, uint32_t minsup,
-    uint32_t *pairs, uint64_t cap, unsigned long long *n_pairs, unsigned long long *work) {
+    const uint32_t *__restrict__ rk, const uint32_t *__restrict__ tlp,
+    const uint16_t *__restrict__ suf, const uint64_t *__restrict__ tl_off, uint32_t n, uint32_t R,
+    uint32_t J, uint32_t minsup, uint32_t *pairs, uint64_t cap, unsigned long long *n_pairs,
+    unsigned long long *work) {
     extern __shared__ uint32_t cnt[];
     __shared__ uint64_t s_off[kProjectMaxRows + 1];
+    __shared__ uint32_t s_sc[kWavesPerBlock][kWave], s_q[kWavesPerBlock][kWave],
+        s_a[kWavesPerBlock][kWave];
     const uint32_t nrb = (n + R - 1) / R;
     const uint32_t i0 = (nrb - 1 - blockIdx.x) * R, i1 = min(i0 + R, n);
     const uint32_t j0 = blockIdx.y * J, j1 = min(j0 + J, n);
     if (j1 <= i0 + 1) return;  // no pair (a, b > a) in this tile (uniform over the block)
-    for (uint32_t e = threadIdx.x; e < R * J; e += kBlock) cnt[e] = 0;
+    const uint32_t words = Packed ? (R * J + 1) / 2 : R * J;
+    for (uint32_t e = threadIdx.x; e < words; e += kBlock) cnt[e] = 0;
     for (uint32_t e = threadIdx.x; e <= i1 - i0; e += kBlock) s_off[e] = tl_off[i0 + e];
     __syncthreads();
-    // kProjGroup lanes take one (a, t) pair together: the same search, then
-    // the ranks after a read kProjGroup at a time (independent loads)
+    const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
+    uint32_t *sc = s_sc[wv], *sq = s_q[wv], *sa = s_a[wv];
     unsigned long long wk = 0;
     const uint64_t p1 = s_off[i1 - i0];
-    const uint32_t gl = threadIdx.x % kProjGroup, gid = threadIdx.x / kProjGroup;
-    constexpr uint32_t kGroups = kBlock / kProjGroup;
     uint32_t a_rel = 0;
-    for (uint64_t p = s_off[0] + gid; p < p1; p += kGroups) {
-        while (s_off[a_rel + 1] <= p) a_rel++;  // p only grows: the row index only grows
-        const uint32_t a = i0 + a_rel;
-        const uint32_t t = tl[p];
-        const uint64_t b0 = off[t];
-        const uint32_t L = len[t];
-        // first position after a, then the first rank >= j0
-        const uint32_t lim = max(a + 1, j0);
-        uint32_t lo = 0, hi = L;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (rk[b0 + mid] < lim) lo = mid + 1;
-            else hi = mid;
+    for (uint64_t pb = s_off[0] + (uint64_t)wv * kWave; pb < p1; pb += kBlock) {
+        const uint64_t p = pb + lane;
+        const bool valid = p < p1;
+        while (valid && s_off[a_rel + 1] <= p) a_rel++;  // p only grows: the row only grows
+        const uint32_t len = valid ? suf[p] : 0u;
+        const uint32_t q0 = valid ? tlp[p] + 1 : 0u;
+        uint32_t incl = len;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint32_t v = __shfl_up(incl, o, kWave);
+            if ((int)lane >= o) incl += v;
         }
-        uint32_t *row = cnt + a_rel * J;
-        for (uint32_t q = lo + gl; q < L; q += kProjGroup) {
-            const uint32_t b = rk[b0 + q];
-            if (b >= j1) break;  // ranks ascend: later lanes' ranks are larger too
-            atomicAdd(&row[b - j0], 1u);
-            wk++;
+        const uint32_t total = __shfl(incl, kWave - 1, kWave);
+        sc[lane] = incl - len;
+        sq[lane] = q0;
+        sa[lane] = a_rel;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (uint32_t k0 = 0; k0 < total; k0 += 4 * kWave) {
+            uint32_t b[4], row[4];
+#pragma unroll
+            for (uint32_t u = 0; u < 4; u++) {
+                const uint32_t k = k0 + u * kWave + lane;
+                b[u] = kRankEnd;
+                row[u] = 0;
+                if (k < total) {
+                    uint32_t lo = 0, hi = kWave;  // sc[lo] <= k < sc[hi] (sc[64] = total)
+                    while (hi - lo > 1) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (sc[mid] <= k) lo = mid;
+                        else hi = mid;
+                    }
+                    b[u] = rk[sq[lo] + (k - sc[lo])];
+                    row[u] = sa[lo];
+                }
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < 4; u++) {
+                if (b[u] < j0 || b[u] >= j1) continue;
+                const uint32_t e = row[u] * J + (b[u] - j0);
+                if (Packed) atomicAdd(&cnt[e >> 1], 1u << ((e & 1) * 16));
+                else atomicAdd(&cnt[e], 1u);
+                wk++;
+            }
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     __syncthreads();
     // frequent pairs of the tile, compacted per wave with one atomic
     for (uint32_t e0 = 0; e0 < R * J; e0 += kBlock) {
         const uint32_t e = e0 + threadIdx.x;
         const uint32_t a = i0 + e / J, b = j0 + e % J;
-        const uint32_t c = e < R * J ? cnt[e] : 0u;
+        uint32_t c = 0;
+        if (e < R * J) c = Packed ? (cnt[e >> 1] >> ((e & 1) * 16)) & 0xFFFFu : cnt[e];
         const bool ok = e < R * J && a < i1 && b < j1 && b > a && c >= minsup;
         const uint64_t mask = __ballot(ok);
         unsigned long long base = 0;
@@ -840,28 +1115,24 @@ __device__ void emit_keys(const InstDesc &I, uint32_t inst, uint32_t len, const 
     } else {
         for (uint32_t e = lane; e < nf; e += kWave) {
             const uint32_t c = I.item_of_rank[tmp[e]];
+            // The len codes: the prefix items (ascending in sp) merged with c.
+            // Code x + 1 goes to bits [sh, sh + bits) of hi:lo through
+            // selects on values (a reference to hi or lo would send them
+            // through scratch memory).
             unsigned long long hi = 0, lo = 0;
-            uint32_t sh = 128;
-            auto put = [&](uint32_t x) {
+            uint32_t sh = 128, q = 0;
+            bool ins = false;
+            for (uint32_t k = 0; k < len; k++) {
+                const uint32_t v = q + 1 < len ? sp[q] : ~0u;  // next prefix item, if any
+                const bool take_c = !ins && c < v;
+                const uint32_t x = take_c ? c : v;
+                ins = ins || take_c;
+                q += take_c ? 0u : 1u;
                 const unsigned long long code = (unsigned long long)x + 1;
                 sh -= bits;
-                if (sh >= 64) hi |= code << (sh - 64);
-                else if (sh + bits <= 64) lo |= code << sh;
-                else {
-                    hi |= code >> (64 - sh);
-                    lo |= code << sh;
-                }
-            };
-            bool ins = false;
-            for (uint32_t q = 0; q + 1 < len; q++) {
-                const uint32_t v = sp[q];
-                if (!ins && c < v) {
-                    put(c);
-                    ins = true;
-                }
-                put(v);
+                hi |= sh >= 64 ? code << (sh - 64) : (sh + bits > 64 ? code >> (64 - sh) : 0ull);
+                lo |= sh >= 64 ? 0ull : code << sh;
             }
-            if (!ins) put(c);
             uint4 *o = reinterpret_cast<uint4 *>(out + base + 8ull * e);
             o[0] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
             o[1] = make_uint4(tmp[nj + e], inst, 0u, 0u);
@@ -1308,25 +1579,49 @@ __device__ void run_frame(const InstDesc &I, uint32_t inst, uint32_t task, const
                 flag_stack(ctr, (S - low) + (uint64_t)k * Wq);
                 return;
             }
+            // Groups of kG ballot rounds (kG * 64 transactions, 2 kG words):
+            // the group's transaction ids stay in registers while every atom's
+            // words are gathered, two atoms at a time (2 kG loads in flight);
+            // lane q < 2 kG collects word q of the group and stores it.  The
+            // groups cover every word below Wq (zeros past s).
             const uint32_t *tids = I.tl + t0;
-            const uint32_t filled = (s + 63) / 64 * 2;  // words the ballots write
-            for (uint32_t e = 0; e < k; e++)
-                for (uint32_t q = filled + lane; q < Wq; q += kWave) region[(uint64_t)e * Wq + q] = 0u;
-            for (uint32_t i0 = 0; i0 < s; i0 += kWave) {
-                const bool in = i0 + lane < s;
-                const uint32_t t = in ? tids[i0 + lane] : 0u;
-                const uint32_t tw = t >> 5, tb = t & 31;
-                for (uint32_t e0 = 0; e0 < k; e0 += 4) {
-                    uint32_t x[4];
+            constexpr uint32_t kG = 8;
+            for (uint32_t g0 = 0; g0 < s; g0 += kG * kWave) {
+                uint32_t tg[kG];
 #pragma unroll
-                    for (int j = 0; j < 4; j++)
-                        x[j] = (in && e0 + j < k) ? I.rows[(uint64_t)src.ranks[e0 + j] * Wf + tw] : 0u;
+                for (uint32_t j = 0; j < kG; j++) {
+                    const uint32_t i = g0 + j * kWave + lane;
+                    tg[j] = i < s ? tids[i] : kNone;
+                }
+                const uint32_t wbase = g0 / 32;
+                for (uint32_t e = 0; e < k; e += 2) {
+                    const bool two = e + 1 < k;
+                    const uint32_t *ra = I.rows + (uint64_t)src.ranks[e] * Wf;
+                    const uint32_t *rb = I.rows + (uint64_t)src.ranks[two ? e + 1 : e] * Wf;
+                    uint32_t xa[kG], xb[kG];
 #pragma unroll
-                    for (int j = 0; j < 4; j++) {
-                        const uint64_t bits = __ballot((x[j] >> tb) & 1u);
-                        if (e0 + j < k && lane < 2)
-                            region[(uint64_t)(e0 + j) * Wq + i0 / 32 + lane] =
-                                lane == 0 ? (uint32_t)bits : (uint32_t)(bits >> 32);
+                    for (uint32_t j = 0; j < kG; j++) {
+                        const uint32_t t = tg[j];
+                        xa[j] = t != kNone ? ra[t >> 5] : 0u;
+                        xb[j] = (two && t != kNone) ? rb[t >> 5] : 0u;
+                    }
+                    uint32_t wa = 0, wb = 0;
+#pragma unroll
+                    for (uint32_t j = 0; j < kG; j++) {
+                        const uint32_t tb = tg[j] & 31;
+                        const uint64_t ba = __ballot((xa[j] >> tb) & 1u);
+                        const uint64_t bb = __ballot((xb[j] >> tb) & 1u);
+                        if (lane == 2 * j) {
+                            wa = (uint32_t)ba;
+                            wb = (uint32_t)bb;
+                        } else if (lane == 2 * j + 1) {
+                            wa = (uint32_t)(ba >> 32);
+                            wb = (uint32_t)(bb >> 32);
+                        }
+                    }
+                    if (lane < 2 * kG && wbase + lane < Wq) {
+                        region[(uint64_t)e * Wq + wbase + lane] = wa;
+                        if (two) region[(uint64_t)(e + 1) * Wq + wbase + lane] = wb;
                     }
                 }
             }
@@ -1579,16 +1874,41 @@ __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Tas
 
 // ------------------------------------------------------------------ launch wrappers
 
-hipError_t launch_item_count(const uint64_t *offsets, const uint32_t *items, uint64_t nnz,
-                             uint32_t *counts, uint32_t n_item_ids, hipStream_t stream) {
-    (void)offsets;
-    if (nnz == 0) return hipSuccess;
-    const int use_lds = n_item_ids <= 12288;
-    const size_t lds = use_lds ? n_item_ids * sizeof(uint32_t) : 0;
-    uint64_t blocks = (nnz + kBlock - 1) / kBlock;
-    if (blocks > 2048) blocks = 2048;
-    hipLaunchKernelGGL(k_item_count, dim3((uint32_t)blocks), dim3(kBlock), lds, stream, items, nnz,
-                       counts, n_item_ids, use_lds);
+// blocks of the per-block histograms and the chunk each one counts
+static void item_hist_shape(uint64_t nnz, uint32_t *nb, uint64_t *chunk) {
+    const uint64_t c = std::max<uint64_t>(8192, (nnz + 255) / 256);
+    *chunk = c;
+    *nb = (uint32_t)std::max<uint64_t>(1, (nnz + c - 1) / c);
+}
+
+uint64_t item_count_scratch_words(uint64_t nnz, uint32_t n_item_ids) {
+    if (nnz == 0 || n_item_ids > kHistItems) return 0;
+    uint32_t nb = 0;
+    uint64_t chunk = 0;
+    item_hist_shape(nnz, &nb, &chunk);
+    return (uint64_t)nb * n_item_ids;
+}
+
+hipError_t launch_item_count(const uint32_t *items, uint64_t nnz, uint32_t *counts,
+                             uint32_t n_item_ids, uint32_t *part, hipStream_t stream) {
+    if (n_item_ids == 0) return hipSuccess;
+    if (nnz == 0 || n_item_ids > kHistItems) {
+        hipError_t e = launch_fill_u32(counts, n_item_ids, 0u, stream);
+        if (e != hipSuccess || nnz == 0) return e;
+        const uint64_t blocks = std::min<uint64_t>((nnz + kBlock - 1) / kBlock, 4096);
+        hipLaunchKernelGGL(k_item_count, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, items,
+                           nnz, counts);
+        return hipGetLastError();
+    }
+    uint32_t nb = 0;
+    uint64_t chunk = 0;
+    item_hist_shape(nnz, &nb, &chunk);
+    hipLaunchKernelGGL(k_item_hist, dim3(nb), dim3(kBlock), (size_t)n_item_ids * 4, stream, items,
+                       nnz, chunk, n_item_ids, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_item_sum, dim3((n_item_ids + kWave - 1) / kWave), dim3(kBlock), 0, stream,
+                       part, nb, n_item_ids, counts);
     return hipGetLastError();
 }
 
@@ -1604,10 +1924,54 @@ hipError_t launch_bitmap_build(const uint64_t *offsets, const uint32_t *items, u
                                const uint32_t *rank_of_item, uint32_t *rows, uint32_t Wp,
                                hipStream_t stream) {
     if (n_tx == 0) return hipSuccess;
-    uint64_t blocks = (n_tx + kBlock - 1) / kBlock;
-    if (blocks > 4096) blocks = 4096;
+    const uint64_t blocks = (n_tx + kBuildTx - 1) / kBuildTx;
+    if (blocks >= (1ull << 31)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_bitmap_build, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, offsets,
                        items, n_tx, rank_of_item, rows, Wp);
+    return hipGetLastError();
+}
+
+hipError_t launch_tidlist(const uint32_t *rows, uint32_t n, uint32_t Wp, const uint64_t *tl_off,
+                          uint32_t *tl, uint32_t *rowpre, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tidlist, dim3((n + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock), 0,
+                       stream, rows, n, Wp, tl_off, tl, rowpre, rowpre_words(Wp));
+    return hipGetLastError();
+}
+
+hipError_t launch_rank_tx(const uint64_t *off, const uint32_t *items, uint64_t n_tx,
+                          const uint32_t *rank_of_item, const uint32_t *rows, uint32_t Wp,
+                          const uint32_t *rowpre, const uint64_t *tl_off, uint32_t *rk,
+                          uint32_t *tlp, uint16_t *suf, hipStream_t stream) {
+    if (n_tx == 0) return hipSuccess;
+    const uint64_t groups = (n_tx + kRankGroup - 1) / kRankGroup;
+    const uint64_t blocks = std::min<uint64_t>((groups + kWavesPerBlock - 1) / kWavesPerBlock, 65536);
+    hipLaunchKernelGGL(k_rank_tx, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, off, items, n_tx,
+                       rank_of_item, rows, Wp, rowpre, rowpre_words(Wp), tl_off, rk, tlp, suf);
+    return hipGetLastError();
+}
+
+// words per column tile for n rows within lds_max bytes of LDS, the block's
+// transaction offsets included (0: does not fit)
+uint32_t bitmap_tile_words(uint32_t n, size_t lds_max) {
+    const size_t fixed = (32 * kTileMaxWords + 1) * sizeof(uint64_t);
+    if (lds_max <= fixed) return 0;
+    for (uint32_t K = kTileMaxWords; K >= 4; K /= 2)
+        if ((uint64_t)n * K * 4 <= lds_max - fixed) return K;
+    return 0;
+}
+
+hipError_t launch_bitmap_tiles(const uint64_t *offsets, const uint32_t *items, uint64_t n_tx,
+                               const uint32_t *rank_of_item, uint32_t n, uint32_t *rows,
+                               uint32_t Wp, uint32_t K, hipStream_t stream) {
+    if (n == 0 || Wp == 0) return hipSuccess;
+    if (K < 4 || K > kTileMaxWords || K % 4 != 0 || Wp % 4 != 0) return hipErrorInvalidValue;
+    const size_t lds = (size_t)n * K * 4;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bitmap_tile),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bitmap_tile, dim3((Wp + K - 1) / K), dim3(kBlock), lds, stream, offsets,
+                       items, n_tx, rank_of_item, n, rows, Wp, K);
     return hipGetLastError();
 }
 
@@ -1651,24 +2015,6 @@ hipError_t launch_root_sparse(const uint32_t *bt, uint32_t np, const uint64_t *n
     return hipGetLastError();
 }
 
-hipError_t launch_rank_tx(const uint64_t *off, const uint32_t *items, uint64_t n_tx,
-                          const uint32_t *rank_of_item, uint32_t *rk, uint32_t *len,
-                          hipStream_t stream) {
-    if (n_tx == 0) return hipSuccess;
-    const uint64_t blocks = std::min<uint64_t>((n_tx + kWavesPerBlock - 1) / kWavesPerBlock, 65536);
-    hipLaunchKernelGGL(k_rank_tx, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, off, items, n_tx,
-                       rank_of_item, rk, len);
-    return hipGetLastError();
-}
-
-hipError_t launch_tidlist(const uint32_t *rows, uint32_t n, uint32_t Wp, const uint64_t *tl_off,
-                          uint32_t *tl, hipStream_t stream) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tidlist, dim3((n + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock), 0,
-                       stream, rows, n, Wp, tl_off, tl);
-    return hipGetLastError();
-}
-
 // counters of a block: R rows x J columns in 60 KB of LDS
 void project_tile(uint32_t n, uint32_t *R, uint32_t *J) {
     const uint32_t words = 15360;
@@ -1676,8 +2022,8 @@ void project_tile(uint32_t n, uint32_t *R, uint32_t *J) {
     *R = std::max<uint32_t>(1, std::min<uint32_t>(kProjectMaxRows, words / *J));
 }
 
-hipError_t launch_root_project(const uint64_t *off, const uint32_t *rk, const uint32_t *len,
-                               const uint32_t *tl, const uint64_t *tl_off, uint32_t n,
+hipError_t launch_root_project(const uint32_t *rk, const uint32_t *tlp, const uint16_t *suf,
+                               const uint64_t *tl_off, uint32_t n, uint32_t max_supp,
                                uint32_t minsup, uint32_t *pairs, uint64_t cap,
                                unsigned long long *n_pairs, unsigned long long *work,
                                hipStream_t stream) {
@@ -1685,8 +2031,13 @@ hipError_t launch_root_project(const uint64_t *off, const uint32_t *rk, const ui
     uint32_t R = 0, J = 0;
     project_tile(n, &R, &J);
     const dim3 grid((n + R - 1) / R, (n + J - 1) / J);
-    hipLaunchKernelGGL(k_root_project, grid, dim3(kBlock), (size_t)R * J * 4, stream, off, rk, len,
-                       tl, tl_off, n, R, J, minsup, pairs, cap, n_pairs, work);
+    if (max_supp <= 0xFFFFu) {
+        hipLaunchKernelGGL(k_root_project<true>, grid, dim3(kBlock), (size_t)(R * J + 1) / 2 * 4,
+                           stream, rk, tlp, suf, tl_off, n, R, J, minsup, pairs, cap, n_pairs, work);
+    } else {
+        hipLaunchKernelGGL(k_root_project<false>, grid, dim3(kBlock), (size_t)R * J * 4, stream, rk,
+                           tlp, suf, tl_off, n, R, J, minsup, pairs, cap, n_pairs, work);
+    }
     return hipGetLastError();
 }
 

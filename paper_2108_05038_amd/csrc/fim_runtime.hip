@@ -203,6 +203,7 @@ extern "C" fim_status fim_ctx_create(int device, void *hip_stream, const fim_all
     }
     c->n_cu = prop.multiProcessorCount;
     c->total_mem = prop.totalGlobalMem;
+    c->lds_per_block = prop.sharedMemPerBlock;
     c->arch = arch;
     *out = c;
     return FIM_OK;
@@ -298,6 +299,7 @@ extern "C" fim_status fim_db_create(fim_ctx *ctx, uint64_t n_tx, const uint64_t 
         pos += n;
         db->h_off[t + 1] = pos;
         db->pairs_in_tx += n * (n ? n - 1 : 0) / 2;
+        db->max_tx_len = std::max(db->max_tx_len, n);
     }
     db->h_items.resize(pos);
     db->ctx = ctx;
@@ -422,15 +424,22 @@ struct Inst {
     std::vector<uint64_t> nz_off;
     std::vector<uint32_t> nz_cnt;
     DevBuf d_nz_off, d_nz_w, d_nz_m, d_nz_cnt, d_bt;
-    // projected: ranked transactions, tid lists, pair increments
+    // projected: ranked transactions, tid lists and the lists' pointers into
+    // the ranked transactions, pair increments
     std::vector<uint64_t> tl_off;
-    DevBuf d_rk, d_len, d_tl, d_tl_off, d_work;
+    DevBuf d_rk, d_tlp, d_suf, d_tl, d_tl_off, d_rowpre, d_work;
     unsigned long long project_work = 0;
     fim_stats st{};
     uint64_t first_class_rows = 0;  // sum of atoms over first-level classes with >= 2 atoms
 };
 
 }  // namespace
+
+uint32_t max_supp_of(const Inst &I) {
+    uint32_t m = 0;
+    for (uint32_t r = 0; r < I.n_freq; r++) m = std::max(m, I.supp_of_rank[r]);
+    return m;
+}
 
 // item order key: ascending support, ties by item id (or item id alone)
 static void rank_items(Inst &I, bool by_id) {
@@ -797,16 +806,21 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
     hipStream_t s = ctx->stream;
     std::vector<Inst> insts(n_inst);
 
-    // ---------------- a2: item supports (all instances, one sync)
+    // ---------------- a2: item supports (all instances, one sync; the block
+    // histograms share one scratch buffer, used in stream order)
+    uint64_t part_words = 0;
+    for (uint32_t q = 0; q < n_inst; q++)
+        part_words = std::max(part_words, item_count_scratch_words(reqs[q].db->nnz, reqs[q].db->n_item_ids));
+    DevBuf d_part(ctx);
+    if (part_words) ENSURE(d_part, ctx, part_words * 4);
     for (uint32_t q = 0; q < n_inst; q++) {
         Inst &I = insts[q];
         I.db = reqs[q].db;
         I.minsup = reqs[q].minsup;
         const uint32_t ni = I.db->n_item_ids;
         ENSURE(I.d_counts, ctx, (size_t)ni * 4);
-        HIPCHK(launch_fill_u32(I.d_counts.as<uint32_t>(), ni, 0u, s));
-        HIPCHK(launch_item_count(I.db->d_off.as<uint64_t>(), I.db->d_items.as<uint32_t>(),
-                                 I.db->nnz, I.d_counts.as<uint32_t>(), ni, s));
+        HIPCHK(launch_item_count(I.db->d_items.as<uint32_t>(), I.db->nnz, I.d_counts.as<uint32_t>(),
+                                 ni, part_words ? d_part.as<uint32_t>() : nullptr, s));
         I.counts.resize(ni);
         HIPCHK(hipMemcpyAsync(I.counts.data(), I.d_counts.as<void>(), (size_t)ni * 4,
                               hipMemcpyDeviceToHost, s));
@@ -852,43 +866,51 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                               hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(I.d_item_of_rank.as<void>(), I.item_of_rank.data(),
                               (size_t)I.n_freq * 4, hipMemcpyHostToDevice, s));
-        HIPCHK(launch_fill_u32(I.d_rows.as<uint32_t>(), (uint64_t)I.n_freq * I.Wp, 0u, s));
-        HIPCHK(launch_bitmap_build(I.db->d_off.as<uint64_t>(), I.db->d_items.as<uint32_t>(),
-                                   I.db->n_tx, I.d_rank_of_item.as<uint32_t>(),
-                                   I.d_rows.as<uint32_t>(), I.Wp, s));
-        if (I.n_freq < 2 || opts.max_len == 1) continue;
-        const uint64_t all = (uint64_t)I.n_freq * (I.n_freq - 1) / 2;
-        const uint64_t cap = std::min<uint64_t>(all, std::max<uint64_t>(1u << 16, 64ull * I.n_freq));
-        ENSURE(I.d_pairs, ctx, cap * 12);
-        ENSURE(I.d_npairs, ctx, 8);
-        HIPCHK(launch_fill_u32(I.d_npairs.as<uint32_t>(), 2, 0u, s));
-        // Root-class kernel by estimated time (picoseconds per unit measured
-        // on MI355X): whole rows cost all * W pair-words; covers at most
-        // sum_i min(supp_i, W)(n - 1 - i) pair-words (row i has at most
-        // min(supp_i, W) non-zero words), each a cached 4-byte load; the
-        // projected count one LDS increment per pair inside a transaction
-        // (bounded by the pairs over all items) plus its set-up.
         const uint32_t n = I.n_freq;
-        double bound = 0.0;
-        for (uint32_t r = 0; r < n; r++)
-            bound += (double)std::min<uint32_t>(I.supp_of_rank[r], I.W) * (double)(n - 1 - r);
-        const double t_rows = 0.075 * (double)all * (double)I.W;
-        const double t_covers = n >= 64 && n <= 65535 ? 0.75 * bound + 1.5e5 : 1e300;
-        const double t_project = I.db->n_tx < (1ull << 32)
-                                     ? 20.0 * (double)I.db->pairs_in_tx + 6.0 * (double)I.db->nnz + 1.5e5
-                                     : 1e300;
-        if (opts.flags & FIM_FLAG_DENSE_ROOT) I.root_kind = 0;
-        else if (opts.flags & FIM_FLAG_ROOT_COVERS) I.root_kind = n <= 65535 ? 1 : 0;
-        else if (opts.flags & FIM_FLAG_ROOT_PROJECT) I.root_kind = I.db->n_tx < (1ull << 32) ? 2 : 0;
-        else if (t_project <= t_covers && t_project < t_rows) I.root_kind = 2;
-        else if (t_covers < t_rows) I.root_kind = 1;
-        else I.root_kind = 0;
+        // positions in the ranked transactions are 32-bit, suffix lengths 16-bit
+        const bool fits = I.db->nnz + I.db->n_tx + 8 < (1ull << 32) && I.db->max_tx_len < (1u << 16);
+        const bool pairs_needed = n >= 2 && opts.max_len != 1;
+        if (pairs_needed) {
+            // Root-class kernel by estimated time (picoseconds per unit measured
+            // on MI355X): whole rows cost all * W pair-words; covers at most
+            // sum_i min(supp_i, W)(n - 1 - i) pair-words (row i has at most
+            // min(supp_i, W) non-zero words), each a cached 4-byte load; the
+            // projected count one LDS increment per pair inside a transaction
+            // (bounded by the pairs over all items) plus its set-up.
+            const uint64_t all = (uint64_t)n * (n - 1) / 2;
+            double bound = 0.0;
+            for (uint32_t r = 0; r < n; r++)
+                bound += (double)std::min<uint32_t>(I.supp_of_rank[r], I.W) * (double)(n - 1 - r);
+            const double t_rows = 0.075 * (double)all * (double)I.W;
+            const double t_covers = n >= 64 && n <= 65535 ? 0.75 * bound + 1.5e5 : 1e300;
+            const double t_project =
+                fits ? 20.0 * (double)I.db->pairs_in_tx + 6.0 * (double)I.db->nnz + 1.5e5 : 1e300;
+            if (opts.flags & FIM_FLAG_DENSE_ROOT) I.root_kind = 0;
+            else if (opts.flags & FIM_FLAG_ROOT_COVERS) I.root_kind = n <= 65535 ? 1 : 0;
+            else if (opts.flags & FIM_FLAG_ROOT_PROJECT) I.root_kind = fits ? 2 : 0;
+            else if (t_project <= t_covers && t_project < t_rows) I.root_kind = 2;
+            else if (t_covers < t_rows) I.root_kind = 1;
+            else I.root_kind = 0;
+        }
+        // rows from LDS column tiles when n rows of a tile fit a workgroup's
+        // LDS, else zero fill and global atomics
+        const uint32_t K = bitmap_tile_words(n, ctx->lds_per_block);
+        if (K) {
+            HIPCHK(launch_bitmap_tiles(I.db->d_off.as<uint64_t>(), I.db->d_items.as<uint32_t>(),
+                                       I.db->n_tx, I.d_rank_of_item.as<uint32_t>(), n,
+                                       I.d_rows.as<uint32_t>(), I.Wp, K, s));
+        } else {
+            HIPCHK(launch_fill_u32(I.d_rows.as<uint32_t>(), (uint64_t)n * I.Wp, 0u, s));
+            HIPCHK(launch_bitmap_build(I.db->d_off.as<uint64_t>(), I.db->d_items.as<uint32_t>(),
+                                       I.db->n_tx, I.d_rank_of_item.as<uint32_t>(),
+                                       I.d_rows.as<uint32_t>(), I.Wp, s));
+        }
         // Ascending transaction lists of the ranks (the set bits of their
         // rows), used by the projected root kernel and by pieces of work
         // whose rows are projected on a one-item prefix's cover
         uint32_t min_supp = ~0u;
         for (uint32_t r = 0; r < n; r++) min_supp = std::min(min_supp, I.supp_of_rank[r]);
-        const bool lists = I.root_kind == 2 ||
+        const bool lists = (I.root_kind == 2 && pairs_needed) ||
                            (!(opts.flags & FIM_FLAG_NO_PROJECT) && n >= 3 &&
                             (opts.max_len == 0 || opts.max_len >= 3) &&
                             4ull * min_supp <= I.db->n_tx && I.db->n_tx < (1ull << 32));
@@ -899,21 +921,34 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             ENSURE(I.d_tl_off, ctx, (n + 1) * 8);
             HIPCHK(hipMemcpyAsync(I.d_tl_off.as<void>(), I.tl_off.data(), (n + 1) * 8,
                                   hipMemcpyHostToDevice, s));
+            const bool ranked = I.root_kind == 2 && pairs_needed;
+            if (ranked) ENSURE(I.d_rowpre, ctx, (uint64_t)n * rowpre_words(I.Wp) * 4);
             HIPCHK(launch_tidlist(I.d_rows.as<uint32_t>(), n, I.Wp, I.d_tl_off.as<uint64_t>(),
-                                  I.d_tl.as<uint32_t>(), s));
+                                  I.d_tl.as<uint32_t>(), ranked ? I.d_rowpre.as<uint32_t>() : nullptr, s));
+            if (ranked) {
+                ENSURE(I.d_rk, ctx, (I.db->nnz + I.db->n_tx + 8) * 4);
+                ENSURE(I.d_tlp, ctx, std::max<uint64_t>(I.tl_off[n], 1) * 4);
+                ENSURE(I.d_suf, ctx, std::max<uint64_t>(I.tl_off[n], 1) * 2);
+                HIPCHK(launch_rank_tx(I.db->d_off.as<uint64_t>(), I.db->d_items.as<uint32_t>(),
+                                      I.db->n_tx, I.d_rank_of_item.as<uint32_t>(),
+                                      I.d_rows.as<uint32_t>(), I.Wp, I.d_rowpre.as<uint32_t>(),
+                                      I.d_tl_off.as<uint64_t>(), I.d_rk.as<uint32_t>(),
+                                      I.d_tlp.as<uint32_t>(), I.d_suf.as<uint16_t>(), s));
+            }
         }
+        if (!pairs_needed) continue;
+        const uint64_t all = (uint64_t)n * (n - 1) / 2;
+        const uint64_t cap = std::min<uint64_t>(all, std::max<uint64_t>(1u << 16, 64ull * n));
+        ENSURE(I.d_pairs, ctx, cap * 12);
+        ENSURE(I.d_npairs, ctx, 8);
+        HIPCHK(launch_fill_u32(I.d_npairs.as<uint32_t>(), 2, 0u, s));
         if (I.root_kind == 2) {
-            ENSURE(I.d_rk, ctx, std::max<uint64_t>(I.db->nnz, 1) * 4);
-            ENSURE(I.d_len, ctx, std::max<uint64_t>(I.db->n_tx, 1) * 4);
             ENSURE(I.d_work, ctx, 8);
             HIPCHK(launch_fill_u32(I.d_work.as<uint32_t>(), 2, 0u, s));
-            HIPCHK(launch_rank_tx(I.db->d_off.as<uint64_t>(), I.db->d_items.as<uint32_t>(),
-                                  I.db->n_tx, I.d_rank_of_item.as<uint32_t>(), I.d_rk.as<uint32_t>(),
-                                  I.d_len.as<uint32_t>(), s));
             HIPCHK(hipEventRecord(rev[2 * q], s));
-            HIPCHK(launch_root_project(I.db->d_off.as<uint64_t>(), I.d_rk.as<uint32_t>(),
-                                       I.d_len.as<uint32_t>(), I.d_tl.as<uint32_t>(),
-                                       I.d_tl_off.as<uint64_t>(), n, I.minsup,
+            HIPCHK(launch_root_project(I.d_rk.as<uint32_t>(), I.d_tlp.as<uint32_t>(),
+                                       I.d_suf.as<uint16_t>(), I.d_tl_off.as<uint64_t>(), n,
+                                       max_supp_of(I), I.minsup,
                                        I.d_pairs.as<uint32_t>(), cap,
                                        I.d_npairs.as<unsigned long long>(),
                                        I.d_work.as<unsigned long long>(), s));
@@ -956,7 +991,9 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         HIPCHK(hipMemcpyAsync(&I.n_pairs, I.d_npairs.as<void>(), 8, hipMemcpyDeviceToHost, s));
     }
     const bool deep = opts.max_len == 0 || opts.max_len >= 3;
+    tr.mark("  (root work queued)");
     HIPCHK(hipStreamSynchronize(s));
+    tr.mark("  (root work done)");
     for (uint32_t q = 0; q < n_inst; q++) {
         const Inst &I = insts[q];
         if (I.n_freq < 2 || opts.max_len == 1) continue;
@@ -973,9 +1010,9 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             ENSURE(I.d_pairs, ctx, I.n_pairs * 12);
             HIPCHK(launch_fill_u32(I.d_npairs.as<uint32_t>(), 2, 0u, s));
             if (I.root_kind == 2)
-                HIPCHK(launch_root_project(I.db->d_off.as<uint64_t>(), I.d_rk.as<uint32_t>(),
-                                           I.d_len.as<uint32_t>(), I.d_tl.as<uint32_t>(),
-                                           I.d_tl_off.as<uint64_t>(), I.n_freq, I.minsup,
+                HIPCHK(launch_root_project(I.d_rk.as<uint32_t>(), I.d_tlp.as<uint32_t>(),
+                                           I.d_suf.as<uint16_t>(), I.d_tl_off.as<uint64_t>(),
+                                           I.n_freq, max_supp_of(I), I.minsup,
                                            I.d_pairs.as<uint32_t>(), I.n_pairs,
                                            I.d_npairs.as<unsigned long long>(),
                                            I.d_work.as<unsigned long long>(), s));
@@ -1021,6 +1058,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         I.st.pair_words = I.st.root_pair_words;
     }
     HIPCHK(hipStreamSynchronize(s));
+    tr.mark("  (pairs copied)");
     parallel_for(n_inst, host_threads((uint64_t)n_inst << 14), [&](uint64_t q) {
         Inst &I = insts[q];
         I.st.root_kernel_ns = (uint64_t)(root_ms * 1e6);

@@ -193,6 +193,23 @@ def test_root_kernels_agree(fim, ctx, n_tx, n_items, mlen, minsup):
         assert d["pair_words"] - d["root_pair_words"] < f["pair_words"] - f["root_pair_words"]
 
 
+def test_projected_root_long_transactions(fim, ctx):
+    # transactions of more than one wave of items (up to 127) with infrequent
+    # items among them: the ranked transactions are built 64 items at a time
+    o_, it, ni = synth.basket(3600, 3000, 600, 90.0, 1200, 4.0)
+    db = synth.Database(o_, it, ni, 300)
+    assert max(np.diff(np.asarray(o_))) > 64
+    say("projected root, long transactions")
+    o = oracle.mine_db(db, threads=4)
+    assert max(len(u) for u in o.itemsets()) >= 3
+    for flags in (fim.FIM_FLAG_ROOT_PROJECT, fim.FIM_FLAG_ROOT_PROJECT | fim.FIM_FLAG_NO_PROJECT, 0):
+        g = gpu_mine(fim, ctx, db, flags=flags)
+        if flags & fim.FIM_FLAG_ROOT_PROJECT:
+            assert g.stats["root_kernel"] == 2
+        assert_same(g, o, flags)
+        assert g.stats["candidates"] == o.candidates, flags
+
+
 def test_projection_with_work_sharing(fim, ctx):
     # few workers and a skewed database: donated classes (prefixes of two or
     # more items) are rebuilt projected on their own covers
