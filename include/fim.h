@@ -311,6 +311,16 @@ fim_status fim_result_sizes(const fim_result *r, uint64_t *n_itemsets, uint64_t 
 fim_status fim_result_copy(const fim_result *r, uint64_t *offsets, uint32_t *items,
                            uint32_t *supports);
 
+/*
+ * The same three arrays in place, without a copy: *offsets, *items and
+ * *supports receive pointers into host memory owned by r (laid out as for
+ * fim_result_copy; *items and *supports are NULL for an empty result).  They
+ * stay valid, and must not be written, until fim_result_destroy(r).
+ * Errors: FIM_E_INVALID_ARG (a NULL argument).
+ */
+fim_status fim_result_view(const fim_result *r, const uint64_t **offsets, const uint32_t **items,
+                           const uint32_t **supports);
+
 fim_status fim_result_stats(const fim_result *r, fim_stats *out);
 void fim_result_destroy(fim_result *r);
 

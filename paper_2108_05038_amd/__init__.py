@@ -48,7 +48,8 @@ EXPORTED = [
     "fim_status_str", "fim_last_error", "fim_version", "fim_ctx_create", "fim_ctx_destroy",
     "fim_ctx_release_cached",
     "fim_db_create", "fim_db_destroy", "fim_db_sizes", "fim_minsup_from_relative", "fim_mine",
-    "fim_mine_batch", "fim_autotune", "fim_result_sizes", "fim_result_copy", "fim_result_stats",
+    "fim_mine_batch", "fim_autotune", "fim_result_sizes", "fim_result_copy", "fim_result_view",
+    "fim_result_stats",
     "fim_result_destroy", "fim_server_create", "fim_server_submit", "fim_server_poll",
     "fim_server_wait", "fim_server_next", "fim_server_cancel", "fim_server_stats_get", "fim_server_destroy",
     "fim_estimate_sample_sizes", "fim_reservoir_sample", "fim_partition_lpt", "fim_lpt_schedule",
@@ -133,6 +134,7 @@ def lib():
         "fim_autotune": (i32, [V, u32, P(V), P(u32), P(fim_options), u32, P(fim_options), P(u64)]),
         "fim_result_sizes": (i32, [V, P(u64), P(u64)]),
         "fim_result_copy": (i32, [V, P(u64), P(u32), P(u32)]),
+        "fim_result_view": (i32, [V, P(P(u64)), P(P(u32)), P(P(u32))]),
         "fim_result_stats": (i32, [V, P(fim_stats)]),
         "fim_result_destroy": (None, [V]),
         "fim_server_create": (i32, [V, P(fim_server_config), P(V)]),
@@ -241,20 +243,48 @@ def fim_autotune(ctx, dbs, minsups, base: fim_options | None = None, reps: int =
     return out, ns.value
 
 
+class _ResultHandle:
+    """Owns a result handle; destroyed when the last array viewing it goes."""
+
+    def __init__(self, res):
+        self.res = res
+
+    def __del__(self):
+        L = _lib
+        if self.res is not None and L is not None:
+            L.fim_result_destroy(self.res)
+            self.res = None
+
+
+def _view(addr, n, ctype, dtype, owner):
+    if n == 0 or not addr:
+        return np.zeros(0, dtype)
+    buf = (ctype * n).from_address(addr)
+    buf._owner = owner  # the arrays keep the handle alive
+    return np.frombuffer(buf, dtype=dtype)
+
+
 def fim_result_take(res) -> "Result":
-    """Copy a result handle into numpy arrays and destroy the handle."""
+    """Numpy views of a result handle's arrays (no copy); the handle is
+    destroyed when the last of them is garbage-collected.  The views are
+    read-only."""
     L = lib()
     n, ni = ctypes.c_uint64(), ctypes.c_uint64()
     _check(L.fim_result_sizes(res, ctypes.byref(n), ctypes.byref(ni)))
-    off = np.zeros(n.value + 1, np.uint64)
-    items = np.zeros(max(ni.value, 1), np.uint32)
-    supp = np.zeros(max(n.value, 1), np.uint32)
-    _check(L.fim_result_copy(res, _u64p(off), _u32p(items), _u32p(supp)))
     st = fim_stats()
     _check(L.fim_result_stats(res, ctypes.byref(st)))
-    L.fim_result_destroy(res)
     stats = {name: int(getattr(st, name)) for name, _ in fim_stats._fields_}
-    return Result(off, items[:ni.value], supp[:n.value], stats)
+    po, pi, ps = ctypes.POINTER(ctypes.c_uint64)(), ctypes.POINTER(ctypes.c_uint32)(), \
+        ctypes.POINTER(ctypes.c_uint32)()
+    _check(L.fim_result_view(res, ctypes.byref(po), ctypes.byref(pi), ctypes.byref(ps)))
+    owner = _ResultHandle(res)
+    addr = lambda p: ctypes.cast(p, ctypes.c_void_p).value or 0
+    off = _view(addr(po), n.value + 1, ctypes.c_uint64, np.uint64, owner)
+    items = _view(addr(pi), ni.value, ctypes.c_uint32, np.uint32, owner)
+    supp = _view(addr(ps), n.value, ctypes.c_uint32, np.uint32, owner)
+    for a in (off, items, supp):
+        a.flags.writeable = False
+    return Result(off, items, supp, stats)
 
 
 def fim_estimate_sample_sizes(eps_db=0.02, delta_db=0.05, rho=0.001, eps_fi=0.0005,

@@ -1,12 +1,106 @@
 // Canonical order of a frequent-itemset result (host).
 #include "fim_canon.h"
 
+#include <hip/hip_runtime.h>
+
 #include <algorithm>
+#include <cstdlib>
+#include <map>
 #include <memory>
+#include <mutex>
+#include <new>
+#include <unordered_map>
 
 namespace fim {
 
 thread_local uint32_t g_host_thread_cap = 16;
+
+// ---------------------------------------------------------------- host pool
+// Blocks are sized in powers of two; released blocks wait in per-size lists
+// (up to kPoolCacheBytes in all) for the next request of their size.  Blocks
+// are page-locked while the page-locked total stays below kPinnedBudget,
+// ordinary heap memory beyond it (or when page-locking fails).
+namespace {
+
+constexpr size_t kPoolCacheBytes = size_t(2) << 30;
+constexpr size_t kPinnedBudget = size_t(16) << 30;
+
+struct HostPool {
+    std::mutex mu;
+    std::map<size_t, std::vector<void *>> free_lists;
+    std::unordered_map<void *, bool> pinned;  // every live or cached block
+    size_t cached = 0, pinned_total = 0;
+};
+
+HostPool &host_pool() {
+    static HostPool *p = new HostPool();  // never destroyed: blocks may outlive static teardown
+    return *p;
+}
+
+size_t pool_class(size_t bytes) {
+    size_t c = kHostPoolMin;
+    while (c < bytes) c <<= 1;
+    return c;
+}
+
+}  // namespace
+
+void *host_pool_alloc(size_t bytes) {
+    const size_t c = pool_class(bytes);
+    HostPool &P = host_pool();
+    {
+        std::lock_guard<std::mutex> g(P.mu);
+        auto it = P.free_lists.find(c);
+        if (it != P.free_lists.end() && !it->second.empty()) {
+            void *p = it->second.back();
+            it->second.pop_back();
+            P.cached -= c;
+            return p;
+        }
+    }
+    void *p = nullptr;
+    bool pin = false;
+    {
+        std::lock_guard<std::mutex> g(P.mu);
+        pin = P.pinned_total + c <= kPinnedBudget;
+        if (pin) P.pinned_total += c;
+    }
+    if (pin && hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+        std::lock_guard<std::mutex> g(P.mu);
+        P.pinned_total -= c;
+        pin = false;
+    }
+    if (!p) {
+        p = std::malloc(c);
+        if (!p) throw std::bad_alloc();
+    }
+    std::lock_guard<std::mutex> g(P.mu);
+    P.pinned[p] = pin;
+    return p;
+}
+
+void host_pool_free(void *p, size_t bytes) {
+    if (!p) return;
+    const size_t c = pool_class(bytes);
+    HostPool &P = host_pool();
+    bool pin = false;
+    {
+        std::lock_guard<std::mutex> g(P.mu);
+        if (P.cached + c <= kPoolCacheBytes) {
+            P.free_lists[c].push_back(p);
+            P.cached += c;
+            return;
+        }
+        auto it = P.pinned.find(p);
+        pin = it != P.pinned.end() && it->second;
+        if (it != P.pinned.end()) P.pinned.erase(it);
+        if (pin) P.pinned_total -= c;
+    }
+    if (pin) (void)hipHostFree(p);
+    else std::free(p);
+}
 
 
 namespace {

@@ -13,9 +13,16 @@
 
 namespace fim {
 
+// Host blocks of at least kHostPoolMin bytes for result arrays: page-locked
+// (device copies go straight into them), kept for reuse after release so
+// that a later result does not fault its pages in again.  Thread-safe.
+constexpr size_t kHostPoolMin = 1u << 20;
+void *host_pool_alloc(size_t bytes);
+void host_pool_free(void *p, size_t bytes);
+
 // std::allocator whose value-less construct leaves the element
 // uninitialised, so that resizing large result arrays does not first zero
-// them on one thread
+// them on one thread; large arrays come from the host pool
 template <class T>
 struct UninitAlloc : std::allocator<T> {
     template <class U>
@@ -25,6 +32,14 @@ struct UninitAlloc : std::allocator<T> {
     UninitAlloc() = default;
     template <class U>
     UninitAlloc(const UninitAlloc<U> &) {}
+    T *allocate(size_t n) {
+        if (n * sizeof(T) >= kHostPoolMin) return static_cast<T *>(host_pool_alloc(n * sizeof(T)));
+        return std::allocator<T>::allocate(n);
+    }
+    void deallocate(T *p, size_t n) {
+        if (n * sizeof(T) >= kHostPoolMin) host_pool_free(p, n * sizeof(T));
+        else std::allocator<T>::deallocate(p, n);
+    }
     template <class U>
     void construct(U *p) noexcept {
         ::new ((void *)p) U;

@@ -363,6 +363,15 @@ extern "C" fim_status fim_result_copy(const fim_result *r, uint64_t *offsets, ui
     return FIM_OK;
 }
 
+extern "C" fim_status fim_result_view(const fim_result *r, const uint64_t **offsets,
+                                      const uint32_t **items, const uint32_t **supports) {
+    if (!r || !offsets || !items || !supports) return fim::set_error(FIM_E_INVALID_ARG, "NULL argument");
+    *offsets = r->off.data();
+    *items = r->items.empty() ? nullptr : r->items.data();
+    *supports = r->supp.empty() ? nullptr : r->supp.data();
+    return FIM_OK;
+}
+
 extern "C" fim_status fim_result_stats(const fim_result *r, fim_stats *out) {
     if (!r || !out) return fim::set_error(FIM_E_INVALID_ARG, "NULL argument");
     *out = r->stats;
