@@ -1581,11 +1581,11 @@ __device__ void run_frame(const InstDesc &I, uint32_t inst, uint32_t task, const
             }
             // Groups of kG ballot rounds (kG * 64 transactions, 2 kG words):
             // the group's transaction ids stay in registers while every atom's
-            // words are gathered, two atoms at a time (2 kG loads in flight);
-            // lane q < 2 kG collects word q of the group and stores it.  The
-            // groups cover every word below Wq (zeros past s).
+            // words are gathered, kA atoms at a time (kA * kG loads in
+            // flight); lane q < 2 kG collects word q of the group and stores
+            // it.  The groups cover every word below Wq (zeros past s).
             const uint32_t *tids = I.tl + t0;
-            constexpr uint32_t kG = 8;
+            constexpr uint32_t kG = 8, kA = 2;
             for (uint32_t g0 = 0; g0 < s; g0 += kG * kWave) {
                 uint32_t tg[kG];
 #pragma unroll
@@ -1594,34 +1594,29 @@ __device__ void run_frame(const InstDesc &I, uint32_t inst, uint32_t task, const
                     tg[j] = i < s ? tids[i] : kNone;
                 }
                 const uint32_t wbase = g0 / 32;
-                for (uint32_t e = 0; e < k; e += 2) {
-                    const bool two = e + 1 < k;
-                    const uint32_t *ra = I.rows + (uint64_t)src.ranks[e] * Wf;
-                    const uint32_t *rb = I.rows + (uint64_t)src.ranks[two ? e + 1 : e] * Wf;
-                    uint32_t xa[kG], xb[kG];
+                for (uint32_t e0 = 0; e0 < k; e0 += kA) {
+                    uint32_t x[kA][kG];
 #pragma unroll
-                    for (uint32_t j = 0; j < kG; j++) {
-                        const uint32_t t = tg[j];
-                        xa[j] = t != kNone ? ra[t >> 5] : 0u;
-                        xb[j] = (two && t != kNone) ? rb[t >> 5] : 0u;
-                    }
-                    uint32_t wa = 0, wb = 0;
+                    for (uint32_t a = 0; a < kA; a++) {
+                        const uint32_t e = min(e0 + a, k - 1);  // past k: a repeat, not stored
+                        const uint32_t *ra = I.rows + (uint64_t)src.ranks[e] * Wf;
 #pragma unroll
-                    for (uint32_t j = 0; j < kG; j++) {
-                        const uint32_t tb = tg[j] & 31;
-                        const uint64_t ba = __ballot((xa[j] >> tb) & 1u);
-                        const uint64_t bb = __ballot((xb[j] >> tb) & 1u);
-                        if (lane == 2 * j) {
-                            wa = (uint32_t)ba;
-                            wb = (uint32_t)bb;
-                        } else if (lane == 2 * j + 1) {
-                            wa = (uint32_t)(ba >> 32);
-                            wb = (uint32_t)(bb >> 32);
+                        for (uint32_t j = 0; j < kG; j++) {
+                            const uint32_t t = tg[j];
+                            x[a][j] = t != kNone ? ra[t >> 5] : 0u;
                         }
                     }
-                    if (lane < 2 * kG && wbase + lane < Wq) {
-                        region[(uint64_t)e * Wq + wbase + lane] = wa;
-                        if (two) region[(uint64_t)(e + 1) * Wq + wbase + lane] = wb;
+#pragma unroll
+                    for (uint32_t a = 0; a < kA; a++) {
+                        uint32_t w = 0;
+#pragma unroll
+                        for (uint32_t j = 0; j < kG; j++) {
+                            const uint64_t bits = __ballot((x[a][j] >> (tg[j] & 31)) & 1u);
+                            if (lane == 2 * j) w = (uint32_t)bits;
+                            else if (lane == 2 * j + 1) w = (uint32_t)(bits >> 32);
+                        }
+                        if (e0 + a < k && lane < 2 * kG && wbase + lane < Wq)
+                            region[(uint64_t)(e0 + a) * Wq + wbase + lane] = w;
                     }
                 }
             }

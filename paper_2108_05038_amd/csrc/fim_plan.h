@@ -18,6 +18,9 @@ struct PlanInput {
     const std::vector<uint32_t> *rank_of_item;
     const std::vector<uint32_t> *l2_off;   // atoms of the first-level classes
     const std::vector<uint32_t> *l2_atom;
+    const std::vector<uint32_t> *supp_of_rank = nullptr;  // supports of the frequent items
+    uint32_t Wp = 0;                       // words per stored row
+    bool project = false;                  // rows are projected on small prefix covers
     bool estimate = true;                  // draw the database sample for this instance
 };
 

@@ -303,7 +303,10 @@ fim_status plan_tasks(fim_ctx *ctx, const std::vector<PlanInput> &in, const fim_
     }
     // proxy weight of a second-level class: pairs of its child class times
     // words per row (the weight of a class with k atoms in Zaki's bitonic
-    // scheduling is C(k, 2)); instances without a sample estimate use it
+    // scheduling is C(k, 2)); instances without a sample estimate use it.
+    // The rows of first-level class i are ceil(supp(i) / 32) words wide when
+    // they are projected on its cover (a quarter of the stored width or
+    // less, as the persistent kernel decides), else W.
     std::vector<std::vector<double>> w(n_inst), px(n_inst);
     std::vector<PlanClass> cls_in;
     std::vector<const double *> rw, rp;
@@ -315,9 +318,15 @@ fim_status plan_tasks(fim_ctx *ctx, const std::vector<PlanInput> &in, const fim_
         const bool est = !row_w[q].empty();
         for (uint32_t i = 0; i < in[q].n_freq; i++) {
             const uint32_t f = l2o[i + 1] - l2o[i];
+            double width = (double)in[q].W;
+            if (in[q].project && in[q].supp_of_rank) {
+                const uint32_t s = (*in[q].supp_of_rank)[i];
+                const uint32_t Wq = std::max<uint32_t>(4, ((s + 31) / 32 + 3) / 4 * 4);
+                if (4ull * Wq <= in[q].Wp) width = (double)((s + 31) / 32);
+            }
             for (uint32_t r = 0; r + 1 < f; r++) {
                 const double k = (double)(f - r - 1);
-                px[q][l2o[i] + r] = (k * (k + 1.0) / 2.0 + 1.0) * (double)in[q].W;
+                px[q][l2o[i] + r] = (k * (k + 1.0) / 2.0 + 1.0) * width;
                 w[q][l2o[i] + r] = est ? row_w[q][l2o[i] + r] : px[q][l2o[i] + r];
             }
         }

@@ -1099,6 +1099,9 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             pin[q].rank_of_item = &I.rank_of_item;
             pin[q].l2_off = &I.l2_off;
             pin[q].l2_atom = &I.l2_atom;
+            pin[q].supp_of_rank = &I.supp_of_rank;
+            pin[q].Wp = I.Wp;
+            pin[q].project = !(opts.flags & FIM_FLAG_NO_PROJECT);
             // The sample-based estimate balances the work below the root
             // class.  Its first level holds sum f_i (f_i - 1) / 2 candidate
             // pairs (f_i atoms of first-level class i), known exactly now;
