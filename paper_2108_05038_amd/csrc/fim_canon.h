@@ -13,10 +13,10 @@
 
 namespace fim {
 
-// Host blocks of at least kHostPoolMin bytes for result arrays: page-locked
+// Host blocks of at least kHostPoolMin bytes (16 KB) for result arrays: page-locked
 // (device copies go straight into them), kept for reuse after release so
 // that a later result does not fault its pages in again.  Thread-safe.
-constexpr size_t kHostPoolMin = 1u << 20;
+constexpr size_t kHostPoolMin = 1u << 14;
 void *host_pool_alloc(size_t bytes);
 void host_pool_free(void *p, size_t bytes);
 

@@ -32,6 +32,11 @@ struct fim_ctx {
     // pinned host staging buffer for device-to-host copies of results
     uint32_t *pinned = nullptr;
     size_t pinned_words = 0;
+    // page-locked staging of one run's host-to-device copies (fim::h2d):
+    // bump-allocated during the run, emptied when the next run starts
+    char *up = nullptr;
+    size_t up_cap = 0, up_used = 0, up_need = 0;
+    int up_depth = 0;
     uint32_t *stage(size_t words);
 
     // Device blocks freed by the library are kept by size class for the
@@ -83,6 +88,25 @@ class DevBuf {
     fim_ctx *ctx_ = nullptr;
     void *p_ = nullptr;
     size_t bytes_ = 0;
+};
+
+// Host-to-device copy of `bytes` from src to dst, queued on s through the
+// context's page-locked staging (src may be reused as soon as this returns;
+// the copy does not wait for the stream); a plain copy when the staging of
+// this run is used up (the next run's staging is then larger).
+hipError_t h2d(fim_ctx *ctx, void *dst, const void *src, size_t bytes, hipStream_t s);
+
+// Marks one run on a context: the outermost run starts with an idle stream
+// and an emptied (and if need be grown) staging area.
+class StageRun {
+   public:
+    explicit StageRun(fim_ctx *ctx);
+    ~StageRun();
+    StageRun(const StageRun &) = delete;
+    StageRun &operator=(const StageRun &) = delete;
+
+   private:
+    fim_ctx *ctx_;
 };
 
 // Thread-local error text and status helpers.

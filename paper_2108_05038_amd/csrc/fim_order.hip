@@ -130,7 +130,7 @@ fim_status gpu_order(fim_ctx *ctx, hipStream_t s, const uint32_t *d_rec, uint64_
     OENSURE(idx, n * 4);
     OENSURE(idx2, n * 4);
     OENSURE(d_bits, n_inst * 4);
-    OCHK(hipMemcpyAsync(d_bits.as<void>(), bits_of.data(), n_inst * 4, hipMemcpyHostToDevice, s));
+    OCHK(h2d(ctx, d_bits.as<void>(), bits_of.data(), n_inst * 4, s));
     hipLaunchKernelGGL(k_split, dim3(grid_for(n)), dim3(kOrdBlock), 0, s, d_rec, n,
                        lo.as<unsigned long long>(), hi.as<unsigned long long>(), inst.as<uint32_t>(),
                        idx.as<uint32_t>());

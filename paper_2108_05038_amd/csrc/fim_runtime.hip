@@ -237,11 +237,55 @@ fim_ctx::~fim_ctx() {
     delete aux;
     release_cached();
     if (pinned) (void)hipHostFree(pinned);
+    if (up) {
+        if (stream) (void)hipStreamSynchronize(stream);
+        (void)hipHostFree(up);
+    }
     if (own_stream && stream) {
         (void)hipStreamSynchronize(stream);
         (void)hipStreamDestroy(stream);
     }
 }
+
+namespace fim {
+
+hipError_t h2d(fim_ctx *ctx, void *dst, const void *src, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    const size_t b = (bytes + 255) & ~size_t(255);
+    ctx->up_need += b;
+    if (ctx->up && ctx->up_used + b <= ctx->up_cap) {
+        char *p = ctx->up + ctx->up_used;
+        ctx->up_used += b;
+        memcpy(p, src, bytes);
+        return hipMemcpyAsync(dst, p, bytes, hipMemcpyHostToDevice, s);
+    }
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+}
+
+StageRun::StageRun(fim_ctx *ctx) : ctx_(ctx) {
+    if (ctx_->up_depth++ > 0) return;
+    // copies of an earlier run that ended early may still read the staging
+    (void)hipStreamSynchronize(ctx_->stream);
+    if (ctx_->up_need > ctx_->up_cap) {
+        if (ctx_->up) (void)hipHostFree(ctx_->up);
+        ctx_->up = nullptr;
+        ctx_->up_cap = 0;
+        const size_t want = std::max<size_t>(1u << 20, (ctx_->up_need + ctx_->up_need / 4 + 0xFFFFF) & ~size_t(0xFFFFF));
+        void *p = nullptr;
+        if (hipHostMalloc(&p, want, hipHostMallocDefault) == hipSuccess) {
+            ctx_->up = static_cast<char *>(p);
+            ctx_->up_cap = want;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+    ctx_->up_used = 0;
+    ctx_->up_need = 0;
+}
+
+StageRun::~StageRun() { ctx_->up_depth--; }
+
+}  // namespace fim
 
 extern "C" void fim_ctx_destroy(fim_ctx *ctx) { delete ctx; }
 
@@ -454,11 +498,30 @@ uint32_t max_supp_of(const Inst &I) {
 static void rank_items(Inst &I, bool by_id) {
     const uint32_t ni = I.db->n_item_ids;
     I.item_of_rank.clear();
-    for (uint32_t it = 0; it < ni; it++)
-        if (I.counts[it] >= I.minsup) I.item_of_rank.push_back(it);
-    if (!by_id)
-        std::stable_sort(I.item_of_rank.begin(), I.item_of_rank.end(),
-                         [&](uint32_t a, uint32_t b) { return I.counts[a] < I.counts[b]; });
+    if (by_id) {
+        for (uint32_t it = 0; it < ni; it++)
+            if (I.counts[it] >= I.minsup) I.item_of_rank.push_back(it);
+    } else {
+        // frequent ids (ascending) sorted by support with a stable LSD radix
+        // sort, 11 bits a pass: ties keep the id order
+        std::vector<uint32_t> a, b;
+        a.reserve(ni);
+        uint32_t top = 0;
+        for (uint32_t it = 0; it < ni; it++)
+            if (I.counts[it] >= I.minsup) {
+                a.push_back(it);
+                top = std::max(top, I.counts[it]);
+            }
+        b.resize(a.size());
+        for (uint32_t sh = 0; sh < 32 && (top >> sh); sh += 11) {
+            uint32_t h[2049] = {0};
+            for (uint32_t it : a) h[((I.counts[it] >> sh) & 2047u) + 1]++;
+            for (uint32_t d = 0; d < 2048; d++) h[d + 1] += h[d];
+            for (uint32_t it : a) b[h[(I.counts[it] >> sh) & 2047u]++] = it;
+            a.swap(b);
+        }
+        I.item_of_rank.swap(a);
+    }
     I.n_freq = (uint32_t)I.item_of_rank.size();
     I.rank_of_item.assign(ni, kNone);
     I.supp_of_rank.resize(I.n_freq);
@@ -483,24 +546,36 @@ static void build_level2(Inst &I, bool by_id) {
         I.l2_atom[q] = I.pairs[3 * p + 1];
         I.l2_supp[q] = I.pairs[3 * p + 2];
     }
-    std::vector<uint64_t> key;
+    // every bucket sorted by its key in one array (no allocation per bucket;
+    // insertion sort for the many short buckets)
+    struct E {
+        uint64_t key;
+        uint32_t atom, supp;
+    };
+    std::vector<E> e(I.n_pairs);
+    for (uint64_t q = 0; q < I.n_pairs; q++)
+        e[q] = E{by_id ? I.l2_atom[q] : ((uint64_t)I.l2_supp[q] << 32) | I.item_of_rank[I.l2_atom[q]],
+                 I.l2_atom[q], I.l2_supp[q]};
     for (uint32_t i = 0; i < n; i++) {
         const uint32_t a = I.l2_off[i], b = I.l2_off[i + 1];
         if (b - a < 2) continue;
-        key.resize(b - a);
-        for (uint32_t q = a; q < b; q++)
-            key[q - a] = by_id ? I.l2_atom[q]
-                               : ((uint64_t)I.l2_supp[q] << 32) | I.item_of_rank[I.l2_atom[q]];
-        std::vector<uint32_t> idx(b - a);
-        std::iota(idx.begin(), idx.end(), 0u);
-        std::sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) { return key[x] < key[y]; });
-        std::vector<uint32_t> at(b - a), sp(b - a);
-        for (uint32_t q = 0; q < b - a; q++) {
-            at[q] = I.l2_atom[a + idx[q]];
-            sp[q] = I.l2_supp[a + idx[q]];
+        if (b - a <= 16) {
+            for (uint32_t q = a + 1; q < b; q++) {
+                const E v = e[q];
+                uint32_t j = q;
+                while (j > a && e[j - 1].key > v.key) {
+                    e[j] = e[j - 1];
+                    j--;
+                }
+                e[j] = v;
+            }
+        } else {
+            std::sort(e.begin() + a, e.begin() + b, [](const E &x, const E &y) { return x.key < y.key; });
         }
-        std::copy(at.begin(), at.end(), I.l2_atom.begin() + a);
-        std::copy(sp.begin(), sp.end(), I.l2_supp.begin() + a);
+    }
+    for (uint64_t q = 0; q < I.n_pairs; q++) {
+        I.l2_atom[q] = e[q].atom;
+        I.l2_supp[q] = e[q].supp;
     }
 }
 
@@ -542,10 +617,8 @@ static fim_status run_persistent(fim_ctx *ctx, hipStream_t s, Tracer &tr,
     } evg{ev0, ev1};
     ENSURE(d_desc, ctx, desc.size() * sizeof(InstDesc));
     ENSURE(d_tasks, ctx, tasks.size() * sizeof(Task));
-    HIPCHK(hipMemcpyAsync(d_desc.as<void>(), desc.data(), desc.size() * sizeof(InstDesc),
-                          hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(d_tasks.as<void>(), tasks.data(), tasks.size() * sizeof(Task),
-                          hipMemcpyHostToDevice, s));
+    HIPCHK(h2d(ctx, d_desc.as<void>(), desc.data(), desc.size() * sizeof(InstDesc), s));
+    HIPCHK(h2d(ctx, d_tasks.as<void>(), tasks.data(), tasks.size() * sizeof(Task), s));
     L.ictr.assign(n_inst, InstCounters{});
     // per-worker stack: room for the largest first frame and its subtree,
     // within a quarter of device memory in total
@@ -583,12 +656,13 @@ static fim_status run_persistent(fim_ctx *ctx, hipStream_t s, Tracer &tr,
         unsigned long long start = 0;
         if (L.prefix && !L.prefix->empty()) {
             start = L.prefix->size();
-            HIPCHK(hipMemcpyAsync(d_out.as<void>(), L.prefix->data(), start * 4, hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemcpyAsync(reinterpret_cast<char *>(d_ctr.as<void>()) + offsetof(DfsCounters, out_used),
-                                  &start, 8, hipMemcpyHostToDevice, s));
+            HIPCHK(h2d(ctx, d_out.as<void>(), L.prefix->data(), start * 4, s));
+            HIPCHK(h2d(ctx, reinterpret_cast<char *>(d_ctr.as<void>()) + offsetof(DfsCounters, out_used),
+                       &start, 8, s));
         }
         HIPCHK(launch_fill_u32(d_ictr.as<uint32_t>(), sizeof(InstCounters) / 4 * n_inst, 0u, s));
         if (L.cap_output) HIPCHK(launch_fill_u32(d_out.as<uint32_t>(), L.out_cap, 0u, s));
+        tr.mark("  (dfs inputs queued)");
         HIPCHK(hipEventRecord(ev0, s));
         auto launch = [&]() {
             return launch_dfs(d_desc.as<InstDesc>(), d_tasks.as<Task>(), tasks.size(),
@@ -621,7 +695,9 @@ static fim_status run_persistent(fim_ctx *ctx, hipStream_t s, Tracer &tr,
         HIPCHK(hipMemcpyAsync(&L.ctr, d_ctr.as<void>(), sizeof(L.ctr), hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(L.ictr.data(), d_ictr.as<void>(), sizeof(InstCounters) * n_inst,
                               hipMemcpyDeviceToHost, s));
+        tr.mark("  (dfs queued)");
         HIPCHK(hipStreamSynchronize(s));
+        tr.mark("  (dfs done)");
         HIPCHK(hipEventElapsedTime(&L.ms, ev0, ev1));
         const DfsCounters &ctr = L.ctr;
         if (clk_khz > 0) {
@@ -813,6 +889,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
     const uint32_t n_inst = (uint32_t)reqs.size();
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
+    StageRun stage_run(ctx);
     std::vector<Inst> insts(n_inst);
 
     // ---------------- a2: item supports (all instances, one sync; the block
@@ -859,9 +936,11 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         }
     } evv{rev};
     for (auto &e : rev) HIPCHK(hipEventCreate(&e));
+    tr.mark("  (events)");
     for (uint32_t q = 0; q < n_inst; q++) {
         Inst &I = insts[q];
         rank_items(I, by_id);
+        tr.mark("  (ranks)");
         I.W = (uint32_t)((I.db->n_tx + 31) / 32);
         I.Wp = std::max<uint32_t>(kRowAlign, (I.W + kRowAlign - 1) / kRowAlign * kRowAlign);
         I.st.item_supports = I.db->n_item_ids;
@@ -871,10 +950,9 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         ENSURE(I.d_rank_of_item, ctx, (size_t)ni * 4);
         ENSURE(I.d_item_of_rank, ctx, (size_t)I.n_freq * 4);
         ENSURE(I.d_rows, ctx, (size_t)I.n_freq * I.Wp * 4);
-        HIPCHK(hipMemcpyAsync(I.d_rank_of_item.as<void>(), I.rank_of_item.data(), (size_t)ni * 4,
-                              hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(I.d_item_of_rank.as<void>(), I.item_of_rank.data(),
-                              (size_t)I.n_freq * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(h2d(ctx, I.d_rank_of_item.as<void>(), I.rank_of_item.data(), (size_t)ni * 4, s));
+        HIPCHK(h2d(ctx, I.d_item_of_rank.as<void>(), I.item_of_rank.data(), (size_t)I.n_freq * 4, s));
+        tr.mark("  (rank uploads)");
         const uint32_t n = I.n_freq;
         // positions in the ranked transactions are 32-bit, suffix lengths 16-bit
         const bool fits = I.db->nnz + I.db->n_tx + 8 < (1ull << 32) && I.db->max_tx_len < (1u << 16);
@@ -914,6 +992,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                                        I.db->n_tx, I.d_rank_of_item.as<uint32_t>(),
                                        I.d_rows.as<uint32_t>(), I.Wp, s));
         }
+        tr.mark("  (bitmap queued)");
         // Ascending transaction lists of the ranks (the set bits of their
         // rows), used by the projected root kernel and by pieces of work
         // whose rows are projected on a one-item prefix's cover
@@ -928,8 +1007,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             for (uint32_t r = 0; r < n; r++) I.tl_off[r + 1] = I.tl_off[r] + I.supp_of_rank[r];
             ENSURE(I.d_tl, ctx, std::max<uint64_t>(I.tl_off[n], 1) * 4);
             ENSURE(I.d_tl_off, ctx, (n + 1) * 8);
-            HIPCHK(hipMemcpyAsync(I.d_tl_off.as<void>(), I.tl_off.data(), (n + 1) * 8,
-                                  hipMemcpyHostToDevice, s));
+            HIPCHK(h2d(ctx, I.d_tl_off.as<void>(), I.tl_off.data(), (n + 1) * 8, s));
             const bool ranked = I.root_kind == 2 && pairs_needed;
             if (ranked) ENSURE(I.d_rowpre, ctx, (uint64_t)n * rowpre_words(I.Wp) * 4);
             HIPCHK(launch_tidlist(I.d_rows.as<uint32_t>(), n, I.Wp, I.d_tl_off.as<uint64_t>(),
@@ -945,6 +1023,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                                       I.d_tlp.as<uint32_t>(), I.d_suf.as<uint16_t>(), s));
             }
         }
+        tr.mark("  (lists queued)");
         if (!pairs_needed) continue;
         const uint64_t all = (uint64_t)n * (n - 1) / 2;
         const uint64_t cap = std::min<uint64_t>(all, std::max<uint64_t>(1u << 16, 64ull * n));
@@ -973,8 +1052,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             ENSURE(I.d_nz_m, ctx, std::max<uint64_t>(I.nz_off[n], 1) * 4);
             ENSURE(I.d_nz_cnt, ctx, (size_t)n * 4);
             ENSURE(I.d_bt, ctx, (size_t)I.W * np * 4);
-            HIPCHK(hipMemcpyAsync(I.d_nz_off.as<void>(), I.nz_off.data(), (n + 1) * 8,
-                                  hipMemcpyHostToDevice, s));
+            HIPCHK(h2d(ctx, I.d_nz_off.as<void>(), I.nz_off.data(), (n + 1) * 8, s));
             HIPCHK(launch_row_nonzero(I.d_rows.as<uint32_t>(), n, I.Wp, I.d_nz_off.as<uint64_t>(),
                                       I.d_nz_w.as<uint32_t>(), I.d_nz_m.as<uint32_t>(),
                                       I.d_nz_cnt.as<uint32_t>(), s));
@@ -1133,12 +1211,9 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                 ENSURE(I.d_l2_off, ctx, I.l2_off.size() * 4);
                 ENSURE(I.d_l2_atom, ctx, I.l2_atom.size() * 4);
                 ENSURE(I.d_l2_supp, ctx, I.l2_supp.size() * 4);
-                HIPCHK(hipMemcpyAsync(I.d_l2_off.as<void>(), I.l2_off.data(), I.l2_off.size() * 4,
-                                      hipMemcpyHostToDevice, s));
-                HIPCHK(hipMemcpyAsync(I.d_l2_atom.as<void>(), I.l2_atom.data(),
-                                      I.l2_atom.size() * 4, hipMemcpyHostToDevice, s));
-                HIPCHK(hipMemcpyAsync(I.d_l2_supp.as<void>(), I.l2_supp.data(),
-                                      I.l2_supp.size() * 4, hipMemcpyHostToDevice, s));
+                HIPCHK(h2d(ctx, I.d_l2_off.as<void>(), I.l2_off.data(), I.l2_off.size() * 4, s));
+                HIPCHK(h2d(ctx, I.d_l2_atom.as<void>(), I.l2_atom.data(), I.l2_atom.size() * 4, s));
+                HIPCHK(h2d(ctx, I.d_l2_supp.as<void>(), I.l2_supp.data(), I.l2_supp.size() * 4, s));
             }
             std::vector<std::vector<double>> row_w;
             uint64_t sample_words = 0;
@@ -1201,12 +1276,9 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                 ENSURE(I.d_l2_off, ctx, I.l2_off.size() * 4);
                 ENSURE(I.d_l2_atom, ctx, I.l2_atom.size() * 4);
                 ENSURE(I.d_l2_supp, ctx, I.l2_supp.size() * 4);
-                HIPCHK(hipMemcpyAsync(I.d_l2_off.as<void>(), I.l2_off.data(), I.l2_off.size() * 4,
-                                      hipMemcpyHostToDevice, s));
-                HIPCHK(hipMemcpyAsync(I.d_l2_atom.as<void>(), I.l2_atom.data(),
-                                      I.l2_atom.size() * 4, hipMemcpyHostToDevice, s));
-                HIPCHK(hipMemcpyAsync(I.d_l2_supp.as<void>(), I.l2_supp.data(),
-                                      I.l2_supp.size() * 4, hipMemcpyHostToDevice, s));
+                HIPCHK(h2d(ctx, I.d_l2_off.as<void>(), I.l2_off.data(), I.l2_off.size() * 4, s));
+                HIPCHK(h2d(ctx, I.d_l2_atom.as<void>(), I.l2_atom.data(), I.l2_atom.size() * 4, s));
+                HIPCHK(h2d(ctx, I.d_l2_supp.as<void>(), I.l2_supp.data(), I.l2_supp.size() * 4, s));
             }
             InstDesc &D = desc[q];
             D.rows = I.d_rows.as<uint32_t>();
