@@ -187,6 +187,21 @@ hipError_t launch_root_sparse(const uint32_t *bt, uint32_t np, const uint64_t *n
                               uint32_t n, uint32_t minsup, uint32_t *pairs, uint64_t cap,
                               unsigned long long *n_pairs, hipStream_t stream);
 
+// The key records (see the persistent kernel's key mode) of every frequent
+// item and frequent pair of an instance, written on the device: records
+// [out_rec, out_rec + n_freq + n_pairs) of the output arena, the items
+// first (support counts[id]), then the pairs of the root kernel's triples
+// (rank a, rank b, support).
+struct PrefixSrc {
+    const uint32_t *item_of_rank;
+    const uint32_t *counts;
+    const uint32_t *pairs;
+    uint32_t n_freq, bits, inst, pad_;
+    uint64_t n_pairs, out_rec;
+};
+hipError_t launch_prefix_keys(const PrefixSrc *src, uint32_t n_src, uint64_t max_rec, uint32_t *out,
+                              hipStream_t stream);
+
 // Waves of that persistent kernel variant that fit on the device at once.
 uint32_t dfs_resident_workers(int n_cu, uint32_t variant);
 

@@ -1867,6 +1867,39 @@ __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Tas
 
 }  // namespace
 
+// ------------------------------------------------------------------ records of the 1- and 2-itemsets
+// One thread per record; blockIdx.y is the instance.  Codes (id + 1) of
+// `bits` bits from the top of the 128-bit key, items ascending.
+__global__ void k_prefix_keys(const PrefixSrc *__restrict__ src, uint32_t *out) {
+    const PrefixSrc S = src[blockIdx.y];
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= S.n_freq + S.n_pairs) return;
+    uint32_t id0, id1 = 0, n, supp;
+    if (j < S.n_freq) {
+        id0 = S.item_of_rank[j];
+        n = 1;
+        supp = S.counts[id0];
+    } else {
+        const uint64_t p = j - S.n_freq;
+        const uint32_t a = S.item_of_rank[S.pairs[3 * p]], b = S.item_of_rank[S.pairs[3 * p + 1]];
+        id0 = min(a, b);
+        id1 = max(a, b);
+        n = 2;
+        supp = S.pairs[3 * p + 2];
+    }
+    unsigned long long hi = 0, lo = 0;
+    uint32_t sh = 128;
+    for (uint32_t x = 0; x < n; x++) {
+        const unsigned long long code = (unsigned long long)(x == 0 ? id0 : id1) + 1;
+        sh -= S.bits;
+        hi |= sh >= 64 ? code << (sh - 64) : (sh + S.bits > 64 ? code >> (64 - sh) : 0ull);
+        lo |= sh >= 64 ? 0ull : code << sh;
+    }
+    uint4 *o = reinterpret_cast<uint4 *>(out + 8ull * (S.out_rec + j));
+    o[0] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+    o[1] = make_uint4(supp, S.inst, 0u, 0u);
+}
+
 // ------------------------------------------------------------------ launch wrappers
 
 // blocks of the per-block histograms and the chunk each one counts
@@ -1967,6 +2000,15 @@ hipError_t launch_bitmap_tiles(const uint64_t *offsets, const uint32_t *items, u
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bitmap_tile, dim3((Wp + K - 1) / K), dim3(kBlock), lds, stream, offsets,
                        items, n_tx, rank_of_item, n, rows, Wp, K);
+    return hipGetLastError();
+}
+
+hipError_t launch_prefix_keys(const PrefixSrc *src, uint32_t n_src, uint64_t max_rec, uint32_t *out,
+                              hipStream_t stream) {
+    if (n_src == 0 || max_rec == 0) return hipSuccess;
+    const uint64_t bx = (max_rec + kBlock - 1) / kBlock;
+    if (bx >= (1ull << 31) || n_src > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_prefix_keys, dim3((uint32_t)bx, n_src), dim3(kBlock), 0, stream, src, out);
     return hipGetLastError();
 }
 

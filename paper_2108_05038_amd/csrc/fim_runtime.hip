@@ -590,7 +590,9 @@ struct DfsLaunch {
     uint64_t out_cap = 1ull << 24;
     // words placed at the start of the arena before the launch (key mode:
     // the records of the itemsets found before the persistent kernel)
-    const std::vector<uint32_t> *prefix = nullptr;
+    // key records of the 1- and 2-itemsets, written before the launch
+    const std::vector<PrefixSrc> *prefix = nullptr;
+    uint64_t prefix_rec = 0, prefix_max = 0;  // records in all, most of one instance
     DfsCounters ctr{};
     std::vector<InstCounters> ictr;
     float ms = 0.f;
@@ -604,7 +606,7 @@ static fim_status run_persistent(fim_ctx *ctx, hipStream_t s, Tracer &tr,
                                  DevBuf &d_out, DfsLaunch &L) {
     const uint32_t n_inst = (uint32_t)desc.size();
     DevBuf d_desc(ctx), d_tasks(ctx), d_stack(ctx), d_ctr(ctx), d_ictr(ctx);
-    DevBuf d_slots(ctx), d_heap(ctx), d_trace(ctx);
+    DevBuf d_slots(ctx), d_heap(ctx), d_trace(ctx), d_prefix(ctx);
     hipEvent_t ev0, ev1;
     HIPCHK(hipEventCreate(&ev0));
     HIPCHK(hipEventCreate(&ev1));
@@ -641,7 +643,7 @@ static fim_status run_persistent(fim_ctx *ctx, hipStream_t s, Tracer &tr,
         if (((uint64_t)workers * S > budget_words && S > budget_words / 4) || S > kMaxStack)
             return set_error(FIM_E_OOM_DEVICE, "a first-level class does not fit on the device");
         ENSURE(d_stack, ctx, (size_t)workers * S * 4);
-        if (L.prefix && L.prefix->size() + 8 > L.out_cap) L.out_cap = L.prefix->size() * 2 + 4096;
+        if (L.prefix && 8 * L.prefix_rec + 8 > L.out_cap) L.out_cap = 16 * L.prefix_rec + 4096;
         ENSURE(d_out, ctx, (size_t)L.out_cap * 4);
         ENSURE(d_ctr, ctx, sizeof(DfsCounters));
         ENSURE(d_ictr, ctx, sizeof(InstCounters) * n_inst);
@@ -654,9 +656,12 @@ static fim_status run_persistent(fim_ctx *ctx, hipStream_t s, Tracer &tr,
         HIPCHK(launch_fill_u32(d_slots.as<uint32_t>(), n_slots * 2, 0u, s));
         HIPCHK(launch_fill_u32(d_ctr.as<uint32_t>(), sizeof(DfsCounters) / 4, 0u, s));
         unsigned long long start = 0;
-        if (L.prefix && !L.prefix->empty()) {
-            start = L.prefix->size();
-            HIPCHK(h2d(ctx, d_out.as<void>(), L.prefix->data(), start * 4, s));
+        if (L.prefix && L.prefix_rec) {
+            start = 8 * L.prefix_rec;
+            ENSURE(d_prefix, ctx, L.prefix->size() * sizeof(PrefixSrc));
+            HIPCHK(h2d(ctx, d_prefix.as<void>(), L.prefix->data(), L.prefix->size() * sizeof(PrefixSrc), s));
+            HIPCHK(launch_prefix_keys(d_prefix.as<PrefixSrc>(), (uint32_t)L.prefix->size(), L.prefix_max,
+                                      d_out.as<uint32_t>(), s));
             HIPCHK(h2d(ctx, reinterpret_cast<char *>(d_ctr.as<void>()) + offsetof(DfsCounters, out_used),
                        &start, 8, s));
         }
@@ -1266,7 +1271,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
     for (uint32_t q = 0; q < n_inst; q++)
         while ((uint64_t)insts[q].db->n_item_ids >> bits_of[q]) bits_of[q]++;
     bool keys_done = false;
-    std::vector<uint32_t> key_prefix;  // records of the 1- and 2-itemsets
+    std::vector<PrefixSrc> key_prefix;  // sources of the 1- and 2-itemsets' records
     if (deep && !tasks.empty()) {
         std::vector<InstDesc> desc(n_inst);
         uint64_t frame0 = 0;
@@ -1330,31 +1335,22 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         // an overflow costs a second run of the whole launch
         L.out_cap = L.cap_output ? (1ull << 24) : std::max<uint64_t>(1ull << 26, est_out_words);
         if (key_mode) {
-            auto put = [&](uint32_t q, const uint32_t *ids, uint32_t n, uint32_t supp) {
-                unsigned __int128 k = 0;
-                uint32_t sh = 128;
-                for (uint32_t x = 0; x < n; x++) {
-                    sh -= bits_of[q];
-                    k |= (unsigned __int128)(ids[x] + 1) << sh;
-                }
-                const uint64_t lo = (uint64_t)k, hi = (uint64_t)(k >> 64);
-                const uint32_t w[8] = {(uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi,
-                                       (uint32_t)(hi >> 32), supp, q, 0u, 0u};
-                key_prefix.insert(key_prefix.end(), w, w + 8);
-            };
+            // the 1- and 2-itemsets' records come first in the arena,
+            // written on the device from the ranks and the root pairs
+            uint64_t at = 0;
             for (uint32_t q = 0; q < n_inst; q++) {
                 const Inst &I = insts[q];
-                for (uint32_t r = 0; r < I.n_freq; r++) put(q, &I.item_of_rank[r], 1, I.supp_of_rank[r]);
-                if (opts.max_len != 1)
-                    for (uint32_t i = 0; i < I.n_freq; i++)
-                        for (uint32_t k = I.l2_off[i]; k < I.l2_off[i + 1]; k++) {
-                            uint32_t ids[2] = {I.item_of_rank[i], I.item_of_rank[I.l2_atom[k]]};
-                            if (ids[0] > ids[1]) std::swap(ids[0], ids[1]);
-                            put(q, ids, 2, I.l2_supp[k]);
-                        }
+                const uint64_t np = opts.max_len != 1 ? I.n_pairs : 0;
+                if (I.n_freq + np == 0) continue;
+                key_prefix.push_back(PrefixSrc{I.d_item_of_rank.as<uint32_t>(), I.d_counts.as<uint32_t>(),
+                                               np ? I.d_pairs.as<uint32_t>() : nullptr, I.n_freq,
+                                               bits_of[q], q, 0u, np, at});
+                at += I.n_freq + np;
+                L.prefix_max = std::max<uint64_t>(L.prefix_max, I.n_freq + np);
             }
             L.prefix = &key_prefix;
-            L.out_cap = std::max<uint64_t>(L.out_cap, 2 * key_prefix.size());
+            L.prefix_rec = at;
+            L.out_cap = std::max<uint64_t>(L.out_cap, 16 * at);
         }
         fim_status ls = run_persistent(ctx, s, tr, desc, tasks, d_out, L);
         if (ls != FIM_OK) return ls;
