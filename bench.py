@@ -373,14 +373,16 @@ def main(argv=None):
                         and r.stats["candidates"] == gold["candidates_ascending_support"])
             log("warmup result matches the oracle's golden digest:", verified)
     torch.cuda.synchronize()
-    stats = []
+    stats, ends = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         r = F.mine(ctx, d, db.minsup, flags=args.flags)
         stats.append(r.stats)
+        ends.append(time.perf_counter())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     dt = (t1 - t0) / args.steps
+    step_ms = np.diff([t0] + ends) * 1e3  # per call (each call returns a finished result)
     st = stats[-1]
     cands = st["candidates"]
     value = cands / dt
@@ -439,6 +441,8 @@ def main(argv=None):
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": dt * 1e3,
+        "ms_per_step_min_median_max": [float(step_ms.min()), float(np.median(step_ms)),
+                                       float(step_ms.max())],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -96,6 +96,11 @@ class DevBuf {
 // this run is used up (the next run's staging is then larger).
 hipError_t h2d(fim_ctx *ctx, void *dst, const void *src, size_t bytes, hipStream_t s);
 
+// Wait for the work queued on s: spins on the stream's status (a sleeping
+// wait can wake up milliseconds late on a busy host) for up to 20 ms, then
+// blocks.
+hipError_t stream_wait(hipStream_t s);
+
 // Marks one run on a context: the outermost run starts with an idle stream
 // and an emptied (and if need be grown) staging area.
 class StageRun {

@@ -186,7 +186,7 @@ fim_status gpu_order(fim_ctx *ctx, hipStream_t s, const uint32_t *d_rec, uint64_
                                           ioff.as<unsigned long long>(), ni + 1, s));
     unsigned long long total = 0;
     OCHK(hipMemcpyAsync(&total, ioff.as<unsigned long long>() + n, 8, hipMemcpyDeviceToHost, s));
-    OCHK(hipStreamSynchronize(s));
+    OCHK(stream_wait(s));
     OENSURE(d_items, std::max<uint64_t>(total, 1) * 4);
     OENSURE(d_supp, n * 4);
     OENSURE(d_first, n_inst * 8);
@@ -205,7 +205,7 @@ fim_status gpu_order(fim_ctx *ctx, hipStream_t s, const uint32_t *d_rec, uint64_
     OCHK(hipMemcpyAsync(supp.data(), d_supp.as<void>(), n * 4, hipMemcpyDeviceToHost, s));
     std::vector<unsigned long long> f(n_inst);
     OCHK(hipMemcpyAsync(f.data(), d_first.as<void>(), n_inst * 8, hipMemcpyDeviceToHost, s));
-    OCHK(hipStreamSynchronize(s));
+    OCHK(stream_wait(s));
     for (uint32_t q = 0; q < n_inst; q++) first[q] = f[q];
     return FIM_OK;
 }

@@ -262,6 +262,16 @@ hipError_t h2d(fim_ctx *ctx, void *dst, const void *src, size_t bytes, hipStream
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
 }
 
+hipError_t stream_wait(hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    for (uint32_t k = 0;; k++) {
+        const hipError_t e = hipStreamQuery(s);
+        if (e != hipErrorNotReady) return e;
+        if ((k & 63u) == 63u && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20))
+            return hipStreamSynchronize(s);
+    }
+}
+
 StageRun::StageRun(fim_ctx *ctx) : ctx_(ctx) {
     if (ctx_->up_depth++ > 0) return;
     // copies of an earlier run that ended early may still read the staging
@@ -701,7 +711,7 @@ static fim_status run_persistent(fim_ctx *ctx, hipStream_t s, Tracer &tr,
         HIPCHK(hipMemcpyAsync(L.ictr.data(), d_ictr.as<void>(), sizeof(InstCounters) * n_inst,
                               hipMemcpyDeviceToHost, s));
         tr.mark("  (dfs queued)");
-        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(stream_wait(s));
         tr.mark("  (dfs done)");
         HIPCHK(hipEventElapsedTime(&L.ms, ev0, ev1));
         const DfsCounters &ctr = L.ctr;
@@ -868,7 +878,7 @@ static fim_status count_estimate(fim_ctx *ctx, hipStream_t s, Tracer &tr, std::v
     std::vector<unsigned long long> cnt(count_at[n_inst]);
     if (!cnt.empty())
         HIPCHK(hipMemcpyAsync(cnt.data(), d_count.as<void>(), cnt.size() * 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(stream_wait(s));
     for (uint32_t q = 0; q < n_inst; q++) {
         if (!used[q] || L.ictr[q].stop) continue;  // exploded sample: no estimate
         const Inst &I = insts[q];
@@ -916,7 +926,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         HIPCHK(hipMemcpyAsync(I.counts.data(), I.d_counts.as<void>(), (size_t)ni * 4,
                               hipMemcpyDeviceToHost, s));
     }
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(stream_wait(s));
     tr.mark("item supports");
 
     // ---------------- a3 + root class: bitmaps and frequent pairs
@@ -1084,7 +1094,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
     }
     const bool deep = opts.max_len == 0 || opts.max_len >= 3;
     tr.mark("  (root work queued)");
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(stream_wait(s));
     tr.mark("  (root work done)");
     for (uint32_t q = 0; q < n_inst; q++) {
         const Inst &I = insts[q];
@@ -1149,7 +1159,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         }
         I.st.pair_words = I.st.root_pair_words;
     }
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(stream_wait(s));
     tr.mark("  (pairs copied)");
     parallel_for(n_inst, host_threads((uint64_t)n_inst << 14), [&](uint64_t q) {
         Inst &I = insts[q];
@@ -1377,7 +1387,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             out_host.p = st;
             HIPCHK(hipMemcpyAsync(st, d_out.as<void>(), out_host.n * 4, hipMemcpyDeviceToHost, s));
         }
-        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(stream_wait(s));
     }
 
     tr.mark("persistent dfs + copy");
