@@ -515,15 +515,17 @@ __global__ __launch_bounds__(kBlock) void k_tidlist(const uint32_t *__restrict__
     uint32_t *pre = rowpre + (uint64_t)r * Wb;
     const uint64_t base = tl_off[r], end = tl_off[r + 1];
     uint32_t pos = 0;  // set bits before the current window
-    for (uint32_t w0 = 0; w0 < Wp; w0 += 4 * kWave) {
-        uint32_t x[4];
+    // 4 x 64 words per round: the loads of a window are in flight together
+    constexpr int kTlUnroll = 4;
+    for (uint32_t w0 = 0; w0 < Wp; w0 += kTlUnroll * kWave) {
+        uint32_t x[kTlUnroll];
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
+        for (int j = 0; j < kTlUnroll; j++) {
             const uint32_t w = w0 + j * kWave + lane;
             x[j] = w < Wp ? row[w] : 0u;
         }
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
+        for (int j = 0; j < kTlUnroll; j++) {
             const uint32_t w = w0 + j * kWave + lane;
             const uint32_t pc = __popc(x[j]);
             uint32_t incl = pc;
@@ -587,7 +589,10 @@ __global__ __launch_bounds__(kBlock) void k_rank_tx(
     const uint32_t lane = lane_id();
     const uint64_t waves = (uint64_t)gridDim.x * kWavesPerBlock;
     const uint64_t n_groups = (n_tx + kRankGroup - 1) / kRankGroup;
-    for (uint64_t g = (uint64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; g < n_groups;
+    // each XCD takes a contiguous range of transactions, so that the row
+    // pieces and prefix counts nearby transactions share stay in its L2
+    const uint32_t blk = xcd_local_block(blockIdx.x, gridDim.x);
+    for (uint64_t g = (uint64_t)blk * kWavesPerBlock + threadIdx.x / kWave; g < n_groups;
          g += waves) {
         const uint64_t tg0 = g * kRankGroup;
         const uint32_t ng = (uint32_t)min<uint64_t>(kRankGroup, n_tx - tg0);
@@ -736,10 +741,11 @@ __global__ __launch_bounds__(kBlock) void k_root_project(
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (uint32_t k0 = 0; k0 < total; k0 += 4 * kWave) {
-            uint32_t b[4], row[4];
+        constexpr uint32_t kReads = 4;  // rank reads per lane in flight
+        for (uint32_t k0 = 0; k0 < total; k0 += kReads * kWave) {
+            uint32_t b[kReads], row[kReads];
 #pragma unroll
-            for (uint32_t u = 0; u < 4; u++) {
+            for (uint32_t u = 0; u < kReads; u++) {
                 const uint32_t k = k0 + u * kWave + lane;
                 b[u] = kRankEnd;
                 row[u] = 0;
@@ -755,7 +761,7 @@ __global__ __launch_bounds__(kBlock) void k_root_project(
                 }
             }
 #pragma unroll
-            for (uint32_t u = 0; u < 4; u++) {
+            for (uint32_t u = 0; u < kReads; u++) {
                 if (b[u] < j0 || b[u] >= j1) continue;
                 const uint32_t e = row[u] * J + (b[u] - j0);
                 if (Packed) atomicAdd(&cnt[e >> 1], 1u << ((e & 1) * 16));

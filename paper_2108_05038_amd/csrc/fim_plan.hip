@@ -21,6 +21,8 @@
 
 #include "fim_plan.h"
 
+#include <cstring>
+
 namespace fim {
 
 namespace {
@@ -277,11 +279,33 @@ void partition_lpt_order(const std::vector<PlanClass> &cls_in,
         }
         out.push_back({c.inst, c.node, r0, rows, acc, accp});
     }
-    // LPT order: decreasing estimate, then decreasing proxy, then position
-    std::stable_sort(out.begin(), out.end(), [](const PlanClass &a, const PlanClass &b) {
-        if (a.weight != b.weight) return a.weight > b.weight;
-        return a.proxy > b.proxy;
-    });
+    // LPT order: decreasing estimate, then decreasing proxy, then position.
+    // Weights and proxies are non-negative, so their bit patterns order like
+    // their values; a stable LSD radix sort (11 bits a pass) over the two
+    // 64-bit keys, proxy first, keeps equal classes in position order.
+    const size_t m = out.size();
+    std::vector<uint32_t> idx(m), tmp(m);
+    std::vector<uint64_t> kw(m), kp(m);
+    for (size_t i = 0; i < m; i++) {
+        idx[i] = (uint32_t)i;
+        uint64_t a, b;
+        memcpy(&a, &out[i].weight, 8);
+        memcpy(&b, &out[i].proxy, 8);
+        kw[i] = ~a;  // descending
+        kp[i] = ~b;
+    }
+    for (const std::vector<uint64_t> *key : {&kp, &kw}) {
+        for (uint32_t sh = 0; sh < 64; sh += 11) {
+            uint32_t h[2049] = {0};
+            for (size_t i = 0; i < m; i++) h[(((*key)[idx[i]] >> sh) & 2047u) + 1]++;
+            for (uint32_t d = 0; d < 2048; d++) h[d + 1] += h[d];
+            for (size_t i = 0; i < m; i++) tmp[h[((*key)[idx[i]] >> sh) & 2047u]++] = idx[i];
+            idx.swap(tmp);
+        }
+    }
+    std::vector<PlanClass> sorted(m);
+    for (size_t i = 0; i < m; i++) sorted[i] = out[idx[i]];
+    out.swap(sorted);
 }
 
 fim_status plan_tasks(fim_ctx *ctx, const std::vector<PlanInput> &in, const fim_options &opts,
