@@ -184,10 +184,21 @@ fim_status gpu_order(fim_ctx *ctx, hipStream_t s, const uint32_t *d_rec, uint64_
     tbytes = tmp.bytes();
     OCHK(hipcub::DeviceScan::ExclusiveSum(tmp.as<void>(), tbytes, len.as<uint32_t>(),
                                           ioff.as<unsigned long long>(), ni + 1, s));
+    // The item count is known on the device only.  A small result is
+    // decoded into room for the most items its keys can hold and copied
+    // without waiting for the count (the host arrays are cut to it after);
+    // a large one waits for the count first, so that no slack is copied.
+    uint32_t max_codes = 1;
+    for (uint32_t b : bits_of) max_codes = std::max<uint32_t>(max_codes, 128 / std::max<uint32_t>(b, 1));
+    const uint64_t bound = (uint64_t)n * max_codes;
+    const bool small = bound * 4 <= (8u << 20);
     unsigned long long total = 0;
-    OCHK(hipMemcpyAsync(&total, ioff.as<unsigned long long>() + n, 8, hipMemcpyDeviceToHost, s));
-    OCHK(stream_wait(s));
-    OENSURE(d_items, std::max<uint64_t>(total, 1) * 4);
+    if (!small) {
+        OCHK(hipMemcpyAsync(&total, ioff.as<unsigned long long>() + n, 8, hipMemcpyDeviceToHost, s));
+        OCHK(stream_wait(s));
+    }
+    const uint64_t room = small ? bound : total;
+    OENSURE(d_items, std::max<uint64_t>(room, 1) * 4);
     OENSURE(d_supp, n * 4);
     OENSURE(d_first, n_inst * 8);
     OCHK(launch_fill_u32(d_first.as<uint32_t>(), (uint64_t)n_inst * 2, 0xFFFFFFFFu, s));
@@ -197,15 +208,20 @@ fim_status gpu_order(fim_ctx *ctx, hipStream_t s, const uint32_t *d_rec, uint64_
                        d_first.as<unsigned long long>());
     OCHK(hipGetLastError());
     off.resize(n + 1);
-    items.resize(total);
+    items.resize(room);
     supp.resize(n);
     OCHK(hipMemcpyAsync(off.data(), ioff.as<void>(), (n + 1) * 8, hipMemcpyDeviceToHost, s));
-    if (total)
-        OCHK(hipMemcpyAsync(items.data(), d_items.as<void>(), total * 4, hipMemcpyDeviceToHost, s));
+    if (room)
+        OCHK(hipMemcpyAsync(items.data(), d_items.as<void>(), room * 4, hipMemcpyDeviceToHost, s));
     OCHK(hipMemcpyAsync(supp.data(), d_supp.as<void>(), n * 4, hipMemcpyDeviceToHost, s));
     std::vector<unsigned long long> f(n_inst);
     OCHK(hipMemcpyAsync(f.data(), d_first.as<void>(), n_inst * 8, hipMemcpyDeviceToHost, s));
     OCHK(stream_wait(s));
+    if (small) {
+        total = off[n];
+        if (total > room) return set_error(FIM_E_DEVICE, "ordering: more items than keys hold");
+        items.resize(total);
+    }
     for (uint32_t q = 0; q < n_inst; q++) first[q] = f[q];
     return FIM_OK;
 }
