@@ -363,7 +363,18 @@ def main(argv=None):
 
     db = synth.make(args.workload)
     ctx = F.Context(0)
+    # the upload (validation, set semantics, host-to-device copy) is outside
+    # the timed loop; timed here for the host-inclusive rate
+    t_up = time.perf_counter()
     d = F.Database(ctx, db.offsets, db.items, db.n_items)
+    torch.cuda.synchronize()
+    upload_ms = (time.perf_counter() - t_up) * 1e3
+    d.close()
+    t_up = time.perf_counter()
+    d = F.Database(ctx, db.offsets, db.items, db.n_items)
+    torch.cuda.synchronize()
+    upload_ms = min(upload_ms, (time.perf_counter() - t_up) * 1e3)
+    log("database upload: %.2f ms" % upload_ms)
     gold = load_golden("%s.json" % args.workload)
 
     verified = None
@@ -444,6 +455,7 @@ def main(argv=None):
         "ms_per_step": dt * 1e3,
         "ms_per_step_min_median_max": [float(step_ms.min()), float(np.median(step_ms)),
                                        float(step_ms.max())],
+        "upload_ms": upload_ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

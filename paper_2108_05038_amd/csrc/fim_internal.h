@@ -145,9 +145,9 @@ hipError_t launch_root_pairs(const uint32_t *rows, uint32_t n, uint32_t Wp, uint
 // Preparation of the projected root kernel.  launch_tidlist: the tid lists
 // tl (at offsets tl_off[n + 1]) from the rows, and rowpre (n x
 // rowpre_words(Wp) words: set bits of each row before every 8th word).
-// launch_rank_tx: rk (nnz + n_tx + 8 words) = every transaction's frequent
-// ranks ascending at off[t] + t, closed by 0xFFFFFFFF (also in the slots of
-// infrequent items), tlp (tl_off[n] words) = for tid-list entry p the
+// launch_rank_tx: rk (nnz + n_tx + 8 halfwords; fewer than 65535 frequent
+// items) = every transaction's frequent ranks ascending at off[t] + t,
+// closed by 0xFFFF (also in the slots of infrequent items), tlp (tl_off[n] words) = for tid-list entry p the
 // position in rk of its own rank, and suf (tl_off[n] halfwords) = the number
 // of frequent ranks after it in its transaction (transactions shorter than
 // 65536 items).
@@ -156,14 +156,14 @@ hipError_t launch_tidlist(const uint32_t *rows, uint32_t n, uint32_t Wp, const u
                           uint32_t *tl, uint32_t *rowpre, hipStream_t stream);
 hipError_t launch_rank_tx(const uint64_t *off, const uint32_t *items, uint64_t n_tx,
                           const uint32_t *rank_of_item, const uint32_t *rows, uint32_t Wp,
-                          const uint32_t *rowpre, const uint64_t *tl_off, uint32_t *rk,
+                          const uint32_t *rowpre, const uint64_t *tl_off, uint16_t *rk,
                           uint32_t *tlp, uint16_t *suf, hipStream_t stream);
 // Root class over projected transactions: rk, tlp and suf as above (tid
 // lists at offsets tl_off[n + 1]); 16-bit counters when max_supp (the
 // largest row support) is at most 65535.  Pairs as for launch_root_pairs;
 // *work receives the pair increments.
 void project_tile(uint32_t n, uint32_t *R, uint32_t *J);
-hipError_t launch_root_project(const uint32_t *rk, const uint32_t *tlp, const uint16_t *suf,
+hipError_t launch_root_project(const uint16_t *rk, const uint32_t *tlp, const uint16_t *suf,
                                const uint64_t *tl_off, uint32_t n, uint32_t max_supp,
                                uint32_t minsup, uint32_t *pairs, uint64_t cap,
                                unsigned long long *n_pairs, unsigned long long *work,

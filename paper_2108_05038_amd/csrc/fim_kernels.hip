@@ -500,6 +500,7 @@ __global__ __launch_bounds__(kBlock) void k_root_sparse(
 // choice for long sparse rows.
 
 constexpr uint32_t kRankEnd = 0xFFFFFFFFu;  // equal to kNone: infrequent items sort last
+constexpr uint16_t kRankEnd16 = 0xFFFFu;    // the same in the 16-bit ranked transactions
 
 // tl[tl_off[r] ..) = the transactions holding rank r, ascending: the set
 // bits of row r, one wave per row, compacted with a wave prefix sum of the
@@ -585,7 +586,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_tx(
     const uint64_t *__restrict__ off, const uint32_t *__restrict__ items, uint64_t n_tx,
     const uint32_t *__restrict__ rank_of_item, const uint32_t *__restrict__ rows, uint32_t Wp,
     const uint32_t *__restrict__ rowpre, uint32_t Wb, const uint64_t *__restrict__ tl_off,
-    uint32_t *rk, uint32_t *tlp, uint16_t *suf) {
+    uint16_t *rk, uint32_t *tlp, uint16_t *suf) {
     const uint32_t lane = lane_id();
     const uint64_t waves = (uint64_t)gridDim.x * kWavesPerBlock;
     const uint64_t n_groups = (n_tx + kRankGroup - 1) / kRankGroup;
@@ -641,13 +642,13 @@ __global__ __launch_bounds__(kBlock) void k_rank_tx(
                 const uint64_t base = a[j] + tg0 + j;
                 const uint32_t lf = (uint32_t)__popcll(__ballot(r[j] != kNone));  // frequent items
                 if (lane < L[j]) {
-                    rk[base + pos[j]] = r[j];
+                    rk[base + pos[j]] = (uint16_t)r[j];  // kNone -> kRankEnd16
                     if (r[j] != kNone) {
                         tlp[lo[j] + idx[j]] = (uint32_t)(base + pos[j]);
                         suf[lo[j] + idx[j]] = (uint16_t)(lf - 1 - pos[j]);
                     }
                 }
-                if (lane == 0) rk[base + L[j]] = kRankEnd;
+                if (lane == 0) rk[base + L[j]] = kRankEnd16;
             }
             continue;
         }
@@ -675,14 +676,14 @@ __global__ __launch_bounds__(kBlock) void k_rank_tx(
                     }
                 }
                 if (c >= Lt) continue;
-                rk[base + p] = rc;
+                rk[base + p] = (uint16_t)rc;
                 if (rc != kNone) {
                     const uint64_t i = tl_off[rc] + tid_index(rows, Wp, rowpre, Wb, rc, t);
                     tlp[i] = (uint32_t)(base + p);
                     suf[i] = (uint16_t)(lf - 1 - p);
                 }
             }
-            if (lane == 0) rk[base + Lt] = kRankEnd;
+            if (lane == 0) rk[base + Lt] = kRankEnd16;
         }
     }
 }
@@ -701,7 +702,7 @@ constexpr uint32_t kProjectMaxRows = 64;
 // in flight however the suffix lengths differ.
 template <bool Packed>
 __global__ __launch_bounds__(kBlock) void k_root_project(
-    const uint32_t *__restrict__ rk, const uint32_t *__restrict__ tlp,
+    const uint16_t *__restrict__ rk, const uint32_t *__restrict__ tlp,
     const uint16_t *__restrict__ suf, const uint64_t *__restrict__ tl_off, uint32_t n, uint32_t R,
     uint32_t J, uint32_t minsup, uint32_t *pairs, uint64_t cap, unsigned long long *n_pairs,
     unsigned long long *work) {
@@ -1975,7 +1976,7 @@ hipError_t launch_tidlist(const uint32_t *rows, uint32_t n, uint32_t Wp, const u
 
 hipError_t launch_rank_tx(const uint64_t *off, const uint32_t *items, uint64_t n_tx,
                           const uint32_t *rank_of_item, const uint32_t *rows, uint32_t Wp,
-                          const uint32_t *rowpre, const uint64_t *tl_off, uint32_t *rk,
+                          const uint32_t *rowpre, const uint64_t *tl_off, uint16_t *rk,
                           uint32_t *tlp, uint16_t *suf, hipStream_t stream) {
     if (n_tx == 0) return hipSuccess;
     const uint64_t groups = (n_tx + kRankGroup - 1) / kRankGroup;
@@ -2065,7 +2066,7 @@ void project_tile(uint32_t n, uint32_t *R, uint32_t *J) {
     *R = std::max<uint32_t>(1, std::min<uint32_t>(kProjectMaxRows, words / *J));
 }
 
-hipError_t launch_root_project(const uint32_t *rk, const uint32_t *tlp, const uint16_t *suf,
+hipError_t launch_root_project(const uint16_t *rk, const uint32_t *tlp, const uint16_t *suf,
                                const uint64_t *tl_off, uint32_t n, uint32_t max_supp,
                                uint32_t minsup, uint32_t *pairs, uint64_t cap,
                                unsigned long long *n_pairs, unsigned long long *work,

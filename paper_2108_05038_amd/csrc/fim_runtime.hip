@@ -969,8 +969,10 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         HIPCHK(h2d(ctx, I.d_item_of_rank.as<void>(), I.item_of_rank.data(), (size_t)I.n_freq * 4, s));
         tr.mark("  (rank uploads)");
         const uint32_t n = I.n_freq;
-        // positions in the ranked transactions are 32-bit, suffix lengths 16-bit
-        const bool fits = I.db->nnz + I.db->n_tx + 8 < (1ull << 32) && I.db->max_tx_len < (1u << 16);
+        // positions in the ranked transactions are 32-bit, ranks and suffix
+        // lengths 16-bit
+        const bool fits = I.db->nnz + I.db->n_tx + 8 < (1ull << 32) && I.db->max_tx_len < (1u << 16) &&
+                          n < 0xFFFFu;
         const bool pairs_needed = n >= 2 && opts.max_len != 1;
         if (pairs_needed) {
             // Root-class kernel by estimated time (picoseconds per unit measured
@@ -1028,13 +1030,13 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             HIPCHK(launch_tidlist(I.d_rows.as<uint32_t>(), n, I.Wp, I.d_tl_off.as<uint64_t>(),
                                   I.d_tl.as<uint32_t>(), ranked ? I.d_rowpre.as<uint32_t>() : nullptr, s));
             if (ranked) {
-                ENSURE(I.d_rk, ctx, (I.db->nnz + I.db->n_tx + 8) * 4);
+                ENSURE(I.d_rk, ctx, (I.db->nnz + I.db->n_tx + 8) * 2);
                 ENSURE(I.d_tlp, ctx, std::max<uint64_t>(I.tl_off[n], 1) * 4);
                 ENSURE(I.d_suf, ctx, std::max<uint64_t>(I.tl_off[n], 1) * 2);
                 HIPCHK(launch_rank_tx(I.db->d_off.as<uint64_t>(), I.db->d_items.as<uint32_t>(),
                                       I.db->n_tx, I.d_rank_of_item.as<uint32_t>(),
                                       I.d_rows.as<uint32_t>(), I.Wp, I.d_rowpre.as<uint32_t>(),
-                                      I.d_tl_off.as<uint64_t>(), I.d_rk.as<uint32_t>(),
+                                      I.d_tl_off.as<uint64_t>(), I.d_rk.as<uint16_t>(),
                                       I.d_tlp.as<uint32_t>(), I.d_suf.as<uint16_t>(), s));
             }
         }
@@ -1049,7 +1051,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             ENSURE(I.d_work, ctx, 8);
             HIPCHK(launch_fill_u32(I.d_work.as<uint32_t>(), 2, 0u, s));
             HIPCHK(hipEventRecord(rev[2 * q], s));
-            HIPCHK(launch_root_project(I.d_rk.as<uint32_t>(), I.d_tlp.as<uint32_t>(),
+            HIPCHK(launch_root_project(I.d_rk.as<uint16_t>(), I.d_tlp.as<uint32_t>(),
                                        I.d_suf.as<uint16_t>(), I.d_tl_off.as<uint64_t>(), n,
                                        max_supp_of(I), I.minsup,
                                        I.d_pairs.as<uint32_t>(), cap,
@@ -1112,7 +1114,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             ENSURE(I.d_pairs, ctx, I.n_pairs * 12);
             HIPCHK(launch_fill_u32(I.d_npairs.as<uint32_t>(), 2, 0u, s));
             if (I.root_kind == 2)
-                HIPCHK(launch_root_project(I.d_rk.as<uint32_t>(), I.d_tlp.as<uint32_t>(),
+                HIPCHK(launch_root_project(I.d_rk.as<uint16_t>(), I.d_tlp.as<uint32_t>(),
                                            I.d_suf.as<uint16_t>(), I.d_tl_off.as<uint64_t>(),
                                            I.n_freq, max_supp_of(I), I.minsup,
                                            I.d_pairs.as<uint32_t>(), I.n_pairs,

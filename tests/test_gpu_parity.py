@@ -250,6 +250,28 @@ def test_max_len(fim, ctx):
         assert g.as_dict() == want
 
 
+def test_result_views_outlive_the_result_object(fim, ctx):
+    # the binding hands out views of the library's result arrays (no copy):
+    # they stay valid after the Result object is gone and its handle would
+    # otherwise be released, and they are read-only; the pooled host memory
+    # of released results is reused by later calls without disturbing them
+    import gc
+    o_, it, ni = synth.basket(77, 4000, 300, 12.0, 600, 4.0)
+    db = synth.Database(o_, it, ni, 40)
+    say("result views")
+    o = oracle.mine_db(db, threads=4)
+    r = gpu_mine(fim, ctx, db)
+    off, items, supp = r.offsets, r.items, r.supports
+    del r
+    gc.collect()
+    for _ in range(3):  # later results reuse released pool blocks
+        gpu_mine(fim, ctx, db)
+        gc.collect()
+    assert oracle.digest(off, items, supp) == oracle.digest(o.offsets, o.items, o.supports)
+    with pytest.raises(ValueError):
+        items[0] = 0
+
+
 # ---------------------------------------------------------------- edge cases and errors
 
 def test_edge_cases(fim, ctx):
