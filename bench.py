@@ -49,9 +49,9 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 # bytes per launch measured with rocprofv3 (profiles/<kernel>.<workload>.txt)
 MEASURED_TRAFFIC = {
-    ("k_root_project", "sparse-200k"): (535.5 + 0.4) * 1e6,
-    ("k_dfs", "sparse-200k"): (132.9 + 2.7) * 1e6,
-    ("k_dfs", "dense-50k"): (20860.7 + 9002.2) * 1e6,
+    ("k_root_project", "sparse-200k"): (344.7 + 0.4) * 1e6,
+    ("k_dfs", "sparse-200k"): (131.9 + 2.7) * 1e6,
+    ("k_dfs", "dense-50k"): (20795.4 + 8993.4) * 1e6,
 }
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 

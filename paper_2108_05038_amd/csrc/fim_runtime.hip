@@ -1140,10 +1140,11 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         I.st.root_candidates = all;
         I.st.root_kernel = I.root_kind;
         if (I.root_kind == 2) {
-            // increments: the pairs inside the transactions; bytes: every
-            // transaction of T(a) read for each frequent a, the tid lists once
+            // increments: the pairs inside the transactions; bytes: a 16-bit
+            // rank per increment, and per tid-list entry its 32-bit pointer
+            // and 16-bit suffix length
             I.st.root_pair_words = I.project_work;
-            I.st.bytes_algorithmic = 4 * (I.project_work + 2 * I.tl_off[I.n_freq]);
+            I.st.bytes_algorithmic = 2 * I.project_work + 6 * I.tl_off[I.n_freq];
         } else if (I.root_kind == 1) {
             // words counted: row i's cover words against every later row;
             // bytes: each row's non-zero words (word + mask) and the
