@@ -1415,7 +1415,12 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                 nxt = first[q];
             }
         }
-        parallel_for(n_inst, host_threads(n_all), [&](uint64_t q) {
+        if (n_inst == 1 && lo[0] == 0 && hi[0] == n_all) {
+            // one instance: its result is the whole sorted output, moved as is
+            r_off[0].swap(all_off);
+            r_items[0].swap(all_items);
+            r_supp[0].swap(all_supp);
+        } else parallel_for(n_inst, host_threads(n_all), [&](uint64_t q) {
             const uint64_t a = lo[q], b = hi[q];
             r_off[q].resize(b - a + 1);
             const uint64_t base = all_off[a];
