@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -130,11 +131,26 @@ struct fim_db {
     fim::DevBuf d_off, d_items;
 };
 
+namespace fim {
+// Items and supports of every instance of one batched call, in one pair of
+// arrays that the instances' results share (each holds its own offsets).
+struct SharedArrays {
+    U32Vec items, supp;
+};
+}  // namespace fim
+
 struct fim_result {
     fim::U64Vec off{0};
-    fim::U32Vec items, supp;
+    fim::U32Vec items, supp;  // empty when the arrays are shared
+    std::shared_ptr<const fim::SharedArrays> shared;
+    uint64_t items_at = 0, supp_at = 0;  // this result's start in the shared arrays
     fim_stats stats{};
     bool truncated = false;  // internal sample runs only: output budget exceeded
+
+    uint64_t n_itemsets() const { return off.size() - 1; }
+    uint64_t n_items() const { return off.back(); }
+    const uint32_t *items_data() const { return shared ? shared->items.data() + items_at : items.data(); }
+    const uint32_t *supp_data() const { return shared ? shared->supp.data() + supp_at : supp.data(); }
 };
 
 namespace fim {

@@ -403,8 +403,8 @@ extern "C" fim_status fim_minsup_from_relative(uint64_t n_tx, double rel, uint32
 extern "C" fim_status fim_result_sizes(const fim_result *r, uint64_t *n_itemsets,
                                        uint64_t *n_items_total) {
     if (!r) return fim::set_error(FIM_E_INVALID_ARG, "result is NULL");
-    if (n_itemsets) *n_itemsets = r->supp.size();
-    if (n_items_total) *n_items_total = r->items.size();
+    if (n_itemsets) *n_itemsets = r->n_itemsets();
+    if (n_items_total) *n_items_total = r->n_items();
     return FIM_OK;
 }
 
@@ -412,8 +412,8 @@ extern "C" fim_status fim_result_copy(const fim_result *r, uint64_t *offsets, ui
                                       uint32_t *supports) {
     if (!r) return fim::set_error(FIM_E_INVALID_ARG, "result is NULL");
     if (offsets) memcpy(offsets, r->off.data(), r->off.size() * sizeof(uint64_t));
-    if (items && !r->items.empty()) memcpy(items, r->items.data(), r->items.size() * 4);
-    if (supports && !r->supp.empty()) memcpy(supports, r->supp.data(), r->supp.size() * 4);
+    if (items && r->n_items()) memcpy(items, r->items_data(), r->n_items() * 4);
+    if (supports && r->n_itemsets()) memcpy(supports, r->supp_data(), r->n_itemsets() * 4);
     return FIM_OK;
 }
 
@@ -421,8 +421,8 @@ extern "C" fim_status fim_result_view(const fim_result *r, const uint64_t **offs
                                       const uint32_t **items, const uint32_t **supports) {
     if (!r || !offsets || !items || !supports) return fim::set_error(FIM_E_INVALID_ARG, "NULL argument");
     *offsets = r->off.data();
-    *items = r->items.empty() ? nullptr : r->items.data();
-    *supports = r->supp.empty() ? nullptr : r->supp.data();
+    *items = r->n_items() ? r->items_data() : nullptr;
+    *supports = r->n_itemsets() ? r->supp_data() : nullptr;
     return FIM_OK;
 }
 
@@ -1397,6 +1397,11 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
     // ---------------- a9: results in canonical order
     std::vector<U32Vec> r_items(n_inst), r_supp(n_inst);
     std::vector<U64Vec> r_off(n_inst);
+    // several instances in key mode: items and supports stay in the sorted
+    // output, shared by the instances' results (r_at: each one's start)
+    std::shared_ptr<SharedArrays> shared;
+    std::vector<std::pair<uint64_t, uint64_t>> r_at(n_inst, {0, 0});
+    std::vector<uint64_t> r_n(n_inst, 0);  // itemsets of each instance
     if (key_mode) {
         std::vector<uint64_t> first;
         U64Vec all_off;
@@ -1420,14 +1425,18 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             r_off[0].swap(all_off);
             r_items[0].swap(all_items);
             r_supp[0].swap(all_supp);
-        } else parallel_for(n_inst, host_threads(n_all), [&](uint64_t q) {
-            const uint64_t a = lo[q], b = hi[q];
-            r_off[q].resize(b - a + 1);
-            const uint64_t base = all_off[a];
-            for (uint64_t x = a; x <= b; x++) r_off[q][x - a] = all_off[x] - base;
-            r_items[q].assign(all_items.begin() + base, all_items.begin() + all_off[b]);
-            r_supp[q].assign(all_supp.begin() + a, all_supp.begin() + b);
-        });
+        } else {
+            shared = std::make_shared<SharedArrays>();
+            shared->items.swap(all_items);
+            shared->supp.swap(all_supp);
+            parallel_for(n_inst, host_threads(n_all), [&](uint64_t q) {
+                const uint64_t a = lo[q], b = hi[q];
+                r_off[q].resize(b - a + 1);
+                const uint64_t base = all_off[a];
+                for (uint64_t x = a; x <= b; x++) r_off[q][x - a] = all_off[x] - base;
+                r_at[q] = {base, a};
+            });
+        }
         keys_done = true;
     }
     for (uint32_t q = 0; q < n_inst; q++) {
@@ -1607,10 +1616,11 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         }
     }
     for (uint32_t q = 0; q < n_inst; q++) {
-        if (opts.max_itemsets && r_supp[q].size() > opts.max_itemsets && !truncated)
+        r_n[q] = r_off[q].empty() ? 0 : r_off[q].size() - 1;
+        if (opts.max_itemsets && r_n[q] > opts.max_itemsets && !truncated)
             return set_error(FIM_E_OUTPUT_LIMIT,
                              "instance " + std::to_string(q) + " has " +
-                                 std::to_string(r_supp[q].size()) + " frequent itemsets > max_itemsets");
+                                 std::to_string(r_n[q]) + " frequent itemsets > max_itemsets");
     }
     // canonical order: large instances one after another with all host
     // threads, the others side by side with one thread each (internal
@@ -1642,8 +1652,13 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         R->items.swap(r_items[q]);
         R->off.swap(r_off[q]);
         R->supp.swap(r_supp[q]);
+        if (shared) {
+            R->shared = shared;
+            R->items_at = r_at[q].first;
+            R->supp_at = r_at[q].second;
+        }
         R->stats = insts[q].st;
-        if (!sample_run) R->stats.n_itemsets = R->supp.size();
+        if (!sample_run) R->stats.n_itemsets = R->n_itemsets();
         R->truncated = truncated || (sample_run && ictr[q].stop);
         results[q] = R;
     }
