@@ -498,6 +498,20 @@ struct Inst {
 
 }  // namespace
 
+// Page-locked host memory for one run's device-to-host copies: a copy into
+// it does not stall the host, so every instance's copy is queued before one
+// wait.
+struct PinnedBlock {
+    void *p = nullptr;
+    size_t bytes = 0;
+    explicit PinnedBlock(size_t b) : bytes(std::max<size_t>(b, 8)) { p = host_pool_alloc(bytes); }
+    ~PinnedBlock() { host_pool_free(p, bytes); }
+    PinnedBlock(const PinnedBlock &) = delete;
+    PinnedBlock &operator=(const PinnedBlock &) = delete;
+    template <class T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
 uint32_t max_supp_of(const Inst &I) {
     uint32_t m = 0;
     for (uint32_t r = 0; r < I.n_freq; r++) m = std::max(m, I.supp_of_rank[r]);
@@ -914,6 +928,9 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         part_words = std::max(part_words, item_count_scratch_words(reqs[q].db->nnz, reqs[q].db->n_item_ids));
     DevBuf d_part(ctx);
     if (part_words) ENSURE(d_part, ctx, part_words * 4);
+    std::vector<uint64_t> count_at(n_inst + 1, 0);
+    for (uint32_t q = 0; q < n_inst; q++) count_at[q + 1] = count_at[q] + reqs[q].db->n_item_ids;
+    PinnedBlock h_counts(count_at[n_inst] * 4);
     for (uint32_t q = 0; q < n_inst; q++) {
         Inst &I = insts[q];
         I.db = reqs[q].db;
@@ -922,11 +939,12 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         ENSURE(I.d_counts, ctx, (size_t)ni * 4);
         HIPCHK(launch_item_count(I.db->d_items.as<uint32_t>(), I.db->nnz, I.d_counts.as<uint32_t>(),
                                  ni, part_words ? d_part.as<uint32_t>() : nullptr, s));
-        I.counts.resize(ni);
-        HIPCHK(hipMemcpyAsync(I.counts.data(), I.d_counts.as<void>(), (size_t)ni * 4,
-                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(h_counts.as<uint32_t>() + count_at[q], I.d_counts.as<void>(),
+                              (size_t)ni * 4, hipMemcpyDeviceToHost, s));
     }
     HIPCHK(stream_wait(s));
+    for (uint32_t q = 0; q < n_inst; q++)
+        insts[q].counts.assign(h_counts.as<uint32_t>() + count_at[q], h_counts.as<uint32_t>() + count_at[q + 1]);
     tr.mark("item supports");
 
     // ---------------- a3 + root class: bitmaps and frequent pairs
@@ -951,6 +969,9 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         }
     } evv{rev};
     for (auto &e : rev) HIPCHK(hipEventCreate(&e));
+    // per instance: frequent pairs found, pair increments (projected root)
+    PinnedBlock h_small(16ull * n_inst);
+    memset(h_small.p, 0, 16ull * n_inst);
     tr.mark("  (events)");
     for (uint32_t q = 0; q < n_inst; q++) {
         Inst &I = insts[q];
@@ -1058,7 +1079,8 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                                        I.d_npairs.as<unsigned long long>(),
                                        I.d_work.as<unsigned long long>(), s));
             HIPCHK(hipEventRecord(rev[2 * q + 1], s));
-            HIPCHK(hipMemcpyAsync(&I.project_work, I.d_work.as<void>(), 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(h_small.as<unsigned long long>() + 2 * q + 1, I.d_work.as<void>(), 8,
+                                  hipMemcpyDeviceToHost, s));
         } else if (I.root_kind == 1) {
             I.nz_off.assign(n + 1, 0);
             for (uint32_t r = 0; r < n; r++)
@@ -1092,12 +1114,27 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                                      I.d_npairs.as<unsigned long long>(), s));
             HIPCHK(hipEventRecord(rev[2 * q + 1], s));
         }
-        HIPCHK(hipMemcpyAsync(&I.n_pairs, I.d_npairs.as<void>(), 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(h_small.as<unsigned long long>() + 2 * q, I.d_npairs.as<void>(), 8,
+                              hipMemcpyDeviceToHost, s));
     }
     const bool deep = opts.max_len == 0 || opts.max_len >= 3;
     tr.mark("  (root work queued)");
     HIPCHK(stream_wait(s));
     tr.mark("  (root work done)");
+    for (uint32_t q = 0; q < n_inst; q++) {
+        Inst &I = insts[q];
+        if (I.n_freq < 2 || opts.max_len == 1) continue;
+        I.n_pairs = h_small.as<unsigned long long>()[2 * q];
+        if (I.root_kind == 2) I.project_work = h_small.as<unsigned long long>()[2 * q + 1];
+    }
+    // every instance's frequent pairs into one page-locked block, one wait
+    std::vector<uint64_t> pair_at(n_inst + 1, 0);
+    for (uint32_t q = 0; q < n_inst; q++) {
+        const Inst &I = insts[q];
+        pair_at[q + 1] = pair_at[q] + ((I.n_freq < 2 || opts.max_len == 1) ? 0 : I.n_pairs);
+    }
+    PinnedBlock h_pairs(pair_at[n_inst] * 12);
+    auto h_pairs_of = [&](uint32_t q) { return h_pairs.as<uint32_t>() + 3 * pair_at[q]; };
     for (uint32_t q = 0; q < n_inst; q++) {
         const Inst &I = insts[q];
         if (I.n_freq < 2 || opts.max_len == 1) continue;
@@ -1132,9 +1169,8 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                                          I.d_npairs.as<unsigned long long>(), s));
             I.st.retries++;
         }
-        I.pairs.resize(I.n_pairs * 3);
         if (I.n_pairs)
-            HIPCHK(hipMemcpyAsync(I.pairs.data(), I.d_pairs.as<void>(), I.n_pairs * 12,
+            HIPCHK(hipMemcpyAsync(h_pairs_of(q), I.d_pairs.as<void>(), I.n_pairs * 12,
                                   hipMemcpyDeviceToHost, s));
         I.st.candidates = all;
         I.st.root_candidates = all;
@@ -1166,6 +1202,8 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
     tr.mark("  (pairs copied)");
     parallel_for(n_inst, host_threads((uint64_t)n_inst << 14), [&](uint64_t q) {
         Inst &I = insts[q];
+        if (pair_at[q + 1] > pair_at[q])
+            I.pairs.assign(h_pairs_of((uint32_t)q), h_pairs_of((uint32_t)q) + 3 * (pair_at[q + 1] - pair_at[q]));
         I.st.root_kernel_ns = (uint64_t)(root_ms * 1e6);
         I.st.kernel_ns = I.st.root_kernel_ns;
         if (I.n_pairs) build_level2(I, by_id);
