@@ -1248,13 +1248,15 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             }
             const uint64_t root = (uint64_t)I.n_freq * (I.n_freq ? I.n_freq - 1 : 0) / 2;
             // The sample has about as many frequent itemsets as the database
-            // (same relative support), so mining it costs about as much as
-            // mining the database unless the database is much longer than
-            // the sample: the estimate is drawn for at least 16 |D~|
-            // transactions.
+            // (same relative support), and the persistent kernel's time on
+            // narrow rows goes mostly to latency, so mining the sample costs
+            // a large part of mining the database; with work shared between
+            // the waves at run time the better order saves less than that
+            // on every workload measured (up to 200,000 = 43 |D~|
+            // transactions).  The estimate is drawn for at least 64 |D~|.
             const uint64_t want_tx = opts.sample_tx ? opts.sample_tx : default_sample_tx(0.02, 0.05);
             pin[q].estimate = (opts.flags & FIM_FLAG_ALWAYS_ESTIMATE) ||
-                              (20 * below >= root && I.db->n_tx >= 16 * want_tx);
+                              (20 * below >= root && I.db->n_tx >= 64 * want_tx);
             deep_work = deep_work || 20 * below >= root;
         }
         fim_status ps = FIM_OK;
