@@ -38,6 +38,9 @@ struct fim_ctx {
     char *up = nullptr;
     size_t up_cap = 0, up_used = 0, up_need = 0;
     int up_depth = 0;
+    // streams (default priority) that let the instances of a batched call
+    // overlap their root-class work; created on first use
+    std::vector<hipStream_t> side_streams;
     uint32_t *stage(size_t words);
 
     // Device blocks freed by the library are kept by size class for the
@@ -90,6 +93,9 @@ class DevBuf {
     void *p_ = nullptr;
     size_t bytes_ = 0;
 };
+
+// The context's side streams (created on first use).
+hipError_t ctx_side_streams(fim_ctx *ctx, std::vector<hipStream_t> &out);
 
 // Host-to-device copy of `bytes` from src to dst, queued on s through the
 // context's page-locked staging (src may be reused as soon as this returns;

@@ -235,6 +235,10 @@ uint32_t *fim_ctx::stage(size_t words) {
 
 fim_ctx::~fim_ctx() {
     delete aux;
+    for (hipStream_t x : side_streams) {
+        (void)hipStreamSynchronize(x);
+        (void)hipStreamDestroy(x);
+    }
     release_cached();
     if (pinned) (void)hipHostFree(pinned);
     if (up) {
@@ -248,6 +252,18 @@ fim_ctx::~fim_ctx() {
 }
 
 namespace fim {
+
+hipError_t ctx_side_streams(fim_ctx *ctx, std::vector<hipStream_t> &out) {
+    constexpr size_t kSide = 4;
+    while (ctx->side_streams.size() < kSide) {
+        hipStream_t x = nullptr;
+        const hipError_t e = hipStreamCreateWithFlags(&x, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+        ctx->side_streams.push_back(x);
+    }
+    out = ctx->side_streams;
+    return hipSuccess;
+}
 
 hipError_t h2d(fim_ctx *ctx, void *dst, const void *src, size_t bytes, hipStream_t s) {
     if (bytes == 0) return hipSuccess;
@@ -972,9 +988,26 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
     // per instance: frequent pairs found, pair increments (projected root)
     PinnedBlock h_small(16ull * n_inst);
     memset(h_small.p, 0, 16ull * n_inst);
+    // several instances: their root work spread over side streams so that
+    // the small kernels of different instances overlap (joined below)
+    std::vector<hipStream_t> side;
+    hipEvent_t ev_fork = nullptr;
+    if (n_inst > 1) {
+        HIPCHK(ctx_side_streams(ctx, side));
+        HIPCHK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+        HIPCHK(hipEventRecord(ev_fork, s));
+        for (hipStream_t x : side) HIPCHK(hipStreamWaitEvent(x, ev_fork, 0));
+    }
+    struct ForkGuard {
+        hipEvent_t e;
+        ~ForkGuard() {
+            if (e) (void)hipEventDestroy(e);
+        }
+    } fork_guard{ev_fork};
     tr.mark("  (events)");
     for (uint32_t q = 0; q < n_inst; q++) {
         Inst &I = insts[q];
+        const hipStream_t sq = side.empty() ? s : side[q % side.size()];
         rank_items(I, by_id);
         tr.mark("  (ranks)");
         I.W = (uint32_t)((I.db->n_tx + 31) / 32);
@@ -986,8 +1019,8 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         ENSURE(I.d_rank_of_item, ctx, (size_t)ni * 4);
         ENSURE(I.d_item_of_rank, ctx, (size_t)I.n_freq * 4);
         ENSURE(I.d_rows, ctx, (size_t)I.n_freq * I.Wp * 4);
-        HIPCHK(h2d(ctx, I.d_rank_of_item.as<void>(), I.rank_of_item.data(), (size_t)ni * 4, s));
-        HIPCHK(h2d(ctx, I.d_item_of_rank.as<void>(), I.item_of_rank.data(), (size_t)I.n_freq * 4, s));
+        HIPCHK(h2d(ctx, I.d_rank_of_item.as<void>(), I.rank_of_item.data(), (size_t)ni * 4, sq));
+        HIPCHK(h2d(ctx, I.d_item_of_rank.as<void>(), I.item_of_rank.data(), (size_t)I.n_freq * 4, sq));
         tr.mark("  (rank uploads)");
         const uint32_t n = I.n_freq;
         // positions in the ranked transactions are 32-bit, ranks and suffix
@@ -1023,12 +1056,12 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         if (K) {
             HIPCHK(launch_bitmap_tiles(I.db->d_off.as<uint64_t>(), I.db->d_items.as<uint32_t>(),
                                        I.db->n_tx, I.d_rank_of_item.as<uint32_t>(), n,
-                                       I.d_rows.as<uint32_t>(), I.Wp, K, s));
+                                       I.d_rows.as<uint32_t>(), I.Wp, K, sq));
         } else {
-            HIPCHK(launch_fill_u32(I.d_rows.as<uint32_t>(), (uint64_t)n * I.Wp, 0u, s));
+            HIPCHK(launch_fill_u32(I.d_rows.as<uint32_t>(), (uint64_t)n * I.Wp, 0u, sq));
             HIPCHK(launch_bitmap_build(I.db->d_off.as<uint64_t>(), I.db->d_items.as<uint32_t>(),
                                        I.db->n_tx, I.d_rank_of_item.as<uint32_t>(),
-                                       I.d_rows.as<uint32_t>(), I.Wp, s));
+                                       I.d_rows.as<uint32_t>(), I.Wp, sq));
         }
         tr.mark("  (bitmap queued)");
         // Ascending transaction lists of the ranks (the set bits of their
@@ -1045,11 +1078,11 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             for (uint32_t r = 0; r < n; r++) I.tl_off[r + 1] = I.tl_off[r] + I.supp_of_rank[r];
             ENSURE(I.d_tl, ctx, std::max<uint64_t>(I.tl_off[n], 1) * 4);
             ENSURE(I.d_tl_off, ctx, (n + 1) * 8);
-            HIPCHK(h2d(ctx, I.d_tl_off.as<void>(), I.tl_off.data(), (n + 1) * 8, s));
+            HIPCHK(h2d(ctx, I.d_tl_off.as<void>(), I.tl_off.data(), (n + 1) * 8, sq));
             const bool ranked = I.root_kind == 2 && pairs_needed;
             if (ranked) ENSURE(I.d_rowpre, ctx, (uint64_t)n * rowpre_words(I.Wp) * 4);
             HIPCHK(launch_tidlist(I.d_rows.as<uint32_t>(), n, I.Wp, I.d_tl_off.as<uint64_t>(),
-                                  I.d_tl.as<uint32_t>(), ranked ? I.d_rowpre.as<uint32_t>() : nullptr, s));
+                                  I.d_tl.as<uint32_t>(), ranked ? I.d_rowpre.as<uint32_t>() : nullptr, sq));
             if (ranked) {
                 ENSURE(I.d_rk, ctx, (I.db->nnz + I.db->n_tx + 8) * 2);
                 ENSURE(I.d_tlp, ctx, std::max<uint64_t>(I.tl_off[n], 1) * 4);
@@ -1058,7 +1091,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                                       I.db->n_tx, I.d_rank_of_item.as<uint32_t>(),
                                       I.d_rows.as<uint32_t>(), I.Wp, I.d_rowpre.as<uint32_t>(),
                                       I.d_tl_off.as<uint64_t>(), I.d_rk.as<uint16_t>(),
-                                      I.d_tlp.as<uint32_t>(), I.d_suf.as<uint16_t>(), s));
+                                      I.d_tlp.as<uint32_t>(), I.d_suf.as<uint16_t>(), sq));
             }
         }
         tr.mark("  (lists queued)");
@@ -1067,20 +1100,20 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         const uint64_t cap = std::min<uint64_t>(all, std::max<uint64_t>(1u << 16, 64ull * n));
         ENSURE(I.d_pairs, ctx, cap * 12);
         ENSURE(I.d_npairs, ctx, 8);
-        HIPCHK(launch_fill_u32(I.d_npairs.as<uint32_t>(), 2, 0u, s));
+        HIPCHK(launch_fill_u32(I.d_npairs.as<uint32_t>(), 2, 0u, sq));
         if (I.root_kind == 2) {
             ENSURE(I.d_work, ctx, 8);
-            HIPCHK(launch_fill_u32(I.d_work.as<uint32_t>(), 2, 0u, s));
-            HIPCHK(hipEventRecord(rev[2 * q], s));
+            HIPCHK(launch_fill_u32(I.d_work.as<uint32_t>(), 2, 0u, sq));
+            HIPCHK(hipEventRecord(rev[2 * q], sq));
             HIPCHK(launch_root_project(I.d_rk.as<uint16_t>(), I.d_tlp.as<uint32_t>(),
                                        I.d_suf.as<uint16_t>(), I.d_tl_off.as<uint64_t>(), n,
                                        max_supp_of(I), I.minsup,
                                        I.d_pairs.as<uint32_t>(), cap,
                                        I.d_npairs.as<unsigned long long>(),
-                                       I.d_work.as<unsigned long long>(), s));
-            HIPCHK(hipEventRecord(rev[2 * q + 1], s));
+                                       I.d_work.as<unsigned long long>(), sq));
+            HIPCHK(hipEventRecord(rev[2 * q + 1], sq));
             HIPCHK(hipMemcpyAsync(h_small.as<unsigned long long>() + 2 * q + 1, I.d_work.as<void>(), 8,
-                                  hipMemcpyDeviceToHost, s));
+                                  hipMemcpyDeviceToHost, sq));
         } else if (I.root_kind == 1) {
             I.nz_off.assign(n + 1, 0);
             for (uint32_t r = 0; r < n; r++)
@@ -1091,31 +1124,39 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             ENSURE(I.d_nz_m, ctx, std::max<uint64_t>(I.nz_off[n], 1) * 4);
             ENSURE(I.d_nz_cnt, ctx, (size_t)n * 4);
             ENSURE(I.d_bt, ctx, (size_t)I.W * np * 4);
-            HIPCHK(h2d(ctx, I.d_nz_off.as<void>(), I.nz_off.data(), (n + 1) * 8, s));
+            HIPCHK(h2d(ctx, I.d_nz_off.as<void>(), I.nz_off.data(), (n + 1) * 8, sq));
             HIPCHK(launch_row_nonzero(I.d_rows.as<uint32_t>(), n, I.Wp, I.d_nz_off.as<uint64_t>(),
                                       I.d_nz_w.as<uint32_t>(), I.d_nz_m.as<uint32_t>(),
-                                      I.d_nz_cnt.as<uint32_t>(), s));
+                                      I.d_nz_cnt.as<uint32_t>(), sq));
             HIPCHK(launch_transpose(I.d_rows.as<uint32_t>(), n, I.Wp, I.W, I.d_bt.as<uint32_t>(),
-                                    (uint32_t)np, s));
-            HIPCHK(hipEventRecord(rev[2 * q], s));
+                                    (uint32_t)np, sq));
+            HIPCHK(hipEventRecord(rev[2 * q], sq));
             HIPCHK(launch_root_sparse(I.d_bt.as<uint32_t>(), (uint32_t)np, I.d_nz_off.as<uint64_t>(),
                                       I.d_nz_cnt.as<uint32_t>(), I.d_nz_w.as<uint32_t>(),
                                       I.d_nz_m.as<uint32_t>(), n, I.minsup,
                                       I.d_pairs.as<uint32_t>(), cap,
-                                      I.d_npairs.as<unsigned long long>(), s));
-            HIPCHK(hipEventRecord(rev[2 * q + 1], s));
+                                      I.d_npairs.as<unsigned long long>(), sq));
+            HIPCHK(hipEventRecord(rev[2 * q + 1], sq));
             I.nz_cnt.resize(n);
             HIPCHK(hipMemcpyAsync(I.nz_cnt.data(), I.d_nz_cnt.as<void>(), (size_t)n * 4,
-                                  hipMemcpyDeviceToHost, s));
+                                  hipMemcpyDeviceToHost, sq));
         } else {
-            HIPCHK(hipEventRecord(rev[2 * q], s));
+            HIPCHK(hipEventRecord(rev[2 * q], sq));
             HIPCHK(launch_root_pairs(I.d_rows.as<uint32_t>(), I.n_freq, I.Wp, I.minsup,
                                      I.d_pairs.as<uint32_t>(), cap,
-                                     I.d_npairs.as<unsigned long long>(), s));
-            HIPCHK(hipEventRecord(rev[2 * q + 1], s));
+                                     I.d_npairs.as<unsigned long long>(), sq));
+            HIPCHK(hipEventRecord(rev[2 * q + 1], sq));
         }
         HIPCHK(hipMemcpyAsync(h_small.as<unsigned long long>() + 2 * q, I.d_npairs.as<void>(), 8,
-                              hipMemcpyDeviceToHost, s));
+                              hipMemcpyDeviceToHost, sq));
+    }
+    for (hipStream_t x : side) {
+        hipEvent_t j = nullptr;
+        HIPCHK(hipEventCreateWithFlags(&j, hipEventDisableTiming));
+        hipError_t e1 = hipEventRecord(j, x);
+        hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(s, j, 0) : e1;
+        (void)hipEventDestroy(j);
+        HIPCHK(e2);
     }
     const bool deep = opts.max_len == 0 || opts.max_len >= 3;
     tr.mark("  (root work queued)");
