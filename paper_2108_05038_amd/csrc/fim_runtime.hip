@@ -937,27 +937,65 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
     StageRun stage_run(ctx);
     std::vector<Inst> insts(n_inst);
 
-    // ---------------- a2: item supports (all instances, one sync; the block
-    // histograms share one scratch buffer, used in stream order)
+    // ---------------- a2: item supports (all instances, one sync). Several
+    // instances spread over the context's side streams, forked from and
+    // joined back into s by events; each side stream has its own slice of
+    // the block-histogram scratch, used in that stream's order.
+    std::vector<hipStream_t> side;
+    hipEvent_t ev_fork = nullptr;
+    if (n_inst > 1) {
+        HIPCHK(ctx_side_streams(ctx, side));
+        HIPCHK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+    }
+    struct ForkGuard {
+        hipEvent_t e;
+        ~ForkGuard() {
+            if (e) (void)hipEventDestroy(e);
+        }
+    } fork_guard{ev_fork};
+    // side streams start after everything queued on s so far
+    auto fork = [&]() -> hipError_t {
+        if (side.empty()) return hipSuccess;
+        hipError_t e = hipEventRecord(ev_fork, s);
+        for (size_t i = 0; e == hipSuccess && i < side.size(); i++) e = hipStreamWaitEvent(side[i], ev_fork, 0);
+        return e;
+    };
+    // s continues after everything queued on the side streams
+    auto join = [&]() -> hipError_t {
+        for (hipStream_t x : side) {
+            hipEvent_t ej = nullptr;
+            hipError_t e = hipEventCreateWithFlags(&ej, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventRecord(ej, x);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, ej, 0);
+            if (ej) (void)hipEventDestroy(ej);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    const uint32_t n_lanes = side.empty() ? 1u : (uint32_t)side.size();
     uint64_t part_words = 0;
     for (uint32_t q = 0; q < n_inst; q++)
         part_words = std::max(part_words, item_count_scratch_words(reqs[q].db->nnz, reqs[q].db->n_item_ids));
     DevBuf d_part(ctx);
-    if (part_words) ENSURE(d_part, ctx, part_words * 4);
+    if (part_words) ENSURE(d_part, ctx, part_words * n_lanes * 4);
     std::vector<uint64_t> count_at(n_inst + 1, 0);
     for (uint32_t q = 0; q < n_inst; q++) count_at[q + 1] = count_at[q] + reqs[q].db->n_item_ids;
     PinnedBlock h_counts(count_at[n_inst] * 4);
+    HIPCHK(fork());
     for (uint32_t q = 0; q < n_inst; q++) {
         Inst &I = insts[q];
         I.db = reqs[q].db;
         I.minsup = reqs[q].minsup;
         const uint32_t ni = I.db->n_item_ids;
+        const uint32_t lane = q % n_lanes;
+        const hipStream_t sq = side.empty() ? s : side[lane];
         ENSURE(I.d_counts, ctx, (size_t)ni * 4);
-        HIPCHK(launch_item_count(I.db->d_items.as<uint32_t>(), I.db->nnz, I.d_counts.as<uint32_t>(),
-                                 ni, part_words ? d_part.as<uint32_t>() : nullptr, s));
+        HIPCHK(launch_item_count(I.db->d_items.as<uint32_t>(), I.db->nnz, I.d_counts.as<uint32_t>(), ni,
+                                 part_words ? d_part.as<uint32_t>() + lane * part_words : nullptr, sq));
         HIPCHK(hipMemcpyAsync(h_counts.as<uint32_t>() + count_at[q], I.d_counts.as<void>(),
-                              (size_t)ni * 4, hipMemcpyDeviceToHost, s));
+                              (size_t)ni * 4, hipMemcpyDeviceToHost, sq));
     }
+    HIPCHK(join());
     HIPCHK(stream_wait(s));
     for (uint32_t q = 0; q < n_inst; q++)
         insts[q].counts.assign(h_counts.as<uint32_t>() + count_at[q], h_counts.as<uint32_t>() + count_at[q + 1]);
@@ -988,22 +1026,9 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
     // per instance: frequent pairs found, pair increments (projected root)
     PinnedBlock h_small(16ull * n_inst);
     memset(h_small.p, 0, 16ull * n_inst);
-    // several instances: their root work spread over side streams so that
-    // the small kernels of different instances overlap (joined below)
-    std::vector<hipStream_t> side;
-    hipEvent_t ev_fork = nullptr;
-    if (n_inst > 1) {
-        HIPCHK(ctx_side_streams(ctx, side));
-        HIPCHK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
-        HIPCHK(hipEventRecord(ev_fork, s));
-        for (hipStream_t x : side) HIPCHK(hipStreamWaitEvent(x, ev_fork, 0));
-    }
-    struct ForkGuard {
-        hipEvent_t e;
-        ~ForkGuard() {
-            if (e) (void)hipEventDestroy(e);
-        }
-    } fork_guard{ev_fork};
+    // several instances: their root work spread over the side streams so
+    // that the small kernels of different instances overlap (joined below)
+    HIPCHK(fork());
     tr.mark("  (events)");
     for (uint32_t q = 0; q < n_inst; q++) {
         Inst &I = insts[q];
@@ -1150,14 +1175,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         HIPCHK(hipMemcpyAsync(h_small.as<unsigned long long>() + 2 * q, I.d_npairs.as<void>(), 8,
                               hipMemcpyDeviceToHost, sq));
     }
-    for (hipStream_t x : side) {
-        hipEvent_t j = nullptr;
-        HIPCHK(hipEventCreateWithFlags(&j, hipEventDisableTiming));
-        hipError_t e1 = hipEventRecord(j, x);
-        hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(s, j, 0) : e1;
-        (void)hipEventDestroy(j);
-        HIPCHK(e2);
-    }
+    HIPCHK(join());
     const bool deep = opts.max_len == 0 || opts.max_len >= 3;
     tr.mark("  (root work queued)");
     HIPCHK(stream_wait(s));
