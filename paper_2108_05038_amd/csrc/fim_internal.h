@@ -138,9 +138,13 @@ hipError_t launch_bitmap_tiles(const uint64_t *offsets, const uint32_t *items, u
 // (i < j) with popcount(row_i & row_j) >= minsup is appended as
 // (i, j, support) to pairs (capacity cap triples); *n_pairs counts all
 // frequent pairs (it may exceed cap, then nothing past cap is written).
+// part (root_pairs_scratch_words() words, or nullptr) lets a launch with few
+// tiles over long rows split the words over more blocks: partial counts go
+// there and a second kernel sums them; it is used in stream order.
+uint64_t root_pairs_scratch_words();
 hipError_t launch_root_pairs(const uint32_t *rows, uint32_t n, uint32_t Wp, uint32_t minsup,
                              uint32_t *pairs, uint64_t cap, unsigned long long *n_pairs,
-                             hipStream_t stream);
+                             uint32_t *part, hipStream_t stream);
 
 // Preparation of the projected root kernel.  launch_tidlist: the tid lists
 // tl (at offsets tl_off[n + 1]) from the rows, and rowpre (n x

@@ -259,68 +259,28 @@ __global__ __launch_bounds__(kBlock) void k_bitmap_tile(const uint64_t *__restri
 
 constexpr int kRootRows = 64;
 constexpr int kRootTw = 32;  // words per LDS tile
+// Word-range splits: a launch with few tiles over long rows leaves most CUs
+// idle, so the words are cut into ranges counted by separate blocks (at
+// least kRootSplitMinWords each, at most kRootSplitBlocks blocks in all);
+// each block writes its 64 x 64 partial counts and k_root_finish sums them.
+constexpr uint32_t kRootSplitMinWords = 256;
+constexpr uint32_t kRootSplitBlocks = 512;
+constexpr uint32_t kRootTilePairs = kRootRows * kRootRows;
 
-__global__ __launch_bounds__(kBlock) void k_root_pairs(const uint32_t *__restrict__ rows,
-                                                        uint32_t n, uint32_t Wp, uint32_t minsup,
-                                                        uint32_t *pairs, uint64_t cap,
-                                                        unsigned long long *n_pairs) {
-    __shared__ uint32_t sI[kRootRows][kRootTw + 1];
-    __shared__ uint32_t sJ[kRootRows][kRootTw + 1];
-
-    // logical tile index -> (bi <= bj) in the upper triangle of tiles
-    const uint32_t b = xcd_local_block(blockIdx.x, gridDim.x);
-    uint32_t bj = (uint32_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+// logical tile index b -> (bi <= bj) in the upper triangle of tiles
+__device__ inline void root_tile_of(uint32_t b, uint32_t &bi, uint32_t &bj) {
+    bj = (uint32_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
     while ((uint64_t)bj * (bj + 1) / 2 > b) bj--;
     while ((uint64_t)(bj + 1) * (bj + 2) / 2 <= b) bj++;
-    const uint32_t bi = b - bj * (bj + 1) / 2;
-    const uint32_t I0 = bi * kRootRows, J0 = bj * kRootRows;
+    bi = b - bj * (bj + 1) / 2;
+}
 
+// threshold the 4 x 4 supports of a thread, then compact the frequent
+// pairs of the wave with one atomic
+__device__ inline void root_emit(const uint32_t (&acc)[4][4], uint32_t I0, uint32_t J0, uint32_t n,
+                                 uint32_t minsup, uint32_t *pairs, uint64_t cap,
+                                 unsigned long long *n_pairs) {
     const uint32_t tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    uint32_t acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; a++)
-#pragma unroll
-        for (int c = 0; c < 4; c++) acc[a][c] = 0;
-
-    for (uint32_t w0 = 0; w0 < Wp; w0 += kRootTw) {
-        // 64 rows x 32 words per side = 512 uint4; 2 per thread per side
-#pragma unroll
-        for (int q = 0; q < 2; q++) {
-            uint32_t idx = threadIdx.x + q * kBlock;  // 0..511
-            uint32_t row = idx >> 3, c4 = (idx & 7) * 4;
-            uint4 vi = make_uint4(0, 0, 0, 0), vj = make_uint4(0, 0, 0, 0);
-            if (w0 + c4 < Wp) {
-                if (I0 + row < n)
-                    vi = *reinterpret_cast<const uint4 *>(rows + (uint64_t)(I0 + row) * Wp + w0 + c4);
-                if (J0 + row < n)
-                    vj = *reinterpret_cast<const uint4 *>(rows + (uint64_t)(J0 + row) * Wp + w0 + c4);
-            }
-            sI[row][c4 + 0] = vi.x;
-            sI[row][c4 + 1] = vi.y;
-            sI[row][c4 + 2] = vi.z;
-            sI[row][c4 + 3] = vi.w;
-            sJ[row][c4 + 0] = vj.x;
-            sJ[row][c4 + 1] = vj.y;
-            sJ[row][c4 + 2] = vj.z;
-            sJ[row][c4 + 3] = vj.w;
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int w = 0; w < kRootTw; w++) {
-            uint32_t x[4], y[4];
-#pragma unroll
-            for (int a = 0; a < 4; a++) x[a] = sI[ty + 16 * a][w];
-#pragma unroll
-            for (int c = 0; c < 4; c++) y[c] = sJ[tx + 16 * c][w];
-#pragma unroll
-            for (int a = 0; a < 4; a++)
-#pragma unroll
-                for (int c = 0; c < 4; c++) acc[a][c] += __popc(x[a] & y[c]);
-        }
-        __syncthreads();
-    }
-
-    // threshold, then compact the frequent pairs of the wave with one atomic
     uint32_t mine = 0;
 #pragma unroll
     for (int a = 0; a < 4; a++)
@@ -356,6 +316,104 @@ __global__ __launch_bounds__(kBlock) void k_root_pairs(const uint32_t *__restric
                 pos++;
             }
         }
+}
+
+// blockIdx.x = tile, blockIdx.y = word range [y * chunk, min((y + 1) * chunk, Wp));
+// part == nullptr: one range, pairs emitted here; else the partial counts go
+// to part[(y * gridDim.x + tile) * kRootTilePairs + (4a + c) * kBlock + thread]
+__global__ __launch_bounds__(kBlock) void k_root_pairs(const uint32_t *__restrict__ rows,
+                                                        uint32_t n, uint32_t Wp, uint32_t chunk,
+                                                        uint32_t minsup, uint32_t *pairs, uint64_t cap,
+                                                        unsigned long long *n_pairs,
+                                                        uint32_t *__restrict__ part) {
+    __shared__ uint32_t sI[kRootRows][kRootTw + 1];
+    __shared__ uint32_t sJ[kRootRows][kRootTw + 1];
+
+    const uint32_t b = xcd_local_block(blockIdx.x, gridDim.x);
+    uint32_t bi, bj;
+    root_tile_of(b, bi, bj);
+    const uint32_t I0 = bi * kRootRows, J0 = bj * kRootRows;
+    const uint32_t wb = blockIdx.y * chunk;
+    const uint32_t we = (uint32_t)min<uint64_t>((uint64_t)wb + chunk, Wp);
+
+    const uint32_t tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    uint32_t acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int c = 0; c < 4; c++) acc[a][c] = 0;
+
+    for (uint32_t w0 = wb; w0 < we; w0 += kRootTw) {
+        // 64 rows x 32 words per side = 512 uint4; 2 per thread per side
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+            uint32_t idx = threadIdx.x + q * kBlock;  // 0..511
+            uint32_t row = idx >> 3, c4 = (idx & 7) * 4;
+            uint4 vi = make_uint4(0, 0, 0, 0), vj = make_uint4(0, 0, 0, 0);
+            if (w0 + c4 < we) {
+                if (I0 + row < n)
+                    vi = *reinterpret_cast<const uint4 *>(rows + (uint64_t)(I0 + row) * Wp + w0 + c4);
+                if (J0 + row < n)
+                    vj = *reinterpret_cast<const uint4 *>(rows + (uint64_t)(J0 + row) * Wp + w0 + c4);
+            }
+            sI[row][c4 + 0] = vi.x;
+            sI[row][c4 + 1] = vi.y;
+            sI[row][c4 + 2] = vi.z;
+            sI[row][c4 + 3] = vi.w;
+            sJ[row][c4 + 0] = vj.x;
+            sJ[row][c4 + 1] = vj.y;
+            sJ[row][c4 + 2] = vj.z;
+            sJ[row][c4 + 3] = vj.w;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int w = 0; w < kRootTw; w++) {
+            uint32_t x[4], y[4];
+#pragma unroll
+            for (int a = 0; a < 4; a++) x[a] = sI[ty + 16 * a][w];
+#pragma unroll
+            for (int c = 0; c < 4; c++) y[c] = sJ[tx + 16 * c][w];
+#pragma unroll
+            for (int a = 0; a < 4; a++)
+#pragma unroll
+                for (int c = 0; c < 4; c++) acc[a][c] += __popc(x[a] & y[c]);
+        }
+        __syncthreads();
+    }
+
+    if (part) {
+        uint32_t *dst = part + ((uint64_t)blockIdx.y * gridDim.x + b) * kRootTilePairs + threadIdx.x;
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int c = 0; c < 4; c++) dst[(4 * a + c) * kBlock] = acc[a][c];
+        return;
+    }
+    root_emit(acc, I0, J0, n, minsup, pairs, cap, n_pairs);
+}
+
+// sums the `splits` partial counts of each tile written by k_root_pairs,
+// then emits its frequent pairs
+__global__ __launch_bounds__(kBlock) void k_root_finish(const uint32_t *__restrict__ part,
+                                                         uint32_t splits, uint32_t n, uint32_t minsup,
+                                                         uint32_t *pairs, uint64_t cap,
+                                                         unsigned long long *n_pairs) {
+    const uint32_t b = xcd_local_block(blockIdx.x, gridDim.x);
+    uint32_t bi, bj;
+    root_tile_of(b, bi, bj);
+    uint32_t acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int c = 0; c < 4; c++) acc[a][c] = 0;
+    for (uint32_t y = 0; y < splits; y++) {
+        const uint32_t *src = part + ((uint64_t)y * gridDim.x + b) * kRootTilePairs + threadIdx.x;
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int c = 0; c < 4; c++) acc[a][c] += src[(4 * a + c) * kBlock];
+    }
+    root_emit(acc, bi * kRootRows, bj * kRootRows, n, minsup, pairs, cap, n_pairs);
 }
 
 // ------------------------------------------------------------------ a6/a7: root class over covers
@@ -2019,15 +2077,36 @@ hipError_t launch_prefix_keys(const PrefixSrc *src, uint32_t n_src, uint64_t max
     return hipGetLastError();
 }
 
+uint64_t root_pairs_scratch_words() { return (uint64_t)kRootSplitBlocks * kRootTilePairs; }
+
 hipError_t launch_root_pairs(const uint32_t *rows, uint32_t n, uint32_t Wp, uint32_t minsup,
                              uint32_t *pairs, uint64_t cap, unsigned long long *n_pairs,
-                             hipStream_t stream) {
+                             uint32_t *part, hipStream_t stream) {
     if (n < 2) return hipSuccess;
     const uint64_t nt = (n + kRootRows - 1) / kRootRows;
     const uint64_t tiles = nt * (nt + 1) / 2;
     if (tiles > 0x7FFFFFFFull) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_root_pairs, dim3((uint32_t)tiles), dim3(kBlock), 0, stream, rows, n, Wp,
-                       minsup, pairs, cap, n_pairs);
+    // word ranges: a multiple of the LDS tile width, at least
+    // kRootSplitMinWords each, tiles * splits <= kRootSplitBlocks
+    uint64_t splits = 1;
+    if (part && tiles * 2 <= kRootSplitBlocks)
+        splits = std::min<uint64_t>(kRootSplitBlocks / tiles, (Wp + kRootSplitMinWords - 1) / kRootSplitMinWords);
+    uint32_t chunk = Wp;
+    if (splits > 1) {
+        chunk = (uint32_t)(((Wp + splits - 1) / splits + kRootTw - 1) / kRootTw * kRootTw);
+        splits = (Wp + chunk - 1) / chunk;
+    }
+    if (splits <= 1) {
+        hipLaunchKernelGGL(k_root_pairs, dim3((uint32_t)tiles, 1), dim3(kBlock), 0, stream, rows, n, Wp,
+                           Wp, minsup, pairs, cap, n_pairs, (uint32_t *)nullptr);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_root_pairs, dim3((uint32_t)tiles, (uint32_t)splits), dim3(kBlock), 0, stream, rows,
+                       n, Wp, chunk, minsup, pairs, cap, n_pairs, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_root_finish, dim3((uint32_t)tiles), dim3(kBlock), 0, stream, part,
+                       (uint32_t)splits, n, minsup, pairs, cap, n_pairs);
     return hipGetLastError();
 }
 

@@ -1029,6 +1029,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
     // several instances: their root work spread over the side streams so
     // that the small kernels of different instances overlap (joined below)
     HIPCHK(fork());
+    DevBuf d_rsplit(ctx);
     tr.mark("  (events)");
     for (uint32_t q = 0; q < n_inst; q++) {
         Inst &I = insts[q];
@@ -1166,10 +1167,14 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             HIPCHK(hipMemcpyAsync(I.nz_cnt.data(), I.d_nz_cnt.as<void>(), (size_t)n * 4,
                                   hipMemcpyDeviceToHost, sq));
         } else {
+            // word-range split scratch: one slice per stream, sized once
+            ENSURE(d_rsplit, ctx, root_pairs_scratch_words() * n_lanes * 4);
             HIPCHK(hipEventRecord(rev[2 * q], sq));
             HIPCHK(launch_root_pairs(I.d_rows.as<uint32_t>(), I.n_freq, I.Wp, I.minsup,
                                      I.d_pairs.as<uint32_t>(), cap,
-                                     I.d_npairs.as<unsigned long long>(), sq));
+                                     I.d_npairs.as<unsigned long long>(),
+                                     d_rsplit.as<uint32_t>() + (q % n_lanes) * root_pairs_scratch_words(),
+                                     sq));
             HIPCHK(hipEventRecord(rev[2 * q + 1], sq));
         }
         HIPCHK(hipMemcpyAsync(h_small.as<unsigned long long>() + 2 * q, I.d_npairs.as<void>(), 8,
@@ -1225,7 +1230,8 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             else
                 HIPCHK(launch_root_pairs(I.d_rows.as<uint32_t>(), I.n_freq, I.Wp, I.minsup,
                                          I.d_pairs.as<uint32_t>(), I.n_pairs,
-                                         I.d_npairs.as<unsigned long long>(), s));
+                                         I.d_npairs.as<unsigned long long>(),
+                                         d_rsplit.bytes() ? d_rsplit.as<uint32_t>() : nullptr, s));
             I.st.retries++;
         }
         if (I.n_pairs)

@@ -163,6 +163,7 @@ def test_options_invariance(fim, ctx):
     (20000, 800, 10.0, 40),   # sparse rows: covers or projected transactions by default
     (9000, 300, 25.0, 60),    # denser rows
     (40000, 20000, 6.0, 4),   # more frequent items than one LDS tile of counters
+    (60000, 150, 8.0, 300),   # few row tiles over long rows: whole-row words split over blocks
 ])
 def test_root_kernels_agree(fim, ctx, n_tx, n_items, mlen, minsup):
     # the three exact root-class kernels, forced in turn and by default,
