@@ -1031,11 +1031,14 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
     HIPCHK(fork());
     DevBuf d_rsplit(ctx);
     tr.mark("  (events)");
+    // item ranks of every instance (independent host work, so several
+    // instances are ranked on several threads)
+    parallel_for(n_inst, n_inst > 1 ? host_threads(count_at[n_inst]) : 1u,
+                 [&](uint64_t q) { rank_items(insts[q], by_id); });
+    tr.mark("  (ranks)");
     for (uint32_t q = 0; q < n_inst; q++) {
         Inst &I = insts[q];
         const hipStream_t sq = side.empty() ? s : side[q % side.size()];
-        rank_items(I, by_id);
-        tr.mark("  (ranks)");
         I.W = (uint32_t)((I.db->n_tx + 31) / 32);
         I.Wp = std::max<uint32_t>(kRowAlign, (I.W + kRowAlign - 1) / kRowAlign * kRowAlign);
         I.st.item_supports = I.db->n_item_ids;
