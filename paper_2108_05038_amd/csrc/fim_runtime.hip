@@ -497,6 +497,7 @@ struct Inst {
     std::vector<uint32_t> l2_off, l2_atom, l2_supp;
     DevBuf d_counts, d_rank_of_item, d_item_of_rank, d_rows, d_pairs, d_npairs;
     DevBuf d_l2_off, d_l2_atom, d_l2_supp;
+    bool l2_on_device = false;  // the l2 arrays above hold l2_off, l2_atom, l2_supp
     // root-class kernel: 0 whole rows, 1 covers, 2 projected transactions
     uint32_t root_kind = 0;
     // covers: non-zero words per row and the transposed arena
@@ -1331,19 +1332,25 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         if (opts.flags & (FIM_FLAG_RESERVOIR | FIM_FLAG_NO_ESTIMATE)) {
             ps = plan_tasks(ctx, pin, opts, n_workers, tasks, nullptr, &est_out_words);
         } else {
-            // l2 arrays on the device for the sample's persistent run
-            for (Inst &I : insts) {
-                if (I.l2_atom.empty()) continue;
+            // l2 arrays on the device for the sample's persistent run (only
+            // the instances that draw a sample; kept for the main run)
+            bool any_estimate = false;
+            for (uint32_t q = 0; q < n_inst; q++) {
+                Inst &I = insts[q];
+                if (!pin[q].estimate || I.l2_atom.empty()) continue;
+                any_estimate = true;
                 ENSURE(I.d_l2_off, ctx, I.l2_off.size() * 4);
                 ENSURE(I.d_l2_atom, ctx, I.l2_atom.size() * 4);
                 ENSURE(I.d_l2_supp, ctx, I.l2_supp.size() * 4);
                 HIPCHK(h2d(ctx, I.d_l2_off.as<void>(), I.l2_off.data(), I.l2_off.size() * 4, s));
                 HIPCHK(h2d(ctx, I.d_l2_atom.as<void>(), I.l2_atom.data(), I.l2_atom.size() * 4, s));
                 HIPCHK(h2d(ctx, I.d_l2_supp.as<void>(), I.l2_supp.data(), I.l2_supp.size() * 4, s));
+                I.l2_on_device = true;
             }
-            std::vector<std::vector<double>> row_w;
+            // no sample drawn: every instance planned by the proxy
+            std::vector<std::vector<double>> row_w(n_inst);
             uint64_t sample_words = 0;
-            ps = count_estimate(ctx, s, tr, insts, pin, opts, row_w, sample_words);
+            if (any_estimate) ps = count_estimate(ctx, s, tr, insts, pin, opts, row_w, sample_words);
             if (ps != FIM_OK) return ps;
             // the sample has about as many frequent itemsets as the database
             // at the same relative support: room for twice its records
@@ -1398,7 +1405,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         uint64_t frame0 = 0;
         for (uint32_t q = 0; q < n_inst; q++) {
             Inst &I = insts[q];
-            if (!I.l2_atom.empty()) {
+            if (!I.l2_atom.empty() && !I.l2_on_device) {
                 ENSURE(I.d_l2_off, ctx, I.l2_off.size() * 4);
                 ENSURE(I.d_l2_atom, ctx, I.l2_atom.size() * 4);
                 ENSURE(I.d_l2_supp, ctx, I.l2_supp.size() * 4);
