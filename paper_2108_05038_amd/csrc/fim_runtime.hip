@@ -1400,25 +1400,52 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         while ((uint64_t)insts[q].db->n_item_ids >> bits_of[q]) bits_of[q]++;
     bool keys_done = false;
     std::vector<PrefixSrc> key_prefix;  // sources of the 1- and 2-itemsets' records
+    // the packed second-level arrays (below) live until the call has waited
+    // for its stream
+    DevBuf d_l2_all(ctx);
+    std::unique_ptr<PinnedBlock> h_l2;
     if (deep && !tasks.empty()) {
         std::vector<InstDesc> desc(n_inst);
         uint64_t frame0 = 0;
+        // second-level arrays (l2_off, l2_atom, l2_supp) of the instances not
+        // on the device yet, packed into one page-locked block, one copy
+        std::vector<uint64_t> l2_at(n_inst, ~0ull);
+        uint64_t l2_words = 0;
+        for (uint32_t q = 0; q < n_inst; q++) {
+            const Inst &I = insts[q];
+            if (I.l2_atom.empty() || I.l2_on_device) continue;
+            l2_at[q] = l2_words;
+            l2_words += I.l2_off.size() + 2 * I.l2_atom.size();
+        }
+        if (l2_words) {
+            ENSURE(d_l2_all, ctx, l2_words * 4);
+            h_l2.reset(new PinnedBlock(l2_words * 4));
+            uint32_t *h = h_l2->as<uint32_t>();
+            parallel_for(n_inst, host_threads(l2_words), [&](uint64_t q) {
+                if (l2_at[q] == ~0ull) return;
+                const Inst &I = insts[q];
+                uint32_t *d = h + l2_at[q];
+                memcpy(d, I.l2_off.data(), I.l2_off.size() * 4);
+                memcpy(d + I.l2_off.size(), I.l2_atom.data(), I.l2_atom.size() * 4);
+                memcpy(d + I.l2_off.size() + I.l2_atom.size(), I.l2_supp.data(), I.l2_supp.size() * 4);
+            });
+            HIPCHK(hipMemcpyAsync(d_l2_all.as<void>(), h, l2_words * 4, hipMemcpyHostToDevice, s));
+        }
         for (uint32_t q = 0; q < n_inst; q++) {
             Inst &I = insts[q];
-            if (!I.l2_atom.empty() && !I.l2_on_device) {
-                ENSURE(I.d_l2_off, ctx, I.l2_off.size() * 4);
-                ENSURE(I.d_l2_atom, ctx, I.l2_atom.size() * 4);
-                ENSURE(I.d_l2_supp, ctx, I.l2_supp.size() * 4);
-                HIPCHK(h2d(ctx, I.d_l2_off.as<void>(), I.l2_off.data(), I.l2_off.size() * 4, s));
-                HIPCHK(h2d(ctx, I.d_l2_atom.as<void>(), I.l2_atom.data(), I.l2_atom.size() * 4, s));
-                HIPCHK(h2d(ctx, I.d_l2_supp.as<void>(), I.l2_supp.data(), I.l2_supp.size() * 4, s));
-            }
             InstDesc &D = desc[q];
             D.rows = I.d_rows.as<uint32_t>();
             D.item_of_rank = I.d_item_of_rank.as<uint32_t>();
-            D.l2_off = I.d_l2_off.as<uint32_t>();
-            D.l2_atom = I.d_l2_atom.as<uint32_t>();
-            D.l2_supp = I.d_l2_supp.as<uint32_t>();
+            if (l2_at[q] != ~0ull) {
+                const uint32_t *b = d_l2_all.as<uint32_t>() + l2_at[q];
+                D.l2_off = b;
+                D.l2_atom = b + I.l2_off.size();
+                D.l2_supp = b + I.l2_off.size() + I.l2_atom.size();
+            } else {
+                D.l2_off = I.d_l2_off.as<uint32_t>();
+                D.l2_atom = I.d_l2_atom.as<uint32_t>();
+                D.l2_supp = I.d_l2_supp.as<uint32_t>();
+            }
             D.Wp = I.Wp;
             D.n_freq = I.n_freq;
             D.minsup = I.minsup;
