@@ -97,6 +97,16 @@ class DevBuf {
 // The context's side streams (created on first use).
 hipError_t ctx_side_streams(fim_ctx *ctx, std::vector<hipStream_t> &out);
 
+// Several host pieces copied to consecutive places of dst, each piece's
+// place starting at the sum of the earlier pieces' sizes rounded up to 8
+// bytes: one copy through the context's staging when it has room (else one
+// plain copy per piece); src may be reused as soon as this returns.
+struct H2DPiece {
+    const void *src;
+    size_t bytes;
+};
+hipError_t h2d_pieces(fim_ctx *ctx, void *dst, const H2DPiece *pieces, size_t n, hipStream_t s);
+
 // Host-to-device copy of `bytes` from src to dst, queued on s through the
 // context's page-locked staging (src may be reused as soon as this returns;
 // the copy does not wait for the stream); a plain copy when the staging of

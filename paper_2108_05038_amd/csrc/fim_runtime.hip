@@ -278,6 +278,33 @@ hipError_t h2d(fim_ctx *ctx, void *dst, const void *src, size_t bytes, hipStream
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
 }
 
+hipError_t h2d_pieces(fim_ctx *ctx, void *dst, const H2DPiece *pieces, size_t n, hipStream_t s) {
+    size_t total = 0;
+    for (size_t i = 0; i < n; i++) total += (pieces[i].bytes + 7) & ~size_t(7);
+    if (total == 0) return hipSuccess;
+    const size_t b = (total + 255) & ~size_t(255);
+    ctx->up_need += b;
+    size_t at = 0;
+    if (ctx->up && ctx->up_used + b <= ctx->up_cap) {
+        char *p = ctx->up + ctx->up_used;
+        ctx->up_used += b;
+        for (size_t i = 0; i < n; i++) {
+            if (pieces[i].bytes) memcpy(p + at, pieces[i].src, pieces[i].bytes);
+            at += (pieces[i].bytes + 7) & ~size_t(7);
+        }
+        return hipMemcpyAsync(dst, p, total, hipMemcpyHostToDevice, s);
+    }
+    for (size_t i = 0; i < n; i++) {
+        if (pieces[i].bytes) {
+            const hipError_t e = hipMemcpyAsync(static_cast<char *>(dst) + at, pieces[i].src, pieces[i].bytes,
+                                                hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) return e;
+        }
+        at += (pieces[i].bytes + 7) & ~size_t(7);
+    }
+    return hipSuccess;
+}
+
 hipError_t stream_wait(hipStream_t s) {
     const auto t0 = std::chrono::steady_clock::now();
     for (uint32_t k = 0;; k++) {
@@ -291,7 +318,9 @@ hipError_t stream_wait(hipStream_t s) {
 StageRun::StageRun(fim_ctx *ctx) : ctx_(ctx) {
     if (ctx_->up_depth++ > 0) return;
     // copies of an earlier run that ended early may still read the staging
+    // (from the call's stream or from its side streams)
     (void)hipStreamSynchronize(ctx_->stream);
+    for (hipStream_t x : ctx_->side_streams) (void)hipStreamSynchronize(x);
     if (ctx_->up_need > ctx_->up_cap) {
         if (ctx_->up) (void)hipHostFree(ctx_->up);
         ctx_->up = nullptr;
@@ -495,7 +524,7 @@ struct Inst {
     std::vector<uint32_t> pairs;  // triples (i, j, support)
     uint64_t n_pairs = 0;
     std::vector<uint32_t> l2_off, l2_atom, l2_supp;
-    DevBuf d_counts, d_rank_of_item, d_item_of_rank, d_rows, d_pairs, d_npairs;
+    DevBuf d_counts, d_rank_of_item, d_rows, d_pairs, d_npairs;
     DevBuf d_l2_off, d_l2_atom, d_l2_supp;
     bool l2_on_device = false;  // the l2 arrays above hold l2_off, l2_atom, l2_supp
     // root-class kernel: 0 whole rows, 1 covers, 2 projected transactions
@@ -507,7 +536,11 @@ struct Inst {
     // projected: ranked transactions, tid lists and the lists' pointers into
     // the ranked transactions, pair increments
     std::vector<uint64_t> tl_off;
-    DevBuf d_rk, d_tlp, d_suf, d_tl, d_tl_off, d_rowpre, d_work;
+    DevBuf d_rk, d_tlp, d_suf, d_tl, d_rowpre, d_work;
+    // inside d_rank_of_item (one upload): item_of_rank and tl_off
+    uint32_t *p_item_of_rank = nullptr;
+    uint64_t *p_tl_off = nullptr;
+    bool lists_built = false;  // d_tl holds the transaction lists
     unsigned long long project_work = 0;
     fim_stats st{};
     uint64_t first_class_rows = 0;  // sum of atoms over first-level classes with >= 2 atoms
@@ -864,7 +897,7 @@ static fim_status count_estimate(fim_ctx *ctx, hipStream_t s, Tracer &tr, std::v
                                    I.d_rank_of_item.as<uint32_t>(), s_rows[q].as<uint32_t>(), Wps, s));
         InstDesc &D = desc[q];
         D.rows = s_rows[q].as<uint32_t>();
-        D.item_of_rank = I.d_item_of_rank.as<uint32_t>();
+        D.item_of_rank = I.p_item_of_rank;
         D.l2_off = I.d_l2_off.as<uint32_t>();
         D.l2_atom = I.d_l2_atom.as<uint32_t>();
         D.l2_supp = I.d_l2_supp.as<uint32_t>();
@@ -1046,13 +1079,22 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         I.st.n_frequent_items = I.n_freq;
         if (I.n_freq == 0) continue;
         const uint32_t ni = I.db->n_item_ids;
-        ENSURE(I.d_rank_of_item, ctx, (size_t)ni * 4);
-        ENSURE(I.d_item_of_rank, ctx, (size_t)I.n_freq * 4);
-        ENSURE(I.d_rows, ctx, (size_t)I.n_freq * I.Wp * 4);
-        HIPCHK(h2d(ctx, I.d_rank_of_item.as<void>(), I.rank_of_item.data(), (size_t)ni * 4, sq));
-        HIPCHK(h2d(ctx, I.d_item_of_rank.as<void>(), I.item_of_rank.data(), (size_t)I.n_freq * 4, sq));
-        tr.mark("  (rank uploads)");
         const uint32_t n = I.n_freq;
+        // offsets of the ranks' transaction lists (used if lists are built)
+        I.tl_off.assign(n + 1, 0);
+        for (uint32_t r = 0; r < n; r++) I.tl_off[r + 1] = I.tl_off[r] + I.supp_of_rank[r];
+        // rank_of_item, item_of_rank and tl_off in one device block, one copy
+        const size_t b_rank = ((size_t)ni * 4 + 7) & ~size_t(7);
+        const size_t b_item = ((size_t)n * 4 + 7) & ~size_t(7);
+        ENSURE(I.d_rank_of_item, ctx, b_rank + b_item + (size_t)(n + 1) * 8);
+        ENSURE(I.d_rows, ctx, (size_t)I.n_freq * I.Wp * 4);
+        I.p_item_of_rank = reinterpret_cast<uint32_t *>(I.d_rank_of_item.as<char>() + b_rank);
+        I.p_tl_off = reinterpret_cast<uint64_t *>(I.d_rank_of_item.as<char>() + b_rank + b_item);
+        const H2DPiece up[3] = {{I.rank_of_item.data(), (size_t)ni * 4},
+                                {I.item_of_rank.data(), (size_t)n * 4},
+                                {I.tl_off.data(), (size_t)(n + 1) * 8}};
+        HIPCHK(h2d_pieces(ctx, I.d_rank_of_item.as<void>(), up, 3, sq));
+        tr.mark("  (rank uploads)");
         // positions in the ranked transactions are 32-bit, ranks and suffix
         // lengths 16-bit
         const bool fits = I.db->nnz + I.db->n_tx + 8 < (1ull << 32) && I.db->max_tx_len < (1u << 16) &&
@@ -1104,14 +1146,11 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                             (opts.max_len == 0 || opts.max_len >= 3) &&
                             4ull * min_supp <= I.db->n_tx && I.db->n_tx < (1ull << 32));
         if (lists) {
-            I.tl_off.assign(n + 1, 0);
-            for (uint32_t r = 0; r < n; r++) I.tl_off[r + 1] = I.tl_off[r] + I.supp_of_rank[r];
+            I.lists_built = true;
             ENSURE(I.d_tl, ctx, std::max<uint64_t>(I.tl_off[n], 1) * 4);
-            ENSURE(I.d_tl_off, ctx, (n + 1) * 8);
-            HIPCHK(h2d(ctx, I.d_tl_off.as<void>(), I.tl_off.data(), (n + 1) * 8, sq));
             const bool ranked = I.root_kind == 2 && pairs_needed;
             if (ranked) ENSURE(I.d_rowpre, ctx, (uint64_t)n * rowpre_words(I.Wp) * 4);
-            HIPCHK(launch_tidlist(I.d_rows.as<uint32_t>(), n, I.Wp, I.d_tl_off.as<uint64_t>(),
+            HIPCHK(launch_tidlist(I.d_rows.as<uint32_t>(), n, I.Wp, I.p_tl_off,
                                   I.d_tl.as<uint32_t>(), ranked ? I.d_rowpre.as<uint32_t>() : nullptr, sq));
             if (ranked) {
                 ENSURE(I.d_rk, ctx, (I.db->nnz + I.db->n_tx + 8) * 2);
@@ -1120,7 +1159,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                 HIPCHK(launch_rank_tx(I.db->d_off.as<uint64_t>(), I.db->d_items.as<uint32_t>(),
                                       I.db->n_tx, I.d_rank_of_item.as<uint32_t>(),
                                       I.d_rows.as<uint32_t>(), I.Wp, I.d_rowpre.as<uint32_t>(),
-                                      I.d_tl_off.as<uint64_t>(), I.d_rk.as<uint16_t>(),
+                                      I.p_tl_off, I.d_rk.as<uint16_t>(),
                                       I.d_tlp.as<uint32_t>(), I.d_suf.as<uint16_t>(), sq));
             }
         }
@@ -1136,7 +1175,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             HIPCHK(launch_fill_u32(I.d_work.as<uint32_t>(), 2, 0u, sq));
             HIPCHK(hipEventRecord(rev[2 * q], sq));
             HIPCHK(launch_root_project(I.d_rk.as<uint16_t>(), I.d_tlp.as<uint32_t>(),
-                                       I.d_suf.as<uint16_t>(), I.d_tl_off.as<uint64_t>(), n,
+                                       I.d_suf.as<uint16_t>(), I.p_tl_off, n,
                                        max_supp_of(I), I.minsup,
                                        I.d_pairs.as<uint32_t>(), cap,
                                        I.d_npairs.as<unsigned long long>(),
@@ -1220,7 +1259,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             HIPCHK(launch_fill_u32(I.d_npairs.as<uint32_t>(), 2, 0u, s));
             if (I.root_kind == 2)
                 HIPCHK(launch_root_project(I.d_rk.as<uint16_t>(), I.d_tlp.as<uint32_t>(),
-                                           I.d_suf.as<uint16_t>(), I.d_tl_off.as<uint64_t>(),
+                                           I.d_suf.as<uint16_t>(), I.p_tl_off,
                                            I.n_freq, max_supp_of(I), I.minsup,
                                            I.d_pairs.as<uint32_t>(), I.n_pairs,
                                            I.d_npairs.as<unsigned long long>(),
@@ -1435,7 +1474,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             Inst &I = insts[q];
             InstDesc &D = desc[q];
             D.rows = I.d_rows.as<uint32_t>();
-            D.item_of_rank = I.d_item_of_rank.as<uint32_t>();
+            D.item_of_rank = I.p_item_of_rank;
             if (l2_at[q] != ~0ull) {
                 const uint32_t *b = d_l2_all.as<uint32_t>() + l2_at[q];
                 D.l2_off = b;
@@ -1452,9 +1491,9 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             D.max_len = opts.max_len;
             D.order_by_id = by_id ? 1u : 0u;
             D.project = (opts.flags & FIM_FLAG_NO_PROJECT) ? 0u : 1u;
-            const bool lists = D.project && !I.tl_off.empty();
+            const bool lists = D.project && I.lists_built;
             D.tl = lists ? I.d_tl.as<uint32_t>() : nullptr;
-            D.tl_off = lists ? I.d_tl_off.as<uint64_t>() : nullptr;
+            D.tl_off = lists ? I.p_tl_off : nullptr;
             // A sample drawn with replacement at a small scaled support can
             // make every subset of a repeatedly drawn long transaction
             // frequent; its search is abandoned past a fixed budget (the
@@ -1497,7 +1536,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                 const Inst &I = insts[q];
                 const uint64_t np = opts.max_len != 1 ? I.n_pairs : 0;
                 if (I.n_freq + np == 0) continue;
-                key_prefix.push_back(PrefixSrc{I.d_item_of_rank.as<uint32_t>(), I.d_counts.as<uint32_t>(),
+                key_prefix.push_back(PrefixSrc{I.p_item_of_rank, I.d_counts.as<uint32_t>(),
                                                np ? I.d_pairs.as<uint32_t>() : nullptr, I.n_freq,
                                                bits_of[q], q, 0u, np, at});
                 at += I.n_freq + np;
