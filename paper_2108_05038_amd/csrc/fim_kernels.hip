@@ -1776,7 +1776,7 @@ __device__ __forceinline__ void flush_stats(const InstDesc &I, InstCounters *ict
 }
 
 template <int CPL>
-__global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Task *tasks,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(CPL == 4 ? 2 : 1))) void k_dfs(const InstDesc *insts, const Task *tasks,
                                                 uint64_t n_tasks, uint32_t *stack,
                                                 uint64_t stack_words, uint32_t tasks_per_claim,
                                                 uint32_t *out, uint64_t out_cap,
