@@ -40,6 +40,7 @@ import os
 import sys
 import time
 
+T_START = time.perf_counter()
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -47,12 +48,8 @@ METRIC = "candidate supports/s + HBM GB/s; served p50/p99 latency, batched vs pl
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: 32-bit integer VALU operations per second
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
-# bytes per launch measured with rocprofv3 (profiles/<kernel>.<workload>.txt)
-MEASURED_TRAFFIC = {
-    ("k_root_project", "sparse-200k"): (344.7 + 0.4) * 1e6,
-    ("k_dfs", "sparse-200k"): (131.9 + 2.7) * 1e6,
-    ("k_dfs", "dense-50k"): (20795.4 + 8993.4) * 1e6,
-}
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SRC = os.path.join(ROOT, "paper_2108_05038_amd", "csrc", "fim_kernels.hip")
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
@@ -71,9 +68,134 @@ def digest(r) -> str:
     return h.hexdigest()
 
 
+def kernel_source_sha() -> str:
+    """SHA-256 (first 16 hex digits) of the kernel source file: a profile's
+    counters describe the kernels only while this matches the value the
+    profile records."""
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the rocprofv3
+    counter summary ``profiles/<kernel>.<workload>.txt`` (FETCH_SIZE and
+    WRITE_SIZE scaled by the plain-copy calibration), or None when there is
+    no summary or it was taken with other kernel sources."""
+    p = os.path.join(PROFILES, "%s.%s.txt" % (kernel, workload))
+    if not os.path.exists(p):
+        return None
+    sha, traffic = None, None
+    for line in open(p):
+        if line.startswith("kernel_source_sha256_16:"):
+            sha = line.split(":", 1)[1].strip()
+        if line.startswith("hbm_bytes_per_launch:"):
+            traffic = float(line.split(":", 1)[1].strip())
+    return traffic if sha == kernel_source_sha() else None
+
+
 def load_golden(name):
     p = os.path.join(GOLDEN, name)
     return json.load(open(p)) if os.path.exists(p) else None
+
+
+# ---------------------------------------------------------------- one workload, whole calls
+
+def mine_leg(F, ctx, db, workload, steps, warmup, flags, estimate_leg=False):
+    """Times `steps` whole ``fim_mine`` calls over the resident database and
+    describes the dominant kernel against its roofline (HIP-event times the
+    library records on the stream it launches on)."""
+    import numpy as np
+    import torch
+    # the upload (validation, set semantics, host-to-device copy) is outside
+    # the timed loop; timed here for the host-inclusive rate
+    upload_ms = None
+    for _ in range(2):
+        t_up = time.perf_counter()
+        d = F.Database(ctx, db.offsets, db.items, db.n_items)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t_up) * 1e3
+        upload_ms = ms if upload_ms is None else min(upload_ms, ms)
+        if _ == 0:
+            d.close()
+    log("%s: database upload %.2f ms" % (workload, upload_ms))
+    gold = load_golden("%s.json" % workload)
+    verified = None
+    for i in range(warmup):
+        r = F.mine(ctx, d, db.minsup, flags=flags)
+        if i == 0 and gold is not None:
+            verified = (digest(r) == gold["digest"]
+                        and r.stats["candidates"] == gold["candidates_ascending_support"])
+            log("%s: warm-up result matches the oracle's golden digest: %s" % (workload, verified))
+    torch.cuda.synchronize()
+    stats, ends = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = F.mine(ctx, d, db.minsup, flags=flags)
+        stats.append(r.stats)
+        ends.append(time.perf_counter())
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    step_ms = np.diff([t0] + ends) * 1e3  # per call (each call returns a finished result)
+    log("%s: %.3f ms/step" % (workload, dt * 1e3))
+    est_leg = None
+    if estimate_leg:
+        # The same step with the sample-based class-size estimate forced (the
+        # library draws it by default only where it pays): the cost of that
+        # row of the path where the default policy replaces it.
+        est_steps = max(3, steps // 4)
+        re_ = F.mine(ctx, d, db.minsup, flags=flags | F.FIM_FLAG_ALWAYS_ESTIMATE)
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        for _ in range(est_steps):
+            re_ = F.mine(ctx, d, db.minsup, flags=flags | F.FIM_FLAG_ALWAYS_ESTIMATE)
+        torch.cuda.synchronize()
+        est_leg = {"ms_per_step": (time.perf_counter() - te) / est_steps * 1e3, "steps": est_steps,
+                   "estimate_ms": re_.stats["estimate_ns"] / 1e6,
+                   "dfs_ms": re_.stats["dfs_kernel_ns"] / 1e6,
+                   "candidates": re_.stats["candidates"],
+                   "verified_vs_oracle": (digest(re_) == gold["digest"]) if gold else None}
+        del re_
+        log("%s: with the sample estimate forced %.3f ms/step" % (workload, est_leg["ms_per_step"]))
+    d.close()
+    st = stats[-1]
+    root_ns = float(np.mean([s_["root_kernel_ns"] for s_ in stats]))
+    dfs_ns = float(np.mean([s_["dfs_kernel_ns"] for s_ in stats]))
+    root_name = ("k_root_pairs", "k_root_sparse", "k_root_project")[st["root_kernel"]]
+    dfs_bytes = st["dfs_bytes_algorithmic"]
+    root_bytes = st["bytes_algorithmic"] - dfs_bytes
+    dfs_gbs = dfs_bytes / dfs_ns if dfs_ns else 0.0
+    if st["root_kernel"] == 0:
+        # whole rows: two integer operations (AND, popcount-add) per pair-word
+        root_ops = 2.0 * st["root_pair_words"]
+        root_k = {"ms": root_ns / 1e6, "bound": "alu",
+                  "achieved": root_ops / root_ns / 1e3 if root_ns else 0.0,
+                  "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "algorithmic": root_ops}
+    else:
+        # covers / projected transactions: the bytes the kernel must read
+        root_k = {"ms": root_ns / 1e6, "bound": "hbm",
+                  "achieved": root_bytes / root_ns if root_ns else 0.0,
+                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "algorithmic": root_bytes}
+    root_k["frac"] = root_k["achieved"] / root_k["peak"]
+    dfs_k = {"ms": dfs_ns / 1e6, "bound": "hbm", "achieved": dfs_gbs, "peak": HBM_PEAK_GBS,
+             "unit": "GB/s", "frac": dfs_gbs / HBM_PEAK_GBS, "algorithmic": dfs_bytes}
+    kernels = {root_name: root_k, "k_dfs": dfs_k}
+    name, k = (root_name, root_k) if root_ns >= dfs_ns else ("k_dfs", dfs_k)
+    for kn, kk in kernels.items():
+        kk["traffic"] = measured_traffic(kn, workload)
+    roofline = {"kernel": name, "bound": k["bound"], "achieved": k["achieved"], "peak": k["peak"],
+                "unit": k["unit"], "frac": k["frac"], "traffic": k["traffic"],
+                "traffic_GBs": k["traffic"] / (k["ms"] * 1e6) if k["traffic"] else None}
+    return {
+        "workload": workload, "n_tx": db.n_tx, "n_items": db.n_items, "minsup": db.minsup,
+        "steps": steps, "warmup": warmup, "ms_per_step": dt * 1e3,
+        "ms_per_step_min_median_max": [float(step_ms.min()), float(np.median(step_ms)),
+                                       float(step_ms.max())],
+        "value": st["candidates"] / dt, "unit": "candidate supports/s",
+        "n_itemsets": st["n_itemsets"], "candidates": st["candidates"],
+        "upload_ms": upload_ms, "with_sample_estimate": est_leg,
+        "roofline": roofline, "kernels": kernels, "verified_vs_oracle": verified,
+        "stats": st, "result": r,
+    }
 
 
 # ---------------------------------------------------------------- batched leg
@@ -172,7 +294,35 @@ def _stats(lat, censored, seconds, done):
             "throughput_rps": done / seconds}
 
 
-def serve_served(F, ctx, handles, minsups, arr, idx, seconds, lanes, first):
+class Checker:
+    """Checks served results against the oracle's stored values: every
+    result's itemset and candidate counts (cheap enough for the serving
+    loop), and the full digest of the first result of each pool request."""
+
+    def __init__(self, gold):
+        self.gold = gold
+        self.first = {}
+        self.checked = 0
+        self.bad = []
+
+    def __call__(self, k, r):
+        if self.gold is None:
+            return
+        e = self.gold["instances"][k]
+        self.checked += 1
+        if len(r) != e["n_itemsets"] or r.stats["candidates"] != e["candidates_ascending_support"]:
+            self.bad.append(k)
+        self.first.setdefault(int(k), r)
+
+    def digests(self):
+        if self.gold is None:
+            return None
+        bad = [k for k, r in self.first.items() if self.gold["instances"][k]["digest"] != digest(r)]
+        self.first = {k: None for k in self.first}
+        return bad
+
+
+def serve_served(F, ctx, handles, minsups, arr, idx, seconds, lanes, check):
     srv = F.Server(ctx, lanes=lanes)
     deadline = 2 * seconds + 10
     pending, lat = {}, []
@@ -191,7 +341,7 @@ def serve_served(F, ctx, handles, minsups, arr, idx, seconds, lanes, first):
         if t:
             q = pending.pop(t)
             lat.append(time.perf_counter() - t0 - arr[q])
-            first.setdefault(int(idx[q]), r)
+            check(int(idx[q]), r)
     end = time.perf_counter() - t0
     # requests still open at the deadline count with their waiting time so
     # far (a lower bound), so that overload shows in the percentiles
@@ -199,13 +349,14 @@ def serve_served(F, ctx, handles, minsups, arr, idx, seconds, lanes, first):
     lat += [end - arr[q] for q in pending.values()] + [end - a for a in arr[k:]]
     for t in pending:
         srv.cancel(t)
+    st = srv.stats()
     srv.close()
     out = _stats(lat, censored, max(seconds, end), n - censored)
-    out["server"] = {"lanes": lanes}
+    out["server"] = {"lanes": st["lanes"], "steps": st["steps"], "peak_active": st["peak_active"]}
     return out
 
 
-def serve_plain(F, ctx, handles, minsups, arr, idx, seconds):
+def serve_plain(F, ctx, handles, minsups, arr, idx, seconds, check):
     deadline = 2 * seconds + 10
     lat = []
     t0 = time.perf_counter()
@@ -216,15 +367,17 @@ def serve_plain(F, ctx, handles, minsups, arr, idx, seconds):
             break
         if arr[k] > now:
             time.sleep(arr[k] - now)
-        F.mine(ctx, handles[idx[k]], minsups[idx[k]])
+        r = F.mine(ctx, handles[idx[k]], minsups[idx[k]])
         lat.append(time.perf_counter() - t0 - arr[k])
+        check(int(idx[k]), r)
+        del r
     end = time.perf_counter() - t0
     done = len(lat)
     lat += [end - a for a in arr[done:]]  # open at the deadline: lower bounds
     return _stats(lat, len(arr) - done, max(seconds, end), done)
 
 
-def serve_leg(F, ctx, args):
+def serve_leg(F, ctx, args, seconds):
     import synth
     g = load_golden("serve-pool.json")
     pool_n = args.serve_pool
@@ -243,21 +396,26 @@ def serve_leg(F, ctx, args):
     for k in range(min(8, pool_n)):
         F.mine(ctx, handles[k], minsups[k])
     rates = [float(x) for x in args.serve_rates.split(",") if x]
-    out = {"seconds": args.serve_seconds, "pool": pool_n, "rates": {}}
-    first = {}
+    out = {"seconds": seconds, "configured_seconds": 60.0, "pool": pool_n, "rates": {}}
+    check = Checker(g)
     for rate in rates:
-        arr, idx = _trace(rate, args.serve_seconds, pool_n)
-        log("served: %g req/s, %d requests ..." % (rate, len(arr)))
-        s = serve_served(F, ctx, handles, minsups, arr, idx, args.serve_seconds, args.lanes, first)
+        arr, idx = _trace(rate, seconds, pool_n)
+        t1 = time.perf_counter()
+        log("served: %g req/s for %.0f s, %d requests ..." % (rate, seconds, len(arr)))
+        s = serve_served(F, ctx, handles, minsups, arr, idx, seconds, args.lanes, check)
         log("served: continuous batching", s)
-        p = serve_plain(F, ctx, handles, minsups, arr, idx, args.serve_seconds)
+        p = serve_plain(F, ctx, handles, minsups, arr, idx, seconds, check)
         log("served: plain per request", p)
-        out["rates"]["%g" % rate] = {"requests": len(arr), "batched": s, "plain": p}
+        out["rates"]["%g" % rate] = {"requests": len(arr), "batched": s, "plain": p,
+                                     "wall_s": time.perf_counter() - t1}
+    bad = check.digests()
     if g:
-        bad = [k for k, r in first.items()
-               if g["instances"][k]["digest"] is not None and g["instances"][k]["digest"] != digest(r)]
-        out["verified_vs_oracle"] = not bad
-        out["verified_requests"] = len(first)
+        out["verified_vs_oracle"] = not bad and not check.bad
+        out["verified_requests"] = len(check.first)  # distinct pool requests, full digest
+        out["checked_results"] = check.checked       # every result: itemset and candidate counts
+        out["mismatches"] = sorted(set(bad) | set(check.bad))[:20]
+        log("served: %d distinct requests verified by digest, %d results by counts, %d bad"
+            % (len(check.first), check.checked, len(out["mismatches"])))
     for h in handles:
         h.close()
     ctx.release_cached()
@@ -306,6 +464,54 @@ def study(F, ctx, args):
     return out
 
 
+# ---------------------------------------------------------------- CPU baseline
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_leg(db, r, args):
+    """The oracle (plain Eclat over sorted tid-lists) on this host's cores:
+    the median of three runs on the full workload with up to 16 threads (the
+    host share of one GPU), and one single-thread run when the budget
+    leaves time for it."""
+    import numpy as np
+
+    import oracle
+    nproc = os.cpu_count() or 1
+    threads = max(1, min(args.cpu_threads, nproc))
+    log("timing the CPU oracle with %d threads (median of 3) ..." % threads)
+    walls, o = [], None
+    for _ in range(3):
+        c0 = time.perf_counter()
+        o = oracle.mine_db(db, threads=threads)
+        walls.append(time.perf_counter() - c0)
+    med = float(np.median(walls))
+    out = {"value": o.candidates / med, "unit": "candidate supports/s", "cores": threads,
+           "kind": "oracle", "nproc": nproc, "cpu_model": cpu_model(),
+           "sample": "the full %s workload, median of 3 runs (%d candidate pairs; %s s)"
+                     % (args.workload, o.candidates, ", ".join("%.2f" % w for w in walls)),
+           "matches_gpu": bool(o.digest() == digest(r)), "one_thread": None}
+    left = args.budget_s - (time.perf_counter() - T_START)
+    est1 = med * threads * 1.3  # a single thread takes about threads x as long
+    if args.cpu_one_thread and est1 < left - 20:
+        log("timing the CPU oracle with 1 thread (about %.0f s) ..." % est1)
+        c0 = time.perf_counter()
+        o1 = oracle.mine_db(db, threads=1)
+        w1 = time.perf_counter() - c0
+        out["one_thread"] = {"value": o1.candidates / w1, "seconds": w1, "runs": 1,
+                             "matches_gpu": bool(o1.digest() == digest(r))}
+    else:
+        log("CPU oracle, 1 thread: skipped (about %.0f s needed, %.0f s left)" % (est1, left))
+    return out
+
+
 # ---------------------------------------------------------------- main
 
 def main(argv=None):
@@ -322,9 +528,17 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=256, help="instances of the batched leg")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-rates", default="50,200", help="request rates (req/s)")
-    ap.add_argument("--serve-seconds", type=float, default=12.0)
-    ap.add_argument("--serve-pool", type=int, default=128, help="distinct requests (<= 512)")
+    ap.add_argument("--serve-rates", default="50,100,200,400", help="request rates (req/s)")
+    ap.add_argument("--serve-seconds", type=float, default=0.0,
+                    help="arrival window per rate and mode (0 = what the time budget leaves, "
+                         "at most 60 s)")
+    ap.add_argument("--serve-pool", type=int, default=512, help="distinct requests (<= 512)")
+    ap.add_argument("--no-dense", action="store_true", help="skip the dense-50k leg")
+    ap.add_argument("--dense-steps", type=int, default=10)
+    ap.add_argument("--budget-s", type=float, default=420.0,
+                    help="wall-clock budget of the whole run; the served leg and the "
+                         "single-thread CPU run are sized to stay inside it")
+    ap.add_argument("--no-cpu-one-thread", dest="cpu_one_thread", action="store_false")
     ap.add_argument("--lanes", type=int, default=0, help="server lanes (0 = default)")
     ap.add_argument("--study", action="store_true",
                     help="only run the estimator study and print its JSON line")
@@ -361,104 +575,29 @@ def main(argv=None):
         ctx.close()
         return 0
 
-    db = synth.make(args.workload)
     ctx = F.Context(0)
-    # the upload (validation, set semantics, host-to-device copy) is outside
-    # the timed loop; timed here for the host-inclusive rate
-    t_up = time.perf_counter()
-    d = F.Database(ctx, db.offsets, db.items, db.n_items)
-    torch.cuda.synchronize()
-    upload_ms = (time.perf_counter() - t_up) * 1e3
-    d.close()
-    t_up = time.perf_counter()
-    d = F.Database(ctx, db.offsets, db.items, db.n_items)
-    torch.cuda.synchronize()
-    upload_ms = min(upload_ms, (time.perf_counter() - t_up) * 1e3)
-    log("database upload: %.2f ms" % upload_ms)
-    gold = load_golden("%s.json" % args.workload)
-
-    verified = None
-    for i in range(args.warmup):
-        r = F.mine(ctx, d, db.minsup, flags=args.flags)
-        if i == 0 and gold is not None:
-            verified = (digest(r) == gold["digest"]
-                        and r.stats["candidates"] == gold["candidates_ascending_support"])
-            log("warmup result matches the oracle's golden digest:", verified)
-    torch.cuda.synchronize()
-    stats, ends = [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        r = F.mine(ctx, d, db.minsup, flags=args.flags)
-        stats.append(r.stats)
-        ends.append(time.perf_counter())
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    dt = (t1 - t0) / args.steps
-    step_ms = np.diff([t0] + ends) * 1e3  # per call (each call returns a finished result)
-    # The same step with the sample-based class-size estimate forced (the
-    # library draws it by default only for much longer databases): the cost
-    # of that row of the path where the default policy replaces it.
-    est_steps = max(3, args.steps // 4)
-    r = F.mine(ctx, d, db.minsup, flags=args.flags | F.FIM_FLAG_ALWAYS_ESTIMATE)
-    torch.cuda.synchronize()
-    te = time.perf_counter()
-    for _ in range(est_steps):
-        r = F.mine(ctx, d, db.minsup, flags=args.flags | F.FIM_FLAG_ALWAYS_ESTIMATE)
-    torch.cuda.synchronize()
-    est_leg = {"ms_per_step": (time.perf_counter() - te) / est_steps * 1e3, "steps": est_steps,
-               "estimate_ms": r.stats["estimate_ns"] / 1e6, "dfs_ms": r.stats["dfs_kernel_ns"] / 1e6,
-               "candidates": r.stats["candidates"]}
-    log("with the sample estimate forced: %.3f ms/step" % est_leg["ms_per_step"])
-    st = stats[-1]
-    cands = st["candidates"]
-    value = cands / dt
-    log("main leg: %.3f ms/step" % (dt * 1e3))
-
-    root_ns = float(np.mean([s["root_kernel_ns"] for s in stats]))
-    dfs_ns = float(np.mean([s["dfs_kernel_ns"] for s in stats]))
-    root_name = ("k_root_pairs", "k_root_sparse", "k_root_project")[st["root_kernel"]]
-    dfs_bytes = st["dfs_bytes_algorithmic"]
-    root_bytes = st["bytes_algorithmic"] - dfs_bytes
-    dfs_gbs = dfs_bytes / dfs_ns if dfs_ns else 0.0
-    if st["root_kernel"] == 0:
-        # whole rows: two integer operations (AND, popcount-add) per pair-word
-        root_ops = 2.0 * st["root_pair_words"]
-        root_k = {"ms": root_ns / 1e6, "bound": "alu", "achieved": root_ops / root_ns / 1e3 if root_ns else 0.0,
-                  "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "algorithmic": root_ops}
-    else:
-        # covers / projected transactions: the bytes the kernel must read
-        root_k = {"ms": root_ns / 1e6, "bound": "hbm", "achieved": root_bytes / root_ns if root_ns else 0.0,
-                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "algorithmic": root_bytes}
-    root_k["frac"] = root_k["achieved"] / root_k["peak"]
-    dfs_k = {"ms": dfs_ns / 1e6, "bound": "hbm", "achieved": dfs_gbs, "peak": HBM_PEAK_GBS,
-             "unit": "GB/s", "frac": dfs_gbs / HBM_PEAK_GBS, "algorithmic": dfs_bytes}
-    kernels = {root_name: root_k, "k_dfs": dfs_k}
-    name, k = (root_name, root_k) if root_ns >= dfs_ns else ("k_dfs", dfs_k)
-    # measured HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE,
-    # the copy calibration), from the summaries in profiles/ of this code
-    traffic = MEASURED_TRAFFIC.get((name, args.workload))
-    roofline = {"kernel": name, "bound": k["bound"], "achieved": k["achieved"], "peak": k["peak"],
-                "unit": k["unit"], "frac": k["frac"],
-                "traffic": traffic, "traffic_GBs": traffic / (k["ms"] * 1e6) if traffic else None}
-    d.close()
-
+    db = synth.make(args.workload)
+    main = mine_leg(F, ctx, db, args.workload, args.steps, args.warmup, args.flags,
+                    estimate_leg=True)
+    dense = None
+    if not args.no_dense and args.workload != "dense-50k":
+        dense = mine_leg(F, ctx, synth.make("dense-50k"), "dense-50k", args.dense_steps, 2, args.flags)
+        dense.pop("result", None)
+    r = main.pop("result")
+    st = main["stats"]
     batched = None if args.no_batch else batch_leg(F, ctx, args)
-    served = None if args.no_serve else serve_leg(F, ctx, args)
+    served = None
+    if not args.no_serve:
+        # the served leg gets the time left of the budget (the CPU baseline
+        # runs after it), at most the configuration's 60 s per rate and mode
+        n_rates = len([x for x in args.serve_rates.split(",") if x])
+        left = args.budget_s - (time.perf_counter() - T_START) - (0 if args.no_cpu else 90) - 40
+        secs = args.serve_seconds or max(10.0, min(60.0, left / max(1, 2 * n_rates)))
+        served = serve_leg(F, ctx, args, secs)
 
-    cpu = None
-    if not args.no_cpu:
-        import oracle
-        threads = max(1, min(args.cpu_threads, os.cpu_count() or 1))
-        log("timing the CPU oracle with %d threads ..." % threads)
-        c0 = time.perf_counter()
-        o = oracle.mine_db(db, threads=threads)
-        c1 = time.perf_counter()
-        cpu = {"value": o.candidates / (c1 - c0), "unit": "candidate supports/s",
-               "cores": threads, "kind": "oracle",
-               "sample": "the full %s workload, one run (%d candidate pairs, %.1f s)"
-                         % (args.workload, o.candidates, c1 - c0),
-               "matches_gpu": bool(o.digest() == digest(r))}
+    cpu = None if args.no_cpu else cpu_leg(db, r, args)
 
+    value = main["value"]
     out = {
         "metric": METRIC,
         "value": value,
@@ -466,11 +605,10 @@ def main(argv=None):
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt * 1e3,
-        "ms_per_step_min_median_max": [float(step_ms.min()), float(np.median(step_ms)),
-                                       float(step_ms.max())],
-        "upload_ms": upload_ms,
-        "with_sample_estimate": est_leg,
+        "ms_per_step": main["ms_per_step"],
+        "ms_per_step_min_median_max": main["ms_per_step_min_median_max"],
+        "upload_ms": main["upload_ms"],
+        "with_sample_estimate": main["with_sample_estimate"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -478,14 +616,16 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": args.workload, "n_tx": db.n_tx, "n_items": db.n_items,
                    "minsup": db.minsup, "n_itemsets": st["n_itemsets"],
-                   "candidates": cands, "parallelism": "single GPU"},
-        "roofline": roofline,
+                   "candidates": st["candidates"], "parallelism": "single GPU"},
+        "roofline": main["roofline"],
         "cpu_baseline": cpu,
-        "kernels": kernels,
-        "hbm_GBs_dfs": dfs_gbs,
-        "verified_vs_oracle": verified,
+        "kernels": main["kernels"],
+        "hbm_GBs_dfs": main["kernels"]["k_dfs"]["achieved"],
+        "verified_vs_oracle": main["verified_vs_oracle"],
+        "dense": None if dense is None else {k: v for k, v in dense.items() if k != "stats"},
         "batched": batched,
         "served": served,
+        "wall_s": time.perf_counter() - T_START,
     }
     print(json.dumps(out), flush=True)
     ctx.close()

@@ -421,6 +421,14 @@ typedef struct fim_server_config {
     fim_options opts;
 } fim_server_config;
 
+/*
+ * Server counters.
+ *  submitted, completed, cancelled  requests so far
+ *  steps        batched launches run (each mines the requests it admitted)
+ *  peak_active  most requests resident at once
+ *  peak_bytes   largest admitted footprint (bytes) held at once
+ *  lanes        lanes the server runs (the configured value or its default)
+ */
 typedef struct fim_server_stats {
     uint64_t submitted;
     uint64_t completed;
@@ -428,6 +436,7 @@ typedef struct fim_server_stats {
     uint64_t steps;
     uint64_t peak_active;
     uint64_t peak_bytes;
+    uint64_t lanes;
 } fim_server_stats;
 
 /*

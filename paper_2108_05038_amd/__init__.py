@@ -94,7 +94,7 @@ class fim_server_config(ctypes.Structure):
 
 class fim_server_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
-        "submitted", "completed", "cancelled", "steps", "peak_active", "peak_bytes")]
+        "submitted", "completed", "cancelled", "steps", "peak_active", "peak_bytes", "lanes")]
 
 
 _lib = None

@@ -186,6 +186,7 @@ extern "C" fim_status fim_server_create(fim_ctx *ctx, const fim_server_config *c
         if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = ctx->total_mem / 2;
         s->cfg.hbm_budget_bytes = fr / 4 * 3;
     }
+    s->stats.lanes = s->cfg.lanes;
     // lane 0 mines on the caller's context; the others on contexts of their
     // own (same device and allocator, a stream each)
     s->lanes.resize(s->cfg.lanes);

@@ -397,12 +397,16 @@ def test_autotune_settings_do_not_change_results(fim, ctx):
     t = fim.autotune(ctx, handles, ms, reps=1)
     assert t["tile_words"] in (256, 512, 1024, 2048) and t["classes_per_wg"] in (1, 2, 4)
     ref = fim.mine_batch(ctx, handles, ms)
+    oracles = [oracle.mine_db(d, threads=4) for d in dbs]
+    for r, o, d in zip(ref, oracles, dbs):
+        assert_same(r, o, d.name)
+        assert r.stats["candidates"] == o.candidates
     for tw in (256, 512, 1024, 2048, 3000):
         for c in (1, 4):
             got = fim.mine_batch(ctx, handles, ms, tile_words=tw, classes_per_wg=c)
-            for a, b in zip(got, ref):
-                assert_same(a, b, (tw, c))
-                assert a.stats["candidates"] == b.stats["candidates"]
+            for a, o in zip(got, oracles):
+                assert_same(a, o, (tw, c))
+                assert a.stats["candidates"] == o.candidates
     for h in handles:
         h.close()
 
@@ -413,7 +417,11 @@ def test_server_results_same_alone_and_mixed(fim, ctx, lanes, max_active, budget
     dbs.append(synth.dense_instance(synth.dense_params(9, synth.SERVE_BASE, 1000, 4000)))
     handles = [fim.Database(ctx, d.offsets, d.items, d.n_items) for d in dbs]
     alone = [fim.mine(ctx, h, d.minsup) for d, h in zip(dbs, handles)]
-    assert_same(alone[-1], oracle.mine_db(dbs[-1], threads=4), "dense")
+    # every request alone against the oracle, so that mixed = alone = oracle
+    for k, (d, r) in enumerate(zip(dbs, alone)):
+        o = oracle.mine_db(d, threads=4)
+        assert_same(r, o, ("alone", k))
+        assert r.stats["candidates"] == o.candidates
     say("server", lanes, max_active, budget)
     srv = fim.Server(ctx, max_active=max_active, lanes=lanes, hbm_budget_bytes=budget)
     tickets = [srv.submit(h, d.minsup) for d, h in zip(dbs, handles)]
@@ -438,3 +446,61 @@ def test_server_results_same_alone_and_mixed(fim, ctx, lanes, max_active, budget
     srv.close()
     for h in handles:
         h.close()
+
+
+# ---------------------------------------------------------------- full-size batch and serving pool
+
+def test_batch_256_full_size_vs_golden(fim, ctx):
+    # all 256 batch instances at their full sizes in one batched call, and
+    # each one alone, against the oracle's stored digests and candidate counts
+    g = _load("batch-256.json")
+    say("batch-256: generating")
+    dbs = [synth.batch_instance(synth.batch_params(e["substream"])) for e in g["instances"]]
+    handles = [fim.Database(ctx, d.offsets, d.items, d.n_items) for d in dbs]
+    ms = [d.minsup for d in dbs]
+    assert ms == [e["minsup"] for e in g["instances"]]
+    say("batch-256: one batched call")
+    res = fim.mine_batch(ctx, handles, ms)
+    bad = [i for i, (r, e) in enumerate(zip(res, g["instances"]))
+           if oracle.digest(r.offsets, r.items, r.supports) != e["digest"]
+           or r.stats["candidates"] != e["candidates_ascending_support"]]
+    assert not bad, bad
+    del res
+    say("batch-256: each instance alone")
+    for i, (h, m, e) in enumerate(zip(handles, ms, g["instances"])):
+        r = fim.mine(ctx, h, m)
+        assert oracle.digest(r.offsets, r.items, r.supports) == e["digest"], i
+        assert r.stats["candidates"] == e["candidates_ascending_support"], i
+    for h in handles:
+        h.close()
+    ctx.release_cached()
+
+
+def test_serve_pool_512_vs_golden(fim, ctx):
+    # every request of the 512-request serving pool (one in ten dense)
+    # submitted to the server at once, results against the stored digests;
+    # then a second round in reverse order while the first is still running
+    g = _load("serve-pool.json")
+    say("serve pool: generating")
+    handles, ms = [], []
+    for k, e in enumerate(g["instances"]):
+        d = synth.serve_instance(synth.serve_params(k, e["substream"]))
+        assert d.minsup == e["minsup"], k
+        handles.append(fim.Database(ctx, d.offsets, d.items, d.n_items))
+        ms.append(d.minsup)
+        del d
+    say("serve pool: 2 x 512 requests")
+    srv = fim.Server(ctx)
+    first = [srv.submit(h, m) for h, m in zip(handles, ms)]
+    second = [srv.submit(h, m) for h, m in zip(handles[::-1], ms[::-1])][::-1]
+    for k, e in enumerate(g["instances"]):
+        for t in (first[k], second[k]):
+            r = srv.wait(t)
+            assert oracle.digest(r.offsets, r.items, r.supports) == e["digest"], k
+            assert len(r) == e["n_itemsets"], k
+    st = srv.stats()
+    assert st["completed"] == 2 * len(handles)
+    srv.close()
+    for h in handles:
+        h.close()
+    ctx.release_cached()
