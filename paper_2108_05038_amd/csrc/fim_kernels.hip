@@ -74,6 +74,14 @@ __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// lane 0's value, known to the compiler to be the same in every lane (kept
+// in scalar registers); for wave-uniform points of the code only
+__device__ __forceinline__ uint64_t bcast64(uint64_t v) {
+    const uint64_t x = shfl_u64(v, 0);
+    return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | uni((uint32_t)x);
+}
+__device__ __forceinline__ uint32_t bcast32(uint32_t v) { return uni(__shfl(v, 0, kWave)); }
+
 // Blocks are dispatched round-robin over the 8 XCDs of the chip.  Renumber
 // them so that each XCD receives a contiguous range of logical block ids,
 // which keeps neighbouring tiles (sharing rows) in the same L2.
@@ -862,33 +870,60 @@ __global__ __launch_bounds__(kBlock) void k_root_project(
 //
 // Every wave is one worker with a private region of `stack_words` words:
 // bitmap rows of the classes on its DFS path grow up from the bottom, atom
-// lists (ranks, supports, source rows) grow down from the top.  A worker
-// repeatedly claims tasks (rows [r0, r1) of a first-level class) from a
-// global counter, materialises the class's sibling bitmaps along the prefix
-// path (the thesis's Prepare-Tidlists for a prefix of length one), and runs
-// Eclat-DFS-Computation below those rows: for a row r of a class with k
-// atoms, the supports of (r, j) for all later atoms j are AND-popcounts of
-// the two rows; the frequent ones are reported, ordered by ascending
-// support (ties by item id), their bitmaps are written, and that child
-// class is searched before row r + 1.
+// lists grow down from the top.  A worker repeatedly claims tasks (rows
+// [r0, r1) of a first-level class) from a global counter, materialises the
+// class's sibling bitmaps along the prefix path (the thesis's
+// Prepare-Tidlists for a prefix of length one), and runs
+// Eclat-DFS-Computation below those rows.
+//
+// A class of at most kGramMax atoms is counted when it is built.  While its
+// rows T(P + a_r + a_q) = T(P + a_r) AND T(P + a_q) are formed, word tile by
+// word tile, the supports of all of its pairs (the popcount-Gram of the
+// class) are accumulated from the same words, so every loaded word serves
+// all pairs of the class: up to kRegGram atoms a lane keeps its 128-bit
+// chunks of all rows and all pairs in registers; wider classes stage each
+// 32-word tile of their rows in LDS and every lane accumulates 4x4 blocks of
+// pairs from it.  For every row the frequent later atoms, ordered by
+// ascending support (ties by item id), become that row's child class, and
+// the frequent pairs are reported.  Expanding row r then counts nothing: it
+// builds the child class of row r in the same way.  A class of two atoms
+// never writes its rows (its one pair is all there is to count).  Classes
+// of more than kGramMax atoms (wide first-level classes) are expanded row by
+// row instead: row r is paired with every later row when it is expanded.
+
+constexpr uint32_t kGramMax = 64;     // widest class counted when it is built
+constexpr uint32_t kTileMin = 32;     // narrowest LDS row tile (words)
+constexpr uint32_t kTileDefault = 256;  // widest LDS row tile unless the autotuner picks another
+constexpr uint32_t kGx = 3200;        // LDS words per wave for row tiles and pair supports
+constexpr uint32_t kMaxTileRows = 8;  // rows of a tile one lane loads (see count_lds)
+constexpr uint32_t kListPad = kWave;  // list entries past a class's lists that a wave may read
+static_assert(kGx >= kGramMax * (kGramMax - 1) / 2, "pair supports fit in the tile area");
+static_assert(4 * ((kGramMax + 3) / 4) * (kTileMin + 4) <= kGx, "the widest class fits a narrowest tile");
 
 struct Frame {
-    uint32_t rows_base;    // word offset of the class's row 0
+    uint32_t rows_base;    // word offset of the class's row 0 (rows_top when it was pushed)
     uint32_t k;            // atoms (rows) of the class
     uint32_t r;            // next row to expand
     uint32_t r_end;        // rows [0, r_end) are expanded
-    uint32_t atoms;        // word offset of ranks[k]; supports at +stride, source rows at +2*stride
-    uint32_t stride;       // capacity of each of the three atom arrays
+    uint32_t atoms;        // word offset of ranks[k]; supports at +k, item ids at +2k,
+                           // (counted classes) sizes of the rows' child classes at +3k
+    uint32_t lists;        // counted classes: word offset of the child-class entries
+                           // (rank, support, row, item id); kNone: pairs counted on expansion
+    uint32_t lpos;         // counted classes: first entry of row r's child class
     uint32_t meta_restore; // meta pointer to restore when the class is done
-    uint32_t pad_;
 };
 
 constexpr uint32_t kStageWords = 68;  // words a chunk of 64 projected entries can touch, + slack
+static_assert(4 * kStageWords <= kGx, "the projection stage fits in the tile area");
 
-struct WaveShared {
+struct alignas(16) WaveShared {
+    uint32_t gx[kGx];                // row tiles, then pair supports, of the class being built;
+                                     // assembly of projected rows (16-byte aligned)
     Frame frames[kMaxDepth];
-    uint32_t prefix[kMaxDepth + 3];
-    uint32_t stage[4 * kStageWords];  // assembly of projected rows, four at a time
+    uint32_t prefix[kMaxDepth + 3];  // ranks of the prefix items
+    uint32_t pid[kMaxDepth + 3];     // their item ids
+    uint32_t sid[kMaxDepth + 3];     // the prefix's item ids ascending (key records)
+    uint32_t cid[kGramMax];          // item ids of the atoms of the class being built
 };
 
 struct WaveStats {
@@ -915,6 +950,9 @@ struct FrameSrc {
     // for a one-item prefix the class of row 0 (row r: l2_ref + r), else the
     // class every itemset of the piece belongs to
     uint32_t l2_ref;
+    // the itemsets of the piece's first class (prefix + two of its atoms)
+    // were already reported (a donated part of a class counted when built)
+    uint32_t reported;
 };
 
 // the second-level class of the itemsets reported while row r of the
@@ -968,7 +1006,7 @@ __device__ bool chunk_reserve(OutChunk &c, uint32_t need, uint32_t task, uint32_
     const uint32_t size = max(grow, need + kChunkHeader);
     unsigned long long base = 0;
     if (lane_id() == 0) base = atomicAdd(&ctr->out_used.v, (unsigned long long)size);
-    base = shfl_u64(base, 0);
+    base = bcast64(base);
     c.seq += c.base == kNoChunk ? 0u : 1u;
     c.base = base;
     c.size = size;
@@ -1013,34 +1051,38 @@ __device__ __forceinline__ void store_coherent32(uint32_t *p, uint32_t v) {
 // wait for this wave's own memory operations to complete (no cache maintenance)
 __device__ __forceinline__ void wave_mem_wait() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
 
-// Rank of every key of `tmp` among all nf keys; writes the sorted atoms.
-// Sorts nf atoms (arrays of stride `si` at tmp) ascending by (support, item
-// id) into dst (arrays of stride nf).
+// Sorts nf atoms (ranks, supports, source rows: arrays of stride `si` at
+// tmp) ascending by (support, item id), or by item id alone, into dst as
+// arrays of stride nf: ranks, supports, item ids, source rows.
 __device__ void sort_atoms(const InstDesc &I, const uint32_t *tmp, uint32_t si, uint32_t *dst,
                            uint32_t nf) {
     const uint32_t lane = lane_id();
     for (uint32_t e0 = 0; e0 < nf; e0 += kWave) {
         const uint32_t e = e0 + lane;
         uint64_t key = ~0ull;
-        uint32_t rk = 0, sp = 0, src = 0;
+        uint32_t rk = 0, sp = 0, src = 0, id = 0;
         if (e < nf) {
             rk = tmp[e];
             sp = tmp[si + e];
             src = tmp[2 * si + e];
-            key = ((uint64_t)sp << 32) | I.item_of_rank[rk];
+            id = I.item_of_rank[rk];
+            key = I.order_by_id ? (uint64_t)id : (((uint64_t)sp << 32) | id);
         }
         uint32_t pos = 0;
         for (uint32_t f0 = 0; f0 < nf; f0 += kWave) {
             uint64_t kf = ~0ull;
-            if (f0 + lane < nf)
-                kf = ((uint64_t)tmp[si + f0 + lane] << 32) | I.item_of_rank[tmp[f0 + lane]];
+            if (f0 + lane < nf) {
+                const uint32_t idf = I.item_of_rank[tmp[f0 + lane]];
+                kf = I.order_by_id ? (uint64_t)idf : (((uint64_t)tmp[si + f0 + lane] << 32) | idf);
+            }
             const uint32_t cnt = min(nf - f0, (uint32_t)kWave);
             for (uint32_t t = 0; t < cnt; t++) pos += (shfl_u64(kf, t) < key) ? 1u : 0u;
         }
         if (e < nf) {
             dst[pos] = rk;
             dst[nf + pos] = sp;
-            dst[2 * nf + pos] = src;
+            dst[2 * nf + pos] = id;
+            dst[3 * nf + pos] = src;
         }
     }
 }
@@ -1093,17 +1135,19 @@ __device__ bool try_donate(const InstDesc &I, uint32_t inst, uint32_t plen, uint
         hb = atomicAdd(&ctr->don_heap_used.v, (unsigned long long)words);
         sl = hb + words <= dn.heap_words ? atomicAdd(&ctr->don_tail.v, 1ull) : ~0ull;
     }
-    hb = shfl_u64(hb, 0);
-    sl = shfl_u64(sl, 0);
+    hb = bcast64(hb);
+    sl = bcast64(sl);
     if (sl >= dn.n_slots) return false;  // heap or queue full: keep the work
     uint32_t *rec = dn.heap + hb;
     const uint32_t *ranks = region + F.atoms;
-    const uint32_t *supps = ranks + F.stride;
+    const uint32_t *supps = ranks + F.k;
+    // a class counted when it was built has reported all of its pairs
+    const uint32_t reported = F.lists != kNone ? 0x80000000u : 0u;
     if (lane == 0) {
         store_coherent32(rec + 0, inst);
         store_coherent32(rec + 1, pl);
         store_coherent32(rec + 2, kk);
-        store_coherent32(rec + 3, F.r_end - mid);
+        store_coherent32(rec + 3, (F.r_end - mid) | reported);
         store_coherent32(rec + 4, ref);
     }
     for (uint32_t q = lane; q < pl; q += kWave) store_coherent32(rec + 5 + q, ws.prefix[q]);
@@ -1132,7 +1176,7 @@ __device__ __forceinline__ bool donation_wanted(DfsCounters *ctr) {
             want = idle > queued ? 1u : 0u;
         }
     }
-    return __shfl(want, 0, kWave) != 0;
+    return bcast32(want) != 0;
 }
 
 // CPL > 0: a row spans at most 64 * CPL chunks and the expanded row is held
@@ -1153,10 +1197,10 @@ __device__ void emit_keys(const InstDesc &I, uint32_t inst, uint32_t len, const 
     }
     // the prefix's item ids ascending in LDS: lane q ranks id q among the
     // distinct ids (len - 1 <= kMaxDepth + 1 < 2 * kWave)
-    uint32_t *sp = ws.stage;  // 4 * kStageWords >= kMaxDepth + 2 words
+    uint32_t *sp = ws.sid;
     const uint32_t np = len - 1;
-    uint32_t v0 = lane < np ? I.item_of_rank[ws.prefix[lane]] : ~0u;
-    uint32_t v1 = lane + kWave < np ? I.item_of_rank[ws.prefix[lane + kWave]] : ~0u;
+    uint32_t v0 = lane < np ? ws.pid[lane] : ~0u;
+    uint32_t v1 = lane + kWave < np ? ws.pid[lane + kWave] : ~0u;
     uint32_t p0 = 0, p1 = 0;
     for (uint32_t q = 0; q < np && q < (uint32_t)kWave; q++) {
         const uint32_t u = __shfl(v0, (int)q, kWave);
@@ -1174,7 +1218,7 @@ __device__ void emit_keys(const InstDesc &I, uint32_t inst, uint32_t len, const 
     __builtin_amdgcn_wave_barrier();
     unsigned long long base = 0;
     if (lane == 0) base = atomicAdd(&ctr->out_used.v, 8ull * nf);
-    base = shfl_u64(base, 0);
+    base = bcast64(base);
     if (base + 8ull * nf > out_cap) {
         if (lane == 0) atomicOr(&ctr->flags, kFlagOutOverflow);
     } else {
@@ -1212,44 +1256,585 @@ __device__ __forceinline__ bool inst_stopped(const InstDesc &I, InstCounters *ic
     if (I.rec_budget == 0) return false;
     uint32_t v = 0;
     if (lane_id() == 0) v = load_coherent32(&ictr[inst].stop);
-    return __shfl(v, 0, kWave) != 0;
+    return bcast32(v) != 0;
 }
 
-template <int CPL>
-__device__ void process_frame(const InstDesc &I, uint32_t inst, uint32_t task, uint32_t plen,
-                              uint32_t l2_ref, uint32_t k, uint32_t r_end, uint32_t Wp, uint64_t meta,
-                              uint64_t peak0,
-                              uint32_t *region, uint64_t S, WaveShared &ws, uint32_t *out,
-                              uint64_t out_cap, DfsCounters *ctr, InstCounters *ictr, WaveStats &st,
-                              OutChunk &oc, Donation &dn) {
+// ---------------------------------------------------------------- counting a class when it is built
+
+// Loads and stores of global memory.  The persistent kernel's pointers all
+// point to device memory; spelling the address space out keeps the compiler
+// from emitting generic (flat) accesses, which wait on both the vector memory
+// and the LDS counters.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const u32x4 *g_cu4;
+typedef __attribute__((address_space(1))) u32x4 *g_u4;
+typedef __attribute__((address_space(1))) const uint32_t *g_cu32;
+typedef __attribute__((address_space(1))) uint32_t *g_u32;
+__device__ __forceinline__ uint4 gld4(const uint4 *p) {
+    const u32x4 v = *(g_cu4)p;
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void gst4(uint4 *p, uint4 v) {
+    u32x4 w;
+    w.x = v.x;
+    w.y = v.y;
+    w.z = v.z;
+    w.w = v.w;
+    *(g_u4)p = w;
+}
+__device__ __forceinline__ uint32_t gld(const uint32_t *p) { return *(g_cu32)p; }
+__device__ __forceinline__ void gst(uint32_t *p, uint32_t v) { *(g_u32)p = v; }
+
+// index of pair (a, b), a < b < f, in row-major order of the upper triangle
+__device__ __forceinline__ uint32_t pair_index(uint32_t a, uint32_t b, uint32_t f) {
+    return a * f - a * (a + 1) / 2 + (b - a - 1);
+}
+
+// the pair of index p (inverse of pair_index)
+__device__ __forceinline__ void pair_of(uint32_t p, uint32_t f, uint32_t &a, uint32_t &b) {
+    uint32_t x = 0;
+    while (x + 1 < f && p >= f - 1 - x) {
+        p -= f - 1 - x;
+        x++;
+    }
+    a = x;
+    b = x + 1 + p;
+}
+
+// Reduce-scatter of N values (N a power of two, at most 32) over the wave:
+// the halving steps exchange half of the values with the lane O apart (lane
+// bits 5, 4, ...), so that after log2(N) steps lane l holds one value, the
+// one of index (l >> (6 - log2 N)) & (N - 1), summed over the lanes that
+// share those bits; the remaining lane bits are then summed as usual.
+template <int N, int O = 32>
+__device__ __forceinline__ uint32_t reduce_scatter(uint32_t *v, uint32_t lane) {
+    if constexpr (N == 1) {
+        uint32_t s = v[0];
+#pragma unroll
+        for (int o = O; o >= 1; o >>= 1) s += __shfl_xor(s, o, kWave);
+        return s;
+    } else {
+        constexpr int H = N / 2;
+        const bool up = (lane & O) != 0;
+#pragma unroll
+        for (int i = 0; i < H; i++) {
+            const uint32_t keep = up ? v[i + H] : v[i];
+            const uint32_t give = up ? v[i] : v[i + H];
+            v[i] = keep + __shfl_xor(give, O, kWave);
+        }
+        return reduce_scatter<H, O / 2>(v, lane);
+    }
+}
+
+template <int N>
+constexpr int log2i() {
+    return N <= 1 ? 0 : 1 + log2i<N / 2>();
+}
+
+// Rows of a class of F atoms: row q = xr AND base[src_q] (xr null: base[src_q]
+// itself), src_q held by lane q.  Counts the supports of all F (F - 1) / 2
+// pairs into gx[pair_index] and writes the rows to dst (if not null), row q
+// at dst + q * Wp.  A lane owns 128-bit chunks c = lane, lane + 64, ... of
+// every row and all pairs; U chunks of every row are loaded at once.
+template <int F, int U>
+__device__ __forceinline__ void count_reg(const uint32_t *xr, const uint32_t *base, uint32_t Wp,
+                                          uint32_t src, uint32_t *dst, uint32_t *gx) {
+    constexpr int NP = F * (F - 1) / 2;
+    constexpr int N = NP <= 1 ? 1 : NP <= 2 ? 2 : NP <= 4 ? 4 : NP <= 8 ? 8 : NP <= 16 ? 16 : 32;
+    const uint32_t lane = lane_id();
+    const uint32_t C = Wp / 4;
+    const uint4 *rp[F];
+#pragma unroll
+    for (int q = 0; q < F; q++)
+        rp[q] = reinterpret_cast<const uint4 *>(base + (uint64_t)__builtin_amdgcn_readlane(src, q) * Wp);
+    const uint4 *xp = reinterpret_cast<const uint4 *>(xr);
+    uint4 *dp = reinterpret_cast<uint4 *>(dst);
+    uint32_t acc[N];
+#pragma unroll
+    for (int p = 0; p < N; p++) acc[p] = 0;
+#pragma unroll 1
+    for (uint32_t c0 = lane; c0 < C; c0 += U * kWave) {
+        uint4 x[U][F];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const uint32_t c = c0 + u * kWave;
+#pragma unroll
+            for (int q = 0; q < F; q++) x[u][q] = c < C ? gld4(rp[q] + c) : make_uint4(0, 0, 0, 0);
+        }
+        if (xp) {
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const uint32_t c = c0 + u * kWave;
+                const uint4 r = c < C ? gld4(xp + c) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+                for (int q = 0; q < F; q++) x[u][q] = and4(x[u][q], r);
+            }
+        }
+        if (dp) {
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const uint32_t c = c0 + u * kWave;
+                if (c < C) {
+#pragma unroll
+                    for (int q = 0; q < F; q++) gst4(dp + (uint64_t)q * C + c, x[u][q]);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            int p = 0;
+#pragma unroll
+            for (int a = 0; a < F; a++)
+#pragma unroll
+                for (int b = a + 1; b < F; b++) acc[p++] += popc4(x[u][a], x[u][b]);
+        }
+    }
+    const uint32_t s = reduce_scatter<N>(acc, lane);
+    const uint32_t idx = (lane >> (6 - log2i<N>())) & (N - 1);
+    if ((lane & (kWave / N - 1)) == 0 && idx < (uint32_t)NP) gx[idx] = s;
+}
+
+// LDS tile width (words) of a class of f atoms: the widest power of two up
+// to tmax with f rows of it, padded to a multiple of four rows (row stride
+// width + 4), in kGx words, and at most kMaxTileRows chunks per lane
+__device__ __forceinline__ uint32_t lds_tile(uint32_t f, uint32_t tmax) {
+    uint32_t t = tmax;
+    while (t > kTileMin && (4 * ((f + 3) / 4) * (t + 4) > kGx || f * t > 256 * kMaxTileRows)) t >>= 1;
+    return t;
+}
+
+// The same for kRegGram < f <= kGramMax atoms, with the rows staged in LDS
+// tile by tile (T words per tile, row stride T + 4 words; lane l loads chunk
+// l mod T/4 of its rows).  The next tile is loaded into registers while the
+// pairs of the current one are counted.  The pairs are cut into 4x4 blocks
+// (A <= B over blocks of four rows); a lane accumulates R blocks over whole
+// tiles, or, when there are few blocks, g lanes share a block and split
+// the words.
+template <int R>
+__device__ __forceinline__ void count_lds(const uint32_t *xr, const uint32_t *base, uint32_t Wp,
+                                          uint32_t f, uint32_t src, uint32_t *dst, uint32_t *gx,
+                                          uint32_t tmax) {
+    const uint32_t lane = lane_id();
+    const uint32_t T = lds_tile(f, tmax), CR = T / 4, stride = T + 4;
+    const uint32_t nb = (f + 3) / 4, P = nb * (nb + 1) / 2;
+    uint32_t g = 1;
+    if (R == 1)
+        while (2 * g * P <= (uint32_t)kWave && g < T) g <<= 1;
+    const uint32_t sub = lane % g;
+    uint32_t A[R], B[R];
+    bool has[R];
+#pragma unroll
+    for (int q = 0; q < R; q++) {
+        const uint32_t bp = R == 1 ? lane / g : lane + (uint32_t)kWave * q;
+        has[q] = bp < P;
+        uint32_t a = 0, rem = has[q] ? bp : 0;
+        while (rem >= nb - a) {
+            rem -= nb - a;
+            a++;
+        }
+        A[q] = a;
+        B[q] = a + rem;
+    }
+    uint32_t acc[R][16];
+#pragma unroll
+    for (int q = 0; q < R; q++)
+#pragma unroll
+        for (int e = 0; e < 16; e++) acc[q][e] = 0;
+    // tile rows from f up to 4 nb pad the last block with zeros
+    for (uint32_t i = f * stride + lane; i < 4 * nb * stride; i += kWave) gx[i] = 0u;
+    // this lane's chunks of a tile: chunk cc of rows q0 + j * (64 / CR)
+    const uint32_t cc = lane % CR, q0 = lane / CR, qs = kWave / CR;
+    const uint32_t nl = q0 < f ? (f - q0 + qs - 1) / qs : 0u;  // rows of this lane
+    uint32_t srcj[kMaxTileRows];
+#pragma unroll
+    for (int j = 0; j < kMaxTileRows; j++) srcj[j] = __shfl(src, (int)min(q0 + j * qs, f - 1), kWave);
+    uint4 buf[kMaxTileRows];
+    auto load = [&](uint32_t w0) {
+        const uint32_t w = w0 + 4 * cc;
+        const bool in = w < Wp;
+        const uint4 r = (xr && in) ? gld4(reinterpret_cast<const uint4 *>(xr + w)) : make_uint4(~0u, ~0u, ~0u, ~0u);
+#pragma unroll
+        for (int j = 0; j < kMaxTileRows; j++) {
+            const bool ok = in && (uint32_t)j < nl;
+            buf[j] = ok ? and4(gld4(reinterpret_cast<const uint4 *>(base + (uint64_t)srcj[j] * Wp + w)), r)
+                        : make_uint4(0, 0, 0, 0);
+        }
+    };
+    load(0);
+#pragma unroll 1
+    for (uint32_t w0 = 0; w0 < Wp; w0 += T) {
+        const uint32_t w = w0 + 4 * cc;
+#pragma unroll
+        for (int j = 0; j < kMaxTileRows; j++) {
+            if ((uint32_t)j < nl) {
+                const uint32_t q = q0 + j * qs;
+                *reinterpret_cast<uint4 *>(gx + q * stride + 4 * cc) = buf[j];
+                if (dst && w < Wp) gst4(reinterpret_cast<uint4 *>(dst + (uint64_t)q * Wp + w), buf[j]);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (w0 + T < Wp) load(w0 + T);
+#pragma unroll
+        for (int q = 0; q < R; q++) {
+            if (!has[q]) continue;
+            const uint32_t *ra = gx + 4 * A[q] * stride, *rb = gx + 4 * B[q] * stride;
+#pragma unroll 2
+            for (uint32_t t = sub; t < T; t += g) {
+                uint32_t av[4], bv[4];
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    av[i] = ra[i * stride + t];
+                    bv[i] = rb[i * stride + t];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+#pragma unroll
+                    for (int j = 0; j < 4; j++) acc[q][i * 4 + j] += __popc(av[i] & bv[j]);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    // the lanes of a block add up their words; one of them stores the pairs
+#pragma unroll
+    for (int q = 0; q < R; q++)
+#pragma unroll
+        for (int e = 0; e < 16; e++)
+            for (uint32_t o = g >> 1; o >= 1; o >>= 1) acc[q][e] += __shfl_xor(acc[q][e], (int)o, kWave);
+#pragma unroll
+    for (int q = 0; q < R; q++) {
+        if (!has[q] || sub != 0) continue;
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const uint32_t a = 4 * A[q] + i, b = 4 * B[q] + j;
+                if (a < b && b < f) gx[pair_index(a, b, f)] = acc[q][i * 4 + j];
+            }
+    }
+}
+
+// Pair supports of a class of f atoms (2 <= f <= kGramMax) into ws.gx.
+__device__ __forceinline__ void count_class(const uint32_t *xr, const uint32_t *base, uint32_t Wp,
+                                            uint32_t f, uint32_t src, uint32_t *dst, uint32_t tmax,
+                                            WaveShared &ws) {
+    switch (f) {
+        case 2: count_reg<2, 8>(xr, base, Wp, src, dst, ws.gx); break;
+        case 3: count_reg<3, 4>(xr, base, Wp, src, dst, ws.gx); break;
+        case 4: count_reg<4, 4>(xr, base, Wp, src, dst, ws.gx); break;
+        case 5: count_reg<5, 2>(xr, base, Wp, src, dst, ws.gx); break;
+        case 6: count_reg<6, 2>(xr, base, Wp, src, dst, ws.gx); break;
+        case 7: count_reg<7, 2>(xr, base, Wp, src, dst, ws.gx); break;
+        case 8: count_reg<8, 2>(xr, base, Wp, src, dst, ws.gx); break;
+        default: {
+            const uint32_t nb = (f + 3) / 4, P = nb * (nb + 1) / 2;
+            if (P <= (uint32_t)kWave) count_lds<1>(xr, base, Wp, f, src, dst, ws.gx, tmax);
+            else if (P <= 2u * kWave) count_lds<2>(xr, base, Wp, f, src, dst, ws.gx, tmax);
+            else count_lds<3>(xr, base, Wp, f, src, dst, ws.gx, tmax);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// The prefix's item ids (ws.pid[0, np)) ascending into ws.sid.
+__device__ __forceinline__ void sort_prefix_ids(uint32_t np, WaveShared &ws) {
+    const uint32_t lane = lane_id();
+    const uint32_t v0 = lane < np ? ws.pid[lane] : ~0u;
+    const uint32_t v1 = lane + kWave < np ? ws.pid[lane + kWave] : ~0u;
+    uint32_t p0 = 0, p1 = 0;
+    for (uint32_t q = 0; q < np && q < (uint32_t)kWave; q++) {
+        const uint32_t u = __shfl(v0, (int)q, kWave);
+        p0 += u < v0 ? 1u : 0u;
+        p1 += u < v1 ? 1u : 0u;
+    }
+    for (uint32_t q = kWave; q < np; q++) {
+        const uint32_t u = __shfl(v1, (int)(q - kWave), kWave);
+        p0 += u < v0 ? 1u : 0u;
+        p1 += u < v1 ? 1u : 0u;
+    }
+    if (lane < np) ws.sid[p0] = v0;
+    if (lane + kWave < np) ws.sid[p1] = v1;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// 128-bit key of the itemset: the np prefix ids (ascending in ws.sid) and
+// the two ids x < y, as (id + 1) codes of `bits` bits from the top bit down.
+__device__ __forceinline__ void pair_key(const WaveShared &ws, uint32_t np, uint32_t bits, uint32_t x,
+                                         uint32_t y, unsigned long long &hi, unsigned long long &lo) {
+    hi = 0;
+    lo = 0;
+    uint32_t sh = 128, q = 0, t = 0;  // t: 0, 1 or 2 of {x, y} placed
+    for (uint32_t k = 0; k < np + 2; k++) {
+        const uint32_t v = q < np ? ws.sid[q] : ~0u;
+        const uint32_t c = t == 0 ? x : (t == 1 ? y : ~0u);
+        const bool take_c = c < v;
+        const uint32_t z = take_c ? c : v;
+        t += take_c ? 1u : 0u;
+        q += take_c ? 0u : 1u;
+        const unsigned long long code = (unsigned long long)z + 1;
+        sh -= bits;
+        hi |= sh >= 64 ? code << (sh - 64) : (sh + bits > 64 ? code >> (64 - sh) : 0ull);
+        lo |= sh >= 64 ? 0ull : code << sh;
+    }
+}
+
+// Where the records of a class go (see finish_class).
+struct EmitTo {
+    uint32_t np;       // prefix length of the class
+    uint32_t r_emit;   // rows whose pairs are reported (0: none)
+    uint32_t l2_row0;  // estimate runs: second-level class of row 0 when each row has its own
+    uint32_t l2_cls;   //   (kNone), else the class of every pair
+};
+
+enum : uint32_t { kBuildOk = 0, kBuildStop = 1, kBuildFull = 2 };
+
+// ws.gx holds the supports of the f (f - 1) / 2 pairs of a class (pair_index
+// order) whose atom q is held by lane q (rank, support, item id; ws.cid[q] =
+// item id).  Below `meta` this writes the class's atom arrays, the size of
+// every row's child class and, row after row, those child classes (the
+// frequent later atoms as (rank, support, row, item id), ascending by
+// (support, item id)); it reports the frequent pairs of rows a < r_emit as
+// the itemsets prefix + a + b.  meta moves down to the atom arrays.
+__device__ __forceinline__ uint32_t finish_class(const InstDesc &I, uint32_t inst, uint32_t task,
+                                                 uint32_t f, uint32_t rank, uint32_t supp, uint32_t id,
+                                                 const EmitTo &em, uint64_t rows_end, uint64_t &meta,
+                                                 uint32_t *region, uint64_t S, WaveShared &ws,
+                                                 uint32_t *out, uint64_t out_cap, DfsCounters *ctr,
+                                                 InstCounters *ictr, WaveStats &st, OutChunk &oc,
+                                                 uint32_t &atoms_off, uint32_t &lists_off) {
+    const uint32_t lane = lane_id();
+    const uint32_t m = I.minsup;
+    const uint32_t NP = f * (f - 1) / 2;
+    // frequent later atoms of row `lane`
+    uint32_t cnt = 0;
+    if (lane < f)
+        for (uint32_t b = lane + 1; b < f; b++) cnt += ws.gx[pair_index(lane, b, f)] >= m ? 1u : 0u;
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t v = __shfl_up(incl, o, kWave);
+        if ((int)lane >= o) incl += v;
+    }
+    const uint32_t excl = incl - cnt;
+    const uint32_t nfreq = uni(__shfl(incl, kWave - 1, kWave));
+    const uint32_t r_emit = min(em.r_emit, f);
+    const uint32_t n_emit = uni(r_emit == 0 ? 0u : __shfl(incl, (int)(r_emit - 1), kWave));
+    const uint32_t len = em.np + 2;
+    const bool report = n_emit > 0 && (I.max_len == 0 || len <= I.max_len);
+    const bool keys = report && I.key_bits != 0 && I.class_count == nullptr && len * I.key_bits <= 128;
+    // the key records' place in the arena, reserved now so that the atomic's
+    // round trip overlaps the work below
+    unsigned long long b0 = 0;
+    if (keys && lane == 0) b0 = atomicAdd(&ctr->out_used.v, 8ull * n_emit);
+    // lists (16-byte aligned entries) and atom arrays below meta
+    const uint64_t need = 4ull * (nfreq + kListPad) + 4ull * f + 4;
+    if (meta < need || meta - need < rows_end) {
+        flag_stack(ctr, rows_end + (S - meta) + need);
+        return kBuildFull;
+    }
+    const uint64_t lists = (meta - 4ull * (nfreq + kListPad)) & ~3ull;
+    const uint64_t atoms = lists - 4ull * f;
+    uint32_t *A = region + atoms;
+    if (lane < f) {
+        gst(A + lane, rank);
+        gst(A + f + lane, supp);
+        gst(A + 2 * f + lane, id);
+        gst(A + 3 * f + lane, cnt);
+    }
+    // reporting
+    const bool recs = report && I.key_bits == 0 && I.class_count == nullptr;
+    uint64_t kbase = 0;
+    bool kvalid = false, rvalid = false;
+    const uint32_t rec = kRecHeader + len;
+    if (report) {
+        if (I.rec_budget) st.rec_pending += n_emit;
+        st.out_words += (unsigned long long)n_emit * (I.key_bits ? 8u : rec);
+    }
+    if (report && I.key_bits != 0 && I.class_count == nullptr && len * I.key_bits > 128) {
+        if (lane == 0) atomicOr(&ctr->flags, kFlagKeyOverflow);
+    } else if (keys) {
+        sort_prefix_ids(em.np, ws);
+        kbase = bcast64(b0);
+        kvalid = kbase + 8ull * n_emit <= out_cap;
+        if (!kvalid && lane == 0) atomicOr(&ctr->flags, kFlagOutOverflow);
+    } else if (recs) {
+        rvalid = chunk_reserve(oc, n_emit * rec, task, inst, out, out_cap, ctr);
+    } else if (report && I.class_count) {
+        // estimate run: only the number of itemsets per second-level class
+        if (em.l2_row0 != kNone) {
+            if (lane < r_emit && cnt) atomicAdd(&I.class_count[em.l2_row0 + lane], (unsigned long long)cnt);
+        } else if (lane == 0) {
+            atomicAdd(&I.class_count[em.l2_cls], (unsigned long long)n_emit);
+        }
+    }
+    // the entries, lane-parallel over the pairs
+    uint4 *L = reinterpret_cast<uint4 *>(region + lists);
+    for (uint32_t p0 = 0; p0 < NP; p0 += kWave) {
+        const uint32_t p = p0 + lane;
+        uint32_t a = 0, b = 1, s = 0;
+        if (p < NP) {
+            pair_of(p, f, a, b);
+            s = ws.gx[p];
+        }
+        const bool fr = p < NP && s >= m;
+        const uint32_t off_a = __shfl(excl, (int)a, kWave);
+        const uint32_t rank_b = __shfl(rank, (int)b, kWave);
+        const uint32_t rank_a = __shfl(rank, (int)a, kWave);
+        if (fr) {
+            const uint32_t id_b = ws.cid[b];
+            const uint64_t key = I.order_by_id ? (uint64_t)id_b : (((uint64_t)s << 32) | id_b);
+            uint32_t pos = 0;
+            for (uint32_t c = a + 1; c < f; c++) {
+                if (c == b) continue;
+                const uint32_t sc = ws.gx[pair_index(a, c, f)];
+                const uint32_t idc = ws.cid[c];
+                const uint64_t kc = I.order_by_id ? (uint64_t)idc : (((uint64_t)sc << 32) | idc);
+                pos += (sc >= m && kc < key) ? 1u : 0u;
+            }
+            const uint32_t e = off_a + pos;
+            gst4(L + e, make_uint4(rank_b, s, b, id_b));
+            if (a < r_emit) {
+                if (kvalid) {
+                    const uint32_t id_a = ws.cid[a];
+                    unsigned long long hi, lo;
+                    pair_key(ws, em.np, I.key_bits, min(id_a, id_b), max(id_a, id_b), hi, lo);
+                    uint4 *o = reinterpret_cast<uint4 *>(out + kbase + 8ull * e);
+                    gst4(o, make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32)));
+                    gst4(o + 1, make_uint4(s, inst, 0u, 0u));
+                } else if (rvalid) {
+                    uint32_t *o = out + oc.base + oc.pos + (uint64_t)e * rec;
+                    o[0] = len;
+                    o[1] = s;
+                    for (uint32_t q = 0; q < em.np; q++) o[2 + q] = ws.prefix[q];
+                    o[2 + em.np] = rank_a;
+                    o[3 + em.np] = rank_b;
+                }
+            }
+        }
+    }
+    if (recs) oc.pos += n_emit * rec;
+    meta = atoms;
+    atoms_off = (uint32_t)atoms;
+    lists_off = (uint32_t)lists;
+    if (report && I.rec_budget && st.rec_pending >= 4096) {
+        // records are added to the instance's count in batches; the count
+        // never exceeds the records really found, so the work is abandoned
+        // only once the budget is certainly exceeded
+        unsigned long long before = 0;
+        if (lane == 0) before = atomicAdd(&ictr[inst].records, st.rec_pending);
+        before = bcast64(before);
+        const unsigned long long now = before + st.rec_pending;
+        st.rec_pending = 0;
+        if (now > I.rec_budget) {
+            if (lane == 0) atomicOr(&ictr[inst].stop, 1u);
+            return kBuildStop;
+        }
+    }
+    return kBuildOk;
+}
+
+// Depth-first search of a piece of work.  Its first class has k0 atoms,
+// their rows at region[0, k0 Wp) and their arrays (ranks, supports, item
+// ids) at meta; its rows [0, r_end0) are this piece's.  Classes of at most
+// kGramMax atoms are counted when they are built (the first one right away,
+// its pairs of rows below r_end0 reported unless `reported0`), and every
+// expanded row hands its child class over from their lists; wider classes
+// pair row r with every later row when it is expanded (rows streamed from
+// memory, g lanes per pair).  All builds go through one block at the end of
+// the loop, so that its counting code is present once.
+__device__ __forceinline__ void search(const InstDesc &I, uint32_t inst, uint32_t task, uint32_t plen,
+                       uint32_t l2_ref, uint32_t Wp, uint32_t k0, uint32_t r_end0, uint32_t reported0,
+                       uint64_t meta, uint64_t peak, uint32_t tmax, uint32_t *region, uint64_t S,
+                       WaveShared &ws, uint32_t *out, uint64_t out_cap, DfsCounters *ctr,
+                       InstCounters *ictr, WaveStats &st, OutChunk &oc, Donation &dn) {
     const uint32_t lane = lane_id();
     const uint32_t C = Wp / 4;  // 128-bit chunks per row
-
-    // lanes per pair: about four chunks per lane (their loads in flight at
-    // once), at most a wave; narrow rows put several pairs in one pass
+    // row-by-row pairing: lanes per pair, about four chunks per lane (their
+    // loads in flight at once), at most a wave; narrow rows put several
+    // pairs in one pass
     uint32_t g = 1;
     const uint32_t want = (C + 3) / 4;
     while (g < want && g < (uint32_t)kWave) g <<= 1;
     const uint32_t ppp = kWave / g;  // pairs per pass
     const uint32_t grp = lane / g, sub = lane % g;
 
-    // the first class's rows are region[0, k * Wp), its atom arrays at meta
-    int depth = 0;
-    ws.frames[0] = Frame{0u, k, 0u, r_end, (uint32_t)meta, k, (uint32_t)S, 0u};
-    __builtin_amdgcn_wave_barrier();
-    uint64_t rows_top = (uint64_t)k * Wp;
-    uint64_t peak = peak0;
-    uint32_t polls = 0, cool = 0, iters = 0;
+    uint64_t rows_top = (uint64_t)k0 * Wp;
+    // the class to build (lane q holds atom q) and where it goes
+    bool build = false;
+    uint32_t b_c = 0, b_rank = 0, b_supp = 0, b_id = 0, b_src = 0, b_r_end = 0;
+    const uint32_t *b_xr = nullptr, *b_base = nullptr;
+    bool b_write = false;
+    uint64_t b_rows_base = 0, b_restore = 0;
+    EmitTo b_em{0, 0, kNone, 0};
+    int depth;
+    if (k0 <= kGramMax) {
+        const uint32_t q = lane < k0 ? lane : 0;
+        build = true;
+        b_c = k0;
+        b_rank = region[meta + q];
+        b_supp = region[meta + k0 + q];
+        b_id = region[meta + 2 * k0 + q];
+        b_src = lane;
+        b_r_end = r_end0;
+        b_base = region;
+        b_rows_base = 0;
+        b_restore = S;
+        b_em = EmitTo{plen, reported0 ? 0u : r_end0, plen == 1 ? l2_ref : kNone, l2_ref};
+        depth = -1;
+    } else {
+        if (lane == 0) ws.frames[0] = Frame{0u, k0, 0u, r_end0, (uint32_t)meta, kNone, 0u, (uint32_t)S};
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        depth = 0;
+    }
 
-    while (depth >= 0) {
-        if ((++iters & 15u) == 0 && inst_stopped(I, ictr, inst)) return;
-        if (dn.enabled && cool == 0 && ((++polls & 3u) == 0) && donation_wanted(ctr)) {
+    uint32_t polls = 0, cool = 0, iters = 0;
+    for (;;) {
+        if (build) {
+            // ---- count the class while building it, list its rows' child classes, push it
+            build = false;
+            const uint32_t c = b_c;
+            const uint64_t rows_need = b_write ? (uint64_t)c * Wp : 0;
+            const uint64_t meta_need = 4ull * (c * (c - 1) / 2 + kListPad) + 4ull * c + 4;
+            if (meta < meta_need || meta - meta_need < rows_top + rows_need) {
+                flag_stack(ctr, rows_top + rows_need + (S - meta) + meta_need);
+                break;
+            }
+            if (lane < c) ws.cid[lane] = b_id;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            count_class(b_xr, b_base, Wp, c, b_src, b_write ? region + rows_top : nullptr, tmax, ws);
+            st.pair_words += (unsigned long long)(c * (c - 1) / 2) * Wp;
+            if (depth >= 0) {
+                st.row_words += (unsigned long long)c * Wp;
+                st.child_rows += b_write ? c : 0u;
+            }
+            uint32_t ao = 0, lo = 0;
+            if (finish_class(I, inst, task, c, b_rank, b_supp, b_id, b_em, rows_top + rows_need, meta, region,
+                             S, ws, out, out_cap, ctr, ictr, st, oc, ao, lo) != kBuildOk)
+                break;
+            if (lane == 0)
+                ws.frames[depth + 1] = Frame{(uint32_t)b_rows_base, c, 0u, b_r_end, ao, lo, 0u, (uint32_t)b_restore};
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            rows_top += rows_need;
+            depth++;
+            const uint64_t use = rows_top + (S - meta);
+            if (use > peak) peak = use;
+            continue;
+        }
+        if (depth < 0) break;
+        if ((++iters & 63u) == 0 && inst_stopped(I, ictr, inst)) break;
+        if (dn.enabled && cool == 0 && ((++polls & 7u) == 0) && donation_wanted(ctr)) {
             const bool gave = try_donate(I, inst, plen, l2_ref, depth, region, ws, dn, ctr);
             cool = gave ? 8u : 4u;
             st.given += gave ? 1u : 0u;
-        }
-        else if (cool)
+        } else if (cool) {
             cool--;
+        }
         Frame F = ws.frames[depth];
         __builtin_amdgcn_wave_barrier();
         F.rows_base = uni(F.rows_base);
@@ -1257,7 +1842,8 @@ __device__ void process_frame(const InstDesc &I, uint32_t inst, uint32_t task, u
         F.r = uni(F.r);
         F.r_end = uni(F.r_end);
         F.atoms = uni(F.atoms);
-        F.stride = uni(F.stride);
+        F.lists = uni(F.lists);
+        F.lpos = uni(F.lpos);
         F.meta_restore = uni(F.meta_restore);
         if (F.r >= F.r_end) {
             rows_top = F.rows_base;
@@ -1266,89 +1852,82 @@ __device__ void process_frame(const InstDesc &I, uint32_t inst, uint32_t task, u
             continue;
         }
         const uint32_t r = F.r;
-        ws.frames[depth].r = r + 1;
         const uint32_t nj = F.k - r - 1;
-        if (nj == 0) continue;
-        const uint32_t *ranks = region + F.atoms;
-        ws.prefix[plen + depth] = ranks[r];
-        __builtin_amdgcn_wave_barrier();
+        const uint32_t *A = region + F.atoms;
+        const uint32_t np = plen + (uint32_t)depth + 1;  // prefix of row r's child class
+        if (F.lists != kNone) {
+            // the row's child class, its rank and its item id, in one round
+            const uint32_t c = uni(gld(A + 3 * F.k + r));
+            const uint32_t rank_r = uni(gld(A + r)), id_r = uni(gld(A + 2 * F.k + r));
+            const uint4 e = gld4(reinterpret_cast<const uint4 *>(region + F.lists) + F.lpos + lane);
+            if (lane == 0) {
+                ws.frames[depth].r = r + 1;
+                ws.frames[depth].lpos = F.lpos + c;
+                ws.prefix[plen + depth] = rank_r;
+                ws.pid[plen + depth] = id_r;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            st.candidates += nj;
+            if (F.k > st.max_k) st.max_k = F.k;
+            if ((unsigned long long)depth > st.max_depth) st.max_depth = depth;
+            if (c < 2 || (I.max_len != 0 && np + 2 > I.max_len)) continue;
+            if (depth + 1 >= kMaxDepth || np + 2 > kMaxDepth + 2) {
+                if (lane == 0) atomicOr(&ctr->flags, kFlagDepthOverflow);
+                continue;
+            }
+            build = true;
+            b_c = c;
+            b_rank = e.x;
+            b_supp = e.y;
+            b_src = e.z;
+            b_id = e.w;
+            b_r_end = c - 1;
+            b_xr = region + F.rows_base + (uint64_t)r * Wp;
+            b_base = region + F.rows_base;
+            b_write = c >= 3;  // a class of two atoms keeps no rows
+            b_rows_base = rows_top;
+            b_restore = meta;
+            b_em = EmitTo{np, c - 1, kNone, plen >= 2 ? l2_ref : l2_ref + ws.frames[0].r - 1};
+            continue;
+        }
 
+        // ---- a class too wide to be counted when built: pairs of row r now
+        if (lane == 0) {
+            ws.frames[depth].r = r + 1;
+            ws.prefix[plen + depth] = A[r];
+            ws.pid[plen + depth] = A[2 * F.k + r];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (nj == 0) continue;
+        const uint32_t *ranks = A;
         // frequent children of row r, unsorted: ranks, supports, source rows
         if (3ull * nj > meta || meta - 3ull * nj < rows_top) {
             flag_stack(ctr, rows_top + (S - meta) + 3ull * nj);
-            return;
+            break;
         }
         uint32_t *tmp = region + (meta - 3ull * nj);
-        const uint4 *row_r =
-            reinterpret_cast<const uint4 *>(region + F.rows_base + (uint64_t)r * Wp);
+        const uint4 *row_r = reinterpret_cast<const uint4 *>(region + F.rows_base + (uint64_t)r * Wp);
         uint32_t nf = 0;
-        uint4 rr[CPL > 0 ? CPL : 1];
-        if constexpr (CPL > 0) {
-            // row r in registers; partners two at a time, all their loads in flight
-#pragma unroll
-            for (int m = 0; m < CPL; m++) {
-                const uint32_t c = lane + m * kWave;
-                rr[m] = c < C ? row_r[c] : make_uint4(0, 0, 0, 0);
+        for (uint32_t jb = 0; jb < nj; jb += ppp) {
+            const uint32_t jj = jb + grp;
+            uint32_t acc = 0;
+            if (jj < nj) {
+                const uint4 *row_j =
+                    reinterpret_cast<const uint4 *>(region + F.rows_base + (uint64_t)(r + 1 + jj) * Wp);
+                acc = popc_rows(row_r, row_j, C, sub, g);
             }
-            for (uint32_t jj = 0; jj < nj; jj += 2) {
-                const bool two = jj + 1 < nj;
-                const uint4 *r0 = reinterpret_cast<const uint4 *>(
-                    region + F.rows_base + (uint64_t)(r + 1 + jj) * Wp);
-                const uint4 *r1 = two ? r0 + Wp / 4 : r0;
-                uint4 x0[CPL], x1[CPL];
-#pragma unroll
-                for (int m = 0; m < CPL; m++) {
-                    const uint32_t c = lane + m * kWave;
-                    x0[m] = c < C ? r0[c] : make_uint4(0, 0, 0, 0);
-                    x1[m] = c < C ? r1[c] : make_uint4(0, 0, 0, 0);
-                }
-                uint32_t a0 = 0, a1 = 0;
-#pragma unroll
-                for (int m = 0; m < CPL; m++) {
-                    a0 += popc4(rr[m], x0[m]);
-                    a1 += popc4(rr[m], x1[m]);
-                }
-#pragma unroll
-                for (int off = kWave / 2; off >= 1; off >>= 1) {
-                    a0 += __shfl_xor(a0, off, kWave);
-                    a1 += __shfl_xor(a1, off, kWave);
-                }
-                const bool f0 = a0 >= I.minsup, f1 = two && a1 >= I.minsup;
-                if (lane == 0) {
-                    if (f0) {
-                        tmp[nf] = ranks[r + 1 + jj];
-                        tmp[nj + nf] = a0;
-                        tmp[2 * nj + nf] = r + 1 + jj;
-                    }
-                    if (f1) {
-                        const uint32_t p = nf + (f0 ? 1u : 0u);
-                        tmp[p] = ranks[r + 2 + jj];
-                        tmp[nj + p] = a1;
-                        tmp[2 * nj + p] = r + 2 + jj;
-                    }
-                }
-                nf += (f0 ? 1u : 0u) + (f1 ? 1u : 0u);
+            for (uint32_t off = g >> 1; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+            const bool freq = sub == 0 && jj < nj && acc >= I.minsup;
+            const uint64_t mask = __ballot(freq);
+            if (freq) {
+                const uint32_t p = nf + lanes_below(mask);
+                tmp[p] = ranks[r + 1 + jj];
+                tmp[nj + p] = acc;
+                tmp[2 * nj + p] = r + 1 + jj;
             }
-        } else {
-            for (uint32_t jb = 0; jb < nj; jb += ppp) {
-                const uint32_t jj = jb + grp;
-                uint32_t acc = 0;
-                if (jj < nj) {
-                    const uint4 *row_j = reinterpret_cast<const uint4 *>(
-                        region + F.rows_base + (uint64_t)(r + 1 + jj) * Wp);
-                    acc = popc_rows(row_r, row_j, C, sub, g);
-                }
-                for (uint32_t off = g >> 1; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, kWave);
-                const bool freq = sub == 0 && jj < nj && acc >= I.minsup;
-                const uint64_t mask = __ballot(freq);
-                if (freq) {
-                    const uint32_t p = nf + lanes_below(mask);
-                    tmp[p] = ranks[r + 1 + jj];
-                    tmp[nj + p] = acc;
-                    tmp[2 * nj + p] = r + 1 + jj;
-                }
-                nf += (uint32_t)__popcll(mask);
-            }
+            nf += (uint32_t)__popcll(mask);
         }
         st.candidates += nj;
         st.pair_words += (unsigned long long)nj * Wp;
@@ -1361,28 +1940,24 @@ __device__ void process_frame(const InstDesc &I, uint32_t inst, uint32_t task, u
         const uint32_t len = plen + (uint32_t)depth + 2;
         if (I.max_len == 0 || len <= I.max_len) {
             if (I.rec_budget) {
-                // records are added to the instance's count in batches; the
-                // count never exceeds the records really found, so the work
-                // is abandoned only once the budget is certainly exceeded
                 st.rec_pending += nf;
                 if (st.rec_pending >= 4096) {
                     unsigned long long before = 0;
                     if (lane == 0) before = atomicAdd(&ictr[inst].records, st.rec_pending);
-                    before = shfl_u64(before, 0);
+                    before = bcast64(before);
                     const unsigned long long now = before + st.rec_pending;
                     st.rec_pending = 0;
                     if (now > I.rec_budget) {
                         if (lane == 0) atomicOr(&ictr[inst].stop, 1u);
-                        return;
+                        break;
                     }
                 }
             }
             const uint32_t rec = kRecHeader + len;
             st.out_words += (unsigned long long)nf * (I.key_bits ? 8u : rec);
             if (I.class_count) {
-                // estimate run: only the number of itemsets per second-level class
-                if (lane == 0) atomicAdd(&I.class_count[l2_class(plen, l2_ref, depth, r, ws)],
-                                         (unsigned long long)nf);
+                if (lane == 0)
+                    atomicAdd(&I.class_count[l2_class(plen, l2_ref, depth, r, ws)], (unsigned long long)nf);
             } else if (I.key_bits) {
                 emit_keys(I, inst, len, tmp, nj, nf, ws, out, out_cap, ctr);
             } else if (chunk_reserve(oc, nf * rec, task, inst, out, out_cap, ctr)) {
@@ -1399,91 +1974,76 @@ __device__ void process_frame(const InstDesc &I, uint32_t inst, uint32_t task, u
         }
 
         // the child class [prefix + a_r | frequent later atoms]
-        if (nf >= 2 && (I.max_len == 0 || len + 1 <= I.max_len)) {
-            if (depth + 1 >= kMaxDepth || plen + depth + 3 > kMaxDepth + 2) {
-                if (lane == 0) atomicOr(&ctr->flags, kFlagDepthOverflow);
-                continue;
-            }
-            const uint64_t restore = meta;
-            uint64_t new_meta = meta - 3ull * nj;
-            const uint32_t *sorted = tmp;
-            uint32_t sstride = nj;
-            if (!I.order_by_id) {
-                if (3ull * nf > new_meta || new_meta - 3ull * nf < rows_top + (uint64_t)nf * Wp) {
-                    flag_stack(ctr, rows_top + (uint64_t)nf * Wp + (S - new_meta) + 3ull * nf);
-                    return;
-                }
-                new_meta -= 3ull * nf;
-                uint32_t *dst = region + new_meta;
-                sort_atoms(I, tmp, nj, dst, nf);
-                __threadfence_block();
-                sorted = dst;
-                sstride = nf;
-            } else if (new_meta < rows_top + (uint64_t)nf * Wp) {
-                flag_stack(ctr, rows_top + (uint64_t)nf * Wp + (S - new_meta));
-                return;
-            }
-            // child bitmaps: row_r AND row_src, in the child's atom order
-            if constexpr (CPL > 0) {
-                for (uint32_t c = 0; c < nf; c += 2) {
-                    const bool two = c + 1 < nf;
-                    const uint4 *s0 = reinterpret_cast<const uint4 *>(
-                        region + F.rows_base + (uint64_t)sorted[2 * sstride + c] * Wp);
-                    const uint4 *s1 = two ? reinterpret_cast<const uint4 *>(
-                                                region + F.rows_base +
-                                                (uint64_t)sorted[2 * sstride + c + 1] * Wp)
-                                          : s0;
-                    uint4 *d0 = reinterpret_cast<uint4 *>(region + rows_top + (uint64_t)c * Wp);
-                    uint4 *d1 = d0 + Wp / 4;
-                    uint4 x0[CPL], x1[CPL];
-#pragma unroll
-                    for (int m = 0; m < CPL; m++) {
-                        const uint32_t q = lane + m * kWave;
-                        x0[m] = q < C ? s0[q] : make_uint4(0, 0, 0, 0);
-                        x1[m] = q < C ? s1[q] : make_uint4(0, 0, 0, 0);
-                    }
-#pragma unroll
-                    for (int m = 0; m < CPL; m++) {
-                        const uint32_t q = lane + m * kWave;
-                        if (q < C) {
-                            d0[q] = and4(rr[m], x0[m]);
-                            if (two) d1[q] = and4(rr[m], x1[m]);
-                        }
-                    }
-                }
-            } else if (g == (uint32_t)kWave) {
-                for (uint32_t c = 0; c < nf; c++) {
-                    const uint32_t sr = sorted[2 * sstride + c];
-                    const uint4 *row_j =
-                        reinterpret_cast<const uint4 *>(region + F.rows_base + (uint64_t)sr * Wp);
-                    uint4 *dst = reinterpret_cast<uint4 *>(region + rows_top + (uint64_t)c * Wp);
-                    and_rows(dst, row_r, row_j, C, lane);
-                }
-            } else {
-                // narrow rows: ppp children at a time, g lanes each
-                for (uint32_t c0 = 0; c0 < nf; c0 += ppp) {
-                    const uint32_t c = c0 + grp;
-                    if (c < nf) {
-                        const uint32_t sr = sorted[2 * sstride + c];
-                        const uint4 *row_j = reinterpret_cast<const uint4 *>(
-                            region + F.rows_base + (uint64_t)sr * Wp);
-                        uint4 *dst = reinterpret_cast<uint4 *>(region + rows_top + (uint64_t)c * Wp);
-                        for (uint32_t q = sub; q < C; q += g) dst[q] = and4(row_r[q], row_j[q]);
-                    }
-                }
-            }
-            __threadfence_block();
-            st.child_rows += nf;
-            st.row_words += (unsigned long long)nf * Wp;
-            ws.frames[depth + 1] = Frame{(uint32_t)rows_top, nf, 0u, nf - 1,
-                                         (uint32_t)(sorted - region), sstride, (uint32_t)restore, 0u};
-            __builtin_amdgcn_wave_barrier();
-            rows_top += (uint64_t)nf * Wp;
-            meta = new_meta;
-            depth++;
-            const uint64_t use = rows_top + (S - meta);
-            if (use > peak) peak = use;
+        if (nf < 2 || (I.max_len != 0 && len + 1 > I.max_len)) continue;
+        if (depth + 1 >= kMaxDepth || plen + depth + 3 > kMaxDepth + 2) {
+            if (lane == 0) atomicOr(&ctr->flags, kFlagDepthOverflow);
+            continue;
         }
+        const uint64_t restore = meta;
+        if (4ull * nf > meta - 3ull * nj || meta - 3ull * nj - 4ull * nf < rows_top) {
+            flag_stack(ctr, rows_top + (S - meta) + 3ull * nj + 4ull * nf);
+            break;
+        }
+        const uint64_t new_meta = meta - 3ull * nj - 4ull * nf;
+        uint32_t *dst = region + new_meta;
+        sort_atoms(I, tmp, nj, dst, nf);
+        __threadfence_block();
+        if (nf <= kGramMax) {
+            // the child class is counted as it is built
+            const uint32_t q = lane < nf ? lane : 0;
+            build = true;
+            b_c = nf;
+            b_rank = dst[q];
+            b_supp = dst[nf + q];
+            b_id = dst[2 * nf + q];
+            b_src = dst[3 * nf + q];
+            b_r_end = nf - 1;
+            b_xr = region + F.rows_base + (uint64_t)r * Wp;
+            b_base = region + F.rows_base;
+            b_write = nf >= 3;
+            b_rows_base = rows_top;
+            b_restore = restore;
+            b_em = EmitTo{np, nf - 1, kNone, plen >= 2 ? l2_ref : l2_ref + ws.frames[0].r - 1};
+            meta = new_meta;
+            continue;
+        }
+        if (new_meta < rows_top + (uint64_t)nf * Wp) {
+            flag_stack(ctr, rows_top + (uint64_t)nf * Wp + (S - new_meta));
+            break;
+        }
+        // child bitmaps: row_r AND row_src, in the child's atom order
+        const uint32_t *srcs = dst + 3 * nf;
+        if (g == (uint32_t)kWave) {
+            for (uint32_t c = 0; c < nf; c++) {
+                const uint4 *row_j = reinterpret_cast<const uint4 *>(region + F.rows_base + (uint64_t)srcs[c] * Wp);
+                uint4 *dd = reinterpret_cast<uint4 *>(region + rows_top + (uint64_t)c * Wp);
+                and_rows(dd, row_r, row_j, C, lane);
+            }
+        } else {
+            // narrow rows: ppp children at a time, g lanes each
+            for (uint32_t c0 = 0; c0 < nf; c0 += ppp) {
+                const uint32_t c = c0 + grp;
+                if (c < nf) {
+                    const uint4 *row_j =
+                        reinterpret_cast<const uint4 *>(region + F.rows_base + (uint64_t)srcs[c] * Wp);
+                    uint4 *dd = reinterpret_cast<uint4 *>(region + rows_top + (uint64_t)c * Wp);
+                    for (uint32_t q = sub; q < C; q += g) dd[q] = and4(row_r[q], row_j[q]);
+                }
+            }
+        }
+        __threadfence_block();
+        st.child_rows += nf;
+        st.row_words += (unsigned long long)nf * Wp;
+        if (lane == 0)
+            ws.frames[depth + 1] = Frame{(uint32_t)rows_top, nf, 0u, nf - 1, (uint32_t)new_meta, kNone, 0u,
+                                         (uint32_t)restore};
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        rows_top += (uint64_t)nf * Wp;
+        meta = new_meta;
+        depth++;
+        const uint64_t use = rows_top + (S - meta);
+        if (use > peak) peak = use;
     }
     if (lane == 0) atomicMax(&ctr->stack_need, (unsigned long long)peak);
 }
@@ -1602,35 +2162,37 @@ __device__ bool build_projected(const InstDesc &I, const uint32_t *P, uint32_t s
 }
 
 // The first class of a piece of work: its sibling rows T(prefix + atom) for
-// every atom (Prepare-Tidlists), then its depth-first search.  When the
+// every atom (Prepare-Tidlists), at region[0, k Wp) with the atom arrays at
+// meta_out; returns the row width used (0: nothing to search).  When the
 // cover T(prefix) holds at most a quarter of the row's bits, the rows are
 // built projected on that cover: bit i of a projected row is the row's bit
 // at the i-th transaction of T(prefix).  Every support below the prefix is
 // a popcount of ANDs of such rows, so the results are the same, and the
-// whole subtree works on rows of ceil(supp(prefix) / 32) words.  The
-// process_frame variant is then picked for the width actually used: rows
-// of more than 64 and at most 64 * CPL chunks are held in registers.
-template <int CPL>
-__device__ void run_frame(const InstDesc &I, uint32_t inst, uint32_t task, const FrameSrc &src,
-                          uint32_t *region, uint64_t S, WaveShared &ws, uint32_t *out,
-                          uint64_t out_cap, DfsCounters *ctr, InstCounters *ictr, WaveStats &st,
-                          OutChunk &oc, Donation &dn) {
-    if (inst_stopped(I, ictr, inst)) return;
+// whole subtree works on rows of ceil(supp(prefix) / 32) words.
+__device__ __forceinline__ uint32_t prepare_frame(const InstDesc &I, uint32_t inst, const FrameSrc &src,
+                                                  uint32_t *region, uint64_t S, WaveShared &ws,
+                                                  DfsCounters *ctr, InstCounters *ictr, WaveStats &st,
+                                                  uint64_t &meta_out, uint64_t &low_out) {
+    if (inst_stopped(I, ictr, inst)) return 0;
     const uint32_t lane = lane_id();
     const uint32_t k = src.k, plen = src.plen;
-    if (src.r_end == 0 || src.r_end >= k || plen == 0 || plen + 2 > kMaxDepth) return;
+    if (src.r_end == 0 || src.r_end >= k || plen == 0 || plen + 2 > kMaxDepth) return 0;
     const uint32_t Wf = I.Wp, Cf = Wf / 4;
     if (3ull * k + (uint64_t)k * kRowAlign > S) {
         flag_stack(ctr, 3ull * k + (uint64_t)k * Wf);
-        return;
+        return 0;
     }
     const uint64_t meta = S - 3ull * k;
     for (uint32_t e = lane; e < k; e += kWave) {
-        region[meta + e] = src.ranks[e];
+        const uint32_t rk = src.ranks[e];
+        region[meta + e] = rk;
         region[meta + k + e] = src.supps[e];
-        region[meta + 2 * k + e] = e;
+        region[meta + 2 * k + e] = I.item_of_rank[rk];
     }
-    for (uint32_t q = lane; q < plen; q += kWave) ws.prefix[q] = src.prefix[q];
+    for (uint32_t q = lane; q < plen; q += kWave) {
+        ws.prefix[q] = src.prefix[q];
+        ws.pid[q] = I.item_of_rank[src.prefix[q]];
+    }
     uint64_t low = meta;  // region[0, low) is free
     // One-item prefix with its transaction list at hand: projected row e
     // holds bit i = [the i-th transaction of T(prefix) holds atom e], 64 bits
@@ -1642,7 +2204,7 @@ __device__ void run_frame(const InstDesc &I, uint32_t inst, uint32_t task, const
         if (I.project && 4ull * Wq <= Wf) {
             if (low < (uint64_t)k * Wq) {
                 flag_stack(ctr, (S - low) + (uint64_t)k * Wq);
-                return;
+                return 0;
             }
             // Groups of kG ballot rounds (kG * 64 transactions, 2 kG words):
             // the group's transaction ids stay in registers while every atom's
@@ -1687,15 +2249,9 @@ __device__ void run_frame(const InstDesc &I, uint32_t inst, uint32_t task, const
             }
             __threadfence_block();
             st.row_words += (unsigned long long)k * Wq;
-            const uint64_t peak0 = (S - low) + (uint64_t)k * Wq;
-            const uint32_t C = Wq / 4;
-            if (CPL > 0 && C > (uint32_t)kWave && C <= (uint32_t)(CPL * kWave))
-                process_frame<CPL>(I, inst, task, plen, src.l2_ref, k, src.r_end, Wq, meta, peak0, region, S, ws,
-                                   out, out_cap, ctr, ictr, st, oc, dn);
-            else
-                process_frame<0>(I, inst, task, plen, src.l2_ref, k, src.r_end, Wq, meta, peak0, region, S, ws,
-                                 out, out_cap, ctr, ictr, st, oc, dn);
-            return;
+            meta_out = meta;
+            low_out = low;
+            return Wq;
         }
     }
     // T(prefix): the item's own row, or the AND of the prefix items' rows
@@ -1703,7 +2259,7 @@ __device__ void run_frame(const InstDesc &I, uint32_t inst, uint32_t task, const
     if (plen > 1) {
         if (low < Wf) {
             flag_stack(ctr, (uint64_t)(k + 1) * Wf + 3ull * k);
-            return;
+            return 0;
         }
         low -= Wf;
         uint4 *pr = reinterpret_cast<uint4 *>(region + low);
@@ -1736,12 +2292,12 @@ __device__ void run_frame(const InstDesc &I, uint32_t inst, uint32_t task, const
     const uint32_t Wq = max(kRowAlign, ((s + 31) / 32 + kRowAlign - 1) / kRowAlign * kRowAlign);
     uint32_t Wp = Wf;
     if (I.project && 4ull * Wq <= Wf) {
-        if (!build_projected(I, P, s, src.ranks, k, Wq, region, S, low, ctr, ws.stage)) return;
+        if (!build_projected(I, P, s, src.ranks, k, Wq, region, S, low, ctr, ws.gx)) return 0;
         Wp = Wq;
     } else {
         if (low < (uint64_t)k * Wf) {
             flag_stack(ctr, (uint64_t)k * Wf + (S - low));
-            return;
+            return 0;
         }
         for (uint32_t e = 0; e < k; e++)
             and_rows(reinterpret_cast<uint4 *>(region + (uint64_t)e * Wf),
@@ -1750,14 +2306,9 @@ __device__ void run_frame(const InstDesc &I, uint32_t inst, uint32_t task, const
     }
     __threadfence_block();
     st.row_words += (unsigned long long)k * Wp;
-    const uint64_t peak0 = (S - low) + (uint64_t)k * Wp;
-    const uint32_t C = Wp / 4;
-    if (CPL > 0 && C > (uint32_t)kWave && C <= (uint32_t)(CPL * kWave))
-        process_frame<CPL>(I, inst, task, plen, src.l2_ref, k, src.r_end, Wp, meta, peak0, region, S, ws, out,
-                           out_cap, ctr, ictr, st, oc, dn);
-    else
-        process_frame<0>(I, inst, task, plen, src.l2_ref, k, src.r_end, Wp, meta, peak0, region, S, ws, out,
-                         out_cap, ctr, ictr, st, oc, dn);
+    meta_out = meta;
+    low_out = low;
+    return Wp;
 }
 
 __device__ __forceinline__ void flush_stats(const InstDesc &I, InstCounters *ictr, uint32_t inst,
@@ -1775,15 +2326,15 @@ __device__ __forceinline__ void flush_stats(const InstDesc &I, InstCounters *ict
     }
 }
 
-template <int CPL>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(CPL == 4 ? 2 : 1))) void k_dfs(const InstDesc *insts, const Task *tasks,
+__global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Task *tasks,
                                                 uint64_t n_tasks, uint32_t *stack,
                                                 uint64_t stack_words, uint32_t tasks_per_claim,
+                                                uint32_t tmax,
                                                 uint32_t *out, uint64_t out_cap,
                                                 DfsCounters *ctr, InstCounters *ictr,
                                                 Donation dn) {
     __shared__ WaveShared shared[kWavesPerBlock];
-    const uint32_t w = threadIdx.x / kWave;
+    const uint32_t w = uni(threadIdx.x / kWave);
     const uint32_t lane = lane_id();
     WaveShared &ws = shared[w];
     const uint64_t wave_id = (uint64_t)blockIdx.x * kWavesPerBlock + w;
@@ -1797,52 +2348,63 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(CPL == 4
         wt.max_k = max(wt.max_k, st.max_k);
         wt.max_depth = max(wt.max_depth, st.max_depth);
     };
-    // planned tasks, in LPT order
+    // Pieces of work: the planned tasks in LPT order, then donated classes
+    // until no wave is active and the queue is drained.  Both kinds go
+    // through the one call of the search below.
+    bool planned = true;
+    uint64_t t_next = 0, t_end = 0;
+    unsigned long long since = 0;
+    uint32_t nap = 1;
     for (;;) {
-        unsigned long long t0 = 0;
-        if (lane == 0) {
-            atomicAdd(&ctr->active.v, 1ull);
-            t0 = atomicAdd(&ctr->task_head.v, (unsigned long long)tasks_per_claim);
-        }
-        t0 = shfl_u64(t0, 0);
-        if (t0 >= n_tasks) {
-            wave_mem_wait();
-            if (lane == 0) atomicSub(&ctr->active.v, 1ull);
-            break;
-        }
-        const uint64_t t1 = min((uint64_t)t0 + tasks_per_claim, n_tasks);
-        for (uint64_t t = t0; t < t1; t++) {
-            const Task T = tasks[t];
+        FrameSrc fs{};
+        uint32_t inst = 0, task = 0;
+        uint64_t S = stack_words;
+        bool have = false;
+        if (planned) {
+            if (t_next >= t_end) {
+                if (t_end) {
+                    wave_mem_wait();  // donations of the claimed tasks are published before they count as done
+                    if (lane == 0) atomicSub(&ctr->active.v, 1ull);
+                }
+                unsigned long long t0 = 0;
+                if (lane == 0) {
+                    atomicAdd(&ctr->active.v, 1ull);
+                    t0 = atomicAdd(&ctr->task_head.v, (unsigned long long)tasks_per_claim);
+                }
+                t0 = bcast64(t0);
+                if (t0 >= n_tasks) {
+                    wave_mem_wait();
+                    if (lane == 0) atomicSub(&ctr->active.v, 1ull);
+                    planned = false;
+                    if (!dn.enabled) break;
+                    if (lane == 0) atomicAdd(&ctr->idle.v, 1ull);
+                    since = wall_clock64();
+                    continue;
+                }
+                t_next = t0;
+                t_end = min((uint64_t)t0 + tasks_per_claim, n_tasks);
+            }
+            const uint64_t t = t_next++;
+            Task T = tasks[t];
+            T.inst = uni(T.inst);
+            T.node = uni(T.node);
+            T.r0 = uni(T.r0);
+            T.r1 = uni(T.r1);
             const InstDesc &I = insts[T.inst];
-            const uint32_t a0 = I.l2_off[T.node], k1 = I.l2_off[T.node + 1] - a0;
+            const uint32_t a0 = uni(I.l2_off[T.node]), k1 = uni(I.l2_off[T.node + 1]) - a0;
             if (T.r0 >= T.r1 || T.r1 >= k1) continue;  // rows with a later atom only
-            WaveStats st{};
-            OutChunk oc{kNoChunk, 0u, 0u, 0u, 0u};
-            const FrameSrc fs{&tasks[t].node, I.l2_atom + a0 + T.r0, I.l2_supp + a0 + T.r0, 1u,
-                              k1 - T.r0, T.r1 - T.r0, a0 + T.r0};
-            const unsigned long long c0 = wall_clock64();
-            run_frame<CPL>(I, T.inst, (uint32_t)t, fs, region, stack_words, ws, out, out_cap, ctr,
-                           ictr, st, oc, dn);
-            close_chunk(oc, out);
-            busy += wall_clock64() - c0;
-            flush_stats(I, ictr, T.inst, st);
-            note(st);
-        }
-        wave_mem_wait();  // donations of this task are published before it counts as done
-        if (lane == 0) atomicSub(&ctr->active.v, 1ull);
-    }
-    // donated work until no wave is active and the queue is drained
-    if (dn.enabled) {
-        if (lane == 0) atomicAdd(&ctr->idle.v, 1ull);
-        unsigned long long since = wall_clock64();
-        uint32_t nap = 1;
-        for (;;) {
+            fs = FrameSrc{&tasks[t].node, I.l2_atom + a0 + T.r0, I.l2_supp + a0 + T.r0, 1u,
+                          k1 - T.r0, T.r1 - T.r0, a0 + T.r0, 0u};
+            inst = T.inst;
+            task = (uint32_t)t;
+            have = true;
+        } else {
             unsigned long long got = ~0ull;
             uint32_t done = 0;
             if (lane == 0) {
                 const unsigned long long h = load_coherent(&ctr->don_head.v);
-                const unsigned long long t = min(load_coherent(&ctr->don_tail.v), dn.n_slots);
-                if (h < t) {
+                const unsigned long long tl = min(load_coherent(&ctr->don_tail.v), dn.n_slots);
+                if (h < tl) {
                     if (atomicCAS(&ctr->don_head.v, h, h + 1) == h) got = h;
                 } else if (load_coherent(&ctr->active.v) == 0) {
                     // nobody can donate any more; re-read the queue after
@@ -1852,8 +2414,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(CPL == 4
                     done = h2 >= t2 ? 1u : 0u;
                 }
             }
-            got = shfl_u64(got, 0);
-            done = __shfl(done, 0, kWave);
+            got = bcast64(got);
+            done = bcast32(done);
             if (done) break;
             if (got == ~0ull) {
                 if (wall_clock64() - since > dn.wait_ticks) {
@@ -1875,34 +2437,27 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(CPL == 4
             const unsigned long long w0 = wall_clock64();
             for (;;) {
                 if (lane == 0) off = load_coherent(&dn.slots[got]);
-                off = shfl_u64(off, 0);
+                off = bcast64(off);
                 if (off != 0 || wall_clock64() - w0 > dn.wait_ticks) break;
                 __builtin_amdgcn_s_sleep(4);
             }
             if (off != 0) {
                 // copy the record into this wave's own memory with coherent loads
                 const uint32_t *rec = dn.heap + (off - 1);
-                const uint32_t inst = load_coherent32(rec), pl = load_coherent32(rec + 1);
-                const uint32_t kk = load_coherent32(rec + 2), re = load_coherent32(rec + 3);
-                const uint32_t ref = load_coherent32(rec + 4);
+                const uint32_t di = uni(load_coherent32(rec)), pl = uni(load_coherent32(rec + 1));
+                const uint32_t kk = uni(load_coherent32(rec + 2)), rw = uni(load_coherent32(rec + 3));
+                const uint32_t ref = uni(load_coherent32(rec + 4));
+                const uint32_t re = rw & 0x7FFFFFFFu, reported = rw >> 31;
                 const uint32_t words = pl + 2 * kk;
                 if ((uint64_t)words <= stack_words / 2) {
                     uint32_t *copy = region + (stack_words - words);
-                    for (uint32_t q = lane; q < words; q += kWave)
-                        copy[q] = load_coherent32(rec + 5 + q);
+                    for (uint32_t q = lane; q < words; q += kWave) copy[q] = load_coherent32(rec + 5 + q);
                     wave_mem_wait();
-                    const InstDesc &I = insts[inst];
-                    const FrameSrc fs{copy, copy + pl, copy + pl + kk, pl, kk, re, ref};
-                    WaveStats st{};
-                    OutChunk oc{kNoChunk, 0u, 0u, 0u, 0u};
-                    const unsigned long long c0 = wall_clock64();
-                    // the frame's own atom arrays go below the copy
-                    run_frame<CPL>(I, inst, (uint32_t)(n_tasks + got), fs, region,
-                                   stack_words - words, ws, out, out_cap, ctr, ictr, st, oc, dn);
-                    close_chunk(oc, out);
-                    busy += wall_clock64() - c0;
-                    flush_stats(I, ictr, inst, st);
-                    note(st);
+                    fs = FrameSrc{copy, copy + pl, copy + pl + kk, pl, kk, re, ref, reported};
+                    inst = di;
+                    task = (uint32_t)(n_tasks + got);
+                    S = stack_words - words;  // the frame's own arrays go below the copy
+                    have = true;
                 } else if (lane == 0) {
                     atomicOr(&ctr->flags, kFlagStackOverflow);
                     atomicMax(&ctr->stack_need, 2ull * words);
@@ -1910,6 +2465,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(CPL == 4
             } else if (lane == 0) {
                 atomicOr(&ctr->flags, kFlagSpin);
             }
+        }
+        if (have) {
+            const InstDesc &I = insts[inst];
+            WaveStats st{};
+            OutChunk oc{kNoChunk, 0u, 0u, 0u, 0u};
+            const unsigned long long c0 = wall_clock64();
+            uint64_t meta = 0, low = 0;
+            const uint32_t Wp = prepare_frame(I, inst, fs, region, S, ws, ctr, ictr, st, meta, low);
+            if (Wp)
+                search(I, inst, task, fs.plen, fs.l2_ref, Wp, fs.k, fs.r_end, fs.reported, meta,
+                       (S - low) + (uint64_t)fs.k * Wp, tmax, region, S, ws, out, out_cap, ctr, ictr, st,
+                       oc, dn);
+            close_chunk(oc, out);
+            busy += wall_clock64() - c0;
+            flush_stats(I, ictr, inst, st);
+            note(st);
+        }
+        if (!planned) {
             wave_mem_wait();
             if (lane == 0) {
                 atomicAdd(&ctr->idle.v, 1ull);
@@ -1917,8 +2490,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(CPL == 4
             }
             since = wall_clock64();
         }
-        if (lane == 0) atomicSub(&ctr->idle.v, 1ull);
     }
+    if (!planned && dn.enabled && lane == 0) atomicSub(&ctr->idle.v, 1ull);
     if (lane == 0 && busy) {
         atomicAdd(&ctr->busy_sum, busy);
         atomicMax(&ctr->busy_max, busy);
@@ -2164,42 +2737,24 @@ hipError_t launch_root_project(const uint16_t *rk, const uint32_t *tlp, const ui
     return hipGetLastError();
 }
 
-// row tile in words -> register-resident variant (256 words and wider than
-// 2048 words: streamed)
+// The persistent kernel has one variant; `variant` is the widest LDS row
+// tile (words) of the classes counted from LDS: a power of two from
+// kTileMin to kTileDefault (0 = kTileDefault).
 uint32_t tile_variant(uint32_t tile_words) {
-    if (tile_words <= 256) return 0;
-    if (tile_words <= 512) return 2;
-    if (tile_words <= 1024) return 4;
-    if (tile_words <= 2048) return 8;
-    return 0;
+    uint32_t t = kTileMin;
+    while (t < tile_words && t < kTileDefault) t <<= 1;
+    return t;
 }
 
-uint32_t dfs_variant(uint32_t max_chunks) {
-    if (max_chunks <= (uint32_t)kWave) return 0;
-    if (max_chunks <= 2u * kWave) return 2;
-    if (max_chunks <= 4u * kWave) return 4;
-    if (max_chunks <= 8u * kWave) return 8;
-    return 0;
-}
+uint32_t dfs_variant(uint32_t) { return kTileDefault; }
 
-template <int CPL>
-static uint32_t resident(int n_cu) {
+uint32_t dfs_resident_workers(int n_cu, uint32_t) {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_dfs<CPL>, kBlock, 0) != hipSuccess ||
-        blocks <= 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_dfs, kBlock, 0) != hipSuccess || blocks <= 0) {
         (void)hipGetLastError();
         blocks = 1;
     }
     return (uint32_t)blocks * kWavesPerBlock * (uint32_t)n_cu;
-}
-
-uint32_t dfs_resident_workers(int n_cu, uint32_t variant) {
-    switch (variant) {
-        case 2: return resident<2>(n_cu);
-        case 4: return resident<4>(n_cu);
-        case 8: return resident<8>(n_cu);
-        default: return resident<0>(n_cu);
-    }
 }
 
 hipError_t launch_dfs(const InstDesc *insts, const Task *tasks, uint64_t n_tasks, uint32_t *stack,
@@ -2214,23 +2769,9 @@ hipError_t launch_dfs(const InstDesc *insts, const Task *tasks, uint64_t n_tasks
                 (don_slots && don_heap && n_slots && heap_words) ? 1u : 0u, trace,
                 nap_max ? nap_max : 64u};
     const uint32_t tpc = tasks_per_claim ? tasks_per_claim : 1u;
-    switch (variant) {
-        case 2:
-            hipLaunchKernelGGL(k_dfs<2>, dim3(blocks), dim3(kBlock), 0, stream, insts, tasks,
-                               n_tasks, stack, stack_words, tpc, out, out_cap, ctr, ictr, dn);
-            break;
-        case 4:
-            hipLaunchKernelGGL(k_dfs<4>, dim3(blocks), dim3(kBlock), 0, stream, insts, tasks,
-                               n_tasks, stack, stack_words, tpc, out, out_cap, ctr, ictr, dn);
-            break;
-        case 8:
-            hipLaunchKernelGGL(k_dfs<8>, dim3(blocks), dim3(kBlock), 0, stream, insts, tasks,
-                               n_tasks, stack, stack_words, tpc, out, out_cap, ctr, ictr, dn);
-            break;
-        default:
-            hipLaunchKernelGGL(k_dfs<0>, dim3(blocks), dim3(kBlock), 0, stream, insts, tasks,
-                               n_tasks, stack, stack_words, tpc, out, out_cap, ctr, ictr, dn);
-    }
+    const uint32_t tmax = variant ? tile_variant(variant) : kTileDefault;
+    hipLaunchKernelGGL(k_dfs, dim3(blocks), dim3(kBlock), 0, stream, insts, tasks, n_tasks, stack,
+                       stack_words, tpc, tmax, out, out_cap, ctr, ictr, dn);
     return hipGetLastError();
 }
 

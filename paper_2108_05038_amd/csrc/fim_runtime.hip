@@ -698,7 +698,7 @@ static fim_status run_persistent(fim_ctx *ctx, hipStream_t s, Tracer &tr,
     L.ictr.assign(n_inst, InstCounters{});
     // per-worker stack: room for the largest first frame and its subtree,
     // within a quarter of device memory in total
-    uint64_t S = std::max<uint64_t>(4 * L.frame0, 1ull << 18);
+    uint64_t S = (std::max<uint64_t>(4 * L.frame0, 1ull << 18) + 63) & ~63ull;
     const uint64_t kMaxStack = 0xFFFFFFF0ull;  // frame offsets are 32-bit
     const uint64_t budget_words = (uint64_t)(ctx->total_mem / 4) / 4;
     // work sharing between waves
@@ -792,8 +792,8 @@ static fim_status run_persistent(fim_ctx *ctx, hipStream_t s, Tracer &tr,
                 std::sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) { return wt[8 * a] > wt[8 * b]; });
                 for (uint32_t x = 0; x < std::min<uint32_t>(5, workers); x++) {
                     const unsigned long long *v = &wt[8 * ord[x]];
-                    fprintf(stderr, "[fim %s]   wave %u busy %.3f ms pieces %llu given %llu cands %llu max_k %llu max_depth %llu\n",
-                            tr.tag, ord[x], clk_khz ? v[0] / (double)clk_khz : 0.0, v[1], v[2], v[3], v[4], v[5]);
+                    fprintf(stderr, "[fim %s]   wave %u busy %.3f ms pieces %llu given %llu cands %llu max_k %llu max_depth %llu (%llu %llu)\n",
+                            tr.tag, ord[x], clk_khz ? v[0] / (double)clk_khz : 0.0, v[1], v[2], v[3], v[4], v[5], v[6], v[7]);
                 }
             }
             fprintf(stderr, "[fim %s] dfs kernel %.3f ms, %zu tasks, %llu donations, %u workers, busiest %.3f ms, mean %.3f ms, imbalance %.1f, flags %u\n",
@@ -808,7 +808,8 @@ static fim_status run_persistent(fim_ctx *ctx, hipStream_t s, Tracer &tr,
                                                      std::to_string(kMaxDepth + 2) + " items");
         bool again = false;
         if (ctr.flags & kFlagStackOverflow) {
-            S = std::max<uint64_t>(2 * S, ctr.stack_need + ctr.stack_need / 4);
+            // a multiple of 64 words keeps every wave's region 256-byte aligned
+            S = (std::max<uint64_t>(2 * S, ctr.stack_need + ctr.stack_need / 4) + 63) & ~63ull;
             again = true;
         }
         if (L.stop_is_error)
