@@ -241,6 +241,33 @@ fim_status fim_mine(fim_ctx *ctx, const fim_db *db, uint32_t minsup_abs, const f
 fim_status fim_mine_batch(fim_ctx *ctx, uint32_t n, const fim_db *const *dbs,
                           const uint32_t *minsups, const fim_options *opts, fim_result **outs);
 
+/*
+ * Mining without allocation, for callers that cannot allocate (code under
+ * stream capture, tight serving loops, harnesses that forbid allocation).
+ * Mines like fim_mine(ctx, db, minsup_abs, opts) and gives the same result
+ * (the class-size estimate is always the cheap size proxy:
+ * FIM_FLAG_NO_ESTIMATE is implied; it orders work and never changes the
+ * result), copied in canonical order (as fim_result_copy) into the caller's
+ * host arrays offsets[cap_itemsets + 1], items[cap_items] and
+ * supports[cap_itemsets].  *n_itemsets and *n_items_total receive the
+ * result's sizes, also when they exceed the capacities.
+ * All device memory the call needs comes from one scratch block of
+ * FIM_NOALLOC_SCRATCH_BYTES bytes inside the library, one per GPU it runs on,
+ * held until the process ends; the call allocates no device memory and no
+ * page-locked host memory (host arrays of its own come from the ordinary
+ * heap).  The block keeps the last call's contents; every call clears what
+ * it needs.  Calls that overlap share a GPU's block: the library runs them
+ * one at a time (a call waits for the one before it).
+ * Errors: FIM_E_INVALID_ARG, FIM_E_OUTPUT_LIMIT (the result does not fit the
+ * arrays, or more itemsets than opts->max_itemsets), FIM_E_OOM_DEVICE (the
+ * work does not fit the scratch block), FIM_E_DEVICE.
+ */
+#define FIM_NOALLOC_SCRATCH_BYTES (256ull << 20)
+fim_status fim_mine_noalloc(fim_ctx *ctx, const fim_db *db, uint32_t minsup_abs,
+                            const fim_options *opts, uint64_t cap_itemsets, uint64_t cap_items,
+                            uint64_t *offsets, uint32_t *items, uint32_t *supports,
+                            uint64_t *n_itemsets, uint64_t *n_items_total);
+
 /* ------------------------------------------------------------------ */
 /* Results                                                            */
 

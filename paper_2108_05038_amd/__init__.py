@@ -53,7 +53,10 @@ EXPORTED = [
     "fim_result_destroy", "fim_server_create", "fim_server_submit", "fim_server_poll",
     "fim_server_wait", "fim_server_next", "fim_server_cancel", "fim_server_stats_get", "fim_server_destroy",
     "fim_estimate_sample_sizes", "fim_reservoir_sample", "fim_partition_lpt", "fim_lpt_schedule",
+    "fim_mine_noalloc",
 ]
+
+FIM_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 
 class FimError(RuntimeError):
@@ -150,6 +153,8 @@ def lib():
         "fim_partition_lpt": (i32, [u32, P(u32), P(ctypes.c_double), ctypes.c_double, u32, u32,
                                     P(u32), u32, P(u32), P(ctypes.c_double)]),
         "fim_lpt_schedule": (i32, [P(ctypes.c_double), u64, u32, P(u32), P(ctypes.c_double)]),
+        "fim_mine_noalloc": (i32, [V, V, u32, P(fim_options), u64, u64, P(u64), P(u32), P(u32),
+                                   P(u64), P(u64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -420,6 +425,33 @@ class Database:
 def mine(ctx: Context, db: Database, minsup: int, **opts) -> Result:
     o = make_options(**opts) if opts else None
     return fim_result_take(fim_mine(ctx.handle, db.handle, minsup, o))
+
+
+def fim_mine_noalloc(ctx, db, minsup: int, cap_itemsets: int, cap_items: int,
+                     opts: fim_options | None = None):
+    """``fim_mine_noalloc`` into caller arrays of the given capacities:
+    returns (status, offsets, items, supports, n_itemsets, n_items_total);
+    the arrays hold the result when status is FIM_OK."""
+    off = np.zeros(cap_itemsets + 1, np.uint64)
+    items = np.zeros(max(cap_items, 1), np.uint32)
+    supp = np.zeros(max(cap_itemsets, 1), np.uint32)
+    n, ni = ctypes.c_uint64(), ctypes.c_uint64()
+    st = lib().fim_mine_noalloc(ctx, db, minsup, ctypes.byref(opts) if opts else None, cap_itemsets,
+                                cap_items, _u64p(off), _u32p(items), _u32p(supp), ctypes.byref(n),
+                                ctypes.byref(ni))
+    return st, off, items, supp, n.value, ni.value
+
+
+def mine_noalloc(ctx: Context, db: Database, minsup: int, cap_itemsets: int, cap_items: int,
+                 **opts):
+    """Mining without device allocation (``fim_mine_noalloc``) into arrays of
+    the given capacities; returns (offsets, items, supports) trimmed to the
+    result."""
+    o = make_options(**opts) if opts else None
+    st, off, items, supp, n, ni = fim_mine_noalloc(ctx.handle, db.handle, minsup, cap_itemsets,
+                                                   cap_items, o)
+    _check(st)
+    return off[:n + 1], items[:ni], supp[:n]
 
 
 def mine_batch(ctx: Context, dbs, minsups, **opts):

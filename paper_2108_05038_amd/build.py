@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libfim.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SOURCES = ["fim_kernels.hip", "fim_runtime.hip", "fim_plan.hip", "fim_server.hip", "fim_order.hip",
-           "fim_canon.cpp"]
+           "fim_noalloc.hip", "fim_canon.cpp"]
 
 # Packed FP32 instructions are switched off for every HIP file (the code has
 # no floating-point vector math; the flag keeps the compiler from forming

@@ -14,6 +14,7 @@
 namespace fim {
 
 thread_local uint32_t g_host_thread_cap = 16;
+thread_local bool g_no_pinned = false;
 
 // ---------------------------------------------------------------- host pool
 // Blocks are sized in powers of two; released blocks wait in per-size lists
@@ -62,7 +63,7 @@ void *host_pool_alloc(size_t bytes) {
     bool pin = false;
     {
         std::lock_guard<std::mutex> g(P.mu);
-        pin = P.pinned_total + c <= kPinnedBudget;
+        pin = !g_no_pinned && P.pinned_total + c <= kPinnedBudget;
         if (pin) P.pinned_total += c;
     }
     if (pin && hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess) {
@@ -88,7 +89,9 @@ void host_pool_free(void *p, size_t bytes) {
     bool pin = false;
     {
         std::lock_guard<std::mutex> g(P.mu);
-        if (P.cached + c <= kPoolCacheBytes) {
+        // (a call that allocates nothing may exceed the cache rather than
+        // give page-locked memory back)
+        if (P.cached + c <= kPoolCacheBytes || (g_no_pinned && P.pinned.count(p) && P.pinned[p])) {
             P.free_lists[c].push_back(p);
             P.cached += c;
             return;

@@ -17,6 +17,9 @@ namespace fim {
 // (device copies go straight into them), kept for reuse after release so
 // that a later result does not fault its pages in again.  Thread-safe.
 constexpr size_t kHostPoolMin = 1u << 14;
+// Set while the calling thread runs an entry point that allocates no device
+// or page-locked memory: new host blocks then come from the ordinary heap.
+extern thread_local bool g_no_pinned;
 void *host_pool_alloc(size_t bytes);
 void host_pool_free(void *p, size_t bytes);
 

@@ -57,6 +57,16 @@ struct fim_ctx {
     void *dalloc(size_t bytes);
     void dfree(void *p);
     ~fim_ctx();
+
+    // While `arena` is set, dalloc hands out pieces of this caller-owned
+    // device block (a bump pointer; a free of the most recent piece takes it
+    // back) and never calls the allocator; pinned staging is not used.
+    char *arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0, last_piece_at = ~size_t(0);
+    // device memory a run may plan with: a quarter of the device, or the
+    // arena's free part
+    size_t plan_bytes() const { return arena ? arena_cap - arena_used : total_mem / 4; }
+    bool pinned_heap = false;  // `pinned` came from the ordinary heap
 };
 
 namespace fim {

@@ -84,6 +84,14 @@ void fim_ctx::release_cached() {
 }
 
 void *fim_ctx::dalloc(size_t bytes) {
+    if (arena) {
+        const size_t b = (std::max<size_t>(bytes, 256) + 255) & ~size_t(255);
+        if (b > arena_cap - arena_used) return nullptr;
+        void *p = arena + arena_used;
+        last_piece_at = arena_used;
+        arena_used += b;
+        return p;
+    }
     const size_t cls = size_class(bytes);
     {
         std::lock_guard<std::mutex> lk(cache_mu);
@@ -109,6 +117,15 @@ void *fim_ctx::dalloc(size_t bytes) {
 
 void fim_ctx::dfree(void *p) {
     if (!p) return;
+    if (arena && (char *)p >= arena && (char *)p < arena + arena_cap) {
+        // only the most recent piece can be taken back; the others stay
+        // used until the arena is released at the end of the call
+        if ((char *)p < arena + arena_used) {
+            const size_t at = (size_t)((char *)p - arena);
+            if (last_piece_at == at) arena_used = at;
+        }
+        return;
+    }
     std::unique_lock<std::mutex> lk(cache_mu);
     auto it = block_class.find(p);
     if (it == block_class.end()) {
@@ -220,10 +237,19 @@ fim_ctx *fim_ctx::aux_ctx() {
 
 uint32_t *fim_ctx::stage(size_t words) {
     if (words <= pinned_words && pinned) return pinned;
-    if (pinned) (void)hipHostFree(pinned);
+    if (pinned) {
+        if (pinned_heap) free(pinned);
+        else (void)hipHostFree(pinned);
+    }
     pinned = nullptr;
     pinned_words = 0;
     const size_t want = std::max<size_t>(words + words / 4, 1u << 20);
+    pinned_heap = fim::g_no_pinned;
+    if (pinned_heap) {
+        pinned = static_cast<uint32_t *>(malloc(want * 4));
+        if (pinned) pinned_words = want;
+        return pinned;
+    }
     if (hipHostMalloc((void **)&pinned, want * 4, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         pinned = nullptr;
@@ -240,7 +266,10 @@ fim_ctx::~fim_ctx() {
         (void)hipStreamDestroy(x);
     }
     release_cached();
-    if (pinned) (void)hipHostFree(pinned);
+    if (pinned) {
+        if (pinned_heap) free(pinned);
+        else (void)hipHostFree(pinned);
+    }
     if (up) {
         if (stream) (void)hipStreamSynchronize(stream);
         (void)hipHostFree(up);
@@ -321,7 +350,7 @@ StageRun::StageRun(fim_ctx *ctx) : ctx_(ctx) {
     // (from the call's stream or from its side streams)
     (void)hipStreamSynchronize(ctx_->stream);
     for (hipStream_t x : ctx_->side_streams) (void)hipStreamSynchronize(x);
-    if (ctx_->up_need > ctx_->up_cap) {
+    if (ctx_->up_need > ctx_->up_cap && !g_no_pinned) {
         if (ctx_->up) (void)hipHostFree(ctx_->up);
         ctx_->up = nullptr;
         ctx_->up_cap = 0;
@@ -700,7 +729,9 @@ static fim_status run_persistent(fim_ctx *ctx, hipStream_t s, Tracer &tr,
     // within a quarter of device memory in total
     uint64_t S = (std::max<uint64_t>(4 * L.frame0, 1ull << 18) + 63) & ~63ull;
     const uint64_t kMaxStack = 0xFFFFFFF0ull;  // frame offsets are 32-bit
-    const uint64_t budget_words = (uint64_t)(ctx->total_mem / 4) / 4;
+    // stacks and arena within what the run may plan with (half of an
+    // arena's free part: the output arena and its ordering need the rest)
+    const uint64_t budget_words = (uint64_t)(ctx->arena ? ctx->plan_bytes() / 2 : ctx->plan_bytes()) / 4;
     // work sharing between waves
     const uint64_t n_slots = 1ull << 16;
     const uint64_t heap_words = 1ull << 24;
@@ -1529,6 +1560,8 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         // a generous arena (kept by the context's block cache between calls):
         // an overflow costs a second run of the whole launch
         L.out_cap = L.cap_output ? (1ull << 24) : std::max<uint64_t>(1ull << 26, est_out_words);
+        if (ctx->arena)  // a fixed device block: start small, the overflow check grows it
+            L.out_cap = std::max<uint64_t>(1ull << 18, std::min<uint64_t>(est_out_words, ctx->plan_bytes() / 64));
         if (key_mode) {
             // the 1- and 2-itemsets' records come first in the arena,
             // written on the device from the ranks and the root pairs
