@@ -74,13 +74,15 @@ __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// lane 0's value, known to the compiler to be the same in every lane (kept
-// in scalar registers); for wave-uniform points of the code only
-__device__ __forceinline__ uint64_t bcast64(uint64_t v) {
-    const uint64_t x = shfl_u64(v, 0);
-    return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | uni((uint32_t)x);
+// lane q's value (q the same in every lane) in scalar registers: a register
+// read, not a trip through the LDS crossbar
+__device__ __forceinline__ uint32_t lane_val(uint32_t v, uint32_t q) { return __builtin_amdgcn_readlane(v, q); }
+__device__ __forceinline__ uint64_t lane_val64(uint64_t v, uint32_t q) {
+    return ((uint64_t)lane_val((uint32_t)(v >> 32), q) << 32) | lane_val((uint32_t)v, q);
 }
-__device__ __forceinline__ uint32_t bcast32(uint32_t v) { return uni(__shfl(v, 0, kWave)); }
+// lane 0's value; for wave-uniform points of the code only
+__device__ __forceinline__ uint64_t bcast64(uint64_t v) { return lane_val64(v, 0); }
+__device__ __forceinline__ uint32_t bcast32(uint32_t v) { return lane_val(v, 0); }
 
 // Blocks are dispatched round-robin over the 8 XCDs of the chip.  Renumber
 // them so that each XCD receives a contiguous range of logical block ids,
@@ -916,9 +918,15 @@ struct Frame {
 constexpr uint32_t kStageWords = 68;  // words a chunk of 64 projected entries can touch, + slack
 static_assert(4 * kStageWords <= kGx, "the projection stage fits in the tile area");
 
+constexpr uint32_t kStageRecs = 64;  // key records a wave gathers in LDS before one reservation
+
 struct alignas(16) WaveShared {
     uint32_t gx[kGx];                // row tiles, then pair supports, of the class being built;
                                      // assembly of projected rows (16-byte aligned)
+    uint4 recs[2 * kStageRecs];      // key records not yet in the output arena (two uint4 each)
+    uint4 row0[kGramMax];            // the child class of row 0 of the class built last
+    uint32_t n_recs;                 // records in `recs`
+    uint32_t row0_n, row0_rank, row0_id;  // its size, row 0's rank and item id
     Frame frames[kMaxDepth];
     uint32_t prefix[kMaxDepth + 3];  // ranks of the prefix items
     uint32_t pid[kMaxDepth + 3];     // their item ids
@@ -1076,7 +1084,7 @@ __device__ void sort_atoms(const InstDesc &I, const uint32_t *tmp, uint32_t si, 
                 kf = I.order_by_id ? (uint64_t)idf : (((uint64_t)tmp[si + f0 + lane] << 32) | idf);
             }
             const uint32_t cnt = min(nf - f0, (uint32_t)kWave);
-            for (uint32_t t = 0; t < cnt; t++) pos += (shfl_u64(kf, t) < key) ? 1u : 0u;
+            for (uint32_t t = 0; t < cnt; t++) pos += (lane_val64(kf, t) < key) ? 1u : 0u;
         }
         if (e < nf) {
             dst[pos] = rk;
@@ -1203,12 +1211,12 @@ __device__ void emit_keys(const InstDesc &I, uint32_t inst, uint32_t len, const 
     uint32_t v1 = lane + kWave < np ? ws.pid[lane + kWave] : ~0u;
     uint32_t p0 = 0, p1 = 0;
     for (uint32_t q = 0; q < np && q < (uint32_t)kWave; q++) {
-        const uint32_t u = __shfl(v0, (int)q, kWave);
+        const uint32_t u = lane_val(v0, q);
         p0 += u < v0 ? 1u : 0u;
         p1 += u < v1 ? 1u : 0u;
     }
     for (uint32_t q = kWave; q < np; q++) {
-        const uint32_t u = __shfl(v1, (int)(q - kWave), kWave);
+        const uint32_t u = lane_val(v1, q - kWave);
         p0 += u < v0 ? 1u : 0u;
         p1 += u < v1 ? 1u : 0u;
     }
@@ -1412,11 +1420,12 @@ __device__ __forceinline__ uint32_t lds_tile(uint32_t f, uint32_t tmax) {
 // the words.
 template <int R>
 __device__ __forceinline__ void count_lds(const uint32_t *xr, const uint32_t *base, uint32_t Wp,
-                                          uint32_t f, uint32_t src, uint32_t *dst, uint32_t *gx,
-                                          uint32_t tmax) {
+                                          uint32_t f, uint32_t r_cnt, uint32_t src, uint32_t *dst,
+                                          uint32_t *gx, uint32_t tmax) {
     const uint32_t lane = lane_id();
     const uint32_t T = lds_tile(f, tmax), CR = T / 4, stride = T + 4;
-    const uint32_t nb = (f + 3) / 4, P = nb * (nb + 1) / 2;
+    // blocks (A, B), A <= B, of the block rows A holding rows below r_cnt
+    const uint32_t nb = (f + 3) / 4, nbr = (r_cnt + 3) / 4, P = nbr * nb - nbr * (nbr - 1) / 2;
     uint32_t g = 1;
     if (R == 1)
         while (2 * g * P <= (uint32_t)kWave && g < T) g <<= 1;
@@ -1510,15 +1519,16 @@ __device__ __forceinline__ void count_lds(const uint32_t *xr, const uint32_t *ba
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 const uint32_t a = 4 * A[q] + i, b = 4 * B[q] + j;
-                if (a < b && b < f) gx[pair_index(a, b, f)] = acc[q][i * 4 + j];
+                if (a < b && b < f && a < r_cnt) gx[pair_index(a, b, f)] = acc[q][i * 4 + j];
             }
     }
 }
 
-// Pair supports of a class of f atoms (2 <= f <= kGramMax) into ws.gx.
+// Pair supports of a class of f atoms (2 <= f <= kGramMax) into ws.gx: the
+// pairs (a, b) of rows a < r_cnt at least (up to kRegGram atoms all pairs).
 __device__ __forceinline__ void count_class(const uint32_t *xr, const uint32_t *base, uint32_t Wp,
-                                            uint32_t f, uint32_t src, uint32_t *dst, uint32_t tmax,
-                                            WaveShared &ws) {
+                                            uint32_t f, uint32_t r_cnt, uint32_t src, uint32_t *dst,
+                                            uint32_t tmax, WaveShared &ws) {
     switch (f) {
         case 2: count_reg<2, 8>(xr, base, Wp, src, dst, ws.gx); break;
         case 3: count_reg<3, 4>(xr, base, Wp, src, dst, ws.gx); break;
@@ -1528,10 +1538,10 @@ __device__ __forceinline__ void count_class(const uint32_t *xr, const uint32_t *
         case 7: count_reg<7, 2>(xr, base, Wp, src, dst, ws.gx); break;
         case 8: count_reg<8, 2>(xr, base, Wp, src, dst, ws.gx); break;
         default: {
-            const uint32_t nb = (f + 3) / 4, P = nb * (nb + 1) / 2;
-            if (P <= (uint32_t)kWave) count_lds<1>(xr, base, Wp, f, src, dst, ws.gx, tmax);
-            else if (P <= 2u * kWave) count_lds<2>(xr, base, Wp, f, src, dst, ws.gx, tmax);
-            else count_lds<3>(xr, base, Wp, f, src, dst, ws.gx, tmax);
+            const uint32_t nb = (f + 3) / 4, nbr = (r_cnt + 3) / 4, P = nbr * nb - nbr * (nbr - 1) / 2;
+            if (P <= (uint32_t)kWave) count_lds<1>(xr, base, Wp, f, r_cnt, src, dst, ws.gx, tmax);
+            else if (P <= 2u * kWave) count_lds<2>(xr, base, Wp, f, r_cnt, src, dst, ws.gx, tmax);
+            else count_lds<3>(xr, base, Wp, f, r_cnt, src, dst, ws.gx, tmax);
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -1545,12 +1555,12 @@ __device__ __forceinline__ void sort_prefix_ids(uint32_t np, WaveShared &ws) {
     const uint32_t v1 = lane + kWave < np ? ws.pid[lane + kWave] : ~0u;
     uint32_t p0 = 0, p1 = 0;
     for (uint32_t q = 0; q < np && q < (uint32_t)kWave; q++) {
-        const uint32_t u = __shfl(v0, (int)q, kWave);
+        const uint32_t u = lane_val(v0, q);
         p0 += u < v0 ? 1u : 0u;
         p1 += u < v1 ? 1u : 0u;
     }
     for (uint32_t q = kWave; q < np; q++) {
-        const uint32_t u = __shfl(v1, (int)(q - kWave), kWave);
+        const uint32_t u = lane_val(v1, q - kWave);
         p0 += u < v0 ? 1u : 0u;
         p1 += u < v1 ? 1u : 0u;
     }
@@ -1591,6 +1601,27 @@ struct EmitTo {
 
 enum : uint32_t { kBuildOk = 0, kBuildStop = 1, kBuildFull = 2 };
 
+// Moves the key records gathered in LDS to the output arena: one atomic
+// reservation for all of them.
+__device__ __forceinline__ void flush_recs(WaveShared &ws, uint32_t *out, uint64_t out_cap,
+                                           DfsCounters *ctr) {
+    const uint32_t lane = lane_id();
+    const uint32_t n = uni(ws.n_recs);
+    if (n == 0) return;
+    unsigned long long b0 = 0;
+    if (lane == 0) b0 = atomicAdd(&ctr->out_used.v, 8ull * n);
+    const uint64_t base = bcast64(b0);
+    if (base + 8ull * n <= out_cap) {
+        uint4 *o = reinterpret_cast<uint4 *>(out + base);
+        for (uint32_t i = lane; i < 2 * n; i += kWave) gst4(o + i, ws.recs[i]);
+    } else if (lane == 0) {
+        atomicOr(&ctr->flags, kFlagOutOverflow);
+    }
+    if (lane == 0) ws.n_recs = 0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // ws.gx holds the supports of the f (f - 1) / 2 pairs of a class (pair_index
 // order) whose atom q is held by lane q (rank, support, item id; ws.cid[q] =
 // item id).  Below `meta` this writes the class's atom arrays, the size of
@@ -1599,36 +1630,51 @@ enum : uint32_t { kBuildOk = 0, kBuildStop = 1, kBuildFull = 2 };
 // (support, item id)); it reports the frequent pairs of rows a < r_emit as
 // the itemsets prefix + a + b.  meta moves down to the atom arrays.
 __device__ __forceinline__ uint32_t finish_class(const InstDesc &I, uint32_t inst, uint32_t task,
-                                                 uint32_t f, uint32_t rank, uint32_t supp, uint32_t id,
-                                                 const EmitTo &em, uint64_t rows_end, uint64_t &meta,
+                                                 uint32_t f, uint32_t r_cnt, uint32_t rank, uint32_t supp,
+                                                 uint32_t id, const EmitTo &em, uint64_t rows_end, uint64_t &meta,
                                                  uint32_t *region, uint64_t S, WaveShared &ws,
                                                  uint32_t *out, uint64_t out_cap, DfsCounters *ctr,
                                                  InstCounters *ictr, WaveStats &st, OutChunk &oc,
                                                  uint32_t &atoms_off, uint32_t &lists_off) {
     const uint32_t lane = lane_id();
     const uint32_t m = I.minsup;
-    const uint32_t NP = f * (f - 1) / 2;
-    // frequent later atoms of row `lane`
-    uint32_t cnt = 0;
-    if (lane < f)
-        for (uint32_t b = lane + 1; b < f; b++) cnt += ws.gx[pair_index(lane, b, f)] >= m ? 1u : 0u;
-    uint32_t incl = cnt;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t v = __shfl_up(incl, o, kWave);
-        if ((int)lane >= o) incl += v;
+    // pairs of the rows below r_cnt (the only ones counted), row after row
+    const uint32_t NP = r_cnt >= f - 1 ? f * (f - 1) / 2 : pair_index(r_cnt, r_cnt + 1, f);
+    // Frequent pairs, 64 at a time in pair_index order (row after row): all
+    // of them, and those of the rows that report (the pairs before row
+    // r_emit's first pair).
+    const uint32_t r_emit = min(em.r_emit, r_cnt);
+    const uint32_t emit_end = r_emit == 0 ? 0u : (r_emit >= f - 1 ? NP : pair_index(r_emit, r_emit + 1, f));
+    uint32_t nfreq = 0, n_emit = 0;
+    for (uint32_t p0 = 0; p0 < NP; p0 += kWave) {
+        const uint32_t p = p0 + lane;
+        const uint64_t mask = __ballot(p < NP && ws.gx[p] >= m);
+        nfreq += (uint32_t)__popcll(mask);
+        if (p0 < emit_end) {
+            const uint32_t k = min(emit_end - p0, (uint32_t)kWave);
+            n_emit += (uint32_t)__popcll(k == 64 ? mask : (mask & ((1ull << k) - 1)));
+        }
     }
-    const uint32_t excl = incl - cnt;
-    const uint32_t nfreq = uni(__shfl(incl, kWave - 1, kWave));
-    const uint32_t r_emit = min(em.r_emit, f);
-    const uint32_t n_emit = uni(r_emit == 0 ? 0u : __shfl(incl, (int)(r_emit - 1), kWave));
+    nfreq = uni(nfreq);
+    n_emit = uni(n_emit);
     const uint32_t len = em.np + 2;
     const bool report = n_emit > 0 && (I.max_len == 0 || len <= I.max_len);
     const bool keys = report && I.key_bits != 0 && I.class_count == nullptr && len * I.key_bits <= 128;
-    // the key records' place in the arena, reserved now so that the atomic's
-    // round trip overlaps the work below
+    // Key records are gathered in LDS (one reservation of the arena per
+    // kStageRecs records); a class with more records than that reserves its
+    // own place now, so that the atomic's round trip overlaps the work below.
+    bool staged = false;
+    uint32_t at = 0;  // first LDS slot of this class's records
     unsigned long long b0 = 0;
-    if (keys && lane == 0) b0 = atomicAdd(&ctr->out_used.v, 8ull * n_emit);
+    if (keys) {
+        if (n_emit <= kStageRecs) {
+            if (uni(ws.n_recs) + n_emit > kStageRecs) flush_recs(ws, out, out_cap, ctr);
+            at = uni(ws.n_recs);
+            staged = true;
+        } else if (lane == 0) {
+            b0 = atomicAdd(&ctr->out_used.v, 8ull * n_emit);
+        }
+    }
     // lists (16-byte aligned entries) and atom arrays below meta
     const uint64_t need = 4ull * (nfreq + kListPad) + 4ull * f + 4;
     if (meta < need || meta - need < rows_end) {
@@ -1638,11 +1684,18 @@ __device__ __forceinline__ uint32_t finish_class(const InstDesc &I, uint32_t ins
     const uint64_t lists = (meta - 4ull * (nfreq + kListPad)) & ~3ull;
     const uint64_t atoms = lists - 4ull * f;
     uint32_t *A = region + atoms;
+    if (lane == 0) {
+        ws.row0_n = 0;
+        ws.row0_rank = rank;
+        ws.row0_id = id;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
     if (lane < f) {
         gst(A + lane, rank);
         gst(A + f + lane, supp);
         gst(A + 2 * f + lane, id);
-        gst(A + 3 * f + lane, cnt);
+        if (lane >= r_cnt) gst(A + 3 * f + lane, 0u);  // rows not counted (and the last row)
     }
     // reporting
     const bool recs = report && I.key_bits == 0 && I.class_count == nullptr;
@@ -1657,21 +1710,26 @@ __device__ __forceinline__ uint32_t finish_class(const InstDesc &I, uint32_t ins
         if (lane == 0) atomicOr(&ctr->flags, kFlagKeyOverflow);
     } else if (keys) {
         sort_prefix_ids(em.np, ws);
-        kbase = bcast64(b0);
-        kvalid = kbase + 8ull * n_emit <= out_cap;
-        if (!kvalid && lane == 0) atomicOr(&ctr->flags, kFlagOutOverflow);
+        if (staged) {
+            kvalid = true;
+            if (lane == 0) ws.n_recs = at + n_emit;
+        } else {
+            kbase = bcast64(b0);
+            kvalid = kbase + 8ull * n_emit <= out_cap;
+            if (!kvalid && lane == 0) atomicOr(&ctr->flags, kFlagOutOverflow);
+        }
     } else if (recs) {
         rvalid = chunk_reserve(oc, n_emit * rec, task, inst, out, out_cap, ctr);
-    } else if (report && I.class_count) {
+    } else if (report && I.class_count && em.l2_row0 == kNone && lane == 0) {
         // estimate run: only the number of itemsets per second-level class
-        if (em.l2_row0 != kNone) {
-            if (lane < r_emit && cnt) atomicAdd(&I.class_count[em.l2_row0 + lane], (unsigned long long)cnt);
-        } else if (lane == 0) {
-            atomicAdd(&I.class_count[em.l2_cls], (unsigned long long)n_emit);
-        }
+        atomicAdd(&I.class_count[em.l2_cls], (unsigned long long)n_emit);
     }
-    // the entries, lane-parallel over the pairs
+    // the entries, lane-parallel over the pairs: pair (a, b) goes to row a's
+    // list at (frequent pairs before row a) + (its rank in row a by (support,
+    // item id)); the lane of a row's first pair writes the row's list size
     uint4 *L = reinterpret_cast<uint4 *>(region + lists);
+    const bool per_row_count = report && I.class_count && em.l2_row0 != kNone;
+    uint32_t before = 0;  // frequent pairs of the earlier chunks
     for (uint32_t p0 = 0; p0 < NP; p0 += kWave) {
         const uint32_t p = p0 + lane;
         uint32_t a = 0, b = 1, s = 0;
@@ -1680,42 +1738,66 @@ __device__ __forceinline__ uint32_t finish_class(const InstDesc &I, uint32_t ins
             s = ws.gx[p];
         }
         const bool fr = p < NP && s >= m;
-        const uint32_t off_a = __shfl(excl, (int)a, kWave);
+        const uint64_t mask = __ballot(fr);
         const uint32_t rank_b = __shfl(rank, (int)b, kWave);
         const uint32_t rank_a = __shfl(rank, (int)a, kWave);
-        if (fr) {
+        if (p < NP) {
             const uint32_t id_b = ws.cid[b];
             const uint64_t key = I.order_by_id ? (uint64_t)id_b : (((uint64_t)s << 32) | id_b);
-            uint32_t pos = 0;
+            // frequent pairs of row a: before b in the row, ahead of b in the
+            // list order, and in all
+            uint32_t k_before = 0, pos = 0, row_n = 0;
             for (uint32_t c = a + 1; c < f; c++) {
-                if (c == b) continue;
                 const uint32_t sc = ws.gx[pair_index(a, c, f)];
                 const uint32_t idc = ws.cid[c];
                 const uint64_t kc = I.order_by_id ? (uint64_t)idc : (((uint64_t)sc << 32) | idc);
-                pos += (sc >= m && kc < key) ? 1u : 0u;
+                const bool fc = sc >= m;
+                row_n += fc ? 1u : 0u;
+                k_before += (fc && c < b) ? 1u : 0u;
+                pos += (fc && c != b && kc < key) ? 1u : 0u;
             }
-            const uint32_t e = off_a + pos;
-            gst4(L + e, make_uint4(rank_b, s, b, id_b));
-            if (a < r_emit) {
-                if (kvalid) {
-                    const uint32_t id_a = ws.cid[a];
-                    unsigned long long hi, lo;
-                    pair_key(ws, em.np, I.key_bits, min(id_a, id_b), max(id_a, id_b), hi, lo);
-                    uint4 *o = reinterpret_cast<uint4 *>(out + kbase + 8ull * e);
-                    gst4(o, make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32)));
-                    gst4(o + 1, make_uint4(s, inst, 0u, 0u));
-                } else if (rvalid) {
-                    uint32_t *o = out + oc.base + oc.pos + (uint64_t)e * rec;
-                    o[0] = len;
-                    o[1] = s;
-                    for (uint32_t q = 0; q < em.np; q++) o[2 + q] = ws.prefix[q];
-                    o[2 + em.np] = rank_a;
-                    o[3 + em.np] = rank_b;
+            if (b == a + 1) {
+                gst(A + 3 * f + a, row_n);
+                if (a == 0) ws.row0_n = row_n;
+                if (per_row_count && a < r_emit && row_n)
+                    atomicAdd(&I.class_count[em.l2_row0 + a], (unsigned long long)row_n);
+            }
+            if (fr) {
+                const uint32_t e = before + lanes_below(mask) - k_before + pos;
+                const uint4 entry = make_uint4(rank_b, s, b, id_b);
+                gst4(L + e, entry);
+                if (a == 0) ws.row0[pos] = entry;  // row 0 is expanded next
+                if (a < r_emit) {
+                    if (kvalid) {
+                        const uint32_t id_a = ws.cid[a];
+                        unsigned long long hi, lo;
+                        pair_key(ws, em.np, I.key_bits, min(id_a, id_b), max(id_a, id_b), hi, lo);
+                        const uint4 k0 = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+                        const uint4 k1 = make_uint4(s, inst, 0u, 0u);
+                        if (staged) {
+                            ws.recs[2 * (at + e)] = k0;
+                            ws.recs[2 * (at + e) + 1] = k1;
+                        } else {
+                            uint4 *o = reinterpret_cast<uint4 *>(out + kbase + 8ull * e);
+                            gst4(o, k0);
+                            gst4(o + 1, k1);
+                        }
+                    } else if (rvalid) {
+                        uint32_t *o = out + oc.base + oc.pos + (uint64_t)e * rec;
+                        o[0] = len;
+                        o[1] = s;
+                        for (uint32_t q = 0; q < em.np; q++) o[2 + q] = ws.prefix[q];
+                        o[2 + em.np] = rank_a;
+                        o[3 + em.np] = rank_b;
+                    }
                 }
             }
         }
+        before += (uint32_t)__popcll(mask);
     }
     if (recs) oc.pos += n_emit * rec;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
     meta = atoms;
     atoms_off = (uint32_t)atoms;
     lists_off = (uint32_t)lists;
@@ -1792,6 +1874,7 @@ __device__ __forceinline__ void search(const InstDesc &I, uint32_t inst, uint32_
     }
 
     uint32_t polls = 0, cool = 0, iters = 0;
+    int row0_depth = -1;  // the frame whose row 0 child class is in ws.row0
     for (;;) {
         if (build) {
             // ---- count the class while building it, list its rows' child classes, push it
@@ -1806,14 +1889,14 @@ __device__ __forceinline__ void search(const InstDesc &I, uint32_t inst, uint32_
             if (lane < c) ws.cid[lane] = b_id;
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            count_class(b_xr, b_base, Wp, c, b_src, b_write ? region + rows_top : nullptr, tmax, ws);
-            st.pair_words += (unsigned long long)(c * (c - 1) / 2) * Wp;
+            count_class(b_xr, b_base, Wp, c, b_r_end, b_src, b_write ? region + rows_top : nullptr, tmax, ws);
+            st.pair_words += (unsigned long long)(b_r_end * c - b_r_end * (b_r_end + 1) / 2) * Wp;
             if (depth >= 0) {
                 st.row_words += (unsigned long long)c * Wp;
                 st.child_rows += b_write ? c : 0u;
             }
             uint32_t ao = 0, lo = 0;
-            if (finish_class(I, inst, task, c, b_rank, b_supp, b_id, b_em, rows_top + rows_need, meta, region,
+            if (finish_class(I, inst, task, c, b_r_end, b_rank, b_supp, b_id, b_em, rows_top + rows_need, meta, region,
                              S, ws, out, out_cap, ctr, ictr, st, oc, ao, lo) != kBuildOk)
                 break;
             if (lane == 0)
@@ -1822,6 +1905,7 @@ __device__ __forceinline__ void search(const InstDesc &I, uint32_t inst, uint32_
             __builtin_amdgcn_wave_barrier();
             rows_top += rows_need;
             depth++;
+            row0_depth = depth;
             const uint64_t use = rows_top + (S - meta);
             if (use > peak) peak = use;
             continue;
@@ -1856,10 +1940,21 @@ __device__ __forceinline__ void search(const InstDesc &I, uint32_t inst, uint32_
         const uint32_t *A = region + F.atoms;
         const uint32_t np = plen + (uint32_t)depth + 1;  // prefix of row r's child class
         if (F.lists != kNone) {
-            // the row's child class, its rank and its item id, in one round
-            const uint32_t c = uni(gld(A + 3 * F.k + r));
-            const uint32_t rank_r = uni(gld(A + r)), id_r = uni(gld(A + 2 * F.k + r));
-            const uint4 e = gld4(reinterpret_cast<const uint4 *>(region + F.lists) + F.lpos + lane);
+            // the row's child class, its rank and its item id: from LDS for
+            // row 0 of the class built last, else in one round of loads
+            uint32_t c, rank_r, id_r;
+            uint4 e;
+            if (r == 0 && depth == row0_depth) {
+                c = uni(ws.row0_n);
+                rank_r = uni(ws.row0_rank);
+                id_r = uni(ws.row0_id);
+                e = ws.row0[lane];
+            } else {
+                c = uni(gld(A + 3 * F.k + r));
+                rank_r = uni(gld(A + r));
+                id_r = uni(gld(A + 2 * F.k + r));
+                e = gld4(reinterpret_cast<const uint4 *>(region + F.lists) + F.lpos + lane);
+            }
             if (lane == 0) {
                 ws.frames[depth].r = r + 1;
                 ws.frames[depth].lpos = F.lpos + c;
@@ -2337,6 +2432,7 @@ __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Tas
     const uint32_t w = uni(threadIdx.x / kWave);
     const uint32_t lane = lane_id();
     WaveShared &ws = shared[w];
+    if (lane == 0) ws.n_recs = 0;
     const uint64_t wave_id = (uint64_t)blockIdx.x * kWavesPerBlock + w;
     uint32_t *region = stack + wave_id * stack_words;
     unsigned long long busy = 0;
@@ -2477,6 +2573,7 @@ __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Tas
                 search(I, inst, task, fs.plen, fs.l2_ref, Wp, fs.k, fs.r_end, fs.reported, meta,
                        (S - low) + (uint64_t)fs.k * Wp, tmax, region, S, ws, out, out_cap, ctr, ictr, st,
                        oc, dn);
+            flush_recs(ws, out, out_cap, ctr);
             close_chunk(oc, out);
             busy += wall_clock64() - c0;
             flush_stats(I, ictr, inst, st);
