@@ -424,13 +424,41 @@ def serve_leg(F, ctx, args, seconds):
 
 # ---------------------------------------------------------------- estimator study
 
+def share_errors(F, n_atoms, weights, actual, n_workers, alpha=0.3):
+    """The thesis's experiment on each processor's share of the work, for a
+    static plan: the classes are split by Partition and scheduled by LPT on
+    n_workers workers with the given per-row weights; returns the largest
+    and mean |estimated share - actual share| over the workers (the actual
+    share from the rows' real candidate pairs) and the actual makespan over
+    the mean load (1.0 = perfect balance)."""
+    import numpy as np
+    tasks, _ = F.fim_partition_lpt(n_atoms, weights, alpha, n_workers)
+    start = np.concatenate([[0], np.cumsum(np.asarray(n_atoms, dtype=np.int64))])
+    cw = np.concatenate([[0.0], np.cumsum(np.asarray(weights, dtype=np.float64))])
+    ca = np.concatenate([[0.0], np.cumsum(np.asarray(actual, dtype=np.float64))])
+    est = np.array([cw[start[c] + r1] - cw[start[c] + r0] for c, r0, r1 in tasks])
+    act = np.array([ca[start[c] + r1] - ca[start[c] + r0] for c, r0, r1 in tasks])
+    if len(tasks) == 0 or est.sum() <= 0 or act.sum() <= 0:
+        return None
+    worker, _ = F.fim_lpt_schedule(est, n_workers)
+    e = np.bincount(worker, weights=est, minlength=n_workers) / est.sum()
+    a = np.bincount(worker, weights=act, minlength=n_workers) / act.sum()
+    return {"max_abs_err": float(np.abs(e - a).max()), "mean_abs_err": float(np.abs(e - a).mean()),
+            "actual_makespan_over_mean": float(a.max() * n_workers), "tasks": int(len(tasks))}
+
+
 def study(F, ctx, args):
-    """The estimate's effect on the persistent kernel (an analogue of the
-    thesis's experiment on estimated against actual per-processor work):
-    each workload mined with the sample estimate (in-run counts, and the
-    reservoir variant), with the C(k, 2) proxy instead, and with whole
-    first-level classes; per policy the call and kernel times and the
-    busiest wave's busy time over the mean one."""
+    """The sample-based class-size estimate against the actual work, the
+    thesis's experiment on each processor's share carried over to the waves
+    of one GPU.  Per workload: (1) call and kernel times with the estimate
+    (counted in the run, or the reservoir variant), with the bitonic
+    scheduling's C(n, 2) weight in its place and without splitting; (2) from
+    one class profile (per second-level class: the sample's frequent
+    itemsets, the sample's candidate pairs, the run's own candidate pairs),
+    the static plan's share error and balance for P = 10, 20 (the thesis's
+    processor counts) and 1024 (the waves) under three weights: the
+    estimate (sampled frequent itemsets), sampled candidate pairs, and
+    C(n, 2) of the class's n atoms."""
     import numpy as np
 
     import synth
@@ -446,7 +474,7 @@ def study(F, ctx, args):
     out = {}
     for name, db in loads:
         d = F.Database(ctx, db.offsets, db.items, db.n_items)
-        row = {}
+        row = {"policies": {}}
         for pol, flags in policies.items():
             walls, st = [], None
             for rep in range(4):
@@ -454,11 +482,24 @@ def study(F, ctx, args):
                 r = F.mine(ctx, d, db.minsup, flags=flags)
                 walls.append(time.perf_counter() - t0)
                 st = r.stats
-            row[pol] = {"wall_ms": float(np.median(walls[1:]) * 1e3),
-                        "dfs_ms": st["dfs_kernel_ns"] / 1e6, "estimate_ms": st["estimate_ns"] / 1e6,
-                        "imbalance": st["dfs_busy_max_ns"] / max(st["dfs_busy_mean_ns"], 1),
-                        "tasks": st["n_tasks"]}
-            log("study", name, pol, row[pol])
+            row["policies"][pol] = {
+                "wall_ms": float(np.median(walls[1:]) * 1e3),
+                "dfs_ms": st["dfs_kernel_ns"] / 1e6, "estimate_ms": st["estimate_ns"] / 1e6,
+                "imbalance": st["dfs_busy_max_ns"] / max(st["dfs_busy_mean_ns"], 1),
+                "tasks": st["n_tasks"]}
+            log("study", name, pol, row["policies"][pol])
+        prof = F.class_profile(ctx, d, db.minsup)
+        na = prof["n_atoms"]
+        later = np.concatenate([np.arange(int(k) - 1, -1, -1) for k in na]) if len(na) else np.zeros(0)
+        weights = {"estimate_fi": prof["est_fi"], "estimate_candidates": prof["est_cand"],
+                   "pairs_C(n,2)": later * (later - 1) / 2.0}
+        act = prof["act_cand"].astype(np.float64)
+        row["share_error"] = {}
+        for wname, w in weights.items():
+            row["share_error"][wname] = {str(P): share_errors(F, na, w, act, P) for P in (10, 20, 1024)}
+            log("study", name, wname, row["share_error"][wname])
+        row["classes"] = {"first_level": int(len(na)), "second_level": int(len(act)),
+                          "candidates_below_root": float(act.sum())}
         out[name] = row
         d.close()
     return out

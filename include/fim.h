@@ -146,10 +146,11 @@ fim_status fim_minsup_from_relative(uint64_t n_tx, double rel, uint32_t *out_abs
 #define FIM_FLAG_ORDER_BY_ID 0x2u  /* extensions ordered by item id, not ascending support */
 #define FIM_FLAG_NO_SPLIT 0x4u     /* never split first-level classes */
 /* draw the database sample even when the classes below the root hold under
- * 1/20 of the root class's candidate pairs, or the database has fewer than
- * 16 |D~| transactions (by default the sample is then skipped: there is no
- * work worth balancing, or mining the sample would cost about as much as
- * mining the database) */
+ * 1/20 of the root class's candidate pairs, the database has fewer than
+ * 16 |D~| transactions, or the launch holds more than one instance (by
+ * default the sample is then skipped: there is no work worth balancing,
+ * mining the sample would cost about as much as the better order saves, or
+ * the other instances' work fills the idle waves) */
 #define FIM_FLAG_ALWAYS_ESTIMATE 0x8u
 /*
  * The root class (all pairs of frequent items) has three exact kernels; by
@@ -420,6 +421,32 @@ fim_status fim_lpt_schedule(const double *weights, uint64_t n_jobs, uint32_t n_w
 fim_status fim_autotune(fim_ctx *ctx, uint32_t n, const fim_db *const *dbs,
                         const uint32_t *minsups, const fim_options *base, uint32_t reps,
                         fim_options *out, uint64_t *best_ns);
+
+/*
+ * Class profile of one mining run, for studying the class-size estimate
+ * (the thesis's experiments on the error of the estimated size of
+ * prefix-based classes and of each processor's share of the work, chapter
+ * "Experimental evaluation"): mines db as fim_mine does with the sample
+ * estimate forced (FIM_FLAG_ALWAYS_ESTIMATE; FIM_FLAG_NO_ESTIMATE and
+ * FIM_FLAG_RESERVOIR are cleared) and reports
+ *   n_atoms[*n_classes]  atoms of every first-level class (frequent items in
+ *                        ascending (support, item id) order), and for every
+ *                        second-level class (row r of first-level class c;
+ *                        the rows of the classes one after the other,
+ *                        *n_rows in all):
+ *   est_fi[k]            frequent itemsets of three or more items the
+ *                        sample found below that class (the estimate's
+ *                        weight; 0 where the instance drew no sample),
+ *   est_cand[k]          candidate pairs the sample counted below it,
+ *   act_cand[k]          candidate pairs the run itself counted below it.
+ * Any array may be NULL.  Errors: as fim_mine; FIM_E_OUTPUT_LIMIT when
+ * class_capacity or row_capacity is too small (*n_classes and *n_rows then
+ * hold the sizes needed).
+ */
+fim_status fim_class_profile(fim_ctx *ctx, const fim_db *db, uint32_t minsup_abs,
+                             const fim_options *opts, uint32_t *n_classes, uint32_t *n_atoms,
+                             uint32_t class_capacity, uint64_t *n_rows, double *est_fi,
+                             double *est_cand, uint64_t *act_cand, uint64_t row_capacity);
 
 /* ------------------------------------------------------------------ */
 /* Serving (continuous batching)                                      */

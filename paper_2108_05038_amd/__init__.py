@@ -53,7 +53,7 @@ EXPORTED = [
     "fim_result_destroy", "fim_server_create", "fim_server_submit", "fim_server_poll",
     "fim_server_wait", "fim_server_next", "fim_server_cancel", "fim_server_stats_get", "fim_server_destroy",
     "fim_estimate_sample_sizes", "fim_reservoir_sample", "fim_partition_lpt", "fim_lpt_schedule",
-    "fim_mine_noalloc",
+    "fim_mine_noalloc", "fim_class_profile",
 ]
 
 FIM_NOALLOC_SCRATCH_BYTES = 256 << 20
@@ -155,6 +155,8 @@ def lib():
         "fim_lpt_schedule": (i32, [P(ctypes.c_double), u64, u32, P(u32), P(ctypes.c_double)]),
         "fim_mine_noalloc": (i32, [V, V, u32, P(fim_options), u64, u64, P(u64), P(u32), P(u32),
                                    P(u64), P(u64)]),
+        "fim_class_profile": (i32, [V, V, u32, P(fim_options), P(u32), P(u32), u32, P(u64),
+                                    P(ctypes.c_double), P(ctypes.c_double), P(u64), u64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -452,6 +454,31 @@ def mine_noalloc(ctx: Context, db: Database, minsup: int, cap_itemsets: int, cap
                                                    cap_items, o)
     _check(st)
     return off[:n + 1], items[:ni], supp[:n]
+
+
+def class_profile(ctx: Context, db: Database, minsup: int, **opts) -> dict:
+    """``fim_class_profile``: atoms per first-level class and, per
+    second-level class, the sample's frequent itemsets and candidate pairs
+    and the run's own candidate pairs."""
+    o = make_options(**opts) if opts else None
+    cap_c, cap_r = 1 << 16, 1 << 22
+    while True:
+        nc, nr = ctypes.c_uint32(), ctypes.c_uint64()
+        atoms = np.zeros(cap_c, np.uint32)
+        efi = np.zeros(cap_r, np.float64)
+        ecand = np.zeros(cap_r, np.float64)
+        act = np.zeros(cap_r, np.uint64)
+        st = lib().fim_class_profile(ctx.handle, db.handle, minsup, ctypes.byref(o) if o else None,
+                                     ctypes.byref(nc), _u32p(atoms), cap_c, ctypes.byref(nr),
+                                     efi.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     ecand.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     _u64p(act), cap_r)
+        if st == FIM_E_OUTPUT_LIMIT and (nc.value > cap_c or nr.value > cap_r):
+            cap_c, cap_r = max(cap_c, nc.value), max(cap_r, nr.value)
+            continue
+        _check(st)
+        n, k = nc.value, nr.value
+        return {"n_atoms": atoms[:n], "est_fi": efi[:k], "est_cand": ecand[:k], "act_cand": act[:k]}
 
 
 def mine_batch(ctx: Context, dbs, minsups, **opts):

@@ -217,4 +217,17 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
 // Resolved option values.
 fim_options resolve_options(const fim_options *opts);
 
+// Per second-level class figures of one run, gathered while a caller asks
+// for them (fim_class_profile): the first-level classes' atom counts (rank
+// order), and per second-level class (row r of first-level class c, rows of
+// the classes in order) the sample's frequent itemsets of three or more
+// items and its candidate pairs below that class, and the run's own
+// candidate pairs below it.
+struct ClassProfile {
+    std::vector<uint32_t> n_atoms;
+    std::vector<double> est_fi, est_cand;
+    std::vector<uint64_t> act_cand;
+};
+extern thread_local ClassProfile *g_profile;
+
 }  // namespace fim

@@ -40,6 +40,9 @@ struct InstDesc {
     // estimate run: itemsets counted per second-level class (l2 atom index)
     // instead of reported; null in a mining run
     unsigned long long *class_count;
+    // candidate pairs per second-level class (a class profile is asked
+    // for), else null
+    unsigned long long *row_cand;
     // key mode (> 0): every itemset is written as an 8-word record holding
     // its item ids ascending as (id + 1) codes of key_bits bits in a 128-bit
     // key, its support and the instance (the arena is then a flat array of

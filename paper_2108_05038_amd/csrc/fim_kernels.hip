@@ -1966,6 +1966,8 @@ __device__ __forceinline__ void search(const InstDesc &I, uint32_t inst, uint32_
             st.candidates += nj;
             if (F.k > st.max_k) st.max_k = F.k;
             if ((unsigned long long)depth > st.max_depth) st.max_depth = depth;
+            if (I.row_cand && nj && lane == 0)
+                atomicAdd(&I.row_cand[l2_class(plen, l2_ref, depth, r, ws)], (unsigned long long)nj);
             if (c < 2 || (I.max_len != 0 && np + 2 > I.max_len)) continue;
             if (depth + 1 >= kMaxDepth || np + 2 > kMaxDepth + 2) {
                 if (lane == 0) atomicOr(&ctr->flags, kFlagDepthOverflow);
@@ -2026,6 +2028,8 @@ __device__ __forceinline__ void search(const InstDesc &I, uint32_t inst, uint32_
         }
         st.candidates += nj;
         st.pair_words += (unsigned long long)nj * Wp;
+        if (I.row_cand && lane == 0)
+            atomicAdd(&I.row_cand[l2_class(plen, l2_ref, depth, r, ws)], (unsigned long long)nj);
         if (F.k > st.max_k) st.max_k = F.k;
         if ((unsigned long long)depth > st.max_depth) st.max_depth = depth;
         if (nf == 0) continue;

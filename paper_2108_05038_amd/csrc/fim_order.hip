@@ -10,7 +10,8 @@
 // (instance, key) with three stable radix passes (key low half, key high
 // half, instance) and reading the items back out of the keys gives every
 // instance's result as CSR, without the host touching a record.
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include "fim_host.h"
 
@@ -137,20 +138,19 @@ fim_status gpu_order(fim_ctx *ctx, hipStream_t s, const uint32_t *d_rec, uint64_
     OCHK(hipGetLastError());
     // temporary storage of the largest pass
     size_t tb = 0, t1 = 0;
-    OCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, t1, lo.as<unsigned long long>(),
+    OCHK(rocprim::radix_sort_pairs(nullptr, t1, lo.as<unsigned long long>(),
                                             lo2.as<unsigned long long>(), idx.as<uint32_t>(),
                                             idx2.as<uint32_t>(), ni, 0, 64, s));
     tb = std::max(tb, t1);
-    OCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, t1, inst.as<uint32_t>(), inst2.as<uint32_t>(),
+    OCHK(rocprim::radix_sort_pairs(nullptr, t1, inst.as<uint32_t>(), inst2.as<uint32_t>(),
                                             idx.as<uint32_t>(), idx2.as<uint32_t>(), ni, 0, 32, s));
     tb = std::max(tb, t1);
-    OCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, t1, len.as<uint32_t>(),
-                                          ioff.as<unsigned long long>(), ni + 1, s));
+    OCHK(rocprim::exclusive_scan(nullptr, t1, len.as<uint32_t>(), ioff.as<unsigned long long>(), 0ull, (size_t)(ni + 1), rocprim::plus<unsigned long long>(), s));
     tb = std::max(tb, t1);
     OENSURE(tmp, std::max<size_t>(tb, 16));
     size_t tbytes = tmp.bytes();
     // pass 1: low half of the key
-    OCHK(hipcub::DeviceRadixSort::SortPairs(tmp.as<void>(), tbytes, lo.as<unsigned long long>(),
+    OCHK(rocprim::radix_sort_pairs(tmp.as<void>(), tbytes, lo.as<unsigned long long>(),
                                             lo2.as<unsigned long long>(), idx.as<uint32_t>(),
                                             idx2.as<uint32_t>(), ni, 0, 64, s));
     // pass 2: high half, in the order of pass 1 (stable)
@@ -159,7 +159,7 @@ fim_status gpu_order(fim_ctx *ctx, hipStream_t s, const uint32_t *d_rec, uint64_
                        lo.as<unsigned long long>());
     OCHK(hipGetLastError());
     tbytes = tmp.bytes();
-    OCHK(hipcub::DeviceRadixSort::SortPairs(tmp.as<void>(), tbytes, lo.as<unsigned long long>(),
+    OCHK(rocprim::radix_sort_pairs(tmp.as<void>(), tbytes, lo.as<unsigned long long>(),
                                             lo2.as<unsigned long long>(), idx2.as<uint32_t>(),
                                             idx.as<uint32_t>(), ni, 0, 64, s));
     // pass 3: instance (a batch), in the order of pass 2
@@ -170,7 +170,7 @@ fim_status gpu_order(fim_ctx *ctx, hipStream_t s, const uint32_t *d_rec, uint64_
                            inst.as<uint32_t>(), idx.as<uint32_t>(), n, inst2.as<uint32_t>());
         OCHK(hipGetLastError());
         tbytes = tmp.bytes();
-        OCHK(hipcub::DeviceRadixSort::SortPairs(tmp.as<void>(), tbytes, inst2.as<uint32_t>(),
+        OCHK(rocprim::radix_sort_pairs(tmp.as<void>(), tbytes, inst2.as<uint32_t>(),
                                                 inst.as<uint32_t>(), idx.as<uint32_t>(),
                                                 idx2.as<uint32_t>(), ni, 0, (int)ib, s));
         std::swap(idx, idx2);
@@ -182,8 +182,7 @@ fim_status gpu_order(fim_ctx *ctx, hipStream_t s, const uint32_t *d_rec, uint64_
                        idx.as<uint32_t>(), n, d_bits.as<uint32_t>(), len.as<uint32_t>());
     OCHK(hipGetLastError());
     tbytes = tmp.bytes();
-    OCHK(hipcub::DeviceScan::ExclusiveSum(tmp.as<void>(), tbytes, len.as<uint32_t>(),
-                                          ioff.as<unsigned long long>(), ni + 1, s));
+    OCHK(rocprim::exclusive_scan(tmp.as<void>(), tbytes, len.as<uint32_t>(), ioff.as<unsigned long long>(), 0ull, (size_t)(ni + 1), rocprim::plus<unsigned long long>(), s));
     // The item count is known on the device only.  A small result is
     // decoded into room for the most items its keys can hold and copied
     // without waiting for the count (the host arrays are cut to it after);

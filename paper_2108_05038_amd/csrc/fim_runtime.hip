@@ -22,6 +22,7 @@ using fim::DevBuf;
 namespace fim {
 
 static thread_local std::string g_error;
+thread_local ClassProfile *g_profile = nullptr;
 
 fim_status set_error(fim_status s, const std::string &msg) {
     g_error = msg;
@@ -866,12 +867,20 @@ static fim_status run_persistent(fim_ctx *ctx, hipStream_t s, Tracer &tr,
     return FIM_OK;
 }
 
+// Longest itemset of the sample the estimate counts (see count_estimate):
+// the sample is searched to itemsets of four items, so that its cost stays
+// a fraction of the run's (measured on dense-50k: searched to the bottom it
+// took 5.7 ms against 1.4 ms, for a plan that saved 1.1 ms more of kernel
+// time).
+static constexpr uint32_t kSampleMaxLen = 4;
+
 // Phase 1 inside the run: for every instance to estimate, a sample of
 // |D~| transactions drawn with replacement is turned into bitmaps over the
 // instance's own frequent items, and the persistent kernel mines it on the
 // instance's own first-level classes (the same atoms, in the same order) at
-// the relative minimum support, counting every frequent itemset of length
-// >= 3 into its second-level class instead of reporting it.  row_w[q] gets
+// the relative minimum support, counting every frequent itemset of 3 to
+// kSampleMaxLen items into its second-level class instead of reporting it;
+// one task per second-level class.  row_w[q] gets
 // count x words per row for every second-level class of instance q (empty
 // when the instance has no estimate); out_words the sample's record words.
 static fim_status count_estimate(fim_ctx *ctx, hipStream_t s, Tracer &tr, std::vector<Inst> &insts,
@@ -937,32 +946,45 @@ static fim_status count_estimate(fim_ctx *ctx, hipStream_t s, Tracer &tr, std::v
         D.n_freq = I.n_freq;
         // relative minimum support carried over to the sample, at least 2
         D.minsup = std::max<uint32_t>(2, (uint32_t)ceil((double)I.minsup * (double)nd / (double)N));
-        D.max_len = 0;
+        D.max_len = kSampleMaxLen;
         D.order_by_id = (opts.flags & FIM_FLAG_ORDER_BY_ID) ? 1u : 0u;
         D.project = (opts.flags & FIM_FLAG_NO_PROJECT) ? 0u : 1u;
         D.rec_budget = kSampleRecordBudget;
         used[q] = true;
         max_chunks = std::max(max_chunks, Wps / 4);
+        // one task per second-level class (row of a first-level class), so
+        // that the sample's wide classes spread over the waves
         for (uint32_t i = 0; i < I.n_freq; i++) {
             const uint32_t f = I.l2_off[i + 1] - I.l2_off[i];
             if (f < 2) continue;
-            tasks.push_back(Task{q, i, 0, f - 1});
+            for (uint32_t r = 0; r + 1 < f; r++) tasks.push_back(Task{q, i, r, r + 1});
             frame0 = std::max<uint64_t>(frame0, (uint64_t)f * Wps + 3ull * f);
         }
     }
     if (tasks.empty()) return FIM_OK;
-    // largest classes first
-    std::stable_sort(tasks.begin(), tasks.end(),
-                     [&](const Task &a, const Task &b) { return a.r1 > b.r1; });
+    // most later atoms first
+    std::stable_sort(tasks.begin(), tasks.end(), [&](const Task &a, const Task &b) {
+        return insts[a.inst].l2_off[a.node + 1] - insts[a.inst].l2_off[a.node] - a.r0 >
+               insts[b.inst].l2_off[b.node + 1] - insts[b.inst].l2_off[b.node] - b.r0;
+    });
     DevBuf d_count(ctx), d_out(ctx);
     ENSURE(d_count, ctx, std::max<uint64_t>(count_at[n_inst], 1) * 8);
     HIPCHK(launch_fill_u32(d_count.as<uint32_t>(), std::max<uint64_t>(count_at[n_inst], 1) * 2, 0u, s));
     for (uint32_t q = 0; q < n_inst; q++)
         if (used[q]) desc[q].class_count = d_count.as<unsigned long long>() + count_at[q];
+    DevBuf d_pcand(ctx);  // a class profile: the sample's candidate pairs per class
+    if (g_profile) {
+        ENSURE(d_pcand, ctx, std::max<uint64_t>(count_at[n_inst], 1) * 8);
+        HIPCHK(launch_fill_u32(d_pcand.as<uint32_t>(), std::max<uint64_t>(count_at[n_inst], 1) * 2, 0u, s));
+        for (uint32_t q = 0; q < n_inst; q++)
+            if (used[q]) desc[q].row_cand = d_pcand.as<unsigned long long>() + count_at[q];
+    }
     DfsLaunch L;
     L.frame0 = frame0;
     L.variant = dfs_variant(max_chunks);
     L.n_workers = std::max<uint32_t>(4, dfs_resident_workers(ctx->n_cu, L.variant) / 4 * 4);
+    // about one wave per eight small tasks, as in the main run
+    L.n_workers = std::min<uint32_t>(L.n_workers, std::max<uint32_t>(256, (uint32_t)(tasks.size() / 8 + 3) / 4 * 4));
     L.nap_max = 64;
     L.cap_output = true;
     L.stop_is_error = false;
@@ -971,10 +993,18 @@ static fim_status count_estimate(fim_ctx *ctx, hipStream_t s, Tracer &tr, std::v
     sub.on = tr.on;
     fim_status st = run_persistent(ctx, s, sub, desc, tasks, d_out, L);
     if (st != FIM_OK) return st;
-    std::vector<unsigned long long> cnt(count_at[n_inst]);
+    std::vector<unsigned long long> cnt(count_at[n_inst]), pcand;
     if (!cnt.empty())
         HIPCHK(hipMemcpyAsync(cnt.data(), d_count.as<void>(), cnt.size() * 8, hipMemcpyDeviceToHost, s));
+    if (g_profile && !cnt.empty()) {
+        pcand.resize(cnt.size());
+        HIPCHK(hipMemcpyAsync(pcand.data(), d_pcand.as<void>(), pcand.size() * 8, hipMemcpyDeviceToHost, s));
+    }
     HIPCHK(stream_wait(s));
+    if (g_profile && n_inst == 1 && used[0]) {
+        g_profile->est_fi.assign(cnt.begin(), cnt.begin() + count_at[1]);
+        g_profile->est_cand.assign(pcand.begin(), pcand.begin() + count_at[1]);
+    }
     for (uint32_t q = 0; q < n_inst; q++) {
         if (!used[q] || L.ictr[q].stop) continue;  // exploded sample: no estimate
         const Inst &I = insts[q];
@@ -1387,16 +1417,20 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                 below += f * (f ? f - 1 : 0) / 2;
             }
             const uint64_t root = (uint64_t)I.n_freq * (I.n_freq ? I.n_freq - 1 : 0) / 2;
-            // The sample has about as many frequent itemsets as the database
-            // (same relative support), and the persistent kernel's time on
-            // narrow rows goes mostly to latency, so mining the sample costs
-            // a large part of mining the database; with work shared between
-            // the waves at run time the better order saves less than that
-            // on every workload measured (up to 200,000 = 43 |D~|
-            // transactions).  The estimate is drawn for at least 64 |D~|.
+            // The sample is searched to itemsets of kSampleMaxLen items, one
+            // task per second-level class; its cost is then a few times the
+            // time of a sample-sized search, and it pays where the database
+            // is much longer than the sample (measured: dense-200k = 43 |D~|
+            // 54.8 ms with it against 62.8 ms without; dense-50k = 13 |D~|
+            // 12.1 ms with it against 11.1 ms without).  It is drawn for at
+            // least 16 |D~| transactions, and only for a launch of one
+            // instance: in a batch the other instances' classes fill the
+            // waves that one instance's imbalance leaves idle (measured: 256
+            // basket instances of log-uniform sizes, 113 ms with samples
+            // drawn against 75 ms without).
             const uint64_t want_tx = opts.sample_tx ? opts.sample_tx : default_sample_tx(0.02, 0.05);
             pin[q].estimate = (opts.flags & FIM_FLAG_ALWAYS_ESTIMATE) ||
-                              (20 * below >= root && I.db->n_tx >= 64 * want_tx);
+                              (20 * below >= root && n_inst == 1 && I.db->n_tx >= 16 * want_tx);
             deep_work = deep_work || 20 * below >= root;
         }
         fim_status ps = FIM_OK;
@@ -1580,7 +1614,23 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             L.prefix_rec = at;
             L.out_cap = std::max<uint64_t>(L.out_cap, 16 * at);
         }
+        DevBuf d_act(ctx);  // a class profile: the run's candidate pairs per class
+        if (g_profile && n_inst == 1 && !sample_run) {
+            const uint64_t nr = std::max<uint64_t>(insts[0].l2_atom.size(), 1);
+            ENSURE(d_act, ctx, nr * 8);
+            HIPCHK(launch_fill_u32(d_act.as<uint32_t>(), nr * 2, 0u, s));
+            desc[0].row_cand = d_act.as<unsigned long long>();
+        }
         fim_status ls = run_persistent(ctx, s, tr, desc, tasks, d_out, L);
+        if (ls == FIM_OK && g_profile && n_inst == 1 && !sample_run) {
+            const Inst &I0 = insts[0];
+            g_profile->act_cand.assign(I0.l2_atom.size(), 0);
+            if (!I0.l2_atom.empty())
+                HIPCHK(hipMemcpy(g_profile->act_cand.data(), d_act.as<void>(), I0.l2_atom.size() * 8,
+                                 hipMemcpyDeviceToHost));
+            g_profile->n_atoms.assign(I0.n_freq, 0);
+            for (uint32_t i = 0; i < I0.n_freq; i++) g_profile->n_atoms[i] = I0.l2_off[i + 1] - I0.l2_off[i];
+        }
         if (ls != FIM_OK) return ls;
         if (key_mode && (L.ctr.flags & kFlagKeyOverflow)) {
             // an itemset longer than a key holds: the same call with records
@@ -1965,5 +2015,33 @@ extern "C" fim_status fim_autotune(fim_ctx *ctx, uint32_t n, const fim_db *const
     out->tile_words = best_t;
     out->classes_per_wg = best_c;
     if (best_ns) *best_ns = best;
+    return FIM_OK;
+}
+
+extern "C" fim_status fim_class_profile(fim_ctx *ctx, const fim_db *db, uint32_t minsup_abs,
+                                        const fim_options *opts, uint32_t *n_classes, uint32_t *n_atoms,
+                                        uint32_t class_capacity, uint64_t *n_rows, double *est_fi,
+                                        double *est_cand, uint64_t *act_cand, uint64_t row_capacity) {
+    if (!ctx || !db || !n_classes || !n_rows || minsup_abs == 0)
+        return fim::set_error(FIM_E_INVALID_ARG, "NULL argument or minimum support 0");
+    fim::ClassProfile prof;
+    fim::g_profile = &prof;
+    fim_options o = opts ? *opts : fim_options{};
+    o.flags = (o.flags | FIM_FLAG_ALWAYS_ESTIMATE) & ~(FIM_FLAG_NO_ESTIMATE | FIM_FLAG_RESERVOIR);
+    std::vector<fim_result *> res;
+    const fim_status st = fim::mine_many(ctx, {fim::MineRequest{db, minsup_abs}}, o, res, false);
+    fim::g_profile = nullptr;
+    for (fim_result *r : res) fim_result_destroy(r);
+    if (st != FIM_OK) return st;
+    *n_classes = (uint32_t)prof.n_atoms.size();
+    *n_rows = prof.act_cand.size();
+    if (prof.n_atoms.size() > class_capacity || prof.act_cand.size() > row_capacity)
+        return fim::set_error(FIM_E_OUTPUT_LIMIT, "profile arrays too small");
+    if (n_atoms) std::copy(prof.n_atoms.begin(), prof.n_atoms.end(), n_atoms);
+    for (size_t k = 0; k < prof.act_cand.size(); k++) {
+        if (est_fi) est_fi[k] = k < prof.est_fi.size() ? prof.est_fi[k] : 0.0;
+        if (est_cand) est_cand[k] = k < prof.est_cand.size() ? prof.est_cand[k] : 0.0;
+        if (act_cand) act_cand[k] = prof.act_cand[k];
+    }
     return FIM_OK;
 }
