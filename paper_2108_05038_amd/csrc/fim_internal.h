@@ -150,21 +150,19 @@ hipError_t launch_root_pairs(const uint32_t *rows, uint32_t n, uint32_t Wp, uint
                              uint32_t *part, hipStream_t stream);
 
 // Preparation of the projected root kernel.  launch_tidlist: the tid lists
-// tl (at offsets tl_off[n + 1]) from the rows, and rowpre (n x
-// rowpre_words(Wp) words: set bits of each row before every 8th word).
-// launch_rank_tx: rk (nnz + n_tx + 8 halfwords; fewer than 65535 frequent
-// items) = every transaction's frequent ranks ascending at off[t] + t,
-// closed by 0xFFFF (also in the slots of infrequent items), tlp (tl_off[n] words) = for tid-list entry p the
-// position in rk of its own rank, and suf (tl_off[n] halfwords) = the number
-// of frequent ranks after it in its transaction (transactions shorter than
-// 65536 items).
-inline uint32_t rowpre_words(uint32_t Wp) { return (Wp + 7) / 8; }
+// tl (at offsets tl_off[n + 1]) from the rows, and (tl_rank not null) the
+// rank of every entry.  launch_rank_tx: rk (nnz + n_tx + 48 halfwords; fewer
+// than 65535 frequent items) = every transaction's frequent ranks ascending
+// at off[t] + t, closed by 0xFFFF (also in the slots of infrequent items),
+// and for the n_ent tid-list entries tl (their ranks in suf, as tl_rank
+// wrote them): tlp = for entry p the position in rk of its own rank, and suf
+// = the number of frequent ranks after it in its transaction (transactions
+// shorter than 65536 items).
 hipError_t launch_tidlist(const uint32_t *rows, uint32_t n, uint32_t Wp, const uint64_t *tl_off,
-                          uint32_t *tl, uint32_t *rowpre, hipStream_t stream);
+                          uint32_t *tl, uint16_t *tl_rank, hipStream_t stream);
 hipError_t launch_rank_tx(const uint64_t *off, const uint32_t *items, uint64_t n_tx,
-                          const uint32_t *rank_of_item, const uint32_t *rows, uint32_t Wp,
-                          const uint32_t *rowpre, const uint64_t *tl_off, uint16_t *rk,
-                          uint32_t *tlp, uint16_t *suf, hipStream_t stream);
+                          const uint32_t *rank_of_item, const uint32_t *tl, uint64_t n_ent,
+                          uint16_t *rk, uint32_t *tlp, uint16_t *suf, hipStream_t stream);
 // Root class over projected transactions: rk, tlp and suf as above (tid
 // lists at offsets tl_off[n + 1]); 16-bit counters when max_supp (the
 // largest row support) is at most 65535.  Pairs as for launch_root_pairs;

@@ -572,16 +572,14 @@ constexpr uint16_t kRankEnd16 = 0xFFFFu;    // the same in the 16-bit ranked tra
 
 // tl[tl_off[r] ..) = the transactions holding rank r, ascending: the set
 // bits of row r, one wave per row, compacted with a wave prefix sum of the
-// words' popcounts.  rowpre[r * Wb + j] = set bits of row r before word 8 j,
-// the coarse rank index k_rank_tx uses to place a transaction in the list.
+// words' popcounts; tl_rank (or null) receives r for every entry.
 __global__ __launch_bounds__(kBlock) void k_tidlist(const uint32_t *__restrict__ rows, uint32_t n,
                                                      uint32_t Wp, const uint64_t *__restrict__ tl_off,
-                                                     uint32_t *tl, uint32_t *rowpre, uint32_t Wb) {
+                                                     uint32_t *tl, uint16_t *tl_rank) {
     const uint32_t r = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     if (r >= n) return;
     const uint32_t lane = lane_id();
     const uint32_t *row = rows + (uint64_t)r * Wp;
-    uint32_t *pre = rowpre + (uint64_t)r * Wb;
     const uint64_t base = tl_off[r], end = tl_off[r + 1];
     uint32_t pos = 0;  // set bits before the current window
     // 4 x 64 words per round: the loads of a window are in flight together
@@ -603,13 +601,14 @@ __global__ __launch_bounds__(kBlock) void k_tidlist(const uint32_t *__restrict__
                 const uint32_t v = __shfl_up(incl, o, kWave);
                 if ((int)lane >= o) incl += v;
             }
-            const uint32_t before = pos + incl - pc;
-            if (rowpre != nullptr && w < Wp && (w & 7) == 0) pre[w >> 3] = before;
-            uint64_t q = base + before;
+            uint64_t q = base + pos + incl - pc;
             uint32_t y = x[j];
             while (y) {
                 const uint32_t b = __ffs(y) - 1;
-                if (q < end) tl[q] = w * 32 + b;
+                if (q < end) {
+                    tl[q] = w * 32 + b;
+                    if (tl_rank != nullptr) tl_rank[q] = (uint16_t)r;
+                }
                 q++;
                 y &= y - 1;
             }
@@ -619,49 +618,23 @@ __global__ __launch_bounds__(kBlock) void k_tidlist(const uint32_t *__restrict__
 }
 
 // Ranked transactions: transaction t's ranks ascending at rk[off[t] + t ..),
-// its infrequent items' slots and one slot more holding kRankEnd.  A wave
+// its infrequent items' slots and one slot more holding kRankEnd16 (the
+// infrequent items' rank kNone is stored as kRankEnd16 as well).  A wave
 // takes kRankGroup transactions at a time (their loads overlap): every lane
 // holds one item's rank of each and finds its slot by counting the smaller
 // ranks (ties, only between infrequent items, by position).  A transaction of
-// more than 64 items is done alone, 64 items at a time.  For a frequent rank
-// r the lane also finds t's index in the tid list of r, the set bits of row r
-// before t (rowpre plus at most eight words), and stores the slot's address
-// there: tlp[tl_off[r] + index] = off[t] + t + slot.
-
+// more than 64 items is done alone, 64 items at a time.  Every store is to
+// the transaction's own contiguous slots.
 constexpr uint32_t kRankGroup = 4;
 
-__device__ __forceinline__ uint32_t tid_index(const uint32_t *__restrict__ rows, uint32_t Wp,
-                                              const uint32_t *__restrict__ rowpre, uint32_t Wb,
-                                              uint32_t r, uint64_t t) {
-    // words w8 .. w of row r: w8 + 3 < Wp always (Wp is a multiple of 4), the
-    // second half only when w reaches into it
-    const uint32_t w = (uint32_t)(t >> 5), tb = (uint32_t)(t & 31), w8 = w & ~7u;
-    const uint32_t *row = rows + (uint64_t)r * Wp;
-    const uint4 x0 = *reinterpret_cast<const uint4 *>(row + w8);
-    const uint4 x1 = w >= w8 + 4 ? *reinterpret_cast<const uint4 *>(row + w8 + 4)
-                                 : make_uint4(0u, 0u, 0u, 0u);
-    const uint32_t xs[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-    uint32_t idx = rowpre[(uint64_t)r * Wb + (w >> 3)];
-#pragma unroll
-    for (uint32_t q = 0; q < 8; q++) {
-        if (w8 + q < w) idx += __popc(xs[q]);
-        else if (w8 + q == w) idx += __popc(xs[q] & ((1u << tb) - 1u));
-    }
-    return idx;
-}
-
-__global__ __launch_bounds__(kBlock) void k_rank_tx(
-    const uint64_t *__restrict__ off, const uint32_t *__restrict__ items, uint64_t n_tx,
-    const uint32_t *__restrict__ rank_of_item, const uint32_t *__restrict__ rows, uint32_t Wp,
-    const uint32_t *__restrict__ rowpre, uint32_t Wb, const uint64_t *__restrict__ tl_off,
-    uint16_t *rk, uint32_t *tlp, uint16_t *suf) {
+__global__ __launch_bounds__(kBlock) void k_rank_tx(const uint64_t *__restrict__ off,
+                                                     const uint32_t *__restrict__ items, uint64_t n_tx,
+                                                     const uint32_t *__restrict__ rank_of_item,
+                                                     uint16_t *rk) {
     const uint32_t lane = lane_id();
     const uint64_t waves = (uint64_t)gridDim.x * kWavesPerBlock;
     const uint64_t n_groups = (n_tx + kRankGroup - 1) / kRankGroup;
-    // each XCD takes a contiguous range of transactions, so that the row
-    // pieces and prefix counts nearby transactions share stay in its L2
-    const uint32_t blk = xcd_local_block(blockIdx.x, gridDim.x);
-    for (uint64_t g = (uint64_t)blk * kWavesPerBlock + threadIdx.x / kWave; g < n_groups;
+    for (uint64_t g = (uint64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; g < n_groups;
          g += waves) {
         const uint64_t tg0 = g * kRankGroup;
         const uint32_t ng = (uint32_t)min<uint64_t>(kRankGroup, n_tx - tg0);
@@ -672,6 +645,9 @@ __global__ __launch_bounds__(kBlock) void k_rank_tx(
         for (uint32_t j = 0; j < kRankGroup; j++) {
             a[j] = j < ng ? off[tg0 + j] : 0;
             L[j] = j < ng ? (uint32_t)(off[tg0 + j + 1] - a[j]) : 0u;
+            // the same for every lane: kept in scalar registers
+            a[j] = bcast64(a[j]);
+            L[j] = __builtin_amdgcn_readfirstlane(L[j]);
             small = small && L[j] <= (uint32_t)kWave;
         }
         if (small) {
@@ -685,37 +661,16 @@ __global__ __launch_bounds__(kBlock) void k_rank_tx(
                 const uint32_t rr = rank_of_item[r[j]];
                 r[j] = lane < L[j] ? rr : kNone;
             }
-            uint32_t pos[kRankGroup];
-#pragma unroll
-            for (uint32_t j = 0; j < kRankGroup; j++) {
-                pos[j] = 0;
-                for (uint32_t i = 0; i < L[j]; i++) {
-                    const uint32_t v = __shfl(r[j], (int)i, kWave);
-                    pos[j] += (v < r[j] || (v == r[j] && i < lane)) ? 1u : 0u;
-                }
-            }
-            uint32_t idx[kRankGroup];
-            uint64_t lo[kRankGroup];
-#pragma unroll
-            for (uint32_t j = 0; j < kRankGroup; j++) {
-                // lanes without a frequent rank look up row 0 (in bounds) and
-                // drop the result
-                const uint32_t rq = r[j] != kNone ? r[j] : 0u;
-                idx[j] = tid_index(rows, Wp, rowpre, Wb, rq, j < ng ? tg0 + j : tg0);
-                lo[j] = tl_off[rq];
-            }
 #pragma unroll
             for (uint32_t j = 0; j < kRankGroup; j++) {
                 if (j >= ng) continue;
-                const uint64_t base = a[j] + tg0 + j;
-                const uint32_t lf = (uint32_t)__popcll(__ballot(r[j] != kNone));  // frequent items
-                if (lane < L[j]) {
-                    rk[base + pos[j]] = (uint16_t)r[j];  // kNone -> kRankEnd16
-                    if (r[j] != kNone) {
-                        tlp[lo[j] + idx[j]] = (uint32_t)(base + pos[j]);
-                        suf[lo[j] + idx[j]] = (uint16_t)(lf - 1 - pos[j]);
-                    }
+                uint32_t pos = 0;
+                for (uint32_t i = 0; i < L[j]; i++) {
+                    const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)r[j], (int)i);
+                    pos += (v < r[j] || (v == r[j] && i < lane)) ? 1u : 0u;
                 }
+                const uint64_t base = a[j] + tg0 + j;
+                if (lane < L[j]) rk[base + pos] = (uint16_t)r[j];  // kNone -> kRankEnd16
                 if (lane == 0) rk[base + L[j]] = kRankEnd16;
             }
             continue;
@@ -724,12 +679,6 @@ __global__ __launch_bounds__(kBlock) void k_rank_tx(
         for (uint32_t j = 0; j < ng; j++) {
             const uint64_t t = tg0 + j, base = a[j] + t;
             const uint32_t Lt = L[j];
-            uint32_t lf = 0;  // frequent items of t
-            for (uint32_t c0 = 0; c0 < Lt; c0 += kWave) {
-                const uint32_t c = c0 + lane;
-                const bool f = c < Lt && rank_of_item[items[a[j] + c]] != kNone;
-                lf += (uint32_t)__popcll(__ballot(f));
-            }
             for (uint32_t c0 = 0; c0 < Lt; c0 += kWave) {
                 const uint32_t c = c0 + lane;
                 const uint32_t rc = c < Lt ? rank_of_item[items[a[j] + c]] : kNone;
@@ -743,17 +692,52 @@ __global__ __launch_bounds__(kBlock) void k_rank_tx(
                         p += (v < rc || (v == rc && d0 + i < c)) ? 1u : 0u;
                     }
                 }
-                if (c >= Lt) continue;
-                rk[base + p] = (uint16_t)rc;
-                if (rc != kNone) {
-                    const uint64_t i = tl_off[rc] + tid_index(rows, Wp, rowpre, Wb, rc, t);
-                    tlp[i] = (uint32_t)(base + p);
-                    suf[i] = (uint16_t)(lf - 1 - p);
-                }
+                if (c < Lt) rk[base + p] = (uint16_t)rc;
             }
             if (lane == 0) rk[base + Lt] = kRankEnd16;
         }
     }
+}
+
+// For every tid-list entry q of rank r = suf[q] (written there by
+// k_tidlist) and transaction t = tl[q]: tlp[q] = the position of r among t's
+// ranked slots, off[t] + t + s with rk[off[t] + t + s] = r, and suf[q] = the
+// frequent ranks of t after it.  The L slots of t hold its frequent ranks
+// ascending and then kRankEnd16 (infrequent items), so s is the number of
+// slots below r and the frequent ranks the number of slots other than
+// kRankEnd16: counted over 32 slots (one aligned 64-byte piece) at a time,
+// loads issued together, rather than searched load by dependent load.  One
+// thread per entry: the loads and stores of the lists are coalesced.  rk is
+// padded by kRkPad slots so that a piece never reads past its end.
+constexpr uint32_t kRkPad = 40;
+
+__global__ __launch_bounds__(kBlock) void k_tl_slots(const uint64_t *__restrict__ off,
+                                                      const uint16_t *__restrict__ rk,
+                                                      const uint32_t *__restrict__ tl, uint64_t n_ent,
+                                                      uint32_t *tlp, uint16_t *suf) {
+    const uint64_t q = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= n_ent) return;
+    const uint32_t r = suf[q];
+    const uint32_t t = tl[q];
+    const uint64_t a = off[t];
+    const uint64_t s0 = a + t, s1 = s0 + (off[t + 1] - a);  // slots [s0, s1)
+    uint32_t below = 0, freq = 0;
+    for (uint64_t c = s0 & ~uint64_t(31); c < s1; c += 32) {
+        const uint4 *pc = reinterpret_cast<const uint4 *>(rk + c);
+        const uint4 v[4] = {pc[0], pc[1], pc[2], pc[3]};
+        const uint32_t w[16] = {v[0].x, v[0].y, v[0].z, v[0].w, v[1].x, v[1].y, v[1].z, v[1].w,
+                                v[2].x, v[2].y, v[2].z, v[2].w, v[3].x, v[3].y, v[3].z, v[3].w};
+#pragma unroll
+        for (uint32_t k = 0; k < 32; k++) {
+            const uint64_t slot = c + k;
+            const uint32_t x = (w[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+            const bool in = slot >= s0 && slot < s1;
+            below += (in && x < r) ? 1u : 0u;
+            freq += (in && x != kRankEnd16) ? 1u : 0u;
+        }
+    }
+    tlp[q] = (uint32_t)(s0 + below);
+    suf[q] = (uint16_t)(freq - 1 - below);
 }
 
 constexpr uint32_t kProjectMaxRows = 64;
@@ -2699,22 +2683,27 @@ hipError_t launch_bitmap_build(const uint64_t *offsets, const uint32_t *items, u
 }
 
 hipError_t launch_tidlist(const uint32_t *rows, uint32_t n, uint32_t Wp, const uint64_t *tl_off,
-                          uint32_t *tl, uint32_t *rowpre, hipStream_t stream) {
+                          uint32_t *tl, uint16_t *tl_rank, hipStream_t stream) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_tidlist, dim3((n + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock), 0,
-                       stream, rows, n, Wp, tl_off, tl, rowpre, rowpre_words(Wp));
+                       stream, rows, n, Wp, tl_off, tl, tl_rank);
     return hipGetLastError();
 }
 
 hipError_t launch_rank_tx(const uint64_t *off, const uint32_t *items, uint64_t n_tx,
-                          const uint32_t *rank_of_item, const uint32_t *rows, uint32_t Wp,
-                          const uint32_t *rowpre, const uint64_t *tl_off, uint16_t *rk,
-                          uint32_t *tlp, uint16_t *suf, hipStream_t stream) {
+                          const uint32_t *rank_of_item, const uint32_t *tl, uint64_t n_ent,
+                          uint16_t *rk, uint32_t *tlp, uint16_t *suf, hipStream_t stream) {
     if (n_tx == 0) return hipSuccess;
     const uint64_t groups = (n_tx + kRankGroup - 1) / kRankGroup;
     const uint64_t blocks = std::min<uint64_t>((groups + kWavesPerBlock - 1) / kWavesPerBlock, 65536);
     hipLaunchKernelGGL(k_rank_tx, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, off, items, n_tx,
-                       rank_of_item, rows, Wp, rowpre, rowpre_words(Wp), tl_off, rk, tlp, suf);
+                       rank_of_item, rk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n_ent == 0) return e;
+    const uint64_t eb = (n_ent + kBlock - 1) / kBlock;
+    if (eb >= (1ull << 31)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_tl_slots, dim3((uint32_t)eb), dim3(kBlock), 0, stream, off, rk, tl, n_ent,
+                       tlp, suf);
     return hipGetLastError();
 }
 

@@ -566,7 +566,7 @@ struct Inst {
     // projected: ranked transactions, tid lists and the lists' pointers into
     // the ranked transactions, pair increments
     std::vector<uint64_t> tl_off;
-    DevBuf d_rk, d_tlp, d_suf, d_tl, d_rowpre, d_work;
+    DevBuf d_rk, d_tlp, d_suf, d_tl, d_work;
     // inside d_rank_of_item (one upload): item_of_rank and tl_off
     uint32_t *p_item_of_rank = nullptr;
     uint64_t *p_tl_off = nullptr;
@@ -1211,17 +1211,17 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             I.lists_built = true;
             ENSURE(I.d_tl, ctx, std::max<uint64_t>(I.tl_off[n], 1) * 4);
             const bool ranked = I.root_kind == 2 && pairs_needed;
-            if (ranked) ENSURE(I.d_rowpre, ctx, (uint64_t)n * rowpre_words(I.Wp) * 4);
-            HIPCHK(launch_tidlist(I.d_rows.as<uint32_t>(), n, I.Wp, I.p_tl_off,
-                                  I.d_tl.as<uint32_t>(), ranked ? I.d_rowpre.as<uint32_t>() : nullptr, sq));
+            if (ranked) ENSURE(I.d_suf, ctx, std::max<uint64_t>(I.tl_off[n], 1) * 2);
+            // the ranks of the entries go to suf, which k_tl_slots then
+            // overwrites with the suffix lengths
+            HIPCHK(launch_tidlist(I.d_rows.as<uint32_t>(), n, I.Wp, I.p_tl_off, I.d_tl.as<uint32_t>(),
+                                  ranked ? I.d_suf.as<uint16_t>() : nullptr, sq));
             if (ranked) {
-                ENSURE(I.d_rk, ctx, (I.db->nnz + I.db->n_tx + 8) * 2);
+                ENSURE(I.d_rk, ctx, (I.db->nnz + I.db->n_tx + 48) * 2);
                 ENSURE(I.d_tlp, ctx, std::max<uint64_t>(I.tl_off[n], 1) * 4);
-                ENSURE(I.d_suf, ctx, std::max<uint64_t>(I.tl_off[n], 1) * 2);
                 HIPCHK(launch_rank_tx(I.db->d_off.as<uint64_t>(), I.db->d_items.as<uint32_t>(),
                                       I.db->n_tx, I.d_rank_of_item.as<uint32_t>(),
-                                      I.d_rows.as<uint32_t>(), I.Wp, I.d_rowpre.as<uint32_t>(),
-                                      I.p_tl_off, I.d_rk.as<uint16_t>(),
+                                      I.d_tl.as<uint32_t>(), I.tl_off[n], I.d_rk.as<uint16_t>(),
                                       I.d_tlp.as<uint32_t>(), I.d_suf.as<uint16_t>(), sq));
             }
         }
