@@ -34,6 +34,7 @@ Two more legs go into the same line:
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -128,12 +129,18 @@ def mine_leg(F, ctx, db, workload, steps, warmup, flags, estimate_leg=False):
             log("%s: warm-up result matches the oracle's golden digest: %s" % (workload, verified))
     torch.cuda.synchronize()
     stats, ends = [], []
+    # Python's cyclic garbage collector is run before the timed calls and
+    # kept out of them (as timeit does): a full collection inside one call
+    # would be charged to the library
+    gc.collect()
+    gc.disable()
     t0 = time.perf_counter()
     for _ in range(steps):
         r = F.mine(ctx, d, db.minsup, flags=flags)
         stats.append(r.stats)
         ends.append(time.perf_counter())
     torch.cuda.synchronize()
+    gc.enable()
     dt = (time.perf_counter() - t0) / steps
     step_ms = np.diff([t0] + ends) * 1e3  # per call (each call returns a finished result)
     log("%s: %.3f ms/step" % (workload, dt * 1e3))
@@ -190,6 +197,7 @@ def mine_leg(F, ctx, db, workload, steps, warmup, flags, estimate_leg=False):
         "steps": steps, "warmup": warmup, "ms_per_step": dt * 1e3,
         "ms_per_step_min_median_max": [float(step_ms.min()), float(np.median(step_ms)),
                                        float(step_ms.max())],
+        "step_ms": [round(float(x), 3) for x in step_ms],
         "value": st["candidates"] / dt, "unit": "candidate supports/s",
         "n_itemsets": st["n_itemsets"], "candidates": st["candidates"],
         "upload_ms": upload_ms, "with_sample_estimate": est_leg,

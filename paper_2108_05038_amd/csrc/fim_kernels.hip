@@ -897,6 +897,10 @@ struct Frame {
                            // (rank, support, row, item id); kNone: pairs counted on expansion
     uint32_t lpos;         // counted classes: first entry of row r's child class
     uint32_t meta_restore; // meta pointer to restore when the class is done
+    // counted classes: rows whose child class has at least two atoms (bit r
+    // of m2) and exactly one (m1); rows outside both are passed over without
+    // reading their lists
+    uint32_t m2lo, m2hi, m1lo, m1hi;
 };
 
 constexpr uint32_t kStageWords = 68;  // words a chunk of 64 projected entries can touch, + slack
@@ -911,6 +915,7 @@ struct alignas(16) WaveShared {
     uint4 row0[kGramMax];            // the child class of row 0 of the class built last
     uint32_t n_recs;                 // records in `recs`
     uint32_t row0_n, row0_rank, row0_id;  // its size, row 0's rank and item id
+    uint32_t xm[4];                  // child-class size masks of the class built last (Frame m2, m1)
     Frame frames[kMaxDepth];
     uint32_t prefix[kMaxDepth + 3];  // ranks of the prefix items
     uint32_t pid[kMaxDepth + 3];     // their item ids
@@ -1619,7 +1624,7 @@ __device__ __forceinline__ uint32_t finish_class(const InstDesc &I, uint32_t ins
                                                  uint32_t *region, uint64_t S, WaveShared &ws,
                                                  uint32_t *out, uint64_t out_cap, DfsCounters *ctr,
                                                  InstCounters *ictr, WaveStats &st, OutChunk &oc,
-                                                 uint32_t &atoms_off, uint32_t &lists_off) {
+                                                 uint32_t &atoms_off, uint32_t &lists_off, uint4 &xmask) {
     const uint32_t lane = lane_id();
     const uint32_t m = I.minsup;
     // pairs of the rows below r_cnt (the only ones counted), row after row
@@ -1672,6 +1677,7 @@ __device__ __forceinline__ uint32_t finish_class(const InstDesc &I, uint32_t ins
         ws.row0_n = 0;
         ws.row0_rank = rank;
         ws.row0_id = id;
+        ws.xm[0] = ws.xm[1] = ws.xm[2] = ws.xm[3] = 0u;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -1742,6 +1748,8 @@ __device__ __forceinline__ uint32_t finish_class(const InstDesc &I, uint32_t ins
             }
             if (b == a + 1) {
                 gst(A + 3 * f + a, row_n);
+                if (row_n >= 2) atomicOr(&ws.xm[a >> 5], 1u << (a & 31));
+                else if (row_n == 1) atomicOr(&ws.xm[2 + (a >> 5)], 1u << (a & 31));
                 if (a == 0) ws.row0_n = row_n;
                 if (per_row_count && a < r_emit && row_n)
                     atomicAdd(&I.class_count[em.l2_row0 + a], (unsigned long long)row_n);
@@ -1785,6 +1793,7 @@ __device__ __forceinline__ uint32_t finish_class(const InstDesc &I, uint32_t ins
     meta = atoms;
     atoms_off = (uint32_t)atoms;
     lists_off = (uint32_t)lists;
+    xmask = make_uint4(uni(ws.xm[0]), uni(ws.xm[1]), uni(ws.xm[2]), uni(ws.xm[3]));
     if (report && I.rec_budget && st.rec_pending >= 4096) {
         // records are added to the instance's count in batches; the count
         // never exceeds the records really found, so the work is abandoned
@@ -1811,7 +1820,7 @@ __device__ __forceinline__ uint32_t finish_class(const InstDesc &I, uint32_t ins
 // pair row r with every later row when it is expanded (rows streamed from
 // memory, g lanes per pair).  All builds go through one block at the end of
 // the loop, so that its counting code is present once.
-__device__ __forceinline__ void search(const InstDesc &I, uint32_t inst, uint32_t task, uint32_t plen,
+__device__ __forceinline__ void search(const InstDesc &I, const InstDesc &Ig, uint32_t inst, uint32_t task, uint32_t plen,
                        uint32_t l2_ref, uint32_t Wp, uint32_t k0, uint32_t r_end0, uint32_t reported0,
                        uint64_t meta, uint64_t peak, uint32_t tmax, uint32_t *region, uint64_t S,
                        WaveShared &ws, uint32_t *out, uint64_t out_cap, DfsCounters *ctr,
@@ -1851,7 +1860,7 @@ __device__ __forceinline__ void search(const InstDesc &I, uint32_t inst, uint32_
         b_em = EmitTo{plen, reported0 ? 0u : r_end0, plen == 1 ? l2_ref : kNone, l2_ref};
         depth = -1;
     } else {
-        if (lane == 0) ws.frames[0] = Frame{0u, k0, 0u, r_end0, (uint32_t)meta, kNone, 0u, (uint32_t)S};
+        if (lane == 0) ws.frames[0] = Frame{0u, k0, 0u, r_end0, (uint32_t)meta, kNone, 0u, (uint32_t)S, 0u, 0u, 0u, 0u};
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         depth = 0;
@@ -1880,11 +1889,13 @@ __device__ __forceinline__ void search(const InstDesc &I, uint32_t inst, uint32_
                 st.child_rows += b_write ? c : 0u;
             }
             uint32_t ao = 0, lo = 0;
+            uint4 xm;
             if (finish_class(I, inst, task, c, b_r_end, b_rank, b_supp, b_id, b_em, rows_top + rows_need, meta, region,
-                             S, ws, out, out_cap, ctr, ictr, st, oc, ao, lo) != kBuildOk)
+                             S, ws, out, out_cap, ctr, ictr, st, oc, ao, lo, xm) != kBuildOk)
                 break;
             if (lane == 0)
-                ws.frames[depth + 1] = Frame{(uint32_t)b_rows_base, c, 0u, b_r_end, ao, lo, 0u, (uint32_t)b_restore};
+                ws.frames[depth + 1] = Frame{(uint32_t)b_rows_base, c, 0u, b_r_end, ao, lo, 0u, (uint32_t)b_restore,
+                                             xm.x, xm.y, xm.z, xm.w};
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             rows_top += rows_need;
@@ -1897,7 +1908,7 @@ __device__ __forceinline__ void search(const InstDesc &I, uint32_t inst, uint32_
         if (depth < 0) break;
         if ((++iters & 63u) == 0 && inst_stopped(I, ictr, inst)) break;
         if (dn.enabled && cool == 0 && ((++polls & 7u) == 0) && donation_wanted(ctr)) {
-            const bool gave = try_donate(I, inst, plen, l2_ref, depth, region, ws, dn, ctr);
+            const bool gave = try_donate(Ig, inst, plen, l2_ref, depth, region, ws, dn, ctr);
             cool = gave ? 8u : 4u;
             st.given += gave ? 1u : 0u;
         } else if (cool) {
@@ -1913,16 +1924,52 @@ __device__ __forceinline__ void search(const InstDesc &I, uint32_t inst, uint32_
         F.lists = uni(F.lists);
         F.lpos = uni(F.lpos);
         F.meta_restore = uni(F.meta_restore);
+        F.m2lo = uni(F.m2lo);
+        F.m2hi = uni(F.m2hi);
+        F.m1lo = uni(F.m1lo);
+        F.m1hi = uni(F.m1hi);
         if (F.r >= F.r_end) {
             rows_top = F.rows_base;
             meta = F.meta_restore;
             depth--;
             continue;
         }
-        const uint32_t r = F.r;
-        const uint32_t nj = F.k - r - 1;
+        uint32_t r = F.r;
         const uint32_t *A = region + F.atoms;
         const uint32_t np = plen + (uint32_t)depth + 1;  // prefix of row r's child class
+        if (F.lists != kNone && I.row_cand == nullptr) {
+            // Rows whose child class has fewer than two atoms (or would be
+            // too long) are passed over from the frame's masks: their
+            // candidates are counted and the list position moves past their
+            // single entries, with no load.
+            const uint64_t m2 = ((uint64_t)F.m2hi << 32) | F.m2lo;
+            const uint64_t m1 = ((uint64_t)F.m1hi << 32) | F.m1lo;
+            const uint64_t below_end = F.r_end >= 64 ? ~0ull : (1ull << F.r_end) - 1;
+            const uint64_t from_r = ~((1ull << r) - 1);  // r < r_end <= k <= kGramMax
+            const bool len_ok = I.max_len == 0 || np + 2 <= I.max_len;
+            const uint64_t next = len_ok ? (m2 & below_end & from_r) : 0ull;
+            const uint32_t r2 = next ? (uint32_t)__builtin_ctzll(next) : F.r_end;
+            if (r2 > r) {
+                const uint32_t ns = r2 - r;
+                // rows r .. r2 - 1 have k - 1 - row candidates each
+                st.candidates += (unsigned long long)ns * (F.k - 1) - ((unsigned long long)(r + r2 - 1) * ns) / 2;
+                const uint64_t skipped = from_r & (r2 >= 64 ? ~0ull : (1ull << r2) - 1);
+                F.lpos += (uint32_t)__popcll(m1 & skipped);
+                if (F.k > st.max_k) st.max_k = F.k;
+                if ((unsigned long long)depth > st.max_depth) st.max_depth = depth;
+                if (r2 >= F.r_end) {
+                    if (lane == 0) {
+                        ws.frames[depth].r = r2;
+                        ws.frames[depth].lpos = F.lpos;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    continue;
+                }
+                r = r2;
+            }
+        }
+        const uint32_t nj = F.k - r - 1;
         if (F.lists != kNone) {
             // the row's child class, its rank and its item id: from LDS for
             // row 0 of the class built last, else in one round of loads
@@ -2042,7 +2089,7 @@ __device__ __forceinline__ void search(const InstDesc &I, uint32_t inst, uint32_
                 if (lane == 0)
                     atomicAdd(&I.class_count[l2_class(plen, l2_ref, depth, r, ws)], (unsigned long long)nf);
             } else if (I.key_bits) {
-                emit_keys(I, inst, len, tmp, nj, nf, ws, out, out_cap, ctr);
+                emit_keys(Ig, inst, len, tmp, nj, nf, ws, out, out_cap, ctr);
             } else if (chunk_reserve(oc, nf * rec, task, inst, out, out_cap, ctr)) {
                 uint32_t *obase = out + oc.base + oc.pos;
                 for (uint32_t e = lane; e < nf; e += kWave) {
@@ -2069,7 +2116,7 @@ __device__ __forceinline__ void search(const InstDesc &I, uint32_t inst, uint32_
         }
         const uint64_t new_meta = meta - 3ull * nj - 4ull * nf;
         uint32_t *dst = region + new_meta;
-        sort_atoms(I, tmp, nj, dst, nf);
+        sort_atoms(Ig, tmp, nj, dst, nf);
         __threadfence_block();
         if (nf <= kGramMax) {
             // the child class is counted as it is built
@@ -2119,7 +2166,7 @@ __device__ __forceinline__ void search(const InstDesc &I, uint32_t inst, uint32_
         st.row_words += (unsigned long long)nf * Wp;
         if (lane == 0)
             ws.frames[depth + 1] = Frame{(uint32_t)rows_top, nf, 0u, nf - 1, (uint32_t)new_meta, kNone, 0u,
-                                         (uint32_t)restore};
+                                         (uint32_t)restore, 0u, 0u, 0u, 0u};
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         rows_top += (uint64_t)nf * Wp;
@@ -2252,7 +2299,8 @@ __device__ bool build_projected(const InstDesc &I, const uint32_t *P, uint32_t s
 // at the i-th transaction of T(prefix).  Every support below the prefix is
 // a popcount of ANDs of such rows, so the results are the same, and the
 // whole subtree works on rows of ceil(supp(prefix) / 32) words.
-__device__ __forceinline__ uint32_t prepare_frame(const InstDesc &I, uint32_t inst, const FrameSrc &src,
+__device__ __forceinline__ uint32_t prepare_frame(const InstDesc &I, const InstDesc &Ig, uint32_t inst,
+                                                  const FrameSrc &src,
                                                   uint32_t *region, uint64_t S, WaveShared &ws,
                                                   DfsCounters *ctr, InstCounters *ictr, WaveStats &st,
                                                   uint64_t &meta_out, uint64_t &low_out) {
@@ -2375,7 +2423,7 @@ __device__ __forceinline__ uint32_t prepare_frame(const InstDesc &I, uint32_t in
     const uint32_t Wq = max(kRowAlign, ((s + 31) / 32 + kRowAlign - 1) / kRowAlign * kRowAlign);
     uint32_t Wp = Wf;
     if (I.project && 4ull * Wq <= Wf) {
-        if (!build_projected(I, P, s, src.ranks, k, Wq, region, S, low, ctr, ws.gx)) return 0;
+        if (!build_projected(Ig, P, s, src.ranks, k, Wq, region, S, low, ctr, ws.gx)) return 0;
         Wp = Wq;
     } else {
         if (low < (uint64_t)k * Wf) {
@@ -2551,14 +2599,20 @@ __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Tas
             }
         }
         if (have) {
-            const InstDesc &I = insts[inst];
+            // The descriptor is read once into registers: read through the
+            // reference, every use after a store would load it again and
+            // wait for all of the wave's outstanding stores (the child rows
+            // just written) first.  The out-of-line helpers take the
+            // reference.
+            const InstDesc &Ig = insts[inst];
+            const InstDesc I = Ig;
             WaveStats st{};
             OutChunk oc{kNoChunk, 0u, 0u, 0u, 0u};
             const unsigned long long c0 = wall_clock64();
             uint64_t meta = 0, low = 0;
-            const uint32_t Wp = prepare_frame(I, inst, fs, region, S, ws, ctr, ictr, st, meta, low);
+            const uint32_t Wp = prepare_frame(I, Ig, inst, fs, region, S, ws, ctr, ictr, st, meta, low);
             if (Wp)
-                search(I, inst, task, fs.plen, fs.l2_ref, Wp, fs.k, fs.r_end, fs.reported, meta,
+                search(I, Ig, inst, task, fs.plen, fs.l2_ref, Wp, fs.k, fs.r_end, fs.reported, meta,
                        (S - low) + (uint64_t)fs.k * Wp, tmax, region, S, ws, out, out_cap, ctr, ictr, st,
                        oc, dn);
             flush_recs(ws, out, out_cap, ctr);
