@@ -127,15 +127,16 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t stre
 
 // Bitmap rows (n x Wp words) of the frequent ranks.  launch_bitmap_build
 // sets bits with global atomics into zero-filled rows; launch_bitmap_tiles
-// writes every word of the rows from LDS column tiles of K words
-// (bitmap_tile_words(n, lds_max), 0 when n rows do not fit).
+// writes every word of the rows from LDS tiles of up to 32 words by a group
+// of rows (bitmap_tiles_fit(lds_max) tells whether the device's LDS allows
+// it).
 hipError_t launch_bitmap_build(const uint64_t *offsets, const uint32_t *items, uint64_t n_tx,
                                const uint32_t *rank_of_item, uint32_t *rows, uint32_t Wp,
                                hipStream_t stream);
-uint32_t bitmap_tile_words(uint32_t n, size_t lds_max);
+bool bitmap_tiles_fit(size_t lds_max);
 hipError_t launch_bitmap_tiles(const uint64_t *offsets, const uint32_t *items, uint64_t n_tx,
                                const uint32_t *rank_of_item, uint32_t n, uint32_t *rows,
-                               uint32_t Wp, uint32_t K, hipStream_t stream);
+                               uint32_t Wp, size_t lds_max, hipStream_t stream);
 
 // Upper-triangle pair supports of the n rows (the root class): every pair
 // (i < j) with popcount(row_i & row_j) >= minsup is appended as

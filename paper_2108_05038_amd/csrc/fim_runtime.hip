@@ -1184,13 +1184,12 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             else if (t_covers < t_rows) I.root_kind = 1;
             else I.root_kind = 0;
         }
-        // rows from LDS column tiles when n rows of a tile fit a workgroup's
-        // LDS, else zero fill and global atomics
-        const uint32_t K = bitmap_tile_words(n, ctx->lds_per_block);
-        if (K) {
+        // rows from LDS tiles (a column window of a group of rows) when the
+        // device's LDS allows, else zero fill and global atomics
+        if (bitmap_tiles_fit(ctx->lds_per_block)) {
             HIPCHK(launch_bitmap_tiles(I.db->d_off.as<uint64_t>(), I.db->d_items.as<uint32_t>(),
                                        I.db->n_tx, I.d_rank_of_item.as<uint32_t>(), n,
-                                       I.d_rows.as<uint32_t>(), I.Wp, K, sq));
+                                       I.d_rows.as<uint32_t>(), I.Wp, ctx->lds_per_block, sq));
         } else {
             HIPCHK(launch_fill_u32(I.d_rows.as<uint32_t>(), (uint64_t)n * I.Wp, 0u, sq));
             HIPCHK(launch_bitmap_build(I.db->d_off.as<uint64_t>(), I.db->d_items.as<uint32_t>(),
