@@ -7,8 +7,8 @@
 // and the instance.  Comparing two keys of one instance compares the item
 // sequences lexicographically, a prefix first (its zero codes sort before
 // any item), which is the canonical order.  Sorting the records by
-// (instance, key) with three stable radix passes (key low half, key high
-// half, instance) and reading the items back out of the keys gives every
+// (instance, key) with two stable radix sorts (the 128-bit key, then the
+// instance) and reading the items back out of the keys gives every
 // instance's result as CSR, without the host touching a record.
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
@@ -20,14 +20,15 @@ namespace {
 
 constexpr uint32_t kOrdBlock = 256;
 
-__global__ void k_split(const uint32_t *__restrict__ rec, uint64_t n, unsigned long long *lo,
-                        unsigned long long *hi, uint32_t *inst, uint32_t *idx) {
+__global__ void k_split(const uint32_t *__restrict__ rec, uint64_t n, rocprim::uint128_t *key,
+                        uint32_t *inst, uint32_t *idx) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
         const uint4 a = reinterpret_cast<const uint4 *>(rec)[2 * q];
         const uint4 b = reinterpret_cast<const uint4 *>(rec)[2 * q + 1];
-        lo[q] = ((unsigned long long)a.y << 32) | a.x;
-        hi[q] = ((unsigned long long)a.w << 32) | a.z;
+        const unsigned long long lo = ((unsigned long long)a.y << 32) | a.x;
+        const unsigned long long hi = ((unsigned long long)a.w << 32) | a.z;
+        key[q] = ((rocprim::uint128_t)hi << 64) | lo;
         inst[q] = b.y;
         idx[q] = (uint32_t)q;
     }
@@ -121,11 +122,10 @@ fim_status gpu_order(fim_ctx *ctx, hipStream_t s, const uint32_t *d_rec, uint64_
     if (n == 0) return FIM_OK;
     if (n >= (1ull << 31)) return set_error(FIM_E_OUTPUT_LIMIT, "more than 2^31 itemsets in one call");
     const int ni = (int)n;
-    DevBuf lo(ctx), hi(ctx), lo2(ctx), inst(ctx), inst2(ctx), idx(ctx), idx2(ctx), len(ctx),
+    DevBuf key(ctx), key2(ctx), inst(ctx), inst2(ctx), idx(ctx), idx2(ctx), len(ctx),
         ioff(ctx), d_items(ctx), d_supp(ctx), d_first(ctx), d_bits(ctx), tmp(ctx);
-    OENSURE(lo, n * 8);
-    OENSURE(hi, n * 8);
-    OENSURE(lo2, n * 8);
+    OENSURE(key, n * 16);
+    OENSURE(key2, n * 16);
     OENSURE(inst, n * 4);
     OENSURE(inst2, n * 4);
     OENSURE(idx, n * 4);
@@ -133,14 +133,13 @@ fim_status gpu_order(fim_ctx *ctx, hipStream_t s, const uint32_t *d_rec, uint64_
     OENSURE(d_bits, n_inst * 4);
     OCHK(h2d(ctx, d_bits.as<void>(), bits_of.data(), n_inst * 4, s));
     hipLaunchKernelGGL(k_split, dim3(grid_for(n)), dim3(kOrdBlock), 0, s, d_rec, n,
-                       lo.as<unsigned long long>(), hi.as<unsigned long long>(), inst.as<uint32_t>(),
-                       idx.as<uint32_t>());
+                       key.as<rocprim::uint128_t>(), inst.as<uint32_t>(), idx.as<uint32_t>());
     OCHK(hipGetLastError());
     // temporary storage of the largest pass
     size_t tb = 0, t1 = 0;
-    OCHK(rocprim::radix_sort_pairs(nullptr, t1, lo.as<unsigned long long>(),
-                                            lo2.as<unsigned long long>(), idx.as<uint32_t>(),
-                                            idx2.as<uint32_t>(), ni, 0, 64, s));
+    OCHK(rocprim::radix_sort_pairs(nullptr, t1, key.as<rocprim::uint128_t>(),
+                                   key2.as<rocprim::uint128_t>(), idx.as<uint32_t>(),
+                                   idx2.as<uint32_t>(), ni, 0, 128, s));
     tb = std::max(tb, t1);
     OCHK(rocprim::radix_sort_pairs(nullptr, t1, inst.as<uint32_t>(), inst2.as<uint32_t>(),
                                             idx.as<uint32_t>(), idx2.as<uint32_t>(), ni, 0, 32, s));
@@ -149,20 +148,12 @@ fim_status gpu_order(fim_ctx *ctx, hipStream_t s, const uint32_t *d_rec, uint64_
     tb = std::max(tb, t1);
     OENSURE(tmp, std::max<size_t>(tb, 16));
     size_t tbytes = tmp.bytes();
-    // pass 1: low half of the key
-    OCHK(rocprim::radix_sort_pairs(tmp.as<void>(), tbytes, lo.as<unsigned long long>(),
-                                            lo2.as<unsigned long long>(), idx.as<uint32_t>(),
-                                            idx2.as<uint32_t>(), ni, 0, 64, s));
-    // pass 2: high half, in the order of pass 1 (stable)
-    hipLaunchKernelGGL(k_gather<unsigned long long>, dim3(grid_for(n)), dim3(kOrdBlock), 0, s,
-                       hi.as<unsigned long long>(), idx2.as<uint32_t>(), n,
-                       lo.as<unsigned long long>());
-    OCHK(hipGetLastError());
-    tbytes = tmp.bytes();
-    OCHK(rocprim::radix_sort_pairs(tmp.as<void>(), tbytes, lo.as<unsigned long long>(),
-                                            lo2.as<unsigned long long>(), idx2.as<uint32_t>(),
-                                            idx.as<uint32_t>(), ni, 0, 64, s));
-    // pass 3: instance (a batch), in the order of pass 2
+    // pass 1: the whole key
+    OCHK(rocprim::radix_sort_pairs(tmp.as<void>(), tbytes, key.as<rocprim::uint128_t>(),
+                                   key2.as<rocprim::uint128_t>(), idx.as<uint32_t>(),
+                                   idx2.as<uint32_t>(), ni, 0, 128, s));
+    std::swap(idx, idx2);
+    // pass 2: instance (a batch), in the order of pass 1 (stable)
     if (n_inst > 1) {
         uint32_t ib = 1;
         while (ib < 32 && (n_inst - 1) >> ib) ib++;
