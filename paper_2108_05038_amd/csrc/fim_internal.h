@@ -124,6 +124,9 @@ hipError_t launch_item_count(const uint32_t *items, uint64_t nnz, uint32_t *coun
                              uint32_t n_item_ids, uint32_t *part, hipStream_t stream);
 
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t stream);
+// n words set to zero, except the 64-bit value v at words [at, at + 2)
+hipError_t launch_fill_words(uint32_t *p, uint64_t n, uint64_t at, unsigned long long v,
+                             hipStream_t stream);
 
 // Bitmap rows (n x Wp words) of the frequent ranks.  launch_bitmap_build
 // sets bits with global atomics into zero-filled rows; launch_bitmap_tiles

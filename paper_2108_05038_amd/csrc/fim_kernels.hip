@@ -144,6 +144,13 @@ __global__ __launch_bounds__(kBlock) void k_item_count(const uint32_t *__restric
         atomicAdd(&counts[items[p]], 1u);
 }
 
+// n words: the 64-bit value v at words [at, at + 2), zero elsewhere
+__global__ void k_fill_words(uint32_t *p, uint64_t n, uint64_t at, unsigned long long v) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        p[i] = i == at ? (uint32_t)v : i == at + 1 ? (uint32_t)(v >> 32) : 0u;
+}
+
 __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
@@ -2733,6 +2740,14 @@ hipError_t launch_item_count(const uint32_t *items, uint64_t nnz, uint32_t *coun
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_item_sum, dim3((n_item_ids + kWave - 1) / kWave), dim3(kBlock), 0, stream,
                        part, nb, n_item_ids, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_words(uint32_t *p, uint64_t n, uint64_t at, unsigned long long v,
+                             hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const uint64_t blocks = std::min<uint64_t>((n + kBlock - 1) / kBlock, 4096);
+    hipLaunchKernelGGL(k_fill_words, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, p, n, at, v);
     return hipGetLastError();
 }
 

@@ -566,7 +566,7 @@ struct Inst {
     // projected: ranked transactions, tid lists and the lists' pointers into
     // the ranked transactions, pair increments
     std::vector<uint64_t> tl_off;
-    DevBuf d_rk, d_tlp, d_suf, d_tl, d_work;
+    DevBuf d_rk, d_tlp, d_suf, d_tl;
     // inside d_rank_of_item (one upload): item_of_rank and tl_off
     uint32_t *p_item_of_rank = nullptr;
     uint64_t *p_tl_off = nullptr;
@@ -709,8 +709,7 @@ static fim_status run_persistent(fim_ctx *ctx, hipStream_t s, Tracer &tr,
                                  const std::vector<InstDesc> &desc, const std::vector<Task> &tasks,
                                  DevBuf &d_out, DfsLaunch &L) {
     const uint32_t n_inst = (uint32_t)desc.size();
-    DevBuf d_desc(ctx), d_tasks(ctx), d_stack(ctx), d_ctr(ctx), d_ictr(ctx);
-    DevBuf d_slots(ctx), d_heap(ctx), d_trace(ctx), d_prefix(ctx);
+    DevBuf d_in(ctx), d_stack(ctx), d_cnt(ctx), d_heap(ctx), d_trace(ctx);
     hipEvent_t ev0, ev1;
     HIPCHK(hipEventCreate(&ev0));
     HIPCHK(hipEventCreate(&ev1));
@@ -721,10 +720,20 @@ static fim_status run_persistent(fim_ctx *ctx, hipStream_t s, Tracer &tr,
             (void)hipEventDestroy(b);
         }
     } evg{ev0, ev1};
-    ENSURE(d_desc, ctx, desc.size() * sizeof(InstDesc));
-    ENSURE(d_tasks, ctx, tasks.size() * sizeof(Task));
-    HIPCHK(h2d(ctx, d_desc.as<void>(), desc.data(), desc.size() * sizeof(InstDesc), s));
-    HIPCHK(h2d(ctx, d_tasks.as<void>(), tasks.data(), tasks.size() * sizeof(Task), s));
+    // descriptors, tasks and the prefix-record sources in one upload (pieces
+    // at 8-byte multiples, as h2d_pieces lays them out)
+    const size_t b_desc = desc.size() * sizeof(InstDesc), b_tasks = tasks.size() * sizeof(Task);
+    const size_t b_pre = L.prefix ? L.prefix->size() * sizeof(PrefixSrc) : 0;
+    const size_t at_tasks = (b_desc + 7) & ~size_t(7), at_pre = at_tasks + ((b_tasks + 7) & ~size_t(7));
+    ENSURE(d_in, ctx, at_pre + b_pre + 8);
+    {
+        const H2DPiece up[3] = {{desc.data(), b_desc}, {tasks.data(), b_tasks},
+                                {L.prefix ? L.prefix->data() : nullptr, b_pre}};
+        HIPCHK(h2d_pieces(ctx, d_in.as<void>(), up, 3, s));
+    }
+    const InstDesc *p_desc = d_in.as<InstDesc>();
+    const Task *p_tasks = reinterpret_cast<const Task *>(d_in.as<char>() + at_tasks);
+    const PrefixSrc *p_pre = reinterpret_cast<const PrefixSrc *>(d_in.as<char>() + at_pre);
     L.ictr.assign(n_inst, InstCounters{});
     // per-worker stack: room for the largest first frame and its subtree,
     // within a quarter of device memory in total
@@ -751,35 +760,32 @@ static fim_status run_persistent(fim_ctx *ctx, hipStream_t s, Tracer &tr,
         ENSURE(d_stack, ctx, (size_t)workers * S * 4);
         if (L.prefix && 8 * L.prefix_rec + 8 > L.out_cap) L.out_cap = 16 * L.prefix_rec + 4096;
         ENSURE(d_out, ctx, (size_t)L.out_cap * 4);
-        ENSURE(d_ctr, ctx, sizeof(DfsCounters));
-        ENSURE(d_ictr, ctx, sizeof(InstCounters) * n_inst);
+        // the launch's counters, the instances' counters and the donation
+        // slots in one block, set by one kernel (the output position past
+        // the prefix records, zeros elsewhere)
+        const size_t b_ictr = (sizeof(InstCounters) * n_inst + 255) & ~size_t(255);
+        const size_t cnt_bytes = sizeof(DfsCounters) + b_ictr + n_slots * 8;
+        ENSURE(d_cnt, ctx, cnt_bytes);
+        DfsCounters *p_ctr = d_cnt.as<DfsCounters>();
+        InstCounters *p_ictr = reinterpret_cast<InstCounters *>(d_cnt.as<char>() + sizeof(DfsCounters));
+        unsigned long long *p_slots =
+            reinterpret_cast<unsigned long long *>(d_cnt.as<char>() + sizeof(DfsCounters) + b_ictr);
         if (tr.on) {
             ENSURE(d_trace, ctx, (size_t)workers * 64);
             HIPCHK(launch_fill_u32(d_trace.as<uint32_t>(), (uint64_t)workers * 16, 0u, s));
         }
-        ENSURE(d_slots, ctx, n_slots * 8);
         ENSURE(d_heap, ctx, heap_words * 4);
-        HIPCHK(launch_fill_u32(d_slots.as<uint32_t>(), n_slots * 2, 0u, s));
-        HIPCHK(launch_fill_u32(d_ctr.as<uint32_t>(), sizeof(DfsCounters) / 4, 0u, s));
-        unsigned long long start = 0;
-        if (L.prefix && L.prefix_rec) {
-            start = 8 * L.prefix_rec;
-            ENSURE(d_prefix, ctx, L.prefix->size() * sizeof(PrefixSrc));
-            HIPCHK(h2d(ctx, d_prefix.as<void>(), L.prefix->data(), L.prefix->size() * sizeof(PrefixSrc), s));
-            HIPCHK(launch_prefix_keys(d_prefix.as<PrefixSrc>(), (uint32_t)L.prefix->size(), L.prefix_max,
-                                      d_out.as<uint32_t>(), s));
-            HIPCHK(h2d(ctx, reinterpret_cast<char *>(d_ctr.as<void>()) + offsetof(DfsCounters, out_used),
-                       &start, 8, s));
-        }
-        HIPCHK(launch_fill_u32(d_ictr.as<uint32_t>(), sizeof(InstCounters) / 4 * n_inst, 0u, s));
+        const unsigned long long start = (L.prefix && L.prefix_rec) ? 8 * L.prefix_rec : 0;
+        HIPCHK(launch_fill_words(d_cnt.as<uint32_t>(), cnt_bytes / 4, offsetof(DfsCounters, out_used) / 4, start, s));
+        if (start)
+            HIPCHK(launch_prefix_keys(p_pre, (uint32_t)L.prefix->size(), L.prefix_max, d_out.as<uint32_t>(), s));
         if (L.cap_output) HIPCHK(launch_fill_u32(d_out.as<uint32_t>(), L.out_cap, 0u, s));
         tr.mark("  (dfs inputs queued)");
         HIPCHK(hipEventRecord(ev0, s));
         auto launch = [&]() {
-            return launch_dfs(d_desc.as<InstDesc>(), d_tasks.as<Task>(), tasks.size(),
+            return launch_dfs(p_desc, p_tasks, tasks.size(),
                               d_stack.as<uint32_t>(), S, workers, L.claim, d_out.as<uint32_t>(),
-                              L.out_cap, d_ctr.as<DfsCounters>(), d_ictr.as<InstCounters>(),
-                              d_slots.as<unsigned long long>(), n_slots, d_heap.as<uint32_t>(),
+                              L.out_cap, p_ctr, p_ictr, p_slots, n_slots, d_heap.as<uint32_t>(),
                               heap_words, wait_ticks,
                               tr.on ? d_trace.as<unsigned long long>() : nullptr, L.variant, nap_max,
                               s);
@@ -803,11 +809,13 @@ static fim_status run_persistent(fim_ctx *ctx, hipStream_t s, Tracer &tr,
             HIPCHK(launch());
         }
         HIPCHK(hipEventRecord(ev1, s));
-        HIPCHK(hipMemcpyAsync(&L.ctr, d_ctr.as<void>(), sizeof(L.ctr), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(L.ictr.data(), d_ictr.as<void>(), sizeof(InstCounters) * n_inst,
-                              hipMemcpyDeviceToHost, s));
+        // both kinds of counters in one copy
+        std::vector<char> h_cnt(sizeof(DfsCounters) + sizeof(InstCounters) * n_inst);
+        HIPCHK(hipMemcpyAsync(h_cnt.data(), d_cnt.as<void>(), h_cnt.size(), hipMemcpyDeviceToHost, s));
         tr.mark("  (dfs queued)");
         HIPCHK(stream_wait(s));
+        memcpy(&L.ctr, h_cnt.data(), sizeof(DfsCounters));
+        memcpy(L.ictr.data(), h_cnt.data() + sizeof(DfsCounters), sizeof(InstCounters) * n_inst);
         tr.mark("  (dfs done)");
         HIPCHK(hipEventElapsedTime(&L.ms, ev0, ev1));
         const DfsCounters &ctr = L.ctr;
@@ -1229,21 +1237,19 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         const uint64_t all = (uint64_t)n * (n - 1) / 2;
         const uint64_t cap = std::min<uint64_t>(all, std::max<uint64_t>(1u << 16, 64ull * n));
         ENSURE(I.d_pairs, ctx, cap * 12);
-        ENSURE(I.d_npairs, ctx, 8);
-        HIPCHK(launch_fill_u32(I.d_npairs.as<uint32_t>(), 2, 0u, sq));
+        // the frequent pairs found and (projected root) the pair increments,
+        // side by side: one fill, one copy back
+        ENSURE(I.d_npairs, ctx, 16);
+        HIPCHK(launch_fill_u32(I.d_npairs.as<uint32_t>(), 4, 0u, sq));
         if (I.root_kind == 2) {
-            ENSURE(I.d_work, ctx, 8);
-            HIPCHK(launch_fill_u32(I.d_work.as<uint32_t>(), 2, 0u, sq));
             HIPCHK(hipEventRecord(rev[2 * q], sq));
             HIPCHK(launch_root_project(I.d_rk.as<uint16_t>(), I.d_tlp.as<uint32_t>(),
                                        I.d_suf.as<uint16_t>(), I.p_tl_off, n,
                                        max_supp_of(I), I.minsup,
                                        I.d_pairs.as<uint32_t>(), cap,
                                        I.d_npairs.as<unsigned long long>(),
-                                       I.d_work.as<unsigned long long>(), sq));
+                                       I.d_npairs.as<unsigned long long>() + 1, sq));
             HIPCHK(hipEventRecord(rev[2 * q + 1], sq));
-            HIPCHK(hipMemcpyAsync(h_small.as<unsigned long long>() + 2 * q + 1, I.d_work.as<void>(), 8,
-                                  hipMemcpyDeviceToHost, sq));
         } else if (I.root_kind == 1) {
             I.nz_off.assign(n + 1, 0);
             for (uint32_t r = 0; r < n; r++)
@@ -1281,7 +1287,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                                      sq));
             HIPCHK(hipEventRecord(rev[2 * q + 1], sq));
         }
-        HIPCHK(hipMemcpyAsync(h_small.as<unsigned long long>() + 2 * q, I.d_npairs.as<void>(), 8,
+        HIPCHK(hipMemcpyAsync(h_small.as<unsigned long long>() + 2 * q, I.d_npairs.as<void>(), 16,
                               hipMemcpyDeviceToHost, sq));
     }
     HIPCHK(join());
@@ -1317,14 +1323,14 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         const uint64_t cap = I.d_pairs.bytes() / 12;
         if (I.n_pairs > cap) {  // rerun with room for every frequent pair
             ENSURE(I.d_pairs, ctx, I.n_pairs * 12);
-            HIPCHK(launch_fill_u32(I.d_npairs.as<uint32_t>(), 2, 0u, s));
+            HIPCHK(launch_fill_u32(I.d_npairs.as<uint32_t>(), 4, 0u, s));
             if (I.root_kind == 2)
                 HIPCHK(launch_root_project(I.d_rk.as<uint16_t>(), I.d_tlp.as<uint32_t>(),
                                            I.d_suf.as<uint16_t>(), I.p_tl_off,
                                            I.n_freq, max_supp_of(I), I.minsup,
                                            I.d_pairs.as<uint32_t>(), I.n_pairs,
                                            I.d_npairs.as<unsigned long long>(),
-                                           I.d_work.as<unsigned long long>(), s));
+                                           I.d_npairs.as<unsigned long long>() + 1, s));
             else if (I.root_kind == 1)
                 HIPCHK(launch_root_sparse(I.d_bt.as<uint32_t>(), (uint32_t)((I.n_freq + 3) / 4 * 4),
                                           I.d_nz_off.as<uint64_t>(), I.d_nz_cnt.as<uint32_t>(),
