@@ -27,21 +27,6 @@ __device__ __forceinline__ uint4 and4(uint4 a, uint4 b) {
     return make_uint4(a.x & b.x, a.y & b.y, a.z & b.z, a.w & b.w);
 }
 
-// popcount(a AND b) over the 128-bit chunks c = sub, sub + g, ... < C; four
-// chunk pairs are loaded before any is used, so a lane keeps eight loads
-// in flight
-__device__ __forceinline__ uint32_t popc_rows(const uint4 *a, const uint4 *b, uint32_t C,
-                                              uint32_t sub, uint32_t g) {
-    uint32_t acc = 0, c = sub;
-    for (; c + 3 * g < C; c += 4 * g) {
-        const uint4 a0 = a[c], b0 = b[c], a1 = a[c + g], b1 = b[c + g];
-        const uint4 a2 = a[c + 2 * g], b2 = b[c + 2 * g], a3 = a[c + 3 * g], b3 = b[c + 3 * g];
-        acc += popc4(a0, b0) + popc4(a1, b1) + popc4(a2, b2) + popc4(a3, b3);
-    }
-    for (; c < C; c += g) acc += popc4(a[c], b[c]);
-    return acc;
-}
-
 // dst = a AND b over C chunks, the wave's lanes striding by 64, four
 // chunks in flight per lane
 __device__ __forceinline__ void and_rows(uint4 *dst, const uint4 *a, const uint4 *b, uint32_t C,
@@ -900,10 +885,16 @@ __global__ __launch_bounds__(kBlock) void k_root_project(
 // the frequent pairs are reported.  Expanding row r then counts nothing: it
 // builds the child class of row r in the same way.  A class of two atoms
 // never writes its rows (its one pair is all there is to count).  Classes
-// of more than kGramMax atoms (wide first-level classes) are expanded row by
-// row instead: row r is paired with every later row when it is expanded.
+// of more than kGramMax atoms (wide first-level classes) are counted block
+// by block instead: when row r is reached, the pairs of the next kWideRows
+// rows with all later rows are counted in passes of the same Gram code
+// (kWideRows rows against kGramMax - kWideRows later rows at a time) into a
+// block of counts on the wave's stack, and each of those rows reads its
+// counts when it is expanded, so a later row is loaded once per block of
+// rows rather than once per row.
 
 constexpr uint32_t kGramMax = 64;     // widest class counted when it is built
+constexpr uint32_t kWideRows = 32;    // rows of a wide class counted per block
 constexpr uint32_t kTileMin = 32;     // narrowest LDS row tile (words)
 constexpr uint32_t kTileDefault = 256;  // widest LDS row tile unless the autotuner picks another
 constexpr uint32_t kGx = 3200;        // LDS words per wave for row tiles and pair supports
@@ -921,11 +912,14 @@ struct Frame {
                            // (counted classes) sizes of the rows' child classes at +3k
     uint32_t lists;        // counted classes: word offset of the child-class entries
                            // (rank, support, row, item id); kNone: pairs counted on expansion
-    uint32_t lpos;         // counted classes: first entry of row r's child class
+    uint32_t lpos;         // counted classes: first entry of row r's child class;
+                           // wide classes: rows of the block of counts
     uint32_t meta_restore; // meta pointer to restore when the class is done
     // counted classes: rows whose child class has at least two atoms (bit r
     // of m2) and exactly one (m1); rows outside both are passed over without
-    // reading their lists
+    // reading their lists.  Wide classes: m2hi = first row of the block of
+    // counts (kNone: none yet), m2lo = its word offset, m1lo = meta before
+    // it, m1hi = first later row of the next counting pass.
     uint32_t m2lo, m2hi, m1lo, m1hi;
 };
 
@@ -1021,7 +1015,7 @@ __device__ __forceinline__ void close_chunk(OutChunk &c, uint32_t *out) {
 }
 
 // make room for `need` words; returns false when the arena is full
-__device__ bool chunk_reserve(OutChunk &c, uint32_t need, uint32_t task, uint32_t inst,
+__device__ __forceinline__ bool chunk_reserve(OutChunk &c, uint32_t need, uint32_t task, uint32_t inst,
                               uint32_t *out, uint64_t out_cap, DfsCounters *ctr) {
     if (c.base != kNoChunk && c.pos + need <= c.size) return c.valid != 0;
     close_chunk(c, out);
@@ -1115,7 +1109,7 @@ __device__ void sort_atoms(const InstDesc &I, const uint32_t *tmp, uint32_t si, 
 // have about the same number of candidate pairs; a part is worth handing
 // over if it holds several candidate pairs per row the receiver has to
 // rebuild from the level-1 bitmaps.
-__device__ bool try_donate(const InstDesc &I, uint32_t inst, uint32_t plen, uint32_t l2_ref,
+__device__ __forceinline__ bool try_donate(const InstDesc &I, uint32_t inst, uint32_t plen, uint32_t l2_ref,
                            int depth, uint32_t *region, WaveShared &ws, Donation &dn,
                            DfsCounters *ctr) {
     const uint32_t lane = lane_id();
@@ -1433,14 +1427,23 @@ __device__ __forceinline__ uint32_t lds_tile(uint32_t f, uint32_t tmax) {
 // (A <= B over blocks of four rows); a lane accumulates R blocks over whole
 // tiles, or, when there are few blocks, g lanes share a block and split
 // the words.
+// Blocks (A, B) of four rows each counted for a class of f rows: A over the
+// block rows holding rows below r_cnt, B from max(A, bmin) on.
+__device__ __forceinline__ uint32_t lds_blocks(uint32_t f, uint32_t r_cnt, uint32_t bmin) {
+    const uint32_t nb = (f + 3) / 4, nbr = (r_cnt + 3) / 4;
+    uint32_t P = 0;
+    for (uint32_t a = 0; a < nbr; a++) P += nb - max(a, bmin);
+    return P;
+}
+
 template <int R>
 __device__ __forceinline__ void count_lds(const uint32_t *xr, const uint32_t *base, uint32_t Wp,
-                                          uint32_t f, uint32_t r_cnt, uint32_t src, uint32_t *dst,
-                                          uint32_t *gx, uint32_t tmax) {
+                                          uint32_t f, uint32_t r_cnt, uint32_t bmin, uint32_t src,
+                                          uint32_t *dst, uint32_t *gx, uint32_t tmax) {
     const uint32_t lane = lane_id();
     const uint32_t T = lds_tile(f, tmax), CR = T / 4, stride = T + 4;
-    // blocks (A, B), A <= B, of the block rows A holding rows below r_cnt
-    const uint32_t nb = (f + 3) / 4, nbr = (r_cnt + 3) / 4, P = nbr * nb - nbr * (nbr - 1) / 2;
+    // blocks (A, B), B >= max(A, bmin), of the block rows A holding rows below r_cnt
+    const uint32_t nb = (f + 3) / 4, P = lds_blocks(f, r_cnt, bmin);
     uint32_t g = 1;
     if (R == 1)
         while (2 * g * P <= (uint32_t)kWave && g < T) g <<= 1;
@@ -1452,12 +1455,12 @@ __device__ __forceinline__ void count_lds(const uint32_t *xr, const uint32_t *ba
         const uint32_t bp = R == 1 ? lane / g : lane + (uint32_t)kWave * q;
         has[q] = bp < P;
         uint32_t a = 0, rem = has[q] ? bp : 0;
-        while (rem >= nb - a) {
-            rem -= nb - a;
+        while (rem >= nb - max(a, bmin)) {
+            rem -= nb - max(a, bmin);
             a++;
         }
         A[q] = a;
-        B[q] = a + rem;
+        B[q] = max(a, bmin) + rem;
     }
     uint32_t acc[R][16];
 #pragma unroll
@@ -1540,10 +1543,11 @@ __device__ __forceinline__ void count_lds(const uint32_t *xr, const uint32_t *ba
 }
 
 // Pair supports of a class of f atoms (2 <= f <= kGramMax) into ws.gx: the
-// pairs (a, b) of rows a < r_cnt at least (up to kRegGram atoms all pairs).
+// pairs (a, b) of rows a < r_cnt at least (up to kRegGram atoms all pairs),
+// of the rows b of the four-row blocks from bmin on.
 __device__ __forceinline__ void count_class(const uint32_t *xr, const uint32_t *base, uint32_t Wp,
-                                            uint32_t f, uint32_t r_cnt, uint32_t src, uint32_t *dst,
-                                            uint32_t tmax, WaveShared &ws) {
+                                            uint32_t f, uint32_t r_cnt, uint32_t bmin, uint32_t src,
+                                            uint32_t *dst, uint32_t tmax, WaveShared &ws) {
     switch (f) {
         case 2: count_reg<2, 8>(xr, base, Wp, src, dst, ws.gx); break;
         case 3: count_reg<3, 4>(xr, base, Wp, src, dst, ws.gx); break;
@@ -1553,10 +1557,10 @@ __device__ __forceinline__ void count_class(const uint32_t *xr, const uint32_t *
         case 7: count_reg<7, 2>(xr, base, Wp, src, dst, ws.gx); break;
         case 8: count_reg<8, 2>(xr, base, Wp, src, dst, ws.gx); break;
         default: {
-            const uint32_t nb = (f + 3) / 4, nbr = (r_cnt + 3) / 4, P = nbr * nb - nbr * (nbr - 1) / 2;
-            if (P <= (uint32_t)kWave) count_lds<1>(xr, base, Wp, f, r_cnt, src, dst, ws.gx, tmax);
-            else if (P <= 2u * kWave) count_lds<2>(xr, base, Wp, f, r_cnt, src, dst, ws.gx, tmax);
-            else count_lds<3>(xr, base, Wp, f, r_cnt, src, dst, ws.gx, tmax);
+            const uint32_t P = lds_blocks(f, r_cnt, bmin);
+            if (P <= (uint32_t)kWave) count_lds<1>(xr, base, Wp, f, r_cnt, bmin, src, dst, ws.gx, tmax);
+            else if (P <= 2u * kWave) count_lds<2>(xr, base, Wp, f, r_cnt, bmin, src, dst, ws.gx, tmax);
+            else count_lds<3>(xr, base, Wp, f, r_cnt, bmin, src, dst, ws.gx, tmax);
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -1870,6 +1874,10 @@ __device__ __forceinline__ void search(const InstDesc &I, const InstDesc &Ig, ui
     bool b_write = false;
     uint64_t b_rows_base = 0, b_restore = 0;
     EmitTo b_em{0, 0, kNone, 0};
+    // a counting pass of a wide class: its pairs go to the frame's block of
+    // counts (b_rank = the block's first row, b_restore = the pass's first
+    // later row, kNone for the block's own pairs) instead of building a class
+    bool b_counts = false;
     int depth;
     if (k0 <= kGramMax) {
         const uint32_t q = lane < k0 ? lane : 0;
@@ -1886,7 +1894,7 @@ __device__ __forceinline__ void search(const InstDesc &I, const InstDesc &Ig, ui
         b_em = EmitTo{plen, reported0 ? 0u : r_end0, plen == 1 ? l2_ref : kNone, l2_ref};
         depth = -1;
     } else {
-        if (lane == 0) ws.frames[0] = Frame{0u, k0, 0u, r_end0, (uint32_t)meta, kNone, 0u, (uint32_t)S, 0u, 0u, 0u, 0u};
+        if (lane == 0) ws.frames[0] = Frame{0u, k0, 0u, r_end0, (uint32_t)meta, kNone, 0u, (uint32_t)S, 0u, kNone, 0u, 0u};
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         depth = 0;
@@ -1896,19 +1904,52 @@ __device__ __forceinline__ void search(const InstDesc &I, const InstDesc &Ig, ui
     int row0_depth = -1;  // the frame whose row 0 child class is in ws.row0
     for (;;) {
         if (build) {
-            // ---- count the class while building it, list its rows' child classes, push it
+            // ---- count the class while building it, list its rows' child
+            // classes, push it; or (b_counts) count a pass of a wide class's
+            // block of counts.  The one call of the counting code serves both.
             build = false;
+            const bool counts = b_counts;
+            b_counts = false;
             const uint32_t c = b_c;
-            const uint64_t rows_need = b_write ? (uint64_t)c * Wp : 0;
-            const uint64_t meta_need = 4ull * (c * (c - 1) / 2 + kListPad) + 4ull * c + 4;
-            if (meta < meta_need || meta - meta_need < rows_top + rows_need) {
-                flag_stack(ctr, rows_top + rows_need + (S - meta) + meta_need);
-                break;
+            const uint64_t rows_need = (b_write && !counts) ? (uint64_t)c * Wp : 0;
+            if (!counts) {
+                const uint64_t meta_need = 4ull * (c * (c - 1) / 2 + kListPad) + 4ull * c + 4;
+                if (meta < meta_need || meta - meta_need < rows_top + rows_need) {
+                    flag_stack(ctr, rows_top + rows_need + (S - meta) + meta_need);
+                    break;
+                }
+                if (lane < c) ws.cid[lane] = b_id;
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
             }
-            if (lane < c) ws.cid[lane] = b_id;
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            count_class(b_xr, b_base, Wp, c, b_r_end, b_src, b_write ? region + rows_top : nullptr, tmax, ws);
+            // a pass against later rows needs no pairs inside the block
+            count_class(counts ? nullptr : b_xr, b_base, Wp, c, b_r_end,
+                        (counts && (uint32_t)b_restore != kNone) ? uni(ws.frames[depth].lpos) / 4 : 0u, b_src,
+                        rows_need ? region + rows_top : nullptr, tmax, ws);
+            if (counts) {
+                const uint32_t fk = uni(ws.frames[depth].k), nb = uni(ws.frames[depth].lpos);
+                const uint32_t jc = (uint32_t)b_restore;
+                uint32_t *cb = region + uni(ws.frames[depth].m2lo);
+                if (jc == kNone) {
+                    // the block's own pairs (a < b < nb); b_rank = its first row
+                    const uint32_t np2 = c * (c - 1) / 2;
+                    for (uint32_t p = lane; p < np2; p += kWave) {
+                        uint32_t a = 0, b = 1;
+                        pair_of(p, c, a, b);
+                        gst(cb + (uint64_t)a * fk + (b_rank + b), ws.gx[p]);
+                    }
+                } else {
+                    // the block's rows a < nb against the later rows b_jc + q
+                    const uint32_t nq = c - nb;
+                    for (uint32_t e = lane; e < nb * nq; e += kWave) {
+                        const uint32_t a = e / nq, q = e % nq;
+                        gst(cb + (uint64_t)a * fk + (jc + q), ws.gx[pair_index(a, nb + q, c)]);
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                continue;
+            }
             st.pair_words += (unsigned long long)(b_r_end * c - b_r_end * (b_r_end + 1) / 2) * Wp;
             if (depth >= 0) {
                 st.row_words += (unsigned long long)c * Wp;
@@ -2046,7 +2087,54 @@ __device__ __forceinline__ void search(const InstDesc &I, const InstDesc &Ig, ui
             continue;
         }
 
-        // ---- a class too wide to be counted when built: pairs of row r now
+        // ---- a class too wide to be counted when built: its pairs are
+        // counted kWideRows rows at a time (passes through the build block)
+        // before those rows are expanded
+        if (nj > 0) {
+            const uint32_t blk = F.m2hi;
+            if (blk == kNone || r >= blk + F.lpos) {
+                // a new block of counts for the rows [r, r + nb), below the
+                // previous block's place
+                const uint64_t m0 = blk == kNone ? meta : (uint64_t)F.m1lo;
+                const uint32_t nb = min(min(kWideRows, F.k - 1 - r), F.r_end - r);
+                if ((uint64_t)nb * F.k > m0 || m0 - (uint64_t)nb * F.k < rows_top) {
+                    flag_stack(ctr, rows_top + (S - m0) + (uint64_t)nb * F.k);
+                    break;
+                }
+                meta = m0 - (uint64_t)nb * F.k;
+                if (lane == 0) {
+                    ws.frames[depth].m2hi = r;
+                    ws.frames[depth].m2lo = (uint32_t)meta;
+                    ws.frames[depth].m1lo = (uint32_t)m0;
+                    ws.frames[depth].m1hi = r;
+                    ws.frames[depth].lpos = nb;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                continue;
+            }
+            const uint32_t nb = F.lpos;  // rows of the block
+            if (F.m1hi < F.k) {
+                // one pass: the block's own pairs first, then kGramMax - nb
+                // later rows at a time
+                const uint32_t jc = F.m1hi;
+                const bool own = jc == blk;
+                const uint32_t nq = own ? 0u : min(kGramMax - nb, F.k - jc);
+                if (lane == 0) ws.frames[depth].m1hi = own ? blk + nb : jc + nq;
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                if (own && nb < 2) continue;  // no pair inside a one-row block
+                build = true;
+                b_counts = true;
+                b_c = own ? nb : nb + nq;
+                b_r_end = own ? nb - 1 : nb;  // rows whose pairs are counted
+                b_src = lane < nb ? blk + lane : jc + (lane - nb);
+                b_base = region + F.rows_base;
+                b_restore = own ? kNone : jc;
+                b_rank = blk;
+                continue;
+            }
+        }
         if (lane == 0) {
             ws.frames[depth].r = r + 1;
             ws.prefix[plen + depth] = A[r];
@@ -2063,17 +2151,13 @@ __device__ __forceinline__ void search(const InstDesc &I, const InstDesc &Ig, ui
         }
         uint32_t *tmp = region + (meta - 3ull * nj);
         const uint4 *row_r = reinterpret_cast<const uint4 *>(region + F.rows_base + (uint64_t)r * Wp);
+        // row r's counts: row r - blk of the block
+        const uint32_t *cnt_r = region + F.m2lo + (uint64_t)(r - F.m2hi) * F.k;
         uint32_t nf = 0;
-        for (uint32_t jb = 0; jb < nj; jb += ppp) {
-            const uint32_t jj = jb + grp;
-            uint32_t acc = 0;
-            if (jj < nj) {
-                const uint4 *row_j =
-                    reinterpret_cast<const uint4 *>(region + F.rows_base + (uint64_t)(r + 1 + jj) * Wp);
-                acc = popc_rows(row_r, row_j, C, sub, g);
-            }
-            for (uint32_t off = g >> 1; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, kWave);
-            const bool freq = sub == 0 && jj < nj && acc >= I.minsup;
+        for (uint32_t jb = 0; jb < nj; jb += kWave) {
+            const uint32_t jj = jb + lane;
+            const uint32_t acc = jj < nj ? gld(cnt_r + r + 1 + jj) : 0u;
+            const bool freq = jj < nj && acc >= I.minsup;
             const uint64_t mask = __ballot(freq);
             if (freq) {
                 const uint32_t p = nf + lanes_below(mask);
@@ -2192,7 +2276,7 @@ __device__ __forceinline__ void search(const InstDesc &I, const InstDesc &Ig, ui
         st.row_words += (unsigned long long)nf * Wp;
         if (lane == 0)
             ws.frames[depth + 1] = Frame{(uint32_t)rows_top, nf, 0u, nf - 1, (uint32_t)new_meta, kNone, 0u,
-                                         (uint32_t)restore, 0u, 0u, 0u, 0u};
+                                         (uint32_t)restore, 0u, kNone, 0u, 0u};
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         rows_top += (uint64_t)nf * Wp;
