@@ -123,6 +123,21 @@ uint64_t item_count_scratch_words(uint64_t nnz, uint32_t n_item_ids);
 hipError_t launch_item_count(const uint32_t *items, uint64_t nnz, uint32_t *counts,
                              uint32_t n_item_ids, uint32_t *part, hipStream_t stream);
 
+// Item supports of many instances in one launch: instance q's items
+// counted into counts[out, out + n_item_ids) (zero-filled before; the
+// launch adds to them); first_block = the instance's first block, blocks in
+// all = the sum of count_many_blocks(nnz) over the instances in order.
+struct CountSrc {
+    const uint32_t *items;
+    uint64_t nnz;
+    uint64_t out;
+    uint32_t n_item_ids;
+    uint32_t first_block;
+};
+uint32_t count_many_blocks(uint64_t nnz);
+hipError_t launch_item_count_many(const CountSrc *src, uint32_t n_src, uint32_t blocks, uint32_t max_ids,
+                                  uint32_t *counts, hipStream_t stream);
+
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t stream);
 // n words set to zero, except the 64-bit value v at words [at, at + 2)
 hipError_t launch_fill_words(uint32_t *p, uint64_t n, uint64_t at, unsigned long long v,

@@ -129,6 +129,37 @@ __global__ __launch_bounds__(kBlock) void k_item_count(const uint32_t *__restric
         atomicAdd(&counts[items[p]], 1u);
 }
 
+// Several instances at once: block b belongs to the instance whose block
+// range holds it (binary search over first_block) and counts its chunk of
+// kCountChunk items in LDS (up to kHistItems item ids; more: global atomics
+// per item), then adds its non-zero bins to the instance's supports.
+constexpr uint64_t kCountChunk = 1ull << 18;
+
+__global__ __launch_bounds__(kBlock) void k_item_count_many(const CountSrc *__restrict__ src,
+                                                             uint32_t n_src, uint32_t *counts) {
+    extern __shared__ uint32_t hist[];
+    const uint32_t b = blockIdx.x;
+    uint32_t lo = 0, hi = n_src;  // src[lo].first_block <= b < src[hi].first_block
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (src[mid].first_block <= b) lo = mid;
+        else hi = mid;
+    }
+    const CountSrc S = src[lo];
+    const uint64_t a = (uint64_t)(b - S.first_block) * kCountChunk, e = min(S.nnz, a + kCountChunk);
+    uint32_t *dst = counts + S.out;
+    if (S.n_item_ids > kHistItems) {
+        for (uint64_t p = a + threadIdx.x; p < e; p += kBlock) atomicAdd(&dst[S.items[p]], 1u);
+        return;
+    }
+    for (uint32_t i = threadIdx.x; i < S.n_item_ids; i += kBlock) hist[i] = 0;
+    __syncthreads();
+    for (uint64_t p = a + threadIdx.x; p < e; p += kBlock) atomicAdd(&hist[S.items[p]], 1u);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < S.n_item_ids; i += kBlock)
+        if (hist[i]) atomicAdd(&dst[i], hist[i]);
+}
+
 // n words: the 64-bit value v at words [at, at + 2), zero elsewhere
 __global__ void k_fill_words(uint32_t *p, uint64_t n, uint64_t at, unsigned long long v) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -2824,6 +2855,16 @@ hipError_t launch_item_count(const uint32_t *items, uint64_t nnz, uint32_t *coun
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_item_sum, dim3((n_item_ids + kWave - 1) / kWave), dim3(kBlock), 0, stream,
                        part, nb, n_item_ids, counts);
+    return hipGetLastError();
+}
+
+uint32_t count_many_blocks(uint64_t nnz) { return (uint32_t)((nnz + kCountChunk - 1) / kCountChunk); }
+
+hipError_t launch_item_count_many(const CountSrc *src, uint32_t n_src, uint32_t blocks, uint32_t max_ids,
+                                  uint32_t *counts, hipStream_t stream) {
+    if (n_src == 0 || blocks == 0) return hipSuccess;
+    const size_t lds = (size_t)std::min<uint32_t>(max_ids, kHistItems) * 4;
+    hipLaunchKernelGGL(k_item_count_many, dim3(blocks), dim3(kBlock), lds, stream, src, n_src, counts);
     return hipGetLastError();
 }
 

@@ -555,6 +555,7 @@ struct Inst {
     uint64_t n_pairs = 0;
     std::vector<uint32_t> l2_off, l2_atom, l2_supp;
     DevBuf d_counts, d_rank_of_item, d_rows, d_pairs, d_npairs;
+    uint32_t *p_counts = nullptr;  // item supports on the device (d_counts or a batch's shared array)
     DevBuf d_l2_off, d_l2_atom, d_l2_supp;
     bool l2_on_device = false;  // the l2 arrays above hold l2_off, l2_atom, l2_supp
     // root-class kernel: 0 whole rows, 1 covers, 2 projected transactions
@@ -1077,29 +1078,47 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         return hipSuccess;
     };
     const uint32_t n_lanes = side.empty() ? 1u : (uint32_t)side.size();
-    uint64_t part_words = 0;
-    for (uint32_t q = 0; q < n_inst; q++)
-        part_words = std::max(part_words, item_count_scratch_words(reqs[q].db->nnz, reqs[q].db->n_item_ids));
-    DevBuf d_part(ctx);
-    if (part_words) ENSURE(d_part, ctx, part_words * n_lanes * 4);
     std::vector<uint64_t> count_at(n_inst + 1, 0);
     for (uint32_t q = 0; q < n_inst; q++) count_at[q + 1] = count_at[q] + reqs[q].db->n_item_ids;
     PinnedBlock h_counts(count_at[n_inst] * 4);
-    HIPCHK(fork());
-    for (uint32_t q = 0; q < n_inst; q++) {
-        Inst &I = insts[q];
-        I.db = reqs[q].db;
-        I.minsup = reqs[q].minsup;
+    DevBuf d_part(ctx), d_counts_all(ctx), d_count_src(ctx);
+    if (n_inst > 1) {
+        // every instance's item supports in one launch into one array, and
+        // one copy back
+        std::vector<CountSrc> src(n_inst);
+        uint32_t blocks = 0, max_ids = 0;
+        for (uint32_t q = 0; q < n_inst; q++) {
+            Inst &I = insts[q];
+            I.db = reqs[q].db;
+            I.minsup = reqs[q].minsup;
+            src[q] = CountSrc{I.db->d_items.as<uint32_t>(), I.db->nnz, count_at[q], I.db->n_item_ids, blocks};
+            blocks += count_many_blocks(I.db->nnz);
+            max_ids = std::max(max_ids, I.db->n_item_ids);
+        }
+        ENSURE(d_counts_all, ctx, std::max<uint64_t>(count_at[n_inst], 1) * 4);
+        ENSURE(d_count_src, ctx, n_inst * sizeof(CountSrc));
+        HIPCHK(h2d(ctx, d_count_src.as<void>(), src.data(), n_inst * sizeof(CountSrc), s));
+        HIPCHK(launch_fill_u32(d_counts_all.as<uint32_t>(), count_at[n_inst], 0u, s));
+        HIPCHK(launch_item_count_many(d_count_src.as<CountSrc>(), n_inst, blocks, max_ids,
+                                      d_counts_all.as<uint32_t>(), s));
+        if (count_at[n_inst])
+            HIPCHK(hipMemcpyAsync(h_counts.as<uint32_t>(), d_counts_all.as<void>(), count_at[n_inst] * 4,
+                                  hipMemcpyDeviceToHost, s));
+        for (uint32_t q = 0; q < n_inst; q++) insts[q].p_counts = d_counts_all.as<uint32_t>() + count_at[q];
+    } else {
+        Inst &I = insts[0];
+        I.db = reqs[0].db;
+        I.minsup = reqs[0].minsup;
         const uint32_t ni = I.db->n_item_ids;
-        const uint32_t lane = q % n_lanes;
-        const hipStream_t sq = side.empty() ? s : side[lane];
+        const uint64_t part_words = item_count_scratch_words(I.db->nnz, ni);
+        if (part_words) ENSURE(d_part, ctx, part_words * 4);
         ENSURE(I.d_counts, ctx, (size_t)ni * 4);
         HIPCHK(launch_item_count(I.db->d_items.as<uint32_t>(), I.db->nnz, I.d_counts.as<uint32_t>(), ni,
-                                 part_words ? d_part.as<uint32_t>() + lane * part_words : nullptr, sq));
-        HIPCHK(hipMemcpyAsync(h_counts.as<uint32_t>() + count_at[q], I.d_counts.as<void>(),
-                              (size_t)ni * 4, hipMemcpyDeviceToHost, sq));
+                                 part_words ? d_part.as<uint32_t>() : nullptr, s));
+        HIPCHK(hipMemcpyAsync(h_counts.as<uint32_t>(), I.d_counts.as<void>(), (size_t)ni * 4,
+                              hipMemcpyDeviceToHost, s));
+        I.p_counts = I.d_counts.as<uint32_t>();
     }
-    HIPCHK(join());
     HIPCHK(stream_wait(s));
     for (uint32_t q = 0; q < n_inst; q++)
         insts[q].counts.assign(h_counts.as<uint32_t>() + count_at[q], h_counts.as<uint32_t>() + count_at[q + 1]);
@@ -1609,7 +1628,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
                 const Inst &I = insts[q];
                 const uint64_t np = opts.max_len != 1 ? I.n_pairs : 0;
                 if (I.n_freq + np == 0) continue;
-                key_prefix.push_back(PrefixSrc{I.p_item_of_rank, I.d_counts.as<uint32_t>(),
+                key_prefix.push_back(PrefixSrc{I.p_item_of_rank, I.p_counts,
                                                np ? I.d_pairs.as<uint32_t>() : nullptr, I.n_freq,
                                                bits_of[q], q, 0u, np, at});
                 at += I.n_freq + np;
