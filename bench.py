@@ -591,6 +591,10 @@ def main(argv=None):
     ap.add_argument("--lanes", type=int, default=0, help="server lanes (0 = default)")
     ap.add_argument("--study", action="store_true",
                     help="only run the estimator study and print its JSON line")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only mine the batch instances --batch-steps times with default "
+                         "options, after one untimed call (for kernel traces of the batched "
+                         "path), and print their times")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes three times (the "
                          "reference for scaling the HBM byte counters) and exit")
@@ -622,6 +626,29 @@ def main(argv=None):
         ctx = F.Context(0)
         print(json.dumps({"study": "estimator", "results": study(F, ctx, args)}), flush=True)
         ctx.close()
+        return 0
+
+    if args.batch_only:
+        ctx = F.Context(0)
+        g = load_golden("batch-256.json")
+        subs = [g["instances"][i]["substream"] for i in range(args.batch)] if g else list(range(args.batch))
+        handles, minsups = [], []
+        for sub in subs:
+            d = synth.batch_instance(synth.batch_params(sub))
+            handles.append(F.Database(ctx, d.offsets, d.items, d.n_items))
+            minsups.append(d.minsup)
+        res = F.mine_batch(ctx, handles, minsups)
+        ok = None if not g else all(digest(r_) == g["instances"][i]["digest"] for i, r_ in enumerate(res))
+        del res
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(args.batch_steps):
+            t0 = time.perf_counter()
+            res = F.mine_batch(ctx, handles, minsups)
+            times.append((time.perf_counter() - t0) * 1e3)
+            del res
+        print(json.dumps({"batch_only": args.batch, "calls": args.batch_steps, "ms": times,
+                          "verified_vs_oracle": ok}), flush=True)
         return 0
 
     ctx = F.Context(0)

@@ -236,6 +236,6 @@ hipError_t launch_dfs(const InstDesc *insts, const Task *tasks, uint64_t n_tasks
                       DfsCounters *ctr, InstCounters *ictr, unsigned long long *don_slots,
                       uint64_t n_slots, uint32_t *don_heap, uint64_t heap_words,
                       uint64_t wait_ticks, unsigned long long *trace, uint32_t variant,
-                      uint32_t nap_max, hipStream_t stream);
+                      uint32_t nap_max, uint64_t poll_ticks, hipStream_t stream);
 
 }  // namespace fim

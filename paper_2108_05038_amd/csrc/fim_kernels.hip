@@ -1025,6 +1025,7 @@ struct Donation {
     uint32_t enabled;
     unsigned long long *trace;  // WaveTrace per wave, or null
     uint32_t nap_max;           // longest back-off of an idle wave, in naps of ~8000 cycles
+    uint64_t poll_ticks;        // a busy wave looks for idle waves at most this often (wall clock)
 };
 
 // Output of one piece of work goes to chunks of the output arena claimed
@@ -1931,7 +1932,8 @@ __device__ __forceinline__ void search(const InstDesc &I, const InstDesc &Ig, ui
         depth = 0;
     }
 
-    uint32_t polls = 0, cool = 0, iters = 0;
+    uint32_t cool = 0, iters = 0;
+    unsigned long long last_poll = wall_clock64();
     int row0_depth = -1;  // the frame whose row 0 child class is in ws.row0
     for (;;) {
         if (build) {
@@ -2005,7 +2007,17 @@ __device__ __forceinline__ void search(const InstDesc &I, const InstDesc &Ig, ui
         }
         if (depth < 0) break;
         if ((++iters & 63u) == 0 && inst_stopped(I, ictr, inst)) break;
-        if (dn.enabled && cool == 0 && ((++polls & 7u) == 0) && donation_wanted(ctr)) {
+        // idle waves are looked for by wall clock, not by row count: a row
+        // of a wide dense class can take far longer than many small rows
+        bool poll = false;
+        if (dn.enabled && cool == 0) {
+            const unsigned long long now = wall_clock64();
+            if (now - last_poll >= dn.poll_ticks) {
+                poll = true;
+                last_poll = now;
+            }
+        }
+        if (poll && donation_wanted(ctr)) {
             const bool gave = try_donate(Ig, inst, plen, l2_ref, depth, region, ws, dn, ctr);
             cool = gave ? 8u : 4u;
             st.given += gave ? 1u : 0u;
@@ -3087,12 +3099,12 @@ hipError_t launch_dfs(const InstDesc *insts, const Task *tasks, uint64_t n_tasks
                       uint32_t *out, uint64_t out_cap, DfsCounters *ctr, InstCounters *ictr,
                       unsigned long long *don_slots, uint64_t n_slots, uint32_t *don_heap,
                       uint64_t heap_words, uint64_t wait_ticks, unsigned long long *trace,
-                      uint32_t variant, uint32_t nap_max, hipStream_t stream) {
+                      uint32_t variant, uint32_t nap_max, uint64_t poll_ticks, hipStream_t stream) {
     if (n_tasks == 0) return hipSuccess;
     const uint32_t blocks = (n_workers + kWavesPerBlock - 1) / kWavesPerBlock;
     Donation dn{don_slots, don_heap, n_slots, heap_words, wait_ticks,
                 (don_slots && don_heap && n_slots && heap_words) ? 1u : 0u, trace,
-                nap_max ? nap_max : 64u};
+                nap_max ? nap_max : 64u, poll_ticks ? poll_ticks : 1u};
     const uint32_t tpc = tasks_per_claim ? tasks_per_claim : 1u;
     const uint32_t tmax = variant ? tile_variant(variant) : kTileDefault;
     hipLaunchKernelGGL(k_dfs, dim3(blocks), dim3(kBlock), 0, stream, insts, tasks, n_tasks, stack,
