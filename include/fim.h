@@ -234,8 +234,7 @@ fim_status fim_mine(fim_ctx *ctx, const fim_db *db, uint32_t minsup_abs, const f
                     fim_result **out);
 
 /*
- * Mine n independent instances in one persistent launch (captured in a HIP
- * graph).  dbs[n] and minsups[n]; outs[n] receives one result per instance,
+ * Mine n independent instances in one persistent launch.  dbs[n] and minsups[n]; outs[n] receives one result per instance,
  * identical to what fim_mine returns for that instance.  All-or-nothing: on
  * error no result is returned.
  */

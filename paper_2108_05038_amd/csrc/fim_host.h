@@ -212,7 +212,7 @@ struct MineRequest {
 // Mine every request; results[i] receives the canonical result of request i.
 // Used by fim_mine (one request), fim_mine_batch and the server.
 fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const fim_options &opts,
-                     std::vector<fim_result *> &results, bool use_graph);
+                     std::vector<fim_result *> &results);
 
 // Resolved option values.
 fim_options resolve_options(const fim_options *opts);

@@ -77,7 +77,7 @@ extern "C" fim_status fim_mine_noalloc(fim_ctx *ctx, const fim_db *db, uint32_t 
     fim_options o = opts ? *opts : fim_options{};
     o.flags |= FIM_FLAG_NO_ESTIMATE;  // the estimate would mine a sample on a second context
     std::vector<fim_result *> res;
-    st = fim::mine_many(ctx, {fim::MineRequest{db, minsup_abs}}, o, res, false);
+    st = fim::mine_many(ctx, {fim::MineRequest{db, minsup_abs}}, o, res);
     if (st != FIM_OK) {
         if (st == FIM_E_OOM_DEVICE)
             fim::set_error(st, std::string(fim_last_error()) + " (the work does not fit the " +

@@ -145,7 +145,7 @@ fim_status sample_phase(fim_ctx *ctx, const std::vector<PlanInput> &in, const fi
     so.flags |= FIM_FLAG_NO_ESTIMATE | kFlagInternalSample;
     so.max_itemsets = 0;
     so.max_len = 0;
-    return mine_many(ctx, reqs, so, est.res, false);
+    return mine_many(ctx, reqs, so, est.res);
 }
 
 // Row weights of every first-level class from the sample, or empty when no

@@ -208,7 +208,7 @@ extern "C" fim_status fim_ctx_create(int device, void *hip_stream, const fim_all
     if (!c) return fim::set_error(FIM_E_OOM_HOST, "ctx");
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
-    if (!c->stream) {  // graph capture needs a stream other than the null stream
+    if (!c->stream) {  // a caller capturing work into a graph needs a stream other than the null one
         if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
             delete c;
             return fim::set_error(FIM_E_DEVICE, "hipStreamCreate failed");
@@ -689,7 +689,6 @@ static void build_level2(Inst &I, bool by_id) {
 struct DfsLaunch {
     uint64_t frame0 = 0;  // words of the largest first frame
     uint32_t variant = 0, n_workers = 0, claim = 1, nap_max = 64;
-    bool use_graph = false;
     bool cap_output = false;     // a full output arena ends the run (internal sample runs)
     bool stop_is_error = true;   // an instance over its record budget is an error
     uint64_t out_cap = 1ull << 24;
@@ -797,24 +796,7 @@ static fim_status run_persistent(fim_ctx *ctx, hipStream_t s, Tracer &tr,
                               tr.on ? d_trace.as<unsigned long long>() : nullptr, L.variant, nap_max,
                               poll_ticks, s);
         };
-        if (L.use_graph) {
-            hipGraph_t g;
-            hipGraphExec_t ge;
-            HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            hipError_t le = launch();
-            hipError_t ce = hipStreamEndCapture(s, &g);
-            if (le != hipSuccess || ce != hipSuccess)
-                return set_error(FIM_E_DEVICE, std::string("graph capture: ") +
-                                                   hipGetErrorString(le != hipSuccess ? le : ce));
-            hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-            if (ie == hipSuccess) ie = hipGraphLaunch(ge, s);
-            (void)hipGraphExecDestroy(ge);
-            (void)hipGraphDestroy(g);
-            if (ie != hipSuccess)
-                return set_error(FIM_E_DEVICE, std::string("graph launch: ") + hipGetErrorString(ie));
-        } else {
-            HIPCHK(launch());
-        }
+        HIPCHK(launch());
         HIPCHK(hipEventRecord(ev1, s));
         // both kinds of counters in one copy
         std::vector<char> h_cnt(sizeof(DfsCounters) + sizeof(InstCounters) * n_inst);
@@ -1036,7 +1018,7 @@ static fim_status count_estimate(fim_ctx *ctx, hipStream_t s, Tracer &tr, std::v
 }
 
 fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const fim_options &opts_in,
-                     std::vector<fim_result *> &results, bool use_graph) {
+                     std::vector<fim_result *> &results) {
     const auto t_start = clk::now();
     const fim_options opts = resolve_options(&opts_in);
     const bool sample_run = (opts.flags & kFlagInternalSample) != 0;
@@ -1618,7 +1600,6 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         // slows those updates more than it speeds up hand-overs, while a
         // short run mostly waits for its last sleepers to wake.
         L.nap_max = deep_work ? 64 : 16;
-        L.use_graph = use_graph;
         L.cap_output = (opts.flags & kFlagInternalSample) != 0;
         L.stop_is_error = !L.cap_output;
         // a generous arena (kept by the context's block cache between calls):
@@ -1666,7 +1647,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             // an itemset longer than a key holds: the same call with records
             fim_options ro = opts_in;
             ro.flags |= kFlagInternalRecords;
-            return mine_many(ctx, reqs, ro, results, use_graph);
+            return mine_many(ctx, reqs, ro, results);
         }
         ctr = L.ctr;
         ictr = L.ictr;
@@ -1977,7 +1958,7 @@ extern "C" fim_status fim_mine(fim_ctx *ctx, const fim_db *db, uint32_t minsup_a
     if (minsup_abs == 0) return fim::set_error(FIM_E_INVALID_ARG, "minsup_abs must be >= 1");
     std::vector<fim::MineRequest> reqs{{db, minsup_abs}};
     std::vector<fim_result *> res;
-    fim_status st = fim::mine_many(ctx, reqs, fim::resolve_options(opts), res, false);
+    fim_status st = fim::mine_many(ctx, reqs, fim::resolve_options(opts), res);
     if (st != FIM_OK) return st;
     *out = res[0];
     return FIM_OK;
@@ -2000,7 +1981,7 @@ extern "C" fim_status fim_mine_batch(fim_ctx *ctx, uint32_t n, const fim_db *con
     }
     if (n == 0) return FIM_OK;
     std::vector<fim_result *> res;
-    fim_status st = fim::mine_many(ctx, reqs, fim::resolve_options(opts), res, true);
+    fim_status st = fim::mine_many(ctx, reqs, fim::resolve_options(opts), res);
     if (st != FIM_OK) return st;
     for (uint32_t q = 0; q < n; q++) outs[q] = res[q];
     return FIM_OK;
@@ -2059,7 +2040,7 @@ extern "C" fim_status fim_class_profile(fim_ctx *ctx, const fim_db *db, uint32_t
     fim_options o = opts ? *opts : fim_options{};
     o.flags = (o.flags | FIM_FLAG_ALWAYS_ESTIMATE) & ~(FIM_FLAG_NO_ESTIMATE | FIM_FLAG_RESERVOIR);
     std::vector<fim_result *> res;
-    const fim_status st = fim::mine_many(ctx, {fim::MineRequest{db, minsup_abs}}, o, res, false);
+    const fim_status st = fim::mine_many(ctx, {fim::MineRequest{db, minsup_abs}}, o, res);
     fim::g_profile = nullptr;
     for (fim_result *r : res) fim_result_destroy(r);
     if (st != FIM_OK) return st;

@@ -133,7 +133,7 @@ void worker_loop(fim_server *s, fim_ctx *ctx) {
         std::vector<fim::MineRequest> reqs;
         for (const Request &r : batch) reqs.push_back({r.db, r.minsup});
         std::vector<fim_result *> res;
-        fim_status st = fim::mine_many(ctx, reqs, s->cfg.opts, res, true);
+        fim_status st = fim::mine_many(ctx, reqs, s->cfg.opts, res);
         std::string err = st == FIM_OK ? "" : fim_last_error();
         {
             std::lock_guard<std::mutex> lk(s->mu);
