@@ -1433,7 +1433,7 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             // task per second-level class; its cost is then a few times the
             // time of a sample-sized search, and it pays where the database
             // is much longer than the sample (measured: dense-200k = 43 |D~|
-            // 54.8 ms with it against 62.8 ms without; dense-50k = 13 |D~|
+            // 54.8 ms with it against 62.8 ms without; dense-50k = 11 |D~|
             // 12.1 ms with it against 11.1 ms without).  It is drawn for at
             // least 16 |D~| transactions, and only for a launch of one
             // instance: in a batch the other instances' classes fill the
