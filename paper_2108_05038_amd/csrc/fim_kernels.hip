@@ -23,6 +23,22 @@ __device__ __forceinline__ uint32_t popc4(uint4 a, uint4 b) {
     return __popc(a.x & b.x) + __popc(a.y & b.y) + __popc(a.z & b.z) + __popc(a.w & b.w);
 }
 
+// acc + popcount(x) as one v_bcnt_u32_b32 (the compiler would sum the
+// popcounts of a chunk with separate adds: a fifth more VALU operations)
+__device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
+    uint32_t r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+    return r;
+}
+
+// acc += popcount(a AND b) over a 128-bit chunk
+__device__ __forceinline__ void acc_popc4(uint32_t &acc, uint4 a, uint4 b) {
+    acc = bcnt_acc(a.x & b.x, acc);
+    acc = bcnt_acc(a.y & b.y, acc);
+    acc = bcnt_acc(a.z & b.z, acc);
+    acc = bcnt_acc(a.w & b.w, acc);
+}
+
 __device__ __forceinline__ uint4 and4(uint4 a, uint4 b) {
     return make_uint4(a.x & b.x, a.y & b.y, a.z & b.z, a.w & b.w);
 }
@@ -928,11 +944,13 @@ constexpr uint32_t kGramMax = 64;     // widest class counted when it is built
 constexpr uint32_t kWideRows = 32;    // rows of a wide class counted per block
 constexpr uint32_t kTileMin = 32;     // narrowest LDS row tile (words)
 constexpr uint32_t kTileDefault = 256;  // widest LDS row tile unless the autotuner picks another
-constexpr uint32_t kGx = 3200;        // LDS words per wave for row tiles and pair supports
+constexpr uint32_t kGx = 4640;        // LDS words per wave for row tiles and pair supports
 constexpr uint32_t kMaxTileRows = 8;  // rows of a tile one lane loads (see count_lds)
 constexpr uint32_t kListPad = kWave;  // list entries past a class's lists that a wave may read
 static_assert(kGx >= kGramMax * (kGramMax - 1) / 2, "pair supports fit in the tile area");
-static_assert(4 * ((kGramMax + 3) / 4) * (kTileMin + 4) <= kGx, "the widest class fits a narrowest tile");
+static_assert(4 * ((kGramMax + 3) / 4) * (kTileMin + 4) +
+                      17 * ((kGramMax + 3) / 4) * ((kGramMax + 3) / 4 + 1) / 2 <= kGx,
+              "the widest class fits a narrowest tile with its block counts");
 
 struct Frame {
     uint32_t rows_base;    // word offset of the class's row 0 (rows_top when it was pushed)
@@ -1339,15 +1357,20 @@ __device__ __forceinline__ uint32_t pair_index(uint32_t a, uint32_t b, uint32_t 
     return a * f - a * (a + 1) / 2 + (b - a - 1);
 }
 
-// the pair of index p (inverse of pair_index)
+// the pair of index p < f (f - 1) / 2 (inverse of pair_index): row a is the
+// largest x with pair_index(x, x + 1, f) <= p, the smaller root of
+// x^2 - (2f - 1) x + 2p = 0 rounded down; the single-precision estimate is
+// corrected by whole rows, so the result is exact
 __device__ __forceinline__ void pair_of(uint32_t p, uint32_t f, uint32_t &a, uint32_t &b) {
-    uint32_t x = 0;
-    while (x + 1 < f && p >= f - 1 - x) {
-        p -= f - 1 - x;
-        x++;
-    }
-    a = x;
-    b = x + 1 + p;
+    const float h = 2.0f * (float)f - 1.0f;
+    const float d = h * h - 8.0f * (float)p;
+    int x = (int)((h - __builtin_sqrtf(d > 0.0f ? d : 0.0f)) * 0.5f);
+    x = max(0, min(x, (int)f - 2));
+    auto first = [f](int r) { return (uint32_t)r * f - (uint32_t)r * (uint32_t)(r + 1) / 2; };
+    while (x > 0 && first(x) > p) x--;
+    while (x + 2 < (int)f && first(x + 1) <= p) x++;
+    a = (uint32_t)x;
+    b = p - first(x) + (uint32_t)x + 1;
 }
 
 // Reduce-scatter of N values (N a power of two, at most 32) over the wave:
@@ -1435,7 +1458,7 @@ __device__ __forceinline__ void count_reg(const uint32_t *xr, const uint32_t *ba
 #pragma unroll
             for (int a = 0; a < F; a++)
 #pragma unroll
-                for (int b = a + 1; b < F; b++) acc[p++] += popc4(x[u][a], x[u][b]);
+                for (int b = a + 1; b < F; b++) acc_popc4(acc[p++], x[u][a], x[u][b]);
         }
     }
     const uint32_t s = reduce_scatter<N>(acc, lane);
@@ -1443,22 +1466,6 @@ __device__ __forceinline__ void count_reg(const uint32_t *xr, const uint32_t *ba
     if ((lane & (kWave / N - 1)) == 0 && idx < (uint32_t)NP) gx[idx] = s;
 }
 
-// LDS tile width (words) of a class of f atoms: the widest power of two up
-// to tmax with f rows of it, padded to a multiple of four rows (row stride
-// width + 4), in kGx words, and at most kMaxTileRows chunks per lane
-__device__ __forceinline__ uint32_t lds_tile(uint32_t f, uint32_t tmax) {
-    uint32_t t = tmax;
-    while (t > kTileMin && (4 * ((f + 3) / 4) * (t + 4) > kGx || f * t > 256 * kMaxTileRows)) t >>= 1;
-    return t;
-}
-
-// The same for kRegGram < f <= kGramMax atoms, with the rows staged in LDS
-// tile by tile (T words per tile, row stride T + 4 words; lane l loads chunk
-// l mod T/4 of its rows).  The next tile is loaded into registers while the
-// pairs of the current one are counted.  The pairs are cut into 4x4 blocks
-// (A <= B over blocks of four rows); a lane accumulates R blocks over whole
-// tiles, or, when there are few blocks, g lanes share a block and split
-// the words.
 // Blocks (A, B) of four rows each counted for a class of f rows: A over the
 // block rows holding rows below r_cnt, B from max(A, bmin) on.
 __device__ __forceinline__ uint32_t lds_blocks(uint32_t f, uint32_t r_cnt, uint32_t bmin) {
@@ -1468,39 +1475,58 @@ __device__ __forceinline__ uint32_t lds_blocks(uint32_t f, uint32_t r_cnt, uint3
     return P;
 }
 
-template <int R>
+// LDS tile width (words) of a class of f atoms with P blocks: the widest
+// power of two up to tmax such that the tile (f rows padded to a multiple
+// of four, row stride width + 4) and the blocks' counts and table (17 P
+// words) fit in kGx words, with at most kMaxTileRows chunks per lane
+__device__ __forceinline__ uint32_t lds_tile(uint32_t f, uint32_t P, uint32_t tmax) {
+    uint32_t t = tmax;
+    while (t > kTileMin && (4 * ((f + 3) / 4) * (t + 4) + 17 * P > kGx || f * t > 256 * kMaxTileRows)) t >>= 1;
+    return t;
+}
+
+// The same for kRegGram < f <= kGramMax atoms, with the rows staged in LDS
+// tile by tile (T words per tile, row stride T + 4 words; lane l loads chunk
+// l mod T/4 of its rows).  The next tile is loaded into registers while the
+// pairs of the current one are counted.  The pairs are cut into 4x4 blocks
+// (lds_blocks), and the words of a tile into G slices; the P G items (block,
+// slice) of a tile are dealt to the 64 lanes in rounds, so that all lanes
+// count whatever the number of blocks.  A lane reads its slice of the
+// block's eight rows 128 bits at a time, accumulates the 16 pairs in
+// registers and adds them to the block's counts in LDS.
 __device__ __forceinline__ void count_lds(const uint32_t *xr, const uint32_t *base, uint32_t Wp,
                                           uint32_t f, uint32_t r_cnt, uint32_t bmin, uint32_t src,
                                           uint32_t *dst, uint32_t *gx, uint32_t tmax) {
     const uint32_t lane = lane_id();
-    const uint32_t T = lds_tile(f, tmax), CR = T / 4, stride = T + 4;
-    // blocks (A, B), B >= max(A, bmin), of the block rows A holding rows below r_cnt
     const uint32_t nb = (f + 3) / 4, P = lds_blocks(f, r_cnt, bmin);
-    uint32_t g = 1;
-    if (R == 1)
-        while (2 * g * P <= (uint32_t)kWave && g < T) g <<= 1;
-    const uint32_t sub = lane % g;
-    uint32_t A[R], B[R];
-    bool has[R];
-#pragma unroll
-    for (int q = 0; q < R; q++) {
-        const uint32_t bp = R == 1 ? lane / g : lane + (uint32_t)kWave * q;
-        has[q] = bp < P;
-        uint32_t a = 0, rem = has[q] ? bp : 0;
+    const uint32_t T = lds_tile(f, P, tmax), CR = T / 4, stride = T + 4;
+    uint32_t *cnt = gx + 4 * nb * stride;  // 16 counts of each block (A row i, B row j at 4 i + j)
+    uint32_t *blk = cnt + 16 * P;          // block p: (A << 16) | B
+    for (uint32_t p = lane; p < P; p += kWave) {
+        uint32_t a = 0, rem = p;
         while (rem >= nb - max(a, bmin)) {
             rem -= nb - max(a, bmin);
             a++;
         }
-        A[q] = a;
-        B[q] = max(a, bmin) + rem;
+        blk[p] = (a << 16) | (max(a, bmin) + rem);
     }
-    uint32_t acc[R][16];
-#pragma unroll
-    for (int q = 0; q < R; q++)
-#pragma unroll
-        for (int e = 0; e < 16; e++) acc[q][e] = 0;
+    for (uint32_t i = lane; i < 16 * P; i += kWave) cnt[i] = 0u;
     // tile rows from f up to 4 nb pad the last block with zeros
     for (uint32_t i = f * stride + lane; i < 4 * nb * stride; i += kWave) gx[i] = 0u;
+    // slices: the G of least cost over the rounds of 64 items, a round
+    // costing about 34 operations per word of a slice plus 36 per item
+    uint32_t G = 1, best = ~0u;
+    for (uint32_t g = 1; g <= CR; g <<= 1) {
+        const uint32_t cost = ((P * g + kWave - 1) / kWave) * ((T / g) * 34 + 36);
+        if (cost < best) {
+            best = cost;
+            G = g;
+        }
+    }
+    const uint32_t NI = P * G, SW = T / G;
+    // item i = s P + p; a lane's items are lane, lane + 64, ...
+    const uint32_t p0 = P ? lane % P : 0u, s0 = P ? lane / P : 0u;
+    const uint32_t dp = P ? (uint32_t)kWave % P : 0u, dsl = P ? (uint32_t)kWave / P : 0u;
     // this lane's chunks of a tile: chunk cc of rows q0 + j * (64 / CR)
     const uint32_t cc = lane % CR, q0 = lane / CR, qs = kWave / CR;
     const uint32_t nl = q0 < f ? (f - q0 + qs - 1) / qs : 0u;  // rows of this lane
@@ -1534,43 +1560,48 @@ __device__ __forceinline__ void count_lds(const uint32_t *xr, const uint32_t *ba
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         if (w0 + T < Wp) load(w0 + T);
+        uint32_t p = p0, sl = s0;
+#pragma unroll 1
+        for (uint32_t i0 = 0; i0 < NI; i0 += kWave) {
+            if (i0 + lane < NI) {
+                const uint32_t ab = blk[p];
+                const uint32_t *ra = gx + 4 * (ab >> 16) * stride + sl * SW;
+                const uint32_t *rb = gx + 4 * (ab & 0xffffu) * stride + sl * SW;
+                uint32_t acc[16];
 #pragma unroll
-        for (int q = 0; q < R; q++) {
-            if (!has[q]) continue;
-            const uint32_t *ra = gx + 4 * A[q] * stride, *rb = gx + 4 * B[q] * stride;
-#pragma unroll 2
-            for (uint32_t t = sub; t < T; t += g) {
-                uint32_t av[4], bv[4];
+                for (int e = 0; e < 16; e++) acc[e] = 0;
+#pragma unroll 1
+                for (uint32_t t = 0; t < SW; t += 4) {
+                    uint4 av[4], bv[4];
 #pragma unroll
-                for (int i = 0; i < 4; i++) {
-                    av[i] = ra[i * stride + t];
-                    bv[i] = rb[i * stride + t];
+                    for (int i = 0; i < 4; i++) {
+                        av[i] = *reinterpret_cast<const uint4 *>(ra + i * stride + t);
+                        bv[i] = *reinterpret_cast<const uint4 *>(rb + i * stride + t);
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; i++)
+#pragma unroll
+                        for (int j = 0; j < 4; j++) acc_popc4(acc[i * 4 + j], av[i], bv[j]);
                 }
 #pragma unroll
-                for (int i = 0; i < 4; i++)
-#pragma unroll
-                    for (int j = 0; j < 4; j++) acc[q][i * 4 + j] += __popc(av[i] & bv[j]);
+                for (int e = 0; e < 16; e++) atomicAdd(cnt + 16 * p + e, acc[e]);
+            }
+            p += dp;
+            sl += dsl;
+            if (p >= P) {
+                p -= P;
+                sl++;
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
     }
-    // the lanes of a block add up their words; one of them stores the pairs
-#pragma unroll
-    for (int q = 0; q < R; q++)
-#pragma unroll
-        for (int e = 0; e < 16; e++)
-            for (uint32_t o = g >> 1; o >= 1; o >>= 1) acc[q][e] += __shfl_xor(acc[q][e], (int)o, kWave);
-#pragma unroll
-    for (int q = 0; q < R; q++) {
-        if (!has[q] || sub != 0) continue;
-#pragma unroll
-        for (int i = 0; i < 4; i++)
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const uint32_t a = 4 * A[q] + i, b = 4 * B[q] + j;
-                if (a < b && b < f && a < r_cnt) gx[pair_index(a, b, f)] = acc[q][i * 4 + j];
-            }
+    // the counts of the pairs into gx (below the tile area's end, which
+    // holds more than f (f - 1) / 2 words, so no count is overwritten first)
+    for (uint32_t e = lane; e < 16 * P; e += kWave) {
+        const uint32_t ab = blk[e / 16], q = e % 16;
+        const uint32_t a = 4 * (ab >> 16) + q / 4, b = 4 * (ab & 0xffffu) + q % 4;
+        if (a < b && b < f && a < r_cnt) gx[pair_index(a, b, f)] = cnt[e];
     }
 }
 
@@ -1582,17 +1613,14 @@ __device__ __forceinline__ void count_class(const uint32_t *xr, const uint32_t *
                                             uint32_t *dst, uint32_t tmax, WaveShared &ws) {
     switch (f) {
         case 2: count_reg<2, 8>(xr, base, Wp, src, dst, ws.gx); break;
-        case 3: count_reg<3, 4>(xr, base, Wp, src, dst, ws.gx); break;
-        case 4: count_reg<4, 4>(xr, base, Wp, src, dst, ws.gx); break;
-        case 5: count_reg<5, 2>(xr, base, Wp, src, dst, ws.gx); break;
-        case 6: count_reg<6, 2>(xr, base, Wp, src, dst, ws.gx); break;
+        case 3: count_reg<3, 8>(xr, base, Wp, src, dst, ws.gx); break;
+        case 4: count_reg<4, 8>(xr, base, Wp, src, dst, ws.gx); break;
+        case 5: count_reg<5, 4>(xr, base, Wp, src, dst, ws.gx); break;
+        case 6: count_reg<6, 4>(xr, base, Wp, src, dst, ws.gx); break;
         case 7: count_reg<7, 2>(xr, base, Wp, src, dst, ws.gx); break;
         case 8: count_reg<8, 2>(xr, base, Wp, src, dst, ws.gx); break;
         default: {
-            const uint32_t P = lds_blocks(f, r_cnt, bmin);
-            if (P <= (uint32_t)kWave) count_lds<1>(xr, base, Wp, f, r_cnt, bmin, src, dst, ws.gx, tmax);
-            else if (P <= 2u * kWave) count_lds<2>(xr, base, Wp, f, r_cnt, bmin, src, dst, ws.gx, tmax);
-            else count_lds<3>(xr, base, Wp, f, r_cnt, bmin, src, dst, ws.gx, tmax);
+            count_lds(xr, base, Wp, f, r_cnt, bmin, src, dst, ws.gx, tmax);
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -1799,8 +1827,11 @@ __device__ __forceinline__ uint32_t finish_class(const InstDesc &I, uint32_t ins
             // frequent pairs of row a: before b in the row, ahead of b in the
             // list order, and in all
             uint32_t k_before = 0, pos = 0, row_n = 0;
+            // pair (a, c) sits at row_p + c: the row's pairs are consecutive
+            const uint32_t row_p = pair_index(a, a + 1, f) - (a + 1);
+#pragma unroll 4
             for (uint32_t c = a + 1; c < f; c++) {
-                const uint32_t sc = ws.gx[pair_index(a, c, f)];
+                const uint32_t sc = ws.gx[row_p + c];
                 const uint32_t idc = ws.cid[c];
                 const uint64_t kc = I.order_by_id ? (uint64_t)idc : (((uint64_t)sc << 32) | idc);
                 const bool fc = sc >= m;
