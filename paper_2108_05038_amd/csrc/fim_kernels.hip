@@ -995,6 +995,7 @@ struct alignas(16) WaveShared {
 struct WaveStats {
     unsigned long long candidates, pair_words, child_rows, given, max_k, max_depth, row_words;
     unsigned long long rec_pending;  // records not yet added to the instance's count
+    unsigned long long stack_peak;   // largest stack use of the piece (words)
     unsigned long long out_words;    // words of the records reported (or counted)
 };
 
@@ -1613,10 +1614,10 @@ __device__ __forceinline__ void count_class(const uint32_t *xr, const uint32_t *
                                             uint32_t *dst, uint32_t tmax, WaveShared &ws) {
     switch (f) {
         case 2: count_reg<2, 8>(xr, base, Wp, src, dst, ws.gx); break;
-        case 3: count_reg<3, 8>(xr, base, Wp, src, dst, ws.gx); break;
-        case 4: count_reg<4, 8>(xr, base, Wp, src, dst, ws.gx); break;
-        case 5: count_reg<5, 4>(xr, base, Wp, src, dst, ws.gx); break;
-        case 6: count_reg<6, 4>(xr, base, Wp, src, dst, ws.gx); break;
+        case 3: count_reg<3, 4>(xr, base, Wp, src, dst, ws.gx); break;
+        case 4: count_reg<4, 4>(xr, base, Wp, src, dst, ws.gx); break;
+        case 5: count_reg<5, 2>(xr, base, Wp, src, dst, ws.gx); break;
+        case 6: count_reg<6, 2>(xr, base, Wp, src, dst, ws.gx); break;
         case 7: count_reg<7, 2>(xr, base, Wp, src, dst, ws.gx); break;
         case 8: count_reg<8, 2>(xr, base, Wp, src, dst, ws.gx); break;
         default: {
@@ -2359,7 +2360,7 @@ __device__ __forceinline__ void search(const InstDesc &I, const InstDesc &Ig, ui
         const uint64_t use = rows_top + (S - meta);
         if (use > peak) peak = use;
     }
-    if (lane == 0) atomicMax(&ctr->stack_need, (unsigned long long)peak);
+    st.stack_peak = max(st.stack_peak, (unsigned long long)peak);
 }
 
 // the bits of v at the set bits of m, packed from bit 0 up
@@ -2669,6 +2670,16 @@ __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Tas
     // through the one call of the search below.
     bool planned = true;
     uint64_t t_next = 0, t_end = 0;
+    // statistics of the pieces of instance sum_inst not yet added to its
+    // counters (one flush per wave and instance instead of one per piece)
+    WaveStats sum{};
+    uint32_t sum_inst = kNone;
+    unsigned long long stack_peak = 0;  // of all the wave's pieces
+    auto flush_sum = [&]() {
+        if (sum_inst != kNone) flush_stats(insts[sum_inst], ictr, sum_inst, sum);
+        sum = WaveStats{};
+        sum_inst = kNone;
+    };
     unsigned long long since = 0;
     uint32_t nap = 1;
     for (;;) {
@@ -2678,18 +2689,17 @@ __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Tas
         bool have = false;
         if (planned) {
             if (t_next >= t_end) {
-                if (t_end) {
-                    wave_mem_wait();  // donations of the claimed tasks are published before they count as done
-                    if (lane == 0) atomicSub(&ctr->active.v, 1ull);
-                }
+                // a wave counts as active from its first claim until no
+                // planned task is left, so consecutive claims touch only
+                // the task counter (every counter here is one hot line)
                 unsigned long long t0 = 0;
                 if (lane == 0) {
-                    atomicAdd(&ctr->active.v, 1ull);
+                    if (!t_end) atomicAdd(&ctr->active.v, 1ull);
                     t0 = atomicAdd(&ctr->task_head.v, (unsigned long long)tasks_per_claim);
                 }
                 t0 = bcast64(t0);
                 if (t0 >= n_tasks) {
-                    wave_mem_wait();
+                    wave_mem_wait();  // donations of the claimed tasks are published before they count as done
                     if (lane == 0) atomicSub(&ctr->active.v, 1ull);
                     planned = false;
                     if (!dn.enabled) break;
@@ -2799,10 +2809,20 @@ __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Tas
                 search(I, Ig, inst, task, fs.plen, fs.l2_ref, Wp, fs.k, fs.r_end, fs.reported, meta,
                        (S - low) + (uint64_t)fs.k * Wp, tmax, region, S, ws, out, out_cap, ctr, ictr, st,
                        oc, dn);
-            flush_recs(ws, out, out_cap, ctr);
             close_chunk(oc, out);
             busy += wall_clock64() - c0;
-            flush_stats(I, ictr, inst, st);
+            if (I.rec_budget) {
+                flush_stats(I, ictr, inst, st);  // the budget's stop test needs the records now
+            } else {
+                if (sum_inst != inst) flush_sum();
+                sum_inst = inst;
+                sum.candidates += st.candidates;
+                sum.pair_words += st.pair_words;
+                sum.child_rows += st.child_rows;
+                sum.row_words += st.row_words;
+                sum.out_words += st.out_words;
+            }
+            stack_peak = max(stack_peak, st.stack_peak);
             note(st);
         }
         if (!planned) {
@@ -2815,6 +2835,10 @@ __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Tas
         }
     }
     if (!planned && dn.enabled && lane == 0) atomicSub(&ctr->idle.v, 1ull);
+    // key records staged in LDS go out when the stage fills and here
+    flush_recs(ws, out, out_cap, ctr);
+    flush_sum();
+    if (lane == 0 && stack_peak) atomicMax(&ctr->stack_need, stack_peak);
     if (lane == 0 && busy) {
         atomicAdd(&ctr->busy_sum, busy);
         atomicMax(&ctr->busy_max, busy);
