@@ -182,6 +182,12 @@ hipError_t launch_tidlist(const uint32_t *rows, uint32_t n, uint32_t Wp, const u
 hipError_t launch_rank_tx(const uint64_t *off, const uint32_t *items, uint64_t n_tx,
                           const uint32_t *rank_of_item, const uint32_t *tl, uint64_t n_ent,
                           uint16_t *rk, uint32_t *tlp, uint16_t *suf, hipStream_t stream);
+// The two halves of launch_rank_tx: rk alone (it needs no tid list, so it
+// can run beside the bitmap and list kernels), then tlp and suf.
+hipError_t launch_rank_only(const uint64_t *off, const uint32_t *items, uint64_t n_tx,
+                            const uint32_t *rank_of_item, uint16_t *rk, hipStream_t stream);
+hipError_t launch_tl_slots(const uint64_t *off, uint64_t n_tx, const uint16_t *rk, const uint32_t *tl,
+                           uint64_t n_ent, uint32_t *tlp, uint16_t *suf, hipStream_t stream);
 // Root class over projected transactions: rk, tlp and suf as above (tid
 // lists at offsets tl_off[n + 1]); 16-bit counters when max_supp (the
 // largest row support) is at most 65535.  Pairs as for launch_root_pairs;

@@ -2970,21 +2970,32 @@ hipError_t launch_tidlist(const uint32_t *rows, uint32_t n, uint32_t Wp, const u
     return hipGetLastError();
 }
 
-hipError_t launch_rank_tx(const uint64_t *off, const uint32_t *items, uint64_t n_tx,
-                          const uint32_t *rank_of_item, const uint32_t *tl, uint64_t n_ent,
-                          uint16_t *rk, uint32_t *tlp, uint16_t *suf, hipStream_t stream) {
+hipError_t launch_rank_only(const uint64_t *off, const uint32_t *items, uint64_t n_tx,
+                            const uint32_t *rank_of_item, uint16_t *rk, hipStream_t stream) {
     if (n_tx == 0) return hipSuccess;
     const uint64_t groups = (n_tx + kRankGroup - 1) / kRankGroup;
     const uint64_t blocks = std::min<uint64_t>((groups + kWavesPerBlock - 1) / kWavesPerBlock, 65536);
     hipLaunchKernelGGL(k_rank_tx, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, off, items, n_tx,
                        rank_of_item, rk);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || n_ent == 0) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_tl_slots(const uint64_t *off, uint64_t n_tx, const uint16_t *rk, const uint32_t *tl,
+                           uint64_t n_ent, uint32_t *tlp, uint16_t *suf, hipStream_t stream) {
+    if (n_tx == 0 || n_ent == 0) return hipSuccess;
     const uint64_t eb = (n_ent + kBlock - 1) / kBlock;
     if (eb >= (1ull << 31)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_tl_slots, dim3((uint32_t)eb), dim3(kBlock), 0, stream, off, rk, tl, n_ent,
                        tlp, suf);
     return hipGetLastError();
+}
+
+hipError_t launch_rank_tx(const uint64_t *off, const uint32_t *items, uint64_t n_tx,
+                          const uint32_t *rank_of_item, const uint32_t *tl, uint64_t n_ent,
+                          uint16_t *rk, uint32_t *tlp, uint16_t *suf, hipStream_t stream) {
+    const hipError_t e = launch_rank_only(off, items, n_tx, rank_of_item, rk, stream);
+    if (e != hipSuccess) return e;
+    return launch_tl_slots(off, n_tx, rk, tl, n_ent, tlp, suf, stream);
 }
 
 // words per column tile for n rows within lds_max bytes of LDS, the block's

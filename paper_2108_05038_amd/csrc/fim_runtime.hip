@@ -1199,6 +1199,30 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             else if (t_covers < t_rows) I.root_kind = 1;
             else I.root_kind = 0;
         }
+        // One instance with the projected root: its transactions are ranked
+        // on a side stream while the rows and lists are built on sq (the
+        // ranking reads only the transactions and the ranks just uploaded).
+        hipEvent_t ev_ranked = nullptr;
+        struct EvOne {
+            hipEvent_t &e;
+            ~EvOne() {
+                if (e) (void)hipEventDestroy(e);
+            }
+        } ev_ranked_guard{ev_ranked};
+        if (n_inst == 1 && I.root_kind == 2 && pairs_needed) {
+            std::vector<hipStream_t> rs;
+            HIPCHK(ctx_side_streams(ctx, rs));
+            ENSURE(I.d_rk, ctx, (I.db->nnz + I.db->n_tx + 48) * 2);
+            hipEvent_t ev_up = nullptr;
+            HIPCHK(hipEventCreateWithFlags(&ev_up, hipEventDisableTiming));
+            EvOne ev_up_guard{ev_up};
+            HIPCHK(hipEventRecord(ev_up, sq));
+            HIPCHK(hipStreamWaitEvent(rs[0], ev_up, 0));
+            HIPCHK(launch_rank_only(I.db->d_off.as<uint64_t>(), I.db->d_items.as<uint32_t>(), I.db->n_tx,
+                                    I.d_rank_of_item.as<uint32_t>(), I.d_rk.as<uint16_t>(), rs[0]));
+            HIPCHK(hipEventCreateWithFlags(&ev_ranked, hipEventDisableTiming));
+            HIPCHK(hipEventRecord(ev_ranked, rs[0]));
+        }
         // rows from LDS tiles (a column window of a group of rows) when the
         // device's LDS allows, else zero fill and global atomics
         if (bitmap_tiles_fit(ctx->lds_per_block)) {
@@ -1233,12 +1257,20 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
             if (ranked) {
                 ENSURE(I.d_rk, ctx, (I.db->nnz + I.db->n_tx + 48) * 2);
                 ENSURE(I.d_tlp, ctx, std::max<uint64_t>(I.tl_off[n], 1) * 4);
-                HIPCHK(launch_rank_tx(I.db->d_off.as<uint64_t>(), I.db->d_items.as<uint32_t>(),
-                                      I.db->n_tx, I.d_rank_of_item.as<uint32_t>(),
-                                      I.d_tl.as<uint32_t>(), I.tl_off[n], I.d_rk.as<uint16_t>(),
-                                      I.d_tlp.as<uint32_t>(), I.d_suf.as<uint16_t>(), sq));
+                if (ev_ranked) {
+                    HIPCHK(hipStreamWaitEvent(sq, ev_ranked, 0));
+                    HIPCHK(launch_tl_slots(I.db->d_off.as<uint64_t>(), I.db->n_tx, I.d_rk.as<uint16_t>(),
+                                           I.d_tl.as<uint32_t>(), I.tl_off[n], I.d_tlp.as<uint32_t>(),
+                                           I.d_suf.as<uint16_t>(), sq));
+                } else {
+                    HIPCHK(launch_rank_tx(I.db->d_off.as<uint64_t>(), I.db->d_items.as<uint32_t>(),
+                                          I.db->n_tx, I.d_rank_of_item.as<uint32_t>(),
+                                          I.d_tl.as<uint32_t>(), I.tl_off[n], I.d_rk.as<uint16_t>(),
+                                          I.d_tlp.as<uint32_t>(), I.d_suf.as<uint16_t>(), sq));
+                }
             }
         }
+        if (ev_ranked) HIPCHK(hipStreamWaitEvent(sq, ev_ranked, 0));  // joined in every case
         tr.mark("  (lists queued)");
         if (!pairs_needed) continue;
         const uint64_t all = (uint64_t)n * (n - 1) / 2;
