@@ -41,6 +41,9 @@ struct fim_ctx {
     // streams (default priority) that let the instances of a batched call
     // overlap their root-class work; created on first use
     std::vector<hipStream_t> side_streams;
+    // timing events of the root-class kernels (two per instance), kept for
+    // the next run: a batch of 256 instances spent 0.6 ms creating them
+    std::vector<hipEvent_t> timing_events;
     uint32_t *stage(size_t words);
 
     // Device blocks freed by the library are kept by size class for the
@@ -106,6 +109,9 @@ class DevBuf {
 
 // The context's side streams (created on first use).
 hipError_t ctx_side_streams(fim_ctx *ctx, std::vector<hipStream_t> &out);
+// At least n timing events in ctx->timing_events (created on first use,
+// reused by later runs on the context).
+hipError_t ctx_timing_events(fim_ctx *ctx, size_t n);
 
 // Several host pieces copied to consecutive places of dst, each piece's
 // place starting at the sum of the earlier pieces' sizes rounded up to 8

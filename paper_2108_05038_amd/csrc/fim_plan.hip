@@ -346,9 +346,9 @@ fim_status plan_tasks(fim_ctx *ctx, const std::vector<PlanInput> &in, const fim_
     for (uint32_t q = 0; q < n_inst; q++) {
         const auto &l2o = *in[q].l2_off;
         const size_t na = in[q].l2_atom->size();
-        w[q].assign(na, 0.0);
         px[q].assign(na, 0.0);
         const bool est = !row_w[q].empty();
+        if (est) w[q].assign(na, 0.0);  // else the proxy is the weight
         for (uint32_t i = 0; i < in[q].n_freq; i++) {
             const uint32_t f = l2o[i + 1] - l2o[i];
             double width = (double)in[q].W;
@@ -360,7 +360,7 @@ fim_status plan_tasks(fim_ctx *ctx, const std::vector<PlanInput> &in, const fim_
             for (uint32_t r = 0; r + 1 < f; r++) {
                 const double k = (double)(f - r - 1);
                 px[q][l2o[i] + r] = (k * (k + 1.0) / 2.0 + 1.0) * width;
-                w[q][l2o[i] + r] = est ? row_w[q][l2o[i] + r] : px[q][l2o[i] + r];
+                if (est) w[q][l2o[i] + r] = row_w[q][l2o[i] + r];
             }
         }
     }
@@ -370,7 +370,7 @@ fim_status plan_tasks(fim_ctx *ctx, const std::vector<PlanInput> &in, const fim_
             const uint32_t f = l2o[i + 1] - l2o[i];
             if (f < 2) continue;
             cls_in.push_back({q, i, 0, f - 1, 0.0, 0.0});
-            rw.push_back(w[q].data() + l2o[i]);
+            rw.push_back((w[q].empty() ? px[q] : w[q]).data() + l2o[i]);
             rp.push_back(px[q].data() + l2o[i]);
         }
     }

@@ -262,6 +262,7 @@ uint32_t *fim_ctx::stage(size_t words) {
 
 fim_ctx::~fim_ctx() {
     delete aux;
+    for (hipEvent_t e : timing_events) (void)hipEventDestroy(e);
     for (hipStream_t x : side_streams) {
         (void)hipStreamSynchronize(x);
         (void)hipStreamDestroy(x);
@@ -292,6 +293,16 @@ hipError_t ctx_side_streams(fim_ctx *ctx, std::vector<hipStream_t> &out) {
         ctx->side_streams.push_back(x);
     }
     out = ctx->side_streams;
+    return hipSuccess;
+}
+
+hipError_t ctx_timing_events(fim_ctx *ctx, size_t n) {
+    while (ctx->timing_events.size() < n) {
+        hipEvent_t e = nullptr;
+        const hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        ctx->timing_events.push_back(e);
+    }
     return hipSuccess;
 }
 
@@ -1125,15 +1136,8 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
     } evg{ev0, ev1};
     float root_ms = 0.f;
     // one event pair per instance around its root-class kernel
-    std::vector<hipEvent_t> rev(2 * n_inst, nullptr);
-    struct EvVec {
-        std::vector<hipEvent_t> &v;
-        ~EvVec() {
-            for (auto e : v)
-                if (e) (void)hipEventDestroy(e);
-        }
-    } evv{rev};
-    for (auto &e : rev) HIPCHK(hipEventCreate(&e));
+    HIPCHK(ctx_timing_events(ctx, 2ull * n_inst));
+    const std::vector<hipEvent_t> &rev = ctx->timing_events;
     // per instance: frequent pairs found, pair increments (projected root)
     PinnedBlock h_small(16ull * n_inst);
     memset(h_small.p, 0, 16ull * n_inst);
