@@ -243,6 +243,8 @@ static fim_status estimate_rows(fim_ctx *ctx, const std::vector<PlanInput> &in,
 // cls_in: one entry per first-level class with >= 2 atoms (inst, node,
 // r0 = 0, r1 = n_atoms - 1); rw[k] the row weights of class k; rp[k] the
 // row proxies.  Output classes in LPT order.
+void lpt_order(std::vector<PlanClass> &out);
+
 void partition_lpt_order(const std::vector<PlanClass> &cls_in,
                          const std::vector<const double *> &rw,
                          const std::vector<const double *> &rp, double alpha, uint32_t n_workers,
@@ -279,11 +281,15 @@ void partition_lpt_order(const std::vector<PlanClass> &cls_in,
         }
         out.push_back({c.inst, c.node, r0, rows, acc, accp});
     }
-    // LPT order: decreasing estimate, then decreasing proxy, then position.
-    // One counting pass puts the tasks into 1,024 buckets of decreasing
-    // weight (sixteenths of an octave), then each bucket, a few tasks, is
-    // sorted exactly: the same order as a full sort of the 64-bit keys, whose
-    // radix passes cost the host about 0.1 ms for 2,000 tasks.
+    lpt_order(out);
+}
+
+// LPT order: decreasing estimate, then decreasing proxy, then position.
+// One counting pass puts the tasks into 1,024 buckets of decreasing
+// weight (sixteenths of an octave), then each bucket, a few tasks, is
+// sorted exactly: the same order as a full sort of the 64-bit keys, whose
+// radix passes cost the host about 0.1 ms for 2,000 tasks.
+void lpt_order(std::vector<PlanClass> &out) {
     const size_t m = out.size();
     auto bucket = [](double w) -> uint32_t {  // 0 .. 1023, ascending in w
         if (!(w > 0.0)) return 0u;
@@ -340,6 +346,70 @@ fim_status plan_tasks(fim_ctx *ctx, const std::vector<PlanInput> &in, const fim_
     // The rows of first-level class i are ceil(supp(i) / 32) words wide when
     // they are projected on its cover (a quarter of the stored width or
     // less, as the persistent kernel decides), else W.
+    auto width_of = [&](uint32_t q, uint32_t i) {
+        double width = (double)in[q].W;
+        if (in[q].project && in[q].supp_of_rank) {
+            const uint32_t s = (*in[q].supp_of_rank)[i];
+            const uint32_t Wq = std::max<uint32_t>(4, ((s + 31) / 32 + 3) / 4 * 4);
+            if (4ull * Wq <= in[q].Wp) width = (double)((s + 31) / 32);
+        }
+        return width;
+    };
+    bool any_est = false;
+    for (const auto &v : row_w) any_est = any_est || !v.empty();
+    if (!any_est && !classes_out) {
+        // Proxy weights alone, in closed form: row r of a class of f atoms
+        // weighs (k (k + 1) / 2 + 1) width with k = f - 1 - r, the class
+        // width ((f - 1) f (f + 1) / 6 + f - 1); only the classes above the
+        // Partition threshold are walked row by row.  The tasks are those of
+        // partition_lpt_order over arrays of these weights (whole numbers,
+        // so the sums agree wherever they stay below 2^53), without filling
+        // a weight per second-level class (millions in a batch).
+        std::vector<PlanClass> cls;
+        double total = 0.0;
+        for (uint32_t q = 0; q < n_inst; q++) {
+            const auto &l2o = *in[q].l2_off;
+            for (uint32_t i = 0; i < in[q].n_freq; i++) {
+                const uint32_t f = l2o[i + 1] - l2o[i];
+                if (f < 2) continue;
+                const double fd = (double)f;
+                const double cw = width_of(q, i) * ((fd - 1.0) * fd * (fd + 1.0) / 6.0 + fd - 1.0);
+                cls.push_back({q, i, 0, f - 1, cw, cw});
+                total += cw;
+            }
+        }
+        const double theta =
+            std::max(opts.alpha * total / (double)std::max<uint32_t>(n_workers, 1), 1e-300);
+        const bool no_split = (opts.flags & FIM_FLAG_NO_SPLIT) != 0;
+        std::vector<PlanClass> out;
+        out.reserve(cls.size());
+        for (const PlanClass &c : cls) {
+            const uint32_t rows = c.r1;
+            if (c.weight <= theta || no_split || rows == 1) {
+                out.push_back(c);
+                continue;
+            }
+            const double width = width_of(c.inst, c.node);
+            const uint32_t f = rows + 1;
+            uint32_t r0 = 0;
+            double acc = 0.0;
+            for (uint32_t r = 0; r < rows; r++) {
+                const double k = (double)(f - r - 1);
+                const double v = (k * (k + 1.0) / 2.0 + 1.0) * width;
+                if (r > r0 && acc + v > theta) {
+                    out.push_back({c.inst, c.node, r0, r, acc, acc});
+                    r0 = r;
+                    acc = 0.0;
+                }
+                acc += v;
+            }
+            out.push_back({c.inst, c.node, r0, rows, acc, acc});
+        }
+        lpt_order(out);
+        tasks.reserve(out.size());
+        for (const PlanClass &c : out) tasks.push_back(Task{c.inst, c.node, c.r0, c.r1});
+        return FIM_OK;
+    }
     std::vector<std::vector<double>> w(n_inst), px(n_inst);
     std::vector<PlanClass> cls_in;
     std::vector<const double *> rw, rp;
@@ -351,12 +421,7 @@ fim_status plan_tasks(fim_ctx *ctx, const std::vector<PlanInput> &in, const fim_
         if (est) w[q].assign(na, 0.0);  // else the proxy is the weight
         for (uint32_t i = 0; i < in[q].n_freq; i++) {
             const uint32_t f = l2o[i + 1] - l2o[i];
-            double width = (double)in[q].W;
-            if (in[q].project && in[q].supp_of_rank) {
-                const uint32_t s = (*in[q].supp_of_rank)[i];
-                const uint32_t Wq = std::max<uint32_t>(4, ((s + 31) / 32 + 3) / 4 * 4);
-                if (4ull * Wq <= in[q].Wp) width = (double)((s + 31) / 32);
-            }
+            const double width = width_of(q, i);
             for (uint32_t r = 0; r + 1 < f; r++) {
                 const double k = (double)(f - r - 1);
                 px[q][l2o[i] + r] = (k * (k + 1.0) / 2.0 + 1.0) * width;
