@@ -44,6 +44,8 @@ struct fim_ctx {
     // timing events of the root-class kernels (two per instance), kept for
     // the next run: a batch of 256 instances spent 0.6 ms creating them
     std::vector<hipEvent_t> timing_events;
+    // two events without timing that order a side stream's work within a run
+    hipEvent_t sync_events[2] = {nullptr, nullptr};
     uint32_t *stage(size_t words);
 
     // Device blocks freed by the library are kept by size class for the

@@ -263,6 +263,8 @@ uint32_t *fim_ctx::stage(size_t words) {
 fim_ctx::~fim_ctx() {
     delete aux;
     for (hipEvent_t e : timing_events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : sync_events)
+        if (e) (void)hipEventDestroy(e);
     for (hipStream_t x : side_streams) {
         (void)hipStreamSynchronize(x);
         (void)hipStreamDestroy(x);
@@ -562,7 +564,6 @@ struct Inst {
     uint32_t minsup = 0;
     uint32_t W = 0, Wp = 0, n_freq = 0;
     std::vector<uint32_t> counts, item_of_rank, rank_of_item, supp_of_rank;
-    std::vector<uint32_t> pairs;  // triples (i, j, support)
     uint64_t n_pairs = 0;
     std::vector<uint32_t> l2_off, l2_atom, l2_supp;
     DevBuf d_counts, d_rank_of_item, d_rows, d_pairs, d_npairs;
@@ -649,18 +650,18 @@ static void rank_items(Inst &I, bool by_id) {
 
 // atoms of every first-level class: frequent pairs (i, j) bucketed by i and
 // ordered ascending by (support, item id of j), or by j (= id order)
-static void build_level2(Inst &I, bool by_id) {
+static void build_level2(Inst &I, bool by_id, const uint32_t *pairs) {
     const uint32_t n = I.n_freq;
     I.l2_off.assign(n + 1, 0);
-    for (uint64_t p = 0; p < I.n_pairs; p++) I.l2_off[I.pairs[3 * p] + 1]++;
+    for (uint64_t p = 0; p < I.n_pairs; p++) I.l2_off[pairs[3 * p] + 1]++;
     for (uint32_t i = 0; i < n; i++) I.l2_off[i + 1] += I.l2_off[i];
     I.l2_atom.resize(I.n_pairs);
     I.l2_supp.resize(I.n_pairs);
     std::vector<uint32_t> fill(I.l2_off.begin(), I.l2_off.end() - 1);
     for (uint64_t p = 0; p < I.n_pairs; p++) {
-        const uint32_t i = I.pairs[3 * p], q = fill[i]++;
-        I.l2_atom[q] = I.pairs[3 * p + 1];
-        I.l2_supp[q] = I.pairs[3 * p + 2];
+        const uint32_t i = pairs[3 * p], q = fill[i]++;
+        I.l2_atom[q] = pairs[3 * p + 1];
+        I.l2_supp[q] = pairs[3 * p + 2];
     }
     // every bucket sorted by its key in one array (no allocation per bucket;
     // insertion sort for the many short buckets)
@@ -1207,25 +1208,19 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
         // on a side stream while the rows and lists are built on sq (the
         // ranking reads only the transactions and the ranks just uploaded).
         hipEvent_t ev_ranked = nullptr;
-        struct EvOne {
-            hipEvent_t &e;
-            ~EvOne() {
-                if (e) (void)hipEventDestroy(e);
-            }
-        } ev_ranked_guard{ev_ranked};
         if (n_inst == 1 && I.root_kind == 2 && pairs_needed) {
             std::vector<hipStream_t> rs;
             HIPCHK(ctx_side_streams(ctx, rs));
+            for (hipEvent_t &e : ctx->sync_events)
+                if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
             ENSURE(I.d_rk, ctx, (I.db->nnz + I.db->n_tx + 48) * 2);
-            hipEvent_t ev_up = nullptr;
-            HIPCHK(hipEventCreateWithFlags(&ev_up, hipEventDisableTiming));
-            EvOne ev_up_guard{ev_up};
-            HIPCHK(hipEventRecord(ev_up, sq));
-            HIPCHK(hipStreamWaitEvent(rs[0], ev_up, 0));
+            HIPCHK(hipEventRecord(ctx->sync_events[0], sq));
+            HIPCHK(hipStreamWaitEvent(rs[0], ctx->sync_events[0], 0));
             HIPCHK(launch_rank_only(I.db->d_off.as<uint64_t>(), I.db->d_items.as<uint32_t>(), I.db->n_tx,
                                     I.d_rank_of_item.as<uint32_t>(), I.d_rk.as<uint16_t>(), rs[0]));
-            HIPCHK(hipEventCreateWithFlags(&ev_ranked, hipEventDisableTiming));
+            ev_ranked = ctx->sync_events[1];
             HIPCHK(hipEventRecord(ev_ranked, rs[0]));
+            tr.mark("  (ranking queued)");
         }
         // rows from LDS tiles (a column window of a group of rows) when the
         // device's LDS allows, else zero fill and global atomics
@@ -1420,11 +1415,10 @@ fim_status mine_many(fim_ctx *ctx, const std::vector<MineRequest> &reqs, const f
     tr.mark("  (pairs copied)");
     parallel_for(n_inst, host_threads((uint64_t)n_inst << 14), [&](uint64_t q) {
         Inst &I = insts[q];
-        if (pair_at[q + 1] > pair_at[q])
-            I.pairs.assign(h_pairs_of((uint32_t)q), h_pairs_of((uint32_t)q) + 3 * (pair_at[q + 1] - pair_at[q]));
         I.st.root_kernel_ns = (uint64_t)(root_ms * 1e6);
         I.st.kernel_ns = I.st.root_kernel_ns;
-        if (I.n_pairs) build_level2(I, by_id);
+        // straight from the page-locked copy of the pairs
+        if (I.n_pairs) build_level2(I, by_id, h_pairs_of((uint32_t)q));
         else I.l2_off.assign(I.n_freq + 1, 0);
     });
 
