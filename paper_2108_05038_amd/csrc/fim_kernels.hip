@@ -6,6 +6,7 @@
 // "Support counting").  No MFMA: the work is bitwise, and most of it is
 // bound by memory or by the integer vector ALU.
 #include <algorithm>
+#include <atomic>
 
 #include "fim_internal.h"
 
@@ -925,9 +926,9 @@ __global__ __launch_bounds__(kBlock) void k_root_project(
 // word tile, the supports of all of its pairs (the popcount-Gram of the
 // class) are accumulated from the same words, so every loaded word serves
 // all pairs of the class: up to kRegGram atoms a lane keeps its 128-bit
-// chunks of all rows and all pairs in registers; wider classes stage each
-// 32-word tile of their rows in LDS and every lane accumulates 4x4 blocks of
-// pairs from it.  For every row the frequent later atoms, ordered by
+// chunks of all rows and all pairs in registers; wider classes stage word
+// tiles of their rows in LDS, and the (4x4 block, word slice) items of each
+// tile are dealt to all lanes (see count_lds).  For every row the frequent later atoms, ordered by
 // ascending support (ties by item id), become that row's child class, and
 // the frequent pairs are reported.  Expanding row r then counts nothing: it
 // builds the child class of row r in the same way.  A class of two atoms
@@ -2744,10 +2745,10 @@ __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Tas
             done = bcast32(done);
             if (done) break;
             if (got == ~0ull) {
-                if (wall_clock64() - since > dn.wait_ticks) {
-                    if (lane == 0) atomicOr(&ctr->flags, kFlagSpin);
-                    break;
-                }
+                // A wave that found no donated work for the whole bound
+                // leaves quietly: no work is lost, since a donor that runs
+                // out of work comes back here and drains the queue itself.
+                if (wall_clock64() - since > dn.wait_ticks) break;
                 // back off: 1, 2, 4 ... nap_max naps of about 8000 cycles
                 for (uint32_t q = 0; q < nap; q++) __builtin_amdgcn_s_sleep(127);
                 if (nap < dn.nap_max) nap <<= 1;
@@ -3036,9 +3037,24 @@ hipError_t launch_bitmap_tiles(const uint64_t *offsets, const uint32_t *items, u
     const uint64_t blocks = (uint64_t)groups * ((Wp + K - 1) / K);
     if (blocks >= (1ull << 31)) return hipErrorInvalidValue;
     const size_t lds = (size_t)nr * K * 4;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bitmap_tile),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    // the kernel's dynamic LDS limit is raised once per device to the
+    // largest size asked for (the call costs microseconds per launch)
+    constexpr int kDevs = 64;
+    static std::atomic<int> lds_set[kDevs];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
+    const bool known = dev >= 0 && dev < kDevs;
+    if (!known || lds_set[dev].load() < (int)lds) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bitmap_tile),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        if (known) {
+            int cur = lds_set[dev].load();
+            while (cur < (int)lds && !lds_set[dev].compare_exchange_weak(cur, (int)lds)) {
+            }
+        }
+    }
     hipLaunchKernelGGL(k_bitmap_tile, dim3((uint32_t)blocks), dim3(kBlock), lds, stream, offsets,
                        items, n_tx, rank_of_item, n, rows, Wp, K, nr, groups);
     return hipGetLastError();
