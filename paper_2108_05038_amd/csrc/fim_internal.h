@@ -235,13 +235,15 @@ hipError_t launch_prefix_keys(const PrefixSrc *src, uint32_t n_src, uint64_t max
 // Waves of that persistent kernel variant that fit on the device at once.
 uint32_t dfs_resident_workers(int n_cu, uint32_t variant);
 
-// Persistent depth-first search over the tasks.
+// Persistent depth-first search over the tasks: n_workers waves, in blocks
+// of waves_per_block active waves (1 to 4; n_workers a multiple of it).
 hipError_t launch_dfs(const InstDesc *insts, const Task *tasks, uint64_t n_tasks,
                       uint32_t *stack, uint64_t stack_words, uint32_t n_workers,
                       uint32_t tasks_per_claim, uint32_t *out, uint64_t out_cap,
                       DfsCounters *ctr, InstCounters *ictr, unsigned long long *don_slots,
                       uint64_t n_slots, uint32_t *don_heap, uint64_t heap_words,
                       uint64_t wait_ticks, unsigned long long *trace, uint32_t variant,
-                      uint32_t nap_max, uint64_t poll_ticks, hipStream_t stream);
+                      uint32_t nap_max, uint64_t poll_ticks, uint32_t waves_per_block,
+                      hipStream_t stream);
 
 }  // namespace fim

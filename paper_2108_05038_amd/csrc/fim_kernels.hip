@@ -2649,13 +2649,17 @@ __global__ __launch_bounds__(kBlock) void k_dfs(const InstDesc *insts, const Tas
                                                 uint32_t tmax,
                                                 uint32_t *out, uint64_t out_cap,
                                                 DfsCounters *ctr, InstCounters *ictr,
-                                                Donation dn) {
+                                                Donation dn, uint32_t waves_per_block) {
     __shared__ WaveShared shared[kWavesPerBlock];
     const uint32_t w = uni(threadIdx.x / kWave);
+    // a launch with fewer workers than CUs keeps one wave per block, so that
+    // its waves spread over all CUs (the other waves leave at once; there is
+    // no block barrier)
+    if (w >= waves_per_block) return;
     const uint32_t lane = lane_id();
     WaveShared &ws = shared[w];
     if (lane == 0) ws.n_recs = 0;
-    const uint64_t wave_id = (uint64_t)blockIdx.x * kWavesPerBlock + w;
+    const uint64_t wave_id = (uint64_t)blockIdx.x * waves_per_block + w;
     uint32_t *region = stack + wave_id * stack_words;
     unsigned long long busy = 0;
     WaveTrace wt{0, 0, 0, 0, 0, 0, 0, 0};
@@ -3181,16 +3185,20 @@ hipError_t launch_dfs(const InstDesc *insts, const Task *tasks, uint64_t n_tasks
                       uint32_t *out, uint64_t out_cap, DfsCounters *ctr, InstCounters *ictr,
                       unsigned long long *don_slots, uint64_t n_slots, uint32_t *don_heap,
                       uint64_t heap_words, uint64_t wait_ticks, unsigned long long *trace,
-                      uint32_t variant, uint32_t nap_max, uint64_t poll_ticks, hipStream_t stream) {
+                      uint32_t variant, uint32_t nap_max, uint64_t poll_ticks, uint32_t waves_per_block,
+                      hipStream_t stream) {
     if (n_tasks == 0) return hipSuccess;
-    const uint32_t blocks = (n_workers + kWavesPerBlock - 1) / kWavesPerBlock;
+    const uint32_t wpb = waves_per_block >= 1 && waves_per_block <= (uint32_t)kWavesPerBlock
+                             ? waves_per_block : (uint32_t)kWavesPerBlock;
+    if (n_workers % wpb != 0) return hipErrorInvalidValue;
+    const uint32_t blocks = n_workers / wpb;
     Donation dn{don_slots, don_heap, n_slots, heap_words, wait_ticks,
                 (don_slots && don_heap && n_slots && heap_words) ? 1u : 0u, trace,
                 nap_max ? nap_max : 64u, poll_ticks ? poll_ticks : 1u};
     const uint32_t tpc = tasks_per_claim ? tasks_per_claim : 1u;
     const uint32_t tmax = variant ? tile_variant(variant) : kTileDefault;
     hipLaunchKernelGGL(k_dfs, dim3(blocks), dim3(kBlock), 0, stream, insts, tasks, n_tasks, stack,
-                       stack_words, tpc, tmax, out, out_cap, ctr, ictr, dn);
+                       stack_words, tpc, tmax, out, out_cap, ctr, ictr, dn, wpb);
     return hipGetLastError();
 }
 

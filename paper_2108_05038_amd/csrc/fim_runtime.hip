@@ -800,13 +800,18 @@ static fim_status run_persistent(fim_ctx *ctx, hipStream_t s, Tracer &tr,
         if (L.cap_output) HIPCHK(launch_fill_u32(d_out.as<uint32_t>(), L.out_cap, 0u, s));
         tr.mark("  (dfs inputs queued)");
         HIPCHK(hipEventRecord(ev0, s));
+        // at most one worker per CU: one wave per block, so that the waves
+        // spread over all CUs instead of filling a quarter of them
+        uint32_t wpb = workers <= (uint32_t)std::max(ctx->n_cu, 1) ? 1u : 4u;
+        if (const char *e = getenv("FIM_WPB")) wpb = (uint32_t)std::max(1, std::min(4, atoi(e)));  // tuning
+        if (workers % wpb != 0) wpb = 1;
         auto launch = [&]() {
             return launch_dfs(p_desc, p_tasks, tasks.size(),
                               d_stack.as<uint32_t>(), S, workers, L.claim, d_out.as<uint32_t>(),
                               L.out_cap, p_ctr, p_ictr, p_slots, n_slots, d_heap.as<uint32_t>(),
                               heap_words, wait_ticks,
                               tr.on ? d_trace.as<unsigned long long>() : nullptr, L.variant, nap_max,
-                              poll_ticks, s);
+                              poll_ticks, wpb, s);
         };
         HIPCHK(launch());
         HIPCHK(hipEventRecord(ev1, s));
