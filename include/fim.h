@@ -93,6 +93,8 @@ typedef struct fim_ctx fim_ctx;
  */
 fim_status fim_ctx_create(int device, void *hip_stream, const fim_allocator *alloc,
                           fim_ctx **out);
+/* Destroy the context's servers and databases first: a database is freed
+ * through its context. */
 void fim_ctx_destroy(fim_ctx *ctx);
 
 /*

@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -357,6 +358,9 @@ class Context:
     def __init__(self, device: int = 0, use_torch: bool = True):
         self.device = device
         self._keep = []
+        # databases and servers on this context: closed before it (the
+        # library frees a database through its context)
+        self._deps = weakref.WeakSet()
         stream, alloc = None, None
         if use_torch:
             try:
@@ -392,6 +396,12 @@ class Context:
 
     def close(self):
         if self.handle:
+            deps = list(self._deps)
+            for d in deps:  # servers first: they mine the databases
+                if isinstance(d, Server):
+                    d.close()
+            for d in deps:
+                d.close()
             fim_ctx_destroy(self.handle)
             self.handle = None
 
@@ -408,6 +418,7 @@ class Database:
     def __init__(self, ctx: Context, offsets, items, n_item_ids: int):
         self.ctx = ctx
         self.handle = fim_db_create(ctx.handle, offsets, items, n_item_ids)
+        ctx._deps.add(self)
         n, nnz = ctypes.c_uint64(), ctypes.c_uint64()
         _check(lib().fim_db_sizes(self.handle, ctypes.byref(n), ctypes.byref(nnz)))
         self.n_tx, self.nnz = n.value, nnz.value
@@ -509,6 +520,7 @@ class Server:
         self.ctx = ctx
         self.handle = ctypes.c_void_p()
         _check(lib().fim_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(self.handle)))
+        ctx._deps.add(self)
 
     def submit(self, db: Database, minsup: int) -> int:
         t = ctypes.c_uint64()

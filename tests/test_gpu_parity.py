@@ -504,3 +504,20 @@ def test_serve_pool_512_vs_golden(fim, ctx):
     for h in handles:
         h.close()
     ctx.release_cached()
+
+
+def test_context_closed_before_its_databases(fim):
+    # closing a context first closes the databases and servers made on it
+    # (the library frees a database through its context); closing them again
+    # afterwards does nothing
+    say("context closed before its database and server")
+    c = fim.Context(0)
+    d = fim.Database(c, np.array([0, 2, 3], np.uint64), np.array([0, 1, 1], np.uint32), 2)
+    r = fim.mine(c, d, 1)
+    assert len(r) == 3  # {0}, {1}, {0, 1}
+    srv = fim.Server(c)
+    c.close()
+    assert d.handle is None and not srv.handle
+    d.close()
+    srv.close()
+    del r
