@@ -2021,6 +2021,41 @@ __device__ __forceinline__ void search(const InstDesc &I, const InstDesc &Ig, ui
                 st.row_words += (unsigned long long)c * Wp;
                 st.child_rows += b_write ? c : 0u;
             }
+            if (c == 2 && depth >= 0 && I.key_bits != 0 && I.class_count == nullptr &&
+                I.row_cand == nullptr && I.rec_budget == 0) {
+                // A class of two atoms is a leaf: its one pair is reported
+                // here (a key record staged as finish_class would), and no
+                // frame is pushed, since neither of its rows has a class of
+                // two atoms below it.  Its one candidate is counted as the
+                // frame's rows would have been.
+                const uint32_t s2 = uni(ws.gx[0]);
+                const uint32_t len = b_em.np + 2;
+                if (b_em.r_emit >= 1 && s2 >= I.minsup && (I.max_len == 0 || len <= I.max_len)) {
+                    if (len * I.key_bits > 128) {
+                        if (lane == 0) atomicOr(&ctr->flags, kFlagKeyOverflow);
+                    } else {
+                        if (uni(ws.n_recs) + 1 > kStageRecs) flush_recs(ws, out, out_cap, ctr);
+                        sort_prefix_ids(b_em.np, ws);
+                        if (lane == 0) {
+                            const uint32_t at = ws.n_recs;
+                            const uint32_t ia = ws.cid[0], ib = ws.cid[1];
+                            unsigned long long hi, lo2;
+                            pair_key(ws, b_em.np, I.key_bits, min(ia, ib), max(ia, ib), hi, lo2);
+                            ws.recs[2 * at] = make_uint4((uint32_t)lo2, (uint32_t)(lo2 >> 32), (uint32_t)hi,
+                                                         (uint32_t)(hi >> 32));
+                            ws.recs[2 * at + 1] = make_uint4(s2, inst, 0u, 0u);
+                            ws.n_recs = at + 1;
+                        }
+                        st.out_words += 8;
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                }
+                st.candidates += 1;
+                if (2 > st.max_k) st.max_k = 2;
+                if ((unsigned long long)(depth + 1) > st.max_depth) st.max_depth = depth + 1;
+                continue;
+            }
             uint32_t ao = 0, lo = 0;
             uint4 xm;
             if (finish_class(I, inst, task, c, b_r_end, b_rank, b_supp, b_id, b_em, rows_top + rows_need, meta, region,
